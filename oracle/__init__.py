@@ -1,0 +1,336 @@
+"""FP64 CPU oracle for the batched XPBD substep (test infrastructure).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It compiles ``xpbd_oracle.c`` with gcc
+(no fused multiply-add) and wraps it with ctypes.  It shares nothing with the
+GPU library: mesh set-up (orientation, rest values, edge extraction, greedy
+colouring) and the simulation are recomputed here from the raw input arrays.
+
+The arithmetic lives in ``xpbd_oracle.c``; its header lists the paper
+passages followed and the readings taken where the paper is silent or
+garbled.  This wrapper only marshals arrays, builds the colour schedule
+(a stable sort of constraint ids by colour) and spreads independent
+environments over threads.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "xpbd_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+_lock = threading.Lock()
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int32)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library in-tree with gcc."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                        "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+                build(force=True)
+            lib = ctypes.CDLL(_LIB_PATH)
+            lib.oracle_tet_volume.restype = ctypes.c_double
+            lib.oracle_tet_volume.argtypes = [_D, _D, _D, _D]
+            lib.oracle_tet_gradients.restype = ctypes.c_double
+            lib.oracle_tet_gradients.argtypes = [_D, _D]
+            lib.oracle_project_distance.restype = None
+            lib.oracle_project_distance.argtypes = [_D, _D, ctypes.c_int, ctypes.c_int,
+                                                    ctypes.c_double, ctypes.c_double, _D]
+            lib.oracle_project_volume.restype = None
+            lib.oracle_project_volume.argtypes = [_D, _D, _I, ctypes.c_double, ctypes.c_double, _D]
+            lib.oracle_project_contact.restype = None
+            lib.oracle_project_contact.argtypes = [_D, _D, ctypes.c_double]
+            lib.oracle_setup_tets.restype = ctypes.c_int
+            lib.oracle_setup_tets.argtypes = [ctypes.c_int, _D, _D, ctypes.c_int, _I, _I, _D,
+                                              ctypes.POINTER(ctypes.c_int)]
+            lib.oracle_setup_edges.restype = ctypes.c_int
+            lib.oracle_setup_edges.argtypes = [ctypes.c_int, _D, _D, ctypes.c_int, _I, _I, _D,
+                                               ctypes.POINTER(ctypes.c_int)]
+            lib.oracle_greedy_colour.restype = ctypes.c_int
+            lib.oracle_greedy_colour.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I, _I]
+            lib.oracle_residual.restype = None
+            lib.oracle_residual.argtypes = [_D, ctypes.c_int, _I, _D, ctypes.c_int, _I, _D,
+                                            ctypes.c_double, ctypes.c_double, _D, _D]
+            lib.oracle_run.restype = ctypes.c_int
+            lib.oracle_run.argtypes = [
+                ctypes.c_int, _D,
+                ctypes.c_int, _I, _D,
+                ctypes.c_int, _I, _D,
+                ctypes.c_int, _I, _I,
+                ctypes.c_int, _I, _I,
+                ctypes.c_double, ctypes.c_int, ctypes.c_int, _D,
+                ctypes.c_double, ctypes.c_double,
+                ctypes.c_int, _D,
+                ctypes.c_int, _D,
+                _D, _D,
+                _D, _I, _I, _D]
+            _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D) if a is not None else None
+
+
+def _ip(a):
+    return a.ctypes.data_as(_I) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+# ---------------------------------------------------------------- primitives
+def tet_volume(p):
+    """Signed volume of a tetrahedron p[4][3] (float64)."""
+    p = _f64(p).reshape(4, 3)
+    rows = [np.ascontiguousarray(p[i]) for i in range(4)]
+    return _load().oracle_tet_volume(*[_dp(r) for r in rows])
+
+
+def tet_gradients(p):
+    """(volume, gradients[4][3]) of the volume constraint at p[4][3]."""
+    p = _f64(p).reshape(4, 3).copy()
+    g = np.zeros((4, 3))
+    vol = _load().oracle_tet_gradients(_dp(p), _dp(g))
+    return vol, g
+
+
+def project_distance(x, w, a, b, rest_length, alpha_tilde, lam=0.0):
+    """One distance projection; returns (new x, new lambda)."""
+    x = _f64(x).copy()
+    w = _f64(w)
+    lam_arr = np.array([lam], dtype=np.float64)
+    _load().oracle_project_distance(_dp(x), _dp(w), int(a), int(b), float(rest_length),
+                                    float(alpha_tilde), _dp(lam_arr))
+    return x, float(lam_arr[0])
+
+
+def project_volume(x, w, q, rest_volume, alpha_tilde, lam=0.0):
+    """One volume projection of tetrahedron q; returns (new x, new lambda)."""
+    x = _f64(x).copy()
+    w = _f64(w)
+    q = _i32(q)
+    lam_arr = np.array([lam], dtype=np.float64)
+    _load().oracle_project_volume(_dp(x), _dp(w), _ip(q), float(rest_volume),
+                                  float(alpha_tilde), _dp(lam_arr))
+    return x, float(lam_arr[0])
+
+
+def project_contact(xi, centre, radius):
+    xi = _f64(xi).copy()
+    c = _f64(centre)
+    _load().oracle_project_contact(_dp(xi), _dp(c), float(radius))
+    return xi
+
+
+def greedy_colour(num_vertices, verts):
+    """Greedy colours of constraints verts[n][k]; returns (colours, count)."""
+    verts = _i32(verts)
+    n, k = verts.shape if verts.size else (0, max(1, verts.shape[-1] if verts.ndim == 2 else 1))
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    nc = _load().oracle_greedy_colour(int(num_vertices), int(n), int(k), _ip(verts), _ip(out))
+    if nc < 0:
+        raise OracleError(f"oracle_greedy_colour failed: {nc}")
+    return out[:n], nc
+
+
+def schedule(colours, num_colours):
+    """Processing order: colour ascending, constraint id ascending inside a colour."""
+    colours = np.asarray(colours, dtype=np.int64)
+    order = np.argsort(colours, kind="stable").astype(np.int32)
+    ptr = np.zeros(num_colours + 1, dtype=np.int32)
+    if colours.size:
+        ptr[1:] = np.cumsum(np.bincount(colours, minlength=num_colours))
+    return ptr, order
+
+
+# ---------------------------------------------------------------- mesh set-up
+@dataclass
+class OracleMesh:
+    num_vertices: int
+    w: np.ndarray             # [V] float64 inverse masses
+    rest: np.ndarray          # [V,3] float64
+    tets: np.ndarray          # [T,4] int32, kept + oriented, input order
+    rest_volume: np.ndarray   # [T] float64
+    edges: np.ndarray         # [E,2] int32, sorted, free
+    rest_length: np.ndarray   # [E] float64
+    edge_colour: np.ndarray   # [E] int32
+    tet_colour: np.ndarray    # [T] int32
+    num_edge_colours: int
+    num_tet_colours: int
+    edge_ptr: np.ndarray
+    edge_order: np.ndarray
+    tet_ptr: np.ndarray
+    tet_order: np.ndarray
+
+    @property
+    def num_edges(self):
+        return int(self.edges.shape[0])
+
+    @property
+    def num_tets(self):
+        return int(self.tets.shape[0])
+
+
+def prepare_mesh(rest_pos, inv_mass, tets) -> OracleMesh:
+    """Orientation, rest values, edges and colours of one mesh, from raw input."""
+    lib = _load()
+    rest = _f64(rest_pos).reshape(-1, 3)
+    w = _f64(inv_mass).reshape(-1)
+    tin = _i32(tets).reshape(-1, 4)
+    V, T = rest.shape[0], tin.shape[0]
+    tout = np.zeros((max(T, 1), 4), dtype=np.int32)
+    vol = np.zeros(max(T, 1))
+    kept = ctypes.c_int(0)
+    rc = lib.oracle_setup_tets(V, _dp(rest), _dp(w), T, _ip(tin), _ip(tout), _dp(vol),
+                               ctypes.byref(kept))
+    if rc != 0:
+        raise OracleError(f"oracle_setup_tets failed: {rc}")
+    T = kept.value
+    tout, vol = tout[:T].copy(), vol[:T].copy()
+    edges = np.zeros((max(6 * T, 1), 2), dtype=np.int32)
+    rl = np.zeros(max(6 * T, 1))
+    ne = ctypes.c_int(0)
+    rc = lib.oracle_setup_edges(V, _dp(rest), _dp(w), T, _ip(tout), _ip(edges), _dp(rl),
+                                ctypes.byref(ne))
+    if rc != 0:
+        raise OracleError(f"oracle_setup_edges failed: {rc}")
+    E = ne.value
+    edges, rl = edges[:E].copy(), rl[:E].copy()
+    ecol, nec = greedy_colour(V, edges) if E else (np.zeros(0, np.int32), 0)
+    tcol, ntc = greedy_colour(V, tout) if T else (np.zeros(0, np.int32), 0)
+    eptr, eorder = schedule(ecol, nec)
+    tptr, torder = schedule(tcol, ntc)
+    return OracleMesh(V, w, rest, tout, vol, edges, rl, ecol, tcol, nec, ntc,
+                      eptr, eorder, tptr, torder)
+
+
+# ---------------------------------------------------------------- simulation
+@dataclass
+class OracleParams:
+    dt: float
+    substeps: int
+    iterations: int
+    gravity: tuple
+    num_tools: int = 1
+    tool_radius: tuple = (0.005, 0.005)
+
+
+@dataclass
+class OracleResult:
+    x: np.ndarray
+    v: np.ndarray
+    lam: np.ndarray | None = None
+    contacts: np.ndarray | None = None        # [steps][tools][V]
+    contact_count: np.ndarray | None = None   # [steps][tools]
+    residual: np.ndarray | None = None        # [steps][substeps][2]
+
+
+def run_env(mesh: OracleMesh, compliance, params: OracleParams, tool_pos, num_steps,
+            x0=None, v0=None, want_lambda=False, want_contacts=False, want_residual=False,
+            edge_schedule=None, tet_schedule=None) -> OracleResult:
+    """Advance one environment by ``num_steps`` steps.
+
+    tool_pos: [num_steps][num_tools][3]; compliance: (alpha_edge, alpha_tet).
+    edge_schedule / tet_schedule: optional (ptr, order) overriding the default
+    colour order (used to check independence of the order inside a colour).
+    """
+    lib = _load()
+    V, E, T = mesh.num_vertices, mesh.num_edges, mesh.num_tets
+    nt = int(params.num_tools)
+    x = _f64(mesh.rest if x0 is None else x0).reshape(V, 3).copy()
+    v = np.zeros((V, 3)) if v0 is None else _f64(v0).reshape(V, 3).copy()
+    tp = _f64(tool_pos).reshape(num_steps, nt, 3) if nt else np.zeros((1, 1, 3))
+    radius = _f64(np.asarray(params.tool_radius[:max(nt, 1)]))
+    grav = _f64(params.gravity)
+    eptr, eorder = edge_schedule if edge_schedule is not None else (mesh.edge_ptr, mesh.edge_order)
+    tptr, torder = tet_schedule if tet_schedule is not None else (mesh.tet_ptr, mesh.tet_order)
+    eptr, eorder, tptr, torder = _i32(eptr), _i32(eorder), _i32(tptr), _i32(torder)
+    lam = np.zeros(max(E + T, 1)) if want_lambda else None
+    contacts = np.zeros((max(num_steps, 1), max(nt, 1), V), np.int32) if want_contacts else None
+    ccount = np.zeros((max(num_steps, 1), max(nt, 1)), np.int32) if want_contacts else None
+    resid = np.zeros((max(num_steps, 1), params.substeps, 2)) if want_residual else None
+    edges = mesh.edges if E else np.zeros((1, 2), np.int32)
+    tets = mesh.tets if T else np.zeros((1, 4), np.int32)
+    rl = mesh.rest_length if E else np.ones(1)
+    rv = mesh.rest_volume if T else np.ones(1)
+    rc = lib.oracle_run(V, _dp(mesh.w), E, _ip(_i32(edges)), _dp(_f64(rl)),
+                        T, _ip(_i32(tets)), _dp(_f64(rv)),
+                        len(eptr) - 1, _ip(eptr), _ip(eorder if eorder.size else np.zeros(1, np.int32)),
+                        len(tptr) - 1, _ip(tptr), _ip(torder if torder.size else np.zeros(1, np.int32)),
+                        float(params.dt), int(params.substeps), int(params.iterations), _dp(grav),
+                        float(compliance[0]), float(compliance[1]),
+                        nt, _dp(radius), int(num_steps), _dp(np.ascontiguousarray(tp)),
+                        _dp(x), _dp(v), _dp(lam), _ip(contacts), _ip(ccount), _dp(resid))
+    if rc != 0:
+        raise OracleError(f"oracle_run failed: {rc}")
+    return OracleResult(x, v,
+                        lam[:E + T] if lam is not None else None,
+                        contacts[:num_steps, :nt] if contacts is not None else None,
+                        ccount[:num_steps, :nt] if ccount is not None else None,
+                        resid[:num_steps] if resid is not None else None)
+
+
+def run_batch(meshes, env_mesh, compliance, params: OracleParams, tool_pos, num_steps,
+              env_ids=None, threads=1, **kw):
+    """Run independent environments (optionally on several threads).
+
+    tool_pos: [num_steps][len(env_ids)][tools][3] for the selected envs.
+    Returns a list of OracleResult in env_ids order.
+    """
+    env_ids = list(range(len(env_mesh))) if env_ids is None else list(env_ids)
+
+    def one(n):
+        e = env_ids[n]
+        tp = tool_pos[:, n] if params.num_tools else None
+        return run_env(meshes[int(env_mesh[e])], compliance[e], params, tp, num_steps, **kw)
+
+    if threads <= 1:
+        return [one(n) for n in range(len(env_ids))]
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        return list(pool.map(one, range(len(env_ids))))
+
+
+def contact_candidates_f32(x, inv_mass, centre, radius):
+    """Contact-candidate rule (reading R6) evaluated in single precision with
+    every product and sum rounded separately, as the GPU kernel takes it:
+    d = x - c; d2 = (dx*dx + dy*dy) + dz*dz; candidate iff w > 0 and
+    d2 < (2r)^2 with (2r)^2 rounded to float32."""
+    x = np.asarray(x, dtype=np.float32).reshape(-1, 3)
+    c = np.asarray(centre, dtype=np.float32).reshape(3)
+    d = x - c
+    d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+    reach = np.float32(2.0) * np.float32(radius)
+    reach2 = reach * reach
+    ok = (np.asarray(inv_mass, dtype=np.float32) > 0) & (d2 < reach2)
+    return np.nonzero(ok)[0].astype(np.int32)

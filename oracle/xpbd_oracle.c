@@ -1,0 +1,536 @@
+/*
+ * FP64 oracle for the batched XPBD substep of FF-SRL
+ * (Dall'Alba, Naskret, Kaminska, Korzeniowski: "FF-SRL: High Performance
+ * GPU-Based Surgical Simulation For Robot Learning", arXiv 2503.18616).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, obviously correct
+ * CPU implementation of what the GPU library computes.  Only the tests, the
+ * smoke check and the CPU-baseline leg of the benchmark may build, load or
+ * call it.  It shares no code, header, table or helper with the GPU library,
+ * and the library never calls it.
+ *
+ * What it follows, by passage of the paper:
+ *   Sec. III-A.1      particles with inverse masses w, positions x, velocities v;
+ *                     edges and tetrahedra; rest length and rest volume
+ *                     computed once before the simulation loop.
+ *   Sec. III-A.1 Eq.1 distance constraint C = |x_a - x_b| - d_ab.
+ *   Sec. III-A.1 Eq.2-3 volume constraint C = (1/6)(x_ba x x_ca).x_da - V0.
+ *   Sec. III-A.1 Alg.1 step loop around a substep loop with h = dt/substeps,
+ *                     velocity prediction v + h g, position prediction x + h v,
+ *                     constraint projection, v = (x_new - x_old)/h.
+ *   Sec. III-A.3      tool contact: after the deformation constraints, a
+ *                     penetrating point is pushed out along the penetration
+ *                     direction with stiffness k_c = 1.
+ *   Sec. III-A        the solver is XPBD (the paper's cited method): every
+ *                     constraint j carries a multiplier lambda_j and a compliance
+ *                     alpha_j, alpha~ = alpha / h^2, and one projection is
+ *                       dlambda = (-C - alpha~ lambda) / (sum_i w_i |grad_i C|^2 + alpha~)
+ *                       x_i    += w_i * dlambda * grad_i C
+ *                     With alpha = 0 and lambda = 0 this is exactly the paper's
+ *                     stiffness form (Eq. 1 and corrected Eqs. 2-3) with k = 1.
+ *
+ * Readings taken where the paper is silent, garbled or at odds with the
+ * configurations this oracle serves:
+ *   R1  Gauss-Seidel over graph colours replaces the paper's Jacobi average
+ *       (Sec. III-A.1): all edge colours ascending, then all tetrahedron
+ *       colours ascending, then contact, repeated `iterations` times per substep.
+ *   R2  Eq. 2 as printed permutes the gradient terms and flips one sign; the
+ *       analytic gradients of the printed C are used:
+ *       g_b = x_ca x x_da / 6, g_c = x_da x x_ba / 6, g_d = x_ba x x_ca / 6,
+ *       g_a = -(g_b + g_c + g_d).
+ *   R3  Eq. 3 omits inverse masses; the XPBD denominator sum_i w_i |g_i|^2 is
+ *       used, identical to the paper for uniform free masses.
+ *   R4  lambda is reset to zero at every substep and accumulates over the
+ *       iterations of that substep.
+ *   R5  Pinned particles (w = 0) are not predicted and never move; constraints
+ *       whose particles are all pinned are dropped before colouring.
+ *   R6  The tool pose is constant within a step.  Contact candidates
+ *       K = { i : w_i > 0, |x_i - c|^2 < (2r)^2 } are found once per step on
+ *       the start-of-step positions; the push-out runs after the deformation
+ *       constraints of every iteration: if |x_i - c|^2 < r^2 the particle
+ *       moves to c + r (x_i - c)/|x_i - c|, or to c + (0,0,r) when x_i = c.
+ *   R7  A distance constraint with |x_a - x_b| < 1e-9 m, and any constraint
+ *       whose denominator is <= 1e-30, is skipped.
+ *   R8  Residual of constraint j: (C_j + alpha~_j lambda_j) / s_j with
+ *       s_j = rest length (edges) or rest volume (tetrahedra), evaluated after
+ *       the last iteration of a substep, before the velocity update; reported
+ *       as the RMS and the maximum absolute value over all kept constraints.
+ *   R9  Tetrahedra with negative rest volume have their last two vertices
+ *       swapped; a zero rest volume is an error.
+ *   R10 Edges are the unique vertex pairs of the kept tetrahedra, ordered by
+ *       (smaller id, larger id).  Greedy colouring visits constraints in index
+ *       order and gives each the smallest colour not used by an earlier
+ *       constraint sharing any particle; edges and tetrahedra are coloured
+ *       separately.
+ *
+ * Every function below is pinned by the not-gpu tests (closed forms,
+ * invariants and brute force on tiny meshes).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fused multiply-add, so
+ * that every product and sum is rounded as written).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_E_ARG (-1)
+#define ORACLE_E_MESH (-2)
+#define ORACLE_E_NOMEM (-3)
+
+#define MIN_EDGE_LENGTH 1e-9
+#define MIN_DENOMINATOR 1e-30
+
+/* ------------------------------------------------------------------ */
+/* 3-vector helpers                                                    */
+/* ------------------------------------------------------------------ */
+static void sub3(const double *a, const double *b, double *o)
+{
+    o[0] = a[0] - b[0];
+    o[1] = a[1] - b[1];
+    o[2] = a[2] - b[2];
+}
+
+static double dot3(const double *a, const double *b)
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+static void cross3(const double *a, const double *b, double *o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* ------------------------------------------------------------------ */
+/* Constraint functions (Sec. III-A.1)                                 */
+/* ------------------------------------------------------------------ */
+
+/* Signed volume of tetrahedron (a, b, c, d) (Sec. III-A.1, volume constraint):
+ * (1/6)(x_ba x x_ca) . x_da with x_ba = x_b - x_a, evaluated as the equal
+ * triple product x_ba . (x_ca x x_da / 6), the same expression the constraint
+ * uses, so that a mesh at its rest positions has C = 0 exactly. */
+double oracle_tet_volume(const double *xa, const double *xb, const double *xc,
+                         const double *xd)
+{
+    double xba[3], xca[3], xda[3], gb[3];
+    sub3(xb, xa, xba);
+    sub3(xc, xa, xca);
+    sub3(xd, xa, xda);
+    cross3(xca, xda, gb);
+    for (int k = 0; k < 3; ++k)
+        gb[k] /= 6.0;
+    return dot3(xba, gb);
+}
+
+/* Gradients of the volume constraint (Eqs. 2-3 with reading R2).
+ * x: [4][3] positions of a, b, c, d; g: [4][3] output.  Returns the volume. */
+double oracle_tet_gradients(const double *x, double *g)
+{
+    const double *xa = x, *xb = x + 3, *xc = x + 6, *xd = x + 9;
+    double xba[3], xca[3], xda[3];
+    sub3(xb, xa, xba);
+    sub3(xc, xa, xca);
+    sub3(xd, xa, xda);
+    double *ga = g, *gb = g + 3, *gc = g + 6, *gd = g + 9;
+    cross3(xca, xda, gb);
+    cross3(xda, xba, gc);
+    cross3(xba, xca, gd);
+    for (int k = 0; k < 3; ++k) {
+        gb[k] /= 6.0;
+        gc[k] /= 6.0;
+        gd[k] /= 6.0;
+        ga[k] = -(gb[k] + gc[k] + gd[k]);
+    }
+    return dot3(xba, gb);
+}
+
+/* One XPBD projection of the distance constraint of edge (a, b)
+ * (Eq. 1 in compliance form).  Updates x and *lambda. */
+void oracle_project_distance(double *x, const double *w, int a, int b,
+                             double rest_length, double alpha_tilde, double *lambda)
+{
+    double xab[3];
+    sub3(x + 3 * a, x + 3 * b, xab);
+    double length = sqrt(dot3(xab, xab));
+    if (length < MIN_EDGE_LENGTH)
+        return;
+    double C = length - rest_length;
+    double denominator = w[a] + w[b] + alpha_tilde;
+    if (denominator <= MIN_DENOMINATOR)
+        return;
+    double dlambda = (-C - alpha_tilde * (*lambda)) / denominator;
+    *lambda += dlambda;
+    for (int k = 0; k < 3; ++k) {
+        double n = xab[k] / length;            /* grad_a C = n, grad_b C = -n */
+        x[3 * a + k] += w[a] * dlambda * n;
+        x[3 * b + k] -= w[b] * dlambda * n;
+    }
+}
+
+/* One XPBD projection of the volume constraint of tetrahedron q[4]
+ * (Eqs. 2-3 with readings R2, R3).  Updates x and *lambda. */
+void oracle_project_volume(double *x, const double *w, const int32_t *q,
+                           double rest_volume, double alpha_tilde, double *lambda)
+{
+    double p[12], g[12];
+    for (int i = 0; i < 4; ++i)
+        for (int k = 0; k < 3; ++k)
+            p[3 * i + k] = x[3 * q[i] + k];
+    double volume = oracle_tet_gradients(p, g);
+    double C = volume - rest_volume;
+    double denominator = alpha_tilde;
+    for (int i = 0; i < 4; ++i)
+        denominator += w[q[i]] * dot3(g + 3 * i, g + 3 * i);
+    if (denominator <= MIN_DENOMINATOR)
+        return;
+    double dlambda = (-C - alpha_tilde * (*lambda)) / denominator;
+    *lambda += dlambda;
+    for (int i = 0; i < 4; ++i)
+        for (int k = 0; k < 3; ++k)
+            x[3 * q[i] + k] += w[q[i]] * dlambda * g[3 * i + k];
+}
+
+/* Push a particle out of a sphere tool (Sec. III-A.3, reading R6). */
+void oracle_project_contact(double *xi, const double *centre, double radius)
+{
+    double d[3];
+    sub3(xi, centre, d);
+    double d2 = dot3(d, d);
+    if (!(d2 < radius * radius))
+        return;
+    double dist = sqrt(d2);
+    if (dist > 0.0) {
+        for (int k = 0; k < 3; ++k)
+            xi[k] = centre[k] + d[k] * (radius / dist);
+    } else {
+        xi[0] = centre[0];
+        xi[1] = centre[1];
+        xi[2] = centre[2] + radius;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Set-up (Sec. III-A.1: rest values computed before the loop)         */
+/* ------------------------------------------------------------------ */
+
+/* Keep the tetrahedra that have at least one free particle, orient them
+ * (R9) and compute their rest volumes.  tets_out/rest_volume_out hold up to
+ * T entries; *kept receives the count.  rest: [V][3]. */
+int oracle_setup_tets(int V, const double *rest, const double *w, int T,
+                      const int32_t *tets_in, int32_t *tets_out,
+                      double *rest_volume_out, int *kept)
+{
+    if (V <= 0 || T < 0 || !rest || !w || (T > 0 && (!tets_in || !tets_out || !rest_volume_out)) || !kept)
+        return ORACLE_E_ARG;
+    int n = 0;
+    for (int t = 0; t < T; ++t) {
+        int32_t q[4];
+        for (int i = 0; i < 4; ++i) {
+            q[i] = tets_in[4 * t + i];
+            if (q[i] < 0 || q[i] >= V)
+                return ORACLE_E_ARG;
+        }
+        for (int i = 0; i < 4; ++i)
+            for (int j = i + 1; j < 4; ++j)
+                if (q[i] == q[j])
+                    return ORACLE_E_MESH;
+        if (w[q[0]] == 0.0 && w[q[1]] == 0.0 && w[q[2]] == 0.0 && w[q[3]] == 0.0)
+            continue;
+        double vol = oracle_tet_volume(rest + 3 * q[0], rest + 3 * q[1], rest + 3 * q[2],
+                                       rest + 3 * q[3]);
+        if (vol == 0.0)
+            return ORACLE_E_MESH;
+        if (vol < 0.0) {
+            int32_t s = q[2];
+            q[2] = q[3];
+            q[3] = s;
+            vol = oracle_tet_volume(rest + 3 * q[0], rest + 3 * q[1], rest + 3 * q[2],
+                                    rest + 3 * q[3]);
+        }
+        memcpy(tets_out + 4 * n, q, sizeof q);
+        rest_volume_out[n] = vol;
+        ++n;
+    }
+    *kept = n;
+    return ORACLE_OK;
+}
+
+static int compare_pairs(const void *pa, const void *pb)
+{
+    const int32_t *a = (const int32_t *)pa, *b = (const int32_t *)pb;
+    if (a[0] != b[0])
+        return a[0] < b[0] ? -1 : 1;
+    if (a[1] != b[1])
+        return a[1] < b[1] ? -1 : 1;
+    return 0;
+}
+
+/* Unique edges of the tetrahedra (R10), both-pinned edges dropped (R5), rest
+ * lengths in FP64.  edges_out must hold 6*T pairs; *E receives the count. */
+int oracle_setup_edges(int V, const double *rest, const double *w, int T,
+                       const int32_t *tets, int32_t *edges_out, double *rest_length_out,
+                       int *E)
+{
+    if (V <= 0 || T < 0 || !rest || !w || !E)
+        return ORACLE_E_ARG;
+    if (T == 0) {
+        *E = 0;
+        return ORACLE_OK;
+    }
+    int32_t *pairs = (int32_t *)malloc(sizeof(int32_t) * 12 * (size_t)T);
+    if (!pairs)
+        return ORACLE_E_NOMEM;
+    int n = 0;
+    for (int t = 0; t < T; ++t)
+        for (int i = 0; i < 4; ++i)
+            for (int j = i + 1; j < 4; ++j) {
+                int32_t a = tets[4 * t + i], b = tets[4 * t + j];
+                pairs[2 * n] = a < b ? a : b;
+                pairs[2 * n + 1] = a < b ? b : a;
+                ++n;
+            }
+    qsort(pairs, (size_t)n, 2 * sizeof(int32_t), compare_pairs);
+    int m = 0;
+    for (int i = 0; i < n; ++i) {
+        int32_t a = pairs[2 * i], b = pairs[2 * i + 1];
+        if (i > 0 && a == pairs[2 * i - 2] && b == pairs[2 * i - 1])
+            continue;
+        if (w[a] == 0.0 && w[b] == 0.0)
+            continue;
+        edges_out[2 * m] = a;
+        edges_out[2 * m + 1] = b;
+        double d[3];
+        sub3(rest + 3 * a, rest + 3 * b, d);
+        rest_length_out[m] = sqrt(dot3(d, d));
+        ++m;
+    }
+    free(pairs);
+    *E = m;
+    return ORACLE_OK;
+}
+
+/* Greedy colouring (R10).  verts: [n][k] particle ids of n constraints with
+ * k particles each.  colour_out: [n].  Returns the number of colours, or a
+ * negative error code. */
+int oracle_greedy_colour(int V, int n, int k, const int32_t *verts, int32_t *colour_out)
+{
+    if (V <= 0 || n < 0 || k <= 0 || (n > 0 && (!verts || !colour_out)))
+        return ORACLE_E_ARG;
+    /* incidence lists: constraints touching each particle */
+    int *count = (int *)calloc((size_t)V + 1, sizeof(int));
+    int *incident = (int *)malloc(sizeof(int) * ((size_t)n * k + 1));
+    int *used = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+    if (!count || !incident || !used) {
+        free(count);
+        free(incident);
+        free(used);
+        return ORACLE_E_NOMEM;
+    }
+    for (int i = 0; i < n * k; ++i)
+        count[verts[i] + 1]++;
+    for (int v = 0; v < V; ++v)
+        count[v + 1] += count[v];
+    int *fill = (int *)malloc(sizeof(int) * (size_t)(V + 1));
+    if (!fill) {
+        free(count);
+        free(incident);
+        free(used);
+        return ORACLE_E_NOMEM;
+    }
+    memcpy(fill, count, sizeof(int) * (size_t)(V + 1));
+    for (int c = 0; c < n; ++c)
+        for (int j = 0; j < k; ++j)
+            incident[fill[verts[c * k + j]]++] = c;
+    free(fill);
+
+    int num_colours = 0;
+    for (int c = 0; c < n; ++c) {
+        /* mark the colours of earlier constraints that share a particle */
+        for (int i = 0; i <= num_colours; ++i)
+            used[i] = 0;
+        for (int j = 0; j < k; ++j) {
+            int v = verts[c * k + j];
+            for (int p = count[v]; p < count[v + 1]; ++p) {
+                int other = incident[p];
+                if (other < c)
+                    used[colour_out[other]] = 1;
+            }
+        }
+        int colour = 0;
+        while (used[colour])
+            ++colour;
+        colour_out[c] = colour;
+        if (colour + 1 > num_colours)
+            num_colours = colour + 1;
+    }
+    free(count);
+    free(incident);
+    free(used);
+    return num_colours;
+}
+
+/* ------------------------------------------------------------------ */
+/* Simulation (Algorithm 1 with readings R1-R8)                        */
+/* ------------------------------------------------------------------ */
+
+/* Residual of all kept constraints (R8).  out[0] = RMS, out[1] = max |r|. */
+void oracle_residual(const double *x, int E, const int32_t *edges, const double *rest_length,
+                     int T, const int32_t *tets, const double *rest_volume,
+                     double alpha_tilde_d, double alpha_tilde_v, const double *lambda,
+                     double *out)
+{
+    double sum = 0.0, largest = 0.0;
+    for (int e = 0; e < E; ++e) {
+        double d[3];
+        sub3(x + 3 * edges[2 * e], x + 3 * edges[2 * e + 1], d);
+        double C = sqrt(dot3(d, d)) - rest_length[e];
+        double r = (C + alpha_tilde_d * lambda[e]) / rest_length[e];
+        sum += r * r;
+        if (fabs(r) > largest)
+            largest = fabs(r);
+    }
+    for (int t = 0; t < T; ++t) {
+        const int32_t *q = tets + 4 * t;
+        double C = oracle_tet_volume(x + 3 * q[0], x + 3 * q[1], x + 3 * q[2], x + 3 * q[3])
+                   - rest_volume[t];
+        double r = (C + alpha_tilde_v * lambda[E + t]) / rest_volume[t];
+        sum += r * r;
+        if (fabs(r) > largest)
+            largest = fabs(r);
+    }
+    out[0] = (E + T) > 0 ? sqrt(sum / (double)(E + T)) : 0.0;
+    out[1] = largest;
+}
+
+/*
+ * Advance one environment by num_steps steps.
+ *
+ * Mesh: V particles with inverse masses w; E edges [E][2] with rest lengths;
+ * T tetrahedra [T][4] (oriented) with rest volumes.  Schedule: colour c of the
+ * edges is edge_order[edge_colour_ptr[c] .. edge_colour_ptr[c+1]) (constraint
+ * ids in processing order), likewise for tetrahedra.
+ * Tools: num_tools spheres with radii tool_radius[t]; tool_pos is
+ * [num_steps][num_tools][3].
+ * State: x, v are [V][3], read and overwritten.
+ * Optional outputs (NULL to skip):
+ *   lambda         [E+T]  multipliers after the final iteration of the final substep
+ *   contacts       [num_steps][num_tools][V]  candidate ids ascending, -1 padded
+ *   contact_count  [num_steps][num_tools]
+ *   residual       [num_steps][substeps][2]   (RMS, max) per substep (R8)
+ */
+int oracle_run(int V, const double *w,
+               int E, const int32_t *edges, const double *rest_length,
+               int T, const int32_t *tets, const double *rest_volume,
+               int num_edge_colours, const int32_t *edge_colour_ptr, const int32_t *edge_order,
+               int num_tet_colours, const int32_t *tet_colour_ptr, const int32_t *tet_order,
+               double dt, int substeps, int iterations, const double *gravity,
+               double alpha_d, double alpha_v,
+               int num_tools, const double *tool_radius,
+               int num_steps, const double *tool_pos,
+               double *x, double *v,
+               double *lambda_out, int32_t *contacts, int32_t *contact_count,
+               double *residual)
+{
+    if (V <= 0 || E < 0 || T < 0 || substeps <= 0 || iterations < 0 || num_steps < 0 ||
+        num_tools < 0 || !(dt > 0.0) || !w || !x || !v || !gravity)
+        return ORACLE_E_ARG;
+    if (num_tools > 0 && (!tool_radius || !tool_pos))
+        return ORACLE_E_ARG;
+
+    double *x_prev = (double *)malloc(sizeof(double) * 3 * (size_t)V);
+    double *lambda = (double *)calloc((size_t)(E + T) + 1, sizeof(double));
+    int32_t *candidates = (int32_t *)malloc(sizeof(int32_t) * (size_t)V * (num_tools > 0 ? num_tools : 1));
+    int *num_candidates = (int *)calloc((size_t)(num_tools > 0 ? num_tools : 1), sizeof(int));
+    if (!x_prev || !lambda || !candidates || !num_candidates) {
+        free(x_prev);
+        free(lambda);
+        free(candidates);
+        free(num_candidates);
+        return ORACLE_E_NOMEM;
+    }
+
+    const double h = dt / (double)substeps;                 /* Alg. 1: h = dt / simSubSteps */
+    const double alpha_tilde_d = alpha_d / (h * h);
+    const double alpha_tilde_v = alpha_v / (h * h);
+
+    for (int step = 0; step < num_steps; ++step) {
+        /* evaluate instrument state and the contact candidates (R6) */
+        const double *centres = tool_pos + (size_t)step * num_tools * 3;
+        for (int t = 0; t < num_tools; ++t) {
+            const double *c = centres + 3 * t;
+            double reach = 2.0 * tool_radius[t];
+            int n = 0;
+            for (int i = 0; i < V; ++i) {
+                double d[3];
+                sub3(x + 3 * i, c, d);
+                if (w[i] > 0.0 && dot3(d, d) < reach * reach)
+                    candidates[(size_t)t * V + n++] = i;
+            }
+            num_candidates[t] = n;
+            if (contacts) {
+                int32_t *row = contacts + ((size_t)step * num_tools + t) * V;
+                for (int i = 0; i < V; ++i)
+                    row[i] = i < n ? candidates[(size_t)t * V + i] : -1;
+            }
+            if (contact_count)
+                contact_count[(size_t)step * num_tools + t] = n;
+        }
+
+        for (int sub = 0; sub < substeps; ++sub) {
+            /* predict velocity and position (Alg. 1); pinned particles stay (R5) */
+            for (int i = 0; i < V; ++i) {
+                for (int k = 0; k < 3; ++k)
+                    x_prev[3 * i + k] = x[3 * i + k];
+                if (w[i] > 0.0)
+                    for (int k = 0; k < 3; ++k) {
+                        v[3 * i + k] += h * gravity[k];
+                        x[3 * i + k] += h * v[3 * i + k];
+                    }
+            }
+            for (int j = 0; j < E + T; ++j)                 /* R4 */
+                lambda[j] = 0.0;
+
+            for (int it = 0; it < iterations; ++it) {
+                /* distance constraints, colour by colour (Eq. 1, R1) */
+                for (int c = 0; c < num_edge_colours; ++c)
+                    for (int p = edge_colour_ptr[c]; p < edge_colour_ptr[c + 1]; ++p) {
+                        int e = edge_order[p];
+                        oracle_project_distance(x, w, edges[2 * e], edges[2 * e + 1],
+                                                rest_length[e], alpha_tilde_d, &lambda[e]);
+                    }
+                /* volume constraints, colour by colour (Eqs. 2-3, R1-R3) */
+                for (int c = 0; c < num_tet_colours; ++c)
+                    for (int p = tet_colour_ptr[c]; p < tet_colour_ptr[c + 1]; ++p) {
+                        int t = tet_order[p];
+                        oracle_project_volume(x, w, tets + 4 * t, rest_volume[t],
+                                              alpha_tilde_v, &lambda[E + t]);
+                    }
+                /* tool contact after the deformation constraints (Sec. III-A.3) */
+                for (int t = 0; t < num_tools; ++t)
+                    for (int n = 0; n < num_candidates[t]; ++n) {
+                        int i = candidates[(size_t)t * V + n];
+                        oracle_project_contact(x + 3 * i, centres + 3 * t, tool_radius[t]);
+                    }
+            }
+
+            if (residual)
+                oracle_residual(x, E, edges, rest_length, T, tets, rest_volume,
+                                alpha_tilde_d, alpha_tilde_v, lambda,
+                                residual + 2 * ((size_t)step * substeps + sub));
+
+            /* velocity update v = (x - x_prev) / h (Alg. 1) */
+            for (int i = 0; i < 3 * V; ++i)
+                v[i] = (x[i] - x_prev[i]) / h;
+        }
+    }
+    if (lambda_out)
+        memcpy(lambda_out, lambda, sizeof(double) * (size_t)(E + T));
+    free(x_prev);
+    free(lambda);
+    free(candidates);
+    free(num_candidates);
+    return ORACLE_OK;
+}

@@ -1,0 +1,205 @@
+"""Seeded synthetic inputs for the batched XPBD substep.
+
+This module only *generates inputs*: grid vertex positions and tetrahedron
+connectivity of a hexahedral tissue slab, per-vertex inverse masses (with the
+bottom face pinned), per-environment compliances and per-environment tool
+paths.  It contains none of the solver's arithmetic: rest lengths, rest
+volumes, tetrahedron orientation, edge extraction and constraint colouring
+are computed independently by the library and by the oracle from these raw
+arrays.
+
+The paper's scene is a tissue-retraction slab of about a thousand tetrahedra
+fixed along one side (Sec. IV, Table II); no mesh file is published, so the
+slab below stands in for it.  All units are SI (metres, kilograms, seconds).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Slab extent shared by every workload: 10 x 6 x 3 cm.
+SLAB_EXTENT = (0.10, 0.06, 0.03)
+PARTICLE_MASS = 1.0e-3          # kg per particle
+TOOL_RADIUS = 0.005             # m, kinematic sphere
+GRAVITY = (0.0, 0.0, -9.81)     # m/s^2, z up
+DT = 1.0 / 60.0                 # s per step
+SUBSTEPS = 10
+
+_STREAM_TOOL = 1
+_STREAM_COMPLIANCE = 2
+_STREAM_GRID = 3
+
+
+@dataclass
+class SlabMesh:
+    """Raw slab: vertices, tetrahedra in generation order, inverse masses."""
+    nx: int
+    ny: int
+    nz: int
+    rest_pos: np.ndarray      # [V,3] float32
+    tets: np.ndarray          # [T,4] int32, generation order (orientation NOT fixed)
+    inv_mass: np.ndarray      # [V] float32, 0 on the z = 0 face
+    extent: tuple = field(default=SLAB_EXTENT)
+
+    @property
+    def num_vertices(self) -> int:
+        return int(self.rest_pos.shape[0])
+
+    @property
+    def num_tets(self) -> int:
+        return int(self.tets.shape[0])
+
+
+def vertex_id(i: int, j: int, k: int, nx: int, ny: int) -> int:
+    """Vertex numbering of the grid: x fastest, then y, then z."""
+    return (k * (ny + 1) + j) * (nx + 1) + i
+
+
+def slab_mesh(nx: int, ny: int, nz: int, extent=SLAB_EXTENT,
+              mass: float = PARTICLE_MASS, pin_bottom: bool = True) -> SlabMesh:
+    """Hexahedral slab split into 5 tetrahedra per hexahedron.
+
+    Each hex (i, j, k) contributes a central tetrahedron on its four corners
+    of even global parity (i+j+k+dx+dy+dz even) and one corner tetrahedron
+    per odd-parity corner together with that corner's three edge neighbours.
+    Because the parity is global, the face diagonals of neighbouring hexes
+    coincide and the mesh is conforming.  Vertex order inside a tetrahedron
+    is the generation order; about half come out negatively oriented, which
+    consumers must fix.
+    """
+    if min(nx, ny, nz) < 1:
+        raise ValueError("grid resolution must be >= 1 in every axis")
+    lx, ly, lz = extent
+    ii, jj, kk = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1),
+                             indexing="ij")
+    # flatten with x fastest: order by (k, j, i)
+    order = np.lexsort((ii.ravel(), jj.ravel(), kk.ravel()))
+    gi, gj, gk = ii.ravel()[order], jj.ravel()[order], kk.ravel()[order]
+    pos = np.stack([gi * (lx / nx), gj * (ly / ny), gk * (lz / nz)], axis=1)
+    rest = pos.astype(np.float32)
+
+    tets = []
+    corners = [(dx, dy, dz) for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)]
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                vid = {c: vertex_id(i + c[0], j + c[1], k + c[2], nx, ny) for c in corners}
+                even = [c for c in corners if (i + j + k + sum(c)) % 2 == 0]
+                odd = [c for c in corners if (i + j + k + sum(c)) % 2 == 1]
+                tets.append([vid[c] for c in even])
+                for c in odd:
+                    nbrs = [(1 - c[0], c[1], c[2]), (c[0], 1 - c[1], c[2]), (c[0], c[1], 1 - c[2])]
+                    tets.append([vid[c]] + [vid[n] for n in nbrs])
+    tets = np.asarray(tets, dtype=np.int32)
+
+    inv_mass = np.full(rest.shape[0], 1.0 / mass, dtype=np.float32)
+    if pin_bottom:
+        inv_mass[gk == 0] = 0.0
+    return SlabMesh(nx, ny, nz, rest, tets, inv_mass, tuple(extent))
+
+
+def _env_rng(seed: int, stream: int, env: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(seed), int(stream), int(env)]))
+
+
+def log_uniform_compliance(num_envs: int, lo: float, hi: float, seed: int,
+                           env_ids=None) -> np.ndarray:
+    """Per-environment (edge, tet) compliances, each log-uniform in [lo, hi].
+
+    Environment ``e`` always draws from its own stream, so a subset of
+    environments reproduces exactly the values of the full batch.
+    """
+    env_ids = np.arange(num_envs) if env_ids is None else np.asarray(env_ids)
+    out = np.empty((len(env_ids), 2), dtype=np.float32)
+    for n, e in enumerate(env_ids):
+        u = _env_rng(seed, _STREAM_COMPLIANCE, e).uniform(0.0, 1.0, size=2)
+        out[n] = np.exp(np.log(lo) + u * (np.log(hi) - np.log(lo)))
+    return out
+
+
+def constant_compliance(num_envs: int, alpha_edge: float, alpha_tet: float) -> np.ndarray:
+    out = np.empty((num_envs, 2), dtype=np.float32)
+    out[:, 0] = alpha_edge
+    out[:, 1] = alpha_tet
+    return out
+
+
+def tool_path(num_steps: int, num_envs: int, seed: int, extent=SLAB_EXTENT,
+              radius: float = TOOL_RADIUS, num_tools: int = 1, env_ids=None,
+              step_len: float = 1.0e-3, start_depth: float = 2.0e-3) -> np.ndarray:
+    """Seeded random-walk sphere centres, float32 [num_steps][envs][tools][3].
+
+    Start: slab centre in x, y, sphere pressed ``start_depth`` into the top
+    face.  Each step moves by ``step_len * u`` with u ~ U[-1, 1]^3, clamped to
+    x in [0.2, 0.8] Lx, y in [0.2, 0.8] Ly, z in [Lz - 8 mm, Lz + 10 mm].
+    A second tool (if any) starts mirrored in x.  Environment ``e`` draws from
+    its own stream.
+    """
+    lx, ly, lz = extent
+    env_ids = np.arange(num_envs) if env_ids is None else np.asarray(env_ids)
+    lo = np.array([0.2 * lx, 0.2 * ly, lz - 8.0e-3])
+    hi = np.array([0.8 * lx, 0.8 * ly, lz + 10.0e-3])
+    out = np.empty((num_steps, len(env_ids), num_tools, 3), dtype=np.float32)
+    for n, e in enumerate(env_ids):
+        u = _env_rng(seed, _STREAM_TOOL, e).uniform(-1.0, 1.0, size=(num_steps, num_tools, 3))
+        for t in range(num_tools):
+            fx = 0.5 if num_tools == 1 else (0.35 if t == 0 else 0.65)
+            c = np.array([fx * lx, 0.5 * ly, lz + radius - start_depth])
+            for s in range(num_steps):
+                c = np.clip(c + step_len * u[s, t], lo, hi)
+                out[s, n, t] = c
+    return out
+
+
+def uneven_grids(num_envs: int, seed: int, nx=(6, 20), ny=(4, 12), nz=(2, 6)) -> np.ndarray:
+    """Per-environment slab resolutions drawn uniformly from inclusive ranges."""
+    out = np.empty((num_envs, 3), dtype=np.int32)
+    for e in range(num_envs):
+        r = _env_rng(seed, _STREAM_GRID, e)
+        out[e] = [r.integers(nx[0], nx[1] + 1), r.integers(ny[0], ny[1] + 1),
+                  r.integers(nz[0], nz[1] + 1)]
+    return out
+
+
+@dataclass
+class Workload:
+    """One named workload: mesh(es), per-env mesh id, compliances, solver settings."""
+    name: str
+    meshes: list
+    env_mesh: np.ndarray      # [N] int32
+    compliance: np.ndarray    # [N,2] float32
+    iterations: int
+    num_steps: int
+    seed: int
+    dt: float = DT
+    substeps: int = SUBSTEPS
+    gravity: tuple = GRAVITY
+    num_tools: int = 1
+    tool_radius: tuple = (TOOL_RADIUS, TOOL_RADIUS)
+
+    @property
+    def num_envs(self) -> int:
+        return int(self.env_mesh.shape[0])
+
+    def tools(self, num_steps=None, env_ids=None) -> np.ndarray:
+        n = self.num_steps if num_steps is None else num_steps
+        return tool_path(n, self.num_envs, self.seed, radius=self.tool_radius[0],
+                         num_tools=self.num_tools, env_ids=env_ids)
+
+
+def single_env_workload(seed: int = 0) -> Workload:
+    """One environment, 8x5x3 slab (216 particles, 600 tets), compliances
+    1e-6 (edge) / 1e-7 (tet), 4 iterations, 100 steps."""
+    mesh = slab_mesh(8, 5, 3)
+    return Workload("single-env-8x5x3", [mesh], np.zeros(1, np.int32),
+                    constant_compliance(1, 1e-6, 1e-7), iterations=4, num_steps=100, seed=seed)
+
+
+def batch_workload(num_envs: int = 1024, seed: int = 0, num_steps: int = 1000) -> Workload:
+    """Identical 16x10x4 slabs (935 particles, 3200 tets), per-env compliances
+    log-uniform in [1e-7, 1e-5], 8 iterations, 1000 steps."""
+    mesh = slab_mesh(16, 10, 4)
+    return Workload(f"batch-{num_envs}x16x10x4", [mesh], np.zeros(num_envs, np.int32),
+                    log_uniform_compliance(num_envs, 1e-7, 1e-5, seed),
+                    iterations=8, num_steps=num_steps, seed=seed)
