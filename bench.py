@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Throughput of the batched XPBD step on one MI355X.
+
+A "step" is one simulation step (dt = 1/60 s: 10 substeps, each with the
+prediction, `iterations` colour sweeps over the edge-distance and
+tetrahedral-volume constraints, the tool push-out and the velocity update)
+of every environment of the batch.  The default workload is 1024 identical
+16x10x4 slabs (935 particles, 3200 tetrahedra), per-environment compliances
+log-uniform in [1e-7, 1e-5], per-environment seeded tool paths, 8 iterations,
+1000 steps.  Inputs are resident in GPU memory before the timed region; the
+timed region is K consecutive xpbd_step launches bracketed by HIP events on
+the batch's stream.
+
+Prints one JSON line with the throughput in environment-substeps per second,
+the roofline of the step kernel and the FP64 oracle timed on the host cores
+on a bounded sample of the same workload.
+
+    python bench.py [--steps 1000] [--warmup 20] [--workload batch|single]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "env-substeps/s at fixed constraint residual, plain vs learned warm-start"
+
+# Algorithmic work of one projection / particle update, as written in the kernel
+# (an FMA counts 2 flops; rsq and rcp count 1):
+FLOPS_EDGE = 34        # distance constraint (Eq. 1, compliance form)
+FLOPS_TET = 115        # volume constraint (Eqs. 2-3, compliance form)
+FLOPS_PARTICLE = 18    # prediction + velocity update of a free particle, per substep
+# Algorithmic LDS bytes: particle records (position + inverse mass, 16 B) read,
+# positions (12 B) written, multiplier read + written, constraint record read.
+LDS_EDGE = 2 * 16 + 2 * 12 + 2 * 4 + 8      # 72 B
+LDS_TET = 4 * 16 + 4 * 12 + 2 * 4 + 12      # 132 B
+LDS_PARTICLE = 16 + 16 + 16 + 16            # predict read + write, velocity read, + lambda reset share
+# Algorithmic HBM bytes per environment and launch: positions and velocities in
+# and out (48 B per particle), inverse masses (4 B), tool poses (12 B per tool and step).
+HBM_PARTICLE = 48 + 4
+
+PEAK_FP32_NONPACKED = 256 * 64 * 2 * 2.4e9   # 78.6 TFLOP/s: 256 CU x 64 lanes x FMA x 2.4 GHz
+PEAK_HBM = 8.0e12                            # B/s
+PEAK_LDS = 256 * 128 * 2.4e9                 # 78.6 TB/s at 128 B/clk/CU
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000, help="timed steps")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed steps first")
+    ap.add_argument("--workload", choices=["batch", "single"], default="batch")
+    ap.add_argument("--envs", type=int, default=1024, help="environments of the batch workload")
+    ap.add_argument("--steps-per-launch", type=int, default=1)
+    ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library's choice)")
+    ap.add_argument("--cpu-envs", type=int, default=64, help="oracle sample: environments")
+    ap.add_argument("--cpu-steps", type=int, default=100, help="oracle sample: steps")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "environments are independent, so a multi-GPU run is N copies of this one",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.steps % args.steps_per_launch or args.warmup % args.steps_per_launch:
+        sys.exit("--steps and --warmup must be multiples of --steps-per-launch")
+
+    import numpy as np
+    import torch
+
+    from paper_2503_18616_amd import workloads as W
+    from paper_2503_18616_amd import xpbd
+
+    torch.cuda.set_device(0)
+    total = args.warmup + args.steps
+    if args.workload == "batch":
+        wl = W.batch_workload(args.envs, seed=0, num_steps=total)
+    else:
+        wl = W.single_env_workload(seed=0)
+        wl.num_steps = total
+    m = wl.meshes[0]
+    info = xpbd.xpbd_prepare_mesh(m.rest_pos, m.inv_mass, m.tets)
+    E, T = int(info["edges"].shape[0]), int(info["tets"].shape[0])
+    V = m.num_vertices
+    v_free = int((m.inv_mass > 0).sum())
+    N, S, I = wl.num_envs, wl.substeps, wl.iterations
+
+    tools = torch.from_numpy(wl.tools(total)).cuda()
+    params = xpbd.make_params(wl.dt, S, I, wl.gravity, wl.num_tools, wl.tool_radius,
+                              flags=xpbd.F_RESIDUAL, block_size=args.block)
+    stream = torch.cuda.current_stream()
+    batch = xpbd.Batch([(m.rest_pos, m.inv_mass, m.tets)], wl.env_mesh, wl.compliance, params,
+                       stream=stream.cuda_stream)
+    spl = args.steps_per_launch
+    for s in range(0, args.warmup, spl):
+        batch.step(spl, tools[s:s + spl])
+    torch.cuda.synchronize()
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for s in range(args.warmup, total, spl):
+        batch.step(spl, tools[s:s + spl])
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    launches = args.steps // spl
+    env_substeps = N * args.steps * S
+    value = env_substeps / (ms / 1e3)
+    resid = batch.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)
+    batch.close()
+
+    # roofline of the step kernel (the only kernel in the timed region)
+    launch_s = ms / 1e3 / launches
+    substeps_per_launch = N * spl * S
+    flops = substeps_per_launch * (I * (E * FLOPS_EDGE + T * FLOPS_TET) + v_free * FLOPS_PARTICLE)
+    lds = substeps_per_launch * (I * (E * LDS_EDGE + T * LDS_TET) + V * LDS_PARTICLE)
+    hbm = N * (V * HBM_PARTICLE + spl * wl.num_tools * 12)
+    roofline = {"bound": "alu", "achieved": flops / launch_s / 1e12,
+                "peak": PEAK_FP32_NONPACKED / 1e12, "unit": "TFLOP/s",
+                "frac": flops / launch_s / PEAK_FP32_NONPACKED, "traffic": None,
+                "kernel": "xpbd_step_kernel", "launch_ms": launch_s * 1e3,
+                "flops_per_launch": flops}
+    lds_line = {"achieved": lds / launch_s / 1e9, "peak": PEAK_LDS / 1e9, "unit": "GB/s",
+                "frac": lds / launch_s / PEAK_LDS, "bytes_per_launch": lds}
+    hbm_line = {"achieved": hbm / launch_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": hbm / launch_s / PEAK_HBM, "bytes_per_launch": hbm}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sample_envs = list(range(0, N, max(1, N // args.cpu_envs)))[:args.cpu_envs]
+        f32 = lambda v: float(np.float32(v))
+        om = [oracle.prepare_mesh(m.rest_pos, m.inv_mass, m.tets)]
+        op = oracle.OracleParams(f32(wl.dt), S, I, tuple(f32(g) for g in wl.gravity),
+                                 wl.num_tools, tuple(f32(r) for r in wl.tool_radius))
+        cpu_tools = wl.tools(args.cpu_steps, env_ids=sample_envs)
+        threads = min(16, os.cpu_count() or 1, len(sample_envs))
+        t0 = time.perf_counter()
+        oracle.run_batch(om, wl.env_mesh, wl.compliance, op, cpu_tools, args.cpu_steps,
+                         env_ids=sample_envs, threads=threads)
+        dt = time.perf_counter() - t0
+        cpu = {"value": len(sample_envs) * args.cpu_steps * S / dt, "unit": "env-substeps/s",
+               "cores": threads, "kind": "oracle",
+               "sample": f"{len(sample_envs)} of the {N} environments x {args.cpu_steps} steps "
+                         f"({len(sample_envs) * args.cpu_steps * S} env-substeps, FP64, "
+                         f"{dt:.1f} s wall)"}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "env-substeps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "envs": N, "grid": [m.nx, m.ny, m.nz], "particles": V,
+                   "edges": E, "tets": T, "substeps": S, "iterations": I,
+                   "steps_per_launch": spl, "solver": "plain (no warm start)",
+                   "residual_rms_mean": float(resid[:, 0].mean()),
+                   "residual_max": float(resid[:, 1].max())},
+        "roofline": roofline, "lds": lds_line, "hbm": hbm_line, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

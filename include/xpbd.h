@@ -1,0 +1,175 @@
+/*
+ * xpbd.h -- C ABI of the MI355X batched XPBD substep library (libxpbd.so).
+ *
+ * The library advances many independent soft-tissue environments with the
+ * simulation loop of FF-SRL (Dall'Alba et al., arXiv 2503.18616, Sec. III-A,
+ * Algorithm 1): per step the tool pose is read; per substep velocities and
+ * positions are predicted under gravity, edge-distance (Eq. 1) and
+ * tetrahedral-volume (Eqs. 2-3) constraints are projected in compliance form
+ * with one Lagrange multiplier per constraint, the particles are pushed out of
+ * the tool (Sec. III-A.3), and velocities are recomputed from the position
+ * change.  All environments' arrays are concatenated, one array per variable
+ * (Sec. III-B).
+ *
+ * Conventions shared by every call:
+ *   - Units are SI.  Positions are float32 [V][3] (x, y, z per particle).
+ *   - Environment e owns particles [env_offset[e], env_offset[e+1]) of the
+ *     concatenated particle arrays, in the order of its mesh's vertex ids.
+ *   - No call throws; every failure returns a negative xpbd_status and leaves
+ *     a message for xpbd_last_error() on the calling thread.
+ *   - Pointers documented "host or device" may point to host memory or to
+ *     device memory of the batch's GPU; the library tells them apart.
+ *   - A batch is bound to the HIP device that was current at creation and to
+ *     the stream given then.  Calls on one batch must not overlap.
+ */
+#ifndef XPBD_H
+#define XPBD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xpbd_batch xpbd_batch; /* opaque; freed by xpbd_destroy_batch */
+
+typedef enum {
+    XPBD_OK = 0,
+    XPBD_E_ARG = -1,       /* null pointer, bad count, bad size or non-finite parameter */
+    XPBD_E_MESH = -2,      /* index out of range, repeated vertex, zero-volume tetrahedron,
+                              more than 65535 particles, non-finite rest position or mass */
+    XPBD_E_CAPACITY = -3,  /* a mesh does not fit the per-workgroup LDS plan */
+    XPBD_E_HIP = -4,       /* a HIP runtime call failed (message names it) */
+    XPBD_E_NONFINITE = -5, /* some environment's state became NaN or infinite */
+    XPBD_E_STATE = -6      /* buffer size does not match the field, or unknown field */
+} xpbd_status;
+
+/* Fields for xpbd_read_state / xpbd_write_state / xpbd_field_bytes. */
+enum {
+    XPBD_FIELD_POS = 0,            /* float [sum V][3]  positions (read, write) */
+    XPBD_FIELD_VEL = 1,            /* float [sum V][3]  velocities (read, write) */
+    XPBD_FIELD_LAMBDA = 2,         /* float [sum over envs of (E_m + T_m)] multipliers after the
+                                      last iteration of the last substep, per env: edges in
+                                      constraint order, then tetrahedra.  Needs XPBD_F_LAMBDA. */
+    XPBD_FIELD_CONTACTS = 3,       /* int32 [num_tools][sum V]: for tool t and env e, the
+                                      contact candidates of the last step as ascending local
+                                      particle ids at [t][env_offset[e] ...], padded with -1 */
+    XPBD_FIELD_CONTACT_COUNTS = 4, /* int32 [N][num_tools] number of candidates of the last step */
+    XPBD_FIELD_COLOURS = 5,        /* int32 [sum over meshes of (E_m + T_m)] colour of every kept
+                                      constraint of every mesh, mesh order, edges then tetrahedra */
+    XPBD_FIELD_RESIDUAL = 6,       /* float [N][2] (RMS, max |r|) of the constraint residual
+                                      (C + alpha~ lambda)/rest, at the last substep of the last
+                                      xpbd_step call.  Needs XPBD_F_RESIDUAL. */
+    XPBD_FIELD_ENV_OFFSETS = 7,    /* int32 [N+1] particle offsets of the environments */
+    XPBD_FIELD_NONFINITE = 8,      /* int32 [N] 1 where the env's state went non-finite */
+    XPBD_FIELD_COUNT = 9
+};
+
+/* Flags for xpbd_params.flags. */
+#define XPBD_F_RESIDUAL 0x1u /* compute the residual at the end of every xpbd_step call */
+#define XPBD_F_LAMBDA 0x2u   /* store the multipliers at the end of every xpbd_step call */
+
+/*
+ * One tetrahedral mesh (Sec. III-A.1: V particles with masses, a tetrahedral
+ * mesh, edges between adjacent particles).  Host memory, read during
+ * xpbd_create_batch only.
+ *   rest_pos  [V][3]  rest positions; also the initial positions
+ *   inv_mass  [V]     inverse masses w = 1/m; 0 pins a particle
+ *   tets      [T][4]  particle ids.  The library swaps the last two ids of a
+ *                     tetrahedron whose rest volume is negative.
+ * Edges are the unique particle pairs of the tetrahedra; constraints whose
+ * particles are all pinned are dropped.  Rest lengths and volumes are taken
+ * from rest_pos in double precision and rounded to float.
+ */
+typedef struct {
+    int32_t num_vertices; /* V, 1 .. 65535 */
+    int32_t num_tets;     /* T, >= 1 */
+    const float *rest_pos;
+    const float *inv_mass;
+    const int32_t *tets;
+} xpbd_mesh;
+
+/*
+ * Solver settings (Algorithm 1: dt, simSubSteps; the iteration count of the
+ * Gauss-Seidel colour sweeps per substep; Sec. III-A.2/3: the tool).
+ */
+typedef struct {
+    float dt;            /* step length, > 0 */
+    int32_t substeps;    /* substeps per step, >= 1; h = dt / substeps */
+    int32_t iterations;  /* colour sweeps per substep, >= 0 */
+    float gravity[3];    /* m/s^2 */
+    int32_t num_tools;   /* kinematic spheres, 0 .. 2 */
+    float tool_radius[2];/* m, > 0 for each used tool */
+    uint32_t flags;      /* XPBD_F_* */
+    int32_t block_size;  /* threads per workgroup: 0 = chosen by the library, else a
+                            multiple of 64 in [64, 1024] */
+} xpbd_params;
+
+/*
+ * Create a batch of num_envs environments; environment e uses mesh
+ * env_mesh[e] and compliances compliance[2e] (edges) and compliance[2e+1]
+ * (tetrahedra), both >= 0 and finite (alpha~ = alpha / h^2).  All inputs are
+ * host memory and are copied.  Every environment starts at its mesh's rest
+ * positions with zero velocity.  hip_stream (a hipStream_t, NULL for the
+ * default stream) orders every later device operation of the batch.
+ * On failure *out is set to NULL.
+ */
+xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
+                              const int32_t *env_mesh, int32_t num_envs,
+                              const float *compliance, const xpbd_params *params,
+                              void *hip_stream, xpbd_batch **out);
+
+/*
+ * Advance every environment by num_steps steps in one kernel launch.
+ * tool_pos: float [num_steps][N][num_tools][3] sphere centres, host or
+ * device, ignored when num_tools == 0.  Asynchronous on the batch's stream
+ * (a host tool_pos is copied before the call returns).  num_steps == 0 does
+ * nothing.
+ */
+xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos);
+
+/*
+ * Copy a field (XPBD_FIELD_*) into dst (host or device), dst_bytes must equal
+ * xpbd_field_bytes.  Ordered after all earlier work on the batch's stream;
+ * returns after the copy has completed.  Returns XPBD_E_NONFINITE (after
+ * copying) when any environment's state is non-finite.
+ */
+xpbd_status xpbd_read_state(xpbd_batch *b, int32_t field, void *dst, size_t dst_bytes);
+
+/*
+ * Overwrite XPBD_FIELD_POS or XPBD_FIELD_VEL from src (host or device,
+ * [sum V][3] float).  Pinned particles take the given values too.  Clears
+ * the non-finite flags.  Used to resume from a saved state: a state saved
+ * between xpbd_step calls is exactly (positions, velocities).
+ */
+xpbd_status xpbd_write_state(xpbd_batch *b, int32_t field, const void *src, size_t src_bytes);
+
+/* Byte size of a field of this batch. */
+xpbd_status xpbd_field_bytes(const xpbd_batch *b, int32_t field, size_t *bytes);
+
+/* Free the batch and its device memory (waits for its stream).  NULL is ignored. */
+void xpbd_destroy_batch(xpbd_batch *b);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *xpbd_last_error(void);
+
+/*
+ * Host-only mesh set-up, the same the batch performs at creation, for
+ * inspection without a GPU.  counts[0..3] receive (E, T, edge colours,
+ * tetrahedron colours) of the kept constraints.  Each output pointer may be
+ * NULL; otherwise it must hold:
+ *   edges       int32 [E][2]  ascending (smaller id, larger id)
+ *   tets        int32 [T][4]  kept tetrahedra in input order, oriented
+ *   colours     int32 [E+T]   greedy colour of each constraint
+ *   rest        float [E+T]   rest lengths, then rest volumes
+ * Call once with NULL outputs to size them.
+ */
+xpbd_status xpbd_prepare_mesh(const xpbd_mesh *mesh, int32_t *counts, int32_t *edges,
+                              int32_t *tets, int32_t *colours, float *rest);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XPBD_H */

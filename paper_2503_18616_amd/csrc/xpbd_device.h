@@ -1,0 +1,115 @@
+// Device-side data layout of the XPBD library, shared by the runtime (host)
+// and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace xpbd {
+
+// One distinct mesh, in the order the kernel consumes it.  Constraint arrays
+// are in schedule order: colour-major, constraint id ascending inside a colour.
+struct MeshDev {
+    int32_t num_vertices;
+    int32_t num_edges;
+    int32_t num_tets;
+    int32_t num_edge_colours;
+    int32_t num_tet_colours;
+    int32_t pad[3];
+    const uint32_t *edge_pair;   // [E]  a | b << 16 (local particle ids)
+    const float *edge_rest;      // [E]  rest length
+    const uint2 *tet_quad;       // [T]  (a | b << 16, c | d << 16), oriented
+    const float *tet_rest;       // [T]  rest volume
+    const int32_t *edge_ptr;     // [edge colours + 1] schedule offsets
+    const int32_t *tet_ptr;      // [tet colours + 1]
+    const int32_t *edge_id;      // [E]  constraint id of each schedule slot
+    const int32_t *tet_id;       // [T]
+    const float *inv_mass;       // [V]
+};
+
+struct EnvDev {
+    int32_t mesh;
+    int32_t particle_offset;     // into the concatenated particle arrays
+    int32_t lambda_offset;       // into the concatenated multiplier array
+    int32_t pad;
+};
+
+struct StepArgs {
+    const MeshDev *meshes;
+    const EnvDev *envs;
+    const float *compliance;     // [N][2] (edge, tet)
+    const float *tool_pos;       // [num_steps][N][num_tools][3]
+    float *pos;                  // [3][total_particles]  SoA
+    float *vel;                  // [3][total_particles]  SoA
+    float *lambda_out;           // [sum (E+T)] or null
+    int32_t *contacts;           // [num_tools][total_particles]
+    int32_t *contact_counts;     // [N][num_tools]
+    float *residual;             // [N][2] or null
+    int32_t *nonfinite;          // [N]
+    int32_t num_envs;
+    int32_t total_particles;
+    int32_t num_steps;
+    int32_t substeps;
+    int32_t iterations;
+    int32_t num_tools;
+    float h;                     // dt / substeps
+    float inv_h;
+    float gravity[3];
+    float tool_radius[2];
+    float tool_radius2[2];       // r^2
+    float tool_reach2[2];        // (2r)^2, rounded to float
+};
+
+// Per-workgroup LDS layout for an environment of a given mesh.
+struct LdsLayout {
+    uint32_t xw;        // float4 [V]
+    uint32_t lambda;    // float [E + T]
+    uint32_t contacts;  // uint16 [tools][V]
+    uint32_t edge_pair; // uint32 [E]  (staged topology only)
+    uint32_t edge_rest; // float [E]
+    uint32_t tet_quad;  // uint2 [T]
+    uint32_t tet_rest;  // float [T]
+    uint32_t scratch;   // 64 x uint32 for reductions and counts
+    uint32_t total;
+};
+
+__host__ __device__ inline uint32_t align_up(uint32_t x, uint32_t a) { return (x + a - 1) / a * a; }
+
+__host__ __device__ inline LdsLayout lds_layout(int32_t V, int32_t E, int32_t T, int32_t tools,
+                                                bool stage_topology)
+{
+    LdsLayout l;
+    uint32_t o = 0;
+    l.xw = o;
+    o += 16u * (uint32_t)V;
+    l.lambda = o;
+    o = align_up(o + 4u * (uint32_t)(E + T), 16);
+    l.contacts = o;
+    o = align_up(o + 2u * (uint32_t)(tools > 0 ? tools : 0) * (uint32_t)V, 16);
+    if (stage_topology) {
+        l.edge_pair = o;
+        o += 4u * (uint32_t)E;
+        l.edge_rest = o;
+        o = align_up(o + 4u * (uint32_t)E, 16);
+        l.tet_quad = o;
+        o += 8u * (uint32_t)T;
+        l.tet_rest = o;
+        o = align_up(o + 4u * (uint32_t)T, 16);
+    } else {
+        l.edge_pair = l.edge_rest = l.tet_quad = l.tet_rest = 0;
+    }
+    l.scratch = o;
+    o += 64u * 4u;
+    l.total = o;
+    return l;
+}
+
+// Launchers (xpbd_kernels.hip).
+hipError_t launch_step(const StepArgs &args, int block, int particles_per_thread,
+                       bool stage_topology, uint32_t lds_bytes, bool want_residual,
+                       hipStream_t stream);
+hipError_t launch_soa_to_aos(const float *soa, float *aos, int32_t n, hipStream_t stream);
+hipError_t launch_aos_to_soa(const float *aos, float *soa, int32_t n, hipStream_t stream);
+
+}  // namespace xpbd

@@ -1,0 +1,488 @@
+// HIP kernels of the batched XPBD substep for gfx950 (CDNA4).
+//
+// One workgroup advances one environment through num_steps steps of
+// Algorithm 1 of FF-SRL (Sec. III-A.1): per step the tool pose is read and
+// the contact candidates are collected; per substep the particles are
+// predicted, the multipliers reset, and `iterations` Gauss-Seidel sweeps
+// project the edge-distance (Eq. 1) and tetrahedral-volume (Eqs. 2-3)
+// constraints in compliance form, colour by colour, followed by the tool
+// push-out (Sec. III-A.3); velocities are then recomputed from the position
+// change.
+//
+// Data placement: the environment's particles live in LDS as float4
+// (x, y, z, inverse mass) for the whole launch, the multipliers in LDS, the
+// constraint lists either staged in LDS or read from global memory (they are
+// shared by every environment of a mesh and stay cache-resident).  Each
+// thread keeps the velocity and start-of-substep position of its particles
+// (i = k * blockDim + tid) in registers.  Inside a colour no two constraints
+// share a particle, so the lanes of the workgroup project one colour's
+// constraints concurrently without atomics; a workgroup barrier separates the
+// colours.  Global state is read and written once per launch in
+// structure-of-arrays layout, coalesced across lanes.
+#include <hip/hip_runtime.h>
+
+#include "xpbd_device.h"
+
+namespace xpbd {
+namespace {
+
+constexpr float kMinEdgeLength2 = 1e-18f;   // skip distance constraints shorter than 1e-9 m
+constexpr float kMinDenominator = 1e-30f;
+constexpr float kSixth = 1.0f / 6.0f;
+constexpr float kThirtySixth = 1.0f / 36.0f;
+
+__device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Distance constraint C = |x_a - x_b| - d (Eq. 1), one XPBD projection.
+__device__ __forceinline__ void project_edge(float4 *xw, float *lam, int slot, uint32_t pair,
+                                             float rest, float alpha_tilde)
+{
+    const int a = (int)(pair & 0xffffu), b = (int)(pair >> 16);
+    float4 pa = xw[a];
+    float4 pb = xw[b];
+    const float dx = pa.x - pb.x, dy = pa.y - pb.y, dz = pa.z - pb.z;
+    const float l2 = dx * dx + dy * dy + dz * dz;
+    if (!(l2 >= kMinEdgeLength2))
+        return;
+    const float inv_len = fast_rsq(l2);
+    const float C = l2 * inv_len - rest;
+    const float denom = pa.w + pb.w + alpha_tilde;
+    if (!(denom > kMinDenominator))
+        return;
+    const float l = lam[slot];
+    const float dl = (-C - alpha_tilde * l) * fast_rcp(denom);
+    lam[slot] = l + dl;
+    const float s = dl * inv_len;          // dlambda times the unit direction's scale
+    const float sa = pa.w * s, sb = pb.w * s;
+    pa.x += sa * dx;
+    pa.y += sa * dy;
+    pa.z += sa * dz;
+    pb.x -= sb * dx;
+    pb.y -= sb * dy;
+    pb.z -= sb * dz;
+    xw[a] = pa;
+    xw[b] = pb;
+}
+
+// Volume constraint C = (1/6)(x_ba x x_ca).x_da - V0 (Eqs. 2-3 with the
+// analytic gradients), one XPBD projection.  G_i are six times the gradients.
+__device__ __forceinline__ void project_tet(float4 *xw, float *lam, int slot, uint2 quad,
+                                            float rest, float alpha_tilde)
+{
+    const int a = (int)(quad.x & 0xffffu), b = (int)(quad.x >> 16);
+    const int c = (int)(quad.y & 0xffffu), d = (int)(quad.y >> 16);
+    float4 pa = xw[a];
+    float4 pb = xw[b];
+    float4 pc = xw[c];
+    float4 pd = xw[d];
+    const float bax = pb.x - pa.x, bay = pb.y - pa.y, baz = pb.z - pa.z;
+    const float cax = pc.x - pa.x, cay = pc.y - pa.y, caz = pc.z - pa.z;
+    const float dax = pd.x - pa.x, day = pd.y - pa.y, daz = pd.z - pa.z;
+    // G_b = x_ca x x_da, G_c = x_da x x_ba, G_d = x_ba x x_ca, G_a = -(G_b + G_c + G_d)
+    const float gbx = cay * daz - caz * day, gby = caz * dax - cax * daz, gbz = cax * day - cay * dax;
+    const float gcx = day * baz - daz * bay, gcy = daz * bax - dax * baz, gcz = dax * bay - day * bax;
+    const float gdx = bay * caz - baz * cay, gdy = baz * cax - bax * caz, gdz = bax * cay - bay * cax;
+    const float gax = -(gbx + gcx + gdx), gay = -(gby + gcy + gdy), gaz = -(gbz + gcz + gdz);
+    const float C = (bax * gbx + bay * gby + baz * gbz) * kSixth - rest;
+    const float wg = pa.w * (gax * gax + gay * gay + gaz * gaz) +
+                     pb.w * (gbx * gbx + gby * gby + gbz * gbz) +
+                     pc.w * (gcx * gcx + gcy * gcy + gcz * gcz) +
+                     pd.w * (gdx * gdx + gdy * gdy + gdz * gdz);
+    const float denom = wg * kThirtySixth + alpha_tilde;
+    if (!(denom > kMinDenominator))
+        return;
+    const float l = lam[slot];
+    const float dl = (-C - alpha_tilde * l) * fast_rcp(denom);
+    lam[slot] = l + dl;
+    const float s = dl * kSixth;
+    const float sa = pa.w * s, sb = pb.w * s, sc = pc.w * s, sd = pd.w * s;
+    pa.x += sa * gax;
+    pa.y += sa * gay;
+    pa.z += sa * gaz;
+    pb.x += sb * gbx;
+    pb.y += sb * gby;
+    pb.z += sb * gbz;
+    pc.x += sc * gcx;
+    pc.y += sc * gcy;
+    pc.z += sc * gcz;
+    pd.x += sd * gdx;
+    pd.y += sd * gdy;
+    pd.z += sd * gdz;
+    xw[a] = pa;
+    xw[b] = pb;
+    xw[c] = pc;
+    xw[d] = pd;
+}
+
+// Contact-candidate test in float32 with every product and sum rounded
+// separately (no fused multiply-add), so the host can repeat it bit for bit.
+__device__ __forceinline__ bool within_reach(float4 p, float cx, float cy, float cz, float reach2)
+{
+#pragma clang fp contract(off)
+    const float dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
+    const float d2 = (dx * dx + dy * dy) + dz * dz;
+    return p.w > 0.0f && d2 < reach2;
+}
+
+// Push a particle out of a sphere (Sec. III-A.3, k_c = 1).
+__device__ __forceinline__ void project_contact(float4 *xw, int i, float cx, float cy, float cz,
+                                                float r, float r2)
+{
+    float4 p = xw[i];
+    const float dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
+    const float d2 = dx * dx + dy * dy + dz * dz;
+    if (!(d2 < r2))
+        return;
+    if (d2 > 0.0f) {
+        const float s = r * fast_rsq(d2);
+        p.x = cx + dx * s;
+        p.y = cy + dy * s;
+        p.z = cz + dz * s;
+    } else {
+        p.x = cx;
+        p.y = cy;
+        p.z = cz + r;
+    }
+    xw[i] = p;
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int PPT, bool STAGE, bool RESIDUAL>
+__global__ void __launch_bounds__(1024) xpbd_step_kernel(StepArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int env = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int B = blockDim.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int num_waves = B >> 6;
+
+    const EnvDev ed = A.envs[env];
+    const MeshDev md = A.meshes[ed.mesh];
+    const int V = md.num_vertices, E = md.num_edges, T = md.num_tets;
+    const int tools = A.num_tools;
+    const LdsLayout L = lds_layout(V, E, T, tools, STAGE);
+    float4 *xw = reinterpret_cast<float4 *>(smem + L.xw);
+    float *lam = reinterpret_cast<float *>(smem + L.lambda);
+    uint16_t *clist = reinterpret_cast<uint16_t *>(smem + L.contacts);
+    uint32_t *scratch = reinterpret_cast<uint32_t *>(smem + L.scratch);
+    const uint32_t *e_pair = md.edge_pair;
+    const float *e_rest = md.edge_rest;
+    const uint2 *t_quad = md.tet_quad;
+    const float *t_rest = md.tet_rest;
+    if constexpr (STAGE) {
+        uint32_t *sp = reinterpret_cast<uint32_t *>(smem + L.edge_pair);
+        float *sr = reinterpret_cast<float *>(smem + L.edge_rest);
+        uint2 *sq = reinterpret_cast<uint2 *>(smem + L.tet_quad);
+        float *st = reinterpret_cast<float *>(smem + L.tet_rest);
+        for (int j = tid; j < E; j += B) {
+            sp[j] = md.edge_pair[j];
+            sr[j] = md.edge_rest[j];
+        }
+        for (int j = tid; j < T; j += B) {
+            sq[j] = md.tet_quad[j];
+            st[j] = md.tet_rest[j];
+        }
+        e_pair = sp;
+        e_rest = sr;
+        t_quad = sq;
+        t_rest = st;
+    }
+
+    const float h = A.h, inv_h = A.inv_h;
+    const float gx = A.gravity[0], gy = A.gravity[1], gz = A.gravity[2];
+    const float alpha_d = A.compliance[2 * env] * inv_h * inv_h;   // alpha~ = alpha / h^2
+    const float alpha_v = A.compliance[2 * env + 1] * inv_h * inv_h;
+    const int NP = A.total_particles;
+    const int off = ed.particle_offset;
+
+    // state: positions (+ inverse mass) to LDS, velocities to registers
+    float vx[PPT], vy[PPT], vz[PPT], kx[PPT], ky[PPT], kz[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int i = k * B + tid;
+        vx[k] = vy[k] = vz[k] = kx[k] = ky[k] = kz[k] = 0.0f;
+        if (i < V) {
+            xw[i] = make_float4(A.pos[off + i], A.pos[NP + off + i], A.pos[2 * NP + off + i],
+                                md.inv_mass[i]);
+            vx[k] = A.vel[off + i];
+            vy[k] = A.vel[NP + off + i];
+            vz[k] = A.vel[2 * NP + off + i];
+        }
+    }
+    __syncthreads();
+
+    int count[2] = {0, 0};
+    float cx[2] = {0.f, 0.f}, cy[2] = {0.f, 0.f}, cz[2] = {0.f, 0.f};
+    const int last_step = A.num_steps - 1;
+    for (int step = 0; step < A.num_steps; ++step) {
+        // instrument state and contact candidates on the start-of-step positions
+        for (int t = 0; t < tools; ++t) {
+            const float *c = A.tool_pos + (((size_t)step * A.num_envs + env) * tools + t) * 3;
+            cx[t] = c[0];
+            cy[t] = c[1];
+            cz[t] = c[2];
+            const float reach2 = A.tool_reach2[t];
+            uint16_t *list = clist + t * V;
+            int base = 0;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int i = k * B + tid;
+                const bool flag = i < V && within_reach(xw[i], cx[t], cy[t], cz[t], reach2);
+                const uint64_t mask = __ballot(flag);
+                if (lane == 0)
+                    scratch[wave] = (uint32_t)__popcll(mask);
+                __syncthreads();
+                int before = 0, total = 0;
+                for (int w = 0; w < num_waves; ++w) {
+                    const int n = (int)scratch[w];
+                    before += w < wave ? n : 0;
+                    total += n;
+                }
+                if (flag)
+                    list[base + before + __popcll(mask & __lanemask_lt())] = (uint16_t)i;
+                base += total;
+                __syncthreads();
+            }
+            count[t] = base;
+        }
+
+        for (int sub = 0; sub < A.substeps; ++sub) {
+            // predict velocity and position (Alg. 1); pinned particles stay put
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int i = k * B + tid;
+                if (i < V) {
+                    float4 p = xw[i];
+                    kx[k] = p.x;
+                    ky[k] = p.y;
+                    kz[k] = p.z;
+                    if (p.w > 0.0f) {
+                        vx[k] += h * gx;
+                        vy[k] += h * gy;
+                        vz[k] += h * gz;
+                        p.x += h * vx[k];
+                        p.y += h * vy[k];
+                        p.z += h * vz[k];
+                        xw[i] = p;
+                    }
+                }
+            }
+            for (int j = tid; j < E + T; j += B)
+                lam[j] = 0.0f;
+            __syncthreads();
+
+            for (int it = 0; it < A.iterations; ++it) {
+                for (int c = 0; c < md.num_edge_colours; ++c) {
+                    const int end = md.edge_ptr[c + 1];
+                    for (int j = md.edge_ptr[c] + tid; j < end; j += B)
+                        project_edge(xw, lam, j, e_pair[j], e_rest[j], alpha_d);
+                    __syncthreads();
+                }
+                for (int c = 0; c < md.num_tet_colours; ++c) {
+                    const int end = md.tet_ptr[c + 1];
+                    for (int j = md.tet_ptr[c] + tid; j < end; j += B)
+                        project_tet(xw, lam + E, j, t_quad[j], t_rest[j], alpha_v);
+                    __syncthreads();
+                }
+                for (int t = 0; t < tools; ++t) {
+                    if (count[t] == 0)
+                        continue;
+                    const uint16_t *list = clist + t * V;
+                    for (int n = tid; n < count[t]; n += B)
+                        project_contact(xw, list[n], cx[t], cy[t], cz[t], A.tool_radius[t],
+                                        A.tool_radius2[t]);
+                    __syncthreads();
+                }
+            }
+
+            if constexpr (RESIDUAL) {
+                if (step == last_step && sub == A.substeps - 1) {
+                    float sum = 0.0f, big = 0.0f;
+                    for (int j = tid; j < E; j += B) {
+                        const uint32_t pr = e_pair[j];
+                        const float4 pa = xw[pr & 0xffffu], pb = xw[pr >> 16];
+                        const float dx = pa.x - pb.x, dy = pa.y - pb.y, dz = pa.z - pb.z;
+                        const float len = sqrtf(dx * dx + dy * dy + dz * dz);
+                        const float r = (len - e_rest[j] + alpha_d * lam[j]) / e_rest[j];
+                        sum += r * r;
+                        big = fmaxf(big, fabsf(r));
+                    }
+                    for (int j = tid; j < T; j += B) {
+                        const uint2 q = t_quad[j];
+                        const float4 pa = xw[q.x & 0xffffu], pb = xw[q.x >> 16];
+                        const float4 pc = xw[q.y & 0xffffu], pd = xw[q.y >> 16];
+                        const float bax = pb.x - pa.x, bay = pb.y - pa.y, baz = pb.z - pa.z;
+                        const float cax = pc.x - pa.x, cay = pc.y - pa.y, caz = pc.z - pa.z;
+                        const float dax = pd.x - pa.x, day = pd.y - pa.y, daz = pd.z - pa.z;
+                        const float vol = (bax * (cay * daz - caz * day) + bay * (caz * dax - cax * daz) +
+                                           baz * (cax * day - cay * dax)) * kSixth;
+                        const float r = (vol - t_rest[j] + alpha_v * lam[E + j]) / t_rest[j];
+                        sum += r * r;
+                        big = fmaxf(big, fabsf(r));
+                    }
+                    sum = wave_sum(sum);
+                    big = wave_max(big);
+                    float *fs = reinterpret_cast<float *>(scratch);
+                    if (lane == 0) {
+                        fs[wave] = sum;
+                        fs[32 + wave] = big;
+                    }
+                    __syncthreads();
+                    if (tid == 0) {
+                        float s = 0.0f, m = 0.0f;
+                        for (int w = 0; w < num_waves; ++w) {
+                            s += fs[w];
+                            m = fmaxf(m, fs[32 + w]);
+                        }
+                        A.residual[2 * env] = E + T > 0 ? sqrtf(s / (float)(E + T)) : 0.0f;
+                        A.residual[2 * env + 1] = m;
+                    }
+                    __syncthreads();
+                }
+            }
+
+            // velocity update v = (x - x_prev) / h (Alg. 1)
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int i = k * B + tid;
+                if (i < V) {
+                    const float4 p = xw[i];
+                    vx[k] = (p.x - kx[k]) * inv_h;
+                    vy[k] = (p.y - ky[k]) * inv_h;
+                    vz[k] = (p.z - kz[k]) * inv_h;
+                }
+            }
+        }
+    }
+
+    // write back (structure of arrays, coalesced)
+    int bad = 0;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int i = k * B + tid;
+        if (i < V) {
+            const float4 p = xw[i];
+            A.pos[off + i] = p.x;
+            A.pos[NP + off + i] = p.y;
+            A.pos[2 * NP + off + i] = p.z;
+            A.vel[off + i] = vx[k];
+            A.vel[NP + off + i] = vy[k];
+            A.vel[2 * NP + off + i] = vz[k];
+            bad |= !(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(vx[k]) &&
+                     isfinite(vy[k]) && isfinite(vz[k]));
+        }
+    }
+    bad = __syncthreads_or(bad);
+    if (tid == 0 && bad)
+        A.nonfinite[env] = 1;
+    for (int t = 0; t < tools; ++t) {
+        const uint16_t *list = clist + t * V;
+        for (int n = tid; n < V; n += B)
+            A.contacts[(size_t)t * NP + off + n] = n < count[t] ? (int32_t)list[n] : -1;
+        if (tid == 0)
+            A.contact_counts[env * tools + t] = count[t];
+    }
+    if (A.lambda_out) {
+        float *out = A.lambda_out + ed.lambda_offset;
+        for (int j = tid; j < E; j += B)
+            out[md.edge_id[j]] = lam[j];
+        for (int j = tid; j < T; j += B)
+            out[E + md.tet_id[j]] = lam[E + j];
+    }
+}
+
+__global__ void soa_to_aos_kernel(const float *__restrict__ soa, float *__restrict__ aos, int32_t n)
+{
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) {
+        aos[3 * (size_t)i] = soa[i];
+        aos[3 * (size_t)i + 1] = soa[(size_t)n + i];
+        aos[3 * (size_t)i + 2] = soa[2 * (size_t)n + i];
+    }
+}
+
+__global__ void aos_to_soa_kernel(const float *__restrict__ aos, float *__restrict__ soa, int32_t n)
+{
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) {
+        soa[i] = aos[3 * (size_t)i];
+        soa[(size_t)n + i] = aos[3 * (size_t)i + 1];
+        soa[2 * (size_t)n + i] = aos[3 * (size_t)i + 2];
+    }
+}
+
+template <int PPT, bool STAGE, bool RESIDUAL>
+hipError_t launch_variant(const StepArgs &args, int block, uint32_t lds_bytes, hipStream_t stream)
+{
+    auto kernel = xpbd_step_kernel<PPT, STAGE, RESIDUAL>;
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds_bytes);
+    if (err != hipSuccess)
+        return err;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)args.num_envs), dim3((unsigned)block), lds_bytes,
+                       stream, args);
+    return hipGetLastError();
+}
+
+template <int PPT>
+hipError_t launch_ppt(const StepArgs &args, int block, bool stage, uint32_t lds, bool resid,
+                      hipStream_t s)
+{
+    if (stage)
+        return resid ? launch_variant<PPT, true, true>(args, block, lds, s)
+                     : launch_variant<PPT, true, false>(args, block, lds, s);
+    return resid ? launch_variant<PPT, false, true>(args, block, lds, s)
+                 : launch_variant<PPT, false, false>(args, block, lds, s);
+}
+
+}  // namespace
+
+hipError_t launch_step(const StepArgs &args, int block, int particles_per_thread,
+                       bool stage_topology, uint32_t lds_bytes, bool want_residual,
+                       hipStream_t stream)
+{
+    switch (particles_per_thread) {
+    case 1: return launch_ppt<1>(args, block, stage_topology, lds_bytes, want_residual, stream);
+    case 2: return launch_ppt<2>(args, block, stage_topology, lds_bytes, want_residual, stream);
+    case 4: return launch_ppt<4>(args, block, stage_topology, lds_bytes, want_residual, stream);
+    case 8: return launch_ppt<8>(args, block, stage_topology, lds_bytes, want_residual, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_soa_to_aos(const float *soa, float *aos, int32_t n, hipStream_t stream)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(soa_to_aos_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       soa, aos, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_aos_to_soa(const float *aos, float *soa, int32_t n, hipStream_t stream)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(aos_to_soa_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       aos, soa, n);
+    return hipGetLastError();
+}
+
+}  // namespace xpbd

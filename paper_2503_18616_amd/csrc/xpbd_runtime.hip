@@ -1,0 +1,608 @@
+// Host runtime of the XPBD library: the C ABI declared in include/xpbd.h.
+//
+// Creation prepares every distinct mesh on the host (orientation, rest
+// values, edges, greedy colours), lays the constraints out in colour-major
+// schedule order, plans the per-workgroup LDS footprint and uploads
+// everything once.  A step is one kernel launch over all environments.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/xpbd.h"
+#include "mesh_setup.h"
+#include "xpbd_device.h"
+
+using xpbd::EnvDev;
+using xpbd::MeshDev;
+using xpbd::PreparedMesh;
+
+namespace {
+
+thread_local std::string g_error;
+
+xpbd_status fail(xpbd_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(XPBD_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+    } while (0)
+
+// Device allocation owned by a batch.
+struct DeviceBuffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+bool is_device_pointer(const void *p)
+{
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // plain pageable host memory is not registered
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+struct xpbd_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    xpbd_params params{};
+    int32_t num_envs = 0;
+    int32_t total_particles = 0;
+    int32_t total_lambda = 0;
+    int block = 64;
+    int particles_per_thread = 1;
+    bool stage_topology = false;
+    uint32_t lds_bytes = 0;
+    std::vector<PreparedMesh> meshes;
+    std::vector<int32_t> env_mesh;
+    std::vector<int32_t> env_offsets;       // [N+1]
+    std::vector<int32_t> colours;           // concatenated per mesh: edges then tets
+    std::vector<DeviceBuffer> allocations;
+    float *pos = nullptr, *vel = nullptr, *lambda = nullptr, *residual = nullptr;
+    float *compliance = nullptr;
+    int32_t *contacts = nullptr, *contact_counts = nullptr, *nonfinite = nullptr;
+    MeshDev *meshes_dev = nullptr;
+    EnvDev *envs_dev = nullptr;
+    float *staging = nullptr;                // [sum V][3] for AoS <-> SoA and host tool poses
+    size_t staging_bytes = 0;
+    float *tool_staging = nullptr;
+    size_t tool_staging_bytes = 0;
+    bool stepped_with_residual = false;
+
+    ~xpbd_batch()
+    {
+        (void)hipStreamSynchronize(stream);
+        for (auto &a : allocations)
+            (void)hipFree(a.ptr);
+        if (tool_staging)
+            (void)hipFree(tool_staging);
+    }
+
+    xpbd_status alloc(void **out, size_t bytes)
+    {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+        if (e != hipSuccess)
+            return fail(XPBD_E_HIP, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        allocations.push_back({p, bytes});
+        *out = p;
+        return XPBD_OK;
+    }
+
+    template <typename T>
+    xpbd_status upload(T **out, const std::vector<T> &host)
+    {
+        xpbd_status s = alloc(reinterpret_cast<void **>(out), host.size() * sizeof(T));
+        if (s != XPBD_OK)
+            return s;
+        if (!host.empty())  // blocking: the host vectors are temporaries of creation
+            HIP_TRY(hipMemcpy(*out, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice));
+        return XPBD_OK;
+    }
+};
+
+namespace {
+
+xpbd_status validate_params(const xpbd_params *p)
+{
+    if (!p)
+        return fail(XPBD_E_ARG, "params is NULL");
+    if (!(std::isfinite(p->dt) && p->dt > 0.0f))
+        return fail(XPBD_E_ARG, "dt must be finite and > 0 (got %g)", (double)p->dt);
+    if (p->substeps < 1)
+        return fail(XPBD_E_ARG, "substeps must be >= 1 (got %d)", p->substeps);
+    if (p->iterations < 0)
+        return fail(XPBD_E_ARG, "iterations must be >= 0 (got %d)", p->iterations);
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(p->gravity[k]))
+            return fail(XPBD_E_ARG, "gravity must be finite");
+    if (p->num_tools < 0 || p->num_tools > 2)
+        return fail(XPBD_E_ARG, "num_tools must be 0, 1 or 2 (got %d)", p->num_tools);
+    for (int t = 0; t < p->num_tools; ++t)
+        if (!(std::isfinite(p->tool_radius[t]) && p->tool_radius[t] > 0.0f))
+            return fail(XPBD_E_ARG, "tool_radius[%d] must be finite and > 0", t);
+    if (p->flags & ~(XPBD_F_RESIDUAL | XPBD_F_LAMBDA))
+        return fail(XPBD_E_ARG, "unknown flag bits 0x%x", p->flags);
+    if (p->block_size != 0 &&
+        (p->block_size < 64 || p->block_size > 1024 || p->block_size % 64 != 0))
+        return fail(XPBD_E_ARG, "block_size must be 0 or a multiple of 64 in [64, 1024]");
+    return XPBD_OK;
+}
+
+int next_pow2(int x)
+{
+    int p = 1;
+    while (p < x)
+        p <<= 1;
+    return p;
+}
+
+// Schedule of one constraint type: slot -> constraint id, colour-major and
+// ascending inside a colour, plus the colour offsets.
+void build_schedule(const std::vector<int32_t> &colour, int32_t num_colours,
+                    std::vector<int32_t> &slot_id, std::vector<int32_t> &ptr)
+{
+    ptr.assign((size_t)num_colours + 1, 0);
+    for (int32_t c : colour)
+        ptr[(size_t)c + 1]++;
+    for (int32_t c = 0; c < num_colours; ++c)
+        ptr[(size_t)c + 1] += ptr[(size_t)c];
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    slot_id.assign(colour.size(), 0);
+    for (size_t j = 0; j < colour.size(); ++j)
+        slot_id[(size_t)fill[(size_t)colour[j]]++] = (int32_t)j;
+}
+
+xpbd_status field_bytes(const xpbd_batch *b, int32_t field, size_t *bytes)
+{
+    const size_t NP = (size_t)b->total_particles, N = (size_t)b->num_envs;
+    const size_t tools = (size_t)b->params.num_tools;
+    switch (field) {
+    case XPBD_FIELD_POS:
+    case XPBD_FIELD_VEL: *bytes = NP * 3 * sizeof(float); return XPBD_OK;
+    case XPBD_FIELD_LAMBDA: *bytes = (size_t)b->total_lambda * sizeof(float); return XPBD_OK;
+    case XPBD_FIELD_CONTACTS: *bytes = tools * NP * sizeof(int32_t); return XPBD_OK;
+    case XPBD_FIELD_CONTACT_COUNTS: *bytes = N * tools * sizeof(int32_t); return XPBD_OK;
+    case XPBD_FIELD_COLOURS: *bytes = b->colours.size() * sizeof(int32_t); return XPBD_OK;
+    case XPBD_FIELD_RESIDUAL: *bytes = N * 2 * sizeof(float); return XPBD_OK;
+    case XPBD_FIELD_ENV_OFFSETS: *bytes = (N + 1) * sizeof(int32_t); return XPBD_OK;
+    case XPBD_FIELD_NONFINITE: *bytes = N * sizeof(int32_t); return XPBD_OK;
+    default: return fail(XPBD_E_STATE, "unknown field %d", field);
+    }
+}
+
+// Copy bytes from host memory to dst (host or device).
+xpbd_status copy_host_out(xpbd_batch *b, void *dst, const void *src, size_t bytes)
+{
+    if (bytes == 0)
+        return XPBD_OK;
+    if (is_device_pointer(dst)) {
+        HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+    } else {
+        std::memcpy(dst, src, bytes);
+    }
+    return XPBD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *xpbd_last_error(void) { return g_error.c_str(); }
+
+xpbd_status xpbd_prepare_mesh(const xpbd_mesh *mesh, int32_t *counts, int32_t *edges,
+                              int32_t *tets, int32_t *colours, float *rest)
+{
+    g_error.clear();
+    if (!mesh || !counts)
+        return fail(XPBD_E_ARG, "mesh and counts must not be NULL");
+    PreparedMesh pm;
+    std::string err;
+    int rc = xpbd::prepare_mesh(mesh->num_vertices, mesh->num_tets, mesh->rest_pos,
+                                mesh->inv_mass, mesh->tets, pm, err);
+    if (rc != XPBD_OK)
+        return fail((xpbd_status)rc, "%s", err.c_str());
+    const int32_t E = pm.num_edges(), T = pm.num_tets();
+    counts[0] = E;
+    counts[1] = T;
+    counts[2] = pm.num_edge_colours;
+    counts[3] = pm.num_tet_colours;
+    if (edges)
+        std::copy(pm.edges.begin(), pm.edges.end(), edges);
+    if (tets)
+        std::copy(pm.tets.begin(), pm.tets.end(), tets);
+    if (colours) {
+        std::copy(pm.edge_colour.begin(), pm.edge_colour.end(), colours);
+        std::copy(pm.tet_colour.begin(), pm.tet_colour.end(), colours + E);
+    }
+    if (rest) {
+        for (int32_t e = 0; e < E; ++e)
+            rest[e] = (float)pm.rest_length[(size_t)e];
+        for (int32_t t = 0; t < T; ++t)
+            rest[E + t] = (float)pm.rest_volume[(size_t)t];
+    }
+    return XPBD_OK;
+}
+
+xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
+                              const int32_t *env_mesh, int32_t num_envs,
+                              const float *compliance, const xpbd_params *params,
+                              void *hip_stream, xpbd_batch **out)
+{
+    g_error.clear();
+    if (!out)
+        return fail(XPBD_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!meshes || num_meshes < 1)
+        return fail(XPBD_E_ARG, "need at least one mesh");
+    if (!env_mesh || num_envs < 1)
+        return fail(XPBD_E_ARG, "need at least one environment");
+    if (!compliance)
+        return fail(XPBD_E_ARG, "compliance is NULL");
+    xpbd_status s = validate_params(params);
+    if (s != XPBD_OK)
+        return s;
+    for (int32_t e = 0; e < num_envs; ++e) {
+        if (env_mesh[e] < 0 || env_mesh[e] >= num_meshes)
+            return fail(XPBD_E_ARG, "env %d uses mesh %d of %d", e, env_mesh[e], num_meshes);
+        for (int k = 0; k < 2; ++k)
+            if (!(std::isfinite(compliance[2 * e + k]) && compliance[2 * e + k] >= 0.0f))
+                return fail(XPBD_E_ARG, "compliance of env %d must be finite and >= 0", e);
+    }
+
+    std::vector<PreparedMesh> prepared((size_t)num_meshes);
+    for (int32_t m = 0; m < num_meshes; ++m) {
+        std::string err;
+        int rc = xpbd::prepare_mesh(meshes[m].num_vertices, meshes[m].num_tets,
+                                    meshes[m].rest_pos, meshes[m].inv_mass, meshes[m].tets,
+                                    prepared[(size_t)m], err);
+        if (rc != XPBD_OK)
+            return fail((xpbd_status)rc, "mesh %d: %s", m, err.c_str());
+    }
+
+    // launch shape: enough threads for the largest colour, particles per thread a power of two
+    int vmax = 0, largest_colour = 1;
+    for (const auto &pm : prepared) {
+        vmax = std::max(vmax, pm.num_vertices);
+        std::vector<int32_t> n((size_t)pm.num_edge_colours, 0), q((size_t)pm.num_tet_colours, 0);
+        for (int32_t c : pm.edge_colour)
+            n[(size_t)c]++;
+        for (int32_t c : pm.tet_colour)
+            q[(size_t)c]++;
+        for (int32_t x : n)
+            largest_colour = std::max(largest_colour, x);
+        for (int32_t x : q)
+            largest_colour = std::max(largest_colour, x);
+    }
+    int block = params->block_size;
+    if (block == 0)
+        block = std::min(512, std::max(64, (largest_colour / 2 + 63) / 64 * 64));
+    int ppt = next_pow2((vmax + block - 1) / block);
+    while (ppt > 8 && block < 1024) {
+        block = std::min(1024, block * 2);
+        ppt = next_pow2((vmax + block - 1) / block);
+    }
+    if (ppt > 8)
+        return fail(XPBD_E_CAPACITY, "mesh of %d particles needs more than 8 particles per "
+                    "thread at 1024 threads", vmax);
+
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    int lds_limit = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+    uint32_t lds_staged = 0, lds_global = 0;
+    for (const auto &pm : prepared) {
+        lds_staged = std::max(lds_staged, xpbd::lds_layout(pm.num_vertices, pm.num_edges(),
+                                                           pm.num_tets(), params->num_tools,
+                                                           true).total);
+        lds_global = std::max(lds_global, xpbd::lds_layout(pm.num_vertices, pm.num_edges(),
+                                                           pm.num_tets(), params->num_tools,
+                                                           false).total);
+    }
+    bool stage = lds_staged <= (uint32_t)lds_limit;
+    uint32_t lds = stage ? lds_staged : lds_global;
+    if (lds > (uint32_t)lds_limit)
+        return fail(XPBD_E_CAPACITY, "environment needs %u bytes of LDS; the device has %d",
+                    lds, lds_limit);
+
+    auto *b = new xpbd_batch();
+    b->device = device;
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    b->params = *params;
+    b->params.block_size = block;
+    b->num_envs = num_envs;
+    b->block = block;
+    b->particles_per_thread = ppt;
+    b->stage_topology = stage;
+    b->lds_bytes = lds;
+    b->env_mesh.assign(env_mesh, env_mesh + num_envs);
+    b->meshes = std::move(prepared);
+
+    auto cleanup = [&](xpbd_status st) {
+        delete b;
+        return st;
+    };
+
+    // per-mesh device topology in schedule order
+    std::vector<MeshDev> mdev((size_t)num_meshes);
+    for (int32_t m = 0; m < num_meshes; ++m) {
+        const PreparedMesh &pm = b->meshes[(size_t)m];
+        const int32_t E = pm.num_edges(), T = pm.num_tets();
+        std::vector<int32_t> eslot, eptr, tslot, tptr;
+        build_schedule(pm.edge_colour, pm.num_edge_colours, eslot, eptr);
+        build_schedule(pm.tet_colour, pm.num_tet_colours, tslot, tptr);
+        std::vector<uint32_t> pair((size_t)E);
+        std::vector<float> erest((size_t)E), trest((size_t)T);
+        std::vector<uint2> quad((size_t)T);
+        for (int32_t j = 0; j < E; ++j) {
+            const int32_t e = eslot[(size_t)j];
+            pair[(size_t)j] = (uint32_t)pm.edges[2 * (size_t)e] |
+                              ((uint32_t)pm.edges[2 * (size_t)e + 1] << 16);
+            erest[(size_t)j] = (float)pm.rest_length[(size_t)e];
+        }
+        for (int32_t j = 0; j < T; ++j) {
+            const int32_t t = tslot[(size_t)j];
+            const int32_t *q = &pm.tets[4 * (size_t)t];
+            quad[(size_t)j] = make_uint2((uint32_t)q[0] | ((uint32_t)q[1] << 16),
+                                         (uint32_t)q[2] | ((uint32_t)q[3] << 16));
+            trest[(size_t)j] = (float)pm.rest_volume[(size_t)t];
+        }
+        MeshDev &d = mdev[(size_t)m];
+        std::memset(&d, 0, sizeof d);
+        d.num_vertices = pm.num_vertices;
+        d.num_edges = E;
+        d.num_tets = T;
+        d.num_edge_colours = pm.num_edge_colours;
+        d.num_tet_colours = pm.num_tet_colours;
+        uint32_t *p_pair;
+        float *p_erest, *p_trest, *p_w;
+        uint2 *p_quad;
+        int32_t *p_eptr, *p_tptr, *p_eid, *p_tid;
+        xpbd_status st;
+        if ((st = b->upload(&p_pair, pair)) || (st = b->upload(&p_erest, erest)) ||
+            (st = b->upload(&p_quad, quad)) || (st = b->upload(&p_trest, trest)) ||
+            (st = b->upload(&p_eptr, eptr)) || (st = b->upload(&p_tptr, tptr)) ||
+            (st = b->upload(&p_eid, eslot)) || (st = b->upload(&p_tid, tslot)) ||
+            (st = b->upload(&p_w, pm.inv_mass)))
+            return cleanup(st);
+        d.edge_pair = p_pair;
+        d.edge_rest = p_erest;
+        d.tet_quad = p_quad;
+        d.tet_rest = p_trest;
+        d.edge_ptr = p_eptr;
+        d.tet_ptr = p_tptr;
+        d.edge_id = p_eid;
+        d.tet_id = p_tid;
+        d.inv_mass = p_w;
+        b->colours.insert(b->colours.end(), pm.edge_colour.begin(), pm.edge_colour.end());
+        b->colours.insert(b->colours.end(), pm.tet_colour.begin(), pm.tet_colour.end());
+    }
+
+    // environments
+    std::vector<EnvDev> edev((size_t)num_envs);
+    b->env_offsets.assign((size_t)num_envs + 1, 0);
+    int64_t np = 0, nl = 0;
+    for (int32_t e = 0; e < num_envs; ++e) {
+        const PreparedMesh &pm = b->meshes[(size_t)env_mesh[e]];
+        edev[(size_t)e] = EnvDev{env_mesh[e], (int32_t)np, (int32_t)nl, 0};
+        b->env_offsets[(size_t)e] = (int32_t)np;
+        np += pm.num_vertices;
+        nl += pm.num_edges() + pm.num_tets();
+        if (np > INT32_MAX / 3 || nl > INT32_MAX)
+            return cleanup(fail(XPBD_E_CAPACITY, "batch too large: %lld particles", (long long)np));
+    }
+    b->env_offsets[(size_t)num_envs] = (int32_t)np;
+    b->total_particles = (int32_t)np;
+    b->total_lambda = (int32_t)nl;
+
+    // initial state: rest positions, zero velocity (structure of arrays)
+    std::vector<float> pos_soa((size_t)(3 * np));
+    for (int32_t e = 0; e < num_envs; ++e) {
+        const PreparedMesh &pm = b->meshes[(size_t)env_mesh[e]];
+        const size_t off = (size_t)b->env_offsets[(size_t)e];
+        for (int32_t i = 0; i < pm.num_vertices; ++i)
+            for (int k = 0; k < 3; ++k)
+                pos_soa[(size_t)k * (size_t)np + off + (size_t)i] = pm.rest_pos[3 * (size_t)i + k];
+    }
+    std::vector<float> zeros_f((size_t)(3 * np), 0.0f);
+    std::vector<float> comp(compliance, compliance + 2 * (size_t)num_envs);
+    std::vector<int32_t> zeros_env((size_t)num_envs, 0);
+    const size_t tools = (size_t)params->num_tools;
+    std::vector<int32_t> no_contacts(tools * (size_t)np, -1), no_counts(tools * (size_t)num_envs, 0);
+    std::vector<float> resid((size_t)num_envs * 2, 0.0f);
+    std::vector<float> lam_init((size_t)nl, 0.0f);
+    xpbd_status st;
+    if ((st = b->upload(&b->meshes_dev, mdev)) || (st = b->upload(&b->envs_dev, edev)) ||
+        (st = b->upload(&b->pos, pos_soa)) || (st = b->upload(&b->vel, zeros_f)) ||
+        (st = b->upload(&b->compliance, comp)) || (st = b->upload(&b->nonfinite, zeros_env)) ||
+        (st = b->upload(&b->contacts, no_contacts)) ||
+        (st = b->upload(&b->contact_counts, no_counts)) ||
+        (st = b->upload(&b->residual, resid)) ||
+        (st = b->alloc(reinterpret_cast<void **>(&b->staging), 3 * (size_t)np * sizeof(float))))
+        return cleanup(st);
+    b->staging_bytes = 3 * (size_t)np * sizeof(float);
+    if (params->flags & XPBD_F_LAMBDA)
+        if ((st = b->upload(&b->lambda, lam_init)))
+            return cleanup(st);
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess)
+        return cleanup(fail(XPBD_E_HIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e)));
+    *out = b;
+    return XPBD_OK;
+}
+
+xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
+{
+    g_error.clear();
+    if (!b)
+        return fail(XPBD_E_ARG, "batch is NULL");
+    if (num_steps < 0)
+        return fail(XPBD_E_ARG, "num_steps must be >= 0");
+    if (num_steps == 0)
+        return XPBD_OK;
+    const int tools = b->params.num_tools;
+    const float *tools_dev = nullptr;
+    if (tools > 0) {
+        if (!tool_pos)
+            return fail(XPBD_E_ARG, "tool_pos is NULL but the batch has %d tools", tools);
+        const size_t bytes = (size_t)num_steps * b->num_envs * tools * 3 * sizeof(float);
+        if (is_device_pointer(tool_pos)) {
+            tools_dev = tool_pos;
+        } else {
+            if (b->tool_staging_bytes < bytes) {
+                if (b->tool_staging)
+                    HIP_TRY(hipFree(b->tool_staging));
+                b->tool_staging = nullptr;
+                b->tool_staging_bytes = 0;
+                HIP_TRY(hipMalloc(&b->tool_staging, bytes));
+                b->tool_staging_bytes = bytes;
+            }
+            HIP_TRY(hipMemcpyAsync(b->tool_staging, tool_pos, bytes, hipMemcpyHostToDevice,
+                                   b->stream));
+            HIP_TRY(hipStreamSynchronize(b->stream));
+            tools_dev = b->tool_staging;
+        }
+    }
+    xpbd::StepArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.meshes = b->meshes_dev;
+    a.envs = b->envs_dev;
+    a.compliance = b->compliance;
+    a.tool_pos = tools_dev;
+    a.pos = b->pos;
+    a.vel = b->vel;
+    a.lambda_out = b->lambda;
+    a.contacts = b->contacts;
+    a.contact_counts = b->contact_counts;
+    a.residual = b->residual;
+    a.nonfinite = b->nonfinite;
+    a.num_envs = b->num_envs;
+    a.total_particles = b->total_particles;
+    a.num_steps = num_steps;
+    a.substeps = b->params.substeps;
+    a.iterations = b->params.iterations;
+    a.num_tools = tools;
+    const double h = (double)b->params.dt / (double)b->params.substeps;
+    a.h = (float)h;
+    a.inv_h = (float)(1.0 / h);
+    for (int k = 0; k < 3; ++k)
+        a.gravity[k] = b->params.gravity[k];
+    for (int t = 0; t < tools; ++t) {
+        const float r = b->params.tool_radius[t];
+        a.tool_radius[t] = r;
+        a.tool_radius2[t] = r * r;
+        const float reach = 2.0f * r;
+        a.tool_reach2[t] = reach * reach;
+    }
+    const bool resid = (b->params.flags & XPBD_F_RESIDUAL) != 0;
+    HIP_TRY(xpbd::launch_step(a, b->block, b->particles_per_thread, b->stage_topology,
+                              b->lds_bytes, resid, b->stream));
+    return XPBD_OK;
+}
+
+xpbd_status xpbd_field_bytes(const xpbd_batch *b, int32_t field, size_t *bytes)
+{
+    g_error.clear();
+    if (!b || !bytes)
+        return fail(XPBD_E_ARG, "batch and bytes must not be NULL");
+    return field_bytes(b, field, bytes);
+}
+
+xpbd_status xpbd_read_state(xpbd_batch *b, int32_t field, void *dst, size_t dst_bytes)
+{
+    g_error.clear();
+    if (!b || !dst)
+        return fail(XPBD_E_ARG, "batch and dst must not be NULL");
+    size_t need = 0;
+    xpbd_status s = field_bytes(b, field, &need);
+    if (s != XPBD_OK)
+        return s;
+    if (dst_bytes != need)
+        return fail(XPBD_E_STATE, "field %d needs %zu bytes, got %zu", field, need, dst_bytes);
+    if (field == XPBD_FIELD_LAMBDA && !b->lambda)
+        return fail(XPBD_E_STATE, "multipliers are stored only with XPBD_F_LAMBDA");
+    if (field == XPBD_FIELD_RESIDUAL && !(b->params.flags & XPBD_F_RESIDUAL))
+        return fail(XPBD_E_STATE, "the residual is computed only with XPBD_F_RESIDUAL");
+    switch (field) {
+    case XPBD_FIELD_COLOURS:
+        s = copy_host_out(b, dst, b->colours.data(), need);
+        if (s != XPBD_OK)
+            return s;
+        break;
+    case XPBD_FIELD_ENV_OFFSETS:
+        s = copy_host_out(b, dst, b->env_offsets.data(), need);
+        if (s != XPBD_OK)
+            return s;
+        break;
+    case XPBD_FIELD_POS:
+    case XPBD_FIELD_VEL:
+        HIP_TRY(xpbd::launch_soa_to_aos(field == XPBD_FIELD_POS ? b->pos : b->vel, b->staging,
+                                        b->total_particles, b->stream));
+        HIP_TRY(hipMemcpyAsync(dst, b->staging, need, hipMemcpyDefault, b->stream));
+        break;
+    default: {
+        const void *src = field == XPBD_FIELD_LAMBDA           ? (const void *)b->lambda
+                          : field == XPBD_FIELD_CONTACTS       ? (const void *)b->contacts
+                          : field == XPBD_FIELD_CONTACT_COUNTS ? (const void *)b->contact_counts
+                          : field == XPBD_FIELD_RESIDUAL       ? (const void *)b->residual
+                                                               : (const void *)b->nonfinite;
+        if (need)
+            HIP_TRY(hipMemcpyAsync(dst, src, need, hipMemcpyDefault, b->stream));
+    }
+    }
+    std::vector<int32_t> flags((size_t)b->num_envs);
+    HIP_TRY(hipMemcpyAsync(flags.data(), b->nonfinite, flags.size() * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (size_t e = 0; e < flags.size(); ++e)
+        if (flags[e])
+            return fail(XPBD_E_NONFINITE, "environment %zu has a non-finite state", e);
+    return XPBD_OK;
+}
+
+xpbd_status xpbd_write_state(xpbd_batch *b, int32_t field, const void *src, size_t src_bytes)
+{
+    g_error.clear();
+    if (!b || !src)
+        return fail(XPBD_E_ARG, "batch and src must not be NULL");
+    if (field != XPBD_FIELD_POS && field != XPBD_FIELD_VEL)
+        return fail(XPBD_E_STATE, "only positions and velocities can be written");
+    size_t need = 0;
+    xpbd_status s = field_bytes(b, field, &need);
+    if (s != XPBD_OK)
+        return s;
+    if (src_bytes != need)
+        return fail(XPBD_E_STATE, "field %d needs %zu bytes, got %zu", field, need, src_bytes);
+    HIP_TRY(hipMemcpyAsync(b->staging, src, need, hipMemcpyDefault, b->stream));
+    HIP_TRY(xpbd::launch_aos_to_soa(b->staging, field == XPBD_FIELD_POS ? b->pos : b->vel,
+                                    b->total_particles, b->stream));
+    HIP_TRY(hipMemsetAsync(b->nonfinite, 0, (size_t)b->num_envs * sizeof(int32_t), b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return XPBD_OK;
+}
+
+void xpbd_destroy_batch(xpbd_batch *b) { delete b; }
+
+}  // extern "C"

@@ -140,15 +140,16 @@ def tool_path(num_steps: int, num_envs: int, seed: int, extent=SLAB_EXTENT,
     env_ids = np.arange(num_envs) if env_ids is None else np.asarray(env_ids)
     lo = np.array([0.2 * lx, 0.2 * ly, lz - 8.0e-3])
     hi = np.array([0.8 * lx, 0.8 * ly, lz + 10.0e-3])
+    u = np.stack([_env_rng(seed, _STREAM_TOOL, e).uniform(-1.0, 1.0, size=(num_steps, num_tools, 3))
+                  for e in env_ids], axis=1) if len(env_ids) else np.zeros((num_steps, 0, num_tools, 3))
+    c = np.empty((len(env_ids), num_tools, 3))
+    for t in range(num_tools):
+        fx = 0.5 if num_tools == 1 else (0.35 if t == 0 else 0.65)
+        c[:, t] = [fx * lx, 0.5 * ly, lz + radius - start_depth]
     out = np.empty((num_steps, len(env_ids), num_tools, 3), dtype=np.float32)
-    for n, e in enumerate(env_ids):
-        u = _env_rng(seed, _STREAM_TOOL, e).uniform(-1.0, 1.0, size=(num_steps, num_tools, 3))
-        for t in range(num_tools):
-            fx = 0.5 if num_tools == 1 else (0.35 if t == 0 else 0.65)
-            c = np.array([fx * lx, 0.5 * ly, lz + radius - start_depth])
-            for s in range(num_steps):
-                c = np.clip(c + step_len * u[s, t], lo, hi)
-                out[s, n, t] = c
+    for s in range(num_steps):
+        c = np.clip(c + step_len * u[s], lo, hi)
+        out[s] = c
     return out
 
 

@@ -1,0 +1,338 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Gate: max per-particle position error <= 1e-4 of the mesh extent after 100
+steps; the constraint colouring and the contact-candidate lists bit-exact
+(candidates are decided in float32 on both sides from the GPU's own
+start-of-step positions; against the FP64 trajectory they may differ only for
+particles whose distance to the sphere is within the trajectories' position
+error of the reach 2r).
+"""
+import numpy as np
+import pytest
+
+from paper_2503_18616_amd import workloads as W
+from tests import cases as K
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def xp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2503_18616_amd import xpbd
+    return xpbd
+
+
+def make_batch(xp, wl, flags=0, block_size=0):
+    return xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance,
+                    K.lib_params(xp, wl, flags, block_size))
+
+
+def check_contacts_step(xp, oracle_lib, batch, wl, start_x, tools_step, oracle_lists=None,
+                        envs=None, pos_err=0.0):
+    """Bit-exact candidate lists against the float32 rule on the GPU's start-of-step
+    positions; against the oracle's FP64 lists up to the ambiguous band."""
+    offs = batch.env_offsets
+    counts = batch.read(xp.FIELD_CONTACT_COUNTS).reshape(wl.num_envs, wl.num_tools)
+    lists = batch.read(xp.FIELD_CONTACTS).reshape(wl.num_tools, -1)
+    envs = range(wl.num_envs) if envs is None else envs
+    for n, e in enumerate(envs):
+        m = wl.meshes[int(wl.env_mesh[e])]
+        x0 = K.env_block(start_x, offs, e)
+        for t in range(wl.num_tools):
+            got = K.env_block(lists[t], offs, e)
+            c = int(counts[e, t])
+            assert (got[c:] == -1).all()
+            got = got[:c]
+            expect = oracle_lib.contact_candidates_f32(x0, m.inv_mass, tools_step[e, t],
+                                                       wl.tool_radius[t])
+            assert np.array_equal(got, expect), f"env {e} tool {t}"
+            if oracle_lists is not None:
+                ol = oracle_lists[n][t]
+                diff = np.setxor1d(got, ol)
+                if diff.size:
+                    d = np.linalg.norm(x0[diff].astype(np.float64) - tools_step[e, t], axis=1)
+                    assert np.all(np.abs(d - 2 * wl.tool_radius[t]) <= 10 * pos_err + 1e-7), \
+                        f"env {e} tool {t}: candidates {diff} differ outside the band"
+
+
+# --------------------------------------------------------------------------------------
+@pytest.mark.parametrize("start_depth", [2e-3, 6e-3])
+def test_single_env_parity_per_step(xp, oracle_lib, start_depth):
+    """One environment, 8x5x3 slab, 4 iterations, 100 steps launched one step at a time."""
+    wl = W.single_env_workload(seed=0)
+    steps = 100
+    tools = W.tool_path(steps, 1, wl.seed, start_depth=start_depth)
+    om = K.oracle_meshes(oracle_lib, wl)[0]
+    ref = oracle_lib.run_env(om, wl.compliance[0], K.oracle_params(oracle_lib, wl), tools[:, 0],
+                             steps, want_lambda=True, want_contacts=True, want_residual=True)
+    with make_batch(xp, wl, flags=xp.F_RESIDUAL | xp.F_LAMBDA) as b:
+        x_hist = []
+        for s in range(steps):
+            x0 = b.positions()
+            x_hist.append(x0)
+            b.step(1, tools[s:s + 1])
+            check_contacts_step(xp, oracle_lib, b, wl, x0, tools[s],
+                                [[ref.contacts[s, t, :ref.contact_count[s, t]]
+                                  for t in range(wl.num_tools)]],
+                                pos_err=1e-6)
+        x, v = b.positions(), b.velocities()
+        lam = b.read(xp.FIELD_LAMBDA)
+        res = b.read(xp.FIELD_RESIDUAL)
+    err = K.max_position_error(x, ref.x)
+    assert err <= K.POS_TOL, f"max position error {err:.3e} m > {K.POS_TOL:.1e}"
+    h = wl.dt / wl.substeps
+    assert np.max(np.abs(v - ref.v)) <= 2 * K.POS_TOL / h
+    # multipliers and residual of the final substep
+    lam_scale = np.max(np.abs(ref.lam))
+    assert np.max(np.abs(lam - ref.lam)) <= 1e-2 * lam_scale
+    r_ref = ref.residual[-1, -1]
+    assert abs(res[0] - r_ref[0]) <= 0.05 * r_ref[0] + 1e-6
+    assert abs(res[1] - r_ref[1]) <= 0.05 * r_ref[1] + 1e-6
+
+
+def test_single_launch_equals_step_by_step(xp):
+    wl = W.single_env_workload(seed=1)
+    tools = wl.tools(100)
+    with make_batch(xp, wl) as a, make_batch(xp, wl) as b:
+        a.step(100, tools)
+        for s in range(100):
+            b.step(1, tools[s:s + 1])
+        assert np.array_equal(a.positions(), b.positions())
+        assert np.array_equal(a.velocities(), b.velocities())
+
+
+def test_batch_parity_sampled_envs(xp, oracle_lib):
+    """1024 environments of the 16x10x4 slab, 8 iterations, per-env compliances and
+    tool paths, launched one step at a time; 16 sampled environments against the oracle."""
+    steps = 100
+    wl = W.batch_workload(1024, seed=0, num_steps=steps)
+    sample = list(range(0, 1024, 64))
+    tools = wl.tools(steps)
+    om = K.oracle_meshes(oracle_lib, wl)
+    refs = oracle_lib.run_batch(om, wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
+                                tools[:, sample], steps, env_ids=sample, threads=8,
+                                want_contacts=True)
+    with make_batch(xp, wl) as b:
+        offs = b.env_offsets
+        for s in range(steps):
+            check = s % 10 == 0 or s == steps - 1
+            x0 = b.positions() if check else None
+            b.step(1, tools[s:s + 1])
+            if check:
+                lists = [[r.contacts[s, t, :r.contact_count[s, t]] for t in range(1)] for r in refs]
+                check_contacts_step(xp, oracle_lib, b, wl, x0, tools[s], lists, envs=sample,
+                                    pos_err=1e-5)
+        x = b.positions()
+    worst = 0.0
+    for n, e in enumerate(sample):
+        err = K.max_position_error(K.env_block(x, offs, e), refs[n].x)
+        worst = max(worst, err)
+    assert worst <= K.POS_TOL, f"max position error {worst:.3e} m"
+
+
+def test_colours_read_back(xp, oracle_lib):
+    wl = W.batch_workload(4, seed=0, num_steps=1)
+    om = K.oracle_meshes(oracle_lib, wl)[0]
+    with make_batch(xp, wl) as b:
+        col = b.read(xp.FIELD_COLOURS)
+    assert np.array_equal(col, np.concatenate([om.edge_colour, om.tet_colour]))
+
+
+def test_rest_mesh_stays_at_rest(xp):
+    wl = W.single_env_workload()
+    wl.gravity = (0.0, 0.0, 0.0)
+    wl.num_tools = 0
+    with make_batch(xp, wl) as b:
+        b.step(100, None)
+        x = b.positions()
+    drift = np.max(np.abs(x - wl.meshes[0].rest_pos))
+    assert drift < 1e-6 * K.EXTENT
+
+
+def test_free_fall_closed_form(xp):
+    m = W.slab_mesh(3, 2, 2, pin_bottom=False)
+    wl = W.Workload("free", [m], np.zeros(2, np.int32), W.constant_compliance(2, 1e-6, 1e-7),
+                    iterations=4, num_steps=10, seed=0, num_tools=0)
+    with make_batch(xp, wl) as b:
+        b.step(10, None)
+        x = b.positions().astype(np.float64)
+    h = K.f32(wl.dt) / wl.substeps
+    n = 10 * wl.substeps
+    expect = np.tile(m.rest_pos.astype(np.float64), (2, 1)) + \
+        np.array([0, 0, K.f32(-9.81)]) * h * h * n * (n + 1) / 2
+    assert np.max(np.abs(x - expect)) < K.POS_TOL
+
+
+@pytest.mark.parametrize("block", [64, 128, 256, 512])
+def test_block_size_does_not_change_results(xp, block):
+    """Which lane projects which constraint of a colour cannot matter: bitwise equal."""
+    wl = W.single_env_workload(seed=3)
+    tools = W.tool_path(30, 1, 3, start_depth=6e-3)
+    with make_batch(xp, wl) as ref, make_batch(xp, wl, block_size=block) as b:
+        ref.step(30, tools)
+        b.step(30, tools)
+        assert np.array_equal(ref.positions(), b.positions())
+
+
+def uneven_workload(seed=0):
+    grids = [(6, 4, 2), (8, 5, 3), (10, 6, 3)]
+    meshes = [W.slab_mesh(*g) for g in grids]
+    env_mesh = np.array([0, 1, 2, 2, 1, 0], np.int32)
+    return W.Workload("uneven", meshes, env_mesh,
+                      W.log_uniform_compliance(6, 1e-7, 1e-5, seed), iterations=8,
+                      num_steps=100, seed=seed)
+
+
+def test_uneven_meshes_parity(xp, oracle_lib):
+    wl = uneven_workload()
+    steps = 100
+    tools = W.tool_path(steps, wl.num_envs, wl.seed, start_depth=5e-3)
+    om = K.oracle_meshes(oracle_lib, wl)
+    refs = oracle_lib.run_batch(om, wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
+                                tools, steps, threads=6)
+    with make_batch(xp, wl) as b:
+        b.step(steps, tools)
+        x = b.positions()
+        for e in range(wl.num_envs):
+            err = K.max_position_error(K.env_block(x, b.env_offsets, e), refs[e].x)
+            assert err <= K.POS_TOL, f"env {e}: {err:.3e}"
+
+
+def test_two_tools_parity(xp, oracle_lib):
+    wl = W.single_env_workload(seed=4)
+    wl.num_tools = 2
+    steps = 60
+    tools = W.tool_path(steps, 1, 4, num_tools=2, start_depth=6e-3)
+    om = K.oracle_meshes(oracle_lib, wl)[0]
+    ref = oracle_lib.run_env(om, wl.compliance[0], K.oracle_params(oracle_lib, wl), tools[:, 0],
+                             steps, want_contacts=True)
+    assert ref.contact_count.sum() > 0
+    with make_batch(xp, wl) as b:
+        for s in range(steps):
+            x0 = b.positions()
+            b.step(1, tools[s:s + 1])
+            check_contacts_step(xp, oracle_lib, b, wl, x0, tools[s],
+                                [[ref.contacts[s, t, :ref.contact_count[s, t]] for t in range(2)]],
+                                pos_err=1e-6)
+        err = K.max_position_error(b.positions(), ref.x)
+    assert err <= K.POS_TOL
+
+
+def test_largest_mesh_parity(xp, oracle_lib):
+    """The 20x12x6 slab (1911 particles), the largest of the uneven range: its
+    constraint lists do not fit LDS next to the particles and are read from
+    global memory."""
+    m = W.slab_mesh(20, 12, 6)
+    wl = W.Workload("large", [m], np.zeros(3, np.int32),
+                    W.log_uniform_compliance(3, 1e-7, 1e-5, 9), iterations=8, num_steps=100, seed=9)
+    steps = 100
+    tools = W.tool_path(steps, 3, 9, start_depth=5e-3)
+    om = K.oracle_meshes(oracle_lib, wl)
+    refs = oracle_lib.run_batch(om, wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
+                                tools, steps, threads=3)
+    with make_batch(xp, wl) as b:
+        b.step(steps, tools)
+        x = b.positions()
+        for e in range(3):
+            err = K.max_position_error(K.env_block(x, b.env_offsets, e), refs[e].x)
+            assert err <= K.POS_TOL, f"env {e}: {err:.3e}"
+
+
+def test_resume_is_bitwise(xp):
+    wl = W.batch_workload(8, seed=2, num_steps=40)
+    tools = wl.tools(40)
+    with make_batch(xp, wl) as full, make_batch(xp, wl) as half:
+        full.step(40, tools)
+        half.step(20, tools[:20])
+        x, v = half.positions(), half.velocities()
+        with make_batch(xp, wl) as resumed:
+            resumed.write(xp.FIELD_POS, x)
+            resumed.write(xp.FIELD_VEL, v)
+            resumed.step(20, tools[20:])
+            assert np.array_equal(resumed.positions(), full.positions())
+            assert np.array_equal(resumed.velocities(), full.velocities())
+
+
+def test_runs_are_deterministic(xp):
+    wl = W.batch_workload(32, seed=3, num_steps=20)
+    tools = wl.tools(20)
+    with make_batch(xp, wl, flags=xp.F_LAMBDA) as a, make_batch(xp, wl, flags=xp.F_LAMBDA) as b:
+        a.step(20, tools)
+        b.step(20, tools)
+        assert np.array_equal(a.positions(), b.positions())
+        assert np.array_equal(a.read(xp.FIELD_LAMBDA), b.read(xp.FIELD_LAMBDA))
+
+
+def test_device_tool_poses_match_host(xp):
+    import torch
+    wl = W.batch_workload(16, seed=4, num_steps=10)
+    tools = wl.tools(10)
+    with make_batch(xp, wl) as a, make_batch(xp, wl) as b:
+        a.step(10, tools)
+        dev = torch.from_numpy(tools).cuda()
+        b.step(10, dev)
+        out = torch.empty(int(b.env_offsets[-1]) * 3, dtype=torch.float32, device="cuda")
+        b.read(xp.FIELD_POS, out)
+        assert np.array_equal(a.positions().ravel(), out.cpu().numpy())
+
+
+def test_nonfinite_state_is_reported(xp):
+    wl = W.batch_workload(3, seed=5, num_steps=1)
+    with make_batch(xp, wl) as b:
+        x = b.positions()
+        x[b.env_offsets[1] + 500] = np.nan
+        b.write(xp.FIELD_POS, x)
+        b.step(1, wl.tools(1))
+        with pytest.raises(xp.XpbdError) as e:
+            b.positions()
+        assert e.value.status == xp.XPBD_E_NONFINITE
+        flags = b.read(xp.FIELD_NONFINITE, raise_nonfinite=False)
+        assert flags.tolist() == [0, 1, 0]
+        b.write(xp.FIELD_POS, np.tile(wl.meshes[0].rest_pos, (3, 1)))
+        assert b.read(xp.FIELD_NONFINITE).tolist() == [0, 0, 0]
+
+
+def test_zero_steps_and_zero_iterations(xp):
+    wl = W.single_env_workload()
+    with make_batch(xp, wl) as b:
+        b.step(0, None)
+        assert np.array_equal(b.positions(), wl.meshes[0].rest_pos)
+    wl.iterations = 0
+    wl.num_tools = 0
+    with make_batch(xp, wl) as b:
+        b.step(3, None)
+        x = b.positions().astype(np.float64)
+    m = wl.meshes[0]
+    h = K.f32(wl.dt) / wl.substeps
+    n = 3 * wl.substeps
+    expect = m.rest_pos.astype(np.float64).copy()
+    free = m.inv_mass > 0
+    expect[free, 2] += K.f32(-9.81) * h * h * n * (n + 1) / 2
+    assert np.max(np.abs(x - expect)) < 1e-6
+
+
+def test_tool_centred_on_a_particle(xp, oracle_lib):
+    """Degenerate push-out direction: a particle exactly at the sphere centre moves
+    to centre + (0, 0, r)."""
+    wl = W.single_env_workload()
+    m = wl.meshes[0]
+    i = int(np.nonzero(m.inv_mass > 0)[0][-1])
+    tools = np.tile(m.rest_pos[i], (1, 1, 1, 1)).astype(np.float32)
+    wl.gravity = (0.0, 0.0, 0.0)
+    wl.iterations = 1
+    wl.substeps = 1
+    # compliances so large that the constraints move nothing: the particle stays
+    # exactly on the centre until the push-out
+    wl.compliance = W.constant_compliance(1, 1e30, 1e30)
+    with make_batch(xp, wl) as b:
+        b.step(1, tools)
+        counts = b.read(xp.FIELD_CONTACT_COUNTS)
+        x = b.positions()
+    om = K.oracle_meshes(oracle_lib, wl)[0]
+    ref = oracle_lib.run_env(om, wl.compliance[0], K.oracle_params(oracle_lib, wl), tools[:, 0],
+                             1, want_contacts=True)
+    assert counts[0] == ref.contact_count[0, 0] and counts[0] >= 1
+    assert K.max_position_error(x, ref.x) <= K.POS_TOL
+    np.testing.assert_allclose(x[i], m.rest_pos[i] + [0, 0, wl.tool_radius[0]], atol=1e-6)
