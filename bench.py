@@ -57,6 +57,8 @@ def parse_args():
     ap.add_argument("--envs", type=int, default=1024, help="environments of the batch workload")
     ap.add_argument("--steps-per-launch", type=int, default=1)
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library's choice)")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="0 = library's choice, 1 = multipliers in registers, 2 = multipliers in LDS")
     ap.add_argument("--cpu-envs", type=int, default=64, help="oracle sample: environments")
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle sample: steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -96,7 +98,8 @@ def main():
 
     tools = torch.from_numpy(wl.tools(total)).cuda()
     params = xpbd.make_params(wl.dt, S, I, wl.gravity, wl.num_tools, wl.tool_radius,
-                              flags=xpbd.F_RESIDUAL, block_size=args.block)
+                              flags=xpbd.F_RESIDUAL, block_size=args.block,
+                              solver_variant=args.variant)
     stream = torch.cuda.current_stream()
     batch = xpbd.Batch([(m.rest_pos, m.inv_mass, m.tets)], wl.env_mesh, wl.compliance, params,
                        stream=stream.cuda_stream)

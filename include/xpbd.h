@@ -104,7 +104,18 @@ typedef struct {
     uint32_t flags;      /* XPBD_F_* */
     int32_t block_size;  /* threads per workgroup: 0 = chosen by the library, else a
                             multiple of 64 in [64, 1024] */
+    int32_t solver_variant; /* XPBD_VARIANT_*: where the multipliers live */
 } xpbd_params;
+
+/* Values of xpbd_params.solver_variant.  Both variants compute the same
+ * projections in the same colour order; they differ only in data placement.
+ *   AUTO      registers when every mesh's round schedule fits, else LDS
+ *   REGISTERS each lane keeps the multipliers of its constraints in registers
+ *             (one per round of <= block_size constraints of one colour, at
+ *             most 64 rounds); only particle state occupies LDS
+ *   LDS       multipliers in LDS next to the particles; constraint lists in
+ *             LDS when they fit */
+enum { XPBD_VARIANT_AUTO = 0, XPBD_VARIANT_REGISTERS = 1, XPBD_VARIANT_LDS = 2 };
 
 /*
  * Create a batch of num_envs environments; environment e uses mesh

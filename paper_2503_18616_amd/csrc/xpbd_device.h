@@ -26,7 +26,21 @@ struct MeshDev {
     const int32_t *edge_id;      // [E]  constraint id of each schedule slot
     const int32_t *tet_id;       // [T]
     const float *inv_mass;       // [V]
+    // round schedule of the register-multiplier kernel (see RoundDev)
+    const int4 *rounds;          // [num_rounds] (begin slot, end slot, kind, barrier)
+    const uint2 *edge_rec;       // [E]  (pair, rest length bits), slot order
+    const uint4 *tet_rec;        // [T]  (a | b << 16, c | d << 16, rest volume bits, 0)
+    int32_t num_rounds;
+    int32_t pad2[3];
 };
+
+// One round of the register-multiplier kernel: lane `tid` of the workgroup
+// projects slot begin + tid of the given kind if it is below end (the end of
+// the colour); a workgroup barrier follows when barrier != 0 (last round of a
+// colour).  kind 0 = edge, 1 = tetrahedron.  Each lane keeps the multiplier of
+// its constraint of round r in register r.
+enum { ROUND_EDGE = 0, ROUND_TET = 1 };
+constexpr int kMaxRounds = 64;
 
 struct EnvDev {
     int32_t mesh;
@@ -109,6 +123,29 @@ __host__ __device__ inline LdsLayout lds_layout(int32_t V, int32_t E, int32_t T,
 hipError_t launch_step(const StepArgs &args, int block, int particles_per_thread,
                        bool stage_topology, uint32_t lds_bytes, bool want_residual,
                        hipStream_t stream);
+// LDS layout of the register-multiplier kernel for an environment of V particles.
+struct RegLdsLayout {
+    uint32_t xw;       // float4 [V]  position + inverse mass
+    uint32_t vel;      // float [3][V]
+    uint32_t prev;     // float [3][V]  positions at the start of the substep
+    uint32_t scratch;  // 64 x uint32
+    uint32_t total;
+};
+
+__host__ __device__ inline RegLdsLayout reg_lds_layout(int32_t V)
+{
+    RegLdsLayout l;
+    l.xw = 0;
+    l.vel = 16u * (uint32_t)V;
+    l.prev = l.vel + 12u * (uint32_t)V;
+    l.scratch = align_up(l.prev + 12u * (uint32_t)V, 16);
+    l.total = l.scratch + 256u;
+    return l;
+}
+
+// Register-multiplier kernel; lambda_banks = ceil(rounds / 32) in {1, 2}.
+hipError_t launch_step_reg(const StepArgs &args, int block, int lambda_banks, uint32_t lds_bytes,
+                           bool want_residual, hipStream_t stream);
 hipError_t launch_soa_to_aos(const float *soa, float *aos, int32_t n, hipStream_t stream);
 hipError_t launch_aos_to_soa(const float *aos, float *soa, int32_t n, hipStream_t stream);
 

@@ -34,11 +34,11 @@ constexpr float kThirtySixth = 1.0f / 36.0f;
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Distance constraint C = |x_a - x_b| - d (Eq. 1), one XPBD projection.
-__device__ __forceinline__ void project_edge(float4 *xw, float *lam, int slot, uint32_t pair,
-                                             float rest, float alpha_tilde)
+// Distance constraint C = |x_a - x_b| - d (Eq. 1), one XPBD projection of
+// edge (a, b) with rest length `rest`; `lam` is the edge's multiplier.
+__device__ __forceinline__ void edge_update(float4 *xw, int a, int b, float rest,
+                                            float alpha_tilde, float &lam)
 {
-    const int a = (int)(pair & 0xffffu), b = (int)(pair >> 16);
     float4 pa = xw[a];
     float4 pb = xw[b];
     const float dx = pa.x - pb.x, dy = pa.y - pb.y, dz = pa.z - pb.z;
@@ -50,9 +50,8 @@ __device__ __forceinline__ void project_edge(float4 *xw, float *lam, int slot, u
     const float denom = pa.w + pb.w + alpha_tilde;
     if (!(denom > kMinDenominator))
         return;
-    const float l = lam[slot];
-    const float dl = (-C - alpha_tilde * l) * fast_rcp(denom);
-    lam[slot] = l + dl;
+    const float dl = (-C - alpha_tilde * lam) * fast_rcp(denom);
+    lam += dl;
     const float s = dl * inv_len;          // dlambda times the unit direction's scale
     const float sa = pa.w * s, sb = pb.w * s;
     pa.x += sa * dx;
@@ -66,12 +65,13 @@ __device__ __forceinline__ void project_edge(float4 *xw, float *lam, int slot, u
 }
 
 // Volume constraint C = (1/6)(x_ba x x_ca).x_da - V0 (Eqs. 2-3 with the
-// analytic gradients), one XPBD projection.  G_i are six times the gradients.
-__device__ __forceinline__ void project_tet(float4 *xw, float *lam, int slot, uint2 quad,
-                                            float rest, float alpha_tilde)
+// analytic gradients), one XPBD projection of tetrahedron (a | b << 16,
+// c | d << 16) with rest volume `rest`.  G_i are six times the gradients.
+__device__ __forceinline__ void tet_update(float4 *xw, uint32_t ab, uint32_t cd, float rest,
+                                           float alpha_tilde, float &lam)
 {
-    const int a = (int)(quad.x & 0xffffu), b = (int)(quad.x >> 16);
-    const int c = (int)(quad.y & 0xffffu), d = (int)(quad.y >> 16);
+    const int a = (int)(ab & 0xffffu), b = (int)(ab >> 16);
+    const int c = (int)(cd & 0xffffu), d = (int)(cd >> 16);
     float4 pa = xw[a];
     float4 pb = xw[b];
     float4 pc = xw[c];
@@ -92,9 +92,8 @@ __device__ __forceinline__ void project_tet(float4 *xw, float *lam, int slot, ui
     const float denom = wg * kThirtySixth + alpha_tilde;
     if (!(denom > kMinDenominator))
         return;
-    const float l = lam[slot];
-    const float dl = (-C - alpha_tilde * l) * fast_rcp(denom);
-    lam[slot] = l + dl;
+    const float dl = (-C - alpha_tilde * lam) * fast_rcp(denom);
+    lam += dl;
     const float s = dl * kSixth;
     const float sa = pa.w * s, sb = pb.w * s, sc = pc.w * s, sd = pd.w * s;
     pa.x += sa * gax;
@@ -162,7 +161,7 @@ __device__ __forceinline__ float wave_max(float v)
 }
 
 template <int PPT, bool STAGE, bool RESIDUAL>
-__global__ void __launch_bounds__(1024) xpbd_step_kernel(StepArgs A)
+__global__ void __launch_bounds__(1024) xpbd_step_lds_kernel(StepArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int env = blockIdx.x;
@@ -290,14 +289,22 @@ __global__ void __launch_bounds__(1024) xpbd_step_kernel(StepArgs A)
             for (int it = 0; it < A.iterations; ++it) {
                 for (int c = 0; c < md.num_edge_colours; ++c) {
                     const int end = md.edge_ptr[c + 1];
-                    for (int j = md.edge_ptr[c] + tid; j < end; j += B)
-                        project_edge(xw, lam, j, e_pair[j], e_rest[j], alpha_d);
+                    for (int j = md.edge_ptr[c] + tid; j < end; j += B) {
+                        const uint32_t pr = e_pair[j];
+                        float l = lam[j];
+                        edge_update(xw, (int)(pr & 0xffffu), (int)(pr >> 16), e_rest[j], alpha_d, l);
+                        lam[j] = l;
+                    }
                     __syncthreads();
                 }
                 for (int c = 0; c < md.num_tet_colours; ++c) {
                     const int end = md.tet_ptr[c + 1];
-                    for (int j = md.tet_ptr[c] + tid; j < end; j += B)
-                        project_tet(xw, lam + E, j, t_quad[j], t_rest[j], alpha_v);
+                    for (int j = md.tet_ptr[c] + tid; j < end; j += B) {
+                        const uint2 q = t_quad[j];
+                        float l = lam[E + j];
+                        tet_update(xw, q.x, q.y, t_rest[j], alpha_v, l);
+                        lam[E + j] = l;
+                    }
                     __syncthreads();
                 }
                 for (int t = 0; t < tools; ++t) {
@@ -407,6 +414,363 @@ __global__ void __launch_bounds__(1024) xpbd_step_kernel(StepArgs A)
     }
 }
 
+// Pointers into global memory seen through the global (1) or constant (4)
+// address space, so that loads become global_load (vector memory counter
+// only) or s_load (uniform, scalar cache) instead of flat loads.
+#define XPBD_GLOBAL __attribute__((address_space(1)))
+#define XPBD_CONSTANT __attribute__((address_space(4)))
+
+// Native vector types (the HIP vector classes cannot be loaded through an
+// address-space-qualified pointer).
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+// Constraint record of round d for lane tid (zero when the lane has no slot).
+__device__ __forceinline__ v4u load_record(const XPBD_GLOBAL v2u *edge_rec,
+                                           const XPBD_GLOBAL v4u *tet_rec, v4i d, int tid)
+{
+    const int slot = d.x + tid;
+    v4u r = 0u;
+    if (slot < d.y) {
+        if (d.z == ROUND_EDGE) {
+            const v2u e = edge_rec[slot];
+            r.x = e.x;
+            r.y = e.y;
+        } else {
+            r = tet_rec[slot];
+        }
+    }
+    return r;
+}
+
+// Software pipeline of the round loop: the descriptor of round r + 2 is being
+// fetched (scalar load) and the record of round r + 1 (vector load) while
+// round r is projected.
+struct RoundPipe {
+    const XPBD_CONSTANT v4i *rounds;
+    const XPBD_GLOBAL v2u *edge_rec;
+    const XPBD_GLOBAL v4u *tet_rec;
+    int R;
+    v4i d1;     // descriptor of the next round
+    v4i d2;     // descriptor of the round after it
+    v4u rec1;   // record of the next round for this lane
+};
+
+// Multipliers of a lane's constraints: one register per round, in banks of 32
+// registers held as a vector and indexed with the (workgroup-uniform) round
+// counter, which the compiler lowers to relative register addressing.
+typedef float lambda_bank __attribute__((ext_vector_type(32)));
+
+// Round r of an iteration: the lane projects at most one constraint of the
+// current colour (slot begin + tid) with the record fetched during round r - 1,
+// advances the pipeline, and joins the colour's barrier.
+__device__ __forceinline__ void run_round(float4 *xw, RoundPipe &pp, int r, int tid,
+                                          lambda_bank &bank, float alpha_d, float alpha_v)
+{
+    const v4i d = pp.d1;
+    const v4u rec = pp.rec1;
+    pp.d1 = pp.d2;
+    pp.rec1 = load_record(pp.edge_rec, pp.tet_rec, pp.d1, tid);
+    int r2 = r + 2;
+    r2 = r2 >= pp.R ? r2 - pp.R : r2;
+    r2 = r2 >= pp.R ? r2 - pp.R : r2;
+    pp.d2 = pp.rounds[r2];
+    if (d.x + tid < d.y) {
+        float l = bank[r & 31];
+        if (d.z == ROUND_EDGE)
+            edge_update(xw, (int)(rec.x & 0xffffu), (int)(rec.x >> 16), __uint_as_float(rec.y),
+                        alpha_d, l);
+        else
+            tet_update(xw, rec.x, rec.y, __uint_as_float(rec.z), alpha_v, l);
+        bank[r & 31] = l;
+    }
+    if (d.w)
+        __syncthreads();
+}
+
+// Residual (C + alpha~ lambda) / rest of the lane's constraint of round r.
+__device__ __forceinline__ void residual_round(const float4 *xw, const RoundPipe &pp, int r, int tid,
+                                               float l, float alpha_d, float alpha_v,
+                                               float &sum, float &big)
+{
+    const v4i d = pp.rounds[r];
+    if (d.x + tid >= d.y)
+        return;
+    const v4u rec = load_record(pp.edge_rec, pp.tet_rec, d, tid);
+    float res;
+    if (d.z == ROUND_EDGE) {
+        const float4 pa = xw[rec.x & 0xffffu], pb = xw[rec.x >> 16];
+        const float dx = pa.x - pb.x, dy = pa.y - pb.y, dz = pa.z - pb.z;
+        const float rest = __uint_as_float(rec.y);
+        res = (sqrtf(dx * dx + dy * dy + dz * dz) - rest + alpha_d * l) / rest;
+    } else {
+        const float4 pa = xw[rec.x & 0xffffu], pb = xw[rec.x >> 16];
+        const float4 pc = xw[rec.y & 0xffffu], pd = xw[rec.y >> 16];
+        const float bax = pb.x - pa.x, bay = pb.y - pa.y, baz = pb.z - pa.z;
+        const float cax = pc.x - pa.x, cay = pc.y - pa.y, caz = pc.z - pa.z;
+        const float dax = pd.x - pa.x, day = pd.y - pa.y, daz = pd.z - pa.z;
+        const float vol = (bax * (cay * daz - caz * day) + bay * (caz * dax - cax * daz) +
+                           baz * (cax * day - cay * dax)) * kSixth;
+        const float rest = __uint_as_float(rec.z);
+        res = (vol - rest + alpha_v * l) / rest;
+    }
+    sum += res * res;
+    big = fmaxf(big, fabsf(res));
+}
+
+__device__ __forceinline__ void store_lambda_round(float *out, const MeshDev &md,
+                                                   const RoundPipe &pp, int r, int tid, float l)
+{
+    const v4i d = pp.rounds[r];
+    const int slot = d.x + tid;
+    if (slot < d.y) {
+        if (d.z == ROUND_EDGE)
+            out[md.edge_id[slot]] = l;
+        else
+            out[md.num_edges + md.tet_id[slot]] = l;
+    }
+}
+
+// One workgroup per environment.  LDS: particles as float4 (x, y, z, w), then
+// velocities and start-of-substep positions (structure of arrays), then 256 B
+// of scratch.  Multipliers live in registers (NB banks of 32 rounds).
+template <int NB>
+__global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int env = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int B = blockDim.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int num_waves = B >> 6;
+
+    const EnvDev ed = A.envs[env];
+    const MeshDev md = A.meshes[ed.mesh];
+    const int V = md.num_vertices, E = md.num_edges, T = md.num_tets;
+    const int R = md.num_rounds;
+    const int R0 = R < 32 ? R : 32;
+    const int tools = A.num_tools;
+    const RegLdsLayout L = reg_lds_layout(V);
+    float4 *xw = reinterpret_cast<float4 *>(smem + L.xw);
+    float *vel = reinterpret_cast<float *>(smem + L.vel);      // [3][V]
+    float *prev = reinterpret_cast<float *>(smem + L.prev);    // [3][V]
+    uint32_t *scratch = reinterpret_cast<uint32_t *>(smem + L.scratch);
+
+    const float h = A.h, inv_h = A.inv_h;
+    const float hgx = h * A.gravity[0], hgy = h * A.gravity[1], hgz = h * A.gravity[2];
+    const float alpha_d = A.compliance[2 * env] * inv_h * inv_h;   // alpha~ = alpha / h^2
+    const float alpha_v = A.compliance[2 * env + 1] * inv_h * inv_h;
+    const int NP = A.total_particles;
+    const int off = ed.particle_offset;
+
+    for (int i = tid; i < V; i += B) {
+        xw[i] = make_float4(A.pos[off + i], A.pos[NP + off + i], A.pos[2 * NP + off + i],
+                            md.inv_mass[i]);
+        vel[i] = A.vel[off + i];
+        vel[V + i] = A.vel[NP + off + i];
+        vel[2 * V + i] = A.vel[2 * NP + off + i];
+    }
+    lambda_bank bank0 = 0.0f, bank1 = 0.0f;
+    __syncthreads();
+
+    // prime the round pipeline: descriptors of rounds 0 and 1, record of round 0
+    RoundPipe pp;
+    pp.rounds = (const XPBD_CONSTANT v4i *)(uintptr_t)md.rounds;
+    pp.edge_rec = (const XPBD_GLOBAL v2u *)(uintptr_t)md.edge_rec;
+    pp.tet_rec = (const XPBD_GLOBAL v4u *)(uintptr_t)md.tet_rec;
+    pp.R = R;
+    pp.d1 = pp.rounds[0];
+    pp.d2 = pp.rounds[R > 1 ? 1 : 0];
+    pp.rec1 = load_record(pp.edge_rec, pp.tet_rec, pp.d1, tid);
+
+    uint32_t cand = 0u;  // bit 16 t + k: particle k * B + tid is a candidate of tool t
+    float3 tool0 = make_float3(0.f, 0.f, 0.f), tool1 = tool0;   // sphere centres this step
+    const int last_step = A.num_steps - 1;
+    for (int step = 0; step < A.num_steps; ++step) {
+        // instrument state and contact candidates on the start-of-step positions
+        cand = 0u;
+        for (int t = 0; t < tools; ++t) {
+            const float *c = A.tool_pos + (((size_t)step * A.num_envs + env) * tools + t) * 3;
+            const float3 ct = make_float3(c[0], c[1], c[2]);
+            if (t == 0)
+                tool0 = ct;
+            else
+                tool1 = ct;
+            const float reach2 = t == 0 ? A.tool_reach2[0] : A.tool_reach2[1];
+            for (int k = 0, i = tid; i < V; ++k, i += B)
+                if (within_reach(xw[i], ct.x, ct.y, ct.z, reach2))
+                    cand |= 1u << (16 * t + k);
+        }
+        const bool any_contact = __syncthreads_or(cand != 0u) != 0;
+
+        for (int sub = 0; sub < A.substeps; ++sub) {
+            // predict velocity and position (Alg. 1); pinned particles stay put
+            for (int i = tid; i < V; i += B) {
+                float4 p = xw[i];
+                prev[i] = p.x;
+                prev[V + i] = p.y;
+                prev[2 * V + i] = p.z;
+                if (p.w > 0.0f) {
+                    const float vx = vel[i] + hgx, vy = vel[V + i] + hgy, vz = vel[2 * V + i] + hgz;
+                    vel[i] = vx;
+                    vel[V + i] = vy;
+                    vel[2 * V + i] = vz;
+                    p.x += h * vx;
+                    p.y += h * vy;
+                    p.z += h * vz;
+                    xw[i] = p;
+                }
+            }
+            bank0 = 0.0f;
+            if constexpr (NB > 1)
+                bank1 = 0.0f;
+            __syncthreads();
+
+            for (int it = 0; it < A.iterations; ++it) {
+                for (int r = 0; r < R0; ++r)
+                    run_round(xw, pp, r, tid, bank0, alpha_d, alpha_v);
+                if constexpr (NB > 1)
+                    for (int r = 32; r < R; ++r)
+                        run_round(xw, pp, r, tid, bank1, alpha_d, alpha_v);
+                if (any_contact) {
+                    for (int t = 0; t < tools; ++t) {
+                        const float3 ct = t == 0 ? tool0 : tool1;
+                        const float rt = t == 0 ? A.tool_radius[0] : A.tool_radius[1];
+                        const float rt2 = t == 0 ? A.tool_radius2[0] : A.tool_radius2[1];
+                        for (int k = 0, i = tid; i < V; ++k, i += B)
+                            if ((cand >> (16 * t + k)) & 1u)
+                                project_contact(xw, i, ct.x, ct.y, ct.z, rt, rt2);
+                    }
+                    __syncthreads();
+                }
+            }
+
+            // velocity update v = (x - x_prev) / h (Alg. 1)
+            for (int i = tid; i < V; i += B) {
+                const float4 p = xw[i];
+                vel[i] = (p.x - prev[i]) * inv_h;
+                vel[V + i] = (p.y - prev[V + i]) * inv_h;
+                vel[2 * V + i] = (p.z - prev[2 * V + i]) * inv_h;
+            }
+        }
+    }
+
+    // write back (structure of arrays, coalesced)
+    int bad = 0;
+    for (int i = tid; i < V; i += B) {
+        const float4 p = xw[i];
+        const float vx = vel[i], vy = vel[V + i], vz = vel[2 * V + i];
+        A.pos[off + i] = p.x;
+        A.pos[NP + off + i] = p.y;
+        A.pos[2 * NP + off + i] = p.z;
+        A.vel[off + i] = vx;
+        A.vel[NP + off + i] = vy;
+        A.vel[2 * NP + off + i] = vz;
+        bad |= !(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(vx) &&
+                 isfinite(vy) && isfinite(vz));
+    }
+    bad = __syncthreads_or(bad);
+    if (tid == 0 && bad)
+        A.nonfinite[env] = 1;
+
+    // contact candidates of the last step, ascending particle ids
+    const int kmax = (V + B - 1) / B;
+    for (int t = 0; t < tools; ++t) {
+        int32_t *list = A.contacts + (size_t)t * NP + off;
+        int base = 0;
+        for (int k = 0; k < kmax; ++k) {
+            const bool flag = (cand >> (16 * t + k)) & 1u;
+            const uint64_t mask = __ballot(flag);
+            if (lane == 0)
+                scratch[wave] = (uint32_t)__popcll(mask);
+            __syncthreads();
+            int before = 0, total = 0;
+            for (int w = 0; w < num_waves; ++w) {
+                const int n = (int)scratch[w];
+                before += w < wave ? n : 0;
+                total += n;
+            }
+            if (flag)
+                list[base + before + __popcll(mask & __lanemask_lt())] = k * B + tid;
+            base += total;
+            __syncthreads();
+        }
+        for (int n = base + tid; n < V; n += B)
+            list[n] = -1;
+        if (tid == 0)
+            A.contact_counts[env * tools + t] = base;
+    }
+    if (A.lambda_out) {
+        float *out = A.lambda_out + ed.lambda_offset;
+        for (int r = 0; r < R0; ++r)
+            store_lambda_round(out, md, pp, r, tid, bank0[r & 31]);
+        if constexpr (NB > 1)
+            for (int r = 32; r < R; ++r)
+                store_lambda_round(out, md, pp, r, tid, bank1[r & 31]);
+    }
+}
+
+// Constraint residual (C + alpha~ lambda) / rest of every kept constraint of an
+// environment, from its written-back positions and stored multipliers
+// (constraint order), reduced to (RMS, max |r|).  One workgroup per environment.
+__global__ void __launch_bounds__(256) residual_kernel(StepArgs A)
+{
+    __shared__ float part[2][4];
+    const int env = blockIdx.x;
+    const int tid = threadIdx.x;
+    const EnvDev ed = A.envs[env];
+    const MeshDev md = A.meshes[ed.mesh];
+    const int E = md.num_edges, T = md.num_tets;
+    const int NP = A.total_particles;
+    const int off = ed.particle_offset;
+    const float *px = A.pos + off, *py = A.pos + NP + off, *pz = A.pos + 2 * NP + off;
+    const float *lam = A.lambda_out + ed.lambda_offset;
+    const float inv_h2 = A.inv_h * A.inv_h;
+    const float alpha_d = A.compliance[2 * env] * inv_h2, alpha_v = A.compliance[2 * env + 1] * inv_h2;
+    float sum = 0.0f, big = 0.0f;
+    for (int j = tid; j < E; j += blockDim.x) {
+        const uint2 e = md.edge_rec[j];
+        const int a = (int)(e.x & 0xffffu), b = (int)(e.x >> 16);
+        const float dx = px[a] - px[b], dy = py[a] - py[b], dz = pz[a] - pz[b];
+        const float rest = __uint_as_float(e.y);
+        const float r = (sqrtf(dx * dx + dy * dy + dz * dz) - rest + alpha_d * lam[md.edge_id[j]]) / rest;
+        sum += r * r;
+        big = fmaxf(big, fabsf(r));
+    }
+    for (int j = tid; j < T; j += blockDim.x) {
+        const uint4 q = md.tet_rec[j];
+        const int a = (int)(q.x & 0xffffu), b = (int)(q.x >> 16);
+        const int c = (int)(q.y & 0xffffu), d = (int)(q.y >> 16);
+        const float bax = px[b] - px[a], bay = py[b] - py[a], baz = pz[b] - pz[a];
+        const float cax = px[c] - px[a], cay = py[c] - py[a], caz = pz[c] - pz[a];
+        const float dax = px[d] - px[a], day = py[d] - py[a], daz = pz[d] - pz[a];
+        const float vol = (bax * (cay * daz - caz * day) + bay * (caz * dax - cax * daz) +
+                           baz * (cax * day - cay * dax)) * kSixth;
+        const float rest = __uint_as_float(q.z);
+        const float r = (vol - rest + alpha_v * lam[E + md.tet_id[j]]) / rest;
+        sum += r * r;
+        big = fmaxf(big, fabsf(r));
+    }
+    sum = wave_sum(sum);
+    big = wave_max(big);
+    if ((tid & 63) == 0) {
+        part[0][tid >> 6] = sum;
+        part[1][tid >> 6] = big;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float s = 0.0f, m = 0.0f;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            s += part[0][w];
+            m = fmaxf(m, part[1][w]);
+        }
+        A.residual[2 * env] = E + T > 0 ? sqrtf(s / (float)(E + T)) : 0.0f;
+        A.residual[2 * env + 1] = m;
+    }
+}
+
 __global__ void soa_to_aos_kernel(const float *__restrict__ soa, float *__restrict__ aos, int32_t n)
 {
     const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
@@ -430,7 +794,7 @@ __global__ void aos_to_soa_kernel(const float *__restrict__ aos, float *__restri
 template <int PPT, bool STAGE, bool RESIDUAL>
 hipError_t launch_variant(const StepArgs &args, int block, uint32_t lds_bytes, hipStream_t stream)
 {
-    auto kernel = xpbd_step_kernel<PPT, STAGE, RESIDUAL>;
+    auto kernel = xpbd_step_lds_kernel<PPT, STAGE, RESIDUAL>;
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)lds_bytes);
@@ -452,6 +816,20 @@ hipError_t launch_ppt(const StepArgs &args, int block, bool stage, uint32_t lds,
                  : launch_variant<PPT, false, false>(args, block, lds, s);
 }
 
+template <int NB>
+hipError_t launch_reg_variant(const StepArgs &args, int block, uint32_t lds_bytes, hipStream_t stream)
+{
+    auto kernel = xpbd_step_reg_kernel<NB>;
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds_bytes);
+    if (err != hipSuccess)
+        return err;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)args.num_envs), dim3((unsigned)block), lds_bytes,
+                       stream, args);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_step(const StepArgs &args, int block, int particles_per_thread,
@@ -465,6 +843,18 @@ hipError_t launch_step(const StepArgs &args, int block, int particles_per_thread
     case 8: return launch_ppt<8>(args, block, stage_topology, lds_bytes, want_residual, stream);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_step_reg(const StepArgs &args, int block, int lambda_banks, uint32_t lds_bytes,
+                           bool want_residual, hipStream_t stream)
+{
+    hipError_t err = lambda_banks == 1 ? launch_reg_variant<1>(args, block, lds_bytes, stream)
+                     : lambda_banks == 2 ? launch_reg_variant<2>(args, block, lds_bytes, stream)
+                                         : hipErrorInvalidValue;
+    if (err != hipSuccess || !want_residual)
+        return err;
+    hipLaunchKernelGGL(residual_kernel, dim3((unsigned)args.num_envs), dim3(256), 0, stream, args);
+    return hipGetLastError();
 }
 
 hipError_t launch_soa_to_aos(const float *soa, float *aos, int32_t n, hipStream_t stream)

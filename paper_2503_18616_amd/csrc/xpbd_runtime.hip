@@ -73,6 +73,8 @@ struct xpbd_batch {
     int block = 64;
     int particles_per_thread = 1;
     bool stage_topology = false;
+    bool register_variant = false;
+    int lambda_banks = 1;
     uint32_t lds_bytes = 0;
     std::vector<PreparedMesh> meshes;
     std::vector<int32_t> env_mesh;
@@ -147,6 +149,8 @@ xpbd_status validate_params(const xpbd_params *p)
     if (p->block_size != 0 &&
         (p->block_size < 64 || p->block_size > 1024 || p->block_size % 64 != 0))
         return fail(XPBD_E_ARG, "block_size must be 0 or a multiple of 64 in [64, 1024]");
+    if (p->solver_variant < XPBD_VARIANT_AUTO || p->solver_variant > XPBD_VARIANT_LDS)
+        return fail(XPBD_E_ARG, "unknown solver_variant %d", p->solver_variant);
     return XPBD_OK;
 }
 
@@ -172,6 +176,39 @@ void build_schedule(const std::vector<int32_t> &colour, int32_t num_colours,
     slot_id.assign(colour.size(), 0);
     for (size_t j = 0; j < colour.size(); ++j)
         slot_id[(size_t)fill[(size_t)colour[j]]++] = (int32_t)j;
+}
+
+// Rounds of the register-multiplier kernel for block size B: each colour is
+// cut into ceil(size / B) rounds, the last of which carries the barrier.
+void build_rounds(const std::vector<int32_t> &edge_ptr, const std::vector<int32_t> &tet_ptr, int B,
+                  std::vector<int4> &rounds)
+{
+    rounds.clear();
+    const std::vector<int32_t> *ptrs[2] = {&edge_ptr, &tet_ptr};
+    for (int kind = 0; kind < 2; ++kind) {
+        const std::vector<int32_t> &ptr = *ptrs[kind];
+        for (size_t c = 0; c + 1 < ptr.size(); ++c) {
+            const int32_t begin = ptr[c], end = ptr[c + 1];
+            for (int32_t b0 = begin; b0 < end; b0 += B)
+                rounds.push_back(make_int4(b0, end, kind == 0 ? xpbd::ROUND_EDGE : xpbd::ROUND_TET,
+                                           b0 + B >= end ? 1 : 0));
+        }
+    }
+}
+
+int count_rounds(const PreparedMesh &pm, int B)
+{
+    std::vector<int32_t> n_e((size_t)pm.num_edge_colours, 0), n_t((size_t)pm.num_tet_colours, 0);
+    for (int32_t c : pm.edge_colour)
+        n_e[(size_t)c]++;
+    for (int32_t c : pm.tet_colour)
+        n_t[(size_t)c]++;
+    int r = 0;
+    for (int32_t n : n_e)
+        r += (n + B - 1) / B;
+    for (int32_t n : n_t)
+        r += (n + B - 1) / B;
+    return r;
 }
 
 xpbd_status field_bytes(const xpbd_batch *b, int32_t field, size_t *bytes)
@@ -312,6 +349,36 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     HIP_TRY(hipGetDevice(&device));
     int lds_limit = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+
+    // register-multiplier variant: the smallest block of 256, 512 or 1024 threads (or
+    // the requested one) whose round schedule fits the register banks of every mesh
+    bool use_registers = false;
+    int reg_block = 0, reg_rounds = 0;
+    if (params->solver_variant != XPBD_VARIANT_LDS) {
+        const int tries[3] = {256, 512, 1024};
+        const int n_tries = params->block_size ? 1 : 3;
+        for (int k = 0; k < n_tries && !use_registers; ++k) {
+            const int B = params->block_size ? params->block_size : tries[k];
+            int worst = 0;
+            for (const auto &pm : prepared)
+                worst = std::max(worst, count_rounds(pm, B));
+            const bool fits = worst <= xpbd::kMaxRounds && vmax <= 16 * B &&
+                              xpbd::reg_lds_layout(vmax).total <= (uint32_t)lds_limit;
+            if (fits) {
+                use_registers = true;
+                reg_block = B;
+                reg_rounds = worst;
+            }
+        }
+        if (!use_registers && params->solver_variant == XPBD_VARIANT_REGISTERS)
+            return fail(XPBD_E_CAPACITY, "the round schedule needs more than %d rounds per lane "
+                        "or more LDS than the device has; use the LDS variant",
+                        xpbd::kMaxRounds);
+    }
+    if (use_registers) {
+        block = reg_block;
+        ppt = 1;
+    }
     uint32_t lds_staged = 0, lds_global = 0;
     for (const auto &pm : prepared) {
         lds_staged = std::max(lds_staged, xpbd::lds_layout(pm.num_vertices, pm.num_edges(),
@@ -323,6 +390,10 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     }
     bool stage = lds_staged <= (uint32_t)lds_limit;
     uint32_t lds = stage ? lds_staged : lds_global;
+    if (use_registers) {
+        stage = false;
+        lds = xpbd::reg_lds_layout(vmax).total;
+    }
     if (lds > (uint32_t)lds_limit)
         return fail(XPBD_E_CAPACITY, "environment needs %u bytes of LDS; the device has %d",
                     lds, lds_limit);
@@ -336,6 +407,8 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     b->block = block;
     b->particles_per_thread = ppt;
     b->stage_topology = stage;
+    b->register_variant = use_registers;
+    b->lambda_banks = reg_rounds > 32 ? 2 : 1;
     b->lds_bytes = lds;
     b->env_mesh.assign(env_mesh, env_mesh + num_envs);
     b->meshes = std::move(prepared);
@@ -369,8 +442,25 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
                                          (uint32_t)q[2] | ((uint32_t)q[3] << 16));
             trest[(size_t)j] = (float)pm.rest_volume[(size_t)t];
         }
+        std::vector<uint2> erec((size_t)E);
+        std::vector<uint4> trec((size_t)T);
+        for (int32_t j = 0; j < E; ++j) {
+            uint32_t bits;
+            std::memcpy(&bits, &erest[(size_t)j], 4);
+            erec[(size_t)j] = make_uint2(pair[(size_t)j], bits);
+        }
+        for (int32_t j = 0; j < T; ++j) {
+            uint32_t bits;
+            std::memcpy(&bits, &trest[(size_t)j], 4);
+            trec[(size_t)j] = make_uint4(quad[(size_t)j].x, quad[(size_t)j].y, bits, 0u);
+        }
+        std::vector<int4> rounds;
+        build_rounds(eptr, tptr, block, rounds);
+        if (rounds.empty())
+            rounds.push_back(make_int4(0, 0, xpbd::ROUND_EDGE, 0));
         MeshDev &d = mdev[(size_t)m];
         std::memset(&d, 0, sizeof d);
+        d.num_rounds = use_registers ? (int32_t)rounds.size() : 0;
         d.num_vertices = pm.num_vertices;
         d.num_edges = E;
         d.num_tets = T;
@@ -387,6 +477,15 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
             (st = b->upload(&p_eid, eslot)) || (st = b->upload(&p_tid, tslot)) ||
             (st = b->upload(&p_w, pm.inv_mass)))
             return cleanup(st);
+        uint2 *p_erec;
+        uint4 *p_trec;
+        int4 *p_rounds;
+        if ((st = b->upload(&p_erec, erec)) || (st = b->upload(&p_trec, trec)) ||
+            (st = b->upload(&p_rounds, rounds)))
+            return cleanup(st);
+        d.edge_rec = p_erec;
+        d.tet_rec = p_trec;
+        d.rounds = p_rounds;
         d.edge_pair = p_pair;
         d.edge_rest = p_erest;
         d.tet_quad = p_quad;
@@ -443,7 +542,9 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         (st = b->alloc(reinterpret_cast<void **>(&b->staging), 3 * (size_t)np * sizeof(float))))
         return cleanup(st);
     b->staging_bytes = 3 * (size_t)np * sizeof(float);
-    if (params->flags & XPBD_F_LAMBDA)
+    // the register variant hands its multipliers to the residual kernel through this buffer
+    if ((params->flags & XPBD_F_LAMBDA) ||
+        (use_registers && (params->flags & XPBD_F_RESIDUAL)))
         if ((st = b->upload(&b->lambda, lam_init)))
             return cleanup(st);
     hipError_t e = hipStreamSynchronize(b->stream);
@@ -517,8 +618,11 @@ xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
         a.tool_reach2[t] = reach * reach;
     }
     const bool resid = (b->params.flags & XPBD_F_RESIDUAL) != 0;
-    HIP_TRY(xpbd::launch_step(a, b->block, b->particles_per_thread, b->stage_topology,
-                              b->lds_bytes, resid, b->stream));
+    if (b->register_variant)
+        HIP_TRY(xpbd::launch_step_reg(a, b->block, b->lambda_banks, b->lds_bytes, resid, b->stream));
+    else
+        HIP_TRY(xpbd::launch_step(a, b->block, b->particles_per_thread, b->stage_topology,
+                                  b->lds_bytes, resid, b->stream));
     return XPBD_OK;
 }
 
@@ -541,7 +645,7 @@ xpbd_status xpbd_read_state(xpbd_batch *b, int32_t field, void *dst, size_t dst_
         return s;
     if (dst_bytes != need)
         return fail(XPBD_E_STATE, "field %d needs %zu bytes, got %zu", field, need, dst_bytes);
-    if (field == XPBD_FIELD_LAMBDA && !b->lambda)
+    if (field == XPBD_FIELD_LAMBDA && !(b->params.flags & XPBD_F_LAMBDA))
         return fail(XPBD_E_STATE, "multipliers are stored only with XPBD_F_LAMBDA");
     if (field == XPBD_FIELD_RESIDUAL && !(b->params.flags & XPBD_F_RESIDUAL))
         return fail(XPBD_E_STATE, "the residual is computed only with XPBD_F_RESIDUAL");

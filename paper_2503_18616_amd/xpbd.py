@@ -45,6 +45,10 @@ FIELD_NONFINITE = 8
 F_RESIDUAL = 0x1
 F_LAMBDA = 0x2
 
+VARIANT_AUTO = 0
+VARIANT_REGISTERS = 1
+VARIANT_LDS = 2
+
 # field -> numpy dtype of its elements
 FIELD_DTYPES = {FIELD_POS: np.float32, FIELD_VEL: np.float32, FIELD_LAMBDA: np.float32,
                 FIELD_CONTACTS: np.int32, FIELD_CONTACT_COUNTS: np.int32,
@@ -65,7 +69,8 @@ class XpbdParams(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_float), ("substeps", ctypes.c_int32),
                 ("iterations", ctypes.c_int32), ("gravity", ctypes.c_float * 3),
                 ("num_tools", ctypes.c_int32), ("tool_radius", ctypes.c_float * 2),
-                ("flags", ctypes.c_uint32), ("block_size", ctypes.c_int32)]
+                ("flags", ctypes.c_uint32), ("block_size", ctypes.c_int32),
+                ("solver_variant", ctypes.c_int32)]
 
 
 _lib.xpbd_create_batch.restype = ctypes.c_int
@@ -135,7 +140,8 @@ def _mesh_struct(rest_pos, inv_mass, tets, keep):
 
 
 def make_params(dt, substeps, iterations, gravity=(0.0, 0.0, -9.81), num_tools=1,
-                tool_radius=(0.005, 0.005), flags=0, block_size=0) -> XpbdParams:
+                tool_radius=(0.005, 0.005), flags=0, block_size=0,
+                solver_variant=VARIANT_AUTO) -> XpbdParams:
     p = XpbdParams()
     p.dt = dt
     p.substeps = substeps
@@ -146,6 +152,7 @@ def make_params(dt, substeps, iterations, gravity=(0.0, 0.0, -9.81), num_tools=1
     p.tool_radius[:] = r[:2]
     p.flags = flags
     p.block_size = block_size
+    p.solver_variant = solver_variant
     return p
 
 

@@ -24,9 +24,14 @@ def xp():
     return xpbd
 
 
-def make_batch(xp, wl, flags=0, block_size=0):
-    return xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance,
-                    K.lib_params(xp, wl, flags, block_size))
+VARIANTS = [1, 2]   # multipliers in registers, multipliers in LDS
+VARIANT_IDS = ["registers", "lds"]
+
+
+def make_batch(xp, wl, flags=0, block_size=0, variant=0):
+    p = K.lib_params(xp, wl, flags, block_size)
+    p.solver_variant = variant
+    return xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p)
 
 
 def check_contacts_step(xp, oracle_lib, batch, wl, start_x, tools_step, oracle_lists=None,
@@ -58,8 +63,9 @@ def check_contacts_step(xp, oracle_lib, batch, wl, start_x, tools_step, oracle_l
 
 
 # --------------------------------------------------------------------------------------
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
 @pytest.mark.parametrize("start_depth", [2e-3, 6e-3])
-def test_single_env_parity_per_step(xp, oracle_lib, start_depth):
+def test_single_env_parity_per_step(xp, oracle_lib, start_depth, variant):
     """One environment, 8x5x3 slab, 4 iterations, 100 steps launched one step at a time."""
     wl = W.single_env_workload(seed=0)
     steps = 100
@@ -67,7 +73,7 @@ def test_single_env_parity_per_step(xp, oracle_lib, start_depth):
     om = K.oracle_meshes(oracle_lib, wl)[0]
     ref = oracle_lib.run_env(om, wl.compliance[0], K.oracle_params(oracle_lib, wl), tools[:, 0],
                              steps, want_lambda=True, want_contacts=True, want_residual=True)
-    with make_batch(xp, wl, flags=xp.F_RESIDUAL | xp.F_LAMBDA) as b:
+    with make_batch(xp, wl, flags=xp.F_RESIDUAL | xp.F_LAMBDA, variant=variant) as b:
         x_hist = []
         for s in range(steps):
             x0 = b.positions()
@@ -92,10 +98,11 @@ def test_single_env_parity_per_step(xp, oracle_lib, start_depth):
     assert abs(res[1] - r_ref[1]) <= 0.05 * r_ref[1] + 1e-6
 
 
-def test_single_launch_equals_step_by_step(xp):
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
+def test_single_launch_equals_step_by_step(xp, variant):
     wl = W.single_env_workload(seed=1)
     tools = wl.tools(100)
-    with make_batch(xp, wl) as a, make_batch(xp, wl) as b:
+    with make_batch(xp, wl, variant=variant) as a, make_batch(xp, wl, variant=variant) as b:
         a.step(100, tools)
         for s in range(100):
             b.step(1, tools[s:s + 1])
@@ -103,7 +110,8 @@ def test_single_launch_equals_step_by_step(xp):
         assert np.array_equal(a.velocities(), b.velocities())
 
 
-def test_batch_parity_sampled_envs(xp, oracle_lib):
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
+def test_batch_parity_sampled_envs(xp, oracle_lib, variant):
     """1024 environments of the 16x10x4 slab, 8 iterations, per-env compliances and
     tool paths, launched one step at a time; 16 sampled environments against the oracle."""
     steps = 100
@@ -114,7 +122,7 @@ def test_batch_parity_sampled_envs(xp, oracle_lib):
     refs = oracle_lib.run_batch(om, wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
                                 tools[:, sample], steps, env_ids=sample, threads=8,
                                 want_contacts=True)
-    with make_batch(xp, wl) as b:
+    with make_batch(xp, wl, flags=xp.F_RESIDUAL, variant=variant) as b:
         offs = b.env_offsets
         for s in range(steps):
             check = s % 10 == 0 or s == steps - 1
@@ -125,6 +133,8 @@ def test_batch_parity_sampled_envs(xp, oracle_lib):
                 check_contacts_step(xp, oracle_lib, b, wl, x0, tools[s], lists, envs=sample,
                                     pos_err=1e-5)
         x = b.positions()
+        res = b.read(xp.FIELD_RESIDUAL).reshape(-1, 2)
+    assert np.all(np.isfinite(res)) and np.all(res[:, 0] > 0) and np.all(res[:, 1] >= res[:, 0])
     worst = 0.0
     for n, e in enumerate(sample):
         err = K.max_position_error(K.env_block(x, offs, e), refs[n].x)
@@ -165,12 +175,14 @@ def test_free_fall_closed_form(xp):
     assert np.max(np.abs(x - expect)) < K.POS_TOL
 
 
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
 @pytest.mark.parametrize("block", [64, 128, 256, 512])
-def test_block_size_does_not_change_results(xp, block):
+def test_block_size_does_not_change_results(xp, block, variant):
     """Which lane projects which constraint of a colour cannot matter: bitwise equal."""
     wl = W.single_env_workload(seed=3)
     tools = W.tool_path(30, 1, 3, start_depth=6e-3)
-    with make_batch(xp, wl) as ref, make_batch(xp, wl, block_size=block) as b:
+    with make_batch(xp, wl, variant=variant) as ref, \
+            make_batch(xp, wl, block_size=block, variant=variant) as b:
         ref.step(30, tools)
         b.step(30, tools)
         assert np.array_equal(ref.positions(), b.positions())
@@ -185,14 +197,15 @@ def uneven_workload(seed=0):
                       num_steps=100, seed=seed)
 
 
-def test_uneven_meshes_parity(xp, oracle_lib):
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
+def test_uneven_meshes_parity(xp, oracle_lib, variant):
     wl = uneven_workload()
     steps = 100
     tools = W.tool_path(steps, wl.num_envs, wl.seed, start_depth=5e-3)
     om = K.oracle_meshes(oracle_lib, wl)
     refs = oracle_lib.run_batch(om, wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
                                 tools, steps, threads=6)
-    with make_batch(xp, wl) as b:
+    with make_batch(xp, wl, variant=variant) as b:
         b.step(steps, tools)
         x = b.positions()
         for e in range(wl.num_envs):
@@ -200,7 +213,8 @@ def test_uneven_meshes_parity(xp, oracle_lib):
             assert err <= K.POS_TOL, f"env {e}: {err:.3e}"
 
 
-def test_two_tools_parity(xp, oracle_lib):
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
+def test_two_tools_parity(xp, oracle_lib, variant):
     wl = W.single_env_workload(seed=4)
     wl.num_tools = 2
     steps = 60
@@ -209,7 +223,7 @@ def test_two_tools_parity(xp, oracle_lib):
     ref = oracle_lib.run_env(om, wl.compliance[0], K.oracle_params(oracle_lib, wl), tools[:, 0],
                              steps, want_contacts=True)
     assert ref.contact_count.sum() > 0
-    with make_batch(xp, wl) as b:
+    with make_batch(xp, wl, variant=variant) as b:
         for s in range(steps):
             x0 = b.positions()
             b.step(1, tools[s:s + 1])
@@ -220,7 +234,8 @@ def test_two_tools_parity(xp, oracle_lib):
     assert err <= K.POS_TOL
 
 
-def test_largest_mesh_parity(xp, oracle_lib):
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
+def test_largest_mesh_parity(xp, oracle_lib, variant):
     """The 20x12x6 slab (1911 particles), the largest of the uneven range: its
     constraint lists do not fit LDS next to the particles and are read from
     global memory."""
@@ -232,7 +247,7 @@ def test_largest_mesh_parity(xp, oracle_lib):
     om = K.oracle_meshes(oracle_lib, wl)
     refs = oracle_lib.run_batch(om, wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
                                 tools, steps, threads=3)
-    with make_batch(xp, wl) as b:
+    with make_batch(xp, wl, variant=variant) as b:
         b.step(steps, tools)
         x = b.positions()
         for e in range(3):
@@ -240,14 +255,15 @@ def test_largest_mesh_parity(xp, oracle_lib):
             assert err <= K.POS_TOL, f"env {e}: {err:.3e}"
 
 
-def test_resume_is_bitwise(xp):
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
+def test_resume_is_bitwise(xp, variant):
     wl = W.batch_workload(8, seed=2, num_steps=40)
     tools = wl.tools(40)
-    with make_batch(xp, wl) as full, make_batch(xp, wl) as half:
+    with make_batch(xp, wl, variant=variant) as full, make_batch(xp, wl, variant=variant) as half:
         full.step(40, tools)
         half.step(20, tools[:20])
         x, v = half.positions(), half.velocities()
-        with make_batch(xp, wl) as resumed:
+        with make_batch(xp, wl, variant=variant) as resumed:
             resumed.write(xp.FIELD_POS, x)
             resumed.write(xp.FIELD_VEL, v)
             resumed.step(20, tools[20:])
@@ -255,10 +271,12 @@ def test_resume_is_bitwise(xp):
             assert np.array_equal(resumed.velocities(), full.velocities())
 
 
-def test_runs_are_deterministic(xp):
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
+def test_runs_are_deterministic(xp, variant):
     wl = W.batch_workload(32, seed=3, num_steps=20)
     tools = wl.tools(20)
-    with make_batch(xp, wl, flags=xp.F_LAMBDA) as a, make_batch(xp, wl, flags=xp.F_LAMBDA) as b:
+    with make_batch(xp, wl, flags=xp.F_LAMBDA, variant=variant) as a, \
+            make_batch(xp, wl, flags=xp.F_LAMBDA, variant=variant) as b:
         a.step(20, tools)
         b.step(20, tools)
         assert np.array_equal(a.positions(), b.positions())
@@ -336,3 +354,27 @@ def test_tool_centred_on_a_particle(xp, oracle_lib):
     assert counts[0] == ref.contact_count[0, 0] and counts[0] >= 1
     assert K.max_position_error(x, ref.x) <= K.POS_TOL
     np.testing.assert_allclose(x[i], m.rest_pos[i] + [0, 0, wl.tool_radius[0]], atol=1e-6)
+
+
+def test_variants_agree(xp):
+    """The two data placements run the same projections in the same order."""
+    wl = W.batch_workload(64, seed=6, num_steps=50)
+    tools = wl.tools(50)
+    with make_batch(xp, wl, flags=xp.F_LAMBDA | xp.F_RESIDUAL, variant=1) as a, \
+            make_batch(xp, wl, flags=xp.F_LAMBDA | xp.F_RESIDUAL, variant=2) as b:
+        a.step(50, tools)
+        b.step(50, tools)
+        assert K.max_position_error(a.positions(), b.positions().astype(np.float64)) <= 0.1 * K.POS_TOL
+        la, lb = a.read(xp.FIELD_LAMBDA), b.read(xp.FIELD_LAMBDA)
+        assert np.max(np.abs(la - lb)) <= 1e-2 * np.max(np.abs(lb))
+        ra, rb = a.read(xp.FIELD_RESIDUAL), b.read(xp.FIELD_RESIDUAL)
+        np.testing.assert_allclose(ra, rb, rtol=0.05, atol=1e-6)
+        np.testing.assert_array_equal(a.read(xp.FIELD_CONTACT_COUNTS), b.read(xp.FIELD_CONTACT_COUNTS))
+
+
+def test_register_variant_refuses_oversized_schedules(xp):
+    """64 threads cannot hold the 16x10x4 slab's rounds in registers."""
+    wl = W.batch_workload(2, seed=0, num_steps=1)
+    with pytest.raises(xp.XpbdError) as e:
+        make_batch(xp, wl, block_size=64, variant=1)
+    assert e.value.status == xp.XPBD_E_CAPACITY
