@@ -59,10 +59,28 @@ def parse_args():
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library's choice)")
     ap.add_argument("--variant", type=int, default=0,
                     help="0 = library's choice, 1 = multipliers in registers, 2 = multipliers in LDS")
+    ap.add_argument("--packing", type=int, default=0,
+                    help="0 = library's choice, 1 = id order, 2 = 8-lane bank groups, 3 = 16-lane")
     ap.add_argument("--cpu-envs", type=int, default=64, help="oracle sample: environments")
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle sample: steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run one plain device copy of MIB mebibytes (reference for the "
+                         "HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """One device-to-device copy of a known size, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    torch.cuda.set_device(0)
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"copied {mib} MiB", flush=True)
 
 
 def main():
@@ -73,6 +91,9 @@ def main():
               "environments are independent, so a multi-GPU run is N copies of this one",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.steps % args.steps_per_launch or args.warmup % args.steps_per_launch:
         sys.exit("--steps and --warmup must be multiples of --steps-per-launch")
 
@@ -99,7 +120,7 @@ def main():
     tools = torch.from_numpy(wl.tools(total)).cuda()
     params = xpbd.make_params(wl.dt, S, I, wl.gravity, wl.num_tools, wl.tool_radius,
                               flags=xpbd.F_RESIDUAL, block_size=args.block,
-                              solver_variant=args.variant)
+                              solver_variant=args.variant, colour_packing=args.packing)
     stream = torch.cuda.current_stream()
     batch = xpbd.Batch([(m.rest_pos, m.inv_mass, m.tets)], wl.env_mesh, wl.compliance, params,
                        stream=stream.cuda_stream)

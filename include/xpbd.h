@@ -105,7 +105,22 @@ typedef struct {
     int32_t block_size;  /* threads per workgroup: 0 = chosen by the library, else a
                             multiple of 64 in [64, 1024] */
     int32_t solver_variant; /* XPBD_VARIANT_*: where the multipliers live */
+    int32_t colour_packing; /* XPBD_PACKING_*: order of the constraints inside a colour */
 } xpbd_params;
+
+/* Values of xpbd_params.colour_packing.  Constraints of one colour share no
+ * particle, so their order changes no result; it only decides which lanes
+ * the LDS serves together.
+ *   AUTO     SCATTERED_BANKS16 for the register variant, else BANKS16
+ *   ID_ORDER ascending constraint id
+ *   BANKS8   every aligned run of 8 lanes reads particles in distinct
+ *            16-byte LDS bank groups modulo 8, as far as a greedy fill allows
+ *   BANKS16  the same for runs of 16 lanes modulo 16
+ *   SCATTERED_BANKS16  BANKS16 after placing the particles in LDS in a fixed
+ *            pseudo-random order (register variant only; the placement is
+ *            internal and changes no result either) */
+enum { XPBD_PACKING_AUTO = 0, XPBD_PACKING_ID_ORDER = 1, XPBD_PACKING_BANKS8 = 2,
+       XPBD_PACKING_BANKS16 = 3, XPBD_PACKING_SCATTERED_BANKS16 = 4 };
 
 /* Values of xpbd_params.solver_variant.  Both variants compute the same
  * projections in the same colour order; they differ only in data placement.

@@ -5,6 +5,7 @@
 from __future__ import annotations
 
 import os
+import re
 import subprocess
 import sys
 
@@ -18,9 +19,14 @@ ARCH = "gfx950"
 HIP_SOURCES = ["xpbd_kernels.hip", "xpbd_runtime.hip"]
 CXX_SOURCES = ["mesh_setup.cpp"]
 
-# Packed FP32 instructions are kept out of every kernel.
+# Packed FP32 instructions are kept out of every kernel.  The promotion budget
+# lets both 32-register multiplier banks of the register-variant kernel live
+# in VGPRs (otherwise one of them may be demoted to scratch memory).
 HIP_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
-             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-mllvm", "-amdgpu-promote-alloca-to-vector-vgpr-ratio=2"]
+# A multiplier bank in scratch would show up as at least 128 bytes per lane.
+MAX_REG_KERNEL_SCRATCH = 96
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
 
 
@@ -30,13 +36,44 @@ def _run(cmd, verbose):
     subprocess.run(cmd, check=True)
 
 
+def _check_register_kernels(remarks: str):
+    """Fail if a register-variant kernel keeps a multiplier bank in scratch."""
+    name, scratch = None, {}
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and name:
+            scratch[name] = int(m.group(1))
+    reg = {n: v for n, v in scratch.items() if "xpbd_step_reg_kernel" in n}
+    if not reg:
+        raise RuntimeError("no resource-usage remarks for the register-variant kernels")
+    bad = {n: v for n, v in reg.items() if v > MAX_REG_KERNEL_SCRATCH}
+    if bad:
+        raise RuntimeError(f"register-variant kernels use scratch {bad} bytes/lane: a "
+                           "multiplier bank was not kept in VGPRs")
+
+
 def build(verbose: bool = False) -> str:
     """Compile every source and link the shared library; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
     objects = []
     for name in HIP_SOURCES:
         obj = os.path.join(BUILD, name + ".o")
-        _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(SRC, name), "-o", obj], verbose)
+        cmd = [HIPCC, *HIP_FLAGS, "-c", os.path.join(SRC, name), "-o", obj]
+        if name == "xpbd_kernels.hip":
+            cmd.append("-Rpass-analysis=kernel-resource-usage")
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            out = subprocess.run(cmd, capture_output=True, text=True)
+            if out.returncode != 0:
+                sys.stderr.write(out.stderr)
+                raise subprocess.CalledProcessError(out.returncode, cmd)
+            _check_register_kernels(out.stderr)
+        else:
+            _run(cmd, verbose)
         objects.append(obj)
     for name in CXX_SOURCES:
         obj = os.path.join(BUILD, name + ".o")

@@ -53,6 +53,43 @@ int32_t greedy_colouring(int32_t num_vertices, int32_t n, int32_t k, const int32
     return count;
 }
 
+void pack_colours(const int32_t *ids, int32_t k, const std::vector<int32_t> &ptr, int32_t group,
+                  int32_t modulus, std::vector<int32_t> &slot_id)
+{
+    if (group <= 0 || modulus <= 0)
+        return;
+    std::vector<int32_t> pool, packed;
+    std::vector<uint8_t> used((size_t)k * (size_t)modulus);
+    for (size_t c = 0; c + 1 < ptr.size(); ++c) {
+        pool.assign(slot_id.begin() + ptr[c], slot_id.begin() + ptr[c + 1]);
+        packed.clear();
+        while (!pool.empty()) {
+            std::fill(used.begin(), used.end(), 0);
+            for (int32_t pos = 0; pos < group && !pool.empty(); ++pos) {
+                // first constraint without a bank collision, else the one with fewest
+                size_t best = 0;
+                int best_hits = k + 1;
+                for (size_t q = 0; q < pool.size() && best_hits > 0; ++q) {
+                    const int32_t *v = ids + (size_t)pool[q] * (size_t)k;
+                    int hits = 0;
+                    for (int32_t j = 0; j < k; ++j)
+                        hits += used[(size_t)j * (size_t)modulus + (size_t)(v[j] % modulus)];
+                    if (hits < best_hits) {
+                        best_hits = hits;
+                        best = q;
+                    }
+                }
+                const int32_t *v = ids + (size_t)pool[best] * (size_t)k;
+                for (int32_t j = 0; j < k; ++j)
+                    used[(size_t)j * (size_t)modulus + (size_t)(v[j] % modulus)] = 1;
+                packed.push_back(pool[best]);
+                pool.erase(pool.begin() + (std::ptrdiff_t)best);
+            }
+        }
+        std::copy(packed.begin(), packed.end(), slot_id.begin() + ptr[c]);
+    }
+}
+
 int prepare_mesh(int32_t num_vertices, int32_t num_tets, const float *rest_pos,
                  const float *inv_mass, const int32_t *tets, PreparedMesh &out,
                  std::string &error)

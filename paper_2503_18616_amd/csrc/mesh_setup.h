@@ -37,4 +37,14 @@ int prepare_mesh(int32_t num_vertices, int32_t num_tets, const float *rest_pos,
 int32_t greedy_colouring(int32_t num_vertices, int32_t n, int32_t k, const int32_t *ids,
                          std::vector<int32_t> &colour);
 
+// Order of the constraints inside each colour (the "packing"; it does not
+// change results because constraints of one colour share no particle).
+// slot_id lists constraint ids colour by colour, ptr holds the colour offsets.
+// With group > 0 each aligned run of `group` slots of a colour (the lanes that
+// the LDS serves together) is filled greedily with constraints whose particle
+// ids at every vertex position are distinct modulo `modulus` (the LDS bank
+// group of a 16-byte particle record); group == 0 keeps ascending id order.
+void pack_colours(const int32_t *ids, int32_t k, const std::vector<int32_t> &ptr, int32_t group,
+                  int32_t modulus, std::vector<int32_t> &slot_id);
+
 }  // namespace xpbd

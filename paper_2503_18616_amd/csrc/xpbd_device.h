@@ -27,9 +27,14 @@ struct MeshDev {
     const int32_t *tet_id;       // [T]
     const float *inv_mass;       // [V]
     // round schedule of the register-multiplier kernel (see RoundDev)
-    const int4 *rounds;          // [num_rounds] (begin slot, end slot, kind, barrier)
+    const int4 *rounds;          // [num_rounds + 2] (begin slot, end slot, kind, barrier);
+                                 // entries num_rounds, num_rounds + 1 repeat rounds 0, 1
     const uint2 *edge_rec;       // [E]  (pair, rest length bits), slot order
     const uint4 *tet_rec;        // [T]  (a | b << 16, c | d << 16, rest volume bits, 0)
+    // particle placement of the register-multiplier kernel: mesh id i lives in
+    // LDS slot slot_of[i]; its records name slots
+    const uint16_t *slot_of;     // [V]
+    const uint16_t *id_of;       // [V]  inverse of slot_of
     int32_t num_rounds;
     int32_t pad2[3];
 };

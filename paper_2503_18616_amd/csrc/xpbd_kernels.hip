@@ -426,11 +426,11 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
-// Constraint record of round d for lane tid (zero when the lane has no slot).
+// Constraint record of round d for the lane's item (zero when it has none).
 __device__ __forceinline__ v4u load_record(const XPBD_GLOBAL v2u *edge_rec,
-                                           const XPBD_GLOBAL v4u *tet_rec, v4i d, int tid)
+                                           const XPBD_GLOBAL v4u *tet_rec, v4i d, int item)
 {
-    const int slot = d.x + tid;
+    const int slot = d.x + item;
     v4u r = 0u;
     if (slot < d.y) {
         if (d.z == ROUND_EDGE) {
@@ -452,6 +452,8 @@ struct RoundPipe {
     const XPBD_GLOBAL v2u *edge_rec;
     const XPBD_GLOBAL v4u *tet_rec;
     int R;
+    int tid;
+    int wave_first;  // first lane id of this wave (64 * wave)
     v4i d1;     // descriptor of the next round
     v4i d2;     // descriptor of the round after it
     v4u rec1;   // record of the next round for this lane
@@ -465,18 +467,17 @@ typedef float lambda_bank __attribute__((ext_vector_type(32)));
 // Round r of an iteration: the lane projects at most one constraint of the
 // current colour (slot begin + tid) with the record fetched during round r - 1,
 // advances the pipeline, and joins the colour's barrier.
-__device__ __forceinline__ void run_round(float4 *xw, RoundPipe &pp, int r, int tid,
-                                          lambda_bank &bank, float alpha_d, float alpha_v)
+__device__ __forceinline__ void run_round(float4 *xw, RoundPipe &pp, int r, lambda_bank &bank,
+                                          float alpha_d, float alpha_v)
 {
     const v4i d = pp.d1;
     const v4u rec = pp.rec1;
     pp.d1 = pp.d2;
-    pp.rec1 = load_record(pp.edge_rec, pp.tet_rec, pp.d1, tid);
-    int r2 = r + 2;
-    r2 = r2 >= pp.R ? r2 - pp.R : r2;
-    r2 = r2 >= pp.R ? r2 - pp.R : r2;
-    pp.d2 = pp.rounds[r2];
-    if (d.x + tid < d.y) {
+    pp.d2 = pp.rounds[(unsigned)r + 2u];   // the table repeats rounds 0 and 1 after round R - 1
+    // waves without work in a round skip it as a whole (a uniform branch)
+    if (pp.d1.x + pp.wave_first < pp.d1.y)
+        pp.rec1 = load_record(pp.edge_rec, pp.tet_rec, pp.d1, pp.tid);
+    if (d.x + pp.wave_first < d.y && d.x + pp.tid < d.y) {
         float l = bank[r & 31];
         if (d.z == ROUND_EDGE)
             edge_update(xw, (int)(rec.x & 0xffffu), (int)(rec.x >> 16), __uint_as_float(rec.y),
@@ -489,41 +490,11 @@ __device__ __forceinline__ void run_round(float4 *xw, RoundPipe &pp, int r, int 
         __syncthreads();
 }
 
-// Residual (C + alpha~ lambda) / rest of the lane's constraint of round r.
-__device__ __forceinline__ void residual_round(const float4 *xw, const RoundPipe &pp, int r, int tid,
-                                               float l, float alpha_d, float alpha_v,
-                                               float &sum, float &big)
-{
-    const v4i d = pp.rounds[r];
-    if (d.x + tid >= d.y)
-        return;
-    const v4u rec = load_record(pp.edge_rec, pp.tet_rec, d, tid);
-    float res;
-    if (d.z == ROUND_EDGE) {
-        const float4 pa = xw[rec.x & 0xffffu], pb = xw[rec.x >> 16];
-        const float dx = pa.x - pb.x, dy = pa.y - pb.y, dz = pa.z - pb.z;
-        const float rest = __uint_as_float(rec.y);
-        res = (sqrtf(dx * dx + dy * dy + dz * dz) - rest + alpha_d * l) / rest;
-    } else {
-        const float4 pa = xw[rec.x & 0xffffu], pb = xw[rec.x >> 16];
-        const float4 pc = xw[rec.y & 0xffffu], pd = xw[rec.y >> 16];
-        const float bax = pb.x - pa.x, bay = pb.y - pa.y, baz = pb.z - pa.z;
-        const float cax = pc.x - pa.x, cay = pc.y - pa.y, caz = pc.z - pa.z;
-        const float dax = pd.x - pa.x, day = pd.y - pa.y, daz = pd.z - pa.z;
-        const float vol = (bax * (cay * daz - caz * day) + bay * (caz * dax - cax * daz) +
-                           baz * (cax * day - cay * dax)) * kSixth;
-        const float rest = __uint_as_float(rec.z);
-        res = (vol - rest + alpha_v * l) / rest;
-    }
-    sum += res * res;
-    big = fmaxf(big, fabsf(res));
-}
-
 __device__ __forceinline__ void store_lambda_round(float *out, const MeshDev &md,
-                                                   const RoundPipe &pp, int r, int tid, float l)
+                                                   const RoundPipe &pp, int r, float l)
 {
     const v4i d = pp.rounds[r];
-    const int slot = d.x + tid;
+    const int slot = d.x + pp.tid;
     if (slot < d.y) {
         if (d.z == ROUND_EDGE)
             out[md.edge_id[slot]] = l;
@@ -565,12 +536,14 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
     const int NP = A.total_particles;
     const int off = ed.particle_offset;
 
+    // particle i (mesh order) lives in LDS slot slot_of[i]; all LDS arrays are in slot order
     for (int i = tid; i < V; i += B) {
-        xw[i] = make_float4(A.pos[off + i], A.pos[NP + off + i], A.pos[2 * NP + off + i],
-                            md.inv_mass[i]);
-        vel[i] = A.vel[off + i];
-        vel[V + i] = A.vel[NP + off + i];
-        vel[2 * V + i] = A.vel[2 * NP + off + i];
+        const int sl = md.slot_of[i];
+        xw[sl] = make_float4(A.pos[off + i], A.pos[NP + off + i], A.pos[2 * NP + off + i],
+                             md.inv_mass[i]);
+        vel[sl] = A.vel[off + i];
+        vel[V + sl] = A.vel[NP + off + i];
+        vel[2 * V + sl] = A.vel[2 * NP + off + i];
     }
     lambda_bank bank0 = 0.0f, bank1 = 0.0f;
     __syncthreads();
@@ -581,11 +554,13 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
     pp.edge_rec = (const XPBD_GLOBAL v2u *)(uintptr_t)md.edge_rec;
     pp.tet_rec = (const XPBD_GLOBAL v4u *)(uintptr_t)md.tet_rec;
     pp.R = R;
+    pp.tid = tid;
+    pp.wave_first = __builtin_amdgcn_readfirstlane(64 * wave);
     pp.d1 = pp.rounds[0];
-    pp.d2 = pp.rounds[R > 1 ? 1 : 0];
+    pp.d2 = pp.rounds[1];
     pp.rec1 = load_record(pp.edge_rec, pp.tet_rec, pp.d1, tid);
 
-    uint32_t cand = 0u;  // bit 16 t + k: particle k * B + tid is a candidate of tool t
+    uint32_t cand = 0u;  // bit 16 t + k: the particle in slot k * B + tid is a candidate of tool t
     float3 tool0 = make_float3(0.f, 0.f, 0.f), tool1 = tool0;   // sphere centres this step
     const int last_step = A.num_steps - 1;
     for (int step = 0; step < A.num_steps; ++step) {
@@ -630,10 +605,10 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
 
             for (int it = 0; it < A.iterations; ++it) {
                 for (int r = 0; r < R0; ++r)
-                    run_round(xw, pp, r, tid, bank0, alpha_d, alpha_v);
+                    run_round(xw, pp, r, bank0, alpha_d, alpha_v);
                 if constexpr (NB > 1)
                     for (int r = 32; r < R; ++r)
-                        run_round(xw, pp, r, tid, bank1, alpha_d, alpha_v);
+                        run_round(xw, pp, r, bank1, alpha_d, alpha_v);
                 if (any_contact) {
                     for (int t = 0; t < tools; ++t) {
                         const float3 ct = t == 0 ? tool0 : tool1;
@@ -660,8 +635,9 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
     // write back (structure of arrays, coalesced)
     int bad = 0;
     for (int i = tid; i < V; i += B) {
-        const float4 p = xw[i];
-        const float vx = vel[i], vy = vel[V + i], vz = vel[2 * V + i];
+        const int sl = md.slot_of[i];
+        const float4 p = xw[sl];
+        const float vx = vel[sl], vy = vel[V + sl], vz = vel[2 * V + sl];
         A.pos[off + i] = p.x;
         A.pos[NP + off + i] = p.y;
         A.pos[2 * NP + off + i] = p.z;
@@ -675,13 +651,24 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
     if (tid == 0 && bad)
         A.nonfinite[env] = 1;
 
-    // contact candidates of the last step, ascending particle ids
+    // contact candidates of the last step as ascending mesh ids: flag them by mesh
+    // id in a byte map (the start-of-substep positions are no longer needed), then
+    // compact in mesh order
+    uint8_t *flag_of = reinterpret_cast<uint8_t *>(prev);
     const int kmax = (V + B - 1) / B;
     for (int t = 0; t < tools; ++t) {
+        for (int i = tid; i < V; i += B)
+            flag_of[i] = 0;
+        __syncthreads();
+        for (int k = 0, sl = tid; sl < V; ++k, sl += B)
+            if ((cand >> (16 * t + k)) & 1u)
+                flag_of[md.id_of[sl]] = 1;
+        __syncthreads();
         int32_t *list = A.contacts + (size_t)t * NP + off;
         int base = 0;
         for (int k = 0; k < kmax; ++k) {
-            const bool flag = (cand >> (16 * t + k)) & 1u;
+            const int i = k * B + tid;
+            const bool flag = i < V && flag_of[i];
             const uint64_t mask = __ballot(flag);
             if (lane == 0)
                 scratch[wave] = (uint32_t)__popcll(mask);
@@ -693,7 +680,7 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
                 total += n;
             }
             if (flag)
-                list[base + before + __popcll(mask & __lanemask_lt())] = k * B + tid;
+                list[base + before + __popcll(mask & __lanemask_lt())] = i;
             base += total;
             __syncthreads();
         }
@@ -705,15 +692,16 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
     if (A.lambda_out) {
         float *out = A.lambda_out + ed.lambda_offset;
         for (int r = 0; r < R0; ++r)
-            store_lambda_round(out, md, pp, r, tid, bank0[r & 31]);
+            store_lambda_round(out, md, pp, r, bank0[r & 31]);
         if constexpr (NB > 1)
             for (int r = 32; r < R; ++r)
-                store_lambda_round(out, md, pp, r, tid, bank1[r & 31]);
+                store_lambda_round(out, md, pp, r, bank1[r & 31]);
     }
 }
 
 // Constraint residual (C + alpha~ lambda) / rest of every kept constraint of an
-// environment, from its written-back positions and stored multipliers
+// environment, from its written-back positions (mesh order; the records name
+// LDS slots, mapped back through id_of) and stored multipliers
 // (constraint order), reduced to (RMS, max |r|).  One workgroup per environment.
 __global__ void __launch_bounds__(256) residual_kernel(StepArgs A)
 {
@@ -732,7 +720,7 @@ __global__ void __launch_bounds__(256) residual_kernel(StepArgs A)
     float sum = 0.0f, big = 0.0f;
     for (int j = tid; j < E; j += blockDim.x) {
         const uint2 e = md.edge_rec[j];
-        const int a = (int)(e.x & 0xffffu), b = (int)(e.x >> 16);
+        const int a = md.id_of[e.x & 0xffffu], b = md.id_of[e.x >> 16];
         const float dx = px[a] - px[b], dy = py[a] - py[b], dz = pz[a] - pz[b];
         const float rest = __uint_as_float(e.y);
         const float r = (sqrtf(dx * dx + dy * dy + dz * dz) - rest + alpha_d * lam[md.edge_id[j]]) / rest;
@@ -741,8 +729,8 @@ __global__ void __launch_bounds__(256) residual_kernel(StepArgs A)
     }
     for (int j = tid; j < T; j += blockDim.x) {
         const uint4 q = md.tet_rec[j];
-        const int a = (int)(q.x & 0xffffu), b = (int)(q.x >> 16);
-        const int c = (int)(q.y & 0xffffu), d = (int)(q.y >> 16);
+        const int a = md.id_of[q.x & 0xffffu], b = md.id_of[q.x >> 16];
+        const int c = md.id_of[q.y & 0xffffu], d = md.id_of[q.y >> 16];
         const float bax = px[b] - px[a], bay = py[b] - py[a], baz = pz[b] - pz[a];
         const float cax = px[c] - px[a], cay = py[c] - py[a], caz = pz[c] - pz[a];
         const float dax = px[d] - px[a], day = py[d] - py[a], daz = pz[d] - pz[a];

@@ -8,6 +8,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <numeric>
+#include <random>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -151,6 +153,8 @@ xpbd_status validate_params(const xpbd_params *p)
         return fail(XPBD_E_ARG, "block_size must be 0 or a multiple of 64 in [64, 1024]");
     if (p->solver_variant < XPBD_VARIANT_AUTO || p->solver_variant > XPBD_VARIANT_LDS)
         return fail(XPBD_E_ARG, "unknown solver_variant %d", p->solver_variant);
+    if (p->colour_packing < XPBD_PACKING_AUTO || p->colour_packing > XPBD_PACKING_SCATTERED_BANKS16)
+        return fail(XPBD_E_ARG, "unknown colour_packing %d", p->colour_packing);
     return XPBD_OK;
 }
 
@@ -354,7 +358,9 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     // the requested one) whose round schedule fits the register banks of every mesh
     bool use_registers = false;
     int reg_block = 0, reg_rounds = 0;
-    if (params->solver_variant != XPBD_VARIANT_LDS) {
+    const bool pow2_block = params->block_size == 0 ||
+                            (params->block_size & (params->block_size - 1)) == 0;
+    if (params->solver_variant != XPBD_VARIANT_LDS && pow2_block) {
         const int tries[3] = {256, 512, 1024};
         const int n_tries = params->block_size ? 1 : 3;
         for (int k = 0; k < n_tries && !use_registers; ++k) {
@@ -370,11 +376,11 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
                 reg_rounds = worst;
             }
         }
-        if (!use_registers && params->solver_variant == XPBD_VARIANT_REGISTERS)
-            return fail(XPBD_E_CAPACITY, "the round schedule needs more than %d rounds per lane "
-                        "or more LDS than the device has; use the LDS variant",
-                        xpbd::kMaxRounds);
     }
+    if (!use_registers && params->solver_variant == XPBD_VARIANT_REGISTERS)
+        return fail(XPBD_E_CAPACITY, "the register variant needs a power-of-two block, at most %d "
+                    "rounds per lane and LDS for the particles; use the LDS variant",
+                    xpbd::kMaxRounds);
     if (use_registers) {
         block = reg_block;
         ppt = 1;
@@ -426,6 +432,32 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         std::vector<int32_t> eslot, eptr, tslot, tptr;
         build_schedule(pm.edge_colour, pm.num_edge_colours, eslot, eptr);
         build_schedule(pm.tet_colour, pm.num_tet_colours, tslot, tptr);
+        int packing = params->colour_packing;
+        if (packing == XPBD_PACKING_AUTO)
+            packing = use_registers ? XPBD_PACKING_SCATTERED_BANKS16 : XPBD_PACKING_BANKS16;
+        if (packing == XPBD_PACKING_SCATTERED_BANKS16 && !use_registers)
+            packing = XPBD_PACKING_BANKS16;
+        // LDS placement of the particles (register variant): identity, or a fixed
+        // pseudo-random order that spreads every colour's particles over the banks
+        std::vector<int32_t> slot_of((size_t)pm.num_vertices);
+        std::iota(slot_of.begin(), slot_of.end(), 0);
+        if (packing == XPBD_PACKING_SCATTERED_BANKS16) {
+            std::mt19937 gen(0x5eedu + (uint32_t)m);
+            std::shuffle(slot_of.begin(), slot_of.end(), gen);
+        }
+        std::vector<uint16_t> slot16((size_t)pm.num_vertices), id16((size_t)pm.num_vertices);
+        for (int32_t i = 0; i < pm.num_vertices; ++i) {
+            slot16[(size_t)i] = (uint16_t)slot_of[(size_t)i];
+            id16[(size_t)slot_of[(size_t)i]] = (uint16_t)i;
+        }
+        std::vector<int32_t> edges_in_lds(pm.edges.size()), tets_in_lds(pm.tets.size());
+        for (size_t q = 0; q < pm.edges.size(); ++q)
+            edges_in_lds[q] = slot_of[(size_t)pm.edges[q]];
+        for (size_t q = 0; q < pm.tets.size(); ++q)
+            tets_in_lds[q] = slot_of[(size_t)pm.tets[q]];
+        const int group = packing == XPBD_PACKING_BANKS8 ? 8 : packing == XPBD_PACKING_ID_ORDER ? 0 : 16;
+        xpbd::pack_colours(edges_in_lds.data(), 2, eptr, group, group, eslot);
+        xpbd::pack_colours(tets_in_lds.data(), 4, tptr, group, group, tslot);
         std::vector<uint32_t> pair((size_t)E);
         std::vector<float> erest((size_t)E), trest((size_t)T);
         std::vector<uint2> quad((size_t)T);
@@ -442,25 +474,34 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
                                          (uint32_t)q[2] | ((uint32_t)q[3] << 16));
             trest[(size_t)j] = (float)pm.rest_volume[(size_t)t];
         }
+        // records of the register variant name LDS slots
         std::vector<uint2> erec((size_t)E);
         std::vector<uint4> trec((size_t)T);
         for (int32_t j = 0; j < E; ++j) {
+            const int32_t e = eslot[(size_t)j];
             uint32_t bits;
             std::memcpy(&bits, &erest[(size_t)j], 4);
-            erec[(size_t)j] = make_uint2(pair[(size_t)j], bits);
+            erec[(size_t)j] = make_uint2((uint32_t)edges_in_lds[2 * (size_t)e] |
+                                             ((uint32_t)edges_in_lds[2 * (size_t)e + 1] << 16),
+                                         bits);
         }
         for (int32_t j = 0; j < T; ++j) {
+            const int32_t *q = &tets_in_lds[4 * (size_t)tslot[(size_t)j]];
             uint32_t bits;
             std::memcpy(&bits, &trest[(size_t)j], 4);
-            trec[(size_t)j] = make_uint4(quad[(size_t)j].x, quad[(size_t)j].y, bits, 0u);
+            trec[(size_t)j] = make_uint4((uint32_t)q[0] | ((uint32_t)q[1] << 16),
+                                         (uint32_t)q[2] | ((uint32_t)q[3] << 16), bits, 0u);
         }
         std::vector<int4> rounds;
         build_rounds(eptr, tptr, block, rounds);
         if (rounds.empty())
             rounds.push_back(make_int4(0, 0, xpbd::ROUND_EDGE, 0));
+        const int32_t num_rounds = (int32_t)rounds.size();
+        rounds.push_back(rounds[0]);                          // the kernel prefetches two
+        rounds.push_back(rounds[num_rounds > 1 ? 1 : 0]);     // rounds ahead without wrapping
         MeshDev &d = mdev[(size_t)m];
         std::memset(&d, 0, sizeof d);
-        d.num_rounds = use_registers ? (int32_t)rounds.size() : 0;
+        d.num_rounds = use_registers ? num_rounds : 0;
         d.num_vertices = pm.num_vertices;
         d.num_edges = E;
         d.num_tets = T;
@@ -480,12 +521,16 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         uint2 *p_erec;
         uint4 *p_trec;
         int4 *p_rounds;
+        uint16_t *p_slot, *p_id;
         if ((st = b->upload(&p_erec, erec)) || (st = b->upload(&p_trec, trec)) ||
-            (st = b->upload(&p_rounds, rounds)))
+            (st = b->upload(&p_rounds, rounds)) || (st = b->upload(&p_slot, slot16)) ||
+            (st = b->upload(&p_id, id16)))
             return cleanup(st);
         d.edge_rec = p_erec;
         d.tet_rec = p_trec;
         d.rounds = p_rounds;
+        d.slot_of = p_slot;
+        d.id_of = p_id;
         d.edge_pair = p_pair;
         d.edge_rest = p_erest;
         d.tet_quad = p_quad;

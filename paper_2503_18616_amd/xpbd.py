@@ -49,6 +49,12 @@ VARIANT_AUTO = 0
 VARIANT_REGISTERS = 1
 VARIANT_LDS = 2
 
+PACKING_AUTO = 0
+PACKING_ID_ORDER = 1
+PACKING_BANKS8 = 2
+PACKING_BANKS16 = 3
+PACKING_SCATTERED_BANKS16 = 4
+
 # field -> numpy dtype of its elements
 FIELD_DTYPES = {FIELD_POS: np.float32, FIELD_VEL: np.float32, FIELD_LAMBDA: np.float32,
                 FIELD_CONTACTS: np.int32, FIELD_CONTACT_COUNTS: np.int32,
@@ -70,7 +76,7 @@ class XpbdParams(ctypes.Structure):
                 ("iterations", ctypes.c_int32), ("gravity", ctypes.c_float * 3),
                 ("num_tools", ctypes.c_int32), ("tool_radius", ctypes.c_float * 2),
                 ("flags", ctypes.c_uint32), ("block_size", ctypes.c_int32),
-                ("solver_variant", ctypes.c_int32)]
+                ("solver_variant", ctypes.c_int32), ("colour_packing", ctypes.c_int32)]
 
 
 _lib.xpbd_create_batch.restype = ctypes.c_int
@@ -141,7 +147,7 @@ def _mesh_struct(rest_pos, inv_mass, tets, keep):
 
 def make_params(dt, substeps, iterations, gravity=(0.0, 0.0, -9.81), num_tools=1,
                 tool_radius=(0.005, 0.005), flags=0, block_size=0,
-                solver_variant=VARIANT_AUTO) -> XpbdParams:
+                solver_variant=VARIANT_AUTO, colour_packing=PACKING_AUTO) -> XpbdParams:
     p = XpbdParams()
     p.dt = dt
     p.substeps = substeps
@@ -153,6 +159,7 @@ def make_params(dt, substeps, iterations, gravity=(0.0, 0.0, -9.81), num_tools=1
     p.flags = flags
     p.block_size = block_size
     p.solver_variant = solver_variant
+    p.colour_packing = colour_packing
     return p
 
 

@@ -378,3 +378,24 @@ def test_register_variant_refuses_oversized_schedules(xp):
     with pytest.raises(xp.XpbdError) as e:
         make_batch(xp, wl, block_size=64, variant=1)
     assert e.value.status == xp.XPBD_E_CAPACITY
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
+@pytest.mark.parametrize("packing", [1, 2, 3, 4])
+def test_colour_packing_does_not_change_results(xp, packing, variant):
+    """The order of constraints inside a colour is free: bitwise equal results."""
+    wl = W.batch_workload(8, seed=7, num_steps=30)
+    tools = W.tool_path(30, 8, 7, start_depth=6e-3)
+    p_ref = K.lib_params(xp, wl, xp.F_LAMBDA)
+    p_ref.solver_variant = variant
+    p_ref.colour_packing = 1
+    p = K.lib_params(xp, wl, xp.F_LAMBDA)
+    p.solver_variant = variant
+    p.colour_packing = packing
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p_ref) as a, \
+            xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b:
+        a.step(30, tools)
+        b.step(30, tools)
+        assert np.array_equal(a.positions(), b.positions())
+        assert np.array_equal(a.velocities(), b.velocities())
+        assert np.array_equal(a.read(xp.FIELD_LAMBDA), b.read(xp.FIELD_LAMBDA))
