@@ -60,7 +60,7 @@ enum {
                                       constraint of every mesh, mesh order, edges then tetrahedra */
     XPBD_FIELD_RESIDUAL = 6,       /* float [N][2] (RMS, max |r|) of the constraint residual
                                       (C + alpha~ lambda)/rest, at the last substep of the last
-                                      xpbd_step call.  Needs XPBD_F_RESIDUAL. */
+                                      xpbd_step call made with XPBD_F_RESIDUAL. */
     XPBD_FIELD_ENV_OFFSETS = 7,    /* int32 [N+1] particle offsets of the environments */
     XPBD_FIELD_NONFINITE = 8,      /* int32 [N] 1 where the env's state went non-finite */
     XPBD_FIELD_COUNT = 9
@@ -170,6 +170,15 @@ xpbd_status xpbd_read_state(xpbd_batch *b, int32_t field, void *dst, size_t dst_
  * between xpbd_step calls is exactly (positions, velocities).
  */
 xpbd_status xpbd_write_state(xpbd_batch *b, int32_t field, const void *src, size_t src_bytes);
+
+/*
+ * Replace the batch's flags (XPBD_F_*) for later xpbd_step calls, e.g. to
+ * compute the residual only on the last step of an episode.  Setting
+ * XPBD_F_LAMBDA or XPBD_F_RESIDUAL on a batch created without them allocates
+ * the multiplier buffer (synchronously, on the batch's stream).  Returns
+ * XPBD_E_ARG for unknown bits.
+ */
+xpbd_status xpbd_set_flags(xpbd_batch *b, uint32_t flags);
 
 /* Byte size of a field of this batch. */
 xpbd_status xpbd_field_bytes(const xpbd_batch *b, int32_t field, size_t *bytes);

@@ -92,7 +92,7 @@ struct xpbd_batch {
     size_t staging_bytes = 0;
     float *tool_staging = nullptr;
     size_t tool_staging_bytes = 0;
-    bool stepped_with_residual = false;
+    bool residual_valid = false;   // a step has computed the residual
 
     ~xpbd_batch()
     {
@@ -639,7 +639,9 @@ xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
     a.tool_pos = tools_dev;
     a.pos = b->pos;
     a.vel = b->vel;
-    a.lambda_out = b->lambda;
+    const bool resid_now = (b->params.flags & XPBD_F_RESIDUAL) != 0;
+    a.lambda_out = ((b->params.flags & XPBD_F_LAMBDA) || (b->register_variant && resid_now))
+                       ? b->lambda : nullptr;
     a.contacts = b->contacts;
     a.contact_counts = b->contact_counts;
     a.residual = b->residual;
@@ -663,11 +665,32 @@ xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
         a.tool_reach2[t] = reach * reach;
     }
     const bool resid = (b->params.flags & XPBD_F_RESIDUAL) != 0;
+    b->residual_valid = b->residual_valid || resid;
     if (b->register_variant)
         HIP_TRY(xpbd::launch_step_reg(a, b->block, b->lambda_banks, b->lds_bytes, resid, b->stream));
     else
         HIP_TRY(xpbd::launch_step(a, b->block, b->particles_per_thread, b->stage_topology,
                                   b->lds_bytes, resid, b->stream));
+    return XPBD_OK;
+}
+
+xpbd_status xpbd_set_flags(xpbd_batch *b, uint32_t flags)
+{
+    g_error.clear();
+    if (!b)
+        return fail(XPBD_E_ARG, "batch is NULL");
+    if (flags & ~(XPBD_F_RESIDUAL | XPBD_F_LAMBDA))
+        return fail(XPBD_E_ARG, "unknown flag bits 0x%x", flags);
+    const bool need_lambda = (flags & XPBD_F_LAMBDA) ||
+                             (b->register_variant && (flags & XPBD_F_RESIDUAL));
+    if (need_lambda && !b->lambda) {
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        std::vector<float> zeros((size_t)b->total_lambda, 0.0f);
+        xpbd_status s = b->upload(&b->lambda, zeros);
+        if (s != XPBD_OK)
+            return s;
+    }
+    b->params.flags = flags;
     return XPBD_OK;
 }
 
@@ -692,8 +715,8 @@ xpbd_status xpbd_read_state(xpbd_batch *b, int32_t field, void *dst, size_t dst_
         return fail(XPBD_E_STATE, "field %d needs %zu bytes, got %zu", field, need, dst_bytes);
     if (field == XPBD_FIELD_LAMBDA && !(b->params.flags & XPBD_F_LAMBDA))
         return fail(XPBD_E_STATE, "multipliers are stored only with XPBD_F_LAMBDA");
-    if (field == XPBD_FIELD_RESIDUAL && !(b->params.flags & XPBD_F_RESIDUAL))
-        return fail(XPBD_E_STATE, "the residual is computed only with XPBD_F_RESIDUAL");
+    if (field == XPBD_FIELD_RESIDUAL && !b->residual_valid)
+        return fail(XPBD_E_STATE, "no xpbd_step with XPBD_F_RESIDUAL has run on this batch");
     switch (field) {
     case XPBD_FIELD_COLOURS:
         s = copy_host_out(b, dst, b->colours.data(), need);

@@ -62,7 +62,8 @@ FIELD_DTYPES = {FIELD_POS: np.float32, FIELD_VEL: np.float32, FIELD_LAMBDA: np.f
                 FIELD_ENV_OFFSETS: np.int32, FIELD_NONFINITE: np.int32}
 
 EXPORTED = ["xpbd_create_batch", "xpbd_step", "xpbd_read_state", "xpbd_write_state",
-            "xpbd_field_bytes", "xpbd_destroy_batch", "xpbd_last_error", "xpbd_prepare_mesh"]
+            "xpbd_set_flags", "xpbd_field_bytes", "xpbd_destroy_batch", "xpbd_last_error",
+            "xpbd_prepare_mesh"]
 
 
 class XpbdMesh(ctypes.Structure):
@@ -89,6 +90,8 @@ _lib.xpbd_read_state.restype = ctypes.c_int
 _lib.xpbd_read_state.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]
 _lib.xpbd_write_state.restype = ctypes.c_int
 _lib.xpbd_write_state.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]
+_lib.xpbd_set_flags.restype = ctypes.c_int
+_lib.xpbd_set_flags.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
 _lib.xpbd_field_bytes.restype = ctypes.c_int
 _lib.xpbd_field_bytes.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
 _lib.xpbd_destroy_batch.restype = None
@@ -234,6 +237,10 @@ def xpbd_step(batch, num_steps, tool_pos):
     _check(_lib.xpbd_step(batch, int(num_steps), _ptr(tool_pos)))
 
 
+def xpbd_set_flags(batch, flags):
+    _check(_lib.xpbd_set_flags(batch, int(flags)))
+
+
 def xpbd_field_bytes(batch, field) -> int:
     n = ctypes.c_size_t(0)
     _check(_lib.xpbd_field_bytes(batch, int(field), ctypes.byref(n)))
@@ -288,6 +295,9 @@ class Batch:
 
     def write(self, field, src):
         xpbd_write_state(self.handle, field, src)
+
+    def set_flags(self, flags):
+        xpbd_set_flags(self.handle, flags)
 
     def env_slice(self, e):
         return slice(int(self.env_offsets[e]), int(self.env_offsets[e + 1]))

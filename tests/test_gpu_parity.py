@@ -399,3 +399,26 @@ def test_colour_packing_does_not_change_results(xp, packing, variant):
         assert np.array_equal(a.positions(), b.positions())
         assert np.array_equal(a.velocities(), b.velocities())
         assert np.array_equal(a.read(xp.FIELD_LAMBDA), b.read(xp.FIELD_LAMBDA))
+
+
+def test_flags_can_change_between_steps(xp):
+    """Residual and multipliers requested on a later step only."""
+    wl = W.batch_workload(4, seed=8, num_steps=6)
+    tools = wl.tools(6)
+    with make_batch(xp, wl, flags=xp.F_RESIDUAL | xp.F_LAMBDA) as ref, make_batch(xp, wl) as b:
+        ref.step(6, tools)
+        with pytest.raises(xp.XpbdError) as e:
+            b.read(xp.FIELD_RESIDUAL)
+        assert e.value.status == xp.XPBD_E_STATE
+        b.step(5, tools[:5])
+        b.set_flags(xp.F_RESIDUAL | xp.F_LAMBDA)
+        b.step(1, tools[5:])
+        assert np.array_equal(b.positions(), ref.positions())
+        np.testing.assert_array_equal(b.read(xp.FIELD_RESIDUAL), ref.read(xp.FIELD_RESIDUAL))
+        np.testing.assert_array_equal(b.read(xp.FIELD_LAMBDA), ref.read(xp.FIELD_LAMBDA))
+        b.set_flags(0)
+        b.step(1, tools[5:])
+        with pytest.raises(xp.XpbdError):
+            b.read(xp.FIELD_LAMBDA)
+        with pytest.raises(xp.XpbdError):
+            b.set_flags(0x40)
