@@ -26,24 +26,33 @@ struct MeshDev {
     const int32_t *edge_id;      // [E]  constraint id of each schedule slot
     const int32_t *tet_id;       // [T]
     const float *inv_mass;       // [V]
-    // round schedule of the register-multiplier kernel (see RoundDev)
-    const int4 *rounds;          // [num_rounds + 2] (begin slot, end slot, kind, barrier);
-                                 // entries num_rounds, num_rounds + 1 repeat rounds 0, 1
+    // constraint records in slot order (pairs and quads name LDS slots)
     const uint2 *edge_rec;       // [E]  (pair, rest length bits), slot order
     const uint4 *tet_rec;        // [T]  (a | b << 16, c | d << 16, rest volume bits, 0)
     // particle placement of the register-multiplier kernel: mesh id i lives in
     // LDS slot slot_of[i]; its records name slots
     const uint16_t *slot_of;     // [V]
     const uint16_t *id_of;       // [V]  inverse of slot_of
-    int32_t num_rounds;
-    int32_t pad2[3];
+    // round-major records of the register-multiplier kernel: the record of
+    // lane l in round r sits at [r][l]; edge (pair, rest length bits, 0),
+    // tet (ab, cd, rest volume bits); lanes without a constraint hold
+    // kInvalidRecord in the first word
+    const uint32_t *round_rec;   // [padded rounds][block][3]
+    const int32_t *rr_id;        // [padded rounds][block] constraint id (tets: E + id), -1
+    uint64_t wave_active[16];    // bit r: wave w has a constraint in round r
+    uint64_t tet_mask;           // bit r: round r projects tetrahedra
+    uint64_t barrier_mask;       // bit r: a workgroup barrier follows round r
+    int32_t num_rounds;          // padded to an even count (<= kMaxRounds)
+    int32_t num_edge_rounds;
+    int32_t pad2[2];
 };
 
-// One round of the register-multiplier kernel: lane `tid` of the workgroup
-// projects slot begin + tid of the given kind if it is below end (the end of
-// the colour); a workgroup barrier follows when barrier != 0 (last round of a
-// colour).  kind 0 = edge, 1 = tetrahedron.  Each lane keeps the multiplier of
-// its constraint of round r in register r.
+constexpr uint32_t kInvalidRecord = 0xffffffffu;
+
+// Rounds of the register-multiplier kernel: a colour is cut into rounds of at
+// most blockDim constraints (lane l takes the l-th); a workgroup barrier
+// follows the last round of a colour.  Each lane keeps the multiplier of its
+// constraint of round r in register r.
 enum { ROUND_EDGE = 0, ROUND_TET = 1 };
 constexpr int kMaxRounds = 64;
 

@@ -414,93 +414,77 @@ __global__ void __launch_bounds__(1024) xpbd_step_lds_kernel(StepArgs A)
     }
 }
 
-// Pointers into global memory seen through the global (1) or constant (4)
-// address space, so that loads become global_load (vector memory counter
-// only) or s_load (uniform, scalar cache) instead of flat loads.
+// Pointers into global memory seen through the global address space, so that
+// loads become global_load (vector memory counter only) instead of flat loads.
 #define XPBD_GLOBAL __attribute__((address_space(1)))
-#define XPBD_CONSTANT __attribute__((address_space(4)))
 
 // Native vector types (the HIP vector classes cannot be loaded through an
 // address-space-qualified pointer).
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-
-// Constraint record of round d for the lane's item (zero when it has none).
-__device__ __forceinline__ v4u load_record(const XPBD_GLOBAL v2u *edge_rec,
-                                           const XPBD_GLOBAL v4u *tet_rec, v4i d, int item)
-{
-    const int slot = d.x + item;
-    v4u r = 0u;
-    if (slot < d.y) {
-        if (d.z == ROUND_EDGE) {
-            const v2u e = edge_rec[slot];
-            r.x = e.x;
-            r.y = e.y;
-        } else {
-            r = tet_rec[slot];
-        }
-    }
-    return r;
-}
-
-// Software pipeline of the round loop: the descriptor of round r + 2 is being
-// fetched (scalar load) and the record of round r + 1 (vector load) while
-// round r is projected.
-struct RoundPipe {
-    const XPBD_CONSTANT v4i *rounds;
-    const XPBD_GLOBAL v2u *edge_rec;
-    const XPBD_GLOBAL v4u *tet_rec;
-    int R;
-    int tid;
-    int wave_first;  // first lane id of this wave (64 * wave)
-    v4i d1;     // descriptor of the next round
-    v4i d2;     // descriptor of the round after it
-    v4u rec1;   // record of the next round for this lane
-};
 
 // Multipliers of a lane's constraints: one register per round, in banks of 32
 // registers held as a vector and indexed with the (workgroup-uniform) round
 // counter, which the compiler lowers to relative register addressing.
 typedef float lambda_bank __attribute__((ext_vector_type(32)));
 
-// Round r of an iteration: the lane projects at most one constraint of the
-// current colour (slot begin + tid) with the record fetched during round r - 1,
-// advances the pipeline, and joins the colour's barrier.
-__device__ __forceinline__ void run_round(float4 *xw, RoundPipe &pp, int r, lambda_bank &bank,
-                                          float alpha_d, float alpha_v)
+// Round-major record table of one mesh seen through the global address space:
+// the record of lane l in round r is rr[r][l], three words for both kinds
+// (edge: pair, rest length bits, 0; tet: ab, cd, rest volume bits).
+struct Record {
+    uint32_t w0, w1, w2;
+};
+
+struct RoundTables {
+    const XPBD_GLOBAL Record *rr;
+    int R;                            // rounds (even)
+    int B;
+    int tid;
+};
+
+// Every wave fetches exactly one record per round (a wave without a
+// constraint in round r fetches its lane's entry of round 0, which stays
+// cache-resident), so the loads retire in order and each round waits only
+// for the fetch issued two rounds before it.  The address depends only on
+// (round, lane), so the fetch can run rounds ahead.
+__device__ __forceinline__ Record fetch_record(const RoundTables &t, int r, bool active)
 {
-    const v4i d = pp.d1;
-    const v4u rec = pp.rec1;
-    pp.d1 = pp.d2;
-    pp.d2 = pp.rounds[(unsigned)r + 2u];   // the table repeats rounds 0 and 1 after round R - 1
-    // waves without work in a round skip it as a whole (a uniform branch)
-    if (pp.d1.x + pp.wave_first < pp.d1.y)
-        pp.rec1 = load_record(pp.edge_rec, pp.tet_rec, pp.d1, pp.tid);
-    if (d.x + pp.wave_first < d.y && d.x + pp.tid < d.y) {
-        float l = bank[r & 31];
-        if (d.z == ROUND_EDGE)
-            edge_update(xw, (int)(rec.x & 0xffffu), (int)(rec.x >> 16), __uint_as_float(rec.y),
-                        alpha_d, l);
-        else
-            tet_update(xw, rec.x, rec.y, __uint_as_float(rec.z), alpha_v, l);
-        bank[r & 31] = l;
-    }
-    if (d.w)
-        __syncthreads();
+    const XPBD_GLOBAL Record *p = t.rr + (active ? r : 0) * t.B + t.tid;
+    Record rec;
+    rec.w0 = p->w0;
+    rec.w1 = p->w1;
+    rec.w2 = p->w2;
+    return rec;
 }
 
-__device__ __forceinline__ void store_lambda_round(float *out, const MeshDev &md,
-                                                   const RoundPipe &pp, int r, float l)
+// Round r of an iteration.  `slot` holds this lane's record of round r
+// (fetched two rounds earlier) and receives the record of round r + 2.  Waves
+// without a constraint in a round skip it (uniform branch on the wave's
+// activity mask); a barrier closes every colour.
+__device__ __forceinline__ void run_round(float4 *xw, const RoundTables &t, int r, Record &slot,
+                                          uint64_t active, uint64_t tets, uint64_t barriers,
+                                          lambda_bank &bank, float alpha_d, float alpha_v)
 {
-    const v4i d = pp.rounds[r];
-    const int slot = d.x + pp.tid;
-    if (slot < d.y) {
-        if (d.z == ROUND_EDGE)
-            out[md.edge_id[slot]] = l;
+    // copy the record out of the prefetch slot first, so that the slot's
+    // registers are free for the next fetch and the loop carries it in place
+    // (otherwise the compiler copies the in-flight slot at the loop edge and
+    // must wait for the fetch there)
+    uint32_t w0, w1, w2;
+    asm volatile("v_mov_b32 %0, %3\n\tv_mov_b32 %1, %4\n\tv_mov_b32 %2, %5"
+                 : "=v"(w0), "=v"(w1), "=v"(w2)
+                 : "v"(slot.w0), "v"(slot.w1), "v"(slot.w2));
+    int r2 = r + 2;
+    r2 = r2 >= t.R ? r2 - t.R : r2;
+    slot = fetch_record(t, r2, (active >> r2) & 1u);
+    if (((active >> r) & 1u) && w0 != kInvalidRecord) {
+        float l = bank[r & 31];
+        if ((tets >> r) & 1u)
+            tet_update(xw, w0, w1, __uint_as_float(w2), alpha_v, l);
         else
-            out[md.num_edges + md.tet_id[slot]] = l;
+            edge_update(xw, (int)(w0 & 0xffffu), (int)(w0 >> 16), __uint_as_float(w1), alpha_d, l);
+        bank[r & 31] = l;
     }
+    if ((barriers >> r) & 1u)
+        __syncthreads();
 }
 
 // One workgroup per environment.  LDS: particles as float4 (x, y, z, w), then
@@ -548,21 +532,19 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
     lambda_bank bank0 = 0.0f, bank1 = 0.0f;
     __syncthreads();
 
-    // prime the round pipeline: descriptors of rounds 0 and 1, record of round 0
-    RoundPipe pp;
-    pp.rounds = (const XPBD_CONSTANT v4i *)(uintptr_t)md.rounds;
-    pp.edge_rec = (const XPBD_GLOBAL v2u *)(uintptr_t)md.edge_rec;
-    pp.tet_rec = (const XPBD_GLOBAL v4u *)(uintptr_t)md.tet_rec;
-    pp.R = R;
-    pp.tid = tid;
-    pp.wave_first = __builtin_amdgcn_readfirstlane(64 * wave);
-    pp.d1 = pp.rounds[0];
-    pp.d2 = pp.rounds[1];
-    pp.rec1 = load_record(pp.edge_rec, pp.tet_rec, pp.d1, tid);
+    // round tables and this wave's masks (uniform); prime the two-round prefetch
+    RoundTables tab;
+    tab.rr = (const XPBD_GLOBAL Record *)(uintptr_t)md.round_rec;
+    tab.R = R;
+    tab.B = B;
+    tab.tid = tid;
+    const uint64_t active = A.meshes[ed.mesh].wave_active[__builtin_amdgcn_readfirstlane(wave)];
+    const uint64_t tets = md.tet_mask, barriers = md.barrier_mask;
+    Record slot_a = fetch_record(tab, 0, active & 1u);         // records of the next two
+    Record slot_b = fetch_record(tab, 1, (active >> 1) & 1u);  // rounds (even, odd)
 
     uint32_t cand = 0u;  // bit 16 t + k: the particle in slot k * B + tid is a candidate of tool t
     float3 tool0 = make_float3(0.f, 0.f, 0.f), tool1 = tool0;   // sphere centres this step
-    const int last_step = A.num_steps - 1;
     for (int step = 0; step < A.num_steps; ++step) {
         // instrument state and contact candidates on the start-of-step positions
         cand = 0u;
@@ -604,11 +586,19 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
             __syncthreads();
 
             for (int it = 0; it < A.iterations; ++it) {
-                for (int r = 0; r < R0; ++r)
-                    run_round(xw, pp, r, bank0, alpha_d, alpha_v);
+                // rounds in pairs so that the two prefetch slots never move
+                for (int r = 0; r < R0; r += 2) {
+                    run_round(xw, tab, r, slot_a, active, tets, barriers, bank0, alpha_d, alpha_v);
+                    run_round(xw, tab, r + 1, slot_b, active, tets, barriers, bank0, alpha_d,
+                              alpha_v);
+                }
                 if constexpr (NB > 1)
-                    for (int r = 32; r < R; ++r)
-                        run_round(xw, pp, r, bank1, alpha_d, alpha_v);
+                    for (int r = 32; r < R; r += 2) {
+                        run_round(xw, tab, r, slot_a, active, tets, barriers, bank1, alpha_d,
+                                  alpha_v);
+                        run_round(xw, tab, r + 1, slot_b, active, tets, barriers, bank1, alpha_d,
+                                  alpha_v);
+                    }
                 if (any_contact) {
                     for (int t = 0; t < tools; ++t) {
                         const float3 ct = t == 0 ? tool0 : tool1;
@@ -632,7 +622,9 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
         }
     }
 
-    // write back (structure of arrays, coalesced)
+    // write back (structure of arrays, coalesced); slot_of[i] belongs to another
+    // thread's velocity update, hence the barrier
+    __syncthreads();
     int bad = 0;
     for (int i = tid; i < V; i += B) {
         const int sl = md.slot_of[i];
@@ -690,12 +682,19 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
             A.contact_counts[env * tools + t] = base;
     }
     if (A.lambda_out) {
+        // constraint id of this lane in round r: rr_id[r][tid] (-1: none)
         float *out = A.lambda_out + ed.lambda_offset;
-        for (int r = 0; r < R0; ++r)
-            store_lambda_round(out, md, pp, r, bank0[r & 31]);
+        for (int r = 0; r < R0; ++r) {
+            const int id = md.rr_id[r * B + tid];
+            if (id >= 0)
+                out[id] = bank0[r & 31];
+        }
         if constexpr (NB > 1)
-            for (int r = 32; r < R; ++r)
-                store_lambda_round(out, md, pp, r, bank1[r & 31]);
+            for (int r = 32; r < R; ++r) {
+                const int id = md.rr_id[r * B + tid];
+                if (id >= 0)
+                    out[id] = bank1[r & 31];
+            }
     }
 }
 

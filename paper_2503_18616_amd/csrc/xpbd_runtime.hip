@@ -368,7 +368,8 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
             int worst = 0;
             for (const auto &pm : prepared)
                 worst = std::max(worst, count_rounds(pm, B));
-            const bool fits = worst <= xpbd::kMaxRounds && vmax <= 16 * B &&
+            worst += worst % 2;   // padded to an even count
+            const bool fits = worst <= xpbd::kMaxRounds && vmax <= 16 * B && B / 64 <= 16 &&
                               xpbd::reg_lds_layout(vmax).total <= (uint32_t)lds_limit;
             if (fits) {
                 use_registers = true;
@@ -492,16 +493,41 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
             trec[(size_t)j] = make_uint4((uint32_t)q[0] | ((uint32_t)q[1] << 16),
                                          (uint32_t)q[2] | ((uint32_t)q[3] << 16), bits, 0u);
         }
+        // register variant: round-major record tables, per-wave activity and the
+        // kind / barrier masks of the round schedule
         std::vector<int4> rounds;
         build_rounds(eptr, tptr, block, rounds);
-        if (rounds.empty())
-            rounds.push_back(make_int4(0, 0, xpbd::ROUND_EDGE, 0));
+        if (rounds.size() % 2)   // the kernel runs rounds in pairs: pad with an empty round
+            rounds.push_back(make_int4(0, 0, xpbd::ROUND_TET, 0));
         const int32_t num_rounds = (int32_t)rounds.size();
-        rounds.push_back(rounds[0]);                          // the kernel prefetches two
-        rounds.push_back(rounds[num_rounds > 1 ? 1 : 0]);     // rounds ahead without wrapping
+        int32_t edge_rounds = 0;
+        for (const int4 &rd : rounds)
+            edge_rounds += (rd.z == xpbd::ROUND_EDGE && rd.y > rd.x) ? 1 : 0;
+        std::vector<uint32_t> round_rec((size_t)std::max(num_rounds, 1) * block * 3, 0u);
+        for (size_t q = 0; q < round_rec.size(); q += 3)
+            round_rec[q] = xpbd::kInvalidRecord;
+        std::vector<int32_t> rr_id((size_t)std::max(num_rounds, 1) * block, -1);
         MeshDev &d = mdev[(size_t)m];
         std::memset(&d, 0, sizeof d);
+        for (int32_t r = 0; r < num_rounds && use_registers; ++r) {
+            const int4 rd = rounds[(size_t)r];
+            const bool is_edge = r < edge_rounds;
+            for (int32_t l = 0; l < block && rd.x + l < rd.y; ++l) {
+                const int32_t j = rd.x + l;   // slot within its kind
+                uint32_t *at = &round_rec[((size_t)r * block + l) * 3];
+                at[0] = is_edge ? erec[(size_t)j].x : trec[(size_t)j].x;
+                at[1] = is_edge ? erec[(size_t)j].y : trec[(size_t)j].y;
+                at[2] = is_edge ? 0u : trec[(size_t)j].z;
+                rr_id[(size_t)r * block + l] = is_edge ? eslot[(size_t)j] : E + tslot[(size_t)j];
+                d.wave_active[l / 64] |= 1ull << r;
+            }
+            if (!is_edge)
+                d.tet_mask |= 1ull << r;
+            if (rd.w)
+                d.barrier_mask |= 1ull << r;
+        }
         d.num_rounds = use_registers ? num_rounds : 0;
+        d.num_edge_rounds = edge_rounds;
         d.num_vertices = pm.num_vertices;
         d.num_edges = E;
         d.num_tets = T;
@@ -520,15 +546,17 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
             return cleanup(st);
         uint2 *p_erec;
         uint4 *p_trec;
-        int4 *p_rounds;
+        uint32_t *p_rr;
+        int32_t *p_rrid;
         uint16_t *p_slot, *p_id;
         if ((st = b->upload(&p_erec, erec)) || (st = b->upload(&p_trec, trec)) ||
-            (st = b->upload(&p_rounds, rounds)) || (st = b->upload(&p_slot, slot16)) ||
-            (st = b->upload(&p_id, id16)))
+            (st = b->upload(&p_rr, round_rec)) || (st = b->upload(&p_rrid, rr_id)) ||
+            (st = b->upload(&p_slot, slot16)) || (st = b->upload(&p_id, id16)))
             return cleanup(st);
         d.edge_rec = p_erec;
         d.tet_rec = p_trec;
-        d.rounds = p_rounds;
+        d.round_rec = p_rr;
+        d.rr_id = p_rrid;
         d.slot_of = p_slot;
         d.id_of = p_id;
         d.edge_pair = p_pair;
