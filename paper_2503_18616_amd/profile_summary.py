@@ -56,6 +56,8 @@ def main():
     ap.add_argument("--workload", required=True)
     ap.add_argument("--command", required=True)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--extra", nargs="*", default=[],
+                    help="further --pmc csv directories; their counters are listed per dispatch")
     args = ap.parse_args()
 
     stats = _csv(args.trace, "kernel_stats.csv")
@@ -85,6 +87,16 @@ def main():
               f"- WRITE_SIZE {wk:.1f} KiB x scale {write_scale:.3f} (the copy writes {cw:.1f} KiB) = "
               f"{wk * write_scale / 1024:.2f} MiB ({nw} dispatches)",
               f"- traffic per launch: {traffic / 1e6:.2f} MB", ""]
+    if args.extra:
+        lines += ["Other counters of the step kernel (mean per dispatch; SQ_ cycle counters "
+                  "are in units of 4 cycles, summed over waves):", "",
+                  "| counter | value |", "|---|---|"]
+        for d in args.extra:
+            names = sorted({r["Counter_Name"] for r in _csv(d, "counter_collection.csv")})
+            for c in names:
+                v, _ = counter_mean(d, c, is_step)
+                lines.append(f"| {c} | {v:.4g} |")
+        lines.append("")
     with open(args.out, "w") as f:
         f.write("\n".join(lines))
     rec = {"kernel_source_sha256": kernel_source_sha256(), "workload": args.workload,
