@@ -111,16 +111,23 @@ typedef struct {
 /* Values of xpbd_params.colour_packing.  Constraints of one colour share no
  * particle, so their order changes no result; it only decides which lanes
  * the LDS serves together.
- *   AUTO     SCATTERED_BANKS16 for the register variant, else BANKS16
  *   ID_ORDER ascending constraint id
  *   BANKS8   every aligned run of 8 lanes reads particles in distinct
  *            16-byte LDS bank groups modulo 8, as far as a greedy fill allows
  *   BANKS16  the same for runs of 16 lanes modulo 16
  *   SCATTERED_BANKS16  BANKS16 after placing the particles in LDS in a fixed
  *            pseudo-random order (register variant only; the placement is
- *            internal and changes no result either) */
+ *            internal and changes no result either)
+ *   SEARCH   the scattered placement, then a seeded local search over the
+ *            lane order and the vertex order of every constraint so that
+ *            each aligned run of 16 lanes reads, and each run of 8 lanes
+ *            writes, distinct LDS bank groups (register variant only).  An
+ *            edge may list its particles in either order and a tetrahedron
+ *            in any even permutation (the projection is the same function
+ *            of the particles), so results change only in rounding.
+ * AUTO picks SEARCH for the register variant and BANKS16 otherwise. */
 enum { XPBD_PACKING_AUTO = 0, XPBD_PACKING_ID_ORDER = 1, XPBD_PACKING_BANKS8 = 2,
-       XPBD_PACKING_BANKS16 = 3, XPBD_PACKING_SCATTERED_BANKS16 = 4 };
+       XPBD_PACKING_BANKS16 = 3, XPBD_PACKING_SCATTERED_BANKS16 = 4, XPBD_PACKING_SEARCH = 5 };
 
 /* Values of xpbd_params.solver_variant.  Both variants compute the same
  * projections in the same colour order; they differ only in data placement.

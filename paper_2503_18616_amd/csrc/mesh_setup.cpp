@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <random>
 
 #include "../../include/xpbd.h"
 
@@ -88,6 +89,506 @@ void pack_colours(const int32_t *ids, int32_t k, const std::vector<int32_t> &ptr
         }
         std::copy(packed.begin(), packed.end(), slot_id.begin() + ptr[c]);
     }
+}
+
+namespace {
+
+struct VertexOrders {
+    uint8_t p[24][4];
+    int32_t n = 0;
+    explicit VertexOrders(int32_t k)
+    {
+        uint8_t a[4] = {0, 1, 2, 3};
+        do {
+            int inversions = 0;
+            for (int i = 0; i < k; ++i)
+                for (int j = i + 1; j < k; ++j)
+                    inversions += a[i] > a[j];
+            if (k == 2 || inversions % 2 == 0) {
+                std::copy(a, a + 4, p[n]);
+                ++n;
+            }
+        } while (std::next_permutation(a, a + k));
+    }
+};
+
+const VertexOrders &orders_of(int32_t k)
+{
+    static const VertexOrders two(2), four(4);
+    return k == 2 ? two : four;
+}
+
+// Conflict counters of the lanes of one colour: per aligned 16-lane group,
+// vertex position and residue modulo 16 (reads), per aligned 8-lane group,
+// position and residue modulo 8 (writes).
+struct LaneCounts {
+    int32_t k;
+    std::vector<uint8_t> rd, wr;
+    LaneCounts(int32_t n, int32_t k_)
+        : k(k_), rd((size_t)((n + 15) / 16) * k_ * 16), wr((size_t)((n + 7) / 8) * k_ * 8) {}
+    // pair cost of placing residues res[0..k) at lane l, against the lanes present
+    int32_t cost(int32_t l, const uint8_t *res) const
+    {
+        const uint8_t *r = &rd[(size_t)(l / 16) * k * 16];
+        const uint8_t *w = &wr[(size_t)(l / 8) * k * 8];
+        int32_t c = 0;
+        for (int32_t j = 0; j < k; ++j)
+            c += 2 * r[j * 16 + res[j]] + 3 * w[j * 8 + (res[j] & 7)];
+        return c;
+    }
+    void add(int32_t l, const uint8_t *res, int delta)
+    {
+        uint8_t *r = &rd[(size_t)(l / 16) * k * 16];
+        uint8_t *w = &wr[(size_t)(l / 8) * k * 8];
+        for (int32_t j = 0; j < k; ++j) {
+            r[j * 16 + res[j]] = (uint8_t)(r[j * 16 + res[j]] + delta);
+            w[j * 8 + (res[j] & 7)] = (uint8_t)(w[j * 8 + (res[j] & 7)] + delta);
+        }
+    }
+};
+
+}  // namespace
+
+int32_t num_vertex_orders(int32_t k) { return orders_of(k).n; }
+
+const uint8_t *vertex_order(int32_t k, int32_t index) { return orders_of(k).p[index]; }
+
+void pack_lanes(const int32_t *slots, int32_t k, const std::vector<int32_t> &ptr, uint32_t seed,
+                int32_t effort, std::vector<int32_t> &slot_id, std::vector<uint8_t> &order)
+{
+    const VertexOrders &O = orders_of(k);
+    const int32_t P = O.n;
+    order.assign(slot_id.size(), 0);
+    std::mt19937 gen(seed);
+    std::vector<uint8_t> res;
+    std::vector<int32_t> items, pool, lane_q, lane_o;
+    for (size_t c = 0; c + 1 < ptr.size(); ++c) {
+        const int32_t b = ptr[c], n = ptr[c + 1] - ptr[c];
+        if (n <= 0)
+            continue;
+        items.assign(slot_id.begin() + b, slot_id.begin() + b + n);
+        // residues modulo 16 of every item under every vertex order
+        res.assign((size_t)n * P * k, 0);
+        for (int32_t q = 0; q < n; ++q)
+            for (int32_t o = 0; o < P; ++o)
+                for (int32_t j = 0; j < k; ++j)
+                    res[((size_t)q * P + o) * k + j] =
+                        (uint8_t)(slots[(size_t)items[(size_t)q] * k + O.p[o][j]] & 15);
+        auto R = [&](int32_t q, int32_t o) { return &res[((size_t)q * P + o) * k]; };
+        LaneCounts cnt(n, k);
+        lane_q.assign((size_t)n, 0);
+        lane_o.assign((size_t)n, 0);
+
+        // greedy: each lane takes the cheapest (item, order) among a sample of the pool
+        pool.resize((size_t)n);
+        for (int32_t q = 0; q < n; ++q)
+            pool[(size_t)q] = q;
+        for (int32_t l = 0; l < n; ++l) {
+            const int32_t m = (int32_t)pool.size();
+            const int32_t tries = std::min(m, 96);
+            int32_t best_p = 0, best_o = 0, best_c = INT32_MAX;
+            for (int32_t t = 0; t < tries && best_c > 0; ++t) {
+                const int32_t pi = tries == m ? t : (int32_t)(gen() % (uint32_t)m);
+                for (int32_t o = 0; o < P && best_c > 0; ++o) {
+                    const int32_t cst = cnt.cost(l, R(pool[(size_t)pi], o));
+                    if (cst < best_c) {
+                        best_c = cst;
+                        best_p = pi;
+                        best_o = o;
+                    }
+                }
+            }
+            lane_q[(size_t)l] = pool[(size_t)best_p];
+            lane_o[(size_t)l] = best_o;
+            cnt.add(l, R(lane_q[(size_t)l], best_o), 1);
+            pool[(size_t)best_p] = pool.back();
+            pool.pop_back();
+        }
+
+        // local search: swap two lanes (each item then takes its best order at
+        // its new lane) or re-order one lane; keep moves that do not add cost
+        auto best_order = [&](int32_t l, int32_t q, int32_t &o_out) {
+            int32_t bc = INT32_MAX;
+            for (int32_t o = 0; o < P; ++o) {
+                const int32_t cst = cnt.cost(l, R(q, o));
+                if (cst < bc) {
+                    bc = cst;
+                    o_out = o;
+                }
+            }
+            return bc;
+        };
+        const int64_t moves = n > 1 ? (int64_t)effort * n : 0;
+        for (int64_t mv = 0; mv < moves; ++mv) {
+            const int32_t l1 = (int32_t)(gen() % (uint32_t)n);
+            const int32_t q1 = lane_q[(size_t)l1], o1 = lane_o[(size_t)l1];
+            cnt.add(l1, R(q1, o1), -1);
+            const int32_t c1 = cnt.cost(l1, R(q1, o1));
+            if (c1 == 0) {   // conflict-free lane: leave it
+                cnt.add(l1, R(q1, o1), 1);
+                continue;
+            }
+            if (gen() % 4 == 0) {
+                int32_t o = o1;
+                const int32_t bc = best_order(l1, q1, o);
+                lane_o[(size_t)l1] = bc < c1 ? o : o1;
+                cnt.add(l1, R(q1, lane_o[(size_t)l1]), 1);
+                continue;
+            }
+            const int32_t l2 = (int32_t)(gen() % (uint32_t)n);
+            if (l2 / 8 == l1 / 8) {
+                cnt.add(l1, R(q1, o1), 1);
+                continue;
+            }
+            const int32_t q2 = lane_q[(size_t)l2], o2 = lane_o[(size_t)l2];
+            cnt.add(l2, R(q2, o2), -1);
+            const int32_t before = c1 + cnt.cost(l2, R(q2, o2));
+            int32_t n1 = 0, n2 = 0;
+            int32_t after = best_order(l1, q2, n1);
+            cnt.add(l1, R(q2, n1), 1);
+            after += best_order(l2, q1, n2);
+            if (after <= before) {
+                cnt.add(l2, R(q1, n2), 1);
+                lane_q[(size_t)l1] = q2;
+                lane_o[(size_t)l1] = n1;
+                lane_q[(size_t)l2] = q1;
+                lane_o[(size_t)l2] = n2;
+            } else {
+                cnt.add(l1, R(q2, n1), -1);
+                cnt.add(l1, R(q1, o1), 1);
+                cnt.add(l2, R(q2, o2), 1);
+            }
+        }
+        for (int32_t l = 0; l < n; ++l) {
+            const int32_t id = items[(size_t)lane_q[(size_t)l]];
+            slot_id[(size_t)(b + l)] = id;
+            order[(size_t)id] = (uint8_t)lane_o[(size_t)l];
+        }
+    }
+}
+
+namespace {
+
+// State of the joint search: every kind's lanes with their group counters,
+// and for every particle the constraints that use it.
+struct PackState {
+    struct Kind {
+        const int32_t *ids;
+        int32_t k, n;
+        const VertexOrders *O;
+        std::vector<int32_t> lane_of, item, colour_begin, colour_end;   // per lane / item
+        std::vector<uint8_t> ord;                                        // per item
+        std::vector<int32_t> g16, g8;                                    // per lane
+        std::vector<uint8_t> rd, wr;                                     // counters
+    };
+    std::vector<Kind> kinds;
+    std::vector<int32_t> &slot_of;
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> uses;   // particle -> (kind, item)
+
+    explicit PackState(std::vector<int32_t> &s) : slot_of(s) {}
+
+    void residues(const Kind &K, int32_t q, int32_t o, uint8_t *res) const
+    {
+        for (int32_t j = 0; j < K.k; ++j)
+            res[j] = (uint8_t)(slot_of[(size_t)K.ids[(size_t)q * K.k + K.O->p[o][j]]] & 15);
+    }
+    int32_t cost(const Kind &K, int32_t lane, const uint8_t *res) const
+    {
+        const uint8_t *r = &K.rd[(size_t)K.g16[(size_t)lane] * K.k * 16];
+        const uint8_t *w = &K.wr[(size_t)K.g8[(size_t)lane] * K.k * 8];
+        int32_t c = 0;
+        for (int32_t j = 0; j < K.k; ++j)
+            c += 2 * r[j * 16 + res[j]] + 3 * w[j * 8 + (res[j] & 7)];
+        return c;
+    }
+    void count(Kind &K, int32_t lane, const uint8_t *res, int delta)
+    {
+        uint8_t *r = &K.rd[(size_t)K.g16[(size_t)lane] * K.k * 16];
+        uint8_t *w = &K.wr[(size_t)K.g8[(size_t)lane] * K.k * 8];
+        for (int32_t j = 0; j < K.k; ++j) {
+            r[j * 16 + res[j]] = (uint8_t)(r[j * 16 + res[j]] + delta);
+            w[j * 8 + (res[j] & 7)] = (uint8_t)(w[j * 8 + (res[j] & 7)] + delta);
+        }
+    }
+    // remove item q's lane from the counters; returns its cost against the rest
+    int32_t take(Kind &K, int32_t q)
+    {
+        uint8_t res[4];
+        residues(K, q, K.ord[(size_t)q], res);
+        count(K, K.lane_of[(size_t)q], res, -1);
+        return cost(K, K.lane_of[(size_t)q], res);
+    }
+    int32_t put(Kind &K, int32_t q)
+    {
+        uint8_t res[4];
+        residues(K, q, K.ord[(size_t)q], res);
+        const int32_t c = cost(K, K.lane_of[(size_t)q], res);
+        count(K, K.lane_of[(size_t)q], res, 1);
+        return c;
+    }
+    // best vertex order of item q at its lane (counters without q); returns the cost
+    int32_t best_order(Kind &K, int32_t q)
+    {
+        uint8_t res[4];
+        int32_t bc = INT32_MAX, bo = K.ord[(size_t)q];
+        for (int32_t o = 0; o < K.O->n; ++o) {
+            residues(K, q, o, res);
+            const int32_t c = cost(K, K.lane_of[(size_t)q], res);
+            if (c < bc || (c == bc && o == K.ord[(size_t)q])) {
+                bc = c;
+                bo = o;
+            }
+        }
+        K.ord[(size_t)q] = (uint8_t)bo;
+        return bc;
+    }
+};
+
+}  // namespace
+
+namespace {
+
+// Placement pre-pass: swap particles' slots so that, in every colour of every
+// kind, the particles used are spread evenly over the 16 bank groups (a colour
+// whose particles crowd one bank group cannot be packed conflict-free).
+// Objective: sum over (kind, colour, bank group) of the squared count.
+void balance_placement(int32_t num_particles, std::vector<int32_t> &slot_of,
+                       const LaneSchedule *kinds, int32_t num_kinds, std::mt19937 &gen,
+                       int64_t moves)
+{
+    // colour rows of every (kind, colour), and each particle's rows (with multiplicity)
+    std::vector<std::vector<int32_t>> rows_of((size_t)num_particles);
+    int32_t rows = 0;
+    for (int32_t t = 0; t < num_kinds; ++t) {
+        const LaneSchedule &L = kinds[t];
+        const std::vector<int32_t> &ptr = *L.ptr;
+        for (size_t c = 0; c + 1 < ptr.size(); ++c, ++rows)
+            for (int32_t l = ptr[c]; l < ptr[c + 1]; ++l) {
+                const int32_t q = (*L.slot_id)[(size_t)l];
+                for (int32_t j = 0; j < L.k; ++j)
+                    rows_of[(size_t)L.ids[(size_t)q * L.k + j]].push_back(rows);
+            }
+    }
+    std::vector<int32_t> cnt((size_t)rows * 16, 0);
+    for (int32_t p = 0; p < num_particles; ++p)
+        for (int32_t r : rows_of[(size_t)p])
+            cnt[(size_t)r * 16 + (slot_of[(size_t)p] & 15)]++;
+    for (int64_t mv = 0; mv < moves && num_particles > 1; ++mv) {
+        const int32_t p1 = (int32_t)(gen() % (uint32_t)num_particles);
+        const int32_t p2 = (int32_t)(gen() % (uint32_t)num_particles);
+        const int32_t g1 = slot_of[(size_t)p1] & 15, g2 = slot_of[(size_t)p2] & 15;
+        if (g1 == g2)
+            continue;
+        // change of sum(cnt^2) when p1 moves g1 -> g2 and p2 moves g2 -> g1
+        int64_t delta = 0;
+        for (int32_t r : rows_of[(size_t)p1]) {
+            int32_t &a = cnt[(size_t)r * 16 + g1], &b = cnt[(size_t)r * 16 + g2];
+            delta += 2 * (b - a) + 2;
+            --a;
+            ++b;
+        }
+        for (int32_t r : rows_of[(size_t)p2]) {
+            int32_t &a = cnt[(size_t)r * 16 + g2], &b = cnt[(size_t)r * 16 + g1];
+            delta += 2 * (b - a) + 2;
+            --a;
+            ++b;
+        }
+        if (delta <= 0) {
+            std::swap(slot_of[(size_t)p1], slot_of[(size_t)p2]);
+        } else {
+            for (int32_t r : rows_of[(size_t)p2]) {
+                cnt[(size_t)r * 16 + g2]++;
+                cnt[(size_t)r * 16 + g1]--;
+            }
+            for (int32_t r : rows_of[(size_t)p1]) {
+                cnt[(size_t)r * 16 + g1]++;
+                cnt[(size_t)r * 16 + g2]--;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+void pack_lds(int32_t num_particles, std::vector<int32_t> &slot_of, LaneSchedule *kinds,
+              int32_t num_kinds, uint32_t seed, int32_t effort)
+{
+    std::mt19937 gen(seed);
+    balance_placement(num_particles, slot_of, kinds, num_kinds, gen, 200 * (int64_t)num_particles);
+    // greedy start per kind, on the starting placement
+    std::vector<int32_t> slots;
+    for (int32_t t = 0; t < num_kinds; ++t) {
+        const LaneSchedule &L = kinds[t];
+        const size_t n = L.slot_id->size();
+        slots.resize(n * (size_t)L.k);
+        for (size_t i = 0; i < slots.size(); ++i)
+            slots[i] = slot_of[(size_t)L.ids[i]];
+        pack_lanes(slots.data(), L.k, *L.ptr, (uint32_t)gen(), 0, *L.slot_id, *L.order);
+    }
+    PackState S(slot_of);
+    S.uses.assign((size_t)num_particles, {});
+    S.kinds.resize((size_t)num_kinds);
+    int64_t total_lanes = 0;
+    for (int32_t t = 0; t < num_kinds; ++t) {
+        const LaneSchedule &L = kinds[t];
+        PackState::Kind &K = S.kinds[(size_t)t];
+        K.ids = L.ids;
+        K.k = L.k;
+        K.n = (int32_t)L.slot_id->size();
+        K.O = &orders_of(L.k);
+        K.item = *L.slot_id;
+        K.ord = *L.order;
+        K.lane_of.assign((size_t)K.n, 0);
+        K.colour_begin.assign((size_t)K.n, 0);
+        K.colour_end.assign((size_t)K.n, 0);
+        K.g16.assign((size_t)K.n, 0);
+        K.g8.assign((size_t)K.n, 0);
+        int32_t n16 = 0, n8 = 0;
+        const std::vector<int32_t> &ptr = *L.ptr;
+        for (size_t c = 0; c + 1 < ptr.size(); ++c) {
+            for (int32_t l = ptr[c]; l < ptr[c + 1]; ++l) {
+                K.colour_begin[(size_t)l] = ptr[c];
+                K.colour_end[(size_t)l] = ptr[c + 1];
+                K.g16[(size_t)l] = n16 + (l - ptr[c]) / 16;
+                K.g8[(size_t)l] = n8 + (l - ptr[c]) / 8;
+            }
+            n16 += (ptr[c + 1] - ptr[c] + 15) / 16;
+            n8 += (ptr[c + 1] - ptr[c] + 7) / 8;
+        }
+        K.rd.assign((size_t)n16 * K.k * 16, 0);
+        K.wr.assign((size_t)n8 * K.k * 8, 0);
+        for (int32_t l = 0; l < K.n; ++l)
+            K.lane_of[(size_t)K.item[(size_t)l]] = l;
+        for (int32_t q = 0; q < K.n; ++q) {
+            S.put(K, q);
+            for (int32_t j = 0; j < K.k; ++j)
+                S.uses[(size_t)K.ids[(size_t)q * K.k + j]].push_back({t, q});
+        }
+        total_lanes += K.n;
+    }
+
+    std::vector<std::pair<int32_t, int32_t>> touched;
+    std::vector<uint8_t> old_ord;
+    std::vector<std::vector<int32_t>> seen((size_t)num_kinds);
+    int32_t epoch = 0;
+    for (int32_t t = 0; t < num_kinds; ++t)
+        seen[(size_t)t].assign((size_t)S.kinds[(size_t)t].n, -1);
+    const int64_t moves = (int64_t)effort * total_lanes;
+    for (int64_t mv = 0; mv < moves; ++mv) {
+        const uint32_t kind_of_move = gen() % 8;
+        if (kind_of_move < 3 && num_particles > 1) {
+            // swap the slots of two particles in different bank groups
+            const int32_t p1 = (int32_t)(gen() % (uint32_t)num_particles);
+            const int32_t p2 = (int32_t)(gen() % (uint32_t)num_particles);
+            if (((slot_of[(size_t)p1] ^ slot_of[(size_t)p2]) & 15) == 0)
+                continue;
+            touched.clear();
+            old_ord.clear();
+            ++epoch;
+            for (int32_t p : {p1, p2})
+                for (const auto &u : S.uses[(size_t)p])
+                    if (seen[(size_t)u.first][(size_t)u.second] != epoch) {
+                        seen[(size_t)u.first][(size_t)u.second] = epoch;
+                        touched.push_back(u);
+                    }
+            int32_t before = 0, after = 0;
+            for (const auto &u : touched) {
+                old_ord.push_back(S.kinds[(size_t)u.first].ord[(size_t)u.second]);
+                before += S.take(S.kinds[(size_t)u.first], u.second);
+            }
+            std::swap(slot_of[(size_t)p1], slot_of[(size_t)p2]);
+            for (const auto &u : touched) {
+                PackState::Kind &K = S.kinds[(size_t)u.first];
+                after += S.best_order(K, u.second);
+                S.put(K, u.second);
+            }
+            if (after > before) {
+                for (const auto &u : touched)
+                    S.take(S.kinds[(size_t)u.first], u.second);
+                std::swap(slot_of[(size_t)p1], slot_of[(size_t)p2]);
+                for (size_t i = 0; i < touched.size(); ++i) {
+                    PackState::Kind &K = S.kinds[(size_t)touched[i].first];
+                    K.ord[(size_t)touched[i].second] = old_ord[i];
+                    S.put(K, touched[i].second);
+                }
+            }
+            continue;
+        }
+        // lane moves inside one colour of one kind (kinds chosen by size)
+        int64_t pick = (int64_t)(gen() % (uint64_t)total_lanes);
+        int32_t t = 0;
+        while (pick >= S.kinds[(size_t)t].n) {
+            pick -= S.kinds[(size_t)t].n;
+            ++t;
+        }
+        PackState::Kind &K = S.kinds[(size_t)t];
+        const int32_t l1 = (int32_t)pick;
+        const int32_t q1 = K.item[(size_t)l1];
+        const uint8_t o1 = K.ord[(size_t)q1];
+        const int32_t c1 = S.take(K, q1);
+        if (c1 == 0) {
+            S.put(K, q1);
+            continue;
+        }
+        if (kind_of_move == 3) {
+            S.best_order(K, q1);
+            S.put(K, q1);
+            continue;
+        }
+        const int32_t b = K.colour_begin[(size_t)l1], e = K.colour_end[(size_t)l1];
+        const int32_t l2 = b + (int32_t)(gen() % (uint32_t)(e - b));
+        if (K.g8[(size_t)l2] == K.g8[(size_t)l1]) {
+            S.put(K, q1);
+            continue;
+        }
+        const int32_t q2 = K.item[(size_t)l2];
+        const uint8_t o2 = K.ord[(size_t)q2];
+        const int32_t before = c1 + S.take(K, q2);
+        K.lane_of[(size_t)q1] = l2;
+        K.lane_of[(size_t)q2] = l1;
+        K.item[(size_t)l1] = q2;
+        K.item[(size_t)l2] = q1;
+        int32_t after = S.best_order(K, q2);
+        S.put(K, q2);
+        after += S.best_order(K, q1);
+        if (after <= before) {
+            S.put(K, q1);
+        } else {
+            S.take(K, q2);
+            K.lane_of[(size_t)q1] = l1;
+            K.lane_of[(size_t)q2] = l2;
+            K.item[(size_t)l1] = q1;
+            K.item[(size_t)l2] = q2;
+            K.ord[(size_t)q1] = o1;
+            K.ord[(size_t)q2] = o2;
+            S.put(K, q1);
+            S.put(K, q2);
+        }
+    }
+    for (int32_t t = 0; t < num_kinds; ++t) {
+        *kinds[t].slot_id = S.kinds[(size_t)t].item;
+        *kinds[t].order = S.kinds[(size_t)t].ord;
+    }
+}
+
+int64_t lane_conflicts(const int32_t *slots, int32_t k, const std::vector<int32_t> &ptr,
+                       const std::vector<int32_t> &slot_id, const std::vector<uint8_t> &order)
+{
+    const VertexOrders &O = orders_of(k);
+    int64_t extra = 0;
+    for (size_t c = 0; c + 1 < ptr.size(); ++c)
+        for (int32_t j = 0; j < k; ++j)
+            for (int32_t width = 16; width >= 8; width -= 8)
+                for (int32_t g = ptr[c]; g < ptr[c + 1]; g += width) {
+                    int32_t m[16] = {0}, top = 0;
+                    for (int32_t l = g; l < std::min(g + width, ptr[c + 1]); ++l) {
+                        const int32_t id = slot_id[(size_t)l];
+                        const int32_t s = slots[(size_t)id * k + O.p[order[(size_t)id]][j]];
+                        top = std::max(top, ++m[s % width]);
+                    }
+                    extra += top - 1;
+                }
+    return extra;
 }
 
 int prepare_mesh(int32_t num_vertices, int32_t num_tets, const float *rest_pos,

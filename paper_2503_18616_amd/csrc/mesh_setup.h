@@ -47,4 +47,49 @@ int32_t greedy_colouring(int32_t num_vertices, int32_t n, int32_t k, const int32
 void pack_colours(const int32_t *ids, int32_t k, const std::vector<int32_t> &ptr, int32_t group,
                   int32_t modulus, std::vector<int32_t> &slot_id);
 
+// Even permutations of the vertices of a constraint: the edge update is
+// symmetric in its two particles and the volume update is invariant under the
+// even permutations of its four (they keep the orientation), so a record may
+// list its particles in any of these orders.  Tables: [count][k].
+int32_t num_vertex_orders(int32_t k);
+const uint8_t *vertex_order(int32_t k, int32_t index);
+
+// Lane order and vertex order of the constraints of every colour, searched so
+// that the register kernel's LDS accesses avoid bank conflicts.  gfx950's LDS
+// has 64 four-byte banks: a ds_read_b128 serves 16 lanes per clock and is
+// conflict-free when the 16-byte records read by each aligned group of 16
+// lanes are distinct modulo 16; a ds_write_b96 serves 8 lanes per clock and is
+// conflict-free when the records written by each aligned group of 8 lanes are
+// distinct modulo 8.  slots: [n][k] LDS slots of constraint ids 0..n-1.
+// slot_id: in, colour-major constraint ids (colour offsets ptr); out, the same
+// sets in lane order.  order: out, [n] vertex_order index per constraint id.
+// Deterministic for a given seed; effort scales the local-search moves per
+// lane (0: greedy pass only).
+void pack_lanes(const int32_t *slots, int32_t k, const std::vector<int32_t> &ptr, uint32_t seed,
+                int32_t effort, std::vector<int32_t> &slot_id, std::vector<uint8_t> &order);
+
+// One constraint type for pack_lds: particle ids [n][k] (mesh order), colour
+// offsets, and the two outputs of pack_lanes.
+struct LaneSchedule {
+    const int32_t *ids;
+    int32_t k;
+    const std::vector<int32_t> *ptr;
+    std::vector<int32_t> *slot_id;   // in: colour-major ids; out: lane order
+    std::vector<uint8_t> *order;     // out: [n] vertex_order index
+};
+
+// pack_lanes for several constraint types at once, with the LDS placement of
+// the particles searched as well: slot_of (in: a starting bijection particle
+// -> slot, out: the searched one) decides the bank group (slot modulo 16) of
+// each particle in every constraint that uses it.  Moves swap two particles'
+// slots, swap two lanes of a colour, or change a vertex order.
+void pack_lds(int32_t num_particles, std::vector<int32_t> &slot_of, LaneSchedule *kinds,
+              int32_t num_kinds, uint32_t seed, int32_t effort);
+
+// Bank-conflict cost of a lane order in LDS clocks beyond the conflict-free
+// count, summed over the colours (reads: extra passes of each 16-lane group;
+// writes: extra passes of each 8-lane group), as pack_lanes models it.
+int64_t lane_conflicts(const int32_t *slots, int32_t k, const std::vector<int32_t> &ptr,
+                       const std::vector<int32_t> &slot_id, const std::vector<uint8_t> &order);
+
 }  // namespace xpbd

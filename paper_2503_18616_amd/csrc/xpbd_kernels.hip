@@ -417,6 +417,33 @@ __global__ void __launch_bounds__(1024) xpbd_step_lds_kernel(StepArgs A)
 // Pointers into global memory seen through the global address space, so that
 // loads become global_load (vector memory counter only) instead of flat loads.
 #define XPBD_GLOBAL __attribute__((address_space(1)))
+// Read-only kernel inputs indexed by workgroup-uniform values go through the
+// constant address space, so they load into scalar registers.
+#define XPBD_CONST __attribute__((address_space(4)))
+
+// x unchanged, but opaque to the optimiser: per-lane values derived from it
+// are recomputed where they are used instead of being hoisted and kept live
+// (or spilled) across the solver loop.
+__device__ __forceinline__ int opaque(int x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// Workgroup-wide OR of a per-thread flag: one ballot per wave into words[],
+// one barrier.  Callers separate two uses of the same words by a barrier.
+__device__ __forceinline__ bool block_any(bool v, uint32_t *words, int wave, int lane,
+                                          int num_waves)
+{
+    const uint64_t m = __ballot(v);
+    if (lane == 0)
+        words[wave] = m != 0u ? 1u : 0u;
+    __syncthreads();
+    uint32_t any = 0u;
+    for (int w = 0; w < num_waves; ++w)
+        any |= words[w];
+    return any != 0u;
+}
 
 // Native vector types (the HIP vector classes cannot be loaded through an
 // address-space-qualified pointer).
@@ -549,22 +576,23 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
         // instrument state and contact candidates on the start-of-step positions
         cand = 0u;
         for (int t = 0; t < tools; ++t) {
-            const float *c = A.tool_pos + (((size_t)step * A.num_envs + env) * tools + t) * 3;
+            const XPBD_CONST float *c = (const XPBD_CONST float *)(uintptr_t)A.tool_pos +
+                                        (((size_t)step * A.num_envs + env) * tools + t) * 3;
             const float3 ct = make_float3(c[0], c[1], c[2]);
             if (t == 0)
                 tool0 = ct;
             else
                 tool1 = ct;
             const float reach2 = t == 0 ? A.tool_reach2[0] : A.tool_reach2[1];
-            for (int k = 0, i = tid; i < V; ++k, i += B)
+            for (int k = 0, i = opaque(tid); i < V; ++k, i += B)
                 if (within_reach(xw[i], ct.x, ct.y, ct.z, reach2))
                     cand |= 1u << (16 * t + k);
         }
-        const bool any_contact = __syncthreads_or(cand != 0u) != 0;
+        const bool any_contact = block_any(cand != 0u, scratch + 32, wave, lane, num_waves);
 
         for (int sub = 0; sub < A.substeps; ++sub) {
             // predict velocity and position (Alg. 1); pinned particles stay put
-            for (int i = tid; i < V; i += B) {
+            for (int i = opaque(tid); i < V; i += B) {
                 float4 p = xw[i];
                 prev[i] = p.x;
                 prev[V + i] = p.y;
@@ -604,7 +632,7 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
                         const float3 ct = t == 0 ? tool0 : tool1;
                         const float rt = t == 0 ? A.tool_radius[0] : A.tool_radius[1];
                         const float rt2 = t == 0 ? A.tool_radius2[0] : A.tool_radius2[1];
-                        for (int k = 0, i = tid; i < V; ++k, i += B)
+                        for (int k = 0, i = opaque(tid); i < V; ++k, i += B)
                             if ((cand >> (16 * t + k)) & 1u)
                                 project_contact(xw, i, ct.x, ct.y, ct.z, rt, rt2);
                     }
@@ -613,7 +641,7 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
             }
 
             // velocity update v = (x - x_prev) / h (Alg. 1)
-            for (int i = tid; i < V; i += B) {
+            for (int i = opaque(tid); i < V; i += B) {
                 const float4 p = xw[i];
                 vel[i] = (p.x - prev[i]) * inv_h;
                 vel[V + i] = (p.y - prev[V + i]) * inv_h;
@@ -639,7 +667,7 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
         bad |= !(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(vx) &&
                  isfinite(vy) && isfinite(vz));
     }
-    bad = __syncthreads_or(bad);
+    bad = block_any(bad != 0, scratch + 32, wave, lane, num_waves);
     if (tid == 0 && bad)
         A.nonfinite[env] = 1;
 

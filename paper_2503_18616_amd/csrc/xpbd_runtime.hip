@@ -153,10 +153,13 @@ xpbd_status validate_params(const xpbd_params *p)
         return fail(XPBD_E_ARG, "block_size must be 0 or a multiple of 64 in [64, 1024]");
     if (p->solver_variant < XPBD_VARIANT_AUTO || p->solver_variant > XPBD_VARIANT_LDS)
         return fail(XPBD_E_ARG, "unknown solver_variant %d", p->solver_variant);
-    if (p->colour_packing < XPBD_PACKING_AUTO || p->colour_packing > XPBD_PACKING_SCATTERED_BANKS16)
+    if (p->colour_packing < XPBD_PACKING_AUTO || p->colour_packing > XPBD_PACKING_SEARCH)
         return fail(XPBD_E_ARG, "unknown colour_packing %d", p->colour_packing);
     return XPBD_OK;
 }
+
+// Local-search moves per constraint of the SEARCH colour packing.
+constexpr int32_t kLaneSearchEffort = 64;
 
 int next_pow2(int x)
 {
@@ -435,14 +438,17 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         build_schedule(pm.tet_colour, pm.num_tet_colours, tslot, tptr);
         int packing = params->colour_packing;
         if (packing == XPBD_PACKING_AUTO)
-            packing = use_registers ? XPBD_PACKING_SCATTERED_BANKS16 : XPBD_PACKING_BANKS16;
-        if (packing == XPBD_PACKING_SCATTERED_BANKS16 && !use_registers)
+            packing = use_registers ? XPBD_PACKING_SEARCH : XPBD_PACKING_BANKS16;
+        if ((packing == XPBD_PACKING_SCATTERED_BANKS16 || packing == XPBD_PACKING_SEARCH) &&
+            !use_registers)
             packing = XPBD_PACKING_BANKS16;
+        const bool scattered =
+            packing == XPBD_PACKING_SCATTERED_BANKS16 || packing == XPBD_PACKING_SEARCH;
         // LDS placement of the particles (register variant): identity, or a fixed
         // pseudo-random order that spreads every colour's particles over the banks
         std::vector<int32_t> slot_of((size_t)pm.num_vertices);
         std::iota(slot_of.begin(), slot_of.end(), 0);
-        if (packing == XPBD_PACKING_SCATTERED_BANKS16) {
+        if (scattered) {
             std::mt19937 gen(0x5eedu + (uint32_t)m);
             std::shuffle(slot_of.begin(), slot_of.end(), gen);
         }
@@ -456,9 +462,21 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
             edges_in_lds[q] = slot_of[(size_t)pm.edges[q]];
         for (size_t q = 0; q < pm.tets.size(); ++q)
             tets_in_lds[q] = slot_of[(size_t)pm.tets[q]];
-        const int group = packing == XPBD_PACKING_BANKS8 ? 8 : packing == XPBD_PACKING_ID_ORDER ? 0 : 16;
-        xpbd::pack_colours(edges_in_lds.data(), 2, eptr, group, group, eslot);
-        xpbd::pack_colours(tets_in_lds.data(), 4, tptr, group, group, tslot);
+        // vertex order of each constraint in the register variant's records
+        // (an index into xpbd::vertex_order; 0 keeps the mesh order)
+        std::vector<uint8_t> eorder((size_t)E, 0), torder((size_t)T, 0);
+        if (packing == XPBD_PACKING_SEARCH) {
+            xpbd::pack_lanes(edges_in_lds.data(), 2, eptr, 0x9e37u + 2u * (uint32_t)m,
+                             kLaneSearchEffort, eslot, eorder);
+            xpbd::pack_lanes(tets_in_lds.data(), 4, tptr, 0x9e38u + 2u * (uint32_t)m,
+                             kLaneSearchEffort, tslot, torder);
+        } else {
+            const int group = packing == XPBD_PACKING_BANKS8     ? 8
+                              : packing == XPBD_PACKING_ID_ORDER ? 0
+                                                                 : 16;
+            xpbd::pack_colours(edges_in_lds.data(), 2, eptr, group, group, eslot);
+            xpbd::pack_colours(tets_in_lds.data(), 4, tptr, group, group, tslot);
+        }
         std::vector<uint32_t> pair((size_t)E);
         std::vector<float> erest((size_t)E), trest((size_t)T);
         std::vector<uint2> quad((size_t)T);
@@ -515,9 +533,20 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
             for (int32_t l = 0; l < block && rd.x + l < rd.y; ++l) {
                 const int32_t j = rd.x + l;   // slot within its kind
                 uint32_t *at = &round_rec[((size_t)r * block + l) * 3];
-                at[0] = is_edge ? erec[(size_t)j].x : trec[(size_t)j].x;
-                at[1] = is_edge ? erec[(size_t)j].y : trec[(size_t)j].y;
-                at[2] = is_edge ? 0u : trec[(size_t)j].z;
+                if (is_edge) {
+                    const int32_t e = eslot[(size_t)j];
+                    const uint8_t *o = xpbd::vertex_order(2, eorder[(size_t)e]);
+                    at[0] = (uint32_t)edges_in_lds[2 * (size_t)e + o[0]] |
+                            ((uint32_t)edges_in_lds[2 * (size_t)e + o[1]] << 16);
+                    at[1] = erec[(size_t)j].y;
+                    at[2] = 0u;
+                } else {
+                    const int32_t *q = &tets_in_lds[4 * (size_t)tslot[(size_t)j]];
+                    const uint8_t *o = xpbd::vertex_order(4, torder[(size_t)tslot[(size_t)j]]);
+                    at[0] = (uint32_t)q[o[0]] | ((uint32_t)q[o[1]] << 16);
+                    at[1] = (uint32_t)q[o[2]] | ((uint32_t)q[o[3]] << 16);
+                    at[2] = trec[(size_t)j].z;
+                }
                 rr_id[(size_t)r * block + l] = is_edge ? eslot[(size_t)j] : E + tslot[(size_t)j];
                 d.wave_active[l / 64] |= 1ull << r;
             }

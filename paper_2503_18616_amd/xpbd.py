@@ -54,6 +54,7 @@ PACKING_ID_ORDER = 1
 PACKING_BANKS8 = 2
 PACKING_BANKS16 = 3
 PACKING_SCATTERED_BANKS16 = 4
+PACKING_SEARCH = 5
 
 # field -> numpy dtype of its elements
 FIELD_DTYPES = {FIELD_POS: np.float32, FIELD_VEL: np.float32, FIELD_LAMBDA: np.float32,

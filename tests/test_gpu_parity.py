@@ -401,6 +401,29 @@ def test_colour_packing_does_not_change_results(xp, packing, variant):
         assert np.array_equal(a.read(xp.FIELD_LAMBDA), b.read(xp.FIELD_LAMBDA))
 
 
+@pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
+def test_searched_packing_changes_only_rounding(xp, variant):
+    """The searched packing also reorders the particles inside edges and (by even
+    permutations) tetrahedra: the same projections, different rounding."""
+    wl = W.batch_workload(8, seed=7, num_steps=30)
+    tools = W.tool_path(30, 8, 7, start_depth=6e-3)
+    p_ref = K.lib_params(xp, wl, xp.F_LAMBDA)
+    p_ref.solver_variant = variant
+    p_ref.colour_packing = xp.PACKING_ID_ORDER
+    p = K.lib_params(xp, wl, xp.F_LAMBDA)
+    p.solver_variant = variant
+    p.colour_packing = xp.PACKING_SEARCH
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p_ref) as a, \
+            xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b:
+        a.step(30, tools)
+        b.step(30, tools)
+        assert K.max_position_error(b.positions(), a.positions()) <= K.POS_TOL
+        la, lb = a.read(xp.FIELD_LAMBDA), b.read(xp.FIELD_LAMBDA)
+        assert np.abs(la - lb).max() <= 1e-3 * np.abs(la).max()
+        if variant == 2:   # the LDS variant ignores the register-only packings
+            assert np.array_equal(a.positions(), b.positions())
+
+
 def test_flags_can_change_between_steps(xp):
     """Residual and multipliers requested on a later step only."""
     wl = W.batch_workload(4, seed=8, num_steps=6)
