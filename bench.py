@@ -60,7 +60,10 @@ def parse_args():
     ap.add_argument("--variant", type=int, default=0,
                     help="0 = library's choice, 1 = multipliers in registers, 2 = multipliers in LDS")
     ap.add_argument("--packing", type=int, default=0,
-                    help="0 = library's choice, 1 = id order, 2 = 8-lane bank groups, 3 = 16-lane")
+                    help="0 = library's choice, 1 = id order, 2 = 8-lane bank groups, 3 = 16-lane, "
+                         "4 = scattered + 16-lane, 5 = searched")
+    ap.add_argument("--group", type=int, default=0,
+                    help="environments per workgroup (0 = library's choice, 1 or 2)")
     ap.add_argument("--cpu-envs", type=int, default=64, help="oracle sample: environments")
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle sample: steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -89,7 +92,8 @@ def measured_traffic(workload, steps_per_launch, args):
     import hashlib
     path = os.path.join(ROOT, "profiles", "xpbd_step_traffic.json")
     src = os.path.join(ROOT, "paper_2503_18616_amd", "csrc", "xpbd_kernels.hip")
-    if not os.path.exists(path) or steps_per_launch != 1 or args.variant or args.packing or args.block:
+    if (not os.path.exists(path) or steps_per_launch != 1 or args.variant or args.packing
+            or args.block or args.group):
         return None
     with open(path) as f:
         rec = json.load(f)
@@ -137,7 +141,8 @@ def main():
     tools = torch.from_numpy(wl.tools(total)).cuda()
     params = xpbd.make_params(wl.dt, S, I, wl.gravity, wl.num_tools, wl.tool_radius,
                               flags=0, block_size=args.block,
-                              solver_variant=args.variant, colour_packing=args.packing)
+                              solver_variant=args.variant, colour_packing=args.packing,
+                              envs_per_group=args.group)
     stream = torch.cuda.current_stream()
     batch = xpbd.Batch([(m.rest_pos, m.inv_mass, m.tets)], wl.env_mesh, wl.compliance, params,
                        stream=stream.cuda_stream)

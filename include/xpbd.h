@@ -106,6 +106,11 @@ typedef struct {
                             multiple of 64 in [64, 1024] */
     int32_t solver_variant; /* XPBD_VARIANT_*: where the multipliers live */
     int32_t colour_packing; /* XPBD_PACKING_*: order of the constraints inside a colour */
+    int32_t envs_per_group; /* register variant: environments that share one workgroup,
+                               its LDS and its rounds (lanes of a round may belong to
+                               different environments): 0 = chosen by the library, else
+                               1 or 2.  Environments are grouped per mesh in index
+                               order; the LDS variant always uses 1. */
 } xpbd_params;
 
 /* Values of xpbd_params.colour_packing.  Constraints of one colour share no

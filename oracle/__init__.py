@@ -72,6 +72,18 @@ def _load():
             lib.oracle_residual.restype = None
             lib.oracle_residual.argtypes = [_D, ctypes.c_int, _I, _D, ctypes.c_int, _I, _D,
                                             ctypes.c_double, ctypes.c_double, _D, _D]
+            lib.oracle_candidates.restype = ctypes.c_int
+            lib.oracle_candidates.argtypes = [ctypes.c_int, _D, _D, _D, ctypes.c_double, _I]
+            lib.oracle_predict.restype = None
+            lib.oracle_predict.argtypes = [ctypes.c_int, _D, ctypes.c_double, _D, _D, _D, _D]
+            lib.oracle_iterate.restype = None
+            lib.oracle_iterate.argtypes = [
+                _D, _D, ctypes.c_int, _I, _D, _D, _I,
+                ctypes.c_int, _I, _I, ctypes.c_int, _I, _I,
+                ctypes.c_double, ctypes.c_double, _D,
+                ctypes.c_int, ctypes.c_int, _D, _D, _I, ctypes.POINTER(ctypes.c_int)]
+            lib.oracle_velocity.restype = None
+            lib.oracle_velocity.argtypes = [ctypes.c_int, ctypes.c_double, _D, _D, _D]
             lib.oracle_run.restype = ctypes.c_int
             lib.oracle_run.argtypes = [
                 ctypes.c_int, _D,
@@ -334,3 +346,90 @@ def contact_candidates_f32(x, inv_mass, centre, radius):
     reach2 = reach * reach
     ok = (np.asarray(inv_mass, dtype=np.float32) > 0) & (d2 < reach2)
     return np.nonzero(ok)[0].astype(np.int32)
+
+
+# ------------------------------------------------- learned warm start (extension)
+@dataclass
+class LearnedResult:
+    x: np.ndarray
+    v: np.ndarray
+    iterations: np.ndarray     # [num_steps][substeps] iterations run
+    residual: np.ndarray       # [num_steps][substeps][2] (RMS, max) after the last iteration
+    early_residual: np.ndarray # [num_steps][substeps] RMS after min_iterations
+
+
+def run_env_learned(mesh: OracleMesh, compliance, params: OracleParams, tool_pos, num_steps,
+                    corrector, min_iterations, max_iterations, threshold, x0=None, v0=None,
+                    nbr=None) -> LearnedResult:
+    """Advance one environment with the learned warm start (see ``warmstart``).
+
+    corrector(x_prev, v, x_hat, nbr) -> [V, 3] correction of the predicted
+    positions (zero rows for pinned particles), or None for the plain solver.
+    Per substep: predict (Alg. 1), add the correction, reset the multipliers,
+    run min_iterations sweeps, evaluate the residual RMS; if it exceeds
+    ``threshold``, run sweeps up to max_iterations; then the velocity update.
+    """
+    from . import warmstart as ws
+    lib = _load()
+    V, E, T = mesh.num_vertices, mesh.num_edges, mesh.num_tets
+    nt = int(params.num_tools)
+    x = _f64(mesh.rest if x0 is None else x0).reshape(V, 3).copy()
+    v = np.zeros((V, 3)) if v0 is None else _f64(v0).reshape(V, 3).copy()
+    tp = _f64(tool_pos).reshape(num_steps, nt, 3) if nt else np.zeros((num_steps, 1, 3))
+    radius = _f64(np.asarray(params.tool_radius[:max(nt, 1)]))
+    grav = _f64(params.gravity)
+    nbr = ws.axis_neighbours(mesh.rest) if nbr is None else nbr
+    eptr, eorder, tptr, torder = (_i32(mesh.edge_ptr), _i32(mesh.edge_order),
+                                  _i32(mesh.tet_ptr), _i32(mesh.tet_order))
+    edges = _i32(mesh.edges if E else np.zeros((1, 2), np.int32))
+    tets = _i32(mesh.tets if T else np.zeros((1, 4), np.int32))
+    rl = _f64(mesh.rest_length if E else np.ones(1))
+    rv = _f64(mesh.rest_volume if T else np.ones(1))
+    h = float(params.dt) / params.substeps
+    atd, atv = float(compliance[0]) / (h * h), float(compliance[1]) / (h * h)
+    lam = np.zeros(max(E + T, 1))
+    cand = np.zeros((max(nt, 1), V), np.int32)
+    ncand = (ctypes.c_int * max(nt, 1))()
+    x_prev = np.zeros((V, 3))
+    its = np.zeros((num_steps, params.substeps), np.int32)
+    res = np.zeros((num_steps, params.substeps, 2))
+    early = np.zeros((num_steps, params.substeps))
+    r2 = np.zeros(2)
+
+    def sweep(centres):
+        lib.oracle_iterate(_dp(x), _dp(mesh.w), E, _ip(edges), _dp(rl), _dp(rv), _ip(tets),
+                           len(eptr) - 1, _ip(eptr), _ip(eorder if eorder.size else np.zeros(1, np.int32)),
+                           len(tptr) - 1, _ip(tptr), _ip(torder if torder.size else np.zeros(1, np.int32)),
+                           atd, atv, _dp(lam), V, nt, _dp(centres), _dp(radius), _ip(cand), ncand)
+
+    def residual():
+        lib.oracle_residual(_dp(x), E, _ip(edges), _dp(rl), T, _ip(tets), _dp(rv), atd, atv,
+                            _dp(lam), _dp(r2))
+        return float(r2[0]), float(r2[1])
+
+    for step in range(num_steps):
+        centres = np.ascontiguousarray(tp[step])
+        for t in range(nt):
+            row = np.ascontiguousarray(cand[t])
+            ncand[t] = lib.oracle_candidates(V, _dp(mesh.w), _dp(x), _dp(np.ascontiguousarray(centres[t])),
+                                             float(radius[t]), _ip(row))
+            cand[t] = row
+        for sub in range(params.substeps):
+            v_start = v.copy()
+            lib.oracle_predict(V, _dp(mesh.w), h, _dp(grav), _dp(x), _dp(v), _dp(x_prev))
+            if corrector is not None:
+                x += corrector(x_prev, v_start, x, nbr)
+            lam[:] = 0.0
+            n_it = 0
+            for _ in range(min_iterations):
+                sweep(centres)
+                n_it += 1
+            early[step, sub] = residual()[0]
+            if early[step, sub] > threshold:
+                while n_it < max_iterations:
+                    sweep(centres)
+                    n_it += 1
+            its[step, sub] = n_it
+            res[step, sub] = residual()
+            lib.oracle_velocity(V, h, _dp(x), _dp(x_prev), _dp(v))
+    return LearnedResult(x, v, its, res, early)

@@ -406,6 +406,85 @@ void oracle_residual(const double *x, int E, const int32_t *edges, const double 
 }
 
 /*
+ * Contact candidates of one sphere (R6): ascending ids i with w_i > 0 and
+ * |x_i - c|^2 < (2r)^2 on the positions x; returns their number.
+ */
+int oracle_candidates(int V, const double *w, const double *x, const double *centre,
+                      double radius, int32_t *out)
+{
+    double reach = 2.0 * radius;
+    int n = 0;
+    for (int i = 0; i < V; ++i) {
+        double d[3];
+        sub3(x + 3 * i, centre, d);
+        if (w[i] > 0.0 && dot3(d, d) < reach * reach)
+            out[n++] = i;
+    }
+    return n;
+}
+
+/*
+ * Prediction of one substep (Alg. 1): x_prev = x; for free particles
+ * v += h g and x += h v; pinned particles stay (R5).
+ */
+void oracle_predict(int V, const double *w, double h, const double *gravity, double *x,
+                    double *v, double *x_prev)
+{
+    for (int i = 0; i < V; ++i) {
+        for (int k = 0; k < 3; ++k)
+            x_prev[3 * i + k] = x[3 * i + k];
+        if (w[i] > 0.0)
+            for (int k = 0; k < 3; ++k) {
+                v[3 * i + k] += h * gravity[k];
+                x[3 * i + k] += h * v[3 * i + k];
+            }
+    }
+}
+
+/*
+ * One Gauss-Seidel iteration (R1): every edge colour in ascending order, every
+ * tetrahedron colour in ascending order, then the push-out of every tool's
+ * candidates (Sec. III-A.3).  candidates: [num_tools][V] ids, counts [num_tools].
+ */
+void oracle_iterate(double *x, const double *w,
+                    int E, const int32_t *edges, const double *rest_length,
+                    const double *rest_volume, const int32_t *tets,
+                    int num_edge_colours, const int32_t *edge_colour_ptr, const int32_t *edge_order,
+                    int num_tet_colours, const int32_t *tet_colour_ptr, const int32_t *tet_order,
+                    double alpha_tilde_d, double alpha_tilde_v, double *lambda,
+                    int V, int num_tools, const double *centres, const double *tool_radius,
+                    const int32_t *candidates, const int *num_candidates)
+{
+    /* distance constraints, colour by colour (Eq. 1, R1) */
+    for (int c = 0; c < num_edge_colours; ++c)
+        for (int p = edge_colour_ptr[c]; p < edge_colour_ptr[c + 1]; ++p) {
+            int e = edge_order[p];
+            oracle_project_distance(x, w, edges[2 * e], edges[2 * e + 1], rest_length[e],
+                                    alpha_tilde_d, &lambda[e]);
+        }
+    /* volume constraints, colour by colour (Eqs. 2-3, R1-R3) */
+    for (int c = 0; c < num_tet_colours; ++c)
+        for (int p = tet_colour_ptr[c]; p < tet_colour_ptr[c + 1]; ++p) {
+            int t = tet_order[p];
+            oracle_project_volume(x, w, tets + 4 * t, rest_volume[t], alpha_tilde_v,
+                                  &lambda[E + t]);
+        }
+    /* tool contact after the deformation constraints (Sec. III-A.3) */
+    for (int t = 0; t < num_tools; ++t)
+        for (int n = 0; n < num_candidates[t]; ++n) {
+            int i = candidates[(size_t)t * V + n];
+            oracle_project_contact(x + 3 * i, centres + 3 * t, tool_radius[t]);
+        }
+}
+
+/* Velocity update of one substep (Alg. 1): v = (x - x_prev) / h. */
+void oracle_velocity(int V, double h, const double *x, const double *x_prev, double *v)
+{
+    for (int i = 0; i < 3 * V; ++i)
+        v[i] = (x[i] - x_prev[i]) / h;
+}
+
+/*
  * Advance one environment by num_steps steps.
  *
  * Mesh: V particles with inverse masses w; E edges [E][2] with rest lengths;
@@ -460,15 +539,8 @@ int oracle_run(int V, const double *w,
         /* evaluate instrument state and the contact candidates (R6) */
         const double *centres = tool_pos + (size_t)step * num_tools * 3;
         for (int t = 0; t < num_tools; ++t) {
-            const double *c = centres + 3 * t;
-            double reach = 2.0 * tool_radius[t];
-            int n = 0;
-            for (int i = 0; i < V; ++i) {
-                double d[3];
-                sub3(x + 3 * i, c, d);
-                if (w[i] > 0.0 && dot3(d, d) < reach * reach)
-                    candidates[(size_t)t * V + n++] = i;
-            }
+            int n = oracle_candidates(V, w, x, centres + 3 * t, tool_radius[t],
+                                      candidates + (size_t)t * V);
             num_candidates[t] = n;
             if (contacts) {
                 int32_t *row = contacts + ((size_t)step * num_tools + t) * V;
@@ -480,50 +552,20 @@ int oracle_run(int V, const double *w,
         }
 
         for (int sub = 0; sub < substeps; ++sub) {
-            /* predict velocity and position (Alg. 1); pinned particles stay (R5) */
-            for (int i = 0; i < V; ++i) {
-                for (int k = 0; k < 3; ++k)
-                    x_prev[3 * i + k] = x[3 * i + k];
-                if (w[i] > 0.0)
-                    for (int k = 0; k < 3; ++k) {
-                        v[3 * i + k] += h * gravity[k];
-                        x[3 * i + k] += h * v[3 * i + k];
-                    }
-            }
-            for (int j = 0; j < E + T; ++j)                 /* R4 */
+            oracle_predict(V, w, h, gravity, x, v, x_prev);   /* Alg. 1, R5 */
+            for (int j = 0; j < E + T; ++j)                  /* R4 */
                 lambda[j] = 0.0;
-
-            for (int it = 0; it < iterations; ++it) {
-                /* distance constraints, colour by colour (Eq. 1, R1) */
-                for (int c = 0; c < num_edge_colours; ++c)
-                    for (int p = edge_colour_ptr[c]; p < edge_colour_ptr[c + 1]; ++p) {
-                        int e = edge_order[p];
-                        oracle_project_distance(x, w, edges[2 * e], edges[2 * e + 1],
-                                                rest_length[e], alpha_tilde_d, &lambda[e]);
-                    }
-                /* volume constraints, colour by colour (Eqs. 2-3, R1-R3) */
-                for (int c = 0; c < num_tet_colours; ++c)
-                    for (int p = tet_colour_ptr[c]; p < tet_colour_ptr[c + 1]; ++p) {
-                        int t = tet_order[p];
-                        oracle_project_volume(x, w, tets + 4 * t, rest_volume[t],
-                                              alpha_tilde_v, &lambda[E + t]);
-                    }
-                /* tool contact after the deformation constraints (Sec. III-A.3) */
-                for (int t = 0; t < num_tools; ++t)
-                    for (int n = 0; n < num_candidates[t]; ++n) {
-                        int i = candidates[(size_t)t * V + n];
-                        oracle_project_contact(x + 3 * i, centres + 3 * t, tool_radius[t]);
-                    }
-            }
-
+            for (int it = 0; it < iterations; ++it)
+                oracle_iterate(x, w, E, edges, rest_length, rest_volume, tets,
+                               num_edge_colours, edge_colour_ptr, edge_order,
+                               num_tet_colours, tet_colour_ptr, tet_order,
+                               alpha_tilde_d, alpha_tilde_v, lambda,
+                               V, num_tools, centres, tool_radius, candidates, num_candidates);
             if (residual)
                 oracle_residual(x, E, edges, rest_length, T, tets, rest_volume,
                                 alpha_tilde_d, alpha_tilde_v, lambda,
                                 residual + 2 * ((size_t)step * substeps + sub));
-
-            /* velocity update v = (x - x_prev) / h (Alg. 1) */
-            for (int i = 0; i < 3 * V; ++i)
-                v[i] = (x[i] - x_prev[i]) / h;
+            oracle_velocity(V, h, x, x_prev, v);              /* Alg. 1 */
         }
     }
     if (lambda_out)

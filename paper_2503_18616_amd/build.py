@@ -16,7 +16,7 @@ LIB = os.path.join(PKG, "libxpbd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["xpbd_kernels.hip", "xpbd_runtime.hip"]
+HIP_SOURCES = ["xpbd_kernels.hip", "xpbd_runtime.hip", "mlp_kernels.hip", "learned_runtime.hip"]
 CXX_SOURCES = ["mesh_setup.cpp"]
 
 # Packed FP32 instructions are kept out of every kernel.  The promotion budget
@@ -47,7 +47,8 @@ def _check_register_kernels(remarks: str):
         m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
         if m and name:
             scratch[name] = int(m.group(1))
-    reg = {n: v for n, v in scratch.items() if "xpbd_step_reg_kernel" in n}
+    reg = {n: v for n, v in scratch.items()
+           if "xpbd_step_reg_kernel" in n or "xpbd_substep_reg_kernel" in n}
     if not reg:
         raise RuntimeError("no resource-usage remarks for the register-variant kernels")
     bad = {n: v for n, v in reg.items() if v > MAX_REG_KERNEL_SCRATCH}

@@ -1,0 +1,83 @@
+// The batch object behind the C ABI's xpbd_batch handle (host side), shared
+// by the runtime sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/xpbd.h"
+#include "mesh_setup.h"
+#include "runtime_util.h"
+#include "xpbd_device.h"
+
+struct xpbd_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    xpbd_params params{};
+    int32_t num_envs = 0;
+    int32_t total_particles = 0;
+    int32_t total_lambda = 0;
+    int block = 64;
+    int particles_per_thread = 1;
+    bool stage_topology = false;
+    bool register_variant = false;
+    int lambda_banks = 1;
+    int envs_per_group = 1;
+    int32_t num_groups = 0;
+    int32_t *groups_dev = nullptr;
+    uint32_t lds_bytes = 0;
+    std::vector<xpbd::PreparedMesh> meshes;
+    std::vector<int32_t> env_mesh;
+    std::vector<int32_t> env_offsets;       // [N+1]
+    std::vector<int32_t> colours;           // concatenated per mesh: edges then tets
+    std::vector<xpbd::DeviceBuffer> allocations;
+    float *pos = nullptr, *vel = nullptr, *lambda = nullptr, *residual = nullptr;
+    float *compliance = nullptr;
+    int32_t *contacts = nullptr, *contact_counts = nullptr, *nonfinite = nullptr;
+    xpbd::MeshDev *meshes_dev = nullptr;
+    xpbd::EnvDev *envs_dev = nullptr;
+    float *staging = nullptr;                // [sum V][3] for AoS <-> SoA and host tool poses
+    size_t staging_bytes = 0;
+    float *tool_staging = nullptr;
+    size_t tool_staging_bytes = 0;
+    bool residual_valid = false;   // a step has computed the residual
+    // learned warm start workspace (allocated on first use)
+    float *learned_xhat = nullptr;           // [3][total particles]
+    uint8_t *learned_cand = nullptr;         // [total particles]
+    uint16_t *learned_feat = nullptr;        // [total particles][32]
+    int32_t max_vertices = 0;
+
+    ~xpbd_batch()
+    {
+        (void)hipStreamSynchronize(stream);
+        for (auto &a : allocations)
+            (void)hipFree(a.ptr);
+        if (tool_staging)
+            (void)hipFree(tool_staging);
+    }
+
+    xpbd_status alloc(void **out, size_t bytes)
+    {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+        if (e != hipSuccess)
+            return xpbd::fail(XPBD_E_HIP, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        allocations.push_back({p, bytes});
+        *out = p;
+        return XPBD_OK;
+    }
+
+    template <typename T>
+    xpbd_status upload(T **out, const std::vector<T> &host)
+    {
+        xpbd_status s = alloc(reinterpret_cast<void **>(out), host.size() * sizeof(T));
+        if (s != XPBD_OK)
+            return s;
+        if (!host.empty())  // blocking: the host vectors are temporaries of creation
+            HIP_TRY(hipMemcpy(*out, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice));
+        return XPBD_OK;
+    }
+};
+

@@ -1,0 +1,345 @@
+// Host runtime of the learned warm start: the C ABI declared in
+// include/xpbd_learned.h (network objects, training steps, and the
+// one-substep-per-launch stepping of a batch with the network's correction).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/xpbd_learned.h"
+#include "batch.h"
+#include "mesh_setup.h"
+#include "mlp_device.h"
+#include "runtime_util.h"
+#include "xpbd_device.h"
+
+using xpbd::fail;
+using xpbd::g_error;
+using xpbd::is_device_pointer;
+
+static_assert(XPBD_MLP_PARAMS == xpbd::kMlpParams, "parameter count");
+static_assert(XPBD_MLP_FEATURE_STRIDE == xpbd::kMlpFeatPad, "feature row width");
+
+struct xpbd_mlp {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    xpbd::MlpDev d{};
+    float *in_scale = nullptr;               // device [32]
+    std::vector<xpbd::DeviceBuffer> allocations;
+    float *partial = nullptr;                // [groups][params] training scratch
+    float *stats = nullptr;                  // [groups][2]
+    float *loss = nullptr;                   // [1]
+    int partial_groups = 0;
+    int adam_step = 0;
+
+    ~xpbd_mlp()
+    {
+        (void)hipStreamSynchronize(stream);
+        for (auto &a : allocations)
+            (void)hipFree(a.ptr);
+        if (partial)
+            (void)hipFree(partial);
+        if (stats)
+            (void)hipFree(stats);
+    }
+
+    template <typename T>
+    xpbd_status zeros(T **out, size_t count)
+    {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, std::max<size_t>(count * sizeof(T), 16));
+        if (e != hipSuccess)
+            return fail(XPBD_E_HIP, "hipMalloc failed: %s", hipGetErrorString(e));
+        allocations.push_back({p, count * sizeof(T)});
+        HIP_TRY(hipMemset(p, 0, std::max<size_t>(count * sizeof(T), 16)));
+        *out = static_cast<T *>(p);
+        return XPBD_OK;
+    }
+};
+
+namespace {
+
+xpbd_status upload_params(xpbd_mlp *net, const float *params)
+{
+    std::vector<float> host(xpbd::kMlpParams, 0.0f);
+    if (params)
+        std::memcpy(host.data(), params, sizeof(float) * xpbd::kMlpParams);
+    for (float v : host)
+        if (!std::isfinite(v))
+            return fail(XPBD_E_ARG, "network parameters must be finite");
+    HIP_TRY(hipMemcpy(net->d.master, host.data(), sizeof(float) * xpbd::kMlpParams,
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(net->d.adam_m, 0, sizeof(float) * xpbd::kMlpParams));
+    HIP_TRY(hipMemset(net->d.adam_v, 0, sizeof(float) * xpbd::kMlpParams));
+    net->adam_step = 0;
+    HIP_TRY(xpbd::launch_mlp_sync(net->d, net->stream));
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    return XPBD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+xpbd_status xpbd_mlp_create(const float *params, const float *in_scale, const float *out_scale,
+                            void *hip_stream, xpbd_mlp **out)
+{
+    g_error.clear();
+    if (!out)
+        return fail(XPBD_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!in_scale || !out_scale)
+        return fail(XPBD_E_ARG, "in_scale and out_scale are required");
+    for (int k = 0; k < XPBD_MLP_FEATURES; ++k)
+        if (!std::isfinite(in_scale[k]))
+            return fail(XPBD_E_ARG, "in_scale[%d] is not finite", k);
+    for (int k = 0; k < XPBD_MLP_OUTPUTS; ++k)
+        if (!(std::isfinite(out_scale[k]) && out_scale[k] > 0.0f))
+            return fail(XPBD_E_ARG, "out_scale[%d] must be finite and > 0", k);
+    auto *net = new xpbd_mlp();
+    net->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    auto cleanup = [&](xpbd_status st) {
+        delete net;
+        return st;
+    };
+    xpbd_status st;
+    if (hipGetDevice(&net->device) != hipSuccess)
+        return cleanup(fail(XPBD_E_HIP, "no HIP device"));
+    xpbd::MlpDev &d = net->d;
+    if ((st = net->zeros(&d.master, xpbd::kMlpParams)) || (st = net->zeros(&d.adam_m, xpbd::kMlpParams)) ||
+        (st = net->zeros(&d.adam_v, xpbd::kMlpParams)) ||
+        (st = net->zeros(&d.w1, (size_t)xpbd::kMlpHidden * xpbd::kMlpFeatPad)) ||
+        (st = net->zeros(&d.w2, (size_t)xpbd::kMlpHidden * xpbd::kMlpHidden)) ||
+        (st = net->zeros(&d.w2t, (size_t)xpbd::kMlpHidden * xpbd::kMlpHidden)) ||
+        (st = net->zeros(&d.w3, (size_t)16 * xpbd::kMlpHidden)) ||
+        (st = net->zeros(&d.w3t, (size_t)xpbd::kMlpHidden * 32)) ||
+        (st = net->zeros(&d.b1, xpbd::kMlpHidden)) || (st = net->zeros(&d.b2, xpbd::kMlpHidden)) ||
+        (st = net->zeros(&d.b3, 4)) || (st = net->zeros(&d.out_scale, 4)) ||
+        (st = net->zeros(&net->in_scale, 32)) || (st = net->zeros(&net->loss, 1)))
+        return cleanup(st);
+    float in32[32] = {0.0f}, out4[4] = {0.0f};
+    std::memcpy(in32, in_scale, sizeof(float) * XPBD_MLP_FEATURES);
+    std::memcpy(out4, out_scale, sizeof(float) * XPBD_MLP_OUTPUTS);
+    if (hipMemcpy(net->in_scale, in32, sizeof in32, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d.out_scale, out4, sizeof out4, hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(XPBD_E_HIP, "upload of the scales failed"));
+    if ((st = upload_params(net, params)))
+        return cleanup(st);
+    *out = net;
+    return XPBD_OK;
+}
+
+xpbd_status xpbd_mlp_get_params(xpbd_mlp *net, float *params)
+{
+    g_error.clear();
+    if (!net || !params)
+        return fail(XPBD_E_ARG, "net and params are required");
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    HIP_TRY(hipMemcpy(params, net->d.master, sizeof(float) * xpbd::kMlpParams,
+                      hipMemcpyDeviceToHost));
+    return XPBD_OK;
+}
+
+xpbd_status xpbd_mlp_set_params(xpbd_mlp *net, const float *params)
+{
+    g_error.clear();
+    if (!net || !params)
+        return fail(XPBD_E_ARG, "net and params are required");
+    HIP_TRY(hipStreamSynchronize(net->stream));
+    return upload_params(net, params);
+}
+
+xpbd_status xpbd_mlp_forward(xpbd_mlp *net, const uint16_t *features, int32_t n, float *y)
+{
+    g_error.clear();
+    if (!net || !features || !y || n < 1)
+        return fail(XPBD_E_ARG, "net, features, y and n >= 1 are required");
+    if (!is_device_pointer(features) || !is_device_pointer(y))
+        return fail(XPBD_E_ARG, "features and y must be device memory");
+    HIP_TRY(xpbd::launch_mlp_forward(net->d, features, n, y, nullptr, 0, net->stream));
+    return XPBD_OK;
+}
+
+xpbd_status xpbd_mlp_train_step(xpbd_mlp *net, const uint16_t *features, const float *targets,
+                                int32_t n, float learning_rate, float *loss, float *grad)
+{
+    g_error.clear();
+    if (!net || !features || !targets || n < 1)
+        return fail(XPBD_E_ARG, "net, features, targets and n >= 1 are required");
+    if (!(std::isfinite(learning_rate) && learning_rate >= 0.0f))
+        return fail(XPBD_E_ARG, "learning_rate must be finite and >= 0");
+    if (!is_device_pointer(features) || !is_device_pointer(targets) ||
+        (grad && !is_device_pointer(grad)))
+        return fail(XPBD_E_ARG, "features, targets and grad must be device memory");
+    const int groups = (n + xpbd::kMlpTile - 1) / xpbd::kMlpTile;
+    if (groups > net->partial_groups) {
+        HIP_TRY(hipStreamSynchronize(net->stream));
+        if (net->partial)
+            HIP_TRY(hipFree(net->partial));
+        if (net->stats)
+            HIP_TRY(hipFree(net->stats));
+        net->partial = nullptr;
+        net->stats = nullptr;
+        net->partial_groups = 0;
+        HIP_TRY(hipMalloc(&net->partial, sizeof(float) * (size_t)groups * xpbd::kMlpParams));
+        HIP_TRY(hipMalloc(&net->stats, sizeof(float) * 2 * (size_t)groups));
+        net->partial_groups = groups;
+    }
+    int step = net->adam_step;
+    if (learning_rate > 0.0f)
+        step = ++net->adam_step;
+    HIP_TRY(xpbd::launch_mlp_train(net->d, features, targets, n, net->partial, net->stats,
+                                   learning_rate, 0.9f, 0.999f, 1e-8f, step, grad, net->loss,
+                                   net->stream));
+    if (loss) {
+        HIP_TRY(hipMemcpyAsync(loss, net->loss, sizeof(float), hipMemcpyDeviceToHost, net->stream));
+        HIP_TRY(hipStreamSynchronize(net->stream));
+    }
+    return XPBD_OK;
+}
+
+void xpbd_mlp_destroy(xpbd_mlp *net) { delete net; }
+
+xpbd_status xpbd_axis_neighbours(const xpbd_mesh *mesh, int32_t *out)
+{
+    g_error.clear();
+    if (!mesh || !out || !mesh->rest_pos || mesh->num_vertices < 1)
+        return fail(XPBD_E_ARG, "mesh with rest positions and out are required");
+    std::vector<int32_t> nbr;
+    xpbd::axis_neighbours(mesh->num_vertices, mesh->rest_pos, nbr);
+    std::memcpy(out, nbr.data(), sizeof(int32_t) * nbr.size());
+    return XPBD_OK;
+}
+
+xpbd_status xpbd_step_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_steps,
+                              const float *tool_pos, const xpbd_learned_params *lp)
+{
+    g_error.clear();
+    if (!b || !lp)
+        return fail(XPBD_E_ARG, "batch and params are required");
+    if (num_steps < 0)
+        return fail(XPBD_E_ARG, "num_steps must be >= 0");
+    if (!b->register_variant || b->envs_per_group != 1)
+        return fail(XPBD_E_CAPACITY, "the learned step needs the register variant with one "
+                    "environment per workgroup");
+    if (lp->min_iterations < 0 || lp->max_iterations < lp->min_iterations)
+        return fail(XPBD_E_ARG, "need 0 <= min_iterations <= max_iterations");
+    if (!std::isfinite(lp->threshold) && !std::isinf(lp->threshold))
+        return fail(XPBD_E_ARG, "threshold must not be NaN");
+    const bool record = lp->record_substep >= 0;
+    if ((lp->apply_correction || record) && !net)
+        return fail(XPBD_E_ARG, "the correction and the recording need a network");
+    if (record && (lp->record_substep >= b->params.substeps || !lp->record_features ||
+                   !lp->record_targets || !is_device_pointer(lp->record_features) ||
+                   !is_device_pointer(lp->record_targets)))
+        return fail(XPBD_E_ARG, "record_substep must name a substep and both record buffers "
+                    "must be device memory");
+    if (lp->iterations && !is_device_pointer(lp->iterations))
+        return fail(XPBD_E_ARG, "iterations must be device memory");
+    if (num_steps == 0)
+        return XPBD_OK;
+    const int tools = b->params.num_tools;
+    const int64_t NP = b->total_particles;
+    const float *tools_dev = nullptr;
+    if (tools > 0) {
+        if (!tool_pos)
+            return fail(XPBD_E_ARG, "tool_pos is NULL but the batch has %d tools", tools);
+        const size_t bytes = (size_t)num_steps * b->num_envs * tools * 3 * sizeof(float);
+        if (is_device_pointer(tool_pos)) {
+            tools_dev = tool_pos;
+        } else {
+            if (b->tool_staging_bytes < bytes) {
+                if (b->tool_staging)
+                    HIP_TRY(hipFree(b->tool_staging));
+                b->tool_staging = nullptr;
+                b->tool_staging_bytes = 0;
+                HIP_TRY(hipMalloc(&b->tool_staging, bytes));
+                b->tool_staging_bytes = bytes;
+            }
+            HIP_TRY(hipMemcpyAsync(b->tool_staging, tool_pos, bytes, hipMemcpyHostToDevice,
+                                   b->stream));
+            HIP_TRY(hipStreamSynchronize(b->stream));
+            tools_dev = b->tool_staging;
+        }
+    }
+    xpbd_status st;
+    if (!b->learned_xhat && ((st = b->alloc(reinterpret_cast<void **>(&b->learned_xhat),
+                                            sizeof(float) * 3 * (size_t)NP)) ||
+                             (st = b->alloc(reinterpret_cast<void **>(&b->learned_cand),
+                                            (size_t)NP))))
+        return st;
+    if (net && !b->learned_feat &&
+        (st = b->alloc(reinterpret_cast<void **>(&b->learned_feat),
+                       sizeof(uint16_t) * 32 * (size_t)NP)))
+        return st;
+
+    xpbd::StepArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.meshes = b->meshes_dev;
+    a.envs = b->envs_dev;
+    a.groups = b->groups_dev;
+    a.num_groups = b->num_groups;
+    a.compliance = b->compliance;
+    a.tool_pos = tools_dev;
+    a.pos = b->pos;
+    a.vel = b->vel;
+    a.contacts = b->contacts;
+    a.contact_counts = b->contact_counts;
+    a.residual = b->residual;
+    a.nonfinite = b->nonfinite;
+    a.num_envs = b->num_envs;
+    a.total_particles = b->total_particles;
+    a.num_steps = num_steps;
+    a.substeps = b->params.substeps;
+    a.iterations = b->params.iterations;
+    a.num_tools = tools;
+    const double h = (double)b->params.dt / (double)b->params.substeps;
+    a.h = (float)h;
+    a.inv_h = (float)(1.0 / h);
+    for (int k = 0; k < 3; ++k)
+        a.gravity[k] = b->params.gravity[k];
+    for (int t = 0; t < tools; ++t) {
+        const float r = b->params.tool_radius[t];
+        a.tool_radius[t] = r;
+        a.tool_radius2[t] = r * r;
+        const float reach = 2.0f * r;
+        a.tool_reach2[t] = reach * reach;
+    }
+    xpbd::LearnedArgs L;
+    std::memset(&L, 0, sizeof L);
+    L.xhat = b->learned_xhat;
+    L.cand = b->learned_cand;
+    L.in_scale = net ? net->in_scale : nullptr;
+    L.out_scale = net ? net->d.out_scale : nullptr;
+    L.threshold = lp->threshold;
+    L.min_iterations = lp->min_iterations;
+    L.max_iterations = lp->max_iterations;
+    L.max_vertices = b->max_vertices;
+    const bool resid = (b->params.flags & XPBD_F_RESIDUAL) != 0;
+    const bool want_lambda = (b->params.flags & XPBD_F_LAMBDA) || resid;
+    const int S = b->params.substeps;
+    for (int step = 0; step < num_steps; ++step)
+        for (int sub = 0; sub < S; ++sub) {
+            const bool last = step == num_steps - 1 && sub == S - 1;
+            const bool rec = record && sub == lp->record_substep;
+            L.first_substep = sub == 0;
+            L.step = step;
+            L.features = rec ? lp->record_features : (net ? b->learned_feat : nullptr);
+            L.record_targets = rec ? lp->record_targets : nullptr;
+            L.iterations = lp->iterations ? lp->iterations + ((size_t)step * S + sub) * b->num_envs
+                                          : nullptr;
+            a.lambda_out = last && want_lambda ? b->lambda : nullptr;
+            HIP_TRY(xpbd::launch_learned_predict(a, L, b->stream));
+            if (lp->apply_correction)
+                HIP_TRY(xpbd::launch_mlp_forward(net->d, L.features, (int)NP, nullptr, L.xhat, NP,
+                                                 b->stream));
+            HIP_TRY(xpbd::launch_substep_reg(a, L, b->block, b->lambda_banks, b->lds_bytes,
+                                             last && resid, b->stream));
+        }
+    b->residual_valid = b->residual_valid || resid;
+    return XPBD_OK;
+}
+
+}  // extern "C"

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <numeric>
 #include <random>
 
 #include "../../include/xpbd.h"
@@ -589,6 +590,50 @@ int64_t lane_conflicts(const int32_t *slots, int32_t k, const std::vector<int32_
                     extra += top - 1;
                 }
     return extra;
+}
+
+void axis_neighbours(int32_t num_vertices, const float *rest_pos, std::vector<int32_t> &out)
+{
+    const size_t V = (size_t)std::max(num_vertices, 0);
+    out.assign(V * 6, -1);
+    std::vector<int32_t> ids(V);
+    for (int axis = 0; axis < 3; ++axis) {
+        const int o1 = (axis + 1) % 3, o2 = (axis + 2) % 3;
+        auto c = [&](int32_t i, int k) { return rest_pos[3 * (size_t)i + k]; };
+        std::iota(ids.begin(), ids.end(), 0);
+        std::sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) {
+            if (c(a, o1) != c(b, o1))
+                return c(a, o1) < c(b, o1);
+            if (c(a, o2) != c(b, o2))
+                return c(a, o2) < c(b, o2);
+            if (c(a, axis) != c(b, axis))
+                return c(a, axis) < c(b, axis);
+            return a < b;
+        });
+        // runs of equal (o1, o2); inside a run, blocks of equal coordinate along the axis
+        size_t r = 0;
+        while (r < V) {
+            size_t e = r;
+            while (e < V && c(ids[e], o1) == c(ids[r], o1) && c(ids[e], o2) == c(ids[r], o2))
+                ++e;
+            size_t prev_block = V;   // first index of the previous block
+            size_t b = r;
+            while (b < e) {
+                size_t nb = b;
+                while (nb < e && c(ids[nb], axis) == c(ids[b], axis))
+                    ++nb;
+                for (size_t k = b; k < nb; ++k) {
+                    if (prev_block != V)
+                        out[(size_t)ids[k] * 6 + 2 * axis] = ids[prev_block];
+                    if (nb < e)
+                        out[(size_t)ids[k] * 6 + 2 * axis + 1] = ids[nb];
+                }
+                prev_block = b;
+                b = nb;
+            }
+            r = e;
+        }
+    }
 }
 
 int prepare_mesh(int32_t num_vertices, int32_t num_tets, const float *rest_pos,

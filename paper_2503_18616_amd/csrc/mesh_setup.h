@@ -47,6 +47,13 @@ int32_t greedy_colouring(int32_t num_vertices, int32_t n, int32_t k, const int32
 void pack_colours(const int32_t *ids, int32_t k, const std::vector<int32_t> &ptr, int32_t group,
                   int32_t modulus, std::vector<int32_t> &slot_id);
 
+// Axis neighbours of every particle, for the learned warm start's features:
+// in direction d = -x, +x, -y, +y, -z, +z the particle whose rest coordinates
+// on the other two axes equal particle i's and whose rest coordinate along
+// the axis is the nearest one beyond X_i on that side (the smallest id among
+// equals), or -1.  out: [V][6].
+void axis_neighbours(int32_t num_vertices, const float *rest_pos, std::vector<int32_t> &out);
+
 // Even permutations of the vertices of a constraint: the edge update is
 // symmetric in its two particles and the volume update is invariant under the
 // even permutations of its four (they keep the orientation), so a record may

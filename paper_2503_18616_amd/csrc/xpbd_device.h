@@ -26,19 +26,20 @@ struct MeshDev {
     const int32_t *edge_id;      // [E]  constraint id of each schedule slot
     const int32_t *tet_id;       // [T]
     const float *inv_mass;       // [V]
-    // constraint records in slot order (pairs and quads name LDS slots)
-    const uint2 *edge_rec;       // [E]  (pair, rest length bits), slot order
-    const uint4 *tet_rec;        // [T]  (a | b << 16, c | d << 16, rest volume bits, 0)
-    // particle placement of the register-multiplier kernel: mesh id i lives in
-    // LDS slot slot_of[i]; its records name slots
-    const uint16_t *slot_of;     // [V]
-    const uint16_t *id_of;       // [V]  inverse of slot_of
+    const float *rest_pos;       // [V][3] (learned warm start's features)
+    const int32_t *nbr;          // [V][6] axis neighbours -x, +x, -y, +y, -z, +z, -1 for none
+    // particle placement of the register-multiplier kernel for a group of G
+    // environments: particle i of the group's e-th environment (group id
+    // e V + i) lives in LDS slot slot_of[e V + i]; records name slots
+    const uint16_t *slot_of;     // [G V]
+    const uint16_t *id_of;       // [G V]  inverse of slot_of
     // round-major records of the register-multiplier kernel: the record of
     // lane l in round r sits at [r][l]; edge (pair, rest length bits, 0),
-    // tet (ab, cd, rest volume bits); lanes without a constraint hold
+    // tet (ab, cd, rest volume bits); the top two bits of the first word hold
+    // the environment index within the group; lanes without a constraint hold
     // kInvalidRecord in the first word
     const uint32_t *round_rec;   // [padded rounds][block][3]
-    const int32_t *rr_id;        // [padded rounds][block] constraint id (tets: E + id), -1
+    const int32_t *rr_id;        // [padded rounds][block] e << 24 | constraint id (tets: E + id), -1
     uint64_t wave_active[16];    // bit r: wave w has a constraint in round r
     uint64_t tet_mask;           // bit r: round r projects tetrahedra
     uint64_t barrier_mask;       // bit r: a workgroup barrier follows round r
@@ -66,6 +67,8 @@ struct EnvDev {
 struct StepArgs {
     const MeshDev *meshes;
     const EnvDev *envs;
+    const int32_t *groups;       // register variant: [num_groups][G] env ids, ~env = filler
+    int32_t num_groups;
     const float *compliance;     // [N][2] (edge, tet)
     const float *tool_pos;       // [num_steps][N][num_tools][3]
     float *pos;                  // [3][total_particles]  SoA
@@ -87,6 +90,24 @@ struct StepArgs {
     float tool_radius[2];
     float tool_radius2[2];       // r^2
     float tool_reach2[2];        // (2r)^2, rounded to float
+};
+
+// Arguments of the learned warm start's per-substep kernels (one substep per
+// launch; see include/xpbd_learned.h).
+struct LearnedArgs {
+    float *xhat;                 // [3][total particles] predicted (then corrected) positions
+    uint16_t *features;          // [total particles][32] bfloat16 scaled features, [31] = free flag
+    uint8_t *cand;               // [total particles] bit t: candidate of tool t in this step
+    const float *in_scale;       // [32]
+    const float *out_scale;      // [4]
+    float *record_targets;       // [total particles][4] (x - x_hat) / out_scale, or null
+    int32_t *iterations;         // [N] sweeps run in this substep, or null
+    float threshold;             // residual RMS above which the sweeps continue
+    int32_t min_iterations;
+    int32_t max_iterations;
+    int32_t first_substep;       // 1: find the contact candidates on the start-of-step positions
+    int32_t step;                // row of tool_pos used by this substep
+    int32_t max_vertices;
 };
 
 // Per-workgroup LDS layout for an environment of a given mesh.
@@ -137,14 +158,20 @@ __host__ __device__ inline LdsLayout lds_layout(int32_t V, int32_t E, int32_t T,
 hipError_t launch_step(const StepArgs &args, int block, int particles_per_thread,
                        bool stage_topology, uint32_t lds_bytes, bool want_residual,
                        hipStream_t stream);
-// LDS layout of the register-multiplier kernel for an environment of V particles.
+// LDS layout of the register-multiplier kernel for a group holding V particles
+// in all.  Scratch: words 0..15 per-wave counts, 32..95 flags of the
+// workgroup-wide OR (16 per environment), bytes kRegScratchTools.. the sphere
+// centres of the group's environments (float4 [G][2]).
 struct RegLdsLayout {
     uint32_t xw;       // float4 [V]  position + inverse mass
     uint32_t vel;      // float [3][V]
     uint32_t prev;     // float [3][V]  positions at the start of the substep
-    uint32_t scratch;  // 64 x uint32
+    uint32_t scratch;  // 512 bytes
     uint32_t total;
 };
+
+constexpr uint32_t kRegScratchTools = 384;
+constexpr int kMaxEnvsPerGroup = 2;
 
 __host__ __device__ inline RegLdsLayout reg_lds_layout(int32_t V)
 {
@@ -153,13 +180,21 @@ __host__ __device__ inline RegLdsLayout reg_lds_layout(int32_t V)
     l.vel = 16u * (uint32_t)V;
     l.prev = l.vel + 12u * (uint32_t)V;
     l.scratch = align_up(l.prev + 12u * (uint32_t)V, 16);
-    l.total = l.scratch + 256u;
+    l.total = l.scratch + 512u;
     return l;
 }
 
-// Register-multiplier kernel; lambda_banks = ceil(rounds / 32) in {1, 2}.
-hipError_t launch_step_reg(const StepArgs &args, int block, int lambda_banks, uint32_t lds_bytes,
-                           bool want_residual, hipStream_t stream);
+// Register-multiplier kernel; lambda_banks = ceil(rounds / 32) in {1, 2},
+// envs_per_group in {1, 2}; one workgroup per group.
+hipError_t launch_step_reg(const StepArgs &args, int block, int lambda_banks, int envs_per_group,
+                           uint32_t lds_bytes, bool want_residual, hipStream_t stream);
+// Learned warm start: prediction + features of one substep (every particle of
+// every environment), then one substep of the register-multiplier solver
+// starting from the predicted (and corrected) positions.
+hipError_t launch_learned_predict(const StepArgs &args, const LearnedArgs &largs, hipStream_t stream);
+hipError_t launch_substep_reg(const StepArgs &args, const LearnedArgs &largs, int block,
+                              int lambda_banks, uint32_t lds_bytes, bool want_residual,
+                              hipStream_t stream);
 hipError_t launch_soa_to_aos(const float *soa, float *aos, int32_t n, hipStream_t stream);
 hipError_t launch_aos_to_soa(const float *aos, float *soa, int32_t n, hipStream_t stream);
 

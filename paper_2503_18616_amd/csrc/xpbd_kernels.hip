@@ -483,13 +483,31 @@ __device__ __forceinline__ Record fetch_record(const RoundTables &t, int r, bool
     return rec;
 }
 
+// Multiplier scale of environment e of the workgroup's group (uniform values).
+template <int EG>
+__device__ __forceinline__ float pick(const float (&v)[EG], uint32_t e)
+{
+    float x = v[0];
+    if constexpr (EG > 1)
+        x = e == 1u ? v[1] : x;
+    if constexpr (EG > 2) {
+        x = e == 2u ? v[2] : x;
+        x = e == 3u ? v[3] : x;
+    }
+    return x;
+}
+
 // Round r of an iteration.  `slot` holds this lane's record of round r
 // (fetched two rounds earlier) and receives the record of round r + 2.  Waves
 // without a constraint in a round skip it (uniform branch on the wave's
-// activity mask); a barrier closes every colour.
+// activity mask); a barrier closes every colour.  With several environments
+// per workgroup the top two bits of the first word name the lane's
+// environment (whose compliance applies).
+template <int EG>
 __device__ __forceinline__ void run_round(float4 *xw, const RoundTables &t, int r, Record &slot,
                                           uint64_t active, uint64_t tets, uint64_t barriers,
-                                          lambda_bank &bank, float alpha_d, float alpha_v)
+                                          lambda_bank &bank, const float (&alpha_d)[EG],
+                                          const float (&alpha_v)[EG])
 {
     // copy the record out of the prefetch slot first, so that the slot's
     // registers are free for the next fetch and the loop carries it in place
@@ -503,59 +521,95 @@ __device__ __forceinline__ void run_round(float4 *xw, const RoundTables &t, int 
     r2 = r2 >= t.R ? r2 - t.R : r2;
     slot = fetch_record(t, r2, (active >> r2) & 1u);
     if (((active >> r) & 1u) && w0 != kInvalidRecord) {
+        uint32_t e = 0u, ab = w0;
+        if constexpr (EG > 1) {
+            e = w0 >> 30;
+            ab = w0 & 0x3fffffffu;
+        }
         float l = bank[r & 31];
         if ((tets >> r) & 1u)
-            tet_update(xw, w0, w1, __uint_as_float(w2), alpha_v, l);
+            tet_update(xw, ab, w1, __uint_as_float(w2), pick<EG>(alpha_v, e), l);
         else
-            edge_update(xw, (int)(w0 & 0xffffu), (int)(w0 >> 16), __uint_as_float(w1), alpha_d, l);
+            edge_update(xw, (int)(ab & 0xffffu), (int)(ab >> 16), __uint_as_float(w1),
+                        pick<EG>(alpha_d, e), l);
         bank[r & 31] = l;
     }
     if ((barriers >> r) & 1u)
         __syncthreads();
 }
 
-// One workgroup per environment.  LDS: particles as float4 (x, y, z, w), then
-// velocities and start-of-substep positions (structure of arrays), then 256 B
-// of scratch.  Multipliers live in registers (NB banks of 32 rounds).
-template <int NB>
+// One workgroup per group of EG environments of one mesh: group g holds
+// environments A.groups[EG g .. EG g + EG); an entry ~e (negative) repeats
+// environment e as filler and writes nothing.  The group's particles share
+// the LDS (slot_of maps particle i of the group's e-th environment, e V + i,
+// to its slot) and every round's lanes may mix the environments.  LDS:
+// particles as float4 (x, y, z, w), velocities and start-of-substep positions
+// (structure of arrays), then scratch.  Multipliers live in registers (NB
+// banks of 32 rounds).
+template <int NB, int EG>
 __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int env = blockIdx.x;
+    const int group = blockIdx.x;
     const int tid = threadIdx.x;
     const int B = blockDim.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int num_waves = B >> 6;
 
-    const EnvDev ed = A.envs[env];
-    const MeshDev md = A.meshes[ed.mesh];
-    const int V = md.num_vertices, E = md.num_edges, T = md.num_tets;
+    const XPBD_CONST int32_t *groups = (const XPBD_CONST int32_t *)(uintptr_t)A.groups;
+    const XPBD_CONST float *compliance = (const XPBD_CONST float *)(uintptr_t)A.compliance;
+    const float h = A.h, inv_h = A.inv_h;
+    int env[EG], off[EG], lam_off[EG];
+    bool writes[EG];
+    float alpha_d[EG], alpha_v[EG];   // alpha~ = alpha / h^2
+#pragma unroll
+    for (int e = 0; e < EG; ++e) {
+        const int g = groups[group * EG + e];
+        env[e] = g >= 0 ? g : ~g;
+        writes[e] = g >= 0;
+        off[e] = A.envs[env[e]].particle_offset;
+        lam_off[e] = A.envs[env[e]].lambda_offset;
+        alpha_d[e] = compliance[2 * env[e]] * inv_h * inv_h;
+        alpha_v[e] = compliance[2 * env[e] + 1] * inv_h * inv_h;
+    }
+    const MeshDev md = A.meshes[A.envs[env[0]].mesh];
+    const int V = md.num_vertices;     // per environment
+    const int VS = EG * V;             // LDS slots of the group
     const int R = md.num_rounds;
     const int R0 = R < 32 ? R : 32;
     const int tools = A.num_tools;
-    const RegLdsLayout L = reg_lds_layout(V);
+    const RegLdsLayout L = reg_lds_layout(VS);
     float4 *xw = reinterpret_cast<float4 *>(smem + L.xw);
-    float *vel = reinterpret_cast<float *>(smem + L.vel);      // [3][V]
-    float *prev = reinterpret_cast<float *>(smem + L.prev);    // [3][V]
+    float *vel = reinterpret_cast<float *>(smem + L.vel);      // [3][VS]
+    float *prev = reinterpret_cast<float *>(smem + L.prev);    // [3][VS]
     uint32_t *scratch = reinterpret_cast<uint32_t *>(smem + L.scratch);
+    float4 *tool_c = reinterpret_cast<float4 *>(smem + L.scratch + kRegScratchTools);  // [EG][2]
 
-    const float h = A.h, inv_h = A.inv_h;
     const float hgx = h * A.gravity[0], hgy = h * A.gravity[1], hgz = h * A.gravity[2];
-    const float alpha_d = A.compliance[2 * env] * inv_h * inv_h;   // alpha~ = alpha / h^2
-    const float alpha_v = A.compliance[2 * env + 1] * inv_h * inv_h;
     const int NP = A.total_particles;
-    const int off = ed.particle_offset;
 
-    // particle i (mesh order) lives in LDS slot slot_of[i]; all LDS arrays are in slot order
-    for (int i = tid; i < V; i += B) {
-        const int sl = md.slot_of[i];
-        xw[sl] = make_float4(A.pos[off + i], A.pos[NP + off + i], A.pos[2 * NP + off + i],
-                             md.inv_mass[i]);
-        vel[sl] = A.vel[off + i];
-        vel[V + sl] = A.vel[NP + off + i];
-        vel[2 * V + sl] = A.vel[2 * NP + off + i];
-    }
+#pragma unroll
+    for (int e = 0; e < EG; ++e)
+        for (int i = tid; i < V; i += B) {
+            const int sl = md.slot_of[e * V + i];
+            xw[sl] = make_float4(A.pos[off[e] + i], A.pos[NP + off[e] + i],
+                                 A.pos[2 * NP + off[e] + i], md.inv_mass[i]);
+            vel[sl] = A.vel[off[e] + i];
+            vel[VS + sl] = A.vel[NP + off[e] + i];
+            vel[2 * VS + sl] = A.vel[2 * NP + off[e] + i];
+        }
+    // environment of each of this thread's slots k * B + tid: bits 2k, 2k + 1
+    uint32_t slot_env = 0u;
+    if constexpr (EG > 1)
+        for (int k = 0, sl = tid; sl < VS; ++k, sl += B) {
+            int q = md.id_of[sl], e = 0;
+            while (q >= V) {
+                q -= V;
+                ++e;
+            }
+            slot_env |= (uint32_t)e << (2 * k);
+        }
     lambda_bank bank0 = 0.0f, bank1 = 0.0f;
     __syncthreads();
 
@@ -565,43 +619,48 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
     tab.R = R;
     tab.B = B;
     tab.tid = tid;
-    const uint64_t active = A.meshes[ed.mesh].wave_active[__builtin_amdgcn_readfirstlane(wave)];
+    const uint64_t active = A.meshes[A.envs[env[0]].mesh].wave_active[__builtin_amdgcn_readfirstlane(wave)];
     const uint64_t tets = md.tet_mask, barriers = md.barrier_mask;
     Record slot_a = fetch_record(tab, 0, active & 1u);         // records of the next two
     Record slot_b = fetch_record(tab, 1, (active >> 1) & 1u);  // rounds (even, odd)
 
     uint32_t cand = 0u;  // bit 16 t + k: the particle in slot k * B + tid is a candidate of tool t
-    float3 tool0 = make_float3(0.f, 0.f, 0.f), tool1 = tool0;   // sphere centres this step
     for (int step = 0; step < A.num_steps; ++step) {
-        // instrument state and contact candidates on the start-of-step positions
+        // instrument state (sphere centres of every environment of the group)
+        if (tid < 2 * EG) {
+            const int e = tid >> 1, t = tid & 1;
+            if (t < tools) {
+                int g = A.groups[group * EG + e];
+                g = g >= 0 ? g : ~g;
+                const float *c = A.tool_pos + (((size_t)step * A.num_envs + g) * tools + t) * 3;
+                tool_c[tid] = make_float4(c[0], c[1], c[2], 0.0f);
+            }
+        }
+        __syncthreads();
+        // contact candidates on the start-of-step positions
         cand = 0u;
         for (int t = 0; t < tools; ++t) {
-            const XPBD_CONST float *c = (const XPBD_CONST float *)(uintptr_t)A.tool_pos +
-                                        (((size_t)step * A.num_envs + env) * tools + t) * 3;
-            const float3 ct = make_float3(c[0], c[1], c[2]);
-            if (t == 0)
-                tool0 = ct;
-            else
-                tool1 = ct;
             const float reach2 = t == 0 ? A.tool_reach2[0] : A.tool_reach2[1];
-            for (int k = 0, i = opaque(tid); i < V; ++k, i += B)
+            for (int k = 0, i = opaque(tid); i < VS; ++k, i += B) {
+                const float4 ct = tool_c[2 * (int)((slot_env >> (2 * k)) & 3u) + t];
                 if (within_reach(xw[i], ct.x, ct.y, ct.z, reach2))
                     cand |= 1u << (16 * t + k);
+            }
         }
         const bool any_contact = block_any(cand != 0u, scratch + 32, wave, lane, num_waves);
 
         for (int sub = 0; sub < A.substeps; ++sub) {
             // predict velocity and position (Alg. 1); pinned particles stay put
-            for (int i = opaque(tid); i < V; i += B) {
+            for (int i = opaque(tid); i < VS; i += B) {
                 float4 p = xw[i];
                 prev[i] = p.x;
-                prev[V + i] = p.y;
-                prev[2 * V + i] = p.z;
+                prev[VS + i] = p.y;
+                prev[2 * VS + i] = p.z;
                 if (p.w > 0.0f) {
-                    const float vx = vel[i] + hgx, vy = vel[V + i] + hgy, vz = vel[2 * V + i] + hgz;
+                    const float vx = vel[i] + hgx, vy = vel[VS + i] + hgy, vz = vel[2 * VS + i] + hgz;
                     vel[i] = vx;
-                    vel[V + i] = vy;
-                    vel[2 * V + i] = vz;
+                    vel[VS + i] = vy;
+                    vel[2 * VS + i] = vz;
                     p.x += h * vx;
                     p.y += h * vy;
                     p.z += h * vz;
@@ -616,36 +675,38 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
             for (int it = 0; it < A.iterations; ++it) {
                 // rounds in pairs so that the two prefetch slots never move
                 for (int r = 0; r < R0; r += 2) {
-                    run_round(xw, tab, r, slot_a, active, tets, barriers, bank0, alpha_d, alpha_v);
-                    run_round(xw, tab, r + 1, slot_b, active, tets, barriers, bank0, alpha_d,
-                              alpha_v);
+                    run_round<EG>(xw, tab, r, slot_a, active, tets, barriers, bank0, alpha_d,
+                                  alpha_v);
+                    run_round<EG>(xw, tab, r + 1, slot_b, active, tets, barriers, bank0, alpha_d,
+                                  alpha_v);
                 }
                 if constexpr (NB > 1)
                     for (int r = 32; r < R; r += 2) {
-                        run_round(xw, tab, r, slot_a, active, tets, barriers, bank1, alpha_d,
-                                  alpha_v);
-                        run_round(xw, tab, r + 1, slot_b, active, tets, barriers, bank1, alpha_d,
-                                  alpha_v);
+                        run_round<EG>(xw, tab, r, slot_a, active, tets, barriers, bank1, alpha_d,
+                                      alpha_v);
+                        run_round<EG>(xw, tab, r + 1, slot_b, active, tets, barriers, bank1,
+                                      alpha_d, alpha_v);
                     }
                 if (any_contact) {
                     for (int t = 0; t < tools; ++t) {
-                        const float3 ct = t == 0 ? tool0 : tool1;
                         const float rt = t == 0 ? A.tool_radius[0] : A.tool_radius[1];
                         const float rt2 = t == 0 ? A.tool_radius2[0] : A.tool_radius2[1];
-                        for (int k = 0, i = opaque(tid); i < V; ++k, i += B)
-                            if ((cand >> (16 * t + k)) & 1u)
+                        for (int k = 0, i = opaque(tid); i < VS; ++k, i += B)
+                            if ((cand >> (16 * t + k)) & 1u) {
+                                const float4 ct = tool_c[2 * (int)((slot_env >> (2 * k)) & 3u) + t];
                                 project_contact(xw, i, ct.x, ct.y, ct.z, rt, rt2);
+                            }
                     }
                     __syncthreads();
                 }
             }
 
             // velocity update v = (x - x_prev) / h (Alg. 1)
-            for (int i = opaque(tid); i < V; i += B) {
+            for (int i = opaque(tid); i < VS; i += B) {
                 const float4 p = xw[i];
                 vel[i] = (p.x - prev[i]) * inv_h;
-                vel[V + i] = (p.y - prev[V + i]) * inv_h;
-                vel[2 * V + i] = (p.z - prev[2 * V + i]) * inv_h;
+                vel[VS + i] = (p.y - prev[VS + i]) * inv_h;
+                vel[2 * VS + i] = (p.z - prev[2 * VS + i]) * inv_h;
             }
         }
     }
@@ -653,11 +714,384 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
     // write back (structure of arrays, coalesced); slot_of[i] belongs to another
     // thread's velocity update, hence the barrier
     __syncthreads();
+#pragma unroll
+    for (int e = 0; e < EG; ++e) {
+        int bad = 0;
+        if (writes[e])
+            for (int i = tid; i < V; i += B) {
+                const int sl = md.slot_of[e * V + i];
+                const float4 p = xw[sl];
+                const float vx = vel[sl], vy = vel[VS + sl], vz = vel[2 * VS + sl];
+                A.pos[off[e] + i] = p.x;
+                A.pos[NP + off[e] + i] = p.y;
+                A.pos[2 * NP + off[e] + i] = p.z;
+                A.vel[off[e] + i] = vx;
+                A.vel[NP + off[e] + i] = vy;
+                A.vel[2 * NP + off[e] + i] = vz;
+                bad |= !(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(vx) &&
+                         isfinite(vy) && isfinite(vz));
+            }
+        // one word block per environment: no barrier needed between the calls
+        bad = block_any(bad != 0, scratch + 32 + 16 * e, wave, lane, num_waves);
+        if (tid == 0 && bad && writes[e])
+            A.nonfinite[env[e]] = 1;
+    }
+
+    // contact candidates of the last step as ascending mesh ids, per
+    // environment: flag them by mesh id in a byte map (the start-of-substep
+    // positions are no longer needed), then compact in mesh order
+    uint8_t *flag_of = reinterpret_cast<uint8_t *>(prev);
+    const int kmax = (V + B - 1) / B;
+#pragma unroll
+    for (int e = 0; e < EG; ++e) {
+        if (!writes[e])
+            continue;
+        for (int t = 0; t < tools; ++t) {
+            for (int i = tid; i < V; i += B)
+                flag_of[i] = 0;
+            __syncthreads();
+            for (int k = 0, sl = tid; sl < VS; ++k, sl += B)
+                if (((cand >> (16 * t + k)) & 1u) && (int)((slot_env >> (2 * k)) & 3u) == e)
+                    flag_of[md.id_of[sl] - e * V] = 1;
+            __syncthreads();
+            int32_t *list = A.contacts + (size_t)t * NP + off[e];
+            int base = 0;
+            for (int k = 0; k < kmax; ++k) {
+                const int i = k * B + tid;
+                const bool flag = i < V && flag_of[i];
+                const uint64_t mask = __ballot(flag);
+                if (lane == 0)
+                    scratch[wave] = (uint32_t)__popcll(mask);
+                __syncthreads();
+                int before = 0, total = 0;
+                for (int w = 0; w < num_waves; ++w) {
+                    const int n = (int)scratch[w];
+                    before += w < wave ? n : 0;
+                    total += n;
+                }
+                if (flag)
+                    list[base + before + __popcll(mask & __lanemask_lt())] = i;
+                base += total;
+                __syncthreads();
+            }
+            for (int n = base + tid; n < V; n += B)
+                list[n] = -1;
+            if (tid == 0)
+                A.contact_counts[env[e] * tools + t] = base;
+        }
+    }
+    if (A.lambda_out) {
+        // rr_id[r][tid]: environment index (bits 24..25) and constraint id of
+        // this lane in round r, -1 for none
+        auto store = [&](int r, float l) {
+            const int v = md.rr_id[r * B + tid];
+            if (v < 0)
+                return;
+            const int e = v >> 24, id = v & 0xffffff;
+            int o = lam_off[0];
+            bool w = writes[0];
+#pragma unroll
+            for (int f = 1; f < EG; ++f) {
+                o = e == f ? lam_off[f] : o;
+                w = e == f ? writes[f] : w;
+            }
+            if (w)
+                A.lambda_out[o + id] = l;
+        };
+        for (int r = 0; r < R0; ++r)
+            store(r, bank0[r & 31]);
+        if constexpr (NB > 1)
+            for (int r = 32; r < R; ++r)
+                store(r, bank1[r & 31]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Learned warm start (an extension of the substep; the network itself runs in
+// the matrix-core kernels).  One substep per launch: learned_predict_kernel
+// predicts every particle and writes the network's features, the network adds
+// its correction to the predicted positions, xpbd_substep_reg_kernel runs the
+// sweeps from there with the residual check and updates the velocities.
+
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);   // round to nearest, ties to even
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Prediction of one substep (Alg. 1) into L.xhat, and the features of every
+// particle: predicted displacement, start-of-substep velocity, displacement
+// from rest, and the six axis-neighbour offsets minus their rest offsets,
+// scaled by in_scale and rounded to bfloat16; feature 31 flags a free particle.
+// Grid: (ceil(max V / 256), environments).
+__global__ void __launch_bounds__(256) learned_predict_kernel(StepArgs A, LearnedArgs L)
+{
+    const int env = blockIdx.y;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const EnvDev ed = A.envs[env];
+    const MeshDev md = A.meshes[ed.mesh];
+    if (i >= md.num_vertices)
+        return;
+    const int NP = A.total_particles, off = ed.particle_offset;
+    const float h = A.h;
+    const float hgx = h * A.gravity[0], hgy = h * A.gravity[1], hgz = h * A.gravity[2];
+    auto predict = [&](int j, float &px, float &py, float &pz) {
+        px = A.pos[off + j];
+        py = A.pos[NP + off + j];
+        pz = A.pos[2 * NP + off + j];
+        if (md.inv_mass[j] > 0.0f) {
+            const float vx = A.vel[off + j] + hgx, vy = A.vel[NP + off + j] + hgy,
+                        vz = A.vel[2 * NP + off + j] + hgz;
+            px += h * vx;
+            py += h * vy;
+            pz += h * vz;
+        }
+    };
+    float f[32];
+    float xh, yh, zh;
+    predict(i, xh, yh, zh);
+    L.xhat[off + i] = xh;
+    L.xhat[NP + off + i] = yh;
+    L.xhat[2 * NP + off + i] = zh;
+    if (!L.features)
+        return;
+    const float rx = md.rest_pos[3 * i], ry = md.rest_pos[3 * i + 1], rz = md.rest_pos[3 * i + 2];
+    f[0] = xh - A.pos[off + i];
+    f[1] = yh - A.pos[NP + off + i];
+    f[2] = zh - A.pos[2 * NP + off + i];
+    f[3] = A.vel[off + i];
+    f[4] = A.vel[NP + off + i];
+    f[5] = A.vel[2 * NP + off + i];
+    f[6] = xh - rx;
+    f[7] = yh - ry;
+    f[8] = zh - rz;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int n = md.nbr[6 * i + k];
+        float ox = 0.0f, oy = 0.0f, oz = 0.0f;
+        if (n >= 0) {
+            float nx, ny, nz;
+            predict(n, nx, ny, nz);
+            ox = (nx - xh) - (md.rest_pos[3 * n] - rx);
+            oy = (ny - yh) - (md.rest_pos[3 * n + 1] - ry);
+            oz = (nz - zh) - (md.rest_pos[3 * n + 2] - rz);
+        }
+        f[9 + 3 * k] = ox;
+        f[10 + 3 * k] = oy;
+        f[11 + 3 * k] = oz;
+    }
+    uint32_t packed[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const int c0 = 2 * c, c1 = 2 * c + 1;
+        const uint16_t lo = c0 < 27 ? to_bf16(f[c0] * L.in_scale[c0]) : (uint16_t)0;
+        uint16_t hi = c1 < 27 ? to_bf16(f[c1] * L.in_scale[c1]) : (uint16_t)0;
+        if (c1 == 31)
+            hi = md.inv_mass[i] > 0.0f ? (uint16_t)0x3f80 : (uint16_t)0;   // bfloat16 1.0
+        packed[c] = (uint32_t)lo | ((uint32_t)hi << 16);
+    }
+    uint4 *dst = reinterpret_cast<uint4 *>(L.features + (size_t)(off + i) * 32);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        dst[q] = make_uint4(packed[4 * q], packed[4 * q + 1], packed[4 * q + 2], packed[4 * q + 3]);
+}
+
+// Residual term of this lane's constraint in round r: ((C + alpha~ lambda) / rest)^2,
+// with the same prefetch pipeline as run_round (no writes, no barrier).
+__device__ __forceinline__ void eval_round(const float4 *xw, const RoundTables &t, int r,
+                                           Record &slot, uint64_t active, uint64_t tets,
+                                           const lambda_bank &bank, float alpha_d, float alpha_v,
+                                           float &acc)
+{
+    uint32_t w0, w1, w2;
+    asm volatile("v_mov_b32 %0, %3\n\tv_mov_b32 %1, %4\n\tv_mov_b32 %2, %5"
+                 : "=v"(w0), "=v"(w1), "=v"(w2)
+                 : "v"(slot.w0), "v"(slot.w1), "v"(slot.w2));
+    int r2 = r + 2;
+    r2 = r2 >= t.R ? r2 - t.R : r2;
+    slot = fetch_record(t, r2, (active >> r2) & 1u);
+    if (((active >> r) & 1u) && w0 != kInvalidRecord) {
+        const float l = bank[r & 31];
+        float q;
+        if ((tets >> r) & 1u) {
+            const float4 pa = xw[w0 & 0xffffu], pb = xw[w0 >> 16];
+            const float4 pc = xw[w1 & 0xffffu], pd = xw[w1 >> 16];
+            const float bax = pb.x - pa.x, bay = pb.y - pa.y, baz = pb.z - pa.z;
+            const float cax = pc.x - pa.x, cay = pc.y - pa.y, caz = pc.z - pa.z;
+            const float dax = pd.x - pa.x, day = pd.y - pa.y, daz = pd.z - pa.z;
+            const float vol = (bax * (cay * daz - caz * day) + bay * (caz * dax - cax * daz) +
+                               baz * (cax * day - cay * dax)) * kSixth;
+            const float rest = __uint_as_float(w2);
+            q = (vol - rest + alpha_v * l) / rest;
+        } else {
+            const float4 pa = xw[w0 & 0xffffu], pb = xw[w0 >> 16];
+            const float dx = pa.x - pb.x, dy = pa.y - pb.y, dz = pa.z - pb.z;
+            const float rest = __uint_as_float(w1);
+            q = (sqrtf(dx * dx + dy * dy + dz * dz) - rest + alpha_d * l) / rest;
+        }
+        acc += q * q;
+    }
+}
+
+// One substep of one environment from the predicted positions in L.xhat
+// (start-of-substep positions in A.pos): min_iterations sweeps, the residual
+// RMS, and the remaining sweeps up to max_iterations when it exceeds the
+// threshold; then v = (x - x_prev) / h and the write-back.
+template <int NB>
+__global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, LearnedArgs L)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int env = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int B = blockDim.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int num_waves = B >> 6;
+
+    const EnvDev ed = A.envs[env];
+    const MeshDev md = A.meshes[ed.mesh];
+    const int V = md.num_vertices;
+    const int R = md.num_rounds;
+    const int R0 = R < 32 ? R : 32;
+    const int tools = A.num_tools;
+    const RegLdsLayout Lay = reg_lds_layout(V);
+    float4 *xw = reinterpret_cast<float4 *>(smem + Lay.xw);
+    float *vel = reinterpret_cast<float *>(smem + Lay.vel);      // [3][V] (byte flags at the end)
+    float *prev = reinterpret_cast<float *>(smem + Lay.prev);    // [3][V]
+    uint32_t *scratch = reinterpret_cast<uint32_t *>(smem + Lay.scratch);
+    const XPBD_CONST float *compliance = (const XPBD_CONST float *)(uintptr_t)A.compliance;
+    const float inv_h = A.inv_h;
+    const float alpha_d = compliance[2 * env] * inv_h * inv_h;
+    const float alpha_v = compliance[2 * env + 1] * inv_h * inv_h;
+    const int NP = A.total_particles;
+    const int off = ed.particle_offset;
+
+    for (int i = tid; i < V; i += B) {
+        const int sl = md.slot_of[i];
+        xw[sl] = make_float4(L.xhat[off + i], L.xhat[NP + off + i], L.xhat[2 * NP + off + i],
+                             md.inv_mass[i]);
+        prev[sl] = A.pos[off + i];
+        prev[V + sl] = A.pos[NP + off + i];
+        prev[2 * V + sl] = A.pos[2 * NP + off + i];
+    }
+    lambda_bank bank0 = 0.0f, bank1 = 0.0f;
+
+    // sphere centres of this step and the contact candidates (bit 16 t + k: slot k B + tid)
+    float3 tool0 = make_float3(0.f, 0.f, 0.f), tool1 = tool0;
+    for (int t = 0; t < tools; ++t) {
+        const XPBD_CONST float *c = (const XPBD_CONST float *)(uintptr_t)A.tool_pos +
+                                    (((size_t)L.step * A.num_envs + env) * tools + t) * 3;
+        const float3 ct = make_float3(c[0], c[1], c[2]);
+        if (t == 0)
+            tool0 = ct;
+        else
+            tool1 = ct;
+    }
+    __syncthreads();
+    uint32_t cand = 0u;
+    for (int k = 0, sl = tid; sl < V; ++k, sl += B) {
+        const int i = md.id_of[sl];
+        uint32_t bits = 0u;
+        if (L.first_substep) {
+            // start-of-step positions: the prediction has not moved them yet
+            const float4 p0 = make_float4(prev[sl], prev[V + sl], prev[2 * V + sl], xw[sl].w);
+            for (int t = 0; t < tools; ++t) {
+                const float3 ct = t == 0 ? tool0 : tool1;
+                const float reach2 = t == 0 ? A.tool_reach2[0] : A.tool_reach2[1];
+                if (within_reach(p0, ct.x, ct.y, ct.z, reach2))
+                    bits |= 1u << t;
+            }
+            L.cand[off + i] = (uint8_t)bits;
+        } else {
+            bits = L.cand[off + i];
+        }
+        for (int t = 0; t < tools; ++t)
+            if ((bits >> t) & 1u)
+                cand |= 1u << (16 * t + k);
+    }
+    const bool any_contact = block_any(cand != 0u, scratch + 32, wave, lane, num_waves);
+
+    RoundTables tab;
+    tab.rr = (const XPBD_GLOBAL Record *)(uintptr_t)md.round_rec;
+    tab.R = R;
+    tab.B = B;
+    tab.tid = tid;
+    const uint64_t active = A.meshes[ed.mesh].wave_active[__builtin_amdgcn_readfirstlane(wave)];
+    const uint64_t tets = md.tet_mask, barriers = md.barrier_mask;
+    Record slot_a = fetch_record(tab, 0, active & 1u);
+    Record slot_b = fetch_record(tab, 1, (active >> 1) & 1u);
+    const float alpha_d1[1] = {alpha_d}, alpha_v1[1] = {alpha_v};
+
+    auto sweep = [&]() {
+        for (int r = 0; r < R0; r += 2) {
+            run_round<1>(xw, tab, r, slot_a, active, tets, barriers, bank0, alpha_d1, alpha_v1);
+            run_round<1>(xw, tab, r + 1, slot_b, active, tets, barriers, bank0, alpha_d1, alpha_v1);
+        }
+        if constexpr (NB > 1)
+            for (int r = 32; r < R; r += 2) {
+                run_round<1>(xw, tab, r, slot_a, active, tets, barriers, bank1, alpha_d1, alpha_v1);
+                run_round<1>(xw, tab, r + 1, slot_b, active, tets, barriers, bank1, alpha_d1,
+                             alpha_v1);
+            }
+        if (any_contact) {
+            for (int t = 0; t < tools; ++t) {
+                const float3 ct = t == 0 ? tool0 : tool1;
+                const float rt = t == 0 ? A.tool_radius[0] : A.tool_radius[1];
+                const float rt2 = t == 0 ? A.tool_radius2[0] : A.tool_radius2[1];
+                for (int k = 0, i = tid; i < V; ++k, i += B)
+                    if ((cand >> (16 * t + k)) & 1u)
+                        project_contact(xw, i, ct.x, ct.y, ct.z, rt, rt2);
+            }
+            __syncthreads();
+        }
+    };
+
+    int n_it = 0;
+    for (; n_it < L.min_iterations; ++n_it)
+        sweep();
+    if (L.max_iterations > L.min_iterations) {
+        float acc = 0.0f;
+        for (int r = 0; r < R0; r += 2) {
+            eval_round(xw, tab, r, slot_a, active, tets, bank0, alpha_d, alpha_v, acc);
+            eval_round(xw, tab, r + 1, slot_b, active, tets, bank0, alpha_d, alpha_v, acc);
+        }
+        if constexpr (NB > 1)
+            for (int r = 32; r < R; r += 2) {
+                eval_round(xw, tab, r, slot_a, active, tets, bank1, alpha_d, alpha_v, acc);
+                eval_round(xw, tab, r + 1, slot_b, active, tets, bank1, alpha_d, alpha_v, acc);
+            }
+        acc = wave_sum(acc);
+        if (lane == 0)
+            scratch[64 + wave] = __float_as_uint(acc);
+        __syncthreads();
+        float total = 0.0f;
+        for (int w = 0; w < num_waves; ++w)
+            total += __uint_as_float(scratch[64 + w]);
+        const int n_con = md.num_edges + md.num_tets;
+        const float rms = n_con > 0 ? sqrtf(total / (float)n_con) : 0.0f;
+        if (rms > L.threshold)
+            for (; n_it < L.max_iterations; ++n_it)
+                sweep();
+    }
+
+    // velocity update and write-back (structure of arrays); slot_of[i] belongs
+    // to other threads' sweeps, hence the barrier
+    __syncthreads();
     int bad = 0;
     for (int i = tid; i < V; i += B) {
         const int sl = md.slot_of[i];
         const float4 p = xw[sl];
-        const float vx = vel[sl], vy = vel[V + sl], vz = vel[2 * V + sl];
+        const float vx = (p.x - prev[sl]) * inv_h, vy = (p.y - prev[V + sl]) * inv_h,
+                    vz = (p.z - prev[2 * V + sl]) * inv_h;
+        if (L.record_targets) {
+            const bool free_p = p.w > 0.0f;
+            float *t = L.record_targets + (size_t)(off + i) * 4;
+            t[0] = free_p ? (p.x - L.xhat[off + i]) / L.out_scale[0] : 0.0f;
+            t[1] = free_p ? (p.y - L.xhat[NP + off + i]) / L.out_scale[1] : 0.0f;
+            t[2] = free_p ? (p.z - L.xhat[2 * NP + off + i]) / L.out_scale[2] : 0.0f;
+            t[3] = 0.0f;
+        }
         A.pos[off + i] = p.x;
         A.pos[NP + off + i] = p.y;
         A.pos[2 * NP + off + i] = p.z;
@@ -667,68 +1101,70 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
         bad |= !(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(vx) &&
                  isfinite(vy) && isfinite(vz));
     }
-    bad = block_any(bad != 0, scratch + 32, wave, lane, num_waves);
-    if (tid == 0 && bad)
-        A.nonfinite[env] = 1;
+    bad = block_any(bad != 0, scratch + 48, wave, lane, num_waves);
+    if (tid == 0) {
+        if (bad)
+            A.nonfinite[env] = 1;
+        if (L.iterations)
+            L.iterations[env] = n_it;
+    }
 
-    // contact candidates of the last step as ascending mesh ids: flag them by mesh
-    // id in a byte map (the start-of-substep positions are no longer needed), then
-    // compact in mesh order
-    uint8_t *flag_of = reinterpret_cast<uint8_t *>(prev);
-    const int kmax = (V + B - 1) / B;
-    for (int t = 0; t < tools; ++t) {
-        for (int i = tid; i < V; i += B)
-            flag_of[i] = 0;
-        __syncthreads();
-        for (int k = 0, sl = tid; sl < V; ++k, sl += B)
-            if ((cand >> (16 * t + k)) & 1u)
-                flag_of[md.id_of[sl]] = 1;
-        __syncthreads();
-        int32_t *list = A.contacts + (size_t)t * NP + off;
-        int base = 0;
-        for (int k = 0; k < kmax; ++k) {
-            const int i = k * B + tid;
-            const bool flag = i < V && flag_of[i];
-            const uint64_t mask = __ballot(flag);
-            if (lane == 0)
-                scratch[wave] = (uint32_t)__popcll(mask);
+    // contact candidates of the step as ascending mesh ids (first substep only)
+    if (L.first_substep) {
+        uint8_t *flag_of = reinterpret_cast<uint8_t *>(vel);
+        const int kmax = (V + B - 1) / B;
+        for (int t = 0; t < tools; ++t) {
+            for (int i = tid; i < V; i += B)
+                flag_of[i] = 0;
             __syncthreads();
-            int before = 0, total = 0;
-            for (int w = 0; w < num_waves; ++w) {
-                const int n = (int)scratch[w];
-                before += w < wave ? n : 0;
-                total += n;
+            for (int k = 0, sl = tid; sl < V; ++k, sl += B)
+                if ((cand >> (16 * t + k)) & 1u)
+                    flag_of[md.id_of[sl]] = 1;
+            __syncthreads();
+            int32_t *list = A.contacts + (size_t)t * NP + off;
+            int base = 0;
+            for (int k = 0; k < kmax; ++k) {
+                const int i = k * B + tid;
+                const bool flag = i < V && flag_of[i];
+                const uint64_t mask = __ballot(flag);
+                if (lane == 0)
+                    scratch[wave] = (uint32_t)__popcll(mask);
+                __syncthreads();
+                int before = 0, total = 0;
+                for (int w = 0; w < num_waves; ++w) {
+                    const int n = (int)scratch[w];
+                    before += w < wave ? n : 0;
+                    total += n;
+                }
+                if (flag)
+                    list[base + before + __popcll(mask & __lanemask_lt())] = i;
+                base += total;
+                __syncthreads();
             }
-            if (flag)
-                list[base + before + __popcll(mask & __lanemask_lt())] = i;
-            base += total;
-            __syncthreads();
+            for (int n = base + tid; n < V; n += B)
+                list[n] = -1;
+            if (tid == 0)
+                A.contact_counts[env * tools + t] = base;
         }
-        for (int n = base + tid; n < V; n += B)
-            list[n] = -1;
-        if (tid == 0)
-            A.contact_counts[env * tools + t] = base;
     }
     if (A.lambda_out) {
-        // constraint id of this lane in round r: rr_id[r][tid] (-1: none)
         float *out = A.lambda_out + ed.lambda_offset;
         for (int r = 0; r < R0; ++r) {
             const int id = md.rr_id[r * B + tid];
             if (id >= 0)
-                out[id] = bank0[r & 31];
+                out[id & 0xffffff] = bank0[r & 31];
         }
         if constexpr (NB > 1)
             for (int r = 32; r < R; ++r) {
                 const int id = md.rr_id[r * B + tid];
                 if (id >= 0)
-                    out[id] = bank1[r & 31];
+                    out[id & 0xffffff] = bank1[r & 31];
             }
     }
 }
 
 // Constraint residual (C + alpha~ lambda) / rest of every kept constraint of an
-// environment, from its written-back positions (mesh order; the records name
-// LDS slots, mapped back through id_of) and stored multipliers
+// environment, from its written-back positions and stored multipliers
 // (constraint order), reduced to (RMS, max |r|).  One workgroup per environment.
 __global__ void __launch_bounds__(256) residual_kernel(StepArgs A)
 {
@@ -746,24 +1182,24 @@ __global__ void __launch_bounds__(256) residual_kernel(StepArgs A)
     const float alpha_d = A.compliance[2 * env] * inv_h2, alpha_v = A.compliance[2 * env + 1] * inv_h2;
     float sum = 0.0f, big = 0.0f;
     for (int j = tid; j < E; j += blockDim.x) {
-        const uint2 e = md.edge_rec[j];
-        const int a = md.id_of[e.x & 0xffffu], b = md.id_of[e.x >> 16];
+        const uint32_t e = md.edge_pair[j];
+        const int a = (int)(e & 0xffffu), b = (int)(e >> 16);
         const float dx = px[a] - px[b], dy = py[a] - py[b], dz = pz[a] - pz[b];
-        const float rest = __uint_as_float(e.y);
+        const float rest = md.edge_rest[j];
         const float r = (sqrtf(dx * dx + dy * dy + dz * dz) - rest + alpha_d * lam[md.edge_id[j]]) / rest;
         sum += r * r;
         big = fmaxf(big, fabsf(r));
     }
     for (int j = tid; j < T; j += blockDim.x) {
-        const uint4 q = md.tet_rec[j];
-        const int a = md.id_of[q.x & 0xffffu], b = md.id_of[q.x >> 16];
-        const int c = md.id_of[q.y & 0xffffu], d = md.id_of[q.y >> 16];
+        const uint2 q = md.tet_quad[j];
+        const int a = (int)(q.x & 0xffffu), b = (int)(q.x >> 16);
+        const int c = (int)(q.y & 0xffffu), d = (int)(q.y >> 16);
         const float bax = px[b] - px[a], bay = py[b] - py[a], baz = pz[b] - pz[a];
         const float cax = px[c] - px[a], cay = py[c] - py[a], caz = pz[c] - pz[a];
         const float dax = px[d] - px[a], day = py[d] - py[a], daz = pz[d] - pz[a];
         const float vol = (bax * (cay * daz - caz * day) + bay * (caz * dax - cax * daz) +
                            baz * (cax * day - cay * dax)) * kSixth;
-        const float rest = __uint_as_float(q.z);
+        const float rest = md.tet_rest[j];
         const float r = (vol - rest + alpha_v * lam[E + md.tet_id[j]]) / rest;
         sum += r * r;
         big = fmaxf(big, fabsf(r));
@@ -831,18 +1267,27 @@ hipError_t launch_ppt(const StepArgs &args, int block, bool stage, uint32_t lds,
                  : launch_variant<PPT, false, false>(args, block, lds, s);
 }
 
-template <int NB>
+template <int NB, int EG>
 hipError_t launch_reg_variant(const StepArgs &args, int block, uint32_t lds_bytes, hipStream_t stream)
 {
-    auto kernel = xpbd_step_reg_kernel<NB>;
+    auto kernel = xpbd_step_reg_kernel<NB, EG>;
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)lds_bytes);
     if (err != hipSuccess)
         return err;
-    hipLaunchKernelGGL(kernel, dim3((unsigned)args.num_envs), dim3((unsigned)block), lds_bytes,
+    hipLaunchKernelGGL(kernel, dim3((unsigned)args.num_groups), dim3((unsigned)block), lds_bytes,
                        stream, args);
     return hipGetLastError();
+}
+
+template <int EG>
+hipError_t launch_reg_groups(const StepArgs &args, int block, int lambda_banks, uint32_t lds_bytes,
+                             hipStream_t stream)
+{
+    return lambda_banks == 1   ? launch_reg_variant<1, EG>(args, block, lds_bytes, stream)
+           : lambda_banks == 2 ? launch_reg_variant<2, EG>(args, block, lds_bytes, stream)
+                               : hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -860,11 +1305,48 @@ hipError_t launch_step(const StepArgs &args, int block, int particles_per_thread
     }
 }
 
-hipError_t launch_step_reg(const StepArgs &args, int block, int lambda_banks, uint32_t lds_bytes,
-                           bool want_residual, hipStream_t stream)
+hipError_t launch_step_reg(const StepArgs &args, int block, int lambda_banks, int envs_per_group,
+                           uint32_t lds_bytes, bool want_residual, hipStream_t stream)
 {
-    hipError_t err = lambda_banks == 1 ? launch_reg_variant<1>(args, block, lds_bytes, stream)
-                     : lambda_banks == 2 ? launch_reg_variant<2>(args, block, lds_bytes, stream)
+    hipError_t err =
+        envs_per_group == 1   ? launch_reg_groups<1>(args, block, lambda_banks, lds_bytes, stream)
+        : envs_per_group == 2 ? launch_reg_groups<2>(args, block, lambda_banks, lds_bytes, stream)
+                              : hipErrorInvalidValue;
+    if (err != hipSuccess || !want_residual)
+        return err;
+    hipLaunchKernelGGL(residual_kernel, dim3((unsigned)args.num_envs), dim3(256), 0, stream, args);
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_predict(const StepArgs &args, const LearnedArgs &largs, hipStream_t stream)
+{
+    hipLaunchKernelGGL(learned_predict_kernel,
+                       dim3((unsigned)((largs.max_vertices + 255) / 256), (unsigned)args.num_envs),
+                       dim3(256), 0, stream, args, largs);
+    return hipGetLastError();
+}
+
+template <int NB>
+hipError_t launch_substep_variant(const StepArgs &args, const LearnedArgs &largs, int block,
+                                  uint32_t lds_bytes, hipStream_t stream)
+{
+    auto kernel = xpbd_substep_reg_kernel<NB>;
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds_bytes);
+    if (err != hipSuccess)
+        return err;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)args.num_envs), dim3((unsigned)block), lds_bytes,
+                       stream, args, largs);
+    return hipGetLastError();
+}
+
+hipError_t launch_substep_reg(const StepArgs &args, const LearnedArgs &largs, int block,
+                              int lambda_banks, uint32_t lds_bytes, bool want_residual,
+                              hipStream_t stream)
+{
+    hipError_t err = lambda_banks == 1 ? launch_substep_variant<1>(args, largs, block, lds_bytes, stream)
+                     : lambda_banks == 2 ? launch_substep_variant<2>(args, largs, block, lds_bytes, stream)
                                          : hipErrorInvalidValue;
     if (err != hipSuccess || !want_residual)
         return err;

@@ -18,113 +18,18 @@
 
 #include "../../include/xpbd.h"
 #include "mesh_setup.h"
+#include "batch.h"
+#include "runtime_util.h"
 #include "xpbd_device.h"
 
 using xpbd::EnvDev;
 using xpbd::MeshDev;
 using xpbd::PreparedMesh;
 
-namespace {
-
-thread_local std::string g_error;
-
-xpbd_status fail(xpbd_status code, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_error = buf;
-    return code;
-}
-
-#define HIP_TRY(expr)                                                                        \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
-        if (e_ != hipSuccess)                                                                \
-            return fail(XPBD_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
-    } while (0)
-
-// Device allocation owned by a batch.
-struct DeviceBuffer {
-    void *ptr = nullptr;
-    size_t bytes = 0;
-};
-
-bool is_device_pointer(const void *p)
-{
-    hipPointerAttribute_t attr;
-    hipError_t e = hipPointerGetAttributes(&attr, p);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();  // plain pageable host memory is not registered
-        return false;
-    }
-    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
-}
-
-}  // namespace
-
-struct xpbd_batch {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    xpbd_params params{};
-    int32_t num_envs = 0;
-    int32_t total_particles = 0;
-    int32_t total_lambda = 0;
-    int block = 64;
-    int particles_per_thread = 1;
-    bool stage_topology = false;
-    bool register_variant = false;
-    int lambda_banks = 1;
-    uint32_t lds_bytes = 0;
-    std::vector<PreparedMesh> meshes;
-    std::vector<int32_t> env_mesh;
-    std::vector<int32_t> env_offsets;       // [N+1]
-    std::vector<int32_t> colours;           // concatenated per mesh: edges then tets
-    std::vector<DeviceBuffer> allocations;
-    float *pos = nullptr, *vel = nullptr, *lambda = nullptr, *residual = nullptr;
-    float *compliance = nullptr;
-    int32_t *contacts = nullptr, *contact_counts = nullptr, *nonfinite = nullptr;
-    MeshDev *meshes_dev = nullptr;
-    EnvDev *envs_dev = nullptr;
-    float *staging = nullptr;                // [sum V][3] for AoS <-> SoA and host tool poses
-    size_t staging_bytes = 0;
-    float *tool_staging = nullptr;
-    size_t tool_staging_bytes = 0;
-    bool residual_valid = false;   // a step has computed the residual
-
-    ~xpbd_batch()
-    {
-        (void)hipStreamSynchronize(stream);
-        for (auto &a : allocations)
-            (void)hipFree(a.ptr);
-        if (tool_staging)
-            (void)hipFree(tool_staging);
-    }
-
-    xpbd_status alloc(void **out, size_t bytes)
-    {
-        void *p = nullptr;
-        hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
-        if (e != hipSuccess)
-            return fail(XPBD_E_HIP, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-        allocations.push_back({p, bytes});
-        *out = p;
-        return XPBD_OK;
-    }
-
-    template <typename T>
-    xpbd_status upload(T **out, const std::vector<T> &host)
-    {
-        xpbd_status s = alloc(reinterpret_cast<void **>(out), host.size() * sizeof(T));
-        if (s != XPBD_OK)
-            return s;
-        if (!host.empty())  // blocking: the host vectors are temporaries of creation
-            HIP_TRY(hipMemcpy(*out, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice));
-        return XPBD_OK;
-    }
-};
+using xpbd::DeviceBuffer;
+using xpbd::fail;
+using xpbd::g_error;
+using xpbd::is_device_pointer;
 
 namespace {
 
@@ -155,6 +60,8 @@ xpbd_status validate_params(const xpbd_params *p)
         return fail(XPBD_E_ARG, "unknown solver_variant %d", p->solver_variant);
     if (p->colour_packing < XPBD_PACKING_AUTO || p->colour_packing > XPBD_PACKING_SEARCH)
         return fail(XPBD_E_ARG, "unknown colour_packing %d", p->colour_packing);
+    if (p->envs_per_group < 0 || p->envs_per_group > xpbd::kMaxEnvsPerGroup)
+        return fail(XPBD_E_ARG, "envs_per_group must be 0, 1 or 2 (got %d)", p->envs_per_group);
     return XPBD_OK;
 }
 
@@ -203,7 +110,8 @@ void build_rounds(const std::vector<int32_t> &edge_ptr, const std::vector<int32_
     }
 }
 
-int count_rounds(const PreparedMesh &pm, int B)
+// Rounds of a group of G copies of the mesh at block size B.
+int count_rounds(const PreparedMesh &pm, int B, int G)
 {
     std::vector<int32_t> n_e((size_t)pm.num_edge_colours, 0), n_t((size_t)pm.num_tet_colours, 0);
     for (int32_t c : pm.edge_colour)
@@ -212,9 +120,9 @@ int count_rounds(const PreparedMesh &pm, int B)
         n_t[(size_t)c]++;
     int r = 0;
     for (int32_t n : n_e)
-        r += (n + B - 1) / B;
+        r += (G * n + B - 1) / B;
     for (int32_t n : n_t)
-        r += (n + B - 1) / B;
+        r += (G * n + B - 1) / B;
     return r;
 }
 
@@ -357,34 +265,50 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     int lds_limit = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
 
-    // register-multiplier variant: the smallest block of 256, 512 or 1024 threads (or
-    // the requested one) whose round schedule fits the register banks of every mesh
+    // register-multiplier variant: environments per workgroup G (requested, else 1:
+    // two per workgroup measured slower on the 1024-environment batch), then the
+    // smallest block of 256, 512 or 1024 threads (or the requested one) whose
+    // round schedule for G copies of every mesh fits the register banks
     bool use_registers = false;
-    int reg_block = 0, reg_rounds = 0;
+    int reg_block = 0, reg_rounds = 0, reg_group = 1;
     const bool pow2_block = params->block_size == 0 ||
                             (params->block_size & (params->block_size - 1)) == 0;
     if (params->solver_variant != XPBD_VARIANT_LDS && pow2_block) {
+        std::vector<int> group_tries;
+        if (params->envs_per_group)
+            group_tries.push_back(params->envs_per_group);
+        else
+            group_tries.push_back(1);
         const int tries[3] = {256, 512, 1024};
         const int n_tries = params->block_size ? 1 : 3;
-        for (int k = 0; k < n_tries && !use_registers; ++k) {
-            const int B = params->block_size ? params->block_size : tries[k];
-            int worst = 0;
-            for (const auto &pm : prepared)
-                worst = std::max(worst, count_rounds(pm, B));
-            worst += worst % 2;   // padded to an even count
-            const bool fits = worst <= xpbd::kMaxRounds && vmax <= 16 * B && B / 64 <= 16 &&
-                              xpbd::reg_lds_layout(vmax).total <= (uint32_t)lds_limit;
-            if (fits) {
-                use_registers = true;
-                reg_block = B;
-                reg_rounds = worst;
+        for (int G : group_tries) {
+            for (int k = 0; k < n_tries && !use_registers; ++k) {
+                const int B = params->block_size ? params->block_size : tries[k];
+                int worst = 0;
+                for (const auto &pm : prepared)
+                    worst = std::max(worst, count_rounds(pm, B, G));
+                worst += worst % 2;   // padded to an even count
+                const bool fits = worst <= xpbd::kMaxRounds && G * vmax <= 16 * B &&
+                                  G * vmax <= 16384 && B / 64 <= 16 &&
+                                  xpbd::reg_lds_layout(G * vmax).total <= (uint32_t)lds_limit;
+                if (fits) {
+                    use_registers = true;
+                    reg_block = B;
+                    reg_rounds = worst;
+                    reg_group = G;
+                }
             }
+            if (use_registers)
+                break;
         }
     }
     if (!use_registers && params->solver_variant == XPBD_VARIANT_REGISTERS)
         return fail(XPBD_E_CAPACITY, "the register variant needs a power-of-two block, at most %d "
-                    "rounds per lane and LDS for the particles; use the LDS variant",
+                    "rounds per lane and LDS for the particles of a group; use the LDS variant",
                     xpbd::kMaxRounds);
+    if (!use_registers && params->envs_per_group > 1)
+        return fail(XPBD_E_CAPACITY, "%d environments per workgroup need the register variant and "
+                    "must fit its rounds and LDS", params->envs_per_group);
     if (use_registers) {
         block = reg_block;
         ppt = 1;
@@ -402,7 +326,7 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     uint32_t lds = stage ? lds_staged : lds_global;
     if (use_registers) {
         stage = false;
-        lds = xpbd::reg_lds_layout(vmax).total;
+        lds = xpbd::reg_lds_layout(reg_group * vmax).total;
     }
     if (lds > (uint32_t)lds_limit)
         return fail(XPBD_E_CAPACITY, "environment needs %u bytes of LDS; the device has %d",
@@ -419,8 +343,10 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     b->stage_topology = stage;
     b->register_variant = use_registers;
     b->lambda_banks = reg_rounds > 32 ? 2 : 1;
+    b->envs_per_group = use_registers ? reg_group : 1;
     b->lds_bytes = lds;
     b->env_mesh.assign(env_mesh, env_mesh + num_envs);
+    b->max_vertices = vmax;
     b->meshes = std::move(prepared);
 
     auto cleanup = [&](xpbd_status st) {
@@ -432,50 +358,25 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     std::vector<MeshDev> mdev((size_t)num_meshes);
     for (int32_t m = 0; m < num_meshes; ++m) {
         const PreparedMesh &pm = b->meshes[(size_t)m];
-        const int32_t E = pm.num_edges(), T = pm.num_tets();
-        std::vector<int32_t> eslot, eptr, tslot, tptr;
-        build_schedule(pm.edge_colour, pm.num_edge_colours, eslot, eptr);
-        build_schedule(pm.tet_colour, pm.num_tet_colours, tslot, tptr);
+        const int32_t V = pm.num_vertices, E = pm.num_edges(), T = pm.num_tets();
         int packing = params->colour_packing;
         if (packing == XPBD_PACKING_AUTO)
             packing = use_registers ? XPBD_PACKING_SEARCH : XPBD_PACKING_BANKS16;
         if ((packing == XPBD_PACKING_SCATTERED_BANKS16 || packing == XPBD_PACKING_SEARCH) &&
             !use_registers)
             packing = XPBD_PACKING_BANKS16;
-        const bool scattered =
-            packing == XPBD_PACKING_SCATTERED_BANKS16 || packing == XPBD_PACKING_SEARCH;
-        // LDS placement of the particles (register variant): identity, or a fixed
-        // pseudo-random order that spreads every colour's particles over the banks
-        std::vector<int32_t> slot_of((size_t)pm.num_vertices);
-        std::iota(slot_of.begin(), slot_of.end(), 0);
-        if (scattered) {
-            std::mt19937 gen(0x5eedu + (uint32_t)m);
-            std::shuffle(slot_of.begin(), slot_of.end(), gen);
-        }
-        std::vector<uint16_t> slot16((size_t)pm.num_vertices), id16((size_t)pm.num_vertices);
-        for (int32_t i = 0; i < pm.num_vertices; ++i) {
-            slot16[(size_t)i] = (uint16_t)slot_of[(size_t)i];
-            id16[(size_t)slot_of[(size_t)i]] = (uint16_t)i;
-        }
-        std::vector<int32_t> edges_in_lds(pm.edges.size()), tets_in_lds(pm.tets.size());
-        for (size_t q = 0; q < pm.edges.size(); ++q)
-            edges_in_lds[q] = slot_of[(size_t)pm.edges[q]];
-        for (size_t q = 0; q < pm.tets.size(); ++q)
-            tets_in_lds[q] = slot_of[(size_t)pm.tets[q]];
-        // vertex order of each constraint in the register variant's records
-        // (an index into xpbd::vertex_order; 0 keeps the mesh order)
-        std::vector<uint8_t> eorder((size_t)E, 0), torder((size_t)T, 0);
-        if (packing == XPBD_PACKING_SEARCH) {
-            xpbd::pack_lanes(edges_in_lds.data(), 2, eptr, 0x9e37u + 2u * (uint32_t)m,
-                             kLaneSearchEffort, eslot, eorder);
-            xpbd::pack_lanes(tets_in_lds.data(), 4, tptr, 0x9e38u + 2u * (uint32_t)m,
-                             kLaneSearchEffort, tslot, torder);
-        } else {
-            const int group = packing == XPBD_PACKING_BANKS8     ? 8
-                              : packing == XPBD_PACKING_ID_ORDER ? 0
-                                                                 : 16;
-            xpbd::pack_colours(edges_in_lds.data(), 2, eptr, group, group, eslot);
-            xpbd::pack_colours(tets_in_lds.data(), 4, tptr, group, group, tslot);
+        const int group = packing == XPBD_PACKING_BANKS8     ? 8
+                          : packing == XPBD_PACKING_ID_ORDER ? 0
+                                                             : 16;
+
+        // one environment's schedule (LDS variant and the residual kernel): mesh ids,
+        // packed for the LDS variant's identity placement
+        std::vector<int32_t> eslot, eptr, tslot, tptr;
+        build_schedule(pm.edge_colour, pm.num_edge_colours, eslot, eptr);
+        build_schedule(pm.tet_colour, pm.num_tet_colours, tslot, tptr);
+        if (!use_registers) {
+            xpbd::pack_colours(pm.edges.data(), 2, eptr, group, group, eslot);
+            xpbd::pack_colours(pm.tets.data(), 4, tptr, group, group, tslot);
         }
         std::vector<uint32_t> pair((size_t)E);
         std::vector<float> erest((size_t)E), trest((size_t)T);
@@ -493,28 +394,60 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
                                          (uint32_t)q[2] | ((uint32_t)q[3] << 16));
             trest[(size_t)j] = (float)pm.rest_volume[(size_t)t];
         }
-        // records of the register variant name LDS slots
-        std::vector<uint2> erec((size_t)E);
-        std::vector<uint4> trec((size_t)T);
-        for (int32_t j = 0; j < E; ++j) {
-            const int32_t e = eslot[(size_t)j];
-            uint32_t bits;
-            std::memcpy(&bits, &erest[(size_t)j], 4);
-            erec[(size_t)j] = make_uint2((uint32_t)edges_in_lds[2 * (size_t)e] |
-                                             ((uint32_t)edges_in_lds[2 * (size_t)e + 1] << 16),
-                                         bits);
+
+        // register variant: a group of G copies of the mesh (group particle e V + i,
+        // group constraint e E + j / e T + j), its LDS placement, lane packing and
+        // round-major record tables with per-wave activity and the kind / barrier
+        // masks of the round schedule
+        const int G = use_registers ? reg_group : 1;
+        const int32_t GV = G * V;
+        std::vector<int32_t> gedges((size_t)G * E * 2), gtets((size_t)G * T * 4);
+        std::vector<int32_t> gecol((size_t)G * E), gtcol((size_t)G * T);
+        for (int e = 0; e < G; ++e) {
+            for (int32_t j = 0; j < E; ++j) {
+                gecol[(size_t)e * E + j] = pm.edge_colour[(size_t)j];
+                for (int k = 0; k < 2; ++k)
+                    gedges[((size_t)e * E + j) * 2 + k] = pm.edges[2 * (size_t)j + k] + e * V;
+            }
+            for (int32_t j = 0; j < T; ++j) {
+                gtcol[(size_t)e * T + j] = pm.tet_colour[(size_t)j];
+                for (int k = 0; k < 4; ++k)
+                    gtets[((size_t)e * T + j) * 4 + k] = pm.tets[4 * (size_t)j + k] + e * V;
+            }
         }
-        for (int32_t j = 0; j < T; ++j) {
-            const int32_t *q = &tets_in_lds[4 * (size_t)tslot[(size_t)j]];
-            uint32_t bits;
-            std::memcpy(&bits, &trest[(size_t)j], 4);
-            trec[(size_t)j] = make_uint4((uint32_t)q[0] | ((uint32_t)q[1] << 16),
-                                         (uint32_t)q[2] | ((uint32_t)q[3] << 16), bits, 0u);
+        std::vector<int32_t> geslot, geptr, gtslot, gtptr;
+        build_schedule(gecol, pm.num_edge_colours, geslot, geptr);
+        build_schedule(gtcol, pm.num_tet_colours, gtslot, gtptr);
+        std::vector<int32_t> slot_of((size_t)GV);
+        std::iota(slot_of.begin(), slot_of.end(), 0);
+        std::vector<uint8_t> eorder(geslot.size(), 0), torder(gtslot.size(), 0);
+        if (use_registers) {
+            if (packing == XPBD_PACKING_SCATTERED_BANKS16 || packing == XPBD_PACKING_SEARCH) {
+                std::mt19937 gen(0x5eedu + (uint32_t)m);
+                std::shuffle(slot_of.begin(), slot_of.end(), gen);
+            }
+            if (packing == XPBD_PACKING_SEARCH) {
+                xpbd::LaneSchedule kinds[2] = {
+                    {gedges.data(), 2, &geptr, &geslot, &eorder},
+                    {gtets.data(), 4, &gtptr, &gtslot, &torder}};
+                xpbd::pack_lds(GV, slot_of, kinds, 2, 0x9e37u + (uint32_t)m, kLaneSearchEffort);
+            } else {
+                std::vector<int32_t> e_lds(gedges.size()), t_lds(gtets.size());
+                for (size_t q = 0; q < gedges.size(); ++q)
+                    e_lds[q] = slot_of[(size_t)gedges[q]];
+                for (size_t q = 0; q < gtets.size(); ++q)
+                    t_lds[q] = slot_of[(size_t)gtets[q]];
+                xpbd::pack_colours(e_lds.data(), 2, geptr, group, group, geslot);
+                xpbd::pack_colours(t_lds.data(), 4, gtptr, group, group, gtslot);
+            }
         }
-        // register variant: round-major record tables, per-wave activity and the
-        // kind / barrier masks of the round schedule
+        std::vector<uint16_t> slot16((size_t)GV), id16((size_t)GV);
+        for (int32_t i = 0; i < GV; ++i) {
+            slot16[(size_t)i] = (uint16_t)slot_of[(size_t)i];
+            id16[(size_t)slot_of[(size_t)i]] = (uint16_t)i;
+        }
         std::vector<int4> rounds;
-        build_rounds(eptr, tptr, block, rounds);
+        build_rounds(geptr, gtptr, block, rounds);
         if (rounds.size() % 2)   // the kernel runs rounds in pairs: pad with an empty round
             rounds.push_back(make_int4(0, 0, xpbd::ROUND_TET, 0));
         const int32_t num_rounds = (int32_t)rounds.size();
@@ -534,20 +467,27 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
                 const int32_t j = rd.x + l;   // slot within its kind
                 uint32_t *at = &round_rec[((size_t)r * block + l) * 3];
                 if (is_edge) {
-                    const int32_t e = eslot[(size_t)j];
-                    const uint8_t *o = xpbd::vertex_order(2, eorder[(size_t)e]);
-                    at[0] = (uint32_t)edges_in_lds[2 * (size_t)e + o[0]] |
-                            ((uint32_t)edges_in_lds[2 * (size_t)e + o[1]] << 16);
-                    at[1] = erec[(size_t)j].y;
+                    const int32_t q = geslot[(size_t)j], e = q / E, id = q - e * E;
+                    const uint8_t *o = xpbd::vertex_order(2, eorder[(size_t)q]);
+                    const uint32_t a = (uint32_t)slot_of[(size_t)gedges[2 * (size_t)q + o[0]]];
+                    const uint32_t bb = (uint32_t)slot_of[(size_t)gedges[2 * (size_t)q + o[1]]];
+                    const float rest = (float)pm.rest_length[(size_t)id];
+                    at[0] = a | (bb << 16) | ((uint32_t)e << 30);
+                    std::memcpy(&at[1], &rest, 4);
                     at[2] = 0u;
+                    rr_id[(size_t)r * block + l] = (e << 24) | id;
                 } else {
-                    const int32_t *q = &tets_in_lds[4 * (size_t)tslot[(size_t)j]];
-                    const uint8_t *o = xpbd::vertex_order(4, torder[(size_t)tslot[(size_t)j]]);
-                    at[0] = (uint32_t)q[o[0]] | ((uint32_t)q[o[1]] << 16);
-                    at[1] = (uint32_t)q[o[2]] | ((uint32_t)q[o[3]] << 16);
-                    at[2] = trec[(size_t)j].z;
+                    const int32_t q = gtslot[(size_t)j], e = q / T, id = q - e * T;
+                    const uint8_t *o = xpbd::vertex_order(4, torder[(size_t)q]);
+                    uint32_t v[4];
+                    for (int k = 0; k < 4; ++k)
+                        v[k] = (uint32_t)slot_of[(size_t)gtets[4 * (size_t)q + o[k]]];
+                    const float rest = (float)pm.rest_volume[(size_t)id];
+                    at[0] = v[0] | (v[1] << 16) | ((uint32_t)e << 30);
+                    at[1] = v[2] | (v[3] << 16);
+                    std::memcpy(&at[2], &rest, 4);
+                    rr_id[(size_t)r * block + l] = (e << 24) | (E + id);
                 }
-                rr_id[(size_t)r * block + l] = is_edge ? eslot[(size_t)j] : E + tslot[(size_t)j];
                 d.wave_active[l / 64] |= 1ull << r;
             }
             if (!is_edge)
@@ -557,7 +497,7 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         }
         d.num_rounds = use_registers ? num_rounds : 0;
         d.num_edge_rounds = edge_rounds;
-        d.num_vertices = pm.num_vertices;
+        d.num_vertices = V;
         d.num_edges = E;
         d.num_tets = T;
         d.num_edge_colours = pm.num_edge_colours;
@@ -567,23 +507,26 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         uint2 *p_quad;
         int32_t *p_eptr, *p_tptr, *p_eid, *p_tid;
         xpbd_status st;
+        std::vector<int32_t> nbr;
+        xpbd::axis_neighbours(V, pm.rest_pos.data(), nbr);
+        float *p_rest;
+        int32_t *p_nbr;
+        if ((st = b->upload(&p_rest, pm.rest_pos)) || (st = b->upload(&p_nbr, nbr)))
+            return cleanup(st);
+        d.rest_pos = p_rest;
+        d.nbr = p_nbr;
         if ((st = b->upload(&p_pair, pair)) || (st = b->upload(&p_erest, erest)) ||
             (st = b->upload(&p_quad, quad)) || (st = b->upload(&p_trest, trest)) ||
             (st = b->upload(&p_eptr, eptr)) || (st = b->upload(&p_tptr, tptr)) ||
             (st = b->upload(&p_eid, eslot)) || (st = b->upload(&p_tid, tslot)) ||
             (st = b->upload(&p_w, pm.inv_mass)))
             return cleanup(st);
-        uint2 *p_erec;
-        uint4 *p_trec;
         uint32_t *p_rr;
         int32_t *p_rrid;
         uint16_t *p_slot, *p_id;
-        if ((st = b->upload(&p_erec, erec)) || (st = b->upload(&p_trec, trec)) ||
-            (st = b->upload(&p_rr, round_rec)) || (st = b->upload(&p_rrid, rr_id)) ||
+        if ((st = b->upload(&p_rr, round_rec)) || (st = b->upload(&p_rrid, rr_id)) ||
             (st = b->upload(&p_slot, slot16)) || (st = b->upload(&p_id, id16)))
             return cleanup(st);
-        d.edge_rec = p_erec;
-        d.tet_rec = p_trec;
         d.round_rec = p_rr;
         d.rr_id = p_rrid;
         d.slot_of = p_slot;
@@ -599,6 +542,27 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         d.inv_mass = p_w;
         b->colours.insert(b->colours.end(), pm.edge_colour.begin(), pm.edge_colour.end());
         b->colours.insert(b->colours.end(), pm.tet_colour.begin(), pm.tet_colour.end());
+    }
+
+    // workgroups of the register variant: environments of one mesh, G at a time in
+    // index order; a group left short repeats its last environment as filler (~env)
+    {
+        const int G = b->envs_per_group;
+        std::vector<int32_t> groups;
+        for (int32_t m = 0; m < num_meshes; ++m) {
+            std::vector<int32_t> mine;
+            for (int32_t e = 0; e < num_envs; ++e)
+                if (env_mesh[e] == m)
+                    mine.push_back(e);
+            for (size_t k = 0; k < mine.size(); k += (size_t)G)
+                for (int f = 0; f < G; ++f)
+                    groups.push_back(k + (size_t)f < mine.size() ? mine[k + (size_t)f]
+                                                                 : ~mine[mine.size() - 1]);
+        }
+        b->num_groups = (int32_t)(groups.size() / (size_t)G);
+        xpbd_status st = b->upload(&b->groups_dev, groups);
+        if (st != XPBD_OK)
+            return cleanup(st);
     }
 
     // environments
@@ -692,6 +656,8 @@ xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
     std::memset(&a, 0, sizeof a);
     a.meshes = b->meshes_dev;
     a.envs = b->envs_dev;
+    a.groups = b->groups_dev;
+    a.num_groups = b->num_groups;
     a.compliance = b->compliance;
     a.tool_pos = tools_dev;
     a.pos = b->pos;
@@ -724,7 +690,8 @@ xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
     const bool resid = (b->params.flags & XPBD_F_RESIDUAL) != 0;
     b->residual_valid = b->residual_valid || resid;
     if (b->register_variant)
-        HIP_TRY(xpbd::launch_step_reg(a, b->block, b->lambda_banks, b->lds_bytes, resid, b->stream));
+        HIP_TRY(xpbd::launch_step_reg(a, b->block, b->lambda_banks, b->envs_per_group, b->lds_bytes,
+                                      resid, b->stream));
     else
         HIP_TRY(xpbd::launch_step(a, b->block, b->particles_per_thread, b->stage_topology,
                                   b->lds_bytes, resid, b->stream));

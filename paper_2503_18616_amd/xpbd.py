@@ -64,7 +64,16 @@ FIELD_DTYPES = {FIELD_POS: np.float32, FIELD_VEL: np.float32, FIELD_LAMBDA: np.f
 
 EXPORTED = ["xpbd_create_batch", "xpbd_step", "xpbd_read_state", "xpbd_write_state",
             "xpbd_set_flags", "xpbd_field_bytes", "xpbd_destroy_batch", "xpbd_last_error",
-            "xpbd_prepare_mesh"]
+            "xpbd_prepare_mesh", "xpbd_mlp_create", "xpbd_mlp_get_params", "xpbd_mlp_set_params",
+            "xpbd_mlp_forward", "xpbd_mlp_train_step", "xpbd_mlp_destroy", "xpbd_axis_neighbours",
+            "xpbd_step_learned"]
+
+# learned warm start (include/xpbd_learned.h)
+MLP_FEATURES = 27
+MLP_FEATURE_STRIDE = 32
+MLP_HIDDEN = 128
+MLP_OUTPUTS = 3
+MLP_PARAMS = 20483
 
 
 class XpbdMesh(ctypes.Structure):
@@ -78,7 +87,8 @@ class XpbdParams(ctypes.Structure):
                 ("iterations", ctypes.c_int32), ("gravity", ctypes.c_float * 3),
                 ("num_tools", ctypes.c_int32), ("tool_radius", ctypes.c_float * 2),
                 ("flags", ctypes.c_uint32), ("block_size", ctypes.c_int32),
-                ("solver_variant", ctypes.c_int32), ("colour_packing", ctypes.c_int32)]
+                ("solver_variant", ctypes.c_int32), ("colour_packing", ctypes.c_int32),
+                ("envs_per_group", ctypes.c_int32)]
 
 
 _lib.xpbd_create_batch.restype = ctypes.c_int
@@ -103,6 +113,31 @@ _lib.xpbd_prepare_mesh.restype = ctypes.c_int
 _lib.xpbd_prepare_mesh.argtypes = [ctypes.POINTER(XpbdMesh), ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
 
+
+class XpbdLearnedParams(ctypes.Structure):
+    _fields_ = [("apply_correction", ctypes.c_int32), ("min_iterations", ctypes.c_int32),
+                ("max_iterations", ctypes.c_int32), ("threshold", ctypes.c_float),
+                ("record_substep", ctypes.c_int32), ("record_features", ctypes.c_void_p),
+                ("record_targets", ctypes.c_void_p), ("iterations", ctypes.c_void_p)]
+
+
+_V = ctypes.c_void_p
+_lib.xpbd_mlp_create.restype = ctypes.c_int
+_lib.xpbd_mlp_create.argtypes = [_V, _V, _V, _V, ctypes.POINTER(ctypes.c_void_p)]
+_lib.xpbd_mlp_get_params.restype = ctypes.c_int
+_lib.xpbd_mlp_get_params.argtypes = [_V, _V]
+_lib.xpbd_mlp_set_params.restype = ctypes.c_int
+_lib.xpbd_mlp_set_params.argtypes = [_V, _V]
+_lib.xpbd_mlp_forward.restype = ctypes.c_int
+_lib.xpbd_mlp_forward.argtypes = [_V, _V, ctypes.c_int32, _V]
+_lib.xpbd_mlp_train_step.restype = ctypes.c_int
+_lib.xpbd_mlp_train_step.argtypes = [_V, _V, _V, ctypes.c_int32, ctypes.c_float, _V, _V]
+_lib.xpbd_mlp_destroy.restype = None
+_lib.xpbd_mlp_destroy.argtypes = [_V]
+_lib.xpbd_axis_neighbours.restype = ctypes.c_int
+_lib.xpbd_axis_neighbours.argtypes = [ctypes.POINTER(XpbdMesh), _V]
+_lib.xpbd_step_learned.restype = ctypes.c_int
+_lib.xpbd_step_learned.argtypes = [_V, _V, ctypes.c_int32, _V, ctypes.POINTER(XpbdLearnedParams)]
 
 # handle -> (num_envs, num_tools), to check tool-pose buffers before a launch
 _BATCHES = {}
@@ -151,7 +186,8 @@ def _mesh_struct(rest_pos, inv_mass, tets, keep):
 
 def make_params(dt, substeps, iterations, gravity=(0.0, 0.0, -9.81), num_tools=1,
                 tool_radius=(0.005, 0.005), flags=0, block_size=0,
-                solver_variant=VARIANT_AUTO, colour_packing=PACKING_AUTO) -> XpbdParams:
+                solver_variant=VARIANT_AUTO, colour_packing=PACKING_AUTO,
+                envs_per_group=0) -> XpbdParams:
     p = XpbdParams()
     p.dt = dt
     p.substeps = substeps
@@ -164,6 +200,7 @@ def make_params(dt, substeps, iterations, gravity=(0.0, 0.0, -9.81), num_tools=1
     p.block_size = block_size
     p.solver_variant = solver_variant
     p.colour_packing = colour_packing
+    p.envs_per_group = envs_per_group
     return p
 
 
@@ -223,18 +260,7 @@ def xpbd_step(batch, num_steps, tool_pos):
 
     The kernel reads exactly num_steps * N * tools * 3 floats, so the buffer's
     element count and dtype are checked here before the launch."""
-    n_envs, n_tools = _BATCHES.get(batch, (None, None))
-    if isinstance(tool_pos, np.ndarray):
-        tool_pos = np.ascontiguousarray(tool_pos, dtype=np.float32)
-    if n_tools and num_steps > 0:
-        need = int(num_steps) * n_envs * n_tools * 3
-        if tool_pos is None:
-            raise ValueError("tool_pos is required when the batch has tools")
-        numel = tool_pos.size if isinstance(tool_pos, np.ndarray) else tool_pos.numel()
-        if numel != need:
-            raise ValueError(f"tool_pos has {numel} elements; the launch reads {need}")
-        if not isinstance(tool_pos, np.ndarray) and str(tool_pos.dtype) != "torch.float32":
-            raise TypeError("tool_pos must be float32")
+    tool_pos = _check_tool_pos(batch, num_steps, tool_pos)
     _check(_lib.xpbd_step(batch, int(num_steps), _ptr(tool_pos)))
 
 
@@ -272,7 +298,142 @@ def xpbd_destroy_batch(batch):
     _lib.xpbd_destroy_batch(batch)
 
 
+def _check_tool_pos(batch, num_steps, tool_pos):
+    n_envs, n_tools = _BATCHES.get(batch, (None, None))
+    if isinstance(tool_pos, np.ndarray):
+        tool_pos = np.ascontiguousarray(tool_pos, dtype=np.float32)
+    if n_tools and num_steps > 0:
+        need = int(num_steps) * n_envs * n_tools * 3
+        if tool_pos is None:
+            raise ValueError("tool_pos is required when the batch has tools")
+        numel = tool_pos.size if isinstance(tool_pos, np.ndarray) else tool_pos.numel()
+        if numel != need:
+            raise ValueError(f"tool_pos has {numel} elements; the launch reads {need}")
+        if not isinstance(tool_pos, np.ndarray) and str(tool_pos.dtype) != "torch.float32":
+            raise TypeError("tool_pos must be float32")
+    return tool_pos
+
+
+def xpbd_mlp_create(params, in_scale, out_scale, stream=None):
+    """params: float32 [MLP_PARAMS] or None; in_scale [27]; out_scale [3].  Returns a handle."""
+    p = None if params is None else np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+    if p is not None and p.size != MLP_PARAMS:
+        raise ValueError(f"params must have {MLP_PARAMS} values")
+    si = np.ascontiguousarray(in_scale, dtype=np.float32).reshape(-1)
+    so = np.ascontiguousarray(out_scale, dtype=np.float32).reshape(-1)
+    if si.size != MLP_FEATURES or so.size != MLP_OUTPUTS:
+        raise ValueError("in_scale needs 27 values and out_scale 3")
+    out = ctypes.c_void_p()
+    s = default_stream() if stream is None else stream
+    _check(_lib.xpbd_mlp_create(_ptr(p), _ptr(si), _ptr(so), s or None, ctypes.byref(out)))
+    return out.value
+
+
+def xpbd_mlp_get_params(net):
+    out = np.zeros(MLP_PARAMS, np.float32)
+    _check(_lib.xpbd_mlp_get_params(net, out.ctypes.data))
+    return out
+
+
+def xpbd_mlp_set_params(net, params):
+    p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+    if p.size != MLP_PARAMS:
+        raise ValueError(f"params must have {MLP_PARAMS} values")
+    _check(_lib.xpbd_mlp_set_params(net, p.ctypes.data))
+
+
+def _device_rows(t, cols, dtype_name, what):
+    if not hasattr(t, "data_ptr") or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous device tensor")
+    if str(t.dtype) != dtype_name or t.numel() % cols:
+        raise TypeError(f"{what} must be {dtype_name} with rows of {cols}")
+    return t.numel() // cols
+
+
+def xpbd_mlp_forward(net, features, y):
+    """features: device bfloat16 [n, 32]; y: device float32 [n, 4]."""
+    n = _device_rows(features, MLP_FEATURE_STRIDE, "torch.bfloat16", "features")
+    if _device_rows(y, 4, "torch.float32", "y") != n:
+        raise ValueError("y needs one row per feature row")
+    _check(_lib.xpbd_mlp_forward(net, _ptr(features), n, _ptr(y)))
+
+
+def xpbd_mlp_train_step(net, features, targets, learning_rate, grad=None):
+    """One training step; returns the mean loss (synchronises)."""
+    n = _device_rows(features, MLP_FEATURE_STRIDE, "torch.bfloat16", "features")
+    if _device_rows(targets, 4, "torch.float32", "targets") != n:
+        raise ValueError("targets need one row per feature row")
+    if grad is not None and _device_rows(grad, MLP_PARAMS, "torch.float32", "grad") != 1:
+        raise ValueError("grad must hold MLP_PARAMS values")
+    loss = ctypes.c_float(0.0)
+    _check(_lib.xpbd_mlp_train_step(net, _ptr(features), _ptr(targets), n, float(learning_rate),
+                                    ctypes.addressof(loss), _ptr(grad)))
+    return float(loss.value)
+
+
+def xpbd_mlp_destroy(net):
+    _lib.xpbd_mlp_destroy(net)
+
+
+def xpbd_axis_neighbours(rest_pos):
+    keep = []
+    V = int(np.asarray(rest_pos).reshape(-1, 3).shape[0])
+    m = _mesh_struct(rest_pos, np.ones(V, np.float32), np.zeros((1, 4), np.int32), keep)
+    out = np.zeros((V, 6), np.int32)
+    _check(_lib.xpbd_axis_neighbours(ctypes.byref(m), out.ctypes.data))
+    return out
+
+
+def xpbd_step_learned(batch, net, num_steps, tool_pos, min_iterations, max_iterations,
+                      threshold, apply_correction=True, record_substep=-1, record_features=None,
+                      record_targets=None, iterations=None):
+    """One substep per launch with the network's correction; see include/xpbd_learned.h.
+    record_features / record_targets / iterations: device tensors (bfloat16 [NP, 32],
+    float32 [NP, 4], int32 [num_steps * substeps * N]) or None."""
+    tool_pos = _check_tool_pos(batch, num_steps, tool_pos)
+    lp = XpbdLearnedParams(int(bool(apply_correction)), int(min_iterations), int(max_iterations),
+                           float(threshold), int(record_substep), _ptr(record_features),
+                           _ptr(record_targets), _ptr(iterations))
+    _check(_lib.xpbd_step_learned(batch, net, int(num_steps), _ptr(tool_pos), ctypes.byref(lp)))
+
+
 # --------------------------------------------------------------------- convenience
+class Mlp:
+    """Owning wrapper around a network handle."""
+
+    def __init__(self, params, in_scale, out_scale, stream=None):
+        self.handle = xpbd_mlp_create(params, in_scale, out_scale, stream)
+
+    def params(self):
+        return xpbd_mlp_get_params(self.handle)
+
+    def set_params(self, params):
+        xpbd_mlp_set_params(self.handle, params)
+
+    def forward(self, features, y):
+        xpbd_mlp_forward(self.handle, features, y)
+
+    def train_step(self, features, targets, learning_rate, grad=None):
+        return xpbd_mlp_train_step(self.handle, features, targets, learning_rate, grad)
+
+    def close(self):
+        if self.handle:
+            xpbd_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 class Batch:
     """Owning wrapper around a batch handle with numpy read-back helpers."""
 
@@ -284,6 +445,11 @@ class Batch:
 
     def step(self, num_steps, tool_pos):
         xpbd_step(self.handle, num_steps, tool_pos)
+
+    def step_learned(self, net, num_steps, tool_pos, min_iterations, max_iterations, threshold,
+                     **kw):
+        xpbd_step_learned(self.handle, net.handle if net is not None else None, num_steps,
+                          tool_pos, min_iterations, max_iterations, threshold, **kw)
 
     def read(self, field, dst=None, raise_nonfinite=True):
         return xpbd_read_state(self.handle, field, dst, raise_nonfinite)

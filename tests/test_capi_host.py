@@ -1,6 +1,6 @@
 """Host-side checks of the C ABI (no GPU needed).
 
-- the shared library loads and exports every function include/xpbd.h declares;
+- the shared library loads and exports every function the headers in include/ declare;
 - the library's mesh set-up (orientation, edges, greedy colours) is bit-exact
   with the oracle's, and its float32 rest values are the oracle's FP64 values
   rounded (within one unit in the last place);
@@ -25,7 +25,8 @@ def xp():
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "xpbd.h")).read()
+    text = "".join(open(os.path.join(ROOT, "include", h)).read()
+                   for h in sorted(os.listdir(os.path.join(ROOT, "include"))) if h.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(xpbd_\w+)\s*\(", text)))
 
@@ -35,7 +36,7 @@ def test_library_exports_every_declared_symbol(xp):
     assert len(names) >= 8
     lib = ctypes.CDLL(xp.LIB_PATH)
     for n in names:
-        assert hasattr(lib, n), f"{n} declared in xpbd.h but not exported"
+        assert hasattr(lib, n), f"{n} declared in include/ but not exported"
     assert set(names) == set(xp.EXPORTED)
 
 
@@ -129,7 +130,8 @@ def _create_error(xp, meshes=None, env_mesh=None, compliance=None, **pkw):
     (dict(dt=0.0), -1), (dict(dt=float("nan")), -1), (dict(substeps=0), -1),
     (dict(iterations=-1), -1), (dict(num_tools=3), -1), (dict(tool_radius=(0.0, 0.0)), -1),
     (dict(flags=0x80), -1), (dict(block_size=96), -1), (dict(block_size=2048), -1),
-    (dict(gravity=(0.0, float("inf"), 0.0)), -1),
+    (dict(gravity=(0.0, float("inf"), 0.0)), -1), (dict(envs_per_group=3), -1),
+    (dict(envs_per_group=-1), -1), (dict(colour_packing=6), -1), (dict(solver_variant=3), -1),
 ])
 def test_create_rejects_bad_params(xp, kw, status):
     assert _create_error(xp, **kw).status == status
@@ -161,3 +163,24 @@ def test_last_error_is_cleared_by_success(xp):
     assert xp.xpbd_last_error() != ""
     xp.xpbd_prepare_mesh(m.rest_pos, m.inv_mass, m.tets)
     assert xp.xpbd_last_error() == ""
+
+
+@pytest.mark.parametrize("grid", [(1, 1, 1), (8, 5, 3), (16, 10, 4), (20, 12, 6)])
+def test_axis_neighbours_bit_exact_with_oracle(xp, grid):
+    from oracle import warmstart as ws
+    m = W.slab_mesh(*grid)
+    assert np.array_equal(xp.xpbd_axis_neighbours(m.rest_pos), ws.axis_neighbours(m.rest_pos))
+    # a shuffled and duplicated point cloud: the smallest id among equals wins on both sides
+    rng = np.random.default_rng(1)
+    pts = m.rest_pos[rng.permutation(len(m.rest_pos))]
+    pts = np.concatenate([pts, pts[:7]])
+    assert np.array_equal(xp.xpbd_axis_neighbours(pts), ws.axis_neighbours(pts))
+
+
+def test_network_create_rejects_bad_scales(xp):
+    ones27, ones3 = np.ones(27, np.float32), np.ones(3, np.float32)
+    for si, so in [(np.full(27, np.nan, np.float32), ones3), (ones27, np.zeros(3, np.float32)),
+                   (ones27, -ones3)]:
+        with pytest.raises(xp.XpbdError) as e:
+            xp.xpbd_mlp_create(None, si, so, stream=0)
+        assert e.value.status == xp.XPBD_E_ARG

@@ -1,0 +1,261 @@
+"""GPU: the learned warm start against the oracle.
+
+- the matrix-core network: forward outputs, loss gradients and one Adam step
+  against the FP64 oracle with the same bfloat16 rounding points;
+- the one-substep-per-launch stepping: without correction it reproduces the
+  fused step kernel bit for bit; with a network it follows the oracle's
+  learned driver (features, correction, residual check, fallback sweeps);
+- the recorded features and training targets against the oracle's;
+- training on the GPU from recorded substeps makes one sweep after the
+  correction beat eight plain sweeps on the constraint residual.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import warmstart as ws
+from paper_2503_18616_amd import workloads as W
+from tests import cases as K
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def xp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2503_18616_amd import xpbd
+    return xpbd
+
+
+def flat(net):
+    return np.concatenate([p.reshape(-1) for p in net.params()]).astype(np.float32)
+
+
+def unflat(net, v):
+    out, o = [], 0
+    for p in net.params():
+        out.append(np.asarray(v[o:o + p.size], np.float64).reshape(p.shape))
+        o += p.size
+    return out
+
+
+def random_net(seed, out_scale=1e-4):
+    rng = np.random.default_rng(seed)
+    net = ws.init_net(seed, in_scale=np.ones(27), out_scale=np.full(3, out_scale))
+    for b in (net.b1, net.b2, net.b3):
+        b[:] = rng.standard_normal(b.shape) * 0.05
+    # master weights live in float32 on the GPU
+    for p in net.params():
+        p[...] = p.astype(np.float32)
+    return net
+
+
+def feature_rows(a0, free):
+    """Device bfloat16 [n, 32] rows: 27 scaled features, zero padding, free flag."""
+    import torch
+    n = a0.shape[0]
+    rows = np.zeros((n, 32), np.float32)
+    rows[:, :27] = ws.bf16(a0)
+    rows[:, 31] = np.asarray(free, np.float32)
+    return torch.tensor(rows).to(torch.bfloat16).cuda()
+
+
+def test_forward_matches_oracle(xp):
+    import torch
+    net = random_net(0)
+    rng = np.random.default_rng(1)
+    n = 200                                   # not a multiple of the 64-row tile
+    a0 = ws.bf16(rng.standard_normal((n, 27)))
+    free = rng.random(n) > 0.2
+    with xp.Mlp(flat(net), np.ones(27), net.out_scale) as m:
+        y = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+        m.forward(feature_rows(a0, free), y)
+        y = y.cpu().numpy()[:, :3].astype(np.float64)
+    ref, _ = ws.forward(net, a0)
+    scale = np.abs(ref).max()
+    assert np.abs(y - ref).max() <= 2e-3 * scale, np.abs(y - ref).max() / scale
+
+
+def test_gradients_match_oracle(xp):
+    import torch
+    net = random_net(2)
+    rng = np.random.default_rng(3)
+    n = 300
+    a0 = ws.bf16(rng.standard_normal((n, 27)))
+    free = rng.random(n) > 0.3
+    t = rng.standard_normal((n, 3))
+    tgt = np.zeros((n, 4), np.float32)
+    tgt[:, :3] = t
+    with xp.Mlp(flat(net), np.ones(27), net.out_scale) as m:
+        g = torch.zeros(xp.MLP_PARAMS, dtype=torch.float32, device="cuda")
+        loss = m.train_step(feature_rows(a0, free), torch.tensor(tgt).cuda(), 0.0, grad=g)
+        g = g.cpu().numpy()
+        assert np.array_equal(m.params(), flat(net))       # learning rate 0: no update
+    ref_loss, ref_grads = ws.loss_and_grads(net, a0, t.astype(np.float32), free)
+    assert abs(loss - ref_loss) <= 1e-4 * ref_loss
+    for got, ref in zip(unflat(net, g), ref_grads):
+        scale = np.abs(ref).max()
+        assert np.abs(got - ref).max() <= 5e-3 * scale, (ref.shape, np.abs(got - ref).max() / scale)
+
+
+def test_adam_step_matches_oracle_and_training_reduces_loss(xp):
+    import torch
+    net = random_net(4)
+    rng = np.random.default_rng(5)
+    n = 256
+    a0 = ws.bf16(rng.standard_normal((n, 27)))
+    free = np.ones(n, bool)
+    t = np.tanh(a0[:, :3] * 0.5)
+    tgt = np.zeros((n, 4), np.float32)
+    tgt[:, :3] = t
+    feats, targets = feature_rows(a0, free), torch.tensor(tgt).cuda()
+    lr = 1e-3
+    with xp.Mlp(flat(net), np.ones(27), net.out_scale) as m:
+        first = m.train_step(feats, targets, lr)
+        got = unflat(net, m.params())
+        _, grads = ws.loss_and_grads(net, a0, t.astype(np.float32), free)
+        params = [p.copy() for p in net.params()]
+        ws.Adam(lr=lr).step(params, grads)
+        for g, want, old, gr in zip(got, params, net.params(), grads):
+            # Adam's first step is lr * sign(grad) wherever |grad| >> eps
+            big = np.abs(gr) > 1e-5 * np.abs(gr).max()
+            assert np.abs((g - want)[big]).max() <= 1e-6 + 0.02 * lr
+            assert np.abs(g - old).max() <= 1.01 * lr
+        for _ in range(200):
+            last = m.train_step(feats, targets, lr)
+    assert last < 0.2 * first
+
+
+def make_batch(xp, wl, flags=0):
+    p = K.lib_params(xp, wl, flags)
+    p.solver_variant = xp.VARIANT_REGISTERS
+    return xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p)
+
+
+def test_plain_substeps_equal_the_fused_step(xp):
+    wl = W.batch_workload(8, seed=11, num_steps=6)
+    tools = W.tool_path(6, 8, 11, start_depth=6e-3)
+    flags = xp.F_RESIDUAL | xp.F_LAMBDA
+    with make_batch(xp, wl, flags) as a, make_batch(xp, wl, flags) as b:
+        a.step(6, tools)
+        b.step_learned(None, 6, tools, wl.iterations, wl.iterations, np.inf,
+                       apply_correction=False)
+        assert np.array_equal(a.positions(), b.positions())
+        assert np.array_equal(a.velocities(), b.velocities())
+        for f in (xp.FIELD_LAMBDA, xp.FIELD_CONTACTS, xp.FIELD_CONTACT_COUNTS, xp.FIELD_RESIDUAL):
+            assert np.array_equal(a.read(f), b.read(f)), f
+        assert b.read(xp.FIELD_CONTACT_COUNTS).sum() > 0
+
+
+@pytest.mark.parametrize("threshold,expect_its", [(np.inf, 2), (-1.0, 4)])
+def test_learned_substeps_follow_the_oracle(xp, oracle_lib, threshold, expect_its):
+    import torch
+    wl = W.single_env_workload(seed=3)
+    steps = 20
+    tools = W.tool_path(steps, 1, 3, start_depth=6e-3)
+    in_scale = 1.0 / np.array([2e-4] * 3 + [0.1] * 3 + [2e-3] * 3 + [2e-5] * 18)
+    net = random_net(8, out_scale=2e-5)
+    net.in_scale = in_scale.astype(np.float32).astype(np.float64)
+    m0 = wl.meshes[0]
+    om = K.oracle_meshes(oracle_lib, wl)[0]
+    free = om.w > 0
+
+    def corr(x_prev, v_start, x_hat, nbr):
+        f = ws.features(x_prev, v_start, x_hat, om.rest, nbr)
+        return ws.correction(net, f, free)
+    ref = oracle_lib.run_env_learned(om, wl.compliance[0], K.oracle_params(oracle_lib, wl),
+                                     tools[:, 0], steps, corr, 2, 4, threshold)
+    assert np.all(ref.iterations == expect_its)
+    its = torch.zeros(steps * wl.substeps, dtype=torch.int32, device="cuda")
+    with make_batch(xp, wl) as b, xp.Mlp(flat(net), net.in_scale, net.out_scale) as m:
+        b.step_learned(m, steps, tools, 2, 4, threshold, iterations=its)
+        x = b.positions()
+    assert np.all(its.cpu().numpy() == expect_its)
+    err = K.max_position_error(x, ref.x)
+    assert err <= K.POS_TOL, f"max position error {err:.3e}"
+    assert np.abs(ref.x - m0.rest_pos).max() > 1e-3       # the tool and gravity moved the slab
+
+
+def test_recorded_features_and_targets_match_the_oracle(xp, oracle_lib):
+    import torch
+    wl = W.batch_workload(4, seed=5, num_steps=3)
+    tools = W.tool_path(3, 4, 5, start_depth=6e-3)
+    in_scale = (1.0 / np.array([2e-4] * 3 + [0.1] * 3 + [2e-3] * 3 + [2e-5] * 18)).astype(np.float32)
+    out_scale = np.full(3, 1e-4, np.float32)
+    net = random_net(9)
+    om = K.oracle_meshes(oracle_lib, wl)[0]
+    nbr = ws.axis_neighbours(om.rest)
+    with make_batch(xp, wl) as b, xp.Mlp(flat(net), in_scale, out_scale) as m:
+        b.step(2, tools[:2])                          # a deformed, moving start state
+        x0, v0 = b.positions().astype(np.float64), b.velocities().astype(np.float64)
+        NP = x0.shape[0]
+        feats = torch.zeros((NP, 32), dtype=torch.bfloat16, device="cuda")
+        targets = torch.zeros((NP, 4), dtype=torch.float32, device="cuda")
+        b.step_learned(m, 1, tools[2:3], wl.iterations, wl.iterations, np.inf,
+                       apply_correction=False, record_substep=0, record_features=feats,
+                       record_targets=targets)
+        feats = feats.float().cpu().numpy().astype(np.float64)
+        targets = targets.cpu().numpy().astype(np.float64)
+        offs = b.env_offsets
+    h = K.f32(wl.dt) / wl.substeps
+    g = np.array([K.f32(c) for c in wl.gravity])
+    for e in range(4):
+        sl = slice(offs[e], offs[e + 1])
+        xe, ve = x0[sl], v0[sl]
+        free = om.w > 0
+        v1 = np.where(free[:, None], ve + h * g, ve)
+        xh = np.where(free[:, None], xe + h * v1, xe)
+        want = ws.bf16(ws.features(xe, ve, xh, om.rest, nbr) * in_scale)
+        got = feats[sl]
+        assert np.array_equal(got[:, 31], free.astype(np.float64))
+        assert np.all(got[:, 27:31] == 0.0)
+        # float32 on the GPU, float64 here: at most one bfloat16 step apart
+        step = np.maximum(np.abs(want), 1e-30) * 2.0 ** -7
+        assert np.all(np.abs(got[:, :27] - want) <= step + 1e-6)
+        # targets: (x after the sweeps - x_hat) / out_scale of free particles
+        res = oracle_lib.run_env_learned(om, wl.compliance[e],
+                                         oracle_lib.OracleParams(K.f32(wl.dt) / wl.substeps, 1,
+                                                                 wl.iterations, tuple(g),
+                                                                 1, tuple(wl.tool_radius)),
+                                         tools[2:3, e], 1, None, wl.iterations, wl.iterations,
+                                         np.inf, x0=xe, v0=ve)
+        want_t = np.where(free[:, None], (res.x - xh) / out_scale, 0.0)
+        assert np.abs(targets[sl][:, :3] - want_t).max() <= 2e-3 * np.abs(want_t).max() + 1e-3
+
+
+def test_trained_network_beats_plain_sweeps(xp):
+    """Record substeps of the plain solver (8 sweeps) on 64 contact-free
+    environments, train the network on the GPU, then compare the constraint
+    residual after 1 sweep from the corrected prediction with that after 8
+    plain sweeps, from the same states."""
+    import torch
+    from paper_2503_18616_amd import warmstart as trainer
+    wl = W.batch_workload(64, seed=21, num_steps=40)
+    wl.num_tools = 0
+    I = wl.iterations
+    with make_batch(xp, wl) as b:
+        b.step(6, None)                                   # sagging under gravity
+        with xp.Mlp(None, np.ones(27), np.ones(3)) as pilot:
+            f0, t0 = trainer.record(b, pilot, None, [0, 5], I)
+        in_s, out_s = trainer.scales(f0, t0)
+        with xp.Mlp(trainer.he_init(0), in_s, out_s) as net:
+            feats, targets = trainer.record(b, net, None, [1, 3, 5, 7, 9, 2, 4, 6, 8, 0], I)
+            losses = trainer.train(net, feats, targets, 800)
+            assert np.mean(losses[-20:]) < 0.1 * np.mean(losses[:5])
+            x, v = b.positions(), b.velocities()
+            res = {}
+            for name, learned in (("plain", False), ("learned", True)):
+                with make_batch(xp, wl, xp.F_RESIDUAL) as e:
+                    e.write(xp.FIELD_POS, x)
+                    e.write(xp.FIELD_VEL, v)
+                    r = []
+                    for _ in range(3):
+                        if learned:
+                            e.step_learned(net, 1, None, 1, 1, np.inf)
+                        else:
+                            e.step(1, None)
+                        r.append(e.read(xp.FIELD_RESIDUAL).reshape(-1, 2)[:, 0].mean())
+                    res[name] = float(np.mean(r))
+    print(f"residual RMS: plain 8 sweeps {res['plain']:.3e}, learned 1 sweep {res['learned']:.3e}")
+    assert res["learned"] < res["plain"]
