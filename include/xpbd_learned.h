@@ -11,9 +11,9 @@
  * square-rooted, as XPBD_FIELD_RESIDUAL reports it) is compared with a
  * threshold, and the sweeps continue to max_iterations when it is above.
  *
- * Features of particle i (float32, then multiplied by in_scale and rounded to
- * bfloat16), from the start-of-substep positions x and velocities v, the
- * predicted positions x_hat and the rest positions X:
+ * Features f of particle i (float32; the network sees (f - in_shift) * in_scale
+ * rounded to bfloat16), from the start-of-substep positions x and velocities
+ * v, the predicted positions x_hat and the rest positions X:
  *   [0:3] x_hat_i - x_i, [3:6] v_i, [6:9] x_hat_i - X_i,
  *   [9 + 3k : 12 + 3k] (x_hat_n - x_hat_i) - (X_n - X_i) for the axis
  *   neighbour n of i in direction k = -x, +x, -y, +y, -z, +z (0 if none);
@@ -24,12 +24,15 @@
  *
  * Network (weights [out][in], float32 master copy, bfloat16 operands of the
  * matrix cores, float32 accumulation): a1 = bf16(relu(a0 W1^T + b1)),
- * a2 = bf16(relu(a1 W2^T + b2)), y = a2 W3^T + b3, correction = y * out_scale
- * (applied to free particles only).  Flat parameter order (float32):
+ * a2 = bf16(relu(a1 W2^T + b2)), y = a2 W3^T + b3, correction =
+ * out_shift + clamp(y, -8, 8) * out_scale (applied to free particles only;
+ * the clamp keeps a network queried outside its training range from throwing
+ * particles far).  Flat parameter order (float32):
  * W1 [128][27], b1 [128], W2 [128][128], b2 [128], W3 [3][128], b3 [3].
  *
  * Training: mean squared error over the free rows of a batch,
- * L = (1/2n) sum |y - t|^2, t the target in scaled units; gradients from the
+ * L = (1/2n) sum |y - t|^2, t = (x - x_hat - out_shift) / out_scale the
+ * normalised correction the sweeps found; gradients from the
  * unnormalised error with bfloat16 backward operands, divided by n; one Adam
  * step (beta1 0.9, beta2 0.999, eps 1e-8) on the float32 master weights.
  *
@@ -58,12 +61,14 @@ extern "C" {
 typedef struct xpbd_mlp xpbd_mlp;
 
 /* Create a network on the current device.  params: [XPBD_MLP_PARAMS] initial
- * float32 weights (NULL: all zero); in_scale: [27] feature scales; out_scale:
- * [3] correction scales (metres per network unit).  Adam state starts at zero.
+ * float32 weights (NULL: all zero); in_shift, in_scale: [27] feature
+ * normalisation; out_shift (m), out_scale (m per network unit): [3]; either
+ * shift may be NULL (zero).  Adam state starts at zero.
  * hip_stream: the stream every later call of this network uses (NULL: null
  * stream).  The network owns its device memory until xpbd_mlp_destroy. */
-xpbd_status xpbd_mlp_create(const float *params, const float *in_scale, const float *out_scale,
-                            void *hip_stream, xpbd_mlp **out);
+xpbd_status xpbd_mlp_create(const float *params, const float *in_shift, const float *in_scale,
+                            const float *out_shift, const float *out_scale, void *hip_stream,
+                            xpbd_mlp **out);
 
 /* Copy the float32 master weights to params [XPBD_MLP_PARAMS] (host);
  * synchronises the stream. */
@@ -76,14 +81,17 @@ xpbd_status xpbd_mlp_set_params(xpbd_mlp *net, const float *params);
  * feature rows (device bfloat16 [n][XPBD_MLP_FEATURE_STRIDE]). */
 xpbd_status xpbd_mlp_forward(xpbd_mlp *net, const uint16_t *features, int32_t n, float *y);
 
-/* One training step on n rows: features (device bfloat16 [n][32]; row r
- * counts only if its free flag, feature 31, is set), targets (device float32
- * [n][4], scaled units, columns 0..2).  learning_rate 0 computes the loss and
- * gradient without updating.  loss (host, may be NULL) receives the mean loss
- * (synchronises); grad (device float32 [XPBD_MLP_PARAMS], may be NULL) the
- * normalised gradient.  n >= 1. */
+/* One training step on n samples: sample j is row rows[j] (device int32 [n];
+ * the caller keeps every index inside the two tables) or, with rows NULL,
+ * row j of features (device bfloat16 [.][32]; a row counts only if its free
+ * flag, feature 31, is set) and targets (device float32 [.][4], normalised,
+ * columns 0..2).  learning_rate 0 computes the loss and gradient without
+ * updating.  loss (host, may be NULL) receives the mean loss (synchronises);
+ * grad (device float32 [XPBD_MLP_PARAMS], may be NULL) the normalised
+ * gradient.  n >= 1. */
 xpbd_status xpbd_mlp_train_step(xpbd_mlp *net, const uint16_t *features, const float *targets,
-                                int32_t n, float learning_rate, float *loss, float *grad);
+                                const int32_t *rows, int32_t n, float learning_rate, float *loss,
+                                float *grad);
 
 void xpbd_mlp_destroy(xpbd_mlp *net);
 
@@ -98,13 +106,13 @@ typedef struct {
     int32_t record_substep;    /* -1: none; else the substep (of every step) whose features and
                                   training targets are written to the two buffers below */
     uint16_t *record_features; /* device bfloat16 [total particles][32] */
-    float *record_targets;     /* device float32 [total particles][4]: (x - x_hat) / out_scale
-                                  after the sweeps (zero rows for pinned particles) */
+    float *record_targets;     /* device float32 [total particles][4]: (x - x_hat - out_shift) /
+                                  out_scale after the sweeps (zero rows for pinned particles) */
     int32_t *iterations;       /* device int32 [num_steps][substeps][N] sweeps run, or NULL */
 } xpbd_learned_params;
 
 /* Advance every environment by num_steps steps one substep at a time: the
- * prediction and the features (with net's in_scale), the network's correction
+ * prediction and the features (with net's normalisation), the network's correction
  * when apply_correction is set, then the sweeps of xpbd_learned_params.
  * tool_pos as in xpbd_step.  net may be NULL only without correction and
  * without recording (plain sweeps with the residual check).  Needs the

@@ -25,13 +25,14 @@ Everything here is the plain definition written out in float64:
              (x_hat_n - x_hat_i) - (X_n - X_i), or 0 without a neighbour.
   The axis neighbour of i in direction +x is the particle with the same rest
   y and z and the smallest rest x above X_i (likewise for the other five).
-* Network: a0 = bf16(f * in_scale); z1 = a0 W1^T + b1; a1 = bf16(relu(z1));
-  z2 = a1 W2^T + b2; a2 = bf16(relu(z2)); y = a2 W3^T + b3; correction =
-  y * out_scale.  Weights are stored [out][in]; bf16() rounds to the nearest
+* Network: a0 = bf16((f - in_shift) * in_scale); z1 = a0 W1^T + b1;
+  a1 = bf16(relu(z1)); z2 = a1 W2^T + b2; a2 = bf16(relu(z2)); y = a2 W3^T + b3;
+  correction = out_shift + clamp(y, -8, 8) * out_scale.  Weights are stored [out][in]; bf16() rounds to the nearest
   bfloat16 (ties to even) at exactly the points where the GPU keeps bfloat16
   operands of its matrix cores; every sum is exact here (float64).
 * Loss over the free particles of a batch: L = (1/2n) sum_i |y_i - t_i|^2 with
-  t_i = (x_after_i - x_hat_i) / out_scale, n the number of free particles;
+  t_i = (x_after_i - x_hat_i - out_shift) / out_scale, n the number of free
+  particles;
   its gradient by the chain rule, computed on the unnormalised error
   dy_i = y_i - t_i of the free particles with the same bfloat16 rounding of
   the backward operands (bf16(dz) before each product with a weight matrix
@@ -49,6 +50,7 @@ import numpy as np
 FEATURES = 27
 HIDDEN = 128
 OUTPUTS = 3
+CLIP = 8.0     # bound of the network output used as a correction
 
 
 def bf16(x):
@@ -107,6 +109,8 @@ class Net:
     b3: np.ndarray
     in_scale: np.ndarray = field(default_factory=lambda: np.ones(FEATURES))
     out_scale: np.ndarray = field(default_factory=lambda: np.ones(OUTPUTS))
+    in_shift: np.ndarray = field(default_factory=lambda: np.zeros(FEATURES))
+    out_shift: np.ndarray = field(default_factory=lambda: np.zeros(OUTPUTS))
 
     def params(self):
         return [self.W1, self.b1, self.W2, self.b2, self.W3, self.b3]
@@ -115,7 +119,7 @@ class Net:
 def forward(net: Net, f, emulate_bf16=True):
     """Network output y [n, 3] (scaled units) and the cache for backward."""
     r = bf16 if emulate_bf16 else (lambda a: np.asarray(a, np.float64))
-    a0 = r(np.asarray(f, np.float64) * net.in_scale)
+    a0 = r((np.asarray(f, np.float64) - net.in_shift) * net.in_scale)
     z1 = a0 @ r(net.W1).T + net.b1
     a1 = r(np.maximum(z1, 0.0))
     z2 = a1 @ r(net.W2).T + net.b2
@@ -127,7 +131,8 @@ def forward(net: Net, f, emulate_bf16=True):
 def correction(net: Net, f, free, emulate_bf16=True):
     """Correction of the predicted positions [n, 3] (m); zero for pinned particles."""
     y, _ = forward(net, f, emulate_bf16)
-    return np.where(np.asarray(free)[:, None], y * net.out_scale, 0.0)
+    c = net.out_shift + np.clip(y, -CLIP, CLIP) * net.out_scale
+    return np.where(np.asarray(free)[:, None], c, 0.0)
 
 
 def loss_and_grads(net: Net, f, target, mask, emulate_bf16=True):

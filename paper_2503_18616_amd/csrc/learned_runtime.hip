@@ -26,6 +26,7 @@ struct xpbd_mlp {
     int device = 0;
     hipStream_t stream = nullptr;
     xpbd::MlpDev d{};
+    float *in_shift = nullptr;               // device [32]
     float *in_scale = nullptr;               // device [32]
     std::vector<xpbd::DeviceBuffer> allocations;
     float *partial = nullptr;                // [groups][params] training scratch
@@ -83,8 +84,9 @@ xpbd_status upload_params(xpbd_mlp *net, const float *params)
 
 extern "C" {
 
-xpbd_status xpbd_mlp_create(const float *params, const float *in_scale, const float *out_scale,
-                            void *hip_stream, xpbd_mlp **out)
+xpbd_status xpbd_mlp_create(const float *params, const float *in_shift, const float *in_scale,
+                            const float *out_shift, const float *out_scale, void *hip_stream,
+                            xpbd_mlp **out)
 {
     g_error.clear();
     if (!out)
@@ -93,11 +95,12 @@ xpbd_status xpbd_mlp_create(const float *params, const float *in_scale, const fl
     if (!in_scale || !out_scale)
         return fail(XPBD_E_ARG, "in_scale and out_scale are required");
     for (int k = 0; k < XPBD_MLP_FEATURES; ++k)
-        if (!std::isfinite(in_scale[k]))
-            return fail(XPBD_E_ARG, "in_scale[%d] is not finite", k);
+        if (!std::isfinite(in_scale[k]) || (in_shift && !std::isfinite(in_shift[k])))
+            return fail(XPBD_E_ARG, "in_shift[%d] / in_scale[%d] are not finite", k, k);
     for (int k = 0; k < XPBD_MLP_OUTPUTS; ++k)
-        if (!(std::isfinite(out_scale[k]) && out_scale[k] > 0.0f))
-            return fail(XPBD_E_ARG, "out_scale[%d] must be finite and > 0", k);
+        if (!(std::isfinite(out_scale[k]) && out_scale[k] > 0.0f) ||
+            (out_shift && !std::isfinite(out_shift[k])))
+            return fail(XPBD_E_ARG, "out_scale[%d] must be finite and > 0, out_shift finite", k);
     auto *net = new xpbd_mlp();
     net->stream = reinterpret_cast<hipStream_t>(hip_stream);
     auto cleanup = [&](xpbd_status st) {
@@ -117,14 +120,21 @@ xpbd_status xpbd_mlp_create(const float *params, const float *in_scale, const fl
         (st = net->zeros(&d.w3t, (size_t)xpbd::kMlpHidden * 32)) ||
         (st = net->zeros(&d.b1, xpbd::kMlpHidden)) || (st = net->zeros(&d.b2, xpbd::kMlpHidden)) ||
         (st = net->zeros(&d.b3, 4)) || (st = net->zeros(&d.out_scale, 4)) ||
+        (st = net->zeros(&d.out_shift, 4)) || (st = net->zeros(&net->in_shift, 32)) ||
         (st = net->zeros(&net->in_scale, 32)) || (st = net->zeros(&net->loss, 1)))
         return cleanup(st);
-    float in32[32] = {0.0f}, out4[4] = {0.0f};
-    std::memcpy(in32, in_scale, sizeof(float) * XPBD_MLP_FEATURES);
-    std::memcpy(out4, out_scale, sizeof(float) * XPBD_MLP_OUTPUTS);
-    if (hipMemcpy(net->in_scale, in32, sizeof in32, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d.out_scale, out4, sizeof out4, hipMemcpyHostToDevice) != hipSuccess)
-        return cleanup(fail(XPBD_E_HIP, "upload of the scales failed"));
+    float in_sh[32] = {0.0f}, in_sc[32] = {0.0f}, out_sh[4] = {0.0f}, out_sc[4] = {0.0f};
+    std::memcpy(in_sc, in_scale, sizeof(float) * XPBD_MLP_FEATURES);
+    std::memcpy(out_sc, out_scale, sizeof(float) * XPBD_MLP_OUTPUTS);
+    if (in_shift)
+        std::memcpy(in_sh, in_shift, sizeof(float) * XPBD_MLP_FEATURES);
+    if (out_shift)
+        std::memcpy(out_sh, out_shift, sizeof(float) * XPBD_MLP_OUTPUTS);
+    if (hipMemcpy(net->in_scale, in_sc, sizeof in_sc, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(net->in_shift, in_sh, sizeof in_sh, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d.out_scale, out_sc, sizeof out_sc, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d.out_shift, out_sh, sizeof out_sh, hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(XPBD_E_HIP, "upload of the normalisation failed"));
     if ((st = upload_params(net, params)))
         return cleanup(st);
     *out = net;
@@ -163,7 +173,8 @@ xpbd_status xpbd_mlp_forward(xpbd_mlp *net, const uint16_t *features, int32_t n,
 }
 
 xpbd_status xpbd_mlp_train_step(xpbd_mlp *net, const uint16_t *features, const float *targets,
-                                int32_t n, float learning_rate, float *loss, float *grad)
+                                const int32_t *rows, int32_t n, float learning_rate, float *loss,
+                                float *grad)
 {
     g_error.clear();
     if (!net || !features || !targets || n < 1)
@@ -171,8 +182,8 @@ xpbd_status xpbd_mlp_train_step(xpbd_mlp *net, const uint16_t *features, const f
     if (!(std::isfinite(learning_rate) && learning_rate >= 0.0f))
         return fail(XPBD_E_ARG, "learning_rate must be finite and >= 0");
     if (!is_device_pointer(features) || !is_device_pointer(targets) ||
-        (grad && !is_device_pointer(grad)))
-        return fail(XPBD_E_ARG, "features, targets and grad must be device memory");
+        (grad && !is_device_pointer(grad)) || (rows && !is_device_pointer(rows)))
+        return fail(XPBD_E_ARG, "features, targets, rows and grad must be device memory");
     const int groups = (n + xpbd::kMlpTile - 1) / xpbd::kMlpTile;
     if (groups > net->partial_groups) {
         HIP_TRY(hipStreamSynchronize(net->stream));
@@ -190,7 +201,7 @@ xpbd_status xpbd_mlp_train_step(xpbd_mlp *net, const uint16_t *features, const f
     int step = net->adam_step;
     if (learning_rate > 0.0f)
         step = ++net->adam_step;
-    HIP_TRY(xpbd::launch_mlp_train(net->d, features, targets, n, net->partial, net->stats,
+    HIP_TRY(xpbd::launch_mlp_train(net->d, features, targets, rows, n, net->partial, net->stats,
                                    learning_rate, 0.9f, 0.999f, 1e-8f, step, grad, net->loss,
                                    net->stream));
     if (loss) {
@@ -311,7 +322,9 @@ xpbd_status xpbd_step_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
     std::memset(&L, 0, sizeof L);
     L.xhat = b->learned_xhat;
     L.cand = b->learned_cand;
+    L.in_shift = net ? net->in_shift : nullptr;
     L.in_scale = net ? net->in_scale : nullptr;
+    L.out_shift = net ? net->d.out_shift : nullptr;
     L.out_scale = net ? net->d.out_scale : nullptr;
     L.threshold = lp->threshold;
     L.min_iterations = lp->min_iterations;

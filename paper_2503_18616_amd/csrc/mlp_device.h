@@ -13,6 +13,7 @@ constexpr int kMlpFeatPad = 32;    // row width of a feature record (bf16); colu
 constexpr int kMlpHidden = 128;
 constexpr int kMlpOutputs = 3;
 constexpr int kMlpTile = 64;       // samples per workgroup
+constexpr float kMlpClip = 8.0f;   // the correction clamps y to [-8, 8] (network units)
 
 // Flat parameter order (float32): W1 [128][27], b1 [128], W2 [128][128], b2 [128],
 // W3 [3][128], b3 [3]; weights are [out][in].
@@ -33,6 +34,7 @@ struct MlpDev {
     float *adam_v;      // [kMlpParams]
     uint16_t *w1, *w2, *w2t, *w3, *w3t;
     float *b1, *b2, *b3;   // float32 biases used by the kernels
+    float *out_shift;      // [4]  correction = out_shift + clamp(y) * out_scale
     float *out_scale;      // [4]
 };
 
@@ -45,13 +47,14 @@ hipError_t launch_mlp_sync(const MlpDev &net, hipStream_t stream);
 // row whose free flag is set.
 hipError_t launch_mlp_forward(const MlpDev &net, const uint16_t *feat, int n, float *y_out,
                               float *pos, int64_t np, hipStream_t stream);
-// Gradient of the masked mean squared error on n rows, then one Adam step
+// Gradient of the masked mean squared error on n samples (sample j is row
+// rows[j] of feat / targets, or row j without a row list), then one Adam step
 // (skipped when lr == 0).  partial: [ceil(n / 64)][kMlpParams], stats:
 // [ceil(n / 64)][2] scratch; grad_out (float32 [kMlpParams]) and loss_out may
 // be null.
-hipError_t launch_mlp_train(const MlpDev &net, const uint16_t *feat, const float *targets, int n,
-                            float *partial, float *stats, float lr, float beta1, float beta2,
-                            float eps, int step, float *grad_out, float *loss_out,
-                            hipStream_t stream);
+hipError_t launch_mlp_train(const MlpDev &net, const uint16_t *feat, const float *targets,
+                            const int32_t *rows, int n, float *partial, float *stats, float lr,
+                            float beta1, float beta2, float eps, int step, float *grad_out,
+                            float *loss_out, hipStream_t stream);
 
 }  // namespace xpbd

@@ -1,10 +1,10 @@
 // Matrix-core kernels of the learned warm start (gfx950, v_mfma_f32_16x16x32_bf16).
 //
-// The network maps 27 scaled features of a particle's predicted state to a
-// correction of its predicted position: a0 = bf16(features * in_scale),
+// The network maps 27 normalised features of a particle's predicted state to a
+// correction of its predicted position: a0 = bf16((f - in_shift) * in_scale),
 // a1 = bf16(relu(a0 W1^T + b1)), a2 = bf16(relu(a1 W2^T + b2)),
-// y = a2 W3^T + b3 (float32), correction = y * out_scale.  Products take
-// bfloat16 operands and accumulate in float32.
+// y = a2 W3^T + b3 (float32), correction = out_shift + clamp(y, -8, 8) * out_scale.
+// Products take bfloat16 operands and accumulate in float32.
 //
 // A workgroup of 4 waves takes 64 samples.  MFMA 16x16x32 operand layout:
 // lane l supplies row/column l % 16 and the 8 consecutive k values
@@ -72,16 +72,19 @@ struct MlpFwdLds {
     uint16_t a2[S * PH];
 };
 
-// Load the features of samples base .. base + S (rows beyond n are zero); the
-// unit-major copy only when a0t is given.
-__device__ void load_features(uint16_t *a0, uint16_t *a0t, const uint16_t *feat, int64_t base,
-                              int n, int tid)
+// Load the features of samples base .. base + S (rows beyond n are zero); sample
+// j reads row rows[j] when a row list is given, else row j.  The unit-major
+// copy only when a0t is given.
+__device__ void load_features(uint16_t *a0, uint16_t *a0t, const uint16_t *feat,
+                              const int32_t *rows, int64_t base, int n, int tid)
 {
     for (int i = tid; i < S * F / 8; i += 256) {
         const int s = i / (F / 8), c = (i % (F / 8)) * 8;
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (base + s < n)
-            v = *reinterpret_cast<const uint4 *>(feat + (base + s) * F + c);
+        if (base + s < n) {
+            const int64_t r = rows ? (int64_t)rows[base + s] : base + s;
+            v = *reinterpret_cast<const uint4 *>(feat + r * F + c);
+        }
         *reinterpret_cast<uint4 *>(&a0[s * PF + c]) = v;
         if (a0t) {
             const uint16_t *e = reinterpret_cast<const uint16_t *>(&v);
@@ -160,7 +163,7 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(MlpDev net, const uint
     __shared__ MlpFwdLds L;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t base = (int64_t)blockIdx.x * S;
-    load_features(L.a0, nullptr, feat, base, n, tid);
+    load_features(L.a0, nullptr, feat, nullptr, base, n, tid);
     __syncthreads();
     hidden_layer<F, false>(L.a0, PF, net.w1, net.b1, L.a1, nullptr, nullptr, wave, lane);
     __syncthreads();
@@ -178,7 +181,8 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(MlpDev net, const uint
             if (MODE == 0) {
                 y_out[(base + s) * 4 + o] = y;
             } else if (bf16_float(L.a0[s * PF + 31]) > 0.f) {
-                pos[(int64_t)o * np + base + s] += y * net.out_scale[o];
+                const float yc = fminf(fmaxf(y, -kMlpClip), kMlpClip);
+                pos[(int64_t)o * np + base + s] += net.out_shift[o] + yc * net.out_scale[o];
             }
         }
     }
@@ -199,14 +203,14 @@ __device__ __forceinline__ float column_sum(f32x4 v)
 // (unnormalised) go to partial[blockIdx.x][param], its loss sum and sample
 // count to stats[blockIdx.x][2].  targets: float32 [n][4] in scaled units.
 __global__ void __launch_bounds__(256) mlp_grad_kernel(MlpDev net, const uint16_t *feat,
-                                                       const float *targets, int n, float *partial,
-                                                       float *stats)
+                                                       const float *targets, const int32_t *rows,
+                                                       int n, float *partial, float *stats)
 {
     __shared__ MlpLds L;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t base = (int64_t)blockIdx.x * S;
     float *g = partial + (int64_t)blockIdx.x * kMlpParams;
-    load_features(L.a0, L.a0t, feat, base, n, tid);
+    load_features(L.a0, L.a0t, feat, rows, base, n, tid);
     forward_train(L, net, tid, wave, lane);
 
     // output error dy = (y - t) * free for the 16 samples of this wave
@@ -224,7 +228,8 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(MlpDev net, const uint16_
             const int s = 16 * wave + 4 * (lane >> 4) + e;
             float d = 0.f;
             if (o < 3 && base + s < n && bf16_float(L.a0[s * PF + 31]) > 0.f) {
-                d = acc[e] + net.b3[o] - targets[(base + s) * 4 + o];
+                const int64_t r = rows ? (int64_t)rows[base + s] : base + s;
+                d = acc[e] + net.b3[o] - targets[r * 4 + o];
                 cnt += o == 0 ? 1.f : 0.f;
             }
             dsum += d;
@@ -446,14 +451,14 @@ hipError_t launch_mlp_forward(const MlpDev &net, const uint16_t *feat, int n, fl
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_train(const MlpDev &net, const uint16_t *feat, const float *targets, int n,
-                            float *partial, float *stats, float lr, float beta1, float beta2,
-                            float eps, int step, float *grad_out, float *loss_out,
-                            hipStream_t stream)
+hipError_t launch_mlp_train(const MlpDev &net, const uint16_t *feat, const float *targets,
+                            const int32_t *rows, int n, float *partial, float *stats, float lr,
+                            float beta1, float beta2, float eps, int step, float *grad_out,
+                            float *loss_out, hipStream_t stream)
 {
     const int groups = (n + S - 1) / S;
     hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)groups), dim3(256), 0, stream, net, feat,
-                       targets, n, partial, stats);
+                       targets, rows, n, partial, stats);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;

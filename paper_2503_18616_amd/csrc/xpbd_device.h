@@ -98,9 +98,11 @@ struct LearnedArgs {
     float *xhat;                 // [3][total particles] predicted (then corrected) positions
     uint16_t *features;          // [total particles][32] bfloat16 scaled features, [31] = free flag
     uint8_t *cand;               // [total particles] bit t: candidate of tool t in this step
+    const float *in_shift;       // [32] features are (f - in_shift) * in_scale
     const float *in_scale;       // [32]
+    const float *out_shift;      // [4]
     const float *out_scale;      // [4]
-    float *record_targets;       // [total particles][4] (x - x_hat) / out_scale, or null
+    float *record_targets;       // [total particles][4] (x - x_hat - out_shift) / out_scale, or null
     int32_t *iterations;         // [N] sweeps run in this substep, or null
     float threshold;             // residual RMS above which the sweeps continue
     int32_t min_iterations;

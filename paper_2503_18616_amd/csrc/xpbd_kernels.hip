@@ -823,7 +823,8 @@ __device__ __forceinline__ uint16_t to_bf16(float f)
 // Prediction of one substep (Alg. 1) into L.xhat, and the features of every
 // particle: predicted displacement, start-of-substep velocity, displacement
 // from rest, and the six axis-neighbour offsets minus their rest offsets,
-// scaled by in_scale and rounded to bfloat16; feature 31 flags a free particle.
+// normalised ((f - in_shift) * in_scale) and rounded to bfloat16; feature 31
+// flags a free particle.
 // Grid: (ceil(max V / 256), environments).
 __global__ void __launch_bounds__(256) learned_predict_kernel(StepArgs A, LearnedArgs L)
 {
@@ -885,8 +886,9 @@ __global__ void __launch_bounds__(256) learned_predict_kernel(StepArgs A, Learne
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         const int c0 = 2 * c, c1 = 2 * c + 1;
-        const uint16_t lo = c0 < 27 ? to_bf16(f[c0] * L.in_scale[c0]) : (uint16_t)0;
-        uint16_t hi = c1 < 27 ? to_bf16(f[c1] * L.in_scale[c1]) : (uint16_t)0;
+        const uint16_t lo =
+            c0 < 27 ? to_bf16((f[c0] - L.in_shift[c0]) * L.in_scale[c0]) : (uint16_t)0;
+        uint16_t hi = c1 < 27 ? to_bf16((f[c1] - L.in_shift[c1]) * L.in_scale[c1]) : (uint16_t)0;
         if (c1 == 31)
             hi = md.inv_mass[i] > 0.0f ? (uint16_t)0x3f80 : (uint16_t)0;   // bfloat16 1.0
         packed[c] = (uint32_t)lo | ((uint32_t)hi << 16);
@@ -1087,9 +1089,10 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
         if (L.record_targets) {
             const bool free_p = p.w > 0.0f;
             float *t = L.record_targets + (size_t)(off + i) * 4;
-            t[0] = free_p ? (p.x - L.xhat[off + i]) / L.out_scale[0] : 0.0f;
-            t[1] = free_p ? (p.y - L.xhat[NP + off + i]) / L.out_scale[1] : 0.0f;
-            t[2] = free_p ? (p.z - L.xhat[2 * NP + off + i]) / L.out_scale[2] : 0.0f;
+            t[0] = free_p ? ((p.x - L.xhat[off + i]) - L.out_shift[0]) / L.out_scale[0] : 0.0f;
+            t[1] = free_p ? ((p.y - L.xhat[NP + off + i]) - L.out_shift[1]) / L.out_scale[1] : 0.0f;
+            t[2] = free_p ? ((p.z - L.xhat[2 * NP + off + i]) - L.out_shift[2]) / L.out_scale[2]
+                          : 0.0f;
             t[3] = 0.0f;
         }
         A.pos[off + i] = p.x;

@@ -41,29 +41,36 @@ def record(batch: "xpbd.Batch", net: "xpbd.Mlp", tool_pos, substeps, iterations)
     return feats, targets
 
 
-def scales(feats, targets):
-    """Feature scales 1 / std and output scales std over the free rows of a
-    recording made with unit scales."""
-    f = feats.float().cpu().numpy()
-    t = targets.cpu().numpy()
+def normalisation(feats, targets):
+    """(in_shift, in_scale, out_shift, out_scale): means and 1 / std of the
+    features, means and std of the targets, over the free rows of a recording
+    made with the identity normalisation."""
+    f = feats.float().cpu().numpy().astype(np.float64)
+    t = targets.cpu().numpy().astype(np.float64)
     free = f[:, 31] > 0
-    sf = f[free, :xpbd.MLP_FEATURES].std(axis=0)
-    st = t[free, :3].std(axis=0)
-    in_scale = np.where(sf > 0, 1.0 / np.maximum(sf, 1e-30), 1.0).astype(np.float32)
-    out_scale = np.maximum(st, 1e-12).astype(np.float32)
-    return in_scale, out_scale
+    mf, sf = f[free, :xpbd.MLP_FEATURES].mean(axis=0), f[free, :xpbd.MLP_FEATURES].std(axis=0)
+    mt, st = t[free, :3].mean(axis=0), t[free, :3].std(axis=0)
+    in_scale = np.where(sf > 0, 1.0 / np.maximum(sf, 1e-30), 1.0)
+    return (mf.astype(np.float32), in_scale.astype(np.float32), mt.astype(np.float32),
+            np.maximum(st, 1e-12).astype(np.float32))
 
 
-def train(net: "xpbd.Mlp", feats, targets, steps: int, window: int = 8192, lr: float = 1e-3,
+def train(net: "xpbd.Mlp", feats, targets, steps: int, batch: int = 8192, lr: float = 1e-3,
           seed: int = 0, final_lr: float = 1e-4):
-    """Adam steps over random windows of the recorded rows (learning rate decays
-    geometrically from lr to final_lr).  Returns the loss of every step."""
+    """Adam steps on minibatches drawn from a seeded permutation of the free
+    recorded rows (epoch after epoch; the learning rate decays geometrically
+    from lr to final_lr).  Returns the loss of every step."""
+    import torch
     rng = np.random.default_rng(seed)
-    rows = feats.shape[0]
-    window = min(window, rows)
-    losses = []
+    free = np.flatnonzero(feats[:, 31].float().cpu().numpy() > 0).astype(np.int32)
+    batch = min(batch, free.size)
+    order = torch.from_numpy(free[rng.permutation(free.size)]).cuda()
+    losses, at = [], 0
     for s in range(steps):
+        if at + batch > free.size:
+            order = torch.from_numpy(free[rng.permutation(free.size)]).cuda()
+            at = 0
         rate = lr * (final_lr / lr) ** (s / max(steps - 1, 1))
-        o = int(rng.integers(0, rows - window + 1))
-        losses.append(net.train_step(feats[o:o + window], targets[o:o + window], rate))
+        losses.append(net.train_step(feats, targets, rate, rows=order[at:at + batch]))
+        at += batch
     return losses

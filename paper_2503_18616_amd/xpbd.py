@@ -123,7 +123,7 @@ class XpbdLearnedParams(ctypes.Structure):
 
 _V = ctypes.c_void_p
 _lib.xpbd_mlp_create.restype = ctypes.c_int
-_lib.xpbd_mlp_create.argtypes = [_V, _V, _V, _V, ctypes.POINTER(ctypes.c_void_p)]
+_lib.xpbd_mlp_create.argtypes = [_V, _V, _V, _V, _V, _V, ctypes.POINTER(ctypes.c_void_p)]
 _lib.xpbd_mlp_get_params.restype = ctypes.c_int
 _lib.xpbd_mlp_get_params.argtypes = [_V, _V]
 _lib.xpbd_mlp_set_params.restype = ctypes.c_int
@@ -131,7 +131,7 @@ _lib.xpbd_mlp_set_params.argtypes = [_V, _V]
 _lib.xpbd_mlp_forward.restype = ctypes.c_int
 _lib.xpbd_mlp_forward.argtypes = [_V, _V, ctypes.c_int32, _V]
 _lib.xpbd_mlp_train_step.restype = ctypes.c_int
-_lib.xpbd_mlp_train_step.argtypes = [_V, _V, _V, ctypes.c_int32, ctypes.c_float, _V, _V]
+_lib.xpbd_mlp_train_step.argtypes = [_V, _V, _V, _V, ctypes.c_int32, ctypes.c_float, _V, _V]
 _lib.xpbd_mlp_destroy.restype = None
 _lib.xpbd_mlp_destroy.argtypes = [_V]
 _lib.xpbd_axis_neighbours.restype = ctypes.c_int
@@ -314,18 +314,26 @@ def _check_tool_pos(batch, num_steps, tool_pos):
     return tool_pos
 
 
-def xpbd_mlp_create(params, in_scale, out_scale, stream=None):
-    """params: float32 [MLP_PARAMS] or None; in_scale [27]; out_scale [3].  Returns a handle."""
+def xpbd_mlp_create(params, in_shift, in_scale, out_shift, out_scale, stream=None):
+    """params: float32 [MLP_PARAMS] or None; in_shift, in_scale [27]; out_shift,
+    out_scale [3] (shifts may be None).  Returns a handle."""
     p = None if params is None else np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
     if p is not None and p.size != MLP_PARAMS:
         raise ValueError(f"params must have {MLP_PARAMS} values")
-    si = np.ascontiguousarray(in_scale, dtype=np.float32).reshape(-1)
-    so = np.ascontiguousarray(out_scale, dtype=np.float32).reshape(-1)
-    if si.size != MLP_FEATURES or so.size != MLP_OUTPUTS:
-        raise ValueError("in_scale needs 27 values and out_scale 3")
+
+    def vec(a, n, name, optional=False):
+        if a is None and optional:
+            return None
+        a = np.ascontiguousarray(a, dtype=np.float32).reshape(-1)
+        if a.size != n:
+            raise ValueError(f"{name} needs {n} values")
+        return a
+    ish, isc = vec(in_shift, MLP_FEATURES, "in_shift", True), vec(in_scale, MLP_FEATURES, "in_scale")
+    osh, osc = vec(out_shift, MLP_OUTPUTS, "out_shift", True), vec(out_scale, MLP_OUTPUTS, "out_scale")
     out = ctypes.c_void_p()
     s = default_stream() if stream is None else stream
-    _check(_lib.xpbd_mlp_create(_ptr(p), _ptr(si), _ptr(so), s or None, ctypes.byref(out)))
+    _check(_lib.xpbd_mlp_create(_ptr(p), _ptr(ish), _ptr(isc), _ptr(osh), _ptr(osc), s or None,
+                                ctypes.byref(out)))
     return out.value
 
 
@@ -358,16 +366,22 @@ def xpbd_mlp_forward(net, features, y):
     _check(_lib.xpbd_mlp_forward(net, _ptr(features), n, _ptr(y)))
 
 
-def xpbd_mlp_train_step(net, features, targets, learning_rate, grad=None):
-    """One training step; returns the mean loss (synchronises)."""
+def xpbd_mlp_train_step(net, features, targets, learning_rate, grad=None, rows=None):
+    """One training step on every row, or on the rows listed in ``rows`` (device
+    int32, each index checked here against the tables); returns the mean loss."""
     n = _device_rows(features, MLP_FEATURE_STRIDE, "torch.bfloat16", "features")
     if _device_rows(targets, 4, "torch.float32", "targets") != n:
         raise ValueError("targets need one row per feature row")
     if grad is not None and _device_rows(grad, MLP_PARAMS, "torch.float32", "grad") != 1:
         raise ValueError("grad must hold MLP_PARAMS values")
+    count = n
+    if rows is not None:
+        count = _device_rows(rows, 1, "torch.int32", "rows")
+        if count and (int(rows.min()) < 0 or int(rows.max()) >= n):
+            raise ValueError("rows must index the feature table")
     loss = ctypes.c_float(0.0)
-    _check(_lib.xpbd_mlp_train_step(net, _ptr(features), _ptr(targets), n, float(learning_rate),
-                                    ctypes.addressof(loss), _ptr(grad)))
+    _check(_lib.xpbd_mlp_train_step(net, _ptr(features), _ptr(targets), _ptr(rows), count,
+                                    float(learning_rate), ctypes.addressof(loss), _ptr(grad)))
     return float(loss.value)
 
 
@@ -401,8 +415,8 @@ def xpbd_step_learned(batch, net, num_steps, tool_pos, min_iterations, max_itera
 class Mlp:
     """Owning wrapper around a network handle."""
 
-    def __init__(self, params, in_scale, out_scale, stream=None):
-        self.handle = xpbd_mlp_create(params, in_scale, out_scale, stream)
+    def __init__(self, params, in_shift, in_scale, out_shift, out_scale, stream=None):
+        self.handle = xpbd_mlp_create(params, in_shift, in_scale, out_shift, out_scale, stream)
 
     def params(self):
         return xpbd_mlp_get_params(self.handle)
@@ -413,8 +427,8 @@ class Mlp:
     def forward(self, features, y):
         xpbd_mlp_forward(self.handle, features, y)
 
-    def train_step(self, features, targets, learning_rate, grad=None):
-        return xpbd_mlp_train_step(self.handle, features, targets, learning_rate, grad)
+    def train_step(self, features, targets, learning_rate, grad=None, rows=None):
+        return xpbd_mlp_train_step(self.handle, features, targets, learning_rate, grad, rows)
 
     def close(self):
         if self.handle:

@@ -182,5 +182,5 @@ def test_network_create_rejects_bad_scales(xp):
     for si, so in [(np.full(27, np.nan, np.float32), ones3), (ones27, np.zeros(3, np.float32)),
                    (ones27, -ones3)]:
         with pytest.raises(xp.XpbdError) as e:
-            xp.xpbd_mlp_create(None, si, so, stream=0)
+            xp.xpbd_mlp_create(None, None, si, None, so, stream=0)
         assert e.value.status == xp.XPBD_E_ARG

@@ -87,6 +87,15 @@ def test_network_zero_weights_gives_bias_and_hand_example():
     assert np.allclose(y, [[0.0, -4.5, 0.0], [0.0, 0.0, 0.0]])
 
 
+def test_correction_clamps_the_output_and_skips_pinned_particles():
+    net = ws.init_net(0, out_scale=np.array([1e-3, 2e-3, 3e-3]))
+    for p in (net.W1, net.W2, net.W3, net.b1, net.b2):
+        p[...] = 0.0
+    net.b3[:] = [20.0, -3.0, -9.0]
+    c = ws.correction(net, np.zeros((3, ws.FEATURES)), np.array([True, False, True]))
+    assert np.allclose(c, [[8e-3, -6e-3, -24e-3], [0.0, 0.0, 0.0], [8e-3, -6e-3, -24e-3]])
+
+
 def test_network_is_positively_homogeneous_without_biases():
     net = ws.init_net(1)
     rng = np.random.default_rng(2)
