@@ -67,6 +67,15 @@ def parse_args():
     ap.add_argument("--cpu-envs", type=int, default=64, help="oracle sample: environments")
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle sample: steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned warm-start leg (training + timed learned steps)")
+    ap.add_argument("--learned-steps", type=int, default=100, help="timed learned steps")
+    ap.add_argument("--learned-min", type=int, default=1,
+                    help="sweeps before the residual check of the learned solver")
+    ap.add_argument("--train-envs", type=int, default=128, help="environments of the training run")
+    ap.add_argument("--train-records", type=int, default=24,
+                    help="recorded substeps (one per step) of the training run")
+    ap.add_argument("--train-steps", type=int, default=1500, help="Adam steps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB mebibytes (reference for the "
                          "HBM byte counters) and exit")
@@ -102,6 +111,84 @@ def measured_traffic(workload, steps_per_launch, args):
     if rec.get("kernel_source_sha256") != sha or rec.get("workload") != workload:
         return None
     return rec["traffic_bytes_per_launch"]
+
+
+def learned_leg(args, wl_fn, mesh, make_batch, I, S):
+    """The learned warm start on the same workload: train the network on
+    recorded substeps of a separate training run (untimed), then time
+    learned stepping with the residual check against the plain solver's
+    residual from the same start state."""
+    import numpy as np
+    import torch
+
+    from paper_2503_18616_amd import warmstart as trainer
+    from paper_2503_18616_amd import xpbd
+
+    t0 = time.perf_counter()
+    # training run: its own seeds, the same mesh and compliance distribution
+    warm = 20
+    tw = wl_fn(args.train_envs, seed=1, num_steps=warm + args.train_records)
+    ttools = torch.from_numpy(tw.tools(warm + args.train_records)).cuda()
+    subs = [k % S for k in range(args.train_records)]
+    with make_batch(tw, 0) as tb:
+        tb.step(warm, ttools[:warm])
+        x0, v0 = tb.positions(), tb.velocities()
+        with xpbd.Mlp(None, None, np.ones(xpbd.MLP_FEATURES), None, np.ones(3)) as pilot:
+            f0, t0_ = trainer.record(tb, pilot, ttools[warm:], subs, I)
+        norm = trainer.normalisation(f0, t0_)
+        del f0, t0_
+        tb.write(xpbd.FIELD_POS, x0)
+        tb.write(xpbd.FIELD_VEL, v0)
+        net = xpbd.Mlp(trainer.he_init(0), *norm)
+        feats, targets = trainer.record(tb, net, ttools[warm:], subs, I)
+    rows = int((feats[:, 31].float() > 0).sum())
+    losses = trainer.train(net, feats, targets, args.train_steps)
+    del feats, targets
+    train_s = time.perf_counter() - t0
+
+    # evaluation: plain and learned from the same state of the benchmark workload
+    N = args.envs
+    total = args.warmup + args.learned_steps
+    wl = wl_fn(N, seed=0, num_steps=total)
+    tools = torch.from_numpy(wl.tools(total)).cuda()
+    its = torch.zeros(args.learned_steps * S * N, dtype=torch.int32, device="cuda")
+    with make_batch(wl, xpbd.F_RESIDUAL) as pb, make_batch(wl, xpbd.F_RESIDUAL) as lb:
+        pb.step(args.warmup, tools[:args.warmup])
+        lb.step(args.warmup, tools[:args.warmup])
+        threshold = float(pb.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)[:, 0].mean())
+        stream = torch.cuda.current_stream()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for s in range(args.warmup, total):
+            lb.step_learned(net, 1, tools[s:s + 1], args.learned_min, I, threshold,
+                            iterations=its[(s - args.warmup) * S * N:(s - args.warmup + 1) * S * N])
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+        start.record(stream)
+        pb.step(args.learned_steps, tools[args.warmup:])
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms_plain = start.elapsed_time(end)
+        r_l = lb.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)
+        r_p = pb.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)
+    net.close()
+    it = its.cpu().numpy()
+    return {"value": N * args.learned_steps * S / (ms / 1e3), "unit": "env-substeps/s",
+            "ms_per_step": ms / args.learned_steps, "steps": args.learned_steps,
+            "plain_value_same_steps": N * args.learned_steps * S / (ms_plain / 1e3),
+            "min_iterations": args.learned_min, "max_iterations": I,
+            "threshold": threshold, "sweeps_mean": float(it.mean()),
+            "fallback_fraction": float((it > args.learned_min).mean()),
+            "residual_rms_mean": float(r_l[:, 0].mean()),
+            "plain_residual_rms_mean": float(r_p[:, 0].mean()),
+            "training": {"envs": args.train_envs, "recorded_substeps": args.train_records,
+                         "free_rows": rows, "adam_steps": args.train_steps,
+                         "loss_first": float(np.mean(losses[:5])),
+                         "loss_last": float(np.mean(losses[-50:])), "seconds": train_s},
+            "network": "27-128-128-3 ReLU, bf16 MFMA, fp32 accumulate"}
 
 
 def main():
@@ -204,6 +291,15 @@ def main():
                          f"({len(sample_envs) * args.cpu_steps * S} env-substeps, FP64, "
                          f"{dt:.1f} s wall)"}
 
+    learned = None
+    if not args.no_learned and args.workload == "batch":
+        def make(w, flags):
+            p = xpbd.make_params(w.dt, S, I, w.gravity, w.num_tools, w.tool_radius, flags=flags,
+                                 solver_variant=xpbd.VARIANT_REGISTERS)
+            return xpbd.Batch([(m.rest_pos, m.inv_mass, m.tets)], w.env_mesh, w.compliance, p,
+                              stream=stream.cuda_stream)
+        learned = learned_leg(args, W.batch_workload, m, make, I, S)
+
     out = {
         "metric": METRIC, "value": value, "unit": "env-substeps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
@@ -215,6 +311,7 @@ def main():
                    "residual_rms_mean": float(resid[:, 0].mean()),
                    "residual_max": float(resid[:, 1].max())},
         "roofline": roofline, "lds": lds_line, "hbm": hbm_line, "cpu_baseline": cpu,
+        "learned": learned,
     }
     print(json.dumps(out), flush=True)
 
