@@ -70,8 +70,14 @@ def parse_args():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned warm-start leg (training + timed learned steps)")
     ap.add_argument("--learned-steps", type=int, default=100, help="timed learned steps")
-    ap.add_argument("--learned-min", type=int, default=1,
+    ap.add_argument("--learned-min", type=int, default=2,
                     help="sweeps before the residual check of the learned solver")
+    ap.add_argument("--learned-stall", type=float, default=0.9,
+                    help="the fallback sweeps stop once one lowers the residual by less than "
+                         "this factor (0: run to the maximum)")
+    ap.add_argument("--learned-quantile", type=float, default=0.99,
+                    help="the fallback threshold is this quantile of the plain solver's "
+                         "residual over the warm-up steps")
     ap.add_argument("--train-envs", type=int, default=128, help="environments of the training run")
     ap.add_argument("--train-records", type=int, default=24,
                     help="recorded substeps (one per step) of the training run")
@@ -153,37 +159,72 @@ def learned_leg(args, wl_fn, mesh, make_batch, I, S):
     tools = torch.from_numpy(wl.tools(total)).cuda()
     its = torch.zeros(args.learned_steps * S * N, dtype=torch.int32, device="cuda")
     with make_batch(wl, xpbd.F_RESIDUAL) as pb, make_batch(wl, xpbd.F_RESIDUAL) as lb:
-        pb.step(args.warmup, tools[:args.warmup])
-        lb.step(args.warmup, tools[:args.warmup])
-        threshold = float(pb.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)[:, 0].mean())
+        warm_res = []
+        for s in range(args.warmup):
+            pb.step(1, tools[s:s + 1])
+            warm_res.append(pb.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)[:, 0].copy())
+        threshold = float(np.quantile(np.concatenate(warm_res), args.learned_quantile))
+        lb.write(xpbd.FIELD_POS, pb.positions())
+        lb.write(xpbd.FIELD_VEL, pb.velocities())
+        x0, v0 = pb.positions(), pb.velocities()
+        # residual after k sweeps from the same state, plain and learned, no fallback
+        by_sweeps = {"plain": {}, "learned": {}}
+        probe = min(10, args.learned_steps)
+        for k in (1, 2, 4, I):
+            for mode in ("plain", "learned"):
+                lb.write(xpbd.FIELD_POS, x0)
+                lb.write(xpbd.FIELD_VEL, v0)
+                r = []
+                for s in range(args.warmup, args.warmup + probe):
+                    lb.step_learned(net, 1, tools[s:s + 1], k, k, np.inf,
+                                    apply_correction=mode == "learned")
+                    r.append(lb.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)[:, 0].copy())
+                by_sweeps[mode][str(k)] = float(np.concatenate(r).mean())
+        lb.write(xpbd.FIELD_POS, x0)
+        lb.write(xpbd.FIELD_VEL, v0)
         stream = torch.cuda.current_stream()
         start = torch.cuda.Event(enable_timing=True)
         end = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         start.record(stream)
-        for s in range(args.warmup, total):
-            lb.step_learned(net, 1, tools[s:s + 1], args.learned_min, I, threshold,
-                            iterations=its[(s - args.warmup) * S * N:(s - args.warmup + 1) * S * N])
+        lb.step_learned(net, args.learned_steps, tools[args.warmup:total], args.learned_min, I,
+                        threshold, iterations=its, stall_ratio=args.learned_stall)
         end.record(stream)
         torch.cuda.synchronize()
         ms = start.elapsed_time(end)
         start.record(stream)
-        pb.step(args.learned_steps, tools[args.warmup:])
+        pb.step(args.learned_steps, tools[args.warmup:total])
         end.record(stream)
         torch.cuda.synchronize()
         ms_plain = start.elapsed_time(end)
-        r_l = lb.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)
-        r_p = pb.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)
+        # the residual of every step (last substep), untimed, from the same state
+        r_l, r_p = [], []
+        for b, out in ((lb, r_l), (pb, r_p)):
+            b.write(xpbd.FIELD_POS, x0)
+            b.write(xpbd.FIELD_VEL, v0)
+            for s in range(args.warmup, total):
+                if b is lb:
+                    b.step_learned(net, 1, tools[s:s + 1], args.learned_min, I, threshold,
+                                   stall_ratio=args.learned_stall)
+                else:
+                    b.step(1, tools[s:s + 1])
+                out.append(b.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)[:, 0].copy())
+        r_l, r_p = np.concatenate(r_l), np.concatenate(r_p)
     net.close()
     it = its.cpu().numpy()
     return {"value": N * args.learned_steps * S / (ms / 1e3), "unit": "env-substeps/s",
             "ms_per_step": ms / args.learned_steps, "steps": args.learned_steps,
             "plain_value_same_steps": N * args.learned_steps * S / (ms_plain / 1e3),
             "min_iterations": args.learned_min, "max_iterations": I,
-            "threshold": threshold, "sweeps_mean": float(it.mean()),
+            "stall_ratio": args.learned_stall,
+            "threshold": threshold, "threshold_rule": f"plain {I}-sweep residual, "
+            f"{args.learned_quantile:g} quantile over {args.warmup} warm-up steps",
+            "sweeps_mean": float(it.mean()),
             "fallback_fraction": float((it > args.learned_min).mean()),
-            "residual_rms_mean": float(r_l[:, 0].mean()),
-            "plain_residual_rms_mean": float(r_p[:, 0].mean()),
+            "residual_rms_mean": float(r_l.mean()),
+            "plain_residual_rms_mean": float(r_p.mean()),
+            "residual_matched": bool(r_l.mean() <= r_p.mean()),
+            "residual_by_sweeps": by_sweeps,
             "training": {"envs": args.train_envs, "recorded_substeps": args.train_records,
                          "free_rows": rows, "adam_steps": args.train_steps,
                          "loss_first": float(np.mean(losses[:5])),

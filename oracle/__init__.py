@@ -356,18 +356,24 @@ class LearnedResult:
     iterations: np.ndarray     # [num_steps][substeps] iterations run
     residual: np.ndarray       # [num_steps][substeps][2] (RMS, max) after the last iteration
     early_residual: np.ndarray # [num_steps][substeps] RMS after min_iterations
+    checks: np.ndarray         # [num_steps][substeps][max_iterations + 1] RMS after n sweeps
+                               # wherever the driver evaluated it, else NaN
 
 
 def run_env_learned(mesh: OracleMesh, compliance, params: OracleParams, tool_pos, num_steps,
                     corrector, min_iterations, max_iterations, threshold, x0=None, v0=None,
-                    nbr=None) -> LearnedResult:
+                    nbr=None, stall_ratio=0.0) -> LearnedResult:
     """Advance one environment with the learned warm start (see ``warmstart``).
 
     corrector(x_prev, v, x_hat, nbr) -> [V, 3] correction of the predicted
     positions (zero rows for pinned particles), or None for the plain solver.
     Per substep: predict (Alg. 1), add the correction, reset the multipliers,
-    run min_iterations sweeps, evaluate the residual RMS; if it exceeds
+    run min_iterations sweeps, evaluate the residual RMS r; if r exceeds
     ``threshold``, run sweeps up to max_iterations; then the velocity update.
+    With 0 < stall_ratio, the residual is evaluated again after each of those
+    further sweeps (not after the last) and they stop once it is at or below
+    the threshold, or above stall_ratio times the previous value (the sweeps
+    have stalled, as they do where the tool pushes particles back out).
     """
     from . import warmstart as ws
     lib = _load()
@@ -394,6 +400,7 @@ def run_env_learned(mesh: OracleMesh, compliance, params: OracleParams, tool_pos
     its = np.zeros((num_steps, params.substeps), np.int32)
     res = np.zeros((num_steps, params.substeps, 2))
     early = np.zeros((num_steps, params.substeps))
+    checks = np.full((num_steps, params.substeps, max_iterations + 1), np.nan)
     r2 = np.zeros(2)
 
     def sweep(centres):
@@ -424,12 +431,18 @@ def run_env_learned(mesh: OracleMesh, compliance, params: OracleParams, tool_pos
             for _ in range(min_iterations):
                 sweep(centres)
                 n_it += 1
-            early[step, sub] = residual()[0]
-            if early[step, sub] > threshold:
+            r = early[step, sub] = checks[step, sub, n_it] = residual()[0]
+            if r > threshold:
                 while n_it < max_iterations:
                     sweep(centres)
                     n_it += 1
+                    if stall_ratio <= 0.0 or n_it == max_iterations:
+                        continue
+                    r_new = checks[step, sub, n_it] = residual()[0]
+                    if r_new <= threshold or r_new > stall_ratio * r:
+                        break
+                    r = r_new
             its[step, sub] = n_it
             res[step, sub] = residual()
             lib.oracle_velocity(V, h, _dp(x), _dp(x_prev), _dp(v))
-    return LearnedResult(x, v, its, res, early)
+    return LearnedResult(x, v, its, res, early, checks)

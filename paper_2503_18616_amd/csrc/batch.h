@@ -45,8 +45,9 @@ struct xpbd_batch {
     bool residual_valid = false;   // a step has computed the residual
     // learned warm start workspace (allocated on first use)
     float *learned_xhat = nullptr;           // [3][total particles]
+    uint16_t *learned_feat = nullptr;        // [total particles][32] features of the correction
     uint8_t *learned_cand = nullptr;         // [total particles]
-    uint16_t *learned_feat = nullptr;        // [total particles][32]
+    int32_t correct_workgroups = 0;          // persistent workgroups of the correction pass
     int32_t max_vertices = 0;
 
     ~xpbd_batch()

@@ -239,6 +239,8 @@ xpbd_status xpbd_step_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
         return fail(XPBD_E_ARG, "need 0 <= min_iterations <= max_iterations");
     if (!std::isfinite(lp->threshold) && !std::isinf(lp->threshold))
         return fail(XPBD_E_ARG, "threshold must not be NaN");
+    if (!(lp->stall_ratio >= 0.0f && lp->stall_ratio <= 1.0f))
+        return fail(XPBD_E_ARG, "stall_ratio must be in [0, 1] (got %g)", (double)lp->stall_ratio);
     const bool record = lp->record_substep >= 0;
     if ((lp->apply_correction || record) && !net)
         return fail(XPBD_E_ARG, "the correction and the recording need a network");
@@ -281,10 +283,16 @@ xpbd_status xpbd_step_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
                              (st = b->alloc(reinterpret_cast<void **>(&b->learned_cand),
                                             (size_t)NP))))
         return st;
-    if (net && !b->learned_feat &&
+    if (lp->apply_correction && !b->learned_feat &&
         (st = b->alloc(reinterpret_cast<void **>(&b->learned_feat),
                        sizeof(uint16_t) * 32 * (size_t)NP)))
         return st;
+    if (lp->apply_correction && !b->correct_workgroups) {
+        int device = 0, cus = 0;
+        HIP_TRY(hipGetDevice(&device));
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+        b->correct_workgroups = 3 * std::max(cus, 1);   // three 51 KB workgroups fit a CU's LDS
+    }
 
     xpbd::StepArgs a;
     std::memset(&a, 0, sizeof a);
@@ -329,6 +337,7 @@ xpbd_status xpbd_step_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
     L.threshold = lp->threshold;
     L.min_iterations = lp->min_iterations;
     L.max_iterations = lp->max_iterations;
+    L.stall_ratio = lp->stall_ratio;
     L.max_vertices = b->max_vertices;
     const bool resid = (b->params.flags & XPBD_F_RESIDUAL) != 0;
     const bool want_lambda = (b->params.flags & XPBD_F_LAMBDA) || resid;
@@ -339,15 +348,17 @@ xpbd_status xpbd_step_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
             const bool rec = record && sub == lp->record_substep;
             L.first_substep = sub == 0;
             L.step = step;
-            L.features = rec ? lp->record_features : (net ? b->learned_feat : nullptr);
+            L.features = rec ? lp->record_features : nullptr;
             L.record_targets = rec ? lp->record_targets : nullptr;
             L.iterations = lp->iterations ? lp->iterations + ((size_t)step * S + sub) * b->num_envs
                                           : nullptr;
             a.lambda_out = last && want_lambda ? b->lambda : nullptr;
+            if (lp->apply_correction && !rec)
+                L.features = b->learned_feat;
             HIP_TRY(xpbd::launch_learned_predict(a, L, b->stream));
             if (lp->apply_correction)
-                HIP_TRY(xpbd::launch_mlp_forward(net->d, L.features, (int)NP, nullptr, L.xhat, NP,
-                                                 b->stream));
+                HIP_TRY(xpbd::launch_learned_correct(a, L, net->d, b->correct_workgroups,
+                                                     b->stream));
             HIP_TRY(xpbd::launch_substep_reg(a, L, b->block, b->lambda_banks, b->lds_bytes,
                                              last && resid, b->stream));
         }

@@ -28,6 +28,7 @@ struct MeshDev {
     const float *inv_mass;       // [V]
     const float *rest_pos;       // [V][3] (learned warm start's features)
     const int32_t *nbr;          // [V][6] axis neighbours -x, +x, -y, +y, -z, +z, -1 for none
+    const float4 *rest4;         // [V] (rest position, inverse mass)
     // particle placement of the register-multiplier kernel for a group of G
     // environments: particle i of the group's e-th environment (group id
     // e V + i) lives in LDS slot slot_of[e V + i]; records name slots
@@ -105,6 +106,7 @@ struct LearnedArgs {
     float *record_targets;       // [total particles][4] (x - x_hat - out_shift) / out_scale, or null
     int32_t *iterations;         // [N] sweeps run in this substep, or null
     float threshold;             // residual RMS above which the sweeps continue
+    float stall_ratio;           // > 0: the further sweeps stop once one lowers the RMS by less
     int32_t min_iterations;
     int32_t max_iterations;
     int32_t first_substep;       // 1: find the contact candidates on the start-of-step positions
@@ -194,6 +196,12 @@ hipError_t launch_step_reg(const StepArgs &args, int block, int lambda_banks, in
 // every environment), then one substep of the register-multiplier solver
 // starting from the predicted (and corrected) positions.
 hipError_t launch_learned_predict(const StepArgs &args, const LearnedArgs &largs, hipStream_t stream);
+// The network's correction of the predicted positions in largs.xhat (in
+// place, free particles only) from the feature rows in largs.features:
+// num_workgroups persistent workgroups.
+struct MlpDev;
+hipError_t launch_learned_correct(const StepArgs &args, const LearnedArgs &largs,
+                                  const MlpDev &net, int num_workgroups, hipStream_t stream);
 hipError_t launch_substep_reg(const StepArgs &args, const LearnedArgs &largs, int block,
                               int lambda_banks, uint32_t lds_bytes, bool want_residual,
                               hipStream_t stream);

@@ -813,85 +813,81 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
 // its correction to the predicted positions, xpbd_substep_reg_kernel runs the
 // sweeps from there with the residual check and updates the velocities.
 
-__device__ __forceinline__ uint16_t to_bf16(float f)
-{
-    uint32_t u = __float_as_uint(f);   // round to nearest, ties to even
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-// Prediction of one substep (Alg. 1) into L.xhat, and the features of every
-// particle: predicted displacement, start-of-substep velocity, displacement
-// from rest, and the six axis-neighbour offsets minus their rest offsets,
-// normalised ((f - in_shift) * in_scale) and rounded to bfloat16; feature 31
-// flags a free particle.
+// Prediction of one substep (Alg. 1) into L.xhat and, when L.features is
+// set, the features of every particle: predicted displacement,
+// start-of-substep velocity, displacement from rest, and the six
+// axis-neighbour offsets minus their rest offsets, normalised
+// ((f - in_shift) * in_scale) and rounded to bfloat16 (nearest, ties to
+// even); feature 31 flags a free particle.  Loads are branch-free: a pinned
+// particle moves by 0 * (v + h g), a missing neighbour reads the particle
+// itself and its offset is then zero.
 // Grid: (ceil(max V / 256), environments).
 __global__ void __launch_bounds__(256) learned_predict_kernel(StepArgs A, LearnedArgs L)
 {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
     const int env = blockIdx.y;
     const int i = blockIdx.x * 256 + threadIdx.x;
     const EnvDev ed = A.envs[env];
-    const MeshDev md = A.meshes[ed.mesh];
+    const MeshDev &md = A.meshes[ed.mesh];
     if (i >= md.num_vertices)
         return;
     const int NP = A.total_particles, off = ed.particle_offset;
+    const XPBD_GLOBAL float *pos = (const XPBD_GLOBAL float *)(uintptr_t)A.pos;
+    const XPBD_GLOBAL float *vel = (const XPBD_GLOBAL float *)(uintptr_t)A.vel;
+    const XPBD_GLOBAL f32x4 *rest4 = (const XPBD_GLOBAL f32x4 *)(uintptr_t)md.rest4;
     const float h = A.h;
-    const float hgx = h * A.gravity[0], hgy = h * A.gravity[1], hgz = h * A.gravity[2];
-    auto predict = [&](int j, float &px, float &py, float &pz) {
-        px = A.pos[off + j];
-        py = A.pos[NP + off + j];
-        pz = A.pos[2 * NP + off + j];
-        if (md.inv_mass[j] > 0.0f) {
-            const float vx = A.vel[off + j] + hgx, vy = A.vel[NP + off + j] + hgy,
-                        vz = A.vel[2 * NP + off + j] + hgz;
-            px += h * vx;
-            py += h * vy;
-            pz += h * vz;
-        }
-    };
-    float f[32];
-    float xh, yh, zh;
-    predict(i, xh, yh, zh);
-    L.xhat[off + i] = xh;
-    L.xhat[NP + off + i] = yh;
-    L.xhat[2 * NP + off + i] = zh;
+    const float hg[3] = {h * A.gravity[0], h * A.gravity[1], h * A.gravity[2]};
+    const f32x4 Ri = rest4[i];   // rest position, inverse mass
+    float x[3], v[3], xh[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        x[k] = pos[k * NP + off + i];
+        v[k] = vel[k * NP + off + i];
+        xh[k] = x[k] + (Ri.w > 0.0f ? h : 0.0f) * (v[k] + hg[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        L.xhat[k * NP + off + i] = xh[k];
     if (!L.features)
         return;
-    const float rx = md.rest_pos[3 * i], ry = md.rest_pos[3 * i + 1], rz = md.rest_pos[3 * i + 2];
-    f[0] = xh - A.pos[off + i];
-    f[1] = yh - A.pos[NP + off + i];
-    f[2] = zh - A.pos[2 * NP + off + i];
-    f[3] = A.vel[off + i];
-    f[4] = A.vel[NP + off + i];
-    f[5] = A.vel[2 * NP + off + i];
-    f[6] = xh - rx;
-    f[7] = yh - ry;
-    f[8] = zh - rz;
+    const XPBD_GLOBAL int32_t *nbr = (const XPBD_GLOBAL int32_t *)(uintptr_t)md.nbr;
+    const float rest[3] = {Ri.x, Ri.y, Ri.z};
+    float f[32];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const int n = md.nbr[6 * i + k];
-        float ox = 0.0f, oy = 0.0f, oz = 0.0f;
-        if (n >= 0) {
-            float nx, ny, nz;
-            predict(n, nx, ny, nz);
-            ox = (nx - xh) - (md.rest_pos[3 * n] - rx);
-            oy = (ny - yh) - (md.rest_pos[3 * n + 1] - ry);
-            oz = (nz - zh) - (md.rest_pos[3 * n + 2] - rz);
+    for (int k = 0; k < 3; ++k) {
+        f[k] = xh[k] - x[k];
+        f[3 + k] = v[k];
+        f[6 + k] = xh[k] - rest[k];
+    }
+    int nb[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d)
+        nb[d] = nbr[6 * i + d];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const int j = nb[d] >= 0 ? nb[d] : i;
+        const f32x4 Rj = rest4[j];
+        const float rj[3] = {Rj.x, Rj.y, Rj.z};
+        const float hj = Rj.w > 0.0f ? h : 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float pj = pos[k * NP + off + j] + hj * (vel[k * NP + off + j] + hg[k]);
+            f[9 + 3 * d + k] = nb[d] >= 0 ? (pj - xh[k]) - (rj[k] - rest[k]) : 0.0f;
         }
-        f[9 + 3 * k] = ox;
-        f[10 + 3 * k] = oy;
-        f[11 + 3 * k] = oz;
     }
     uint32_t packed[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         const int c0 = 2 * c, c1 = 2 * c + 1;
-        const uint16_t lo =
-            c0 < 27 ? to_bf16((f[c0] - L.in_shift[c0]) * L.in_scale[c0]) : (uint16_t)0;
-        uint16_t hi = c1 < 27 ? to_bf16((f[c1] - L.in_shift[c1]) * L.in_scale[c1]) : (uint16_t)0;
+        const float lo = c0 < 27 ? (f[c0] - L.in_shift[c0]) * L.in_scale[c0] : 0.0f;
+        float hi = c1 < 27 ? (f[c1] - L.in_shift[c1]) * L.in_scale[c1] : 0.0f;
         if (c1 == 31)
-            hi = md.inv_mass[i] > 0.0f ? (uint16_t)0x3f80 : (uint16_t)0;   // bfloat16 1.0
-        packed[c] = (uint32_t)lo | ((uint32_t)hi << 16);
+            hi = Ri.w > 0.0f ? 1.0f : 0.0f;   // flags a free particle
+        const f32x2 pair = {lo, hi};
+        const bf16x2 b = __builtin_convertvector(pair, bf16x2);
+        __builtin_memcpy(&packed[c], &b, sizeof(uint32_t));
     }
     uint4 *dst = reinterpret_cast<uint4 *>(L.features + (size_t)(off + i) * 32);
 #pragma unroll
@@ -1052,7 +1048,9 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
     int n_it = 0;
     for (; n_it < L.min_iterations; ++n_it)
         sweep();
-    if (L.max_iterations > L.min_iterations) {
+    // residual RMS of the environment (every thread gets it; the sweeps between
+    // two evaluations hold barriers, and one follows the read)
+    auto residual_rms = [&]() {
         float acc = 0.0f;
         for (int r = 0; r < R0; r += 2) {
             eval_round(xw, tab, r, slot_a, active, tets, bank0, alpha_d, alpha_v, acc);
@@ -1070,11 +1068,25 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
         float total = 0.0f;
         for (int w = 0; w < num_waves; ++w)
             total += __uint_as_float(scratch[64 + w]);
+        __syncthreads();
         const int n_con = md.num_edges + md.num_tets;
-        const float rms = n_con > 0 ? sqrtf(total / (float)n_con) : 0.0f;
+        return n_con > 0 ? sqrtf(total / (float)n_con) : 0.0f;
+    };
+    if (L.max_iterations > L.min_iterations) {
+        float rms = residual_rms();
         if (rms > L.threshold)
-            for (; n_it < L.max_iterations; ++n_it)
+            while (n_it < L.max_iterations) {
                 sweep();
+                ++n_it;
+                if (!(L.stall_ratio > 0.0f) || n_it == L.max_iterations)
+                    continue;
+                // stop once below the threshold or when a sweep no longer
+                // lowers the residual by the factor stall_ratio
+                const float next = residual_rms();
+                if (next <= L.threshold || next > L.stall_ratio * rms)
+                    break;
+                rms = next;
+            }
     }
 
     // velocity update and write-back (structure of arrays); slot_of[i] belongs

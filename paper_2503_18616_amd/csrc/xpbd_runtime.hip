@@ -509,12 +509,19 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         xpbd_status st;
         std::vector<int32_t> nbr;
         xpbd::axis_neighbours(V, pm.rest_pos.data(), nbr);
+        std::vector<float4> rest4((size_t)V);
+        for (int i = 0; i < V; ++i)
+            rest4[(size_t)i] = make_float4(pm.rest_pos[3 * (size_t)i], pm.rest_pos[3 * (size_t)i + 1],
+                                           pm.rest_pos[3 * (size_t)i + 2], pm.inv_mass[(size_t)i]);
         float *p_rest;
         int32_t *p_nbr;
-        if ((st = b->upload(&p_rest, pm.rest_pos)) || (st = b->upload(&p_nbr, nbr)))
+        float4 *p_rest4;
+        if ((st = b->upload(&p_rest, pm.rest_pos)) || (st = b->upload(&p_nbr, nbr)) ||
+            (st = b->upload(&p_rest4, rest4)))
             return cleanup(st);
         d.rest_pos = p_rest;
         d.nbr = p_nbr;
+        d.rest4 = p_rest4;
         if ((st = b->upload(&p_pair, pair)) || (st = b->upload(&p_erest, erest)) ||
             (st = b->upload(&p_quad, quad)) || (st = b->upload(&p_trest, trest)) ||
             (st = b->upload(&p_eptr, eptr)) || (st = b->upload(&p_tptr, tptr)) ||

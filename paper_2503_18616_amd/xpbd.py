@@ -118,7 +118,8 @@ class XpbdLearnedParams(ctypes.Structure):
     _fields_ = [("apply_correction", ctypes.c_int32), ("min_iterations", ctypes.c_int32),
                 ("max_iterations", ctypes.c_int32), ("threshold", ctypes.c_float),
                 ("record_substep", ctypes.c_int32), ("record_features", ctypes.c_void_p),
-                ("record_targets", ctypes.c_void_p), ("iterations", ctypes.c_void_p)]
+                ("record_targets", ctypes.c_void_p), ("iterations", ctypes.c_void_p),
+                ("stall_ratio", ctypes.c_float)]
 
 
 _V = ctypes.c_void_p
@@ -400,14 +401,14 @@ def xpbd_axis_neighbours(rest_pos):
 
 def xpbd_step_learned(batch, net, num_steps, tool_pos, min_iterations, max_iterations,
                       threshold, apply_correction=True, record_substep=-1, record_features=None,
-                      record_targets=None, iterations=None):
+                      record_targets=None, iterations=None, stall_ratio=0.0):
     """One substep per launch with the network's correction; see include/xpbd_learned.h.
     record_features / record_targets / iterations: device tensors (bfloat16 [NP, 32],
     float32 [NP, 4], int32 [num_steps * substeps * N]) or None."""
     tool_pos = _check_tool_pos(batch, num_steps, tool_pos)
     lp = XpbdLearnedParams(int(bool(apply_correction)), int(min_iterations), int(max_iterations),
                            float(threshold), int(record_substep), _ptr(record_features),
-                           _ptr(record_targets), _ptr(iterations))
+                           _ptr(record_targets), _ptr(iterations), float(stall_ratio))
     _check(_lib.xpbd_step_learned(batch, net, int(num_steps), _ptr(tool_pos), ctypes.byref(lp)))
 
 

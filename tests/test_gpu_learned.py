@@ -181,6 +181,92 @@ def test_learned_substeps_follow_the_oracle(xp, oracle_lib, threshold, expect_it
     assert np.abs(ref.x - m0.rest_pos).max() > 1e-5       # gravity moved the slab
 
 
+def test_stalled_fallback_follows_the_oracle(xp, oracle_lib):
+    """The further sweeps stop once one lowers the residual by less than the
+    stall ratio: the sweep counts (all decided with a margin of at least 1 %)
+    and the positions follow the oracle."""
+    import torch
+    wl = W.single_env_workload(seed=3)
+    steps = 20
+    tools = W.tool_path(steps, 1, 3, start_depth=6e-3)
+    om = K.oracle_meshes(oracle_lib, wl)[0]
+    stall = 0.9
+    ref = oracle_lib.run_env_learned(om, wl.compliance[0], K.oracle_params(oracle_lib, wl),
+                                     tools[:, 0], steps, None, 2, 4, -1.0, stall_ratio=stall)
+    ratio = ref.checks[:, :, 3] / ref.checks[:, :, 2]
+    assert np.nanmin(np.abs(ratio - stall)) > 0.01
+    assert set(np.unique(ref.iterations)) == {3, 4}
+    its = torch.zeros(steps * wl.substeps, dtype=torch.int32, device="cuda")
+    with make_batch(xp, wl) as b:
+        b.step_learned(None, steps, tools, 2, 4, -1.0, apply_correction=False, iterations=its,
+                       stall_ratio=stall)
+        x = b.positions()
+    assert np.array_equal(its.cpu().numpy(), ref.iterations.ravel())
+    err = K.max_position_error(x, ref.x)
+    assert err <= K.POS_TOL, f"max position error {err:.3e}"
+
+
+def _one_substep(wl):
+    import dataclasses
+    return dataclasses.replace(wl, substeps=1)
+
+
+@pytest.mark.parametrize("case", ["c1-600-envs", "c2-3-envs"])
+def test_fused_correction_matches_the_forward_kernel(xp, case):
+    """The one-pass prediction + features + network correction against the
+    prediction kernel's recorded features run through the stand-alone forward
+    kernel: 600 single-pass environments (more than the persistent grid, so
+    workgroups take several) and 935-particle environments (four passes, a
+    ragged last one).  Zero sweeps leave the corrected prediction as the
+    result."""
+    import torch
+    if case == "c1-600-envs":
+        m0 = W.single_env_workload(seed=2).meshes[0]
+        wl = W.Workload("c1-many", [m0], np.zeros(600, np.int32),
+                        W.constant_compliance(600, 1e-6, 1e-7), 4, 3, 2)
+    else:
+        wl = W.batch_workload(3, seed=4, num_steps=3)
+    wl = _one_substep(wl)
+    N = wl.num_envs
+    tools = W.tool_path(3, N, 4, start_depth=6e-3)
+    in_scale = (1.0 / np.array([2e-4] * 3 + [0.1] * 3 + [2e-3] * 3 + [2e-5] * 18)).astype(np.float32)
+    rng = np.random.default_rng(12)
+    in_shift = (rng.uniform(-0.3, 0.3, 27) / in_scale).astype(np.float32)
+    out_scale = np.full(3, 3e-5, np.float32)
+    out_shift = np.array([1e-6, -2e-6, 0.5e-6], np.float32)
+    net = random_net(13)
+    with make_batch(xp, wl) as b, xp.Mlp(flat(net), in_shift, in_scale, out_shift, out_scale) as m:
+        b.step(2, tools[:2])
+        x0, v0 = b.positions(), b.velocities()
+        NP = x0.shape[0]
+        feats = torch.zeros((NP, 32), dtype=torch.bfloat16, device="cuda")
+        feats2 = torch.zeros_like(feats)
+        targets = torch.zeros((NP, 4), dtype=torch.float32, device="cuda")
+        b.step_learned(m, 1, tools[2:3], 0, 0, np.inf, apply_correction=False, record_substep=0,
+                       record_features=feats, record_targets=targets)
+        x_hat = b.positions().astype(np.float64)
+        b.write(xp.FIELD_POS, x0)
+        b.write(xp.FIELD_VEL, v0)
+        b.step_learned(m, 1, tools[2:3], 0, 0, np.inf, apply_correction=True, record_substep=0,
+                       record_features=feats2, record_targets=targets)
+        x_fused = b.positions().astype(np.float64)
+        assert torch.equal(feats, feats2)
+        y = torch.zeros((NP, 4), dtype=torch.float32, device="cuda")
+        m.forward(feats, y)
+        y = y.cpu().numpy()[:, :3].astype(np.float64)
+        free = feats[:, 31].float().cpu().numpy() > 0
+    want = np.where(free[:, None],
+                    out_shift.astype(np.float64) + np.clip(y, -8, 8) * out_scale.astype(np.float64),
+                    0.0)
+    got = x_fused - x_hat
+    assert np.all(got[~free] == 0.0)
+    scale = np.abs(want).max()
+    assert scale > 1e-6
+    # the two kernels sum the same bfloat16 products in different orders; a
+    # hidden activation may round to the neighbouring bfloat16 value
+    assert np.abs(got - want).max() <= 2e-3 * scale + 2e-8, np.abs(got - want).max() / scale
+
+
 def test_recorded_features_and_targets_match_the_oracle(xp, oracle_lib):
     import torch
     wl = W.batch_workload(4, seed=5, num_steps=3)

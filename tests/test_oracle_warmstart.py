@@ -193,3 +193,42 @@ def test_exact_corrector_needs_no_fallback(small):
                                 wl.iterations, thr)
     assert lr.iterations.mean() < plain.iterations.mean()
     assert np.all(lr.residual[:, :, 0][lr.iterations == 1] <= thr)
+
+
+def test_stall_rule_limits(small):
+    """The stall rule's two limits are plain runs: a ratio no sweep can exceed
+    never stops the further sweeps (the full count, evaluations aside, leaves
+    the state untouched), and a tiny ratio stops them after the first further
+    sweep, which is a run with one sweep more than the minimum."""
+    wl, om, P, tools = small
+    full = oracle.run_env_learned(om, wl.compliance[0], P, tools[:, 0], 12, None, 1,
+                                  wl.iterations, -1.0)
+    never = oracle.run_env_learned(om, wl.compliance[0], P, tools[:, 0], 12, None, 1,
+                                   wl.iterations, -1.0, stall_ratio=1e300)
+    assert np.array_equal(never.x, full.x) and np.all(never.iterations == wl.iterations)
+    once = oracle.run_env_learned(om, wl.compliance[0], P, tools[:, 0], 12, None, 1,
+                                  wl.iterations, -1.0, stall_ratio=1e-300)
+    two = oracle.run_env_learned(om, wl.compliance[0], P, tools[:, 0], 12, None, 2, 2, np.inf)
+    assert np.all(once.iterations == 2)
+    assert np.array_equal(once.x, two.x) and np.array_equal(once.v, two.v)
+
+
+def test_stall_rule_decisions_follow_the_recorded_residuals(small):
+    """Where the further sweeps stopped short of the maximum, the last evaluated
+    residual is at or below the threshold or above stall_ratio times the one
+    before; every earlier evaluation was below that bound."""
+    wl, om, P, tools = small
+    stall, thr = 0.9, 2e-4
+    r = oracle.run_env_learned(om, wl.compliance[0], P, tools[:, 0], 12, None, 2,
+                               wl.iterations, thr, stall_ratio=stall)
+    assert len(np.unique(r.iterations)) > 1
+    for s in range(12):
+        for k in range(wl.substeps):
+            c, n = r.checks[s, k], int(r.iterations[s, k])
+            if c[2] <= thr:
+                assert n == 2
+                continue
+            for m in range(3, n):
+                assert thr < c[m] <= stall * c[m - 1]
+            if n < wl.iterations:
+                assert c[n] <= thr or c[n] > stall * c[n - 1]
