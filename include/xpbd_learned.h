@@ -9,8 +9,8 @@
  * sweeps remain the judge: after min_iterations the residual RMS of the
  * environment (the mean over all constraints of ((C + alpha~ lambda) / rest)^2,
  * square-rooted, as XPBD_FIELD_RESIDUAL reports it) is compared with a
- * threshold, and the sweeps continue towards max_iterations when it is above
- * (optionally stopping early once they stall, see stall_ratio).
+ * threshold, and the sweeps continue to max_iterations when it is above
+ * (unless the sweeps have stalled, see stall_ratio).
  *
  * Features f of particle i (float32; the network sees (f - in_shift) * in_scale
  * rounded to bfloat16), from the start-of-substep positions x and velocities
@@ -110,10 +110,12 @@ typedef struct {
     float *record_targets;     /* device float32 [total particles][4]: (x - x_hat - out_shift) /
                                   out_scale after the sweeps (zero rows for pinned particles) */
     int32_t *iterations;       /* device int32 [num_steps][substeps][N] sweeps run, or NULL */
-    float stall_ratio;         /* 0: the sweeps above the threshold run to max_iterations; in
-                                  (0, 1]: the residual is evaluated after each of them (not
-                                  after the last) and they stop once it is at or below the
-                                  threshold or above stall_ratio times the previous value */
+    float stall_ratio;         /* 0: off.  In (0, 1], with min_iterations >= 1: the residual
+                                  is also evaluated before the last of the min_iterations
+                                  sweeps, and the sweeps continue past the minimum only if
+                                  that sweep lowered it to at most stall_ratio times that
+                                  value (a stalled sweep marks a state the further sweeps
+                                  cannot improve, as where the tool holds particles) */
 } xpbd_learned_params;
 
 /* Advance every environment by num_steps steps one substep at a time: the

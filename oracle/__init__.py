@@ -370,10 +370,12 @@ def run_env_learned(mesh: OracleMesh, compliance, params: OracleParams, tool_pos
     Per substep: predict (Alg. 1), add the correction, reset the multipliers,
     run min_iterations sweeps, evaluate the residual RMS r; if r exceeds
     ``threshold``, run sweeps up to max_iterations; then the velocity update.
-    With 0 < stall_ratio, the residual is evaluated again after each of those
-    further sweeps (not after the last) and they stop once it is at or below
-    the threshold, or above stall_ratio times the previous value (the sweeps
-    have stalled, as they do where the tool pushes particles back out).
+    With 0 < stall_ratio and min_iterations >= 1, the residual is also
+    evaluated before the last of the min_iterations sweeps, and the further
+    sweeps run only if that sweep lowered it to at most stall_ratio times the
+    value before it: a sweep that no longer lowers the residual marks a state
+    the further sweeps cannot improve (as where the tool pushes particles back
+    out against the constraints).
     """
     from . import warmstart as ws
     lib = _load()
@@ -428,20 +430,20 @@ def run_env_learned(mesh: OracleMesh, compliance, params: OracleParams, tool_pos
                 x += corrector(x_prev, v_start, x, nbr)
             lam[:] = 0.0
             n_it = 0
+            stall_check = stall_ratio > 0.0 and min_iterations >= 1
             for _ in range(min_iterations):
+                if stall_check and n_it == min_iterations - 1:
+                    checks[step, sub, n_it] = residual()[0]
                 sweep(centres)
                 n_it += 1
             r = early[step, sub] = checks[step, sub, n_it] = residual()[0]
-            if r > threshold:
+            go_on = r > threshold
+            if go_on and stall_check:
+                go_on = r <= stall_ratio * checks[step, sub, n_it - 1]
+            if go_on:
                 while n_it < max_iterations:
                     sweep(centres)
                     n_it += 1
-                    if stall_ratio <= 0.0 or n_it == max_iterations:
-                        continue
-                    r_new = checks[step, sub, n_it] = residual()[0]
-                    if r_new <= threshold or r_new > stall_ratio * r:
-                        break
-                    r = r_new
             its[step, sub] = n_it
             res[step, sub] = residual()
             lib.oracle_velocity(V, h, _dp(x), _dp(x_prev), _dp(v))

@@ -342,6 +342,9 @@ xpbd_status xpbd_step_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
     const bool resid = (b->params.flags & XPBD_F_RESIDUAL) != 0;
     const bool want_lambda = (b->params.flags & XPBD_F_LAMBDA) || resid;
     const int S = b->params.substeps;
+    auto feature_buffer = [&](int sub) {
+        return record && sub == lp->record_substep ? lp->record_features : b->learned_feat;
+    };
     for (int step = 0; step < num_steps; ++step)
         for (int sub = 0; sub < S; ++sub) {
             const bool last = step == num_steps - 1 && sub == S - 1;
@@ -353,12 +356,20 @@ xpbd_status xpbd_step_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
             L.iterations = lp->iterations ? lp->iterations + ((size_t)step * S + sub) * b->num_envs
                                           : nullptr;
             a.lambda_out = last && want_lambda ? b->lambda : nullptr;
-            if (lp->apply_correction && !rec)
-                L.features = b->learned_feat;
-            HIP_TRY(xpbd::launch_learned_predict(a, L, b->stream));
-            if (lp->apply_correction)
+            L.next_features = nullptr;
+            if (lp->apply_correction) {
+                // the first substep of the call predicts in a kernel of its own; every
+                // substep kernel leaves the next one's prediction and features
+                L.features = feature_buffer(sub);
+                if (step == 0 && sub == 0)
+                    HIP_TRY(xpbd::launch_learned_predict(a, L, b->stream));
                 HIP_TRY(xpbd::launch_learned_correct(a, L, net->d, b->correct_workgroups,
                                                      b->stream));
+                if (!last)
+                    L.next_features = feature_buffer((sub + 1) % S);
+            } else {
+                HIP_TRY(xpbd::launch_learned_predict(a, L, b->stream));
+            }
             HIP_TRY(xpbd::launch_substep_reg(a, L, b->block, b->lambda_banks, b->lds_bytes,
                                              last && resid, b->stream));
         }

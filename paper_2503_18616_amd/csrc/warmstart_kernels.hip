@@ -175,90 +175,128 @@ learned_correct_kernel(StepArgs A, LearnedArgs L, MlpDev net)
     const int G = (L.max_vertices + 16 * kTiles - 1) / (16 * kTiles);
     const int items = A.num_envs * G;
     const int waves = gridDim.x * (kThreads / 64);
-    for (int item = __builtin_amdgcn_readfirstlane(blockIdx.x * (kThreads / 64) + (tid >> 6));
-         item < items; item += waves) {
-        const int env = item / G, p0 = (item % G) * 16 * kTiles;
+    // the loads of a work item are issued one item ahead, so they are in
+    // flight while the previous item's products run
+    struct Item {
+        bool ok;            // inside a mesh
+        int V, off, p0;
+        u32x4 w[kTiles];    // this lane's 16 bytes of each tile's feature rows
+        float xh[kTiles][3];
+        bool free_p[kTiles];
+    };
+    auto fetch = [&](int item, Item &d) {
+        d.ok = false;
+        if (item >= items)
+            return;
+        const int env = item / G;
         const EnvDev ed = A.envs[env];
         const MeshDev &md = A.meshes[ed.mesh];
-        const int V = md.num_vertices, off = ed.particle_offset;
-        if (p0 >= V)
-            continue;
-        const GLOBAL u32x4 *feat = (const GLOBAL u32x4 *)(uintptr_t)(L.features + (size_t)off * kMlpFeatPad);
-        bf16x8 x[kTiles];
+        d.V = md.num_vertices;
+        d.off = ed.particle_offset;
+        d.p0 = (item % G) * 16 * kTiles;
+        if (d.p0 >= d.V)
+            return;
+        d.ok = true;
+        const GLOBAL u32x4 *feat =
+            (const GLOBAL u32x4 *)(uintptr_t)(L.features + (size_t)d.off * kMlpFeatPad);
+        const GLOBAL float *xhat = (const GLOBAL float *)(uintptr_t)L.xhat;
+        const GLOBAL float *inv_mass = (const GLOBAL float *)(uintptr_t)md.inv_mass;
 #pragma unroll
         for (int t = 0; t < kTiles; ++t) {
-            const int i = p0 + 16 * t + r;
-            u32x4 w = {0u, 0u, 0u, 0u};
-            if (i < V)
-                w = feat[i * (kMlpFeatPad / 8) + g];
-            __builtin_memcpy(&x[t], &w, sizeof w);
-        }
-        // layer 1: 8 unit tiles, one k block
-        f32x4 acc[kTiles][8];
+            const int i = d.p0 + 16 * t + r;
+            const u32x4 zero = {0u, 0u, 0u, 0u};
+            d.w[t] = i < d.V ? feat[i * (kMlpFeatPad / 8) + g] : zero;
+            d.free_p[t] = false;
+            if (g == 0 && i < d.V) {
 #pragma unroll
-        for (int nt = 0; nt < 8; ++nt) {
-            const f32x4 bias = *reinterpret_cast<const f32x4 *>(&S.b1[16 * nt + 4 * g]);
-            const bf16x8 w = lds_frag(&S.w1[(16 * nt + r) * PF + 8 * g]);
+                for (int o = 0; o < 3; ++o)
+                    d.xh[t][o] = xhat[(size_t)o * NP + d.off + i];
+                d.free_p[t] = inv_mass[i] > 0.0f;
+            }
+        }
+    };
+    int item = __builtin_amdgcn_readfirstlane(blockIdx.x * (kThreads / 64) + (tid >> 6));
+    Item cur;
+    fetch(item, cur);
+    for (; item < items; item += waves) {
+        Item next;
+        fetch(item + waves, next);
+        if (cur.ok) {
+            bf16x8 x[kTiles];
 #pragma unroll
             for (int t = 0; t < kTiles; ++t)
-                acc[t][nt] = mfma(w, x[t], bias);
-        }
-        bf16x8 hid[kTiles][4];
+                __builtin_memcpy(&x[t], &cur.w[t], sizeof x[t]);
+            // layer 1: 8 unit tiles, one k block
+            f32x4 acc[kTiles][8];
 #pragma unroll
-        for (int t = 0; t < kTiles; ++t)
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb)
-                hid[t][kb] = relu_pack(acc[t][2 * kb], acc[t][2 * kb + 1]);
-        // layer 2: 8 unit tiles, four k blocks; independent accumulators innermost
-#pragma unroll
-        for (int mt = 0; mt < 8; ++mt) {
-            const f32x4 bias = *reinterpret_cast<const f32x4 *>(&S.b2[16 * mt + 4 * g]);
-#pragma unroll
-            for (int t = 0; t < kTiles; ++t)
-                acc[t][mt] = bias;
-        }
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-            for (int mt = 0; mt < 8; ++mt) {
-                const bf16x8 w = lds_frag(&S.w2[(16 * mt + r) * PW + 32 * kb + 8 * g]);
+            for (int nt = 0; nt < 8; ++nt) {
+                const f32x4 bias = *reinterpret_cast<const f32x4 *>(&S.b1[16 * nt + 4 * g]);
+                const bf16x8 w = lds_frag(&S.w1[(16 * nt + r) * PF + 8 * g]);
 #pragma unroll
                 for (int t = 0; t < kTiles; ++t)
-                    acc[t][mt] = mfma(w, hid[t][kb], acc[t][mt]);
+                    acc[t][nt] = mfma(w, x[t], bias);
             }
-#pragma unroll
-        for (int t = 0; t < kTiles; ++t)
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb)
-                hid[t][kb] = relu_pack(acc[t][2 * kb], acc[t][2 * kb + 1]);
-        // layer 3: outputs 0..2 (rows 3..15 of W3 are zero)
-        f32x4 y[kTiles];
-        const f32x4 b3 = *reinterpret_cast<const f32x4 *>(&S.b3[4 * g]);
-#pragma unroll
-        for (int t = 0; t < kTiles; ++t)
-            y[t] = b3;
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            const bf16x8 w = lds_frag(&S.w3[r * PW + 32 * kb + 8 * g]);
+            bf16x8 hid[kTiles][4];
 #pragma unroll
             for (int t = 0; t < kTiles; ++t)
-                y[t] = mfma(w, hid[t][kb], y[t]);
-        }
-        // lanes 0..15 hold outputs 0..2 of particle r of every tile
-        if (g == 0) {
-            const GLOBAL float *inv_mass = (const GLOBAL float *)(uintptr_t)md.inv_mass;
 #pragma unroll
-            for (int t = 0; t < kTiles; ++t) {
-                const int i = p0 + 16 * t + r;
-                if (i >= V || !(inv_mass[i] > 0.0f))
-                    continue;
+                for (int kb = 0; kb < 4; ++kb)
+                    hid[t][kb] = relu_pack(acc[t][2 * kb], acc[t][2 * kb + 1]);
+            // layer 2: 8 unit tiles, four k blocks; independent accumulators innermost
 #pragma unroll
-                for (int o = 0; o < 3; ++o) {
-                    const float yc = fminf(fmaxf(y[t][o], -kMlpClip), kMlpClip);
-                    L.xhat[(size_t)o * NP + off + i] += oshift[o] + yc * oscale[o];
+            for (int mt = 0; mt < 8; ++mt) {
+                const f32x4 bias = *reinterpret_cast<const f32x4 *>(&S.b2[16 * mt + 4 * g]);
+#pragma unroll
+                for (int t = 0; t < kTiles; ++t)
+                    acc[t][mt] = bias;
+            }
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+                for (int mt = 0; mt < 8; ++mt) {
+                    const bf16x8 w = lds_frag(&S.w2[(16 * mt + r) * PW + 32 * kb + 8 * g]);
+#pragma unroll
+                    for (int t = 0; t < kTiles; ++t)
+                        acc[t][mt] = mfma(w, hid[t][kb], acc[t][mt]);
+                }
+#pragma unroll
+            for (int t = 0; t < kTiles; ++t)
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb)
+                    hid[t][kb] = relu_pack(acc[t][2 * kb], acc[t][2 * kb + 1]);
+            // layer 3: outputs 0..2 (rows 3..15 of W3 are zero)
+            f32x4 y[kTiles];
+            const f32x4 b3 = *reinterpret_cast<const f32x4 *>(&S.b3[4 * g]);
+#pragma unroll
+            for (int t = 0; t < kTiles; ++t)
+                y[t] = b3;
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                const bf16x8 w = lds_frag(&S.w3[r * PW + 32 * kb + 8 * g]);
+#pragma unroll
+                for (int t = 0; t < kTiles; ++t)
+                    y[t] = mfma(w, hid[t][kb], y[t]);
+            }
+            // lanes 0..15 hold outputs 0..2 of particle r of every tile
+            if (g == 0) {
+#pragma unroll
+                for (int t = 0; t < kTiles; ++t) {
+                    const int i = cur.p0 + 16 * t + r;
+                    if (i >= cur.V)
+                        continue;
+#pragma unroll
+                    for (int o = 0; o < 3; ++o) {
+                        float p = cur.xh[t][o];
+                        if (cur.free_p[t]) {
+                            const float yc = fminf(fmaxf(y[t][o], -kMlpClip), kMlpClip);
+                            p += oshift[o] + yc * oscale[o];
+                        }
+                        L.xhat[(size_t)o * NP + cur.off + i] = p;
+                    }
                 }
             }
         }
+        cur = next;
     }
 }
 

@@ -98,6 +98,8 @@ struct StepArgs {
 struct LearnedArgs {
     float *xhat;                 // [3][total particles] predicted (then corrected) positions
     uint16_t *features;          // [total particles][32] bfloat16 scaled features, [31] = free flag
+    uint16_t *next_features;     // the substep kernel writes the next substep's prediction to
+                                 // xhat and its features here when set
     uint8_t *cand;               // [total particles] bit t: candidate of tool t in this step
     const float *in_shift;       // [32] features are (f - in_shift) * in_scale
     const float *in_scale;       // [32]
@@ -106,7 +108,7 @@ struct LearnedArgs {
     float *record_targets;       // [total particles][4] (x - x_hat - out_shift) / out_scale, or null
     int32_t *iterations;         // [N] sweeps run in this substep, or null
     float threshold;             // residual RMS above which the sweeps continue
-    float stall_ratio;           // > 0: the further sweeps stop once one lowers the RMS by less
+    float stall_ratio;           // > 0: no further sweeps when the last minimum sweep stalled
     int32_t min_iterations;
     int32_t max_iterations;
     int32_t first_substep;       // 1: find the contact candidates on the start-of-step positions

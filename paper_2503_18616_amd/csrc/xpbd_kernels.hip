@@ -1046,8 +1046,6 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
     };
 
     int n_it = 0;
-    for (; n_it < L.min_iterations; ++n_it)
-        sweep();
     // residual RMS of the environment (every thread gets it; the sweeps between
     // two evaluations hold barriers, and one follows the read)
     auto residual_rms = [&]() {
@@ -1072,21 +1070,25 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
         const int n_con = md.num_edges + md.num_tets;
         return n_con > 0 ? sqrtf(total / (float)n_con) : 0.0f;
     };
-    if (L.max_iterations > L.min_iterations) {
-        float rms = residual_rms();
-        if (rms > L.threshold)
-            while (n_it < L.max_iterations) {
+    // min_iterations sweeps; with a stall ratio the residual is taken before the
+    // last of them too, and the further sweeps run only if that sweep lowered
+    // it to at most stall_ratio times that value
+    const bool check = L.max_iterations > L.min_iterations;
+    const bool stall_check = check && L.stall_ratio > 0.0f && L.min_iterations >= 1;
+    float before = 0.0f;
+    for (; n_it < L.min_iterations; ++n_it) {
+        if (stall_check && n_it == L.min_iterations - 1)
+            before = residual_rms();
+        sweep();
+    }
+    if (check) {
+        const float rms = residual_rms();
+        bool go_on = rms > L.threshold;
+        if (go_on && stall_check)
+            go_on = rms <= L.stall_ratio * before;
+        if (go_on)
+            for (; n_it < L.max_iterations; ++n_it)
                 sweep();
-                ++n_it;
-                if (!(L.stall_ratio > 0.0f) || n_it == L.max_iterations)
-                    continue;
-                // stop once below the threshold or when a sweep no longer
-                // lowers the residual by the factor stall_ratio
-                const float next = residual_rms();
-                if (next <= L.threshold || next > L.stall_ratio * rms)
-                    break;
-                rms = next;
-            }
     }
 
     // velocity update and write-back (structure of arrays); slot_of[i] belongs
@@ -1122,6 +1124,78 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
             A.nonfinite[env] = 1;
         if (L.iterations)
             L.iterations[env] = n_it;
+    }
+
+    // the prediction and features of the next substep from the state just
+    // written (the same arithmetic as learned_predict_kernel): x_hat into the
+    // start-of-substep slots first, then every particle reads its neighbours'
+    if (L.next_features) {
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        typedef float f32x2 __attribute__((ext_vector_type(2)));
+        typedef float f32x4 __attribute__((ext_vector_type(4)));
+        const XPBD_GLOBAL f32x4 *rest4 = (const XPBD_GLOBAL f32x4 *)(uintptr_t)md.rest4;
+        const XPBD_GLOBAL int32_t *nbr = (const XPBD_GLOBAL int32_t *)(uintptr_t)md.nbr;
+        const float h = A.h;
+        const float hg[3] = {h * A.gravity[0], h * A.gravity[1], h * A.gravity[2]};
+        for (int i = tid; i < V; i += B) {
+            const int sl = md.slot_of[i];
+            const float4 p = xw[sl];
+            const float x[3] = {p.x, p.y, p.z};
+            const float hs = p.w > 0.0f ? h : 0.0f;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const float v = (x[k] - prev[k * V + sl]) * inv_h;
+                prev[k * V + sl] = x[k] + hs * (v + hg[k]);
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < V; i += B) {
+            const int sl = md.slot_of[i];
+            const float4 p = xw[sl];
+            const f32x4 Ri = rest4[i];
+            const float x[3] = {p.x, p.y, p.z}, rest[3] = {Ri.x, Ri.y, Ri.z};
+            float xh[3], f[32];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                xh[k] = prev[k * V + sl];
+                L.xhat[k * NP + off + i] = xh[k];
+                f[k] = xh[k] - x[k];
+                f[3 + k] = A.vel[k * NP + off + i];
+                f[6 + k] = xh[k] - rest[k];
+            }
+            int nb[6];
+#pragma unroll
+            for (int d = 0; d < 6; ++d)
+                nb[d] = nbr[6 * i + d];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                const int j = nb[d] >= 0 ? nb[d] : i;
+                const int sj = md.slot_of[j];
+                const f32x4 Rj = rest4[j];
+                const float rj[3] = {Rj.x, Rj.y, Rj.z};
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    f[9 + 3 * d + k] =
+                        nb[d] >= 0 ? (prev[k * V + sj] - xh[k]) - (rj[k] - rest[k]) : 0.0f;
+            }
+            uint32_t packed[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int c0 = 2 * c, c1 = 2 * c + 1;
+                const float lo = c0 < 27 ? (f[c0] - L.in_shift[c0]) * L.in_scale[c0] : 0.0f;
+                float hi = c1 < 27 ? (f[c1] - L.in_shift[c1]) * L.in_scale[c1] : 0.0f;
+                if (c1 == 31)
+                    hi = Ri.w > 0.0f ? 1.0f : 0.0f;
+                const f32x2 pair = {lo, hi};
+                const bf16x2 b = __builtin_convertvector(pair, bf16x2);
+                __builtin_memcpy(&packed[c], &b, sizeof(uint32_t));
+            }
+            uint4 *dst = reinterpret_cast<uint4 *>(L.next_features + (size_t)(off + i) * 32);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                dst[q] = make_uint4(packed[4 * q], packed[4 * q + 1], packed[4 * q + 2],
+                                    packed[4 * q + 3]);
+        }
     }
 
     // contact candidates of the step as ascending mesh ids (first substep only)

@@ -197,38 +197,31 @@ def test_exact_corrector_needs_no_fallback(small):
 
 def test_stall_rule_limits(small):
     """The stall rule's two limits are plain runs: a ratio no sweep can exceed
-    never stops the further sweeps (the full count, evaluations aside, leaves
-    the state untouched), and a tiny ratio stops them after the first further
-    sweep, which is a run with one sweep more than the minimum."""
+    never stops the further sweeps (the extra evaluation leaves the state
+    untouched), and a tiny ratio always does, which is a run with the minimum
+    number of sweeps."""
     wl, om, P, tools = small
-    full = oracle.run_env_learned(om, wl.compliance[0], P, tools[:, 0], 12, None, 1,
+    full = oracle.run_env_learned(om, wl.compliance[0], P, tools[:, 0], 12, None, 2,
                                   wl.iterations, -1.0)
-    never = oracle.run_env_learned(om, wl.compliance[0], P, tools[:, 0], 12, None, 1,
+    never = oracle.run_env_learned(om, wl.compliance[0], P, tools[:, 0], 12, None, 2,
                                    wl.iterations, -1.0, stall_ratio=1e300)
     assert np.array_equal(never.x, full.x) and np.all(never.iterations == wl.iterations)
-    once = oracle.run_env_learned(om, wl.compliance[0], P, tools[:, 0], 12, None, 1,
-                                  wl.iterations, -1.0, stall_ratio=1e-300)
+    always = oracle.run_env_learned(om, wl.compliance[0], P, tools[:, 0], 12, None, 2,
+                                    wl.iterations, -1.0, stall_ratio=1e-300)
     two = oracle.run_env_learned(om, wl.compliance[0], P, tools[:, 0], 12, None, 2, 2, np.inf)
-    assert np.all(once.iterations == 2)
-    assert np.array_equal(once.x, two.x) and np.array_equal(once.v, two.v)
+    assert np.all(always.iterations == 2)
+    assert np.array_equal(always.x, two.x) and np.array_equal(always.v, two.v)
 
 
 def test_stall_rule_decisions_follow_the_recorded_residuals(small):
-    """Where the further sweeps stopped short of the maximum, the last evaluated
-    residual is at or below the threshold or above stall_ratio times the one
-    before; every earlier evaluation was below that bound."""
+    """The further sweeps ran exactly where the residual after the minimum was
+    above the threshold and the last of the minimum sweeps had lowered it to at
+    most stall_ratio times the value before it."""
     wl, om, P, tools = small
     stall, thr = 0.9, 2e-4
     r = oracle.run_env_learned(om, wl.compliance[0], P, tools[:, 0], 12, None, 2,
                                wl.iterations, thr, stall_ratio=stall)
-    assert len(np.unique(r.iterations)) > 1
-    for s in range(12):
-        for k in range(wl.substeps):
-            c, n = r.checks[s, k], int(r.iterations[s, k])
-            if c[2] <= thr:
-                assert n == 2
-                continue
-            for m in range(3, n):
-                assert thr < c[m] <= stall * c[m - 1]
-            if n < wl.iterations:
-                assert c[n] <= thr or c[n] > stall * c[n - 1]
+    c = r.checks
+    go_on = (c[:, :, 2] > thr) & (c[:, :, 2] <= stall * c[:, :, 1])
+    assert np.array_equal(r.iterations, np.where(go_on, wl.iterations, 2))
+    assert 0 < go_on.sum() < go_on.size
