@@ -67,6 +67,8 @@ def parse_args():
     ap.add_argument("--cpu-envs", type=int, default=64, help="oracle sample: environments")
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle sample: steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tool-lift", type=float, default=0.0, metavar="M",
+                    help="raise every tool pose by M metres (1.0: no contact anywhere)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned warm-start leg (training + timed learned steps)")
     ap.add_argument("--learned-steps", type=int, default=100, help="timed learned steps")
@@ -119,6 +121,14 @@ def measured_traffic(workload, steps_per_launch, args):
     return rec["traffic_bytes_per_launch"]
 
 
+def lifted(tool_pos, args):
+    """Tool poses raised by --tool-lift metres along z."""
+    if args.tool_lift:
+        tool_pos = tool_pos.copy()
+        tool_pos[..., 2] += args.tool_lift
+    return tool_pos
+
+
 def learned_leg(args, wl_fn, mesh, make_batch, I, S):
     """The learned warm start on the same workload: train the network on
     recorded substeps of a separate training run (untimed), then time
@@ -134,7 +144,7 @@ def learned_leg(args, wl_fn, mesh, make_batch, I, S):
     # training run: its own seeds, the same mesh and compliance distribution
     warm = 20
     tw = wl_fn(args.train_envs, seed=1, num_steps=warm + args.train_records)
-    ttools = torch.from_numpy(tw.tools(warm + args.train_records)).cuda()
+    ttools = torch.from_numpy(lifted(tw.tools(warm + args.train_records), args)).cuda()
     subs = [k % S for k in range(args.train_records)]
     with make_batch(tw, 0) as tb:
         tb.step(warm, ttools[:warm])
@@ -156,7 +166,7 @@ def learned_leg(args, wl_fn, mesh, make_batch, I, S):
     N = args.envs
     total = args.warmup + args.learned_steps
     wl = wl_fn(N, seed=0, num_steps=total)
-    tools = torch.from_numpy(wl.tools(total)).cuda()
+    tools = torch.from_numpy(lifted(wl.tools(total), args)).cuda()
     its = torch.zeros(args.learned_steps * S * N, dtype=torch.int32, device="cuda")
     with make_batch(wl, xpbd.F_RESIDUAL) as pb, make_batch(wl, xpbd.F_RESIDUAL) as lb:
         warm_res = []
@@ -266,7 +276,7 @@ def main():
     v_free = int((m.inv_mass > 0).sum())
     N, S, I = wl.num_envs, wl.substeps, wl.iterations
 
-    tools = torch.from_numpy(wl.tools(total)).cuda()
+    tools = torch.from_numpy(lifted(wl.tools(total), args)).cuda()
     params = xpbd.make_params(wl.dt, S, I, wl.gravity, wl.num_tools, wl.tool_radius,
                               flags=0, block_size=args.block,
                               solver_variant=args.variant, colour_packing=args.packing,
@@ -320,7 +330,7 @@ def main():
         om = [oracle.prepare_mesh(m.rest_pos, m.inv_mass, m.tets)]
         op = oracle.OracleParams(f32(wl.dt), S, I, tuple(f32(g) for g in wl.gravity),
                                  wl.num_tools, tuple(f32(r) for r in wl.tool_radius))
-        cpu_tools = wl.tools(args.cpu_steps, env_ids=sample_envs)
+        cpu_tools = lifted(wl.tools(args.cpu_steps, env_ids=sample_envs), args)
         threads = min(16, os.cpu_count() or 1, len(sample_envs))
         t0 = time.perf_counter()
         oracle.run_batch(om, wl.env_mesh, wl.compliance, op, cpu_tools, args.cpu_steps,
@@ -349,6 +359,7 @@ def main():
         "config": {"workload": wl.name, "envs": N, "grid": [m.nx, m.ny, m.nz], "particles": V,
                    "edges": E, "tets": T, "substeps": S, "iterations": I,
                    "steps_per_launch": spl, "solver": "plain (no warm start)",
+                   "tool_lift_m": args.tool_lift,
                    "residual_rms_mean": float(resid[:, 0].mean()),
                    "residual_max": float(resid[:, 1].max())},
         "roofline": roofline, "lds": lds_line, "hbm": hbm_line, "cpu_baseline": cpu,
