@@ -53,8 +53,9 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000, help="timed steps")
     ap.add_argument("--warmup", type=int, default=20, help="untimed steps first")
-    ap.add_argument("--workload", choices=["batch", "single"], default="batch")
-    ap.add_argument("--envs", type=int, default=1024, help="environments of the batch workload")
+    ap.add_argument("--workload", choices=["batch", "uneven", "single"], default="batch")
+    ap.add_argument("--envs", type=int, default=0,
+                    help="environments (0: 1024 for the batch workload, 4096 for the uneven one)")
     ap.add_argument("--steps-per-launch", type=int, default=1)
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library's choice)")
     ap.add_argument("--variant", type=int, default=0,
@@ -121,6 +122,11 @@ def measured_traffic(workload, steps_per_launch, args):
     return rec["traffic_bytes_per_launch"]
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def lifted(tool_pos, args):
     """Tool poses raised by --tool-lift metres along z."""
     if args.tool_lift:
@@ -161,6 +167,7 @@ def learned_leg(args, wl_fn, mesh, make_batch, I, S):
     losses = trainer.train(net, feats, targets, args.train_steps)
     del feats, targets
     train_s = time.perf_counter() - t0
+    progress(f"learned warm start: trained in {train_s:.1f} s")
 
     # evaluation: plain and learned from the same state of the benchmark workload
     N = args.envs
@@ -265,16 +272,25 @@ def main():
     torch.cuda.set_device(0)
     total = args.warmup + args.steps
     if args.workload == "batch":
+        args.envs = args.envs or 1024
         wl = W.batch_workload(args.envs, seed=0, num_steps=total)
+    elif args.workload == "uneven":
+        args.envs = args.envs or 4096
+        wl = W.uneven_workload(args.envs, seed=0, num_steps=total)
     else:
         wl = W.single_env_workload(seed=0)
         wl.num_steps = total
+        args.envs = 1
     m = wl.meshes[0]
-    info = xpbd.xpbd_prepare_mesh(m.rest_pos, m.inv_mass, m.tets)
-    E, T = int(info["edges"].shape[0]), int(info["tets"].shape[0])
-    V = m.num_vertices
-    v_free = int((m.inv_mass > 0).sum())
     N, S, I = wl.num_envs, wl.substeps, wl.iterations
+    # per-mesh sizes (kept edges and tets, free particles), summed over the environments
+    sizes = []
+    for mm in wl.meshes:
+        info = xpbd.xpbd_prepare_mesh(mm.rest_pos, mm.inv_mass, mm.tets)
+        sizes.append((int(info["edges"].shape[0]), int(info["tets"].shape[0]), mm.num_vertices,
+                      int((mm.inv_mass > 0).sum())))
+    env_sizes = np.array([sizes[int(k)] for k in wl.env_mesh], np.int64)   # [N][E, T, V, free]
+    E, T, V, v_free = (int(x) for x in sizes[0])
 
     tools = torch.from_numpy(lifted(wl.tools(total), args)).cuda()
     params = xpbd.make_params(wl.dt, S, I, wl.gravity, wl.num_tools, wl.tool_radius,
@@ -282,8 +298,11 @@ def main():
                               solver_variant=args.variant, colour_packing=args.packing,
                               envs_per_group=args.group)
     stream = torch.cuda.current_stream()
-    batch = xpbd.Batch([(m.rest_pos, m.inv_mass, m.tets)], wl.env_mesh, wl.compliance, params,
-                       stream=stream.cuda_stream)
+    t_create = time.perf_counter()
+    batch = xpbd.Batch([(mm.rest_pos, mm.inv_mass, mm.tets) for mm in wl.meshes], wl.env_mesh,
+                       wl.compliance, params, stream=stream.cuda_stream)
+    t_create = time.perf_counter() - t_create
+    progress(f"{wl.name}: {N} environments of {len(wl.meshes)} meshes set up in {t_create:.1f} s")
     spl = args.steps_per_launch
     for s in range(0, args.warmup, spl):
         batch.step(spl, tools[s:s + spl])
@@ -299,6 +318,7 @@ def main():
     end.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
+    progress(f"timed {args.steps} steps: {ms / args.steps:.3f} ms per step")
     launches = args.steps // spl
     env_substeps = N * args.steps * S
     value = env_substeps / (ms / 1e3)
@@ -307,10 +327,10 @@ def main():
 
     # roofline of the step kernel (the only kernel in the timed region)
     launch_s = ms / 1e3 / launches
-    substeps_per_launch = N * spl * S
-    flops = substeps_per_launch * (I * (E * FLOPS_EDGE + T * FLOPS_TET) + v_free * FLOPS_PARTICLE)
-    lds = substeps_per_launch * (I * (E * LDS_EDGE + T * LDS_TET) + V * LDS_PARTICLE)
-    hbm = N * (V * HBM_PARTICLE + spl * wl.num_tools * 12)
+    Es, Ts, Vs, Fs = (env_sizes[:, k] for k in range(4))
+    flops = int(spl * S * (I * (Es * FLOPS_EDGE + Ts * FLOPS_TET) + Fs * FLOPS_PARTICLE).sum())
+    lds = int(spl * S * (I * (Es * LDS_EDGE + Ts * LDS_TET) + Vs * LDS_PARTICLE).sum())
+    hbm = int((Vs * HBM_PARTICLE + spl * wl.num_tools * 12).sum())
     roofline = {"bound": "alu", "achieved": flops / launch_s / 1e12,
                 "peak": PEAK_FP32_NONPACKED / 1e12, "unit": "TFLOP/s",
                 "frac": flops / launch_s / PEAK_FP32_NONPACKED,
@@ -327,7 +347,9 @@ def main():
         import oracle
         sample_envs = list(range(0, N, max(1, N // args.cpu_envs)))[:args.cpu_envs]
         f32 = lambda v: float(np.float32(v))
-        om = [oracle.prepare_mesh(m.rest_pos, m.inv_mass, m.tets)]
+        used = sorted({int(wl.env_mesh[e]) for e in sample_envs})
+        om = [oracle.prepare_mesh(wl.meshes[k].rest_pos, wl.meshes[k].inv_mass, wl.meshes[k].tets)
+              if k in used else None for k in range(len(wl.meshes))]
         op = oracle.OracleParams(f32(wl.dt), S, I, tuple(f32(g) for g in wl.gravity),
                                  wl.num_tools, tuple(f32(r) for r in wl.tool_radius))
         cpu_tools = lifted(wl.tools(args.cpu_steps, env_ids=sample_envs), args)
@@ -336,6 +358,7 @@ def main():
         oracle.run_batch(om, wl.env_mesh, wl.compliance, op, cpu_tools, args.cpu_steps,
                          env_ids=sample_envs, threads=threads)
         dt = time.perf_counter() - t0
+        progress(f"oracle sample: {dt:.1f} s")
         cpu = {"value": len(sample_envs) * args.cpu_steps * S / dt, "unit": "env-substeps/s",
                "cores": threads, "kind": "oracle",
                "sample": f"{len(sample_envs)} of the {N} environments x {args.cpu_steps} steps "
@@ -356,8 +379,12 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "envs": N, "grid": [m.nx, m.ny, m.nz], "particles": V,
-                   "edges": E, "tets": T, "substeps": S, "iterations": I,
+        "config": {"workload": wl.name, "envs": N, "meshes": len(wl.meshes),
+                   "grid": [m.nx, m.ny, m.nz] if len(wl.meshes) == 1 else "per environment",
+                   "particles": V if len(wl.meshes) == 1 else int(Vs.sum()),
+                   "edges": E if len(wl.meshes) == 1 else int(Es.sum()),
+                   "tets": T if len(wl.meshes) == 1 else int(Ts.sum()),
+                   "substeps": S, "iterations": I, "create_s": round(t_create, 3),
                    "steps_per_launch": spl, "solver": "plain (no warm start)",
                    "tool_lift_m": args.tool_lift,
                    "residual_rms_mean": float(resid[:, 0].mean()),

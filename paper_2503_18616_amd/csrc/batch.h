@@ -12,6 +12,20 @@
 #include "runtime_util.h"
 #include "xpbd_device.h"
 
+// A size class of the register variant: environments whose meshes share a
+// block size and an LDS tier run in one launch; several classes run
+// concurrently on streams of their own, forked from and joined to the
+// batch's stream.
+struct RegClass {
+    int block = 256;
+    int lambda_banks = 1;
+    uint32_t lds_bytes = 0;
+    int32_t num_groups = 0;
+    int32_t *groups_dev = nullptr;
+    hipStream_t stream = nullptr;   // own stream when the batch has several classes
+    hipEvent_t done = nullptr;
+};
+
 struct xpbd_batch {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -28,6 +42,8 @@ struct xpbd_batch {
     int32_t num_groups = 0;
     int32_t *groups_dev = nullptr;
     uint32_t lds_bytes = 0;
+    std::vector<RegClass> classes;           // register variant
+    hipEvent_t fork = nullptr;               // start of a step on the batch's stream
     std::vector<xpbd::PreparedMesh> meshes;
     std::vector<int32_t> env_mesh;
     std::vector<int32_t> env_offsets;       // [N+1]
@@ -53,6 +69,16 @@ struct xpbd_batch {
     ~xpbd_batch()
     {
         (void)hipStreamSynchronize(stream);
+        for (auto &c : classes) {
+            if (c.stream) {
+                (void)hipStreamSynchronize(c.stream);
+                (void)hipStreamDestroy(c.stream);
+            }
+            if (c.done)
+                (void)hipEventDestroy(c.done);
+        }
+        if (fork)
+            (void)hipEventDestroy(fork);
         for (auto &a : allocations)
             (void)hipFree(a.ptr);
         if (tool_staging)

@@ -194,6 +194,9 @@ __host__ __device__ inline RegLdsLayout reg_lds_layout(int32_t V)
 // envs_per_group in {1, 2}; one workgroup per group.
 hipError_t launch_step_reg(const StepArgs &args, int block, int lambda_banks, int envs_per_group,
                            uint32_t lds_bytes, bool want_residual, hipStream_t stream);
+// Residual RMS and max of every environment from the multipliers of the last
+// launch (register variant).
+hipError_t launch_residual(const StepArgs &args, hipStream_t stream);
 // Learned warm start: prediction + features of one substep (every particle of
 // every environment), then one substep of the register-multiplier solver
 // starting from the predicted (and corrected) positions.

@@ -1407,6 +1407,12 @@ hipError_t launch_step_reg(const StepArgs &args, int block, int lambda_banks, in
     return hipGetLastError();
 }
 
+hipError_t launch_residual(const StepArgs &args, hipStream_t stream)
+{
+    hipLaunchKernelGGL(residual_kernel, dim3((unsigned)args.num_envs), dim3(256), 0, stream, args);
+    return hipGetLastError();
+}
+
 hipError_t launch_learned_predict(const StepArgs &args, const LearnedArgs &largs, hipStream_t stream)
 {
     hipLaunchKernelGGL(learned_predict_kernel,

@@ -15,6 +15,8 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <thread>
+#include <atomic>
 
 #include "../../include/xpbd.h"
 #include "mesh_setup.h"
@@ -67,6 +69,9 @@ xpbd_status validate_params(const xpbd_params *p)
 
 // Local-search moves per constraint of the SEARCH colour packing.
 constexpr int32_t kLaneSearchEffort = 64;
+// Distinct particles (summed over the batch's meshes) up to which the default
+// colour packing runs the lane search.
+constexpr int64_t kSearchParticles = 16384;
 
 int next_pow2(int x)
 {
@@ -349,19 +354,99 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     b->max_vertices = vmax;
     b->meshes = std::move(prepared);
 
+    // register variant: each mesh gets the smallest block whose rounds fit the
+    // register banks (every mesh fits the batch-wide choice), and an LDS tier:
+    // the most workgroups per CU its LDS and the 16 resident waves of a CU
+    // allow.  Meshes of equal (block, tier) form a size class, launched
+    // together; a requested block size makes one class.
+    std::vector<int> mesh_block((size_t)num_meshes, block), mesh_class((size_t)num_meshes, 0);
+    if (use_registers) {
+        int lds_cu = 0;
+        HIP_TRY(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                      device));
+        lds_cu = std::max(lds_cu, lds_limit);
+        const int G = reg_group;
+        std::vector<std::pair<int, int>> keys;
+        for (int32_t m = 0; m < num_meshes; ++m) {
+            const PreparedMesh &pm = b->meshes[(size_t)m];
+            int B = block;
+            if (params->block_size == 0) {
+                for (int cand : {256, 512, 1024}) {
+                    int r = count_rounds(pm, cand, G);
+                    r += r % 2;
+                    if (r <= xpbd::kMaxRounds && G * pm.num_vertices <= 16 * cand) {
+                        B = cand;
+                        break;
+                    }
+                }
+            }
+            mesh_block[(size_t)m] = B;
+            const uint32_t lm = xpbd::reg_lds_layout(G * pm.num_vertices).total;
+            const int tier = std::max(1, std::min(16 / (B / 64), (int)((uint32_t)lds_cu / lm)));
+            const std::pair<int, int> key(B, tier);
+            auto it = std::find(keys.begin(), keys.end(), key);
+            if (it == keys.end()) {
+                keys.push_back(key);
+                it = keys.end() - 1;
+            }
+            mesh_class[(size_t)m] = (int)(it - keys.begin());
+        }
+        b->classes.resize(keys.size());
+        for (size_t c = 0; c < keys.size(); ++c) {
+            b->classes[c].block = keys[c].first;
+            b->classes[c].lds_bytes = 0;
+            b->classes[c].lambda_banks = 1;
+        }
+        for (int32_t m = 0; m < num_meshes; ++m) {
+            RegClass &c = b->classes[(size_t)mesh_class[(size_t)m]];
+            const PreparedMesh &pm = b->meshes[(size_t)m];
+            c.lds_bytes = std::max(c.lds_bytes, xpbd::reg_lds_layout(G * pm.num_vertices).total);
+            int r = count_rounds(pm, c.block, G);
+            r += r % 2;
+            if (r > 32)
+                c.lambda_banks = 2;
+        }
+        if (b->classes.size() > 1) {
+            HIP_TRY(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+            for (auto &c : b->classes) {
+                HIP_TRY(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+                HIP_TRY(hipEventCreateWithFlags(&c.done, hipEventDisableTiming));
+            }
+        }
+    }
+
     auto cleanup = [&](xpbd_status st) {
         delete b;
         return st;
     };
 
-    // per-mesh device topology in schedule order
-    std::vector<MeshDev> mdev((size_t)num_meshes);
-    for (int32_t m = 0; m < num_meshes; ++m) {
+    // per-mesh tables in schedule order, built on host threads (the meshes are
+    // independent), then uploaded in mesh order
+    struct MeshHost {
+        MeshDev d;
+        std::vector<int32_t> eslot, eptr, tslot, tptr, rr_id, nbr;
+        std::vector<uint32_t> pair, round_rec;
+        std::vector<float> erest, trest;
+        std::vector<uint2> quad;
+        std::vector<uint16_t> slot16, id16;
+        std::vector<float4> rest4;
+    };
+    std::vector<MeshHost> host((size_t)num_meshes);
+    // the lane search costs about a second per thousand particles: the default
+    // uses it while the batch's distinct meshes stay small in total
+    int64_t distinct_particles = 0;
+    for (const auto &pm : b->meshes)
+        distinct_particles += pm.num_vertices;
+    auto build = [&](int32_t m) {
+        MeshHost &h = host[(size_t)m];
         const PreparedMesh &pm = b->meshes[(size_t)m];
+        const int block = mesh_block[(size_t)m];
         const int32_t V = pm.num_vertices, E = pm.num_edges(), T = pm.num_tets();
         int packing = params->colour_packing;
         if (packing == XPBD_PACKING_AUTO)
-            packing = use_registers ? XPBD_PACKING_SEARCH : XPBD_PACKING_BANKS16;
+            packing = !use_registers                            ? XPBD_PACKING_BANKS16
+                      : distinct_particles <= kSearchParticles ? XPBD_PACKING_SEARCH
+                                                                : XPBD_PACKING_SCATTERED_BANKS16;
         if ((packing == XPBD_PACKING_SCATTERED_BANKS16 || packing == XPBD_PACKING_SEARCH) &&
             !use_registers)
             packing = XPBD_PACKING_BANKS16;
@@ -371,16 +456,20 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
 
         // one environment's schedule (LDS variant and the residual kernel): mesh ids,
         // packed for the LDS variant's identity placement
-        std::vector<int32_t> eslot, eptr, tslot, tptr;
+        std::vector<int32_t> &eslot = h.eslot, &eptr = h.eptr, &tslot = h.tslot, &tptr = h.tptr;
         build_schedule(pm.edge_colour, pm.num_edge_colours, eslot, eptr);
         build_schedule(pm.tet_colour, pm.num_tet_colours, tslot, tptr);
         if (!use_registers) {
             xpbd::pack_colours(pm.edges.data(), 2, eptr, group, group, eslot);
             xpbd::pack_colours(pm.tets.data(), 4, tptr, group, group, tslot);
         }
-        std::vector<uint32_t> pair((size_t)E);
-        std::vector<float> erest((size_t)E), trest((size_t)T);
-        std::vector<uint2> quad((size_t)T);
+        std::vector<uint32_t> &pair = h.pair;
+        std::vector<float> &erest = h.erest, &trest = h.trest;
+        std::vector<uint2> &quad = h.quad;
+        pair.resize((size_t)E);
+        erest.resize((size_t)E);
+        trest.resize((size_t)T);
+        quad.resize((size_t)T);
         for (int32_t j = 0; j < E; ++j) {
             const int32_t e = eslot[(size_t)j];
             pair[(size_t)j] = (uint32_t)pm.edges[2 * (size_t)e] |
@@ -441,7 +530,9 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
                 xpbd::pack_colours(t_lds.data(), 4, gtptr, group, group, gtslot);
             }
         }
-        std::vector<uint16_t> slot16((size_t)GV), id16((size_t)GV);
+        std::vector<uint16_t> &slot16 = h.slot16, &id16 = h.id16;
+        slot16.resize((size_t)GV);
+        id16.resize((size_t)GV);
         for (int32_t i = 0; i < GV; ++i) {
             slot16[(size_t)i] = (uint16_t)slot_of[(size_t)i];
             id16[(size_t)slot_of[(size_t)i]] = (uint16_t)i;
@@ -454,11 +545,13 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         int32_t edge_rounds = 0;
         for (const int4 &rd : rounds)
             edge_rounds += (rd.z == xpbd::ROUND_EDGE && rd.y > rd.x) ? 1 : 0;
-        std::vector<uint32_t> round_rec((size_t)std::max(num_rounds, 1) * block * 3, 0u);
+        std::vector<uint32_t> &round_rec = h.round_rec;
+        round_rec.assign((size_t)std::max(num_rounds, 1) * block * 3, 0u);
         for (size_t q = 0; q < round_rec.size(); q += 3)
             round_rec[q] = xpbd::kInvalidRecord;
-        std::vector<int32_t> rr_id((size_t)std::max(num_rounds, 1) * block, -1);
-        MeshDev &d = mdev[(size_t)m];
+        std::vector<int32_t> &rr_id = h.rr_id;
+        rr_id.assign((size_t)std::max(num_rounds, 1) * block, -1);
+        MeshDev &d = h.d;
         std::memset(&d, 0, sizeof d);
         for (int32_t r = 0; r < num_rounds && use_registers; ++r) {
             const int4 rd = rounds[(size_t)r];
@@ -502,37 +595,66 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         d.num_tets = T;
         d.num_edge_colours = pm.num_edge_colours;
         d.num_tet_colours = pm.num_tet_colours;
+        xpbd::axis_neighbours(V, pm.rest_pos.data(), h.nbr);
+        h.rest4.resize((size_t)V);
+        for (int i = 0; i < V; ++i)
+            h.rest4[(size_t)i] = make_float4(pm.rest_pos[3 * (size_t)i], pm.rest_pos[3 * (size_t)i + 1],
+                                             pm.rest_pos[3 * (size_t)i + 2], pm.inv_mass[(size_t)i]);
+    };
+    {
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        const int workers = (int)std::min<unsigned>(hw, (unsigned)num_meshes);
+        std::atomic<int> next{0};
+        std::atomic<bool> failed{false};
+        auto work = [&]() {
+            for (int m; (m = next.fetch_add(1)) < num_meshes;) {
+                try {
+                    build(m);
+                } catch (...) {
+                    failed = true;
+                }
+            }
+        };
+        std::vector<std::thread> pool;
+        for (int t = 1; t < workers; ++t)
+            pool.emplace_back(work);
+        work();
+        for (auto &t : pool)
+            t.join();
+        if (failed)
+            return cleanup(fail(XPBD_E_ARG, "out of host memory while building the mesh tables"));
+    }
+    std::vector<MeshDev> mdev((size_t)num_meshes);
+    for (int32_t m = 0; m < num_meshes; ++m) {
+        const PreparedMesh &pm = b->meshes[(size_t)m];
+        MeshHost &h = host[(size_t)m];
+        MeshDev &d = mdev[(size_t)m];
+        d = h.d;
         uint32_t *p_pair;
         float *p_erest, *p_trest, *p_w;
         uint2 *p_quad;
         int32_t *p_eptr, *p_tptr, *p_eid, *p_tid;
         xpbd_status st;
-        std::vector<int32_t> nbr;
-        xpbd::axis_neighbours(V, pm.rest_pos.data(), nbr);
-        std::vector<float4> rest4((size_t)V);
-        for (int i = 0; i < V; ++i)
-            rest4[(size_t)i] = make_float4(pm.rest_pos[3 * (size_t)i], pm.rest_pos[3 * (size_t)i + 1],
-                                           pm.rest_pos[3 * (size_t)i + 2], pm.inv_mass[(size_t)i]);
         float *p_rest;
         int32_t *p_nbr;
         float4 *p_rest4;
-        if ((st = b->upload(&p_rest, pm.rest_pos)) || (st = b->upload(&p_nbr, nbr)) ||
-            (st = b->upload(&p_rest4, rest4)))
+        if ((st = b->upload(&p_rest, pm.rest_pos)) || (st = b->upload(&p_nbr, h.nbr)) ||
+            (st = b->upload(&p_rest4, h.rest4)))
             return cleanup(st);
         d.rest_pos = p_rest;
         d.nbr = p_nbr;
         d.rest4 = p_rest4;
-        if ((st = b->upload(&p_pair, pair)) || (st = b->upload(&p_erest, erest)) ||
-            (st = b->upload(&p_quad, quad)) || (st = b->upload(&p_trest, trest)) ||
-            (st = b->upload(&p_eptr, eptr)) || (st = b->upload(&p_tptr, tptr)) ||
-            (st = b->upload(&p_eid, eslot)) || (st = b->upload(&p_tid, tslot)) ||
+        if ((st = b->upload(&p_pair, h.pair)) || (st = b->upload(&p_erest, h.erest)) ||
+            (st = b->upload(&p_quad, h.quad)) || (st = b->upload(&p_trest, h.trest)) ||
+            (st = b->upload(&p_eptr, h.eptr)) || (st = b->upload(&p_tptr, h.tptr)) ||
+            (st = b->upload(&p_eid, h.eslot)) || (st = b->upload(&p_tid, h.tslot)) ||
             (st = b->upload(&p_w, pm.inv_mass)))
             return cleanup(st);
         uint32_t *p_rr;
         int32_t *p_rrid;
         uint16_t *p_slot, *p_id;
-        if ((st = b->upload(&p_rr, round_rec)) || (st = b->upload(&p_rrid, rr_id)) ||
-            (st = b->upload(&p_slot, slot16)) || (st = b->upload(&p_id, id16)))
+        if ((st = b->upload(&p_rr, h.round_rec)) || (st = b->upload(&p_rrid, h.rr_id)) ||
+            (st = b->upload(&p_slot, h.slot16)) || (st = b->upload(&p_id, h.id16)))
             return cleanup(st);
         d.round_rec = p_rr;
         d.rr_id = p_rrid;
@@ -549,27 +671,46 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         d.inv_mass = p_w;
         b->colours.insert(b->colours.end(), pm.edge_colour.begin(), pm.edge_colour.end());
         b->colours.insert(b->colours.end(), pm.tet_colour.begin(), pm.tet_colour.end());
+        host[(size_t)m] = MeshHost();   // release the host tables
     }
 
-    // workgroups of the register variant: environments of one mesh, G at a time in
-    // index order; a group left short repeats its last environment as filler (~env)
-    {
+    // workgroups of the register variant, per size class: environments of one
+    // mesh, G at a time; meshes with more constraints first, so the longest
+    // workgroups start first; a group left short repeats its last environment
+    // as filler (~env)
+    if (use_registers) {
         const int G = b->envs_per_group;
-        std::vector<int32_t> groups;
-        for (int32_t m = 0; m < num_meshes; ++m) {
-            std::vector<int32_t> mine;
-            for (int32_t e = 0; e < num_envs; ++e)
-                if (env_mesh[e] == m)
-                    mine.push_back(e);
-            for (size_t k = 0; k < mine.size(); k += (size_t)G)
-                for (int f = 0; f < G; ++f)
-                    groups.push_back(k + (size_t)f < mine.size() ? mine[k + (size_t)f]
-                                                                 : ~mine[mine.size() - 1]);
+        std::vector<int32_t> order((size_t)num_meshes);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+            const PreparedMesh &px = b->meshes[(size_t)x], &py = b->meshes[(size_t)y];
+            return px.num_edges() + px.num_tets() > py.num_edges() + py.num_tets();
+        });
+        std::vector<std::vector<int32_t>> mine((size_t)num_meshes);
+        for (int32_t e = 0; e < num_envs; ++e)
+            mine[(size_t)env_mesh[e]].push_back(e);
+        for (size_t c = 0; c < b->classes.size(); ++c) {
+            std::vector<int32_t> groups;
+            for (int32_t m : order) {
+                if (mesh_class[(size_t)m] != (int)c)
+                    continue;
+                const std::vector<int32_t> &v = mine[(size_t)m];
+                for (size_t k = 0; k < v.size(); k += (size_t)G)
+                    for (int f = 0; f < G; ++f)
+                        groups.push_back(k + (size_t)f < v.size() ? v[k + (size_t)f] : ~v.back());
+            }
+            RegClass &rc = b->classes[c];
+            rc.num_groups = (int32_t)(groups.size() / (size_t)G);
+            xpbd_status st = b->upload(&rc.groups_dev, groups);
+            if (st != XPBD_OK)
+                return cleanup(st);
         }
-        b->num_groups = (int32_t)(groups.size() / (size_t)G);
-        xpbd_status st = b->upload(&b->groups_dev, groups);
-        if (st != XPBD_OK)
-            return cleanup(st);
+        // the single-class fields of the batch (the learned step needs one class)
+        b->groups_dev = b->classes[0].groups_dev;
+        b->num_groups = b->classes[0].num_groups;
+        b->block = b->classes[0].block;
+        b->lds_bytes = b->classes[0].lds_bytes;
+        b->lambda_banks = b->classes[0].lambda_banks;
     }
 
     // environments
@@ -696,10 +837,31 @@ xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
     }
     const bool resid = (b->params.flags & XPBD_F_RESIDUAL) != 0;
     b->residual_valid = b->residual_valid || resid;
-    if (b->register_variant)
-        HIP_TRY(xpbd::launch_step_reg(a, b->block, b->lambda_banks, b->envs_per_group, b->lds_bytes,
+    if (b->register_variant && b->classes.size() == 1) {
+        const RegClass &c = b->classes[0];
+        a.groups = c.groups_dev;
+        a.num_groups = c.num_groups;
+        HIP_TRY(xpbd::launch_step_reg(a, c.block, c.lambda_banks, b->envs_per_group, c.lds_bytes,
                                       resid, b->stream));
-    else
+    } else if (b->register_variant) {
+        // one launch per size class on the class streams, joined before the residual
+        HIP_TRY(hipEventRecord(b->fork, b->stream));
+        for (const RegClass &c : b->classes) {
+            if (c.num_groups == 0)
+                continue;
+            HIP_TRY(hipStreamWaitEvent(c.stream, b->fork, 0));
+            a.groups = c.groups_dev;
+            a.num_groups = c.num_groups;
+            HIP_TRY(xpbd::launch_step_reg(a, c.block, c.lambda_banks, b->envs_per_group,
+                                          c.lds_bytes, false, c.stream));
+            HIP_TRY(hipEventRecord(c.done, c.stream));
+        }
+        for (const RegClass &c : b->classes)
+            if (c.num_groups > 0)
+                HIP_TRY(hipStreamWaitEvent(b->stream, c.done, 0));
+        if (resid)
+            HIP_TRY(xpbd::launch_residual(a, b->stream));
+    } else
         HIP_TRY(xpbd::launch_step(a, b->block, b->particles_per_thread, b->stage_topology,
                                   b->lds_bytes, resid, b->stream));
     return XPBD_OK;

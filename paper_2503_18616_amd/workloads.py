@@ -204,3 +204,18 @@ def batch_workload(num_envs: int = 1024, seed: int = 0, num_steps: int = 1000) -
     return Workload(f"batch-{num_envs}x16x10x4", [mesh], np.zeros(num_envs, np.int32),
                     log_uniform_compliance(num_envs, 1e-7, 1e-5, seed),
                     iterations=8, num_steps=num_steps, seed=seed)
+
+
+def uneven_workload(num_envs: int = 4096, seed: int = 0, num_steps: int = 1000) -> Workload:
+    """Slabs of per-environment resolutions nx in [6, 20], ny in [4, 12],
+    nz in [2, 6] (105 to 1911 particles), one mesh per distinct resolution,
+    per-env compliances log-uniform in [1e-7, 1e-5], 8 iterations."""
+    grids = uneven_grids(num_envs, seed)
+    keys = sorted({tuple(int(v) for v in g) for g in grids})
+    index = {k: i for i, k in enumerate(keys)}
+    meshes = [slab_mesh(*k) for k in keys]
+    env_mesh = np.array([index[tuple(int(v) for v in g)] for g in grids], np.int32)
+    return Workload(f"uneven-{num_envs}", meshes, env_mesh,
+                    log_uniform_compliance(num_envs, 1e-7, 1e-5, seed),
+                    iterations=8, num_steps=num_steps, seed=seed)
+

@@ -445,3 +445,25 @@ def test_flags_can_change_between_steps(xp):
             b.read(xp.FIELD_LAMBDA)
         with pytest.raises(xp.XpbdError):
             b.set_flags(0x40)
+
+
+def test_uneven_4096_sampled_parity(xp, oracle_lib):
+    """The 4096-environment uneven workload (675 distinct slabs of 105 to 1911
+    particles) in one launch: the smallest and largest environments and four
+    others follow the oracle after 20 steps."""
+    steps = 20
+    wl = W.uneven_workload(4096, seed=0, num_steps=steps)
+    V = np.array([m.num_vertices for m in wl.meshes])[wl.env_mesh]
+    sample = sorted({int(np.argmin(V)), int(np.argmax(V)), 0, 1000, 2047, 4095})
+    tools = wl.tools(steps)
+    om = [oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass, m.tets)
+          if k in {int(wl.env_mesh[e]) for e in sample} else None
+          for k, m in enumerate(wl.meshes)]
+    refs = oracle_lib.run_batch(om, wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
+                                tools[:, sample], steps, env_ids=sample, threads=len(sample))
+    with make_batch(xp, wl) as b:
+        b.step(steps, tools)
+        x = b.positions()
+        for n, e in enumerate(sample):
+            err = K.max_position_error(K.env_block(x, b.env_offsets, e), refs[n].x)
+            assert err <= K.POS_TOL, f"env {e} ({V[e]} particles): {err:.3e}"
