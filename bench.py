@@ -68,6 +68,9 @@ def parse_args():
     ap.add_argument("--cpu-envs", type=int, default=64, help="oracle sample: environments")
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle sample: steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", type=int, default=0, metavar="STEPS",
+                    help="time the library's launch configurations for STEPS steps each "
+                         "(xpbd_autotune) and bench the fastest (0: the default configuration)")
     ap.add_argument("--tool-lift", type=float, default=0.0, metavar="M",
                     help="raise every tool pose by M metres (1.0: no contact anywhere)")
     ap.add_argument("--no-learned", action="store_true",
@@ -298,6 +301,17 @@ def main():
                               solver_variant=args.variant, colour_packing=args.packing,
                               envs_per_group=args.group)
     stream = torch.cuda.current_stream()
+    tuned = None
+    if args.autotune:
+        t_tune = time.perf_counter()
+        best, default = xpbd.xpbd_autotune(
+            [(mm.rest_pos, mm.inv_mass, mm.tets) for mm in wl.meshes], wl.env_mesh, wl.compliance,
+            params, args.autotune, tools[:args.autotune], stream=stream.cuda_stream)
+        tuned = {"ms_per_step_tuned": best, "ms_per_step_default": default,
+                 "solver_variant": params.solver_variant, "block_size": params.block_size,
+                 "envs_per_group": params.envs_per_group, "colour_packing": params.colour_packing,
+                 "seconds": round(time.perf_counter() - t_tune, 1)}
+        progress(f"autotune: {tuned}")
     t_create = time.perf_counter()
     batch = xpbd.Batch([(mm.rest_pos, mm.inv_mass, mm.tets) for mm in wl.meshes], wl.env_mesh,
                        wl.compliance, params, stream=stream.cuda_stream)
@@ -386,7 +400,7 @@ def main():
                    "tets": T if len(wl.meshes) == 1 else int(Ts.sum()),
                    "substeps": S, "iterations": I, "create_s": round(t_create, 3),
                    "steps_per_launch": spl, "solver": "plain (no warm start)",
-                   "tool_lift_m": args.tool_lift,
+                   "tool_lift_m": args.tool_lift, "autotune": tuned,
                    "residual_rms_mean": float(resid[:, 0].mean()),
                    "residual_max": float(resid[:, 1].max())},
         "roofline": roofline, "lds": lds_line, "hbm": hbm_line, "cpu_baseline": cpu,

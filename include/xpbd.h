@@ -102,8 +102,11 @@ typedef struct {
     int32_t num_tools;   /* kinematic spheres, 0 .. 2 */
     float tool_radius[2];/* m, > 0 for each used tool */
     uint32_t flags;      /* XPBD_F_* */
-    int32_t block_size;  /* threads per workgroup: 0 = chosen by the library, else a
-                            multiple of 64 in [64, 1024] */
+    int32_t block_size;  /* threads per workgroup: 0 = chosen by the library (register
+                            variant: per mesh, the smallest of 256, 512, 1024 whose rounds
+                            fit; meshes of equal block and LDS tier form a size class,
+                            and the classes run concurrently), else a multiple of 64 in
+                            [64, 1024] for every mesh */
     int32_t solver_variant; /* XPBD_VARIANT_*: where the multipliers live */
     int32_t colour_packing; /* XPBD_PACKING_*: order of the constraints inside a colour */
     int32_t envs_per_group; /* register variant: environments that share one workgroup,
@@ -130,7 +133,11 @@ typedef struct {
  *            edge may list its particles in either order and a tetrahedron
  *            in any even permutation (the projection is the same function
  *            of the particles), so results change only in rounding.
- * AUTO picks SEARCH for the register variant and BANKS16 otherwise. */
+ * AUTO picks SEARCH for the register variant while the batch's distinct
+ * meshes hold at most 16384 particles in total (the search costs about a
+ * second of host time per thousand particles at creation),
+ * SCATTERED_BANKS16 for larger register-variant batches, and BANKS16 for the
+ * LDS variant. */
 enum { XPBD_PACKING_AUTO = 0, XPBD_PACKING_ID_ORDER = 1, XPBD_PACKING_BANKS8 = 2,
        XPBD_PACKING_BANKS16 = 3, XPBD_PACKING_SCATTERED_BANKS16 = 4, XPBD_PACKING_SEARCH = 5 };
 
@@ -194,6 +201,28 @@ xpbd_status xpbd_set_flags(xpbd_batch *b, uint32_t flags);
 
 /* Byte size of a field of this batch. */
 xpbd_status xpbd_field_bytes(const xpbd_batch *b, int32_t field, size_t *bytes);
+
+/*
+ * Autotuner of the launch configuration (not a method of the paper: a tool
+ * for picking the fastest data placement).  Candidates vary four fields of
+ * *params: solver_variant (registers, LDS), block_size (0, 256, 512, 1024),
+ * envs_per_group (1, 2; registers only) and colour_packing (AUTO, BANKS16);
+ * the first candidate is the library's default (all four 0).  Each candidate
+ * is a batch created from the given meshes, environments and compliances
+ * (the other fields of *params are kept, flags cleared) on hip_stream,
+ * stepped once untimed and then num_steps times with tool_pos (as in
+ * xpbd_step, from the rest state) between two events, and destroyed;
+ * candidates the library rejects with XPBD_E_CAPACITY are skipped.  On
+ * success the four fields of *params hold the fastest candidate,
+ * ms_per_step[0] its time per step and ms_per_step[1] the default's (host
+ * float [2]).  The candidates compute the same projections in the same
+ * colour order; they differ only in rounding where colour_packing says so.
+ * Blocks the calling thread until every candidate has run.
+ */
+xpbd_status xpbd_autotune(const xpbd_mesh *meshes, int32_t num_meshes, const int32_t *env_mesh,
+                          int32_t num_envs, const float *compliance, xpbd_params *params,
+                          void *hip_stream, int32_t num_steps, const float *tool_pos,
+                          float *ms_per_step);
 
 /* Free the batch and its device memory (waits for its stream).  NULL is ignored. */
 void xpbd_destroy_batch(xpbd_batch *b);

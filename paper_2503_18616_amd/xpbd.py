@@ -66,7 +66,7 @@ EXPORTED = ["xpbd_create_batch", "xpbd_step", "xpbd_read_state", "xpbd_write_sta
             "xpbd_set_flags", "xpbd_field_bytes", "xpbd_destroy_batch", "xpbd_last_error",
             "xpbd_prepare_mesh", "xpbd_mlp_create", "xpbd_mlp_get_params", "xpbd_mlp_set_params",
             "xpbd_mlp_forward", "xpbd_mlp_train_step", "xpbd_mlp_destroy", "xpbd_axis_neighbours",
-            "xpbd_step_learned"]
+            "xpbd_step_learned", "xpbd_autotune"]
 
 # learned warm start (include/xpbd_learned.h)
 MLP_FEATURES = 27
@@ -97,6 +97,10 @@ _lib.xpbd_create_batch.argtypes = [ctypes.POINTER(XpbdMesh), ctypes.c_int32, cty
                                    ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
 _lib.xpbd_step.restype = ctypes.c_int
 _lib.xpbd_step.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+_lib.xpbd_autotune.restype = ctypes.c_int
+_lib.xpbd_autotune.argtypes = [ctypes.POINTER(XpbdMesh), ctypes.c_int32, ctypes.c_void_p,
+                               ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
 _lib.xpbd_read_state.restype = ctypes.c_int
 _lib.xpbd_read_state.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]
 _lib.xpbd_write_state.restype = ctypes.c_int
@@ -254,6 +258,30 @@ def xpbd_create_batch(meshes, env_mesh, compliance, params: XpbdParams, stream=N
                                   ctypes.byref(out)))
     _BATCHES[out.value] = (int(env_mesh.shape[0]), int(params.num_tools))
     return out.value
+
+
+def xpbd_autotune(meshes, env_mesh, compliance, params: XpbdParams, num_steps, tool_pos,
+                  stream=None):
+    """Time the candidate launch configurations (see include/xpbd.h) and write the
+    fastest into params.  tool_pos: [num_steps][N][tools][3] (host or device).
+    Returns (ms per step of the choice, ms per step of the default)."""
+    keep = []
+    arr = (XpbdMesh * len(meshes))(*[_mesh_struct(*m, keep) for m in meshes])
+    env_mesh = np.ascontiguousarray(env_mesh, dtype=np.int32)
+    compliance = np.ascontiguousarray(compliance, dtype=np.float32).reshape(-1, 2)
+    if compliance.shape[0] != env_mesh.shape[0]:
+        raise ValueError("compliance must be [num_envs, 2]")
+    n = int(env_mesh.shape[0])
+    if params.num_tools:
+        want = num_steps * n * params.num_tools * 3
+        if tool_pos is None or int(np.prod(tool_pos.shape)) != want:
+            raise ValueError(f"tool_pos must hold {want} floats")
+    ms = (ctypes.c_float * 2)()
+    s = default_stream() if stream is None else stream
+    _check(_lib.xpbd_autotune(arr, len(meshes), env_mesh.ctypes.data, n, compliance.ctypes.data,
+                              ctypes.byref(params), s or None, int(num_steps), _ptr(tool_pos),
+                              ms))
+    return float(ms[0]), float(ms[1])
 
 
 def xpbd_step(batch, num_steps, tool_pos):

@@ -184,3 +184,15 @@ def test_network_create_rejects_bad_scales(xp):
         with pytest.raises(xp.XpbdError) as e:
             xp.xpbd_mlp_create(None, None, si, None, so, stream=0)
         assert e.value.status == xp.XPBD_E_ARG
+
+
+def test_autotune_rejects_bad_arguments(xp):
+    """Argument errors are reported before any device work."""
+    m = W.slab_mesh(2, 1, 1)
+    meshes = [(m.rest_pos, m.inv_mass, m.tets)]
+    p = xp.make_params(dt=1 / 60, substeps=10, iterations=4, num_tools=0)
+    for steps in (0, -3):
+        with pytest.raises(xp.XpbdError) as e:
+            xp.xpbd_autotune(meshes, np.zeros(2, np.int32), np.full((2, 2), 1e-6, np.float32), p,
+                             steps, None, stream=0)
+        assert e.value.status == xp.XPBD_E_ARG and "num_steps" in str(e.value)

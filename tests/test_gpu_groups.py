@@ -95,3 +95,31 @@ def test_groups_need_the_register_variant(xp):
     with pytest.raises(xp.XpbdError) as e:
         xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p)
     assert e.value.status == xp.XPBD_E_CAPACITY
+
+
+def test_autotune_picks_a_configuration_that_runs(xp, oracle_lib):
+    """The autotuner times its candidates on an uneven batch and returns the
+    fastest (never slower than the default, which is one of them); a batch
+    made with the choice follows the oracle."""
+    import dataclasses
+    grids = [(6, 4, 2), (12, 8, 3), (20, 12, 6)]
+    meshes = [W.slab_mesh(*g) for g in grids]
+    env_mesh = np.array([k % 3 for k in range(24)], np.int32)
+    wl = W.Workload("tune", meshes, env_mesh, W.log_uniform_compliance(24, 1e-7, 1e-5, 5),
+                    iterations=8, num_steps=10, seed=5)
+    tools = W.tool_path(10, 24, 5, start_depth=5e-3)
+    p = K.lib_params(xp, wl)
+    best, default = xp.xpbd_autotune(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p, 3,
+                                     tools[:3])
+    assert 0 < best <= default
+    assert p.solver_variant in (0, 1, 2) and p.envs_per_group in (0, 1, 2)
+    sample = [0, 1, 2, 23]
+    om = K.oracle_meshes(oracle_lib, wl)
+    refs = oracle_lib.run_batch(om, wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
+                                tools[:, sample], 10, env_ids=sample, threads=4)
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b:
+        b.step(10, tools)
+        x = b.positions()
+        for n, e in enumerate(sample):
+            err = K.max_position_error(K.env_block(x, b.env_offsets, e), refs[n].x)
+            assert err <= K.POS_TOL, f"env {e}: {err:.3e}"
