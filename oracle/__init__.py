@@ -82,6 +82,11 @@ def _load():
                 ctypes.c_int, _I, _I, ctypes.c_int, _I, _I,
                 ctypes.c_double, ctypes.c_double, _D,
                 ctypes.c_int, ctypes.c_int, _D, _D, _I, ctypes.POINTER(ctypes.c_int)]
+            lib.oracle_iterate_jacobi.restype = None
+            lib.oracle_iterate_jacobi.argtypes = [
+                _D, _D, ctypes.c_int, _I, _D, ctypes.c_int, _I, _D,
+                ctypes.c_double, ctypes.c_double, _D, _I, _D,
+                ctypes.c_int, ctypes.c_int, _D, _D, _I, ctypes.POINTER(ctypes.c_int)]
             lib.oracle_velocity.restype = None
             lib.oracle_velocity.argtypes = [ctypes.c_int, ctypes.c_double, _D, _D, _D]
             lib.oracle_run.restype = ctypes.c_int
@@ -96,7 +101,7 @@ def _load():
                 ctypes.c_int, _D,
                 ctypes.c_int, _D,
                 _D, _D,
-                _D, _I, _I, _D]
+                _D, _I, _I, _D, ctypes.c_int]
             _lib = lib
     return _lib
 
@@ -270,12 +275,15 @@ class OracleResult:
 
 def run_env(mesh: OracleMesh, compliance, params: OracleParams, tool_pos, num_steps,
             x0=None, v0=None, want_lambda=False, want_contacts=False, want_residual=False,
-            edge_schedule=None, tet_schedule=None) -> OracleResult:
+            edge_schedule=None, tet_schedule=None, jacobi=False) -> OracleResult:
     """Advance one environment by ``num_steps`` steps.
 
     tool_pos: [num_steps][num_tools][3]; compliance: (alpha_edge, alpha_tet).
     edge_schedule / tet_schedule: optional (ptr, order) overriding the default
     colour order (used to check independence of the order inside a colour).
+    jacobi: the paper's own parallel solver (``oracle_iterate_jacobi``:
+    every constraint from the same positions, corrections averaged by each
+    particle's number of constraints) instead of coloured Gauss-Seidel.
     """
     lib = _load()
     V, E, T = mesh.num_vertices, mesh.num_edges, mesh.num_tets
@@ -303,7 +311,8 @@ def run_env(mesh: OracleMesh, compliance, params: OracleParams, tool_pos, num_st
                         float(params.dt), int(params.substeps), int(params.iterations), _dp(grav),
                         float(compliance[0]), float(compliance[1]),
                         nt, _dp(radius), int(num_steps), _dp(np.ascontiguousarray(tp)),
-                        _dp(x), _dp(v), _dp(lam), _ip(contacts), _ip(ccount), _dp(resid))
+                        _dp(x), _dp(v), _dp(lam), _ip(contacts), _ip(ccount), _dp(resid),
+                        int(bool(jacobi)))
     if rc != 0:
         raise OracleError(f"oracle_run failed: {rc}")
     return OracleResult(x, v,
@@ -311,6 +320,33 @@ def run_env(mesh: OracleMesh, compliance, params: OracleParams, tool_pos, num_st
                         contacts[:num_steps, :nt] if contacts is not None else None,
                         ccount[:num_steps, :nt] if ccount is not None else None,
                         resid[:num_steps] if resid is not None else None)
+
+
+def iterate_jacobi(x, w, edges, rest_length, tets, rest_volume, alpha_tilde_d=0.0,
+                   alpha_tilde_v=0.0, lam=None):
+    """One iteration of ``oracle_iterate_jacobi`` without tools, on raw arrays:
+    x [V][3] (updated in place), w [V], edges [E][2], tets [T][4] (oriented),
+    rest lengths / volumes, multipliers lam [E+T] (updated; zeros if None).
+    The particle counts n are those of the given constraints."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    V = x.shape[0]
+    edges = _i32(np.asarray(edges).reshape(-1, 2))
+    tets = _i32(np.asarray(tets).reshape(-1, 4))
+    E, T = edges.shape[0], tets.shape[0]
+    count = np.zeros(V, np.int32)
+    np.add.at(count, edges.ravel(), 1)
+    np.add.at(count, tets.ravel(), 1)
+    lam = np.zeros(max(E + T, 1)) if lam is None else lam
+    dx = np.zeros((V, 3))
+    ncand = (ctypes.c_int * 1)()
+    lib.oracle_iterate_jacobi(_dp(x), _dp(_f64(w)), E, _ip(edges if E else np.zeros((1, 2), np.int32)),
+                              _dp(_f64(rest_length if E else np.ones(1))), T,
+                              _ip(tets if T else np.zeros((1, 4), np.int32)),
+                              _dp(_f64(rest_volume if T else np.ones(1))),
+                              float(alpha_tilde_d), float(alpha_tilde_v), _dp(lam), _ip(count),
+                              _dp(dx), V, 0, None, None, None, ncand)
+    return x, lam
 
 
 def run_batch(meshes, env_mesh, compliance, params: OracleParams, tool_pos, num_steps,

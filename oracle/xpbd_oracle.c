@@ -477,6 +477,74 @@ void oracle_iterate(double *x, const double *w,
         }
 }
 
+/*
+ * One iteration of the paper's own parallel solver (Sec. III-A.1, Alg. 1):
+ * every constraint is projected from the same positions x (Jacobi), its
+ * correction w_i dlambda grad_i C is summed per particle, and each particle
+ * then moves by its sum divided by n_i, the number of kept constraints that
+ * include it (count[i]; particles without one do not move).  The multipliers
+ * accumulate as in oracle_iterate; with one iteration, zero compliance and
+ * uniform free masses this is the printed update with k = 1 averaged by n.
+ * dx: [V][3] scratch.  Tool contact follows, as in oracle_iterate.
+ */
+void oracle_iterate_jacobi(double *x, const double *w,
+                           int E, const int32_t *edges, const double *rest_length,
+                           int T, const int32_t *tets, const double *rest_volume,
+                           double alpha_tilde_d, double alpha_tilde_v, double *lambda,
+                           const int32_t *count, double *dx,
+                           int V, int num_tools, const double *centres, const double *tool_radius,
+                           const int32_t *candidates, const int *num_candidates)
+{
+    for (int i = 0; i < 3 * V; ++i)
+        dx[i] = 0.0;
+    for (int e = 0; e < E; ++e) {
+        const int a = edges[2 * e], b = edges[2 * e + 1];
+        double xab[3];
+        sub3(x + 3 * a, x + 3 * b, xab);
+        const double length = sqrt(dot3(xab, xab));
+        if (length < MIN_EDGE_LENGTH)
+            continue;
+        const double C = length - rest_length[e];
+        const double denominator = w[a] + w[b] + alpha_tilde_d;
+        if (denominator <= MIN_DENOMINATOR)
+            continue;
+        const double dlambda = (-C - alpha_tilde_d * lambda[e]) / denominator;
+        lambda[e] += dlambda;
+        for (int k = 0; k < 3; ++k) {
+            const double n = xab[k] / length;
+            dx[3 * a + k] += w[a] * dlambda * n;
+            dx[3 * b + k] -= w[b] * dlambda * n;
+        }
+    }
+    for (int t = 0; t < T; ++t) {
+        const int32_t *q = tets + 4 * t;
+        double p[12], g[12];
+        for (int i = 0; i < 4; ++i)
+            for (int k = 0; k < 3; ++k)
+                p[3 * i + k] = x[3 * q[i] + k];
+        const double C = oracle_tet_gradients(p, g) - rest_volume[t];
+        double denominator = alpha_tilde_v;
+        for (int i = 0; i < 4; ++i)
+            denominator += w[q[i]] * dot3(g + 3 * i, g + 3 * i);
+        if (denominator <= MIN_DENOMINATOR)
+            continue;
+        const double dlambda = (-C - alpha_tilde_v * lambda[E + t]) / denominator;
+        lambda[E + t] += dlambda;
+        for (int i = 0; i < 4; ++i)
+            for (int k = 0; k < 3; ++k)
+                dx[3 * q[i] + k] += w[q[i]] * dlambda * g[3 * i + k];
+    }
+    for (int i = 0; i < V; ++i)
+        if (count[i] > 0)
+            for (int k = 0; k < 3; ++k)
+                x[3 * i + k] += dx[3 * i + k] / (double)count[i];
+    for (int t = 0; t < num_tools; ++t)
+        for (int n = 0; n < num_candidates[t]; ++n) {
+            int i = candidates[(size_t)t * V + n];
+            oracle_project_contact(x + 3 * i, centres + 3 * t, tool_radius[t]);
+        }
+}
+
 /* Velocity update of one substep (Alg. 1): v = (x - x_prev) / h. */
 void oracle_velocity(int V, double h, const double *x, const double *x_prev, double *v)
 {
@@ -511,7 +579,7 @@ int oracle_run(int V, const double *w,
                int num_steps, const double *tool_pos,
                double *x, double *v,
                double *lambda_out, int32_t *contacts, int32_t *contact_count,
-               double *residual)
+               double *residual, int jacobi)
 {
     if (V <= 0 || E < 0 || T < 0 || substeps <= 0 || iterations < 0 || num_steps < 0 ||
         num_tools < 0 || !(dt > 0.0) || !w || !x || !v || !gravity)
@@ -523,13 +591,25 @@ int oracle_run(int V, const double *w,
     double *lambda = (double *)calloc((size_t)(E + T) + 1, sizeof(double));
     int32_t *candidates = (int32_t *)malloc(sizeof(int32_t) * (size_t)V * (num_tools > 0 ? num_tools : 1));
     int *num_candidates = (int *)calloc((size_t)(num_tools > 0 ? num_tools : 1), sizeof(int));
-    if (!x_prev || !lambda || !candidates || !num_candidates) {
+    int32_t *count = (int32_t *)calloc((size_t)V, sizeof(int32_t));
+    double *dx = (double *)malloc(sizeof(double) * 3 * (size_t)V);
+    if (!x_prev || !lambda || !candidates || !num_candidates || !count || !dx) {
         free(x_prev);
         free(lambda);
         free(candidates);
         free(num_candidates);
+        free(count);
+        free(dx);
         return ORACLE_E_NOMEM;
     }
+    /* Jacobi: constraints per particle (n of Sec. III-A.1) */
+    for (int e = 0; e < E; ++e) {
+        count[edges[2 * e]]++;
+        count[edges[2 * e + 1]]++;
+    }
+    for (int t = 0; t < T; ++t)
+        for (int i = 0; i < 4; ++i)
+            count[tets[4 * t + i]]++;
 
     const double h = dt / (double)substeps;                 /* Alg. 1: h = dt / simSubSteps */
     const double alpha_tilde_d = alpha_d / (h * h);
@@ -555,12 +635,19 @@ int oracle_run(int V, const double *w,
             oracle_predict(V, w, h, gravity, x, v, x_prev);   /* Alg. 1, R5 */
             for (int j = 0; j < E + T; ++j)                  /* R4 */
                 lambda[j] = 0.0;
-            for (int it = 0; it < iterations; ++it)
-                oracle_iterate(x, w, E, edges, rest_length, rest_volume, tets,
-                               num_edge_colours, edge_colour_ptr, edge_order,
-                               num_tet_colours, tet_colour_ptr, tet_order,
-                               alpha_tilde_d, alpha_tilde_v, lambda,
-                               V, num_tools, centres, tool_radius, candidates, num_candidates);
+            for (int it = 0; it < iterations; ++it) {
+                if (jacobi)
+                    oracle_iterate_jacobi(x, w, E, edges, rest_length, T, tets, rest_volume,
+                                          alpha_tilde_d, alpha_tilde_v, lambda, count, dx,
+                                          V, num_tools, centres, tool_radius, candidates,
+                                          num_candidates);
+                else
+                    oracle_iterate(x, w, E, edges, rest_length, rest_volume, tets,
+                                   num_edge_colours, edge_colour_ptr, edge_order,
+                                   num_tet_colours, tet_colour_ptr, tet_order,
+                                   alpha_tilde_d, alpha_tilde_v, lambda,
+                                   V, num_tools, centres, tool_radius, candidates, num_candidates);
+            }
             if (residual)
                 oracle_residual(x, E, edges, rest_length, T, tets, rest_volume,
                                 alpha_tilde_d, alpha_tilde_v, lambda,
@@ -574,5 +661,7 @@ int oracle_run(int V, const double *w,
     free(lambda);
     free(candidates);
     free(num_candidates);
+    free(count);
+    free(dx);
     return ORACLE_OK;
 }
