@@ -148,8 +148,16 @@ enum { XPBD_PACKING_AUTO = 0, XPBD_PACKING_ID_ORDER = 1, XPBD_PACKING_BANKS8 = 2
  *             (one per round of <= block_size constraints of one colour, at
  *             most 64 rounds); only particle state occupies LDS
  *   LDS       multipliers in LDS next to the particles; constraint lists in
- *             LDS when they fit */
-enum { XPBD_VARIANT_AUTO = 0, XPBD_VARIANT_REGISTERS = 1, XPBD_VARIANT_LDS = 2 };
+ *             LDS when they fit
+ * JACOBI is a different solver, the paper's own parallel one (Sec. III-A.1,
+ * Alg. 1), for comparison: in every iteration all constraints are projected
+ * from the same positions (multipliers as above), each particle's corrections
+ * are summed and the particle moves by the sum divided by the number of kept
+ * constraints that include it; tool contact follows as in the other
+ * variants.  The sums run colour by colour (no atomics, a fixed order), so
+ * results are reproducible.  Multipliers and particles in LDS. */
+enum { XPBD_VARIANT_AUTO = 0, XPBD_VARIANT_REGISTERS = 1, XPBD_VARIANT_LDS = 2,
+       XPBD_VARIANT_JACOBI = 3 };
 
 /*
  * Create a batch of num_envs environments; environment e uses mesh

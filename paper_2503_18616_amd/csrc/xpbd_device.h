@@ -29,6 +29,7 @@ struct MeshDev {
     const float *rest_pos;       // [V][3] (learned warm start's features)
     const int32_t *nbr;          // [V][6] axis neighbours -x, +x, -y, +y, -z, +z, -1 for none
     const float4 *rest4;         // [V] (rest position, inverse mass)
+    const float *inv_count;      // [V] 1 / (kept constraints that include the particle), 0 if none
     // particle placement of the register-multiplier kernel for a group of G
     // environments: particle i of the group's e-th environment (group id
     // e V + i) lives in LDS slot slot_of[e V + i]; records name slots
@@ -126,13 +127,15 @@ struct LdsLayout {
     uint32_t tet_quad;  // uint2 [T]
     uint32_t tet_rest;  // float [T]
     uint32_t scratch;   // 64 x uint32 for reductions and counts
+    uint32_t dx;        // float [3][V] summed corrections (Jacobi only)
+    uint32_t inv_count; // float [V] 1 / constraints per particle (Jacobi only)
     uint32_t total;
 };
 
 __host__ __device__ inline uint32_t align_up(uint32_t x, uint32_t a) { return (x + a - 1) / a * a; }
 
 __host__ __device__ inline LdsLayout lds_layout(int32_t V, int32_t E, int32_t T, int32_t tools,
-                                                bool stage_topology)
+                                                bool stage_topology, bool jacobi = false)
 {
     LdsLayout l;
     uint32_t o = 0;
@@ -156,12 +159,21 @@ __host__ __device__ inline LdsLayout lds_layout(int32_t V, int32_t E, int32_t T,
     }
     l.scratch = o;
     o += 64u * 4u;
+    l.dx = l.inv_count = 0;
+    if (jacobi) {
+        l.dx = o;
+        o = align_up(o + 12u * (uint32_t)V, 16);
+        l.inv_count = o;
+        o = align_up(o + 4u * (uint32_t)V, 16);
+    }
     l.total = o;
     return l;
 }
 
 // Launchers (xpbd_kernels.hip).
-hipError_t launch_step(const StepArgs &args, int block, int particles_per_thread,
+// LDS-multiplier kernel; jacobi selects the paper's Jacobi iteration instead
+// of the coloured Gauss-Seidel sweep.
+hipError_t launch_step(const StepArgs &args, int block, int particles_per_thread, bool jacobi,
                        bool stage_topology, uint32_t lds_bytes, bool want_residual,
                        hipStream_t stream);
 // LDS layout of the register-multiplier kernel for a group holding V particles

@@ -114,6 +114,75 @@ __device__ __forceinline__ void tet_update(float4 *xw, uint32_t ab, uint32_t cd,
     xw[d] = pd;
 }
 
+// Jacobi forms of the two projections (Sec. III-A.1): the correction of every
+// particle of the constraint is added to dx (structure of arrays [3][V])
+// instead of being applied; the multiplier accumulates as in Gauss-Seidel.
+// Callers run one colour at a time, so no two lanes add to the same particle
+// and plain adds suffice (a fixed summation order: results are reproducible).
+__device__ __forceinline__ void edge_delta(const float4 *xw, float *dx, int V, int a, int b,
+                                           float rest, float alpha_tilde, float &lam)
+{
+    const float4 pa = xw[a], pb = xw[b];
+    const float ex = pa.x - pb.x, ey = pa.y - pb.y, ez = pa.z - pb.z;
+    const float l2 = ex * ex + ey * ey + ez * ez;
+    if (!(l2 >= kMinEdgeLength2))
+        return;
+    const float inv_len = fast_rsq(l2);
+    const float C = l2 * inv_len - rest;
+    const float denom = pa.w + pb.w + alpha_tilde;
+    if (!(denom > kMinDenominator))
+        return;
+    const float dl = (-C - alpha_tilde * lam) * fast_rcp(denom);
+    lam += dl;
+    const float s = dl * inv_len;
+    const float sa = pa.w * s, sb = pb.w * s;
+    dx[a] += sa * ex;
+    dx[V + a] += sa * ey;
+    dx[2 * V + a] += sa * ez;
+    dx[b] -= sb * ex;
+    dx[V + b] -= sb * ey;
+    dx[2 * V + b] -= sb * ez;
+}
+
+__device__ __forceinline__ void tet_delta(const float4 *xw, float *dx, int V, uint32_t ab,
+                                          uint32_t cd, float rest, float alpha_tilde, float &lam)
+{
+    const int q[4] = {(int)(ab & 0xffffu), (int)(ab >> 16), (int)(cd & 0xffffu), (int)(cd >> 16)};
+    const float4 pa = xw[q[0]], pb = xw[q[1]], pc = xw[q[2]], pd = xw[q[3]];
+    const float bax = pb.x - pa.x, bay = pb.y - pa.y, baz = pb.z - pa.z;
+    const float cax = pc.x - pa.x, cay = pc.y - pa.y, caz = pc.z - pa.z;
+    const float dax = pd.x - pa.x, day = pd.y - pa.y, daz = pd.z - pa.z;
+    float g[4][3];
+    g[1][0] = cay * daz - caz * day;
+    g[1][1] = caz * dax - cax * daz;
+    g[1][2] = cax * day - cay * dax;
+    g[2][0] = day * baz - daz * bay;
+    g[2][1] = daz * bax - dax * baz;
+    g[2][2] = dax * bay - day * bax;
+    g[3][0] = bay * caz - baz * cay;
+    g[3][1] = baz * cax - bax * caz;
+    g[3][2] = bax * cay - bay * cax;
+    for (int k = 0; k < 3; ++k)
+        g[0][k] = -(g[1][k] + g[2][k] + g[3][k]);
+    const float C = (bax * g[1][0] + bay * g[1][1] + baz * g[1][2]) * kSixth - rest;
+    const float w[4] = {pa.w, pb.w, pc.w, pd.w};
+    float wg = 0.0f;
+    for (int i = 0; i < 4; ++i)
+        wg += w[i] * (g[i][0] * g[i][0] + g[i][1] * g[i][1] + g[i][2] * g[i][2]);
+    const float denom = wg * kThirtySixth + alpha_tilde;
+    if (!(denom > kMinDenominator))
+        return;
+    const float dl = (-C - alpha_tilde * lam) * fast_rcp(denom);
+    lam += dl;
+    const float s = dl * kSixth;
+    for (int i = 0; i < 4; ++i) {
+        const float si = w[i] * s;
+        dx[q[i]] += si * g[i][0];
+        dx[V + q[i]] += si * g[i][1];
+        dx[2 * V + q[i]] += si * g[i][2];
+    }
+}
+
 // Contact-candidate test in float32 with every product and sum rounded
 // separately (no fused multiply-add), so the host can repeat it bit for bit.
 __device__ __forceinline__ bool within_reach(float4 p, float cx, float cy, float cz, float reach2)
@@ -160,7 +229,7 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
-template <int PPT, bool STAGE, bool RESIDUAL>
+template <int PPT, bool STAGE, bool RESIDUAL, bool JACOBI>
 __global__ void __launch_bounds__(1024) xpbd_step_lds_kernel(StepArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -175,8 +244,15 @@ __global__ void __launch_bounds__(1024) xpbd_step_lds_kernel(StepArgs A)
     const MeshDev md = A.meshes[ed.mesh];
     const int V = md.num_vertices, E = md.num_edges, T = md.num_tets;
     const int tools = A.num_tools;
-    const LdsLayout L = lds_layout(V, E, T, tools, STAGE);
+    const LdsLayout L = lds_layout(V, E, T, tools, STAGE, JACOBI);
     float4 *xw = reinterpret_cast<float4 *>(smem + L.xw);
+    float *dxs = reinterpret_cast<float *>(smem + L.dx);            // Jacobi only
+    float *inv_n = reinterpret_cast<float *>(smem + L.inv_count);   // Jacobi only
+    if constexpr (JACOBI)
+        for (int i = tid; i < V; i += B) {
+            dxs[i] = dxs[V + i] = dxs[2 * V + i] = 0.0f;
+            inv_n[i] = md.inv_count[i];
+        }
     float *lam = reinterpret_cast<float *>(smem + L.lambda);
     uint16_t *clist = reinterpret_cast<uint16_t *>(smem + L.contacts);
     uint32_t *scratch = reinterpret_cast<uint32_t *>(smem + L.scratch);
@@ -287,6 +363,42 @@ __global__ void __launch_bounds__(1024) xpbd_step_lds_kernel(StepArgs A)
             __syncthreads();
 
             for (int it = 0; it < A.iterations; ++it) {
+                if constexpr (JACOBI) {
+                    // the paper's iteration: every constraint from the same
+                    // positions (summed colour by colour: no two lanes of a colour
+                    // share a particle), then each particle moves by its mean correction
+                    for (int c = 0; c < md.num_edge_colours; ++c) {
+                        const int end = md.edge_ptr[c + 1];
+                        for (int j = md.edge_ptr[c] + tid; j < end; j += B) {
+                            const uint32_t pr = e_pair[j];
+                            float l = lam[j];
+                            edge_delta(xw, dxs, V, (int)(pr & 0xffffu), (int)(pr >> 16),
+                                       e_rest[j], alpha_d, l);
+                            lam[j] = l;
+                        }
+                        __syncthreads();
+                    }
+                    for (int c = 0; c < md.num_tet_colours; ++c) {
+                        const int end = md.tet_ptr[c + 1];
+                        for (int j = md.tet_ptr[c] + tid; j < end; j += B) {
+                            const uint2 q = t_quad[j];
+                            float l = lam[E + j];
+                            tet_delta(xw, dxs, V, q.x, q.y, t_rest[j], alpha_v, l);
+                            lam[E + j] = l;
+                        }
+                        __syncthreads();
+                    }
+                    for (int i = tid; i < V; i += B) {
+                        float4 p = xw[i];
+                        const float s = inv_n[i];
+                        p.x += dxs[i] * s;
+                        p.y += dxs[V + i] * s;
+                        p.z += dxs[2 * V + i] * s;
+                        xw[i] = p;
+                        dxs[i] = dxs[V + i] = dxs[2 * V + i] = 0.0f;
+                    }
+                    __syncthreads();
+                } else {
                 for (int c = 0; c < md.num_edge_colours; ++c) {
                     const int end = md.edge_ptr[c + 1];
                     for (int j = md.edge_ptr[c] + tid; j < end; j += B) {
@@ -306,6 +418,7 @@ __global__ void __launch_bounds__(1024) xpbd_step_lds_kernel(StepArgs A)
                         lam[E + j] = l;
                     }
                     __syncthreads();
+                }
                 }
                 for (int t = 0; t < tools; ++t) {
                     if (count[t] == 0)
@@ -1331,10 +1444,10 @@ __global__ void aos_to_soa_kernel(const float *__restrict__ aos, float *__restri
     }
 }
 
-template <int PPT, bool STAGE, bool RESIDUAL>
+template <int PPT, bool STAGE, bool RESIDUAL, bool JACOBI = false>
 hipError_t launch_variant(const StepArgs &args, int block, uint32_t lds_bytes, hipStream_t stream)
 {
-    auto kernel = xpbd_step_lds_kernel<PPT, STAGE, RESIDUAL>;
+    auto kernel = xpbd_step_lds_kernel<PPT, STAGE, RESIDUAL, JACOBI>;
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)lds_bytes);
@@ -1346,9 +1459,12 @@ hipError_t launch_variant(const StepArgs &args, int block, uint32_t lds_bytes, h
 }
 
 template <int PPT>
-hipError_t launch_ppt(const StepArgs &args, int block, bool stage, uint32_t lds, bool resid,
-                      hipStream_t s)
+hipError_t launch_ppt(const StepArgs &args, int block, bool jacobi, bool stage, uint32_t lds,
+                      bool resid, hipStream_t s)
 {
+    if (jacobi)   // topology read from global memory
+        return resid ? launch_variant<PPT, false, true, true>(args, block, lds, s)
+                     : launch_variant<PPT, false, false, true>(args, block, lds, s);
     if (stage)
         return resid ? launch_variant<PPT, true, true>(args, block, lds, s)
                      : launch_variant<PPT, true, false>(args, block, lds, s);
@@ -1381,15 +1497,16 @@ hipError_t launch_reg_groups(const StepArgs &args, int block, int lambda_banks, 
 
 }  // namespace
 
-hipError_t launch_step(const StepArgs &args, int block, int particles_per_thread,
+hipError_t launch_step(const StepArgs &args, int block, int particles_per_thread, bool jacobi,
                        bool stage_topology, uint32_t lds_bytes, bool want_residual,
                        hipStream_t stream)
 {
+    const bool st = stage_topology && !jacobi;
     switch (particles_per_thread) {
-    case 1: return launch_ppt<1>(args, block, stage_topology, lds_bytes, want_residual, stream);
-    case 2: return launch_ppt<2>(args, block, stage_topology, lds_bytes, want_residual, stream);
-    case 4: return launch_ppt<4>(args, block, stage_topology, lds_bytes, want_residual, stream);
-    case 8: return launch_ppt<8>(args, block, stage_topology, lds_bytes, want_residual, stream);
+    case 1: return launch_ppt<1>(args, block, jacobi, st, lds_bytes, want_residual, stream);
+    case 2: return launch_ppt<2>(args, block, jacobi, st, lds_bytes, want_residual, stream);
+    case 4: return launch_ppt<4>(args, block, jacobi, st, lds_bytes, want_residual, stream);
+    case 8: return launch_ppt<8>(args, block, jacobi, st, lds_bytes, want_residual, stream);
     default: return hipErrorInvalidValue;
     }
 }

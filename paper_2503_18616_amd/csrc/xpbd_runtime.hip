@@ -58,7 +58,7 @@ xpbd_status validate_params(const xpbd_params *p)
     if (p->block_size != 0 &&
         (p->block_size < 64 || p->block_size > 1024 || p->block_size % 64 != 0))
         return fail(XPBD_E_ARG, "block_size must be 0 or a multiple of 64 in [64, 1024]");
-    if (p->solver_variant < XPBD_VARIANT_AUTO || p->solver_variant > XPBD_VARIANT_LDS)
+    if (p->solver_variant < XPBD_VARIANT_AUTO || p->solver_variant > XPBD_VARIANT_JACOBI)
         return fail(XPBD_E_ARG, "unknown solver_variant %d", p->solver_variant);
     if (p->colour_packing < XPBD_PACKING_AUTO || p->colour_packing > XPBD_PACKING_SEARCH)
         return fail(XPBD_E_ARG, "unknown colour_packing %d", p->colour_packing);
@@ -278,7 +278,8 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     int reg_block = 0, reg_rounds = 0, reg_group = 1;
     const bool pow2_block = params->block_size == 0 ||
                             (params->block_size & (params->block_size - 1)) == 0;
-    if (params->solver_variant != XPBD_VARIANT_LDS && pow2_block) {
+    const bool jacobi = params->solver_variant == XPBD_VARIANT_JACOBI;
+    if (params->solver_variant != XPBD_VARIANT_LDS && !jacobi && pow2_block) {
         std::vector<int> group_tries;
         if (params->envs_per_group)
             group_tries.push_back(params->envs_per_group);
@@ -322,12 +323,12 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     for (const auto &pm : prepared) {
         lds_staged = std::max(lds_staged, xpbd::lds_layout(pm.num_vertices, pm.num_edges(),
                                                            pm.num_tets(), params->num_tools,
-                                                           true).total);
+                                                           true, jacobi).total);
         lds_global = std::max(lds_global, xpbd::lds_layout(pm.num_vertices, pm.num_edges(),
                                                            pm.num_tets(), params->num_tools,
-                                                           false).total);
+                                                           false, jacobi).total);
     }
-    bool stage = lds_staged <= (uint32_t)lds_limit;
+    bool stage = lds_staged <= (uint32_t)lds_limit && !jacobi;
     uint32_t lds = stage ? lds_staged : lds_global;
     if (use_registers) {
         stage = false;
@@ -430,6 +431,7 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         std::vector<uint2> quad;
         std::vector<uint16_t> slot16, id16;
         std::vector<float4> rest4;
+        std::vector<float> inv_count;
     };
     std::vector<MeshHost> host((size_t)num_meshes);
     // the lane search costs about a second per thousand particles: the default
@@ -595,6 +597,16 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         d.num_tets = T;
         d.num_edge_colours = pm.num_edge_colours;
         d.num_tet_colours = pm.num_tet_colours;
+        h.inv_count.assign((size_t)V, 0.0f);
+        {
+            std::vector<int32_t> n((size_t)V, 0);
+            for (int32_t q = 0; q < 2 * E; ++q)
+                n[(size_t)pm.edges[(size_t)q]]++;
+            for (int32_t q = 0; q < 4 * T; ++q)
+                n[(size_t)pm.tets[(size_t)q]]++;
+            for (int32_t i = 0; i < V; ++i)
+                h.inv_count[(size_t)i] = n[(size_t)i] > 0 ? 1.0f / (float)n[(size_t)i] : 0.0f;
+        }
         xpbd::axis_neighbours(V, pm.rest_pos.data(), h.nbr);
         h.rest4.resize((size_t)V);
         for (int i = 0; i < V; ++i)
@@ -638,9 +650,11 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         float *p_rest;
         int32_t *p_nbr;
         float4 *p_rest4;
+        float *p_inv_count;
         if ((st = b->upload(&p_rest, pm.rest_pos)) || (st = b->upload(&p_nbr, h.nbr)) ||
-            (st = b->upload(&p_rest4, h.rest4)))
+            (st = b->upload(&p_rest4, h.rest4)) || (st = b->upload(&p_inv_count, h.inv_count)))
             return cleanup(st);
+        d.inv_count = p_inv_count;
         d.rest_pos = p_rest;
         d.nbr = p_nbr;
         d.rest4 = p_rest4;
@@ -862,7 +876,8 @@ xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
         if (resid)
             HIP_TRY(xpbd::launch_residual(a, b->stream));
     } else
-        HIP_TRY(xpbd::launch_step(a, b->block, b->particles_per_thread, b->stage_topology,
+        HIP_TRY(xpbd::launch_step(a, b->block, b->particles_per_thread,
+                                  b->params.solver_variant == XPBD_VARIANT_JACOBI, b->stage_topology,
                                   b->lds_bytes, resid, b->stream));
     return XPBD_OK;
 }

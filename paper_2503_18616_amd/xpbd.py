@@ -48,6 +48,7 @@ F_LAMBDA = 0x2
 VARIANT_AUTO = 0
 VARIANT_REGISTERS = 1
 VARIANT_LDS = 2
+VARIANT_JACOBI = 3
 
 PACKING_AUTO = 0
 PACKING_ID_ORDER = 1

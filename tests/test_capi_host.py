@@ -131,7 +131,7 @@ def _create_error(xp, meshes=None, env_mesh=None, compliance=None, **pkw):
     (dict(iterations=-1), -1), (dict(num_tools=3), -1), (dict(tool_radius=(0.0, 0.0)), -1),
     (dict(flags=0x80), -1), (dict(block_size=96), -1), (dict(block_size=2048), -1),
     (dict(gravity=(0.0, float("inf"), 0.0)), -1), (dict(envs_per_group=3), -1),
-    (dict(envs_per_group=-1), -1), (dict(colour_packing=6), -1), (dict(solver_variant=3), -1),
+    (dict(envs_per_group=-1), -1), (dict(colour_packing=6), -1), (dict(solver_variant=4), -1),
 ])
 def test_create_rejects_bad_params(xp, kw, status):
     assert _create_error(xp, **kw).status == status

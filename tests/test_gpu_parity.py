@@ -467,3 +467,34 @@ def test_uneven_4096_sampled_parity(xp, oracle_lib):
         for n, e in enumerate(sample):
             err = K.max_position_error(K.env_block(x, b.env_offsets, e), refs[n].x)
             assert err <= K.POS_TOL, f"env {e} ({V[e]} particles): {err:.3e}"
+
+
+@pytest.mark.parametrize("case", ["single-4-iterations", "single-1-iteration", "batch-3-envs"])
+def test_jacobi_follows_the_oracle(xp, oracle_lib, case):
+    """The paper's Jacobi solver (XPBD_VARIANT_JACOBI) against the oracle's
+    Jacobi iteration, with the tool pressing: positions within the tolerance,
+    and a second run equal bit for bit (sums in a fixed order)."""
+    if case.startswith("single"):
+        wl = W.single_env_workload(seed=7)
+        if case == "single-1-iteration":
+            wl.iterations = 1
+        steps, envs = 60, [0]
+    else:
+        wl = W.batch_workload(3, seed=8, num_steps=40)
+        steps, envs = 40, [0, 1, 2]
+    tools = W.tool_path(steps, wl.num_envs, wl.seed, start_depth=6e-3)
+    om = K.oracle_meshes(oracle_lib, wl)
+    refs = oracle_lib.run_batch(om, wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
+                                tools, steps, threads=len(envs), jacobi=True)
+    with make_batch(xp, wl, variant=xp.VARIANT_JACOBI) as b, \
+            make_batch(xp, wl, variant=xp.VARIANT_JACOBI) as again:
+        b.step(steps, tools)
+        again.step(steps, tools)
+        x = b.positions()
+        assert np.array_equal(x, again.positions())
+        for e in envs:
+            err = K.max_position_error(K.env_block(x, b.env_offsets, e), refs[e].x)
+            assert err <= K.POS_TOL, f"env {e}: {err:.3e}"
+    plain = oracle_lib.run_batch(om, wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
+                                 tools, steps, threads=len(envs))
+    assert max(np.abs(plain[e].x - refs[e].x).max() for e in envs) > K.POS_TOL
