@@ -87,6 +87,16 @@ def _load():
                 _D, _D, ctypes.c_int, _I, _D, ctypes.c_int, _I, _D,
                 ctypes.c_double, ctypes.c_double, _D, _I, _D,
                 ctypes.c_int, ctypes.c_int, _D, _D, _I, ctypes.POINTER(ctypes.c_int)]
+            lib.oracle_segment_triangle.restype = ctypes.c_double
+            lib.oracle_segment_triangle.argtypes = [_D, _D, _D, _D, _D, _D, _D, _D]
+            lib.oracle_project_capsule_face.restype = None
+            lib.oracle_project_capsule_face.argtypes = [_D, _D, _I, _D, _D, ctypes.c_double]
+            lib.oracle_project_capsule_faces.restype = None
+            lib.oracle_project_capsule_faces.argtypes = [_D, _D, _I, _I, ctypes.c_int, _D, _D,
+                                                         ctypes.c_double]
+            lib.oracle_face_candidates.restype = ctypes.c_int
+            lib.oracle_face_candidates.argtypes = [_D, _D, ctypes.c_int, _I, _I, _D, _D,
+                                                   ctypes.c_double, _I]
             lib.oracle_velocity.restype = None
             lib.oracle_velocity.argtypes = [ctypes.c_int, ctypes.c_double, _D, _D, _D]
             lib.oracle_run.restype = ctypes.c_int
@@ -191,6 +201,47 @@ def schedule(colours, num_colours):
     return ptr, order
 
 
+def surface_faces(rest, tets):
+    """Boundary triangles of a tetrahedral mesh (faces of exactly one
+    tetrahedron), each ordered so that (x1 - x0) x (x2 - x0) points away from
+    its tetrahedron's fourth vertex; sorted by their ascending vertex triple.
+    Returns int32 [F][3]."""
+    rest = _f64(rest).reshape(-1, 3)
+    tets = _i32(tets).reshape(-1, 4)
+    seen = {}
+    for t in tets:
+        for skip in range(4):
+            tri = tuple(int(t[k]) for k in range(4) if k != skip)
+            key = tuple(sorted(tri))
+            seen.setdefault(key, []).append((tri, int(t[skip])))
+    out = []
+    for key in sorted(seen):
+        if len(seen[key]) != 1:
+            continue
+        (i, j, k), l = seen[key][0]
+        normal = np.cross(rest[j] - rest[i], rest[k] - rest[i])
+        if np.dot(normal, rest[l] - rest[i]) > 0.0:
+            j, k = k, j
+        out.append((i, j, k))
+    return np.array(out, dtype=np.int32).reshape(-1, 3)
+
+
+def segment_triangle(p0, p1, a, b, c):
+    """Closest points of segment p0 p1 and triangle (a, b, c):
+    (squared distance, triangle point, segment point, barycentrics)."""
+    q, s_, bary = np.zeros(3), np.zeros(3), np.zeros(3)
+    d2 = _load().oracle_segment_triangle(*(_dp(_f64(v)) for v in (p0, p1, a, b, c)), _dp(q),
+                                         _dp(s_), _dp(bary))
+    return d2, q, s_, bary
+
+
+def capsule_push(x, w, face, p0, p1, radius):
+    """One push-out of a face (x updated in place)."""
+    _load().oracle_project_capsule_face(_dp(x), _dp(_f64(w)), _ip(_i32(face)), _dp(_f64(p0)),
+                                        _dp(_f64(p1)), float(radius))
+    return x
+
+
 # ---------------------------------------------------------------- mesh set-up
 @dataclass
 class OracleMesh:
@@ -209,6 +260,10 @@ class OracleMesh:
     edge_order: np.ndarray
     tet_ptr: np.ndarray
     tet_order: np.ndarray
+    faces: np.ndarray = None       # [F,3] int32 outward surface triangles
+    face_colour: np.ndarray = None # [F] int32 greedy colours (faces sharing a particle differ)
+    face_ptr: np.ndarray = None
+    face_order: np.ndarray = None
 
     @property
     def num_edges(self):
@@ -248,8 +303,11 @@ def prepare_mesh(rest_pos, inv_mass, tets) -> OracleMesh:
     tcol, ntc = greedy_colour(V, tout) if T else (np.zeros(0, np.int32), 0)
     eptr, eorder = schedule(ecol, nec)
     tptr, torder = schedule(tcol, ntc)
+    faces = surface_faces(rest, tout) if T else np.zeros((0, 3), np.int32)
+    fcol, nfc = greedy_colour(V, faces) if len(faces) else (np.zeros(0, np.int32), 0)
+    fptr, forder = schedule(fcol, nfc)
     return OracleMesh(V, w, rest, tout, vol, edges, rl, ecol, tcol, nec, ntc,
-                      eptr, eorder, tptr, torder)
+                      eptr, eorder, tptr, torder, faces, fcol, fptr, forder)
 
 
 # ---------------------------------------------------------------- simulation
@@ -347,6 +405,68 @@ def iterate_jacobi(x, w, edges, rest_length, tets, rest_volume, alpha_tilde_d=0.
                               float(alpha_tilde_d), float(alpha_tilde_v), _dp(lam), _ip(count),
                               _dp(dx), V, 0, None, None, None, ncand)
     return x, lam
+
+
+def run_env_capsule(mesh: OracleMesh, compliance, params: OracleParams, capsules, num_steps,
+                    x0=None, v0=None, want_contacts=False):
+    """Advance one environment with capsule tools against the surface faces
+    (Sec. III-A.3) instead of spheres against particles.  capsules:
+    [num_steps][num_tools][6] axis end points (p0, p1), radii
+    params.tool_radius.  Per step: face candidates on the start-of-step
+    positions; per iteration: the deformation constraints (the plain sweep of
+    ``oracle_iterate``), then, per tool, the candidate faces in face-colour
+    order pushed out with k_c = 1."""
+    lib = _load()
+    V, E, T = mesh.num_vertices, mesh.num_edges, mesh.num_tets
+    nt = int(params.num_tools)
+    F = len(mesh.faces)
+    x = _f64(mesh.rest if x0 is None else x0).reshape(V, 3).copy()
+    v = np.zeros((V, 3)) if v0 is None else _f64(v0).reshape(V, 3).copy()
+    cp = _f64(capsules).reshape(num_steps, nt, 6)
+    radius = [float(params.tool_radius[t]) for t in range(nt)]
+    grav = _f64(params.gravity)
+    eptr, eorder, tptr, torder = (_i32(mesh.edge_ptr), _i32(mesh.edge_order),
+                                  _i32(mesh.tet_ptr), _i32(mesh.tet_order))
+    edges = _i32(mesh.edges if E else np.zeros((1, 2), np.int32))
+    tets = _i32(mesh.tets if T else np.zeros((1, 4), np.int32))
+    faces = _i32(mesh.faces if F else np.zeros((1, 3), np.int32))
+    forder = _i32(mesh.face_order if F else np.zeros(1, np.int32))
+    rl = _f64(mesh.rest_length if E else np.ones(1))
+    rv = _f64(mesh.rest_volume if T else np.ones(1))
+    h = float(params.dt) / params.substeps
+    atd, atv = float(compliance[0]) / (h * h), float(compliance[1]) / (h * h)
+    lam = np.zeros(max(E + T, 1))
+    x_prev = np.zeros((V, 3))
+    ncand0 = (ctypes.c_int * 1)()
+    lists = [np.zeros(max(F, 1), np.int32) for _ in range(max(nt, 1))]
+    counts = np.zeros((num_steps, max(nt, 1)), np.int32)
+    contacts = [] if want_contacts else None
+    for step in range(num_steps):
+        for t in range(nt):
+            p0, p1 = np.ascontiguousarray(cp[step, t, :3]), np.ascontiguousarray(cp[step, t, 3:])
+            counts[step, t] = lib.oracle_face_candidates(_dp(x), _dp(mesh.w), F, _ip(faces),
+                                                         _ip(forder), _dp(p0), _dp(p1),
+                                                         radius[t], _ip(lists[t]))
+        if want_contacts:
+            contacts.append([lists[t][:counts[step, t]].copy() for t in range(nt)])
+        for sub in range(params.substeps):
+            lib.oracle_predict(V, _dp(mesh.w), h, _dp(grav), _dp(x), _dp(v), _dp(x_prev))
+            lam[:] = 0.0
+            for _ in range(params.iterations):
+                lib.oracle_iterate(_dp(x), _dp(mesh.w), E, _ip(edges), _dp(rl), _dp(rv),
+                                   _ip(tets), len(eptr) - 1, _ip(eptr),
+                                   _ip(eorder if eorder.size else np.zeros(1, np.int32)),
+                                   len(tptr) - 1, _ip(tptr),
+                                   _ip(torder if torder.size else np.zeros(1, np.int32)),
+                                   atd, atv, _dp(lam), V, 0, None, None, None, ncand0)
+                for t in range(nt):
+                    p0 = np.ascontiguousarray(cp[step, t, :3])
+                    p1 = np.ascontiguousarray(cp[step, t, 3:])
+                    lib.oracle_project_capsule_faces(_dp(x), _dp(mesh.w), _ip(faces),
+                                                     _ip(lists[t]), int(counts[step, t]),
+                                                     _dp(p0), _dp(p1), radius[t])
+            lib.oracle_velocity(V, h, _dp(x), _dp(x_prev), _dp(v))
+    return OracleResult(x, v, None, contacts, counts, None)
 
 
 def run_batch(meshes, env_mesh, compliance, params: OracleParams, tool_pos, num_steps,

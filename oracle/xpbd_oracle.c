@@ -62,6 +62,19 @@
  *       order and gives each the smallest colour not used by an earlier
  *       constraint sharing any particle; edges and tetrahedra are coloured
  *       separately.
+ *   R11 Capsule tools (the paper's grasper capsules, Sec. III-A.2/3) act on
+ *       the surface triangles (faces of exactly one kept tetrahedron, ordered
+ *       outward), not on particles: a capsule is a segment p0 p1 and a radius
+ *       r, its SDF is the distance to the segment minus r.  The deepest point
+ *       of a face is its exact closest point to the segment (the local
+ *       optimisation of the cited contact scheme reaches it: the distance is
+ *       convex over the triangle).  Candidates: faces with a free particle
+ *       closer than 2r to the segment on the start-of-step positions, found
+ *       once per step; after the deformation constraints of every iteration
+ *       each candidate (face colour ascending, face id ascending) is pushed
+ *       out with k_c = 1 as a constraint C = d - r on its closest point
+ *       q = sum_i b_i x_i (gradient b_i n, n from the axis to q, the face
+ *       normal when d ~ 0).
  *
  * Every function below is pinned by the not-gpu tests (closed forms,
  * invariants and brute force on tiny meshes).
@@ -543,6 +556,234 @@ void oracle_iterate_jacobi(double *x, const double *w,
             int i = candidates[(size_t)t * V + n];
             oracle_project_contact(x + 3 * i, centres + 3 * t, tool_radius[t]);
         }
+}
+
+/* ------------------------------------------------------------------ */
+/* Capsule tools against surface faces (Sec. III-A.3: each capsule of   */
+/* the grasper is an SDF tested against the mesh faces; a penetrating  */
+/* face is pushed out along the penetration direction with k_c = 1).   */
+/* ------------------------------------------------------------------ */
+
+/* Closest point on triangle (a, b, c) to p, by the region of p's projection:
+ * vertex, edge or interior.  Writes the point and its barycentrics. */
+static void closest_on_triangle(const double *p, const double *a, const double *b,
+                                const double *c, double *q, double *bary)
+{
+    double ab[3], ac[3], ap[3], bp[3], cp[3];
+    sub3(b, a, ab);
+    sub3(c, a, ac);
+    sub3(p, a, ap);
+    double d1 = dot3(ab, ap), d2 = dot3(ac, ap);
+    if (d1 <= 0.0 && d2 <= 0.0) {                       /* vertex a */
+        bary[0] = 1.0, bary[1] = 0.0, bary[2] = 0.0;
+    } else {
+        sub3(p, b, bp);
+        double d3 = dot3(ab, bp), d4 = dot3(ac, bp);
+        sub3(p, c, cp);
+        double d5 = dot3(ab, cp), d6 = dot3(ac, cp);
+        double vc = d1 * d4 - d3 * d2, vb = d5 * d2 - d1 * d6, va = d3 * d6 - d5 * d4;
+        if (d3 >= 0.0 && d4 <= d3) {                    /* vertex b */
+            bary[0] = 0.0, bary[1] = 1.0, bary[2] = 0.0;
+        } else if (d6 >= 0.0 && d5 <= d6) {             /* vertex c */
+            bary[0] = 0.0, bary[1] = 0.0, bary[2] = 1.0;
+        } else if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {   /* edge ab */
+            double t = d1 / (d1 - d3);
+            bary[0] = 1.0 - t, bary[1] = t, bary[2] = 0.0;
+        } else if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {   /* edge ac */
+            double t = d2 / (d2 - d6);
+            bary[0] = 1.0 - t, bary[1] = 0.0, bary[2] = t;
+        } else if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {   /* edge bc */
+            double t = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+            bary[0] = 0.0, bary[1] = 1.0 - t, bary[2] = t;
+        } else {                                        /* interior */
+            double den = 1.0 / (va + vb + vc);
+            bary[1] = vb * den, bary[2] = vc * den, bary[0] = 1.0 - bary[1] - bary[2];
+        }
+    }
+    for (int k = 0; k < 3; ++k)
+        q[k] = bary[0] * a[k] + bary[1] * b[k] + bary[2] * c[k];
+}
+
+/* Closest points of segments p0 p1 and q0 q1: parameters s, t in [0, 1]. */
+static void closest_segments(const double *p0, const double *p1, const double *q0,
+                             const double *q1, double *s_out, double *t_out)
+{
+    double d1[3], d2[3], r[3];
+    sub3(p1, p0, d1);
+    sub3(q1, q0, d2);
+    sub3(p0, q0, r);
+    double a = dot3(d1, d1), e = dot3(d2, d2), f = dot3(d2, r);
+    double s = 0.0, t = 0.0;
+    if (a <= 1e-30 && e <= 1e-30) {
+        s = t = 0.0;
+    } else if (a <= 1e-30) {
+        t = fmin(fmax(f / e, 0.0), 1.0);
+    } else {
+        double c = dot3(d1, r);
+        if (e <= 1e-30) {
+            s = fmin(fmax(-c / a, 0.0), 1.0);
+        } else {
+            double b = dot3(d1, d2), den = a * e - b * b;
+            s = den > 0.0 ? fmin(fmax((b * f - c * e) / den, 0.0), 1.0) : 0.0;
+            t = (b * s + f) / e;
+            if (t < 0.0) {
+                t = 0.0;
+                s = fmin(fmax(-c / a, 0.0), 1.0);
+            } else if (t > 1.0) {
+                t = 1.0;
+                s = fmin(fmax((b - c) / a, 0.0), 1.0);
+            }
+        }
+    }
+    *s_out = s;
+    *t_out = t;
+}
+
+/*
+ * Closest points between segment p0 p1 and triangle (a, b, c): the minimum
+ * of |S(t) - T(u, v)| over the segment and the triangle is attained at a
+ * segment end against the triangle, at a triangle edge against the segment,
+ * or where the segment crosses the triangle (distance 0).  Writes the
+ * triangle point q with barycentrics bary and the segment point s; returns
+ * the squared distance.
+ */
+double oracle_segment_triangle(const double *p0, const double *p1, const double *a,
+                               const double *b, const double *c, double *q, double *s,
+                               double *bary)
+{
+    double best = INFINITY, qq[3], bb[3], d[3];
+    /* segment ends against the triangle */
+    for (int e = 0; e < 2; ++e) {
+        const double *p = e == 0 ? p0 : p1;
+        closest_on_triangle(p, a, b, c, qq, bb);
+        sub3(qq, p, d);
+        double d2 = dot3(d, d);
+        if (d2 < best) {
+            best = d2;
+            memcpy(q, qq, sizeof qq);
+            memcpy(bary, bb, sizeof bb);
+            memcpy(s, p, 3 * sizeof(double));
+        }
+    }
+    /* triangle edges against the segment */
+    const double *v[3] = {a, b, c};
+    for (int e = 0; e < 3; ++e) {
+        const double *e0 = v[e], *e1 = v[(e + 1) % 3];
+        double ts, te;
+        closest_segments(p0, p1, e0, e1, &ts, &te);
+        double ps[3], pe[3];
+        for (int k = 0; k < 3; ++k) {
+            ps[k] = p0[k] + ts * (p1[k] - p0[k]);
+            pe[k] = e0[k] + te * (e1[k] - e0[k]);
+        }
+        sub3(pe, ps, d);
+        double d2 = dot3(d, d);
+        if (d2 < best) {
+            best = d2;
+            memcpy(q, pe, sizeof pe);
+            memcpy(s, ps, sizeof ps);
+            bary[0] = bary[1] = bary[2] = 0.0;
+            bary[e] = 1.0 - te;
+            bary[(e + 1) % 3] = te;
+        }
+    }
+    /* the segment crossing the triangle */
+    double ab[3], ac[3], n[3], dir[3], w0[3];
+    sub3(b, a, ab);
+    sub3(c, a, ac);
+    cross3(ab, ac, n);
+    sub3(p1, p0, dir);
+    double den = dot3(n, dir);
+    if (fabs(den) > 1e-30) {
+        sub3(a, p0, w0);
+        double t = dot3(n, w0) / den;
+        if (t >= 0.0 && t <= 1.0) {
+            double x[3];
+            for (int k = 0; k < 3; ++k)
+                x[k] = p0[k] + t * dir[k];
+            double bc[3];
+            closest_on_triangle(x, a, b, c, qq, bc);
+            sub3(qq, x, d);
+            if (dot3(d, d) <= 1e-24 * (1.0 + dot3(ab, ab))) {   /* inside the triangle */
+                best = 0.0;
+                memcpy(q, qq, sizeof qq);
+                memcpy(bary, bc, sizeof bc);
+                memcpy(s, x, sizeof x);
+            }
+        }
+    }
+    return best;
+}
+
+/*
+ * Push face f = (a, b, c) (outward oriented) out of the capsule p0 p1 of
+ * radius r, k_c = 1: with q = sum_i b_i x_i its closest point to the axis
+ * point s at distance d < r, the constraint C = d - r has gradient b_i n
+ * (n = (q - s)/d, or the face normal when d ~ 0) and one projection moves
+ * x_i by -w_i b_i C n / sum_j w_j b_j^2.
+ */
+void oracle_project_capsule_face(double *x, const double *w, const int32_t *f, const double *p0,
+                                 const double *p1, double radius)
+{
+    const double *a = x + 3 * f[0], *b = x + 3 * f[1], *c = x + 3 * f[2];
+    double q[3], s[3], bary[3], n[3];
+    double d2 = oracle_segment_triangle(p0, p1, a, b, c, q, s, bary);
+    if (d2 >= radius * radius)
+        return;
+    double d = sqrt(d2);
+    if (d > 1e-12) {
+        for (int k = 0; k < 3; ++k)
+            n[k] = (q[k] - s[k]) / d;
+    } else {
+        double ab[3], ac[3];
+        sub3(b, a, ab);
+        sub3(c, a, ac);
+        cross3(ab, ac, n);
+        double l = sqrt(dot3(n, n));
+        if (l <= 0.0)
+            return;
+        for (int k = 0; k < 3; ++k)
+            n[k] /= l;
+    }
+    double den = 0.0;
+    for (int i = 0; i < 3; ++i)
+        den += w[f[i]] * bary[i] * bary[i];
+    if (den <= MIN_DENOMINATOR)
+        return;
+    double C = d - radius;
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k)
+            x[3 * f[i] + k] += -w[f[i]] * bary[i] * C / den * n[k];
+}
+
+/* Face candidates of a capsule for a step: faces with a free vertex whose
+ * closest distance to the axis is below 2r on the start-of-step positions,
+ * in the given processing order.  Returns the count. */
+int oracle_face_candidates(const double *x, const double *w, int F, const int32_t *faces,
+                           const int32_t *order, const double *p0, const double *p1,
+                           double radius, int32_t *out)
+{
+    int n = 0;
+    for (int p = 0; p < F; ++p) {
+        const int32_t *f = faces + 3 * order[p];
+        if (!(w[f[0]] > 0.0 || w[f[1]] > 0.0 || w[f[2]] > 0.0))
+            continue;
+        double q[3], s[3], bary[3];
+        double d2 = oracle_segment_triangle(p0, p1, x + 3 * f[0], x + 3 * f[1], x + 3 * f[2], q,
+                                            s, bary);
+        if (d2 < 4.0 * radius * radius)
+            out[n++] = order[p];
+    }
+    return n;
+}
+
+/* The push-out of a list of faces in the given order (one capsule). */
+void oracle_project_capsule_faces(double *x, const double *w, const int32_t *faces,
+                                  const int32_t *list, int n, const double *p0, const double *p1,
+                                  double radius)
+{
+    for (int k = 0; k < n; ++k)
+        oracle_project_capsule_face(x, w, faces + 3 * list[k], p0, p1, radius);
 }
 
 /* Velocity update of one substep (Alg. 1): v = (x - x_prev) / h. */

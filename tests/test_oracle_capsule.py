@@ -1,0 +1,137 @@
+"""Pins of the oracle's capsule tools against surface faces (Sec. III-A.3):
+surface extraction, segment-triangle closest points, the k_c = 1 push-out
+and the stepping driver.  Values fixed by closed forms, brute force and
+invariants."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_18616_amd import workloads as W
+
+
+@pytest.mark.parametrize("grid", [(1, 1, 1), (3, 2, 2), (8, 5, 3)])
+def test_surface_faces_close_the_slab(grid):
+    m = W.slab_mesh(*grid)
+    om = oracle.prepare_mesh(m.rest_pos, m.inv_mass, m.tets)
+    f = om.faces
+    nx, ny, nz = grid
+    assert len(f) == 4 * (nx * ny + nx * nz + ny * nz)          # two triangles per hex face
+    directed = {(int(a), int(b)) for tri in f for a, b in zip(tri, np.roll(tri, -1))}
+    assert len(directed) == 3 * len(f)                          # no directed edge twice
+    assert all((b, a) in directed for a, b in directed)         # closed and consistent
+    x = om.rest
+    vol = sum(np.dot(x[a], np.cross(x[b], x[c])) for a, b, c in f) / 6.0   # divergence theorem
+    ext = om.rest.max(axis=0) - om.rest.min(axis=0)
+    assert abs(vol - np.prod(ext)) < 1e-15
+    # colours: faces of one colour share no particle
+    for c in range(int(om.face_colour.max()) + 1):
+        ids = f[om.face_colour == c].ravel()
+        assert len(ids) == len(set(ids.tolist()))
+
+
+def brute_distance(p0, p1, a, b, c, ns=201, nt=81):
+    s = np.linspace(0, 1, ns)[:, None] * (p1 - p0) + p0
+    u, v = np.meshgrid(np.linspace(0, 1, nt), np.linspace(0, 1, nt))
+    keep = u + v <= 1.0
+    tri = a + u[keep][:, None] * (b - a) + v[keep][:, None] * (c - a)
+    d = np.linalg.norm(s[:, None, :] - tri[None, :, :], axis=2)
+    step = np.linalg.norm(p1 - p0) / (ns - 1) + max(np.linalg.norm(b - a), np.linalg.norm(c - a),
+                                                    np.linalg.norm(c - b)) / (nt - 1)
+    return d.min(), step
+
+
+def test_segment_triangle_matches_brute_force():
+    rng = np.random.default_rng(21)
+    for _ in range(60):
+        a, b, c = rng.normal(size=(3, 3))
+        p0, p1 = rng.normal(size=(2, 3)) * 1.5
+        d2, q, s, bary = oracle.segment_triangle(p0, p1, a, b, c)
+        d = np.sqrt(d2)
+        brute, step = brute_distance(p0, p1, a, b, c)
+        assert d <= brute + 1e-12 and brute - d <= step
+        assert np.all(bary >= -1e-12) and abs(bary.sum() - 1.0) < 1e-12
+        np.testing.assert_allclose(q, bary[0] * a + bary[1] * b + bary[2] * c, atol=1e-12)
+        t = np.dot(s - p0, p1 - p0) / np.dot(p1 - p0, p1 - p0)
+        np.testing.assert_allclose(s, p0 + t * (p1 - p0), atol=1e-12)
+        assert -1e-12 <= t <= 1 + 1e-12
+        assert abs(np.linalg.norm(q - s) - d) < 1e-12
+
+
+def test_segment_triangle_special_cases():
+    a, b, c = np.array([0.0, 0, 0]), np.array([1.0, 0, 0]), np.array([0.0, 1, 0])
+    d2, q, s, _ = oracle.segment_triangle(np.array([0.2, 0.2, -1]), np.array([0.2, 0.2, 1]), a, b, c)
+    assert d2 == 0.0 and np.allclose(q, [0.2, 0.2, 0]) and np.allclose(s, [0.2, 0.2, 0])
+    d2, q, s, _ = oracle.segment_triangle(np.array([0.1, 0.1, 0.3]), np.array([0.3, 0.2, 0.3]),
+                                          a, b, c)
+    assert abs(np.sqrt(d2) - 0.3) < 1e-15                        # parallel above the interior
+    d2, _, _, _ = oracle.segment_triangle(np.array([2.0, 2, 0]), np.array([3.0, 3, 0]), a, b, c)
+    assert abs(np.sqrt(d2) - np.sqrt(2 * 1.5 ** 2)) < 1e-12      # in plane, beyond edge bc
+
+
+def test_centroid_push_is_a_rigid_translation_to_the_surface():
+    tri = np.array([[0.0, 0, 0], [1.0, 0, 0], [0.0, 1, 0]])
+    centroid = tri.mean(axis=0)
+    r, depth = 0.25, 0.1
+    p0 = centroid + np.array([0, 0, r - depth])                  # axis end above the face
+    p1 = p0 + np.array([0, 0, 1.0])
+    x = tri.copy()
+    oracle.capsule_push(x, np.ones(3), [0, 1, 2], p0, p1, r)
+    np.testing.assert_allclose(x - tri, np.tile([0, 0, -depth], (3, 1)), atol=1e-15)
+    d2, _, _, _ = oracle.segment_triangle(p0, p1, *x)
+    assert abs(np.sqrt(d2) - r) < 1e-14
+
+
+def test_pinned_vertex_stays():
+    tri = np.array([[0.0, 0, 0], [1.0, 0, 0], [0.0, 1, 0]])
+    p0, p1 = np.array([0.3, 0.3, 0.1]), np.array([0.3, 0.3, 1.0])
+    x = tri.copy()
+    oracle.capsule_push(x, np.array([0.0, 1.0, 1.0]), [0, 1, 2], p0, p1, 0.2)
+    assert np.array_equal(x[0], tri[0]) and np.all(x[1:, 2] < 0.0)
+
+
+def capsule_path(steps, seed, radius=0.005, depth=6e-3):
+    """A horizontal capsule (length 2 cm along x) pressed into the top face."""
+    tp = W.tool_path(steps, 1, seed, radius=radius, start_depth=depth)[:, 0, 0]
+    half = np.array([0.01, 0.0, 0.0])
+    return np.concatenate([tp - half, tp + half], axis=1)[:, None, :]
+
+
+def test_far_capsule_is_the_plain_run():
+    m = W.slab_mesh(4, 3, 2)
+    om = oracle.prepare_mesh(m.rest_pos, m.inv_mass, m.tets)
+    p = oracle.OracleParams(1 / 60, 10, 4, (0, 0, -9.81), 1, (0.005, 0.005))
+    caps = capsule_path(6, 3)
+    caps[..., 2] += 1.0
+    caps[..., 5] += 1.0
+    r = oracle.run_env_capsule(om, (1e-6, 1e-7), p, caps, 6)
+    plain = oracle.run_env(om, (1e-6, 1e-7), oracle.OracleParams(1 / 60, 10, 4, (0, 0, -9.81), 0),
+                           None, 6)
+    assert np.array_equal(r.x, plain.x) and r.contact_count.sum() == 0
+
+
+def test_pressing_capsule_pushes_faces_out_and_is_rigid_motion_invariant():
+    m = W.slab_mesh(8, 5, 3)
+    om = oracle.prepare_mesh(m.rest_pos, m.inv_mass, m.tets)
+    p = oracle.OracleParams(1 / 60, 10, 4, (0, 0, -9.81), 1, (0.005, 0.005))
+    caps = capsule_path(10, 4)
+    r = oracle.run_env_capsule(om, (1e-6, 1e-7), p, caps, 10)
+    assert r.contact_count.sum() > 0
+    # the top surface under the capsule was pushed down below its rest height
+    top = om.rest[:, 2].max()
+    assert r.x[:, 2].min() < top - 1e-3
+    worst = min(np.sqrt(oracle.segment_triangle(caps[-1, 0, :3], caps[-1, 0, 3:], *r.x[f])[0])
+                for f in om.faces)
+    assert worst > 0.005 * 0.8                                  # faces (nearly) outside at the end
+    rng = np.random.default_rng(5)
+    qm, rr = np.linalg.qr(rng.normal(size=(3, 3)))
+    R = qm * np.sign(np.diag(rr))
+    if np.linalg.det(R) < 0:
+        R[:, 0] = -R[:, 0]
+    t = rng.normal(scale=0.1, size=3)
+    om2 = oracle.prepare_mesh(om.rest @ R.T + t, m.inv_mass, m.tets)
+    assert np.array_equal(om2.faces, om.faces)
+    p2 = oracle.OracleParams(1 / 60, 10, 4, tuple(R @ np.array(p.gravity)), 1, (0.005, 0.005))
+    caps2 = np.concatenate([caps[..., :3] @ R.T + t, caps[..., 3:] @ R.T + t], axis=-1)
+    r2 = oracle.run_env_capsule(om2, (1e-6, 1e-7), p2, caps2, 10)
+    assert np.array_equal(r2.contact_count, r.contact_count)
+    np.testing.assert_allclose(r2.x, r.x @ R.T + t, rtol=0, atol=1e-12)
