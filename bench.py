@@ -71,6 +71,9 @@ def parse_args():
     ap.add_argument("--autotune", type=int, default=0, metavar="STEPS",
                     help="time the library's launch configurations for STEPS steps each "
                          "(xpbd_autotune) and bench the fastest (0: the default configuration)")
+    ap.add_argument("--tool-shape", choices=["sphere", "capsule"], default="sphere",
+                    help="spheres against particles, or 2 cm capsules against the surface "
+                         "faces (needs the LDS or Jacobi variant)")
     ap.add_argument("--tool-lift", type=float, default=0.0, metavar="M",
                     help="raise every tool pose by M metres (1.0: no contact anywhere)")
     ap.add_argument("--no-learned", action="store_true",
@@ -131,10 +134,11 @@ def progress(msg):
 
 
 def lifted(tool_pos, args):
-    """Tool poses raised by --tool-lift metres along z."""
+    """Tool poses raised by --tool-lift metres along z (every point of a pose)."""
     if args.tool_lift:
         tool_pos = tool_pos.copy()
-        tool_pos[..., 2] += args.tool_lift
+        for k in range(2, tool_pos.shape[-1], 3):
+            tool_pos[..., k] += args.tool_lift
     return tool_pos
 
 
@@ -295,11 +299,16 @@ def main():
     env_sizes = np.array([sizes[int(k)] for k in wl.env_mesh], np.int64)   # [N][E, T, V, free]
     E, T, V, v_free = (int(x) for x in sizes[0])
 
-    tools = torch.from_numpy(lifted(wl.tools(total), args)).cuda()
+    capsules = args.tool_shape == "capsule"
+    if capsules:
+        tools = torch.from_numpy(lifted(W.capsule_path(total, N, wl.seed), args)).cuda()
+    else:
+        tools = torch.from_numpy(lifted(wl.tools(total), args)).cuda()
     params = xpbd.make_params(wl.dt, S, I, wl.gravity, wl.num_tools, wl.tool_radius,
                               flags=0, block_size=args.block,
                               solver_variant=args.variant, colour_packing=args.packing,
-                              envs_per_group=args.group)
+                              envs_per_group=args.group,
+                              tool_shape=xpbd.TOOL_CAPSULE if capsules else xpbd.TOOL_SPHERE)
     stream = torch.cuda.current_stream()
     tuned = None
     if args.autotune:
@@ -357,7 +366,7 @@ def main():
                 "frac": hbm / launch_s / PEAK_HBM, "bytes_per_launch": hbm}
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not capsules and args.variant != 3:
         import oracle
         sample_envs = list(range(0, N, max(1, N // args.cpu_envs)))[:args.cpu_envs]
         f32 = lambda v: float(np.float32(v))
@@ -380,7 +389,7 @@ def main():
                          f"{dt:.1f} s wall)"}
 
     learned = None
-    if not args.no_learned and args.workload == "batch":
+    if not args.no_learned and args.workload == "batch" and not capsules and args.variant in (0, 1):
         def make(w, flags):
             p = xpbd.make_params(w.dt, S, I, w.gravity, w.num_tools, w.tool_radius, flags=flags,
                                  solver_variant=xpbd.VARIANT_REGISTERS)
@@ -401,6 +410,8 @@ def main():
                    "substeps": S, "iterations": I, "create_s": round(t_create, 3),
                    "steps_per_launch": spl, "solver": "plain (no warm start)",
                    "tool_lift_m": args.tool_lift, "autotune": tuned,
+                   "tool_shape": args.tool_shape,
+                   "solver_variant": ["auto", "registers", "lds", "jacobi"][args.variant],
                    "residual_rms_mean": float(resid[:, 0].mean()),
                    "residual_max": float(resid[:, 1].max())},
         "roofline": roofline, "lds": lds_line, "hbm": hbm_line, "cpu_baseline": cpu,

@@ -114,7 +114,29 @@ typedef struct {
                                different environments): 0 = chosen by the library, else
                                1 or 2.  Environments are grouped per mesh in index
                                order; the LDS variant always uses 1. */
+    int32_t tool_shape;     /* XPBD_TOOL_*: spheres against particles, or capsules against
+                               the surface triangles */
 } xpbd_params;
+
+/* Values of xpbd_params.tool_shape.
+ *   SPHERE   a tool is a sphere of radius tool_radius[t] around a centre;
+ *            tool_pos holds 3 floats per tool; particles within 2r of the
+ *            centre at the start of a step are pushed out to the surface
+ *            after the deformation constraints of every iteration.
+ *   CAPSULE  the grasper capsules of Sec. III-A.2/3: a tool is a segment
+ *            (p0, p1) with radius tool_radius[t]; tool_pos holds 6 floats
+ *            per tool (p0 then p1).  It acts on the mesh's surface triangles
+ *            (faces of exactly one kept tetrahedron): a face with a free
+ *            particle closer than 2r to the segment at the start of a step
+ *            is a candidate; after the deformation constraints of every
+ *            iteration each candidate, face colour by face colour, is pushed
+ *            out with k_c = 1 as the constraint d - r >= 0 on its point
+ *            closest to the segment (d that distance; the correction of
+ *            corner i is proportional to w_i and its barycentric weight).
+ *            Needs the LDS or Jacobi variant (AUTO picks LDS); the
+ *            contact fields then hold the number of candidate faces per
+ *            tool and no particle lists (all -1). */
+enum { XPBD_TOOL_SPHERE = 0, XPBD_TOOL_CAPSULE = 1 };
 
 /* Values of xpbd_params.colour_packing.  Constraints of one colour share no
  * particle, so their order changes no result; it only decides which lanes
@@ -175,8 +197,8 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
 
 /*
  * Advance every environment by num_steps steps in one kernel launch.
- * tool_pos: float [num_steps][N][num_tools][3] sphere centres, host or
- * device, ignored when num_tools == 0.  Asynchronous on the batch's stream
+ * tool_pos: float [num_steps][N][num_tools][3] sphere centres (capsules: [6],
+ * the two axis ends), host or device, ignored when num_tools == 0.  Asynchronous on the batch's stream
  * (a host tool_pos is copied before the call returns).  num_steps == 0 does
  * nothing.
  */
@@ -251,6 +273,18 @@ const char *xpbd_last_error(void);
  */
 xpbd_status xpbd_prepare_mesh(const xpbd_mesh *mesh, int32_t *counts, int32_t *edges,
                               int32_t *tets, int32_t *colours, float *rest);
+
+/*
+ * Host-only: the surface triangles the capsule tools act on (the same set-up
+ * the batch performs).  counts[0..1] receive (F, face colours).  faces int32
+ * [F][3]: the faces of exactly one kept tetrahedron, each ordered so that
+ * (x1 - x0) x (x2 - x0) points away from its tetrahedron, sorted by their
+ * ascending vertex triple; colours int32 [F]: greedy colours in that order
+ * (faces sharing a particle differ).  Either output may be NULL; call once
+ * with NULL outputs to size them.
+ */
+xpbd_status xpbd_surface_faces(const xpbd_mesh *mesh, int32_t *counts, int32_t *faces,
+                               int32_t *colours);
 
 #ifdef __cplusplus
 }

@@ -408,14 +408,15 @@ def iterate_jacobi(x, w, edges, rest_length, tets, rest_volume, alpha_tilde_d=0.
 
 
 def run_env_capsule(mesh: OracleMesh, compliance, params: OracleParams, capsules, num_steps,
-                    x0=None, v0=None, want_contacts=False):
+                    x0=None, v0=None, want_contacts=False, jacobi=False):
     """Advance one environment with capsule tools against the surface faces
     (Sec. III-A.3) instead of spheres against particles.  capsules:
     [num_steps][num_tools][6] axis end points (p0, p1), radii
     params.tool_radius.  Per step: face candidates on the start-of-step
     positions; per iteration: the deformation constraints (the plain sweep of
     ``oracle_iterate``), then, per tool, the candidate faces in face-colour
-    order pushed out with k_c = 1."""
+    order pushed out with k_c = 1.  jacobi: the deformation constraints by
+    ``oracle_iterate_jacobi`` instead."""
     lib = _load()
     V, E, T = mesh.num_vertices, mesh.num_edges, mesh.num_tets
     nt = int(params.num_tools)
@@ -439,6 +440,10 @@ def run_env_capsule(mesh: OracleMesh, compliance, params: OracleParams, capsules
     x_prev = np.zeros((V, 3))
     ncand0 = (ctypes.c_int * 1)()
     lists = [np.zeros(max(F, 1), np.int32) for _ in range(max(nt, 1))]
+    count = np.zeros(V, np.int32)
+    np.add.at(count, mesh.edges.ravel(), 1)
+    np.add.at(count, mesh.tets.ravel(), 1)
+    dx = np.zeros((V, 3))
     counts = np.zeros((num_steps, max(nt, 1)), np.int32)
     contacts = [] if want_contacts else None
     for step in range(num_steps):
@@ -453,12 +458,18 @@ def run_env_capsule(mesh: OracleMesh, compliance, params: OracleParams, capsules
             lib.oracle_predict(V, _dp(mesh.w), h, _dp(grav), _dp(x), _dp(v), _dp(x_prev))
             lam[:] = 0.0
             for _ in range(params.iterations):
-                lib.oracle_iterate(_dp(x), _dp(mesh.w), E, _ip(edges), _dp(rl), _dp(rv),
-                                   _ip(tets), len(eptr) - 1, _ip(eptr),
-                                   _ip(eorder if eorder.size else np.zeros(1, np.int32)),
-                                   len(tptr) - 1, _ip(tptr),
-                                   _ip(torder if torder.size else np.zeros(1, np.int32)),
-                                   atd, atv, _dp(lam), V, 0, None, None, None, ncand0)
+                if jacobi:
+                    lib.oracle_iterate_jacobi(_dp(x), _dp(mesh.w), E, _ip(edges), _dp(rl), T,
+                                              _ip(tets), _dp(rv), atd, atv, _dp(lam),
+                                              _ip(count), _dp(dx), V, 0, None, None, None,
+                                              ncand0)
+                else:
+                    lib.oracle_iterate(_dp(x), _dp(mesh.w), E, _ip(edges), _dp(rl), _dp(rv),
+                                       _ip(tets), len(eptr) - 1, _ip(eptr),
+                                       _ip(eorder if eorder.size else np.zeros(1, np.int32)),
+                                       len(tptr) - 1, _ip(tptr),
+                                       _ip(torder if torder.size else np.zeros(1, np.int32)),
+                                       atd, atv, _dp(lam), V, 0, None, None, None, ncand0)
                 for t in range(nt):
                     p0 = np.ascontiguousarray(cp[step, t, :3])
                     p1 = np.ascontiguousarray(cp[step, t, 3:])

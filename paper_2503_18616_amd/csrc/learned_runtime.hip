@@ -232,7 +232,8 @@ xpbd_status xpbd_step_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
         return fail(XPBD_E_ARG, "batch and params are required");
     if (num_steps < 0)
         return fail(XPBD_E_ARG, "num_steps must be >= 0");
-    if (!b->register_variant || b->envs_per_group != 1 || b->classes.size() != 1)
+    if (!b->register_variant || b->envs_per_group != 1 || b->classes.size() != 1 ||
+        b->params.tool_shape != XPBD_TOOL_SPHERE)
         return fail(XPBD_E_CAPACITY, "the learned step needs the register variant with one "
                     "environment per workgroup and one size class (set block_size for meshes "
                     "of different sizes)");

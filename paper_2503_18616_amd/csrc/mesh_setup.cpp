@@ -734,6 +734,56 @@ int prepare_mesh(int32_t num_vertices, int32_t num_tets, const float *rest_pos,
                                             out.edge_colour);
     out.num_tet_colours = greedy_colouring(num_vertices, out.num_tets(), 4, out.tets.data(),
                                            out.tet_colour);
+
+    // surface triangles (capsule tools): faces of exactly one kept tetrahedron,
+    // ordered outward (away from the tetrahedron's fourth vertex), sorted by
+    // their ascending vertex triple
+    struct FaceKey {
+        int32_t v[3];      // ascending
+        int32_t tri[3];    // as taken from the tetrahedron
+        int32_t opposite;
+    };
+    std::vector<FaceKey> fk;
+    fk.reserve(4 * T);
+    for (size_t t = 0; t < T; ++t)
+        for (int skip = 0; skip < 4; ++skip) {
+            FaceKey f;
+            int n = 0;
+            for (int k = 0; k < 4; ++k)
+                if (k != skip)
+                    f.tri[n++] = out.tets[4 * t + k];
+            f.opposite = out.tets[4 * t + skip];
+            std::copy(f.tri, f.tri + 3, f.v);
+            std::sort(f.v, f.v + 3);
+            fk.push_back(f);
+        }
+    std::sort(fk.begin(), fk.end(), [](const FaceKey &x, const FaceKey &y) {
+        return std::lexicographical_compare(x.v, x.v + 3, y.v, y.v + 3);
+    });
+    for (size_t k = 0; k < fk.size();) {
+        size_t e = k + 1;
+        while (e < fk.size() && std::equal(fk[e].v, fk[e].v + 3, fk[k].v))
+            ++e;
+        if (e - k == 1) {
+            int32_t i = fk[k].tri[0], j = fk[k].tri[1], m = fk[k].tri[2];
+            double u[3], w[3], o[3];
+            for (int c = 0; c < 3; ++c) {
+                u[c] = (double)rest_pos[3 * j + c] - (double)rest_pos[3 * i + c];
+                w[c] = (double)rest_pos[3 * m + c] - (double)rest_pos[3 * i + c];
+                o[c] = (double)rest_pos[3 * fk[k].opposite + c] - (double)rest_pos[3 * i + c];
+            }
+            const double nx = u[1] * w[2] - u[2] * w[1], ny = u[2] * w[0] - u[0] * w[2],
+                         nz = u[0] * w[1] - u[1] * w[0];
+            if (nx * o[0] + ny * o[1] + nz * o[2] > 0.0)
+                std::swap(j, m);
+            out.faces.push_back(i);
+            out.faces.push_back(j);
+            out.faces.push_back(m);
+        }
+        k = e;
+    }
+    out.num_face_colours = greedy_colouring(num_vertices, out.num_faces(), 3, out.faces.data(),
+                                            out.face_colour);
     return XPBD_OK;
 }
 

@@ -22,8 +22,12 @@ struct PreparedMesh {
     int32_t num_edge_colours = 0;
     int32_t num_tet_colours = 0;
 
+    std::vector<int32_t> faces;         // [F][3] outward surface triangles, sorted by vertex set
+    std::vector<int32_t> face_colour;   // [F]
+    int32_t num_face_colours = 0;
     int32_t num_edges() const { return (int32_t)rest_length.size(); }
     int32_t num_tets() const { return (int32_t)rest_volume.size(); }
+    int32_t num_faces() const { return (int32_t)(faces.size() / 3); }
 };
 
 // Returns 0 on success; on failure a negative xpbd_status and a message.

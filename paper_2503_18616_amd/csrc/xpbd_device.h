@@ -30,6 +30,10 @@ struct MeshDev {
     const int32_t *nbr;          // [V][6] axis neighbours -x, +x, -y, +y, -z, +z, -1 for none
     const float4 *rest4;         // [V] (rest position, inverse mass)
     const float *inv_count;      // [V] 1 / (kept constraints that include the particle), 0 if none
+    const uint2 *faces;          // [F] surface triangles in schedule order (a | b << 16, c)
+    const int32_t *face_ptr;     // [face colours + 1]
+    int32_t num_faces;
+    int32_t num_face_colours;
     // particle placement of the register-multiplier kernel for a group of G
     // environments: particle i of the group's e-th environment (group id
     // e V + i) lives in LDS slot slot_of[e V + i]; records name slots
@@ -86,6 +90,7 @@ struct StepArgs {
     int32_t substeps;
     int32_t iterations;
     int32_t num_tools;
+    int32_t tool_shape;          // XPBD_TOOL_SPHERE or XPBD_TOOL_CAPSULE (p0, p1 per tool)
     float h;                     // dt / substeps
     float inv_h;
     float gravity[3];
@@ -129,13 +134,15 @@ struct LdsLayout {
     uint32_t scratch;   // 64 x uint32 for reductions and counts
     uint32_t dx;        // float [3][V] summed corrections (Jacobi only)
     uint32_t inv_count; // float [V] 1 / constraints per particle (Jacobi only)
+    uint32_t face_flag; // uint8 [tools][F] candidate faces of capsule tools
     uint32_t total;
 };
 
 __host__ __device__ inline uint32_t align_up(uint32_t x, uint32_t a) { return (x + a - 1) / a * a; }
 
 __host__ __device__ inline LdsLayout lds_layout(int32_t V, int32_t E, int32_t T, int32_t tools,
-                                                bool stage_topology, bool jacobi = false)
+                                                bool stage_topology, bool jacobi = false,
+                                                int32_t capsule_faces = 0)
 {
     LdsLayout l;
     uint32_t o = 0;
@@ -166,6 +173,9 @@ __host__ __device__ inline LdsLayout lds_layout(int32_t V, int32_t E, int32_t T,
         l.inv_count = o;
         o = align_up(o + 4u * (uint32_t)V, 16);
     }
+    l.face_flag = o;
+    if (capsule_faces > 0)
+        o = align_up(o + (uint32_t)(tools > 0 ? tools : 0) * (uint32_t)capsule_faces, 16);
     l.total = o;
     return l;
 }

@@ -183,6 +183,181 @@ __device__ __forceinline__ void tet_delta(const float4 *xw, float *dx, int V, ui
     }
 }
 
+// ---------------------------------------------------------------------------
+// Capsule tools against surface triangles (Sec. III-A.2/3).  A capsule is the
+// segment p0 p1 with radius r; a face's deepest point is its closest point to
+// the segment, found exactly: a segment end against the triangle, a triangle
+// edge against the segment, or the segment crossing the triangle.
+
+struct V3 {
+    float x, y, z;
+};
+__device__ __forceinline__ V3 v3(float4 p) { return {p.x, p.y, p.z}; }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ V3 operator*(float s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b)
+{
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+// Barycentrics of the point of triangle (a, b, c) closest to p (vertex, edge
+// or interior region of p's projection).
+__device__ V3 triangle_closest(V3 p, V3 a, V3 b, V3 c)
+{
+    const V3 ab = b - a, ac = c - a, ap = p - a;
+    const float d1 = dot(ab, ap), d2 = dot(ac, ap);
+    if (d1 <= 0.f && d2 <= 0.f)
+        return {1.f, 0.f, 0.f};
+    const V3 bp = p - b;
+    const float d3 = dot(ab, bp), d4 = dot(ac, bp);
+    if (d3 >= 0.f && d4 <= d3)
+        return {0.f, 1.f, 0.f};
+    const V3 cp = p - c;
+    const float d5 = dot(ab, cp), d6 = dot(ac, cp);
+    if (d6 >= 0.f && d5 <= d6)
+        return {0.f, 0.f, 1.f};
+    const float vc = d1 * d4 - d3 * d2;
+    if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) {
+        const float t = d1 / (d1 - d3);
+        return {1.f - t, t, 0.f};
+    }
+    const float vb = d5 * d2 - d1 * d6;
+    if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) {
+        const float t = d2 / (d2 - d6);
+        return {1.f - t, 0.f, t};
+    }
+    const float va = d3 * d6 - d5 * d4;
+    if (va <= 0.f && (d4 - d3) >= 0.f && (d5 - d6) >= 0.f) {
+        const float t = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+        return {0.f, 1.f - t, t};
+    }
+    const float den = 1.f / (va + vb + vc);
+    const float v = vb * den, w = vc * den;
+    return {1.f - v - w, v, w};
+}
+
+// Parameters (s on p0 p1, t on q0 q1) of the closest points of two segments.
+__device__ void segments_closest(V3 p0, V3 p1, V3 q0, V3 q1, float &s, float &t)
+{
+    const V3 d1 = p1 - p0, d2 = q1 - q0, r = p0 - q0;
+    const float a = dot(d1, d1), e = dot(d2, d2), f = dot(d2, r);
+    s = t = 0.f;
+    if (a <= 1e-30f && e <= 1e-30f)
+        return;
+    if (a <= 1e-30f) {
+        t = fminf(fmaxf(f / e, 0.f), 1.f);
+        return;
+    }
+    const float c = dot(d1, r);
+    if (e <= 1e-30f) {
+        s = fminf(fmaxf(-c / a, 0.f), 1.f);
+        return;
+    }
+    const float b = dot(d1, d2), den = a * e - b * b;
+    s = den > 0.f ? fminf(fmaxf((b * f - c * e) / den, 0.f), 1.f) : 0.f;
+    t = (b * s + f) / e;
+    if (t < 0.f) {
+        t = 0.f;
+        s = fminf(fmaxf(-c / a, 0.f), 1.f);
+    } else if (t > 1.f) {
+        t = 1.f;
+        s = fminf(fmaxf((b - c) / a, 0.f), 1.f);
+    }
+}
+
+// Squared distance of segment p0 p1 and triangle (a, b, c); bary and s_pt
+// receive the triangle point's barycentrics and the segment point.
+__device__ float segment_triangle(V3 p0, V3 p1, V3 a, V3 b, V3 c, V3 &bary, V3 &s_pt)
+{
+    float best = 3.0e38f;
+    for (int e = 0; e < 2; ++e) {
+        const V3 p = e == 0 ? p0 : p1;
+        const V3 w = triangle_closest(p, a, b, c);
+        const V3 q = w.x * a + w.y * b + w.z * c;
+        const float d2 = dot(q - p, q - p);
+        if (d2 < best) {
+            best = d2;
+            bary = w;
+            s_pt = p;
+        }
+    }
+    const V3 v[3] = {a, b, c};
+    for (int e = 0; e < 3; ++e) {
+        const V3 e0 = v[e], e1 = v[(e + 1) % 3];
+        float ts, te;
+        segments_closest(p0, p1, e0, e1, ts, te);
+        const V3 ps = p0 + ts * (p1 - p0), pe = e0 + te * (e1 - e0);
+        const float d2 = dot(pe - ps, pe - ps);
+        if (d2 < best) {
+            best = d2;
+            float wv[3] = {0.f, 0.f, 0.f};
+            wv[e] = 1.f - te;
+            wv[(e + 1) % 3] = te;
+            bary = {wv[0], wv[1], wv[2]};
+            s_pt = ps;
+        }
+    }
+    const V3 ab = b - a, ac = c - a, n = cross(ab, ac), dir = p1 - p0;
+    const float den = dot(n, dir);
+    if (fabsf(den) > 1e-30f) {
+        const float t = dot(n, a - p0) / den;
+        if (t >= 0.f && t <= 1.f) {
+            const V3 x = p0 + t * dir;
+            const V3 w = triangle_closest(x, a, b, c);
+            const V3 q = w.x * a + w.y * b + w.z * c;
+            if (dot(q - x, q - x) <= 1e-12f * (1.f + dot(ab, ab))) {
+                best = 0.f;
+                bary = w;
+                s_pt = x;
+            }
+        }
+    }
+    return best;
+}
+
+// Push face (a | b << 16, c) out of capsule p0 p1 of radius r with k_c = 1:
+// C = d - r on the closest point q = sum b_i x_i, gradient b_i n.
+__device__ void capsule_push(float4 *xw, uint2 f, V3 p0, V3 p1, float r)
+{
+    const int ia = (int)(f.x & 0xffffu), ib = (int)(f.x >> 16), ic = (int)f.y;
+    float4 pa = xw[ia], pb = xw[ib], pc = xw[ic];
+    V3 bary, s;
+    const float d2 = segment_triangle(p0, p1, v3(pa), v3(pb), v3(pc), bary, s);
+    if (!(d2 < r * r))
+        return;
+    const float d = sqrtf(d2);
+    V3 n;
+    if (d > 1e-12f) {
+        const V3 q = bary.x * v3(pa) + bary.y * v3(pb) + bary.z * v3(pc);
+        n = (1.f / d) * (q - s);
+    } else {
+        n = cross(v3(pb) - v3(pa), v3(pc) - v3(pa));
+        const float l = sqrtf(dot(n, n));
+        if (!(l > 0.f))
+            return;
+        n = (1.f / l) * n;
+    }
+    const float den = pa.w * bary.x * bary.x + pb.w * bary.y * bary.y + pc.w * bary.z * bary.z;
+    if (!(den > kMinDenominator))
+        return;
+    const float k = -(d - r) / den;
+    const float sa = pa.w * bary.x * k, sb = pb.w * bary.y * k, sc = pc.w * bary.z * k;
+    pa.x += sa * n.x;
+    pa.y += sa * n.y;
+    pa.z += sa * n.z;
+    pb.x += sb * n.x;
+    pb.y += sb * n.y;
+    pb.z += sb * n.z;
+    pc.x += sc * n.x;
+    pc.y += sc * n.y;
+    pc.z += sc * n.z;
+    xw[ia] = pa;
+    xw[ib] = pb;
+    xw[ic] = pc;
+}
+
 // Contact-candidate test in float32 with every product and sum rounded
 // separately (no fused multiply-add), so the host can repeat it bit for bit.
 __device__ __forceinline__ bool within_reach(float4 p, float cx, float cy, float cz, float reach2)
@@ -244,7 +419,10 @@ __global__ void __launch_bounds__(1024) xpbd_step_lds_kernel(StepArgs A)
     const MeshDev md = A.meshes[ed.mesh];
     const int V = md.num_vertices, E = md.num_edges, T = md.num_tets;
     const int tools = A.num_tools;
-    const LdsLayout L = lds_layout(V, E, T, tools, STAGE, JACOBI);
+    const bool capsule = A.tool_shape == 1;   // XPBD_TOOL_CAPSULE: faces against segments
+    const int F = capsule ? md.num_faces : 0;
+    const LdsLayout L = lds_layout(V, E, T, tools, STAGE, JACOBI, F);
+    uint8_t *fflag = reinterpret_cast<uint8_t *>(smem + L.face_flag);
     float4 *xw = reinterpret_cast<float4 *>(smem + L.xw);
     float *dxs = reinterpret_cast<float *>(smem + L.dx);            // Jacobi only
     float *inv_n = reinterpret_cast<float *>(smem + L.inv_count);   // Jacobi only
@@ -304,10 +482,39 @@ __global__ void __launch_bounds__(1024) xpbd_step_lds_kernel(StepArgs A)
 
     int count[2] = {0, 0};
     float cx[2] = {0.f, 0.f}, cy[2] = {0.f, 0.f}, cz[2] = {0.f, 0.f};
+    V3 cap0[2] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}}, cap1[2] = {cap0[0], cap0[1]};
     const int last_step = A.num_steps - 1;
     for (int step = 0; step < A.num_steps; ++step) {
-        // instrument state and contact candidates on the start-of-step positions
-        for (int t = 0; t < tools; ++t) {
+        // capsules: candidate faces (a free corner, closer than 2r to the axis)
+        // on the start-of-step positions
+        for (int t = 0; t < tools && capsule; ++t) {
+            const float *c = A.tool_pos + (((size_t)step * A.num_envs + env) * tools + t) * 6;
+            cap0[t] = {c[0], c[1], c[2]};
+            cap1[t] = {c[3], c[4], c[5]};
+            const float r = A.tool_radius[t];
+            int mine = 0;
+            for (int j = tid; j < F; j += B) {
+                const uint2 f = md.faces[j];
+                const float4 pa = xw[f.x & 0xffffu], pb = xw[f.x >> 16], pc = xw[f.y];
+                V3 bary, sp;
+                const bool flag = (pa.w > 0.f || pb.w > 0.f || pc.w > 0.f) &&
+                                  segment_triangle(cap0[t], cap1[t], v3(pa), v3(pb), v3(pc), bary,
+                                                   sp) < 4.f * r * r;
+                fflag[t * F + j] = flag ? 1 : 0;
+                mine += flag ? 1 : 0;
+            }
+            const float total = wave_sum((float)mine);
+            if (lane == 0)
+                scratch[wave] = (uint32_t)total;
+            __syncthreads();
+            int n = 0;
+            for (int w = 0; w < num_waves; ++w)
+                n += (int)scratch[w];
+            count[t] = n;
+            __syncthreads();
+        }
+        // spheres: instrument state and contact candidates on the start-of-step positions
+        for (int t = 0; t < tools && !capsule; ++t) {
             const float *c = A.tool_pos + (((size_t)step * A.num_envs + env) * tools + t) * 3;
             cx[t] = c[0];
             cy[t] = c[1];
@@ -420,7 +627,7 @@ __global__ void __launch_bounds__(1024) xpbd_step_lds_kernel(StepArgs A)
                     __syncthreads();
                 }
                 }
-                for (int t = 0; t < tools; ++t) {
+                for (int t = 0; t < tools && !capsule; ++t) {
                     if (count[t] == 0)
                         continue;
                     const uint16_t *list = clist + t * V;
@@ -428,6 +635,17 @@ __global__ void __launch_bounds__(1024) xpbd_step_lds_kernel(StepArgs A)
                         project_contact(xw, list[n], cx[t], cy[t], cz[t], A.tool_radius[t],
                                         A.tool_radius2[t]);
                     __syncthreads();
+                }
+                for (int t = 0; t < tools && capsule; ++t) {
+                    if (count[t] == 0)
+                        continue;
+                    for (int c = 0; c < md.num_face_colours; ++c) {
+                        const int end = md.face_ptr[c + 1];
+                        for (int j = md.face_ptr[c] + tid; j < end; j += B)
+                            if (fflag[t * F + j])
+                                capsule_push(xw, md.faces[j], cap0[t], cap1[t], A.tool_radius[t]);
+                        __syncthreads();
+                    }
                 }
             }
 
@@ -514,9 +732,9 @@ __global__ void __launch_bounds__(1024) xpbd_step_lds_kernel(StepArgs A)
     for (int t = 0; t < tools; ++t) {
         const uint16_t *list = clist + t * V;
         for (int n = tid; n < V; n += B)
-            A.contacts[(size_t)t * NP + off + n] = n < count[t] ? (int32_t)list[n] : -1;
+            A.contacts[(size_t)t * NP + off + n] = !capsule && n < count[t] ? (int32_t)list[n] : -1;
         if (tid == 0)
-            A.contact_counts[env * tools + t] = count[t];
+            A.contact_counts[env * tools + t] = count[t];   // capsules: candidate faces
     }
     if (A.lambda_out) {
         float *out = A.lambda_out + ed.lambda_offset;

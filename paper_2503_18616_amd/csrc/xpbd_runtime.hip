@@ -64,6 +64,8 @@ xpbd_status validate_params(const xpbd_params *p)
         return fail(XPBD_E_ARG, "unknown colour_packing %d", p->colour_packing);
     if (p->envs_per_group < 0 || p->envs_per_group > xpbd::kMaxEnvsPerGroup)
         return fail(XPBD_E_ARG, "envs_per_group must be 0, 1 or 2 (got %d)", p->envs_per_group);
+    if (p->tool_shape != XPBD_TOOL_SPHERE && p->tool_shape != XPBD_TOOL_CAPSULE)
+        return fail(XPBD_E_ARG, "unknown tool_shape %d", p->tool_shape);
     return XPBD_OK;
 }
 
@@ -203,6 +205,27 @@ xpbd_status xpbd_prepare_mesh(const xpbd_mesh *mesh, int32_t *counts, int32_t *e
     return XPBD_OK;
 }
 
+xpbd_status xpbd_surface_faces(const xpbd_mesh *mesh, int32_t *counts, int32_t *faces,
+                               int32_t *colours)
+{
+    g_error.clear();
+    if (!mesh || !counts)
+        return fail(XPBD_E_ARG, "mesh and counts must not be NULL");
+    PreparedMesh pm;
+    std::string err;
+    int rc = xpbd::prepare_mesh(mesh->num_vertices, mesh->num_tets, mesh->rest_pos,
+                                mesh->inv_mass, mesh->tets, pm, err);
+    if (rc != XPBD_OK)
+        return fail((xpbd_status)rc, "%s", err.c_str());
+    counts[0] = pm.num_faces();
+    counts[1] = pm.num_face_colours;
+    if (faces)
+        std::copy(pm.faces.begin(), pm.faces.end(), faces);
+    if (colours)
+        std::copy(pm.face_colour.begin(), pm.face_colour.end(), colours);
+    return XPBD_OK;
+}
+
 xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
                               const int32_t *env_mesh, int32_t num_envs,
                               const float *compliance, const xpbd_params *params,
@@ -279,7 +302,10 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     const bool pow2_block = params->block_size == 0 ||
                             (params->block_size & (params->block_size - 1)) == 0;
     const bool jacobi = params->solver_variant == XPBD_VARIANT_JACOBI;
-    if (params->solver_variant != XPBD_VARIANT_LDS && !jacobi && pow2_block) {
+    const bool capsules = params->tool_shape == XPBD_TOOL_CAPSULE && params->num_tools > 0;
+    if (capsules && params->solver_variant == XPBD_VARIANT_REGISTERS)
+        return fail(XPBD_E_CAPACITY, "capsule tools need the LDS or Jacobi variant");
+    if (params->solver_variant != XPBD_VARIANT_LDS && !jacobi && !capsules && pow2_block) {
         std::vector<int> group_tries;
         if (params->envs_per_group)
             group_tries.push_back(params->envs_per_group);
@@ -321,12 +347,13 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     }
     uint32_t lds_staged = 0, lds_global = 0;
     for (const auto &pm : prepared) {
+        const int32_t nf = capsules ? pm.num_faces() : 0;
         lds_staged = std::max(lds_staged, xpbd::lds_layout(pm.num_vertices, pm.num_edges(),
                                                            pm.num_tets(), params->num_tools,
-                                                           true, jacobi).total);
+                                                           true, jacobi, nf).total);
         lds_global = std::max(lds_global, xpbd::lds_layout(pm.num_vertices, pm.num_edges(),
                                                            pm.num_tets(), params->num_tools,
-                                                           false, jacobi).total);
+                                                           false, jacobi, nf).total);
     }
     bool stage = lds_staged <= (uint32_t)lds_limit && !jacobi;
     uint32_t lds = stage ? lds_staged : lds_global;
@@ -432,6 +459,8 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         std::vector<uint16_t> slot16, id16;
         std::vector<float4> rest4;
         std::vector<float> inv_count;
+        std::vector<uint2> faces;         // schedule order: a | b << 16, c
+        std::vector<int32_t> face_ptr;
     };
     std::vector<MeshHost> host((size_t)num_meshes);
     // the lane search costs about a second per thousand particles: the default
@@ -597,6 +626,15 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         d.num_tets = T;
         d.num_edge_colours = pm.num_edge_colours;
         d.num_tet_colours = pm.num_tet_colours;
+        {
+            std::vector<int32_t> fslot;
+            build_schedule(pm.face_colour, pm.num_face_colours, fslot, h.face_ptr);
+            h.faces.resize(fslot.size());
+            for (size_t j = 0; j < fslot.size(); ++j) {
+                const int32_t *f = &pm.faces[3 * (size_t)fslot[j]];
+                h.faces[j] = make_uint2((uint32_t)f[0] | ((uint32_t)f[1] << 16), (uint32_t)f[2]);
+            }
+        }
         h.inv_count.assign((size_t)V, 0.0f);
         {
             std::vector<int32_t> n((size_t)V, 0);
@@ -655,6 +693,14 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
             (st = b->upload(&p_rest4, h.rest4)) || (st = b->upload(&p_inv_count, h.inv_count)))
             return cleanup(st);
         d.inv_count = p_inv_count;
+        uint2 *p_faces;
+        int32_t *p_face_ptr;
+        if ((st = b->upload(&p_faces, h.faces)) || (st = b->upload(&p_face_ptr, h.face_ptr)))
+            return cleanup(st);
+        d.faces = p_faces;
+        d.face_ptr = p_face_ptr;
+        d.num_faces = pm.num_faces();
+        d.num_face_colours = pm.num_face_colours;
         d.rest_pos = p_rest;
         d.nbr = p_nbr;
         d.rest4 = p_rest4;
@@ -796,7 +842,8 @@ xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
     if (tools > 0) {
         if (!tool_pos)
             return fail(XPBD_E_ARG, "tool_pos is NULL but the batch has %d tools", tools);
-        const size_t bytes = (size_t)num_steps * b->num_envs * tools * 3 * sizeof(float);
+        const size_t per_tool = b->params.tool_shape == XPBD_TOOL_CAPSULE ? 6 : 3;
+        const size_t bytes = (size_t)num_steps * b->num_envs * tools * per_tool * sizeof(float);
         if (is_device_pointer(tool_pos)) {
             tools_dev = tool_pos;
         } else {
@@ -837,6 +884,7 @@ xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
     a.substeps = b->params.substeps;
     a.iterations = b->params.iterations;
     a.num_tools = tools;
+    a.tool_shape = b->params.tool_shape;
     const double h = (double)b->params.dt / (double)b->params.substeps;
     a.h = (float)h;
     a.inv_h = (float)(1.0 / h);

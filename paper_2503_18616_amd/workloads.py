@@ -153,6 +153,18 @@ def tool_path(num_steps: int, num_envs: int, seed: int, extent=SLAB_EXTENT,
     return out
 
 
+def capsule_path(num_steps: int, num_envs: int, seed: int, length: float = 0.02,
+                 radius: float = TOOL_RADIUS, start_depth: float = 6.0e-3,
+                 env_ids=None) -> np.ndarray:
+    """Capsule tools: the sphere walk of ``tool_path`` as the centre of a
+    horizontal axis of ``length`` along x; float32 [num_steps][envs][1][6]
+    (axis ends p0, p1)."""
+    c = tool_path(num_steps, num_envs, seed, radius=radius, start_depth=start_depth,
+                  env_ids=env_ids)[:, :, 0]
+    half = np.array([length / 2, 0.0, 0.0], np.float32)
+    return np.concatenate([c - half, c + half], axis=-1)[:, :, None, :].astype(np.float32)
+
+
 def uneven_grids(num_envs: int, seed: int, nx=(6, 20), ny=(4, 12), nz=(2, 6)) -> np.ndarray:
     """Per-environment slab resolutions drawn uniformly from inclusive ranges."""
     out = np.empty((num_envs, 3), dtype=np.int32)

@@ -49,6 +49,8 @@ VARIANT_AUTO = 0
 VARIANT_REGISTERS = 1
 VARIANT_LDS = 2
 VARIANT_JACOBI = 3
+TOOL_SPHERE = 0
+TOOL_CAPSULE = 1
 
 PACKING_AUTO = 0
 PACKING_ID_ORDER = 1
@@ -67,7 +69,7 @@ EXPORTED = ["xpbd_create_batch", "xpbd_step", "xpbd_read_state", "xpbd_write_sta
             "xpbd_set_flags", "xpbd_field_bytes", "xpbd_destroy_batch", "xpbd_last_error",
             "xpbd_prepare_mesh", "xpbd_mlp_create", "xpbd_mlp_get_params", "xpbd_mlp_set_params",
             "xpbd_mlp_forward", "xpbd_mlp_train_step", "xpbd_mlp_destroy", "xpbd_axis_neighbours",
-            "xpbd_step_learned", "xpbd_autotune"]
+            "xpbd_step_learned", "xpbd_autotune", "xpbd_surface_faces"]
 
 # learned warm start (include/xpbd_learned.h)
 MLP_FEATURES = 27
@@ -89,7 +91,7 @@ class XpbdParams(ctypes.Structure):
                 ("num_tools", ctypes.c_int32), ("tool_radius", ctypes.c_float * 2),
                 ("flags", ctypes.c_uint32), ("block_size", ctypes.c_int32),
                 ("solver_variant", ctypes.c_int32), ("colour_packing", ctypes.c_int32),
-                ("envs_per_group", ctypes.c_int32)]
+                ("envs_per_group", ctypes.c_int32), ("tool_shape", ctypes.c_int32)]
 
 
 _lib.xpbd_create_batch.restype = ctypes.c_int
@@ -193,7 +195,7 @@ def _mesh_struct(rest_pos, inv_mass, tets, keep):
 def make_params(dt, substeps, iterations, gravity=(0.0, 0.0, -9.81), num_tools=1,
                 tool_radius=(0.005, 0.005), flags=0, block_size=0,
                 solver_variant=VARIANT_AUTO, colour_packing=PACKING_AUTO,
-                envs_per_group=0) -> XpbdParams:
+                envs_per_group=0, tool_shape=0) -> XpbdParams:
     p = XpbdParams()
     p.dt = dt
     p.substeps = substeps
@@ -207,6 +209,7 @@ def make_params(dt, substeps, iterations, gravity=(0.0, 0.0, -9.81), num_tools=1
     p.solver_variant = solver_variant
     p.colour_packing = colour_packing
     p.envs_per_group = envs_per_group
+    p.tool_shape = tool_shape
     return p
 
 
@@ -224,6 +227,25 @@ def default_stream():
 # --------------------------------------------------------------------- C names
 def xpbd_last_error() -> str:
     return _lib.xpbd_last_error().decode()
+
+
+_lib.xpbd_surface_faces.restype = ctypes.c_int
+_lib.xpbd_surface_faces.argtypes = [ctypes.POINTER(XpbdMesh), ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p]
+
+
+def xpbd_surface_faces(rest_pos, inv_mass, tets):
+    """Host-only surface triangles and their colours (include/xpbd.h)."""
+    keep = []
+    mesh = _mesh_struct(rest_pos, inv_mass, tets, keep)
+    counts = np.zeros(2, np.int32)
+    _check(_lib.xpbd_surface_faces(ctypes.byref(mesh), counts.ctypes.data, None, None))
+    faces = np.zeros((max(int(counts[0]), 1), 3), np.int32)
+    colours = np.zeros(max(int(counts[0]), 1), np.int32)
+    _check(_lib.xpbd_surface_faces(ctypes.byref(mesh), counts.ctypes.data, faces.ctypes.data,
+                                   colours.ctypes.data))
+    F = int(counts[0])
+    return faces[:F], colours[:F], int(counts[1])
 
 
 def xpbd_prepare_mesh(rest_pos, inv_mass, tets):
@@ -257,7 +279,8 @@ def xpbd_create_batch(meshes, env_mesh, compliance, params: XpbdParams, stream=N
     _check(_lib.xpbd_create_batch(arr, len(meshes), env_mesh.ctypes.data, env_mesh.shape[0],
                                   compliance.ctypes.data, ctypes.byref(params), s or None,
                                   ctypes.byref(out)))
-    _BATCHES[out.value] = (int(env_mesh.shape[0]), int(params.num_tools))
+    _BATCHES[out.value] = (int(env_mesh.shape[0]), int(params.num_tools),
+                           6 if params.tool_shape == TOOL_CAPSULE else 3)
     return out.value
 
 
@@ -329,11 +352,11 @@ def xpbd_destroy_batch(batch):
 
 
 def _check_tool_pos(batch, num_steps, tool_pos):
-    n_envs, n_tools = _BATCHES.get(batch, (None, None))
+    n_envs, n_tools, per_tool = _BATCHES.get(batch, (None, None, 3))
     if isinstance(tool_pos, np.ndarray):
         tool_pos = np.ascontiguousarray(tool_pos, dtype=np.float32)
     if n_tools and num_steps > 0:
-        need = int(num_steps) * n_envs * n_tools * 3
+        need = int(num_steps) * n_envs * n_tools * per_tool
         if tool_pos is None:
             raise ValueError("tool_pos is required when the batch has tools")
         numel = tool_pos.size if isinstance(tool_pos, np.ndarray) else tool_pos.numel()

@@ -196,3 +196,14 @@ def test_autotune_rejects_bad_arguments(xp):
             xp.xpbd_autotune(meshes, np.zeros(2, np.int32), np.full((2, 2), 1e-6, np.float32), p,
                              steps, None, stream=0)
         assert e.value.status == xp.XPBD_E_ARG and "num_steps" in str(e.value)
+
+
+@pytest.mark.parametrize("grid", [(1, 1, 1), (4, 3, 2), (16, 10, 4)])
+def test_surface_faces_equal_the_oracle(xp, grid):
+    import oracle
+    m = W.slab_mesh(*grid)
+    faces, colours, n_col = xp.xpbd_surface_faces(m.rest_pos, m.inv_mass, m.tets)
+    om = oracle.prepare_mesh(m.rest_pos, m.inv_mass, m.tets)
+    assert np.array_equal(faces, om.faces)
+    assert np.array_equal(colours, om.face_colour)
+    assert n_col == int(om.face_colour.max()) + 1

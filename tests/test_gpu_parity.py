@@ -498,3 +498,36 @@ def test_jacobi_follows_the_oracle(xp, oracle_lib, case):
     plain = oracle_lib.run_batch(om, wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
                                  tools, steps, threads=len(envs))
     assert max(np.abs(plain[e].x - refs[e].x).max() for e in envs) > K.POS_TOL
+
+
+@pytest.mark.parametrize("case", ["single", "batch-3-envs", "jacobi"])
+def test_capsule_tools_follow_the_oracle(xp, oracle_lib, case):
+    """Capsule tools against the surface faces (XPBD_TOOL_CAPSULE): positions
+    follow the oracle's capsule driver; the first step's candidate-face counts
+    are equal."""
+    if case == "batch-3-envs":
+        wl = W.batch_workload(3, seed=9, num_steps=30)
+    else:
+        wl = W.single_env_workload(seed=9)
+    steps = 30
+    caps = W.capsule_path(steps, wl.num_envs, wl.seed)
+    om = K.oracle_meshes(oracle_lib, wl)
+    op = K.oracle_params(oracle_lib, wl)
+    jacobi = case == "jacobi"
+    refs = [oracle_lib.run_env_capsule(om[int(wl.env_mesh[e])], wl.compliance[e], op,
+                                       caps[:, e].astype(np.float64), steps, jacobi=jacobi)
+            for e in range(wl.num_envs)]
+    assert sum(r.contact_count.sum() for r in refs) > 0
+    p = K.lib_params(xp, wl)
+    p.tool_shape = xp.TOOL_CAPSULE
+    if jacobi:
+        p.solver_variant = xp.VARIANT_JACOBI
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b:
+        b.step(1, caps[:1])
+        counts = b.read(xp.FIELD_CONTACT_COUNTS).reshape(wl.num_envs, 1)
+        assert [int(c) for c in counts[:, 0]] == [int(r.contact_count[0, 0]) for r in refs]
+        b.step(steps - 1, caps[1:])
+        x = b.positions()
+    for e in range(wl.num_envs):
+        err = K.max_position_error(K.env_block(x, b.env_offsets, e), refs[e].x)
+        assert err <= K.POS_TOL, f"env {e}: {err:.3e}"

@@ -89,11 +89,9 @@ def test_pinned_vertex_stays():
     assert np.array_equal(x[0], tri[0]) and np.all(x[1:, 2] < 0.0)
 
 
-def capsule_path(steps, seed, radius=0.005, depth=6e-3):
+def capsule_path(steps, seed):
     """A horizontal capsule (length 2 cm along x) pressed into the top face."""
-    tp = W.tool_path(steps, 1, seed, radius=radius, start_depth=depth)[:, 0, 0]
-    half = np.array([0.01, 0.0, 0.0])
-    return np.concatenate([tp - half, tp + half], axis=1)[:, None, :]
+    return W.capsule_path(steps, 1, seed)[:, 0].astype(np.float64)
 
 
 def test_far_capsule_is_the_plain_run():
