@@ -97,6 +97,10 @@ def _load():
             lib.oracle_face_candidates.restype = ctypes.c_int
             lib.oracle_face_candidates.argtypes = [_D, _D, ctypes.c_int, _I, _I, _D, _D,
                                                    ctypes.c_double, _I]
+            lib.oracle_grasp_select.restype = ctypes.c_int
+            lib.oracle_grasp_select.argtypes = [ctypes.c_int, _D, _D, _D, ctypes.c_double, _D]
+            lib.oracle_project_drag.restype = None
+            lib.oracle_project_drag.argtypes = [_D, _D, ctypes.c_int, _D]
             lib.oracle_velocity.restype = None
             lib.oracle_velocity.argtypes = [ctypes.c_int, ctypes.c_double, _D, _D, _D]
             lib.oracle_run.restype = ctypes.c_int

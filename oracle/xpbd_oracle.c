@@ -75,6 +75,17 @@
  *       out with k_c = 1 as a constraint C = d - r on its closest point
  *       q = sum_i b_i x_i (gradient b_i n, n from the axis to q, the face
  *       normal when d ~ 0).
+ *   R12 Grasping (Sec. III-A.2) with a sphere standing in for the closed
+ *       clamps: the dragging point is the grasping tool's centre plus a fixed
+ *       offset.  Closing the grasper (a policy output above 0, the analogue of
+ *       a clamp angle below 3 degrees) while nothing is held takes the free
+ *       particle closest to the dragging point strictly within r_l, on the
+ *       start-of-step positions after the tool has moved; opening releases
+ *       it; a held particle stays held while the grasper stays closed.  One
+ *       particle per grasper is held (the per-particle drag flag is true for
+ *       at most that one).  The drag constraint (k_s = 1, rest length 0)
+ *       runs after the tool contacts of every iteration, so the held
+ *       particle ends every iteration on the dragging point.
  *
  * Every function below is pinned by the not-gpu tests (closed forms,
  * invariants and brute force on tiny meshes).
@@ -784,6 +795,54 @@ void oracle_project_capsule_faces(double *x, const double *w, const int32_t *fac
 {
     for (int k = 0; k < n; ++k)
         oracle_project_capsule_face(x, w, faces + 3 * list[k], p0, p1, radius);
+}
+
+/*
+ * Grasp selection (Sec. III-A.2, reading R12): the free particle closest to
+ * the dragging point among those strictly within r_l of it, on the positions
+ * x; the lowest id wins a tie.  Returns its id, or -1 when none is within
+ * reach.  dist2_out (optional) receives the squared distance of the chosen
+ * particle (unchanged when none is chosen).
+ */
+int oracle_grasp_select(int V, const double *w, const double *x, const double *point,
+                        double radius, double *dist2_out)
+{
+    int best = -1;
+    double best_d2 = 0.0;
+    for (int i = 0; i < V; ++i) {
+        if (!(w[i] > 0.0))
+            continue;
+        double d[3];
+        sub3(x + 3 * i, point, d);
+        double d2 = dot3(d, d);
+        if (d2 < radius * radius && (best < 0 || d2 < best_d2)) {
+            best = i;
+            best_d2 = d2;
+        }
+    }
+    if (best >= 0 && dist2_out)
+        *dist2_out = best_d2;
+    return best;
+}
+
+/*
+ * The dragging constraint (Sec. III-A.2, reading R12): a distance constraint
+ * of rest length 0 and stiffness k_s = 1 between the dragging point p
+ * (kinematic: inverse mass 0) and particle i.  C = |x_i - p|, grad_i C =
+ * (x_i - p) / |x_i - p|, dlambda = -C / w_i, x_i += w_i dlambda grad_i C:
+ * the particle lands on p.  Skipped for a pinned particle and when the
+ * particle already sits on p (|x_i - p| below the edge threshold of R7).
+ */
+void oracle_project_drag(double *x, const double *w, int i, const double *point)
+{
+    double d[3];
+    sub3(x + 3 * i, point, d);
+    double C = sqrt(dot3(d, d));
+    if (!(w[i] > 0.0) || C < MIN_EDGE_LENGTH)
+        return;
+    double dlambda = -C / w[i];
+    for (int k = 0; k < 3; ++k)
+        x[3 * i + k] += w[i] * dlambda * (d[k] / C);
 }
 
 /* Velocity update of one substep (Alg. 1): v = (x - x_prev) / h. */

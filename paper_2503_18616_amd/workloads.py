@@ -231,3 +231,86 @@ def uneven_workload(num_envs: int = 4096, seed: int = 0, num_steps: int = 1000) 
                     log_uniform_compliance(num_envs, 1e-7, 1e-5, seed),
                     iterations=8, num_steps=num_steps, seed=seed)
 
+
+
+# ---------------------------------------------------------------- RL-style step
+_STREAM_RL = 4
+
+# Settings of the RL-style step: grasp reach r_l (the paper gives no value),
+# dragging point at the bottom of the grasping sphere, tool speed at full
+# action, observation scale (about +-1.5 across the slab) and origin (centre
+# of the top face, ``rl_origin``) and the tools' workspace (``rl_box``).
+RL_GRASP_RADIUS = 0.01
+RL_GRASP_OFFSET = (0.0, 0.0, -TOOL_RADIUS)
+RL_MAX_SPEED = 0.05
+RL_OBS_SCALE = 30.0
+RL_TRACKED = 18
+
+
+def rl_origin(extent=SLAB_EXTENT):
+    """Origin of the observed points: the centre of the slab's top face."""
+    lx, ly, lz = extent
+    return (0.5 * lx, 0.5 * ly, lz)
+
+
+def rl_box(extent=SLAB_EXTENT):
+    """Workspace of the tool centres: 5 % .. 95 % of the slab in x and y,
+    8 mm below to 30 mm above its top face."""
+    lx, ly, lz = extent
+    return (0.05 * lx, 0.05 * ly, lz - 8.0e-3), (0.95 * lx, 0.95 * ly, lz + 30.0e-3)
+
+
+def rl_workload(num_envs: int = 8192, seed: int = 0, num_steps: int = 100) -> Workload:
+    """Identical 12x8x3 slabs (468 particles, 1440 tets), two sphere tools
+    (grasp, probe), per-env compliances log-uniform in [1e-7, 1e-5],
+    8 iterations, 10 substeps per 1/60 s step."""
+    mesh = slab_mesh(12, 8, 3)
+    return Workload(f"rl-{num_envs}x12x8x3", [mesh], np.zeros(num_envs, np.int32),
+                    log_uniform_compliance(num_envs, 1e-7, 1e-5, seed),
+                    iterations=8, num_steps=num_steps, seed=seed, num_tools=2)
+
+
+def rl_tracked(mesh: SlabMesh, count: int = RL_TRACKED) -> np.ndarray:
+    """Observed particles: a 6 x 3 lattice of top-face vertices spread evenly
+    over the slab (int32 [18], vertex ids of ``vertex_id``)."""
+    cols, rows = 6, count // 6
+    ii = np.round(np.linspace(1, mesh.nx - 1, cols)).astype(int)
+    jj = np.round(np.linspace(1, mesh.ny - 1, rows + 2)[1:-1]).astype(int)
+    return np.array([vertex_id(int(i), int(j), mesh.nz, mesh.nx, mesh.ny)
+                     for j in jj for i in ii], np.int32)
+
+
+def rl_start(num_envs: int, seed: int, extent=SLAB_EXTENT, radius: float = TOOL_RADIUS,
+             env_ids=None):
+    """Per-environment start of the RL-style step: tool centres float32
+    [envs][2][3] (grasper in the left half, probe in the right half, both
+    pressed 2 mm into the top face) and target points float32 [envs][3]
+    (5 to 20 mm above the top face).  Environment ``e`` draws from its own
+    stream."""
+    lx, ly, lz = extent
+    env_ids = np.arange(num_envs) if env_ids is None else np.asarray(env_ids)
+    tools = np.empty((len(env_ids), 2, 3), np.float32)
+    target = np.empty((len(env_ids), 3), np.float32)
+    for n, e in enumerate(env_ids):
+        r = _env_rng(seed, _STREAM_RL, int(e))
+        u = r.uniform(0.0, 1.0, size=7)
+        z = lz + radius - 2.0e-3
+        tools[n, 0] = [(0.25 + 0.2 * u[0]) * lx, (0.3 + 0.4 * u[1]) * ly, z]
+        tools[n, 1] = [(0.55 + 0.2 * u[2]) * lx, (0.3 + 0.4 * u[3]) * ly, z]
+        target[n] = [(0.2 + 0.6 * u[4]) * lx, (0.2 + 0.6 * u[5]) * ly, lz + 5.0e-3 + 15.0e-3 * u[6]]
+    return tools, target
+
+
+def rl_policy_params(seed: int, obs: int = 64, hidden: int = 256, actions: int = 7) -> np.ndarray:
+    """Random-init policy, flat float32: W1 [256][64], b1, W2 [256][256], b2,
+    W3 [7][256], b3; He-uniform weights, zero biases.  The rows of W2 and W3
+    are shifted to zero mean: the inputs of those layers are non-negative, so
+    rows with a common offset would give every environment the same sign of
+    an action, and the grasp command would never differ between them."""
+    r = np.random.default_rng([seed, _STREAM_RL])
+    w2 = r.uniform(-1, 1, (hidden, hidden)) * np.sqrt(6.0 / hidden)
+    w3 = r.uniform(-1, 1, (actions, hidden)) * np.sqrt(6.0 / hidden)
+    w1 = r.uniform(-1, 1, hidden * obs) * np.sqrt(6.0 / obs)
+    parts = [w1, np.zeros(hidden), (w2 - w2.mean(axis=1, keepdims=True)).ravel(), np.zeros(hidden),
+             (w3 - w3.mean(axis=1, keepdims=True)).ravel(), np.zeros(actions)]
+    return np.concatenate(parts).astype(np.float32)
