@@ -108,3 +108,18 @@ struct xpbd_batch {
     }
 };
 
+namespace xpbd {
+
+// Grasp state of the RL-style step handed to the step launches.
+struct GraspArgs {
+    int32_t *state;      // device [N]: held id, -1 none, -2 closed and empty
+    float offset[3];     // dragging point relative to tool 0's centre
+    float radius;        // r_l
+};
+
+// num_steps steps with the tool poses in device memory ([num_steps][N][tools][3]
+// or [6] for capsules); grasp is null or names the grasp state (register variant).
+xpbd_status run_step(xpbd_batch *b, int32_t num_steps, const float *tools_dev,
+                     const GraspArgs *grasp);
+
+}  // namespace xpbd

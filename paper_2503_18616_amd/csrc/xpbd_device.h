@@ -97,6 +97,14 @@ struct StepArgs {
     float tool_radius[2];
     float tool_radius2[2];       // r^2
     float tool_reach2[2];        // (2r)^2, rounded to float
+    // grasping (register variant; null: no grasper): per environment the
+    // particle tool 0 holds (id within the environment), -1 for none, -2 for
+    // a closed grasper that holds nothing yet (the kernel then takes the free
+    // particle closest to tool 0's centre + grasp_offset strictly within
+    // sqrt(grasp_radius2) and writes its id, or -1)
+    int32_t *grasp;
+    float grasp_offset[3];
+    float grasp_radius2;
 };
 
 // Arguments of the learned warm start's per-substep kernels (one substep per
@@ -189,16 +197,20 @@ hipError_t launch_step(const StepArgs &args, int block, int particles_per_thread
 // LDS layout of the register-multiplier kernel for a group holding V particles
 // in all.  Scratch: words 0..15 per-wave counts, 32..95 flags of the
 // workgroup-wide OR (16 per environment), bytes kRegScratchTools.. the sphere
-// centres of the group's environments (float4 [G][2]).
+// centres of the group's environments (float4 [G][2]), bytes
+// kRegScratchGrasp.. the grasp state (int32 [G] held slots, int32 [G] search
+// flags, uint64 [16 waves][G] partial minima of the grasp search).
 struct RegLdsLayout {
     uint32_t xw;       // float4 [V]  position + inverse mass
     uint32_t vel;      // float [3][V]
     uint32_t prev;     // float [3][V]  positions at the start of the substep
-    uint32_t scratch;  // 512 bytes
+    uint32_t scratch;  // kRegScratchBytes
     uint32_t total;
 };
 
 constexpr uint32_t kRegScratchTools = 384;
+constexpr uint32_t kRegScratchGrasp = 512;
+constexpr uint32_t kRegScratchBytes = 1024;
 constexpr int kMaxEnvsPerGroup = 2;
 
 __host__ __device__ inline RegLdsLayout reg_lds_layout(int32_t V)
@@ -208,7 +220,7 @@ __host__ __device__ inline RegLdsLayout reg_lds_layout(int32_t V)
     l.vel = 16u * (uint32_t)V;
     l.prev = l.vel + 12u * (uint32_t)V;
     l.scratch = align_up(l.prev + 12u * (uint32_t)V, 16);
-    l.total = l.scratch + 512u;
+    l.total = l.scratch + kRegScratchBytes;
     return l;
 }
 

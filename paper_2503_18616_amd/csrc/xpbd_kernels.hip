@@ -404,6 +404,15 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
 template <int PPT, bool STAGE, bool RESIDUAL, bool JACOBI>
 __global__ void __launch_bounds__(1024) xpbd_step_lds_kernel(StepArgs A)
 {
@@ -877,7 +886,7 @@ __device__ __forceinline__ void run_round(float4 *xw, const RoundTables &t, int 
 // particles as float4 (x, y, z, w), velocities and start-of-substep positions
 // (structure of arrays), then scratch.  Multipliers live in registers (NB
 // banks of 32 rounds).
-template <int NB, int EG>
+template <int NB, int EG, bool GRASP>
 __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -968,6 +977,81 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
             }
         }
         __syncthreads();
+        // grasping (Sec. III-A.2): the LDS slot each environment's grasper
+        // holds (uniform; -1 for none) and the thread that owns that slot
+        int held[EG], owner[EG];
+#pragma unroll
+        for (int e = 0; e < EG; ++e)
+            held[e] = owner[e] = -1;
+        bool grasping = false;
+        if constexpr (GRASP) {
+            int32_t *gs = reinterpret_cast<int32_t *>(smem + L.scratch + kRegScratchGrasp);
+            uint64_t *part = reinterpret_cast<uint64_t *>(smem + L.scratch + kRegScratchGrasp + 16);
+#pragma unroll
+            for (int e = 0; e < EG; ++e)
+                if (tid == e) {
+                    const int h = A.grasp[env[e]];
+                    const bool ok = h >= 0 && h < V && md.inv_mass[h] > 0.0f;
+                    gs[e] = ok ? (int)md.slot_of[e * V + h] : -1;
+                    gs[EG + e] = h == -2 ? 1 : 0;
+                }
+            __syncthreads();
+            bool search = false;
+#pragma unroll
+            for (int e = 0; e < EG; ++e)
+                search |= gs[EG + e] != 0;
+            if (search) {
+                // a closed grasper holding nothing: the free particle closest
+                // to the dragging point strictly within reach, on the
+                // start-of-step positions; key (squared distance bits, id)
+                // so that the lowest id wins a tie
+                uint64_t best[EG];
+#pragma unroll
+                for (int e = 0; e < EG; ++e)
+                    best[e] = ~0ull;
+                for (int k = 0, i = opaque(tid); i < VS; ++k, i += B) {
+                    const int e = EG > 1 ? (int)((slot_env >> (2 * k)) & 3u) : 0;
+                    const float4 ct = tool_c[2 * e];
+                    const float4 p = xw[i];
+                    const float dx = p.x - (ct.x + A.grasp_offset[0]);
+                    const float dy = p.y - (ct.y + A.grasp_offset[1]);
+                    const float dz = p.z - (ct.z + A.grasp_offset[2]);
+                    const float d2 = dx * dx + dy * dy + dz * dz;
+                    if (p.w > 0.0f && d2 < A.grasp_radius2) {
+                        const uint64_t key = (uint64_t)__float_as_uint(d2) << 32 |
+                                             (uint32_t)((int)md.id_of[i] - e * V);
+#pragma unroll
+                        for (int f = 0; f < EG; ++f)
+                            best[f] = f == e && key < best[f] ? key : best[f];
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < EG; ++e) {
+                    best[e] = wave_min_u64(best[e]);
+                    if (lane == 0)
+                        part[wave * EG + e] = best[e];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < EG; ++e)
+                    if (tid == e && gs[EG + e]) {
+                        uint64_t m = ~0ull;
+                        for (int w = 0; w < num_waves; ++w)
+                            m = part[w * EG + e] < m ? part[w * EG + e] : m;
+                        const int id = m == ~0ull ? -1 : (int)(uint32_t)m;
+                        gs[e] = id >= 0 ? (int)md.slot_of[e * V + id] : -1;
+                        if (writes[e])
+                            A.grasp[env[e]] = id;
+                    }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int e = 0; e < EG; ++e) {
+                held[e] = __builtin_amdgcn_readfirstlane(gs[e]);
+                owner[e] = held[e] >= 0 ? held[e] % B : -1;
+                grasping |= held[e] >= 0;
+            }
+        }
         // contact candidates on the start-of-step positions
         cand = 0u;
         for (int t = 0; t < tools; ++t) {
@@ -1018,7 +1102,7 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
                         run_round<EG>(xw, tab, r + 1, slot_b, active, tets, barriers, bank1,
                                       alpha_d, alpha_v);
                     }
-                if (any_contact) {
+                if (any_contact || (GRASP && grasping)) {
                     for (int t = 0; t < tools; ++t) {
                         const float rt = t == 0 ? A.tool_radius[0] : A.tool_radius[1];
                         const float rt2 = t == 0 ? A.tool_radius2[0] : A.tool_radius2[1];
@@ -1028,6 +1112,19 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
                                 project_contact(xw, i, ct.x, ct.y, ct.z, rt, rt2);
                             }
                     }
+                    // the dragging constraint (k_s = 1, rest length 0) moves the
+                    // held particle onto the dragging point; its slot's owner
+                    // runs it after its own contacts
+#pragma unroll
+                    for (int e = 0; e < EG; ++e)
+                        if (GRASP && tid == owner[e]) {
+                            const float4 ct = tool_c[2 * e];
+                            float4 p = xw[held[e]];
+                            p.x = ct.x + A.grasp_offset[0];
+                            p.y = ct.y + A.grasp_offset[1];
+                            p.z = ct.z + A.grasp_offset[2];
+                            xw[held[e]] = p;
+                        }
                     __syncthreads();
                 }
             }
@@ -1693,7 +1790,8 @@ hipError_t launch_ppt(const StepArgs &args, int block, bool jacobi, bool stage, 
 template <int NB, int EG>
 hipError_t launch_reg_variant(const StepArgs &args, int block, uint32_t lds_bytes, hipStream_t stream)
 {
-    auto kernel = xpbd_step_reg_kernel<NB, EG>;
+    // the grasping code only in the launches that grasp (it costs registers)
+    auto kernel = args.grasp ? xpbd_step_reg_kernel<NB, EG, true> : xpbd_step_reg_kernel<NB, EG, false>;
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)lds_bytes);

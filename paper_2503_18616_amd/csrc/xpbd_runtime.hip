@@ -861,6 +861,17 @@ xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
             tools_dev = b->tool_staging;
         }
     }
+    return xpbd::run_step(b, num_steps, tools_dev, nullptr);
+}
+
+}  // extern "C"
+
+// The launches of num_steps steps with the tool poses in device memory; the
+// RL-style step passes its grasp state (register variant only).
+xpbd_status xpbd::run_step(xpbd_batch *b, int32_t num_steps, const float *tools_dev,
+                           const GraspArgs *grasp)
+{
+    const int tools = b->params.num_tools;
     xpbd::StepArgs a;
     std::memset(&a, 0, sizeof a);
     a.meshes = b->meshes_dev;
@@ -897,6 +908,12 @@ xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
         const float reach = 2.0f * r;
         a.tool_reach2[t] = reach * reach;
     }
+    if (grasp) {
+        a.grasp = grasp->state;
+        for (int k = 0; k < 3; ++k)
+            a.grasp_offset[k] = grasp->offset[k];
+        a.grasp_radius2 = grasp->radius * grasp->radius;
+    }
     const bool resid = (b->params.flags & XPBD_F_RESIDUAL) != 0;
     b->residual_valid = b->residual_valid || resid;
     if (b->register_variant && b->classes.size() == 1) {
@@ -929,6 +946,8 @@ xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
                                   b->lds_bytes, resid, b->stream));
     return XPBD_OK;
 }
+
+extern "C" {
 
 xpbd_status xpbd_set_flags(xpbd_batch *b, uint32_t flags)
 {

@@ -69,7 +69,8 @@ EXPORTED = ["xpbd_create_batch", "xpbd_step", "xpbd_read_state", "xpbd_write_sta
             "xpbd_set_flags", "xpbd_field_bytes", "xpbd_destroy_batch", "xpbd_last_error",
             "xpbd_prepare_mesh", "xpbd_mlp_create", "xpbd_mlp_get_params", "xpbd_mlp_set_params",
             "xpbd_mlp_forward", "xpbd_mlp_train_step", "xpbd_mlp_destroy", "xpbd_axis_neighbours",
-            "xpbd_step_learned", "xpbd_autotune", "xpbd_surface_faces"]
+            "xpbd_step_learned", "xpbd_autotune", "xpbd_surface_faces", "xpbd_policy_create",
+            "xpbd_policy_destroy", "xpbd_rl_step"]
 
 # learned warm start (include/xpbd_learned.h)
 MLP_FEATURES = 27
@@ -77,6 +78,14 @@ MLP_FEATURE_STRIDE = 32
 MLP_HIDDEN = 128
 MLP_OUTPUTS = 3
 MLP_PARAMS = 20483
+
+
+# RL-style step (include/xpbd_rl.h)
+RL_OBS = 64
+RL_HIDDEN = 256
+RL_ACTIONS = 7
+RL_TRACKED = 18
+RL_POLICY_PARAMS = 84231
 
 
 class XpbdMesh(ctypes.Structure):
@@ -464,7 +473,101 @@ def xpbd_step_learned(batch, net, num_steps, tool_pos, min_iterations, max_itera
     _check(_lib.xpbd_step_learned(batch, net, int(num_steps), _ptr(tool_pos), ctypes.byref(lp)))
 
 
+class XpbdRlParams(ctypes.Structure):
+    _fields_ = [("grasp_radius", ctypes.c_float), ("grasp_offset", ctypes.c_float * 3),
+                ("max_speed", ctypes.c_float), ("obs_scale", ctypes.c_float),
+                ("obs_origin", ctypes.c_float * 3), ("box_lo", ctypes.c_float * 3),
+                ("box_hi", ctypes.c_float * 3), ("tracked", ctypes.c_int32 * RL_TRACKED)]
+
+
+_lib.xpbd_policy_create.restype = ctypes.c_int
+_lib.xpbd_policy_create.argtypes = [_V, ctypes.c_int64, _V, ctypes.POINTER(ctypes.c_void_p)]
+_lib.xpbd_policy_destroy.restype = None
+_lib.xpbd_policy_destroy.argtypes = [_V]
+_lib.xpbd_rl_step.restype = ctypes.c_int
+_lib.xpbd_rl_step.argtypes = [_V, _V, ctypes.POINTER(XpbdRlParams), ctypes.c_int32, _V, _V, _V,
+                              _V, _V]
+
+
+def make_rl_params(grasp_radius, grasp_offset, max_speed, obs_scale, obs_origin, box_lo, box_hi,
+                   tracked) -> XpbdRlParams:
+    p = XpbdRlParams()
+    p.grasp_radius = grasp_radius
+    p.grasp_offset[:] = [float(v) for v in grasp_offset]
+    p.max_speed = max_speed
+    p.obs_scale = obs_scale
+    p.obs_origin[:] = [float(v) for v in obs_origin]
+    p.box_lo[:] = [float(v) for v in box_lo]
+    p.box_hi[:] = [float(v) for v in box_hi]
+    tr = [int(v) for v in np.asarray(tracked).reshape(-1)]
+    if len(tr) != RL_TRACKED:
+        raise ValueError(f"tracked needs {RL_TRACKED} particle ids")
+    p.tracked[:] = tr
+    return p
+
+
+def xpbd_policy_create(params, stream=None):
+    p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+    h = ctypes.c_void_p()
+    _check(_lib.xpbd_policy_create(p.ctypes.data, int(p.size),
+                                   stream if stream is not None else default_stream(),
+                                   ctypes.byref(h)))
+    return h.value
+
+
+def xpbd_policy_destroy(policy):
+    _lib.xpbd_policy_destroy(policy)
+
+
+def xpbd_rl_step(batch, policy, params: XpbdRlParams, num_steps, tool_pos, grasped, target,
+                 obs=None, actions=None):
+    """RL steps on the batch's stream; every array is a contiguous device tensor:
+    tool_pos float32 [N, 2, 3], grasped int32 [N] (both updated in place),
+    target float32 [N, 3], obs float32 [num_steps, N, 64] or None, actions
+    float32 [num_steps, N, 7] or None (sizes checked here)."""
+    n_envs = _BATCHES.get(batch, (None,))[0]
+    steps = int(num_steps)
+    need = [(tool_pos, "torch.float32", n_envs * 6, "tool_pos"),
+            (grasped, "torch.int32", n_envs, "grasped"),
+            (target, "torch.float32", n_envs * 3, "target"),
+            (obs, "torch.float32", steps * n_envs * RL_OBS, "obs"),
+            (actions, "torch.float32", steps * n_envs * RL_ACTIONS, "actions")]
+    for t, dtype, count, what in need:
+        if t is None and what in ("obs", "actions"):
+            continue
+        if not hasattr(t, "data_ptr") or not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"{what} must be a contiguous device tensor")
+        if str(t.dtype) != dtype or t.numel() != count:
+            raise ValueError(f"{what} must be {dtype} with {count} elements")
+    _check(_lib.xpbd_rl_step(batch, policy, ctypes.byref(params), steps, _ptr(tool_pos),
+                             _ptr(grasped), _ptr(target), _ptr(obs), _ptr(actions)))
+
+
 # --------------------------------------------------------------------- convenience
+class Policy:
+    """Owning wrapper around a policy handle."""
+
+    def __init__(self, params, stream=None):
+        self.handle = xpbd_policy_create(params, stream)
+
+    def close(self):
+        if self.handle:
+            xpbd_policy_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 class Mlp:
     """Owning wrapper around a network handle."""
 
@@ -517,6 +620,11 @@ class Batch:
                      **kw):
         xpbd_step_learned(self.handle, net.handle if net is not None else None, num_steps,
                           tool_pos, min_iterations, max_iterations, threshold, **kw)
+
+    def rl_step(self, policy, params: XpbdRlParams, num_steps, tool_pos, grasped, target,
+                obs=None, actions=None):
+        xpbd_rl_step(self.handle, policy.handle, params, num_steps, tool_pos, grasped, target,
+                     obs, actions)
 
     def read(self, field, dst=None, raise_nonfinite=True):
         return xpbd_read_state(self.handle, field, dst, raise_nonfinite)

@@ -207,3 +207,28 @@ def test_surface_faces_equal_the_oracle(xp, grid):
     assert np.array_equal(faces, om.faces)
     assert np.array_equal(colours, om.face_colour)
     assert n_col == int(om.face_colour.max()) + 1
+
+
+def test_policy_create_rejects_bad_parameters(xp):
+    """Checked on the host before any device call."""
+    import ctypes
+    h = ctypes.c_void_p()
+    p = np.zeros(xp.RL_POLICY_PARAMS, np.float32)
+    assert xp._lib.xpbd_policy_create(p.ctypes.data, 10, None, ctypes.byref(h)) == xp.XPBD_E_ARG
+    assert "parameters" in xp.xpbd_last_error()
+    p[7] = np.inf
+    assert xp._lib.xpbd_policy_create(p.ctypes.data, p.size, None, ctypes.byref(h)) == xp.XPBD_E_ARG
+    assert "finite" in xp.xpbd_last_error()
+    assert xp._lib.xpbd_policy_create(None, p.size, None, ctypes.byref(h)) == xp.XPBD_E_ARG
+
+
+def test_rl_constants_match_the_oracle(xp):
+    import oracle.rl as R
+    assert (xp.RL_OBS, xp.RL_HIDDEN, xp.RL_ACTIONS, xp.RL_TRACKED, xp.RL_POLICY_PARAMS) == \
+        (R.OBS, R.HIDDEN, R.ACTIONS, R.TRACKED, R.NUM_PARAMS)
+    assert ctypes_sizeof_rl_params(xp) == 4 * (1 + 3 + 1 + 1 + 3 + 3 + 3) + 4 * 18
+
+
+def ctypes_sizeof_rl_params(xp):
+    import ctypes
+    return ctypes.sizeof(xp.XpbdRlParams)

@@ -1,0 +1,299 @@
+"""GPU parity of the RL-style step (include/xpbd_rl.h) against the FP64 oracle
+(oracle/rl.py): observations, policy outputs, tool motion, grasp decisions
+and the simulation with the dragging constraint.
+
+Tolerances.  The physics gate is the one of the plain step: 1e-4 of the mesh
+extent per particle.  The policy runs in bfloat16 on both sides but sums in
+float32 here and exactly in the oracle, and its inputs come from float32
+positions here: an input or a hidden value whose rounding to bfloat16 flips
+moves an action by up to about 3e-3 (measured on 8192 environments of the
+bench's policy in a float32 emulation); actions are compared to ACT_TOL =
+1e-2.  A tool then moves by at most ACT_TOL * max_speed * dt more per step, so
+tools and particles of a policy-driven run are compared to POS_TOL plus that
+drift times the number of steps.  Decisions taken from floating point (the
+grasp command a[6] > 0, the closest particle within r_l) are compared only
+where the oracle's value is at least DECISION_MARGIN (a[6]) or
+SELECT_MARGIN (relative gap of squared distances) from the tie; every other
+environment is checked for validity only.  With the exactly representable
+policies of ``exact_policy`` there is no policy error at all and the whole
+step is held to POS_TOL.
+"""
+import numpy as np
+import pytest
+
+import oracle.rl as R
+from paper_2503_18616_amd import workloads as W
+from tests import cases as K
+
+pytestmark = pytest.mark.gpu
+
+ACT_TOL = 1e-2
+DECISION_MARGIN = 1e-2
+SELECT_MARGIN = 1e-3
+HELD0 = 395          # a free top-face particle of the 12x8x3 slab
+
+
+@pytest.fixture(scope="module")
+def xp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2503_18616_amd import xpbd
+    return xpbd
+
+
+def f32(v):
+    return float(np.float32(v))
+
+
+def rl_settings(mesh):
+    lo, hi = W.rl_box()
+    return dict(grasp_radius=W.RL_GRASP_RADIUS, grasp_offset=W.RL_GRASP_OFFSET,
+                max_speed=W.RL_MAX_SPEED, obs_scale=W.RL_OBS_SCALE, obs_origin=W.rl_origin(),
+                box_lo=lo, box_hi=hi, tracked=W.rl_tracked(mesh))
+
+
+def oracle_rl_params(mesh):
+    s = rl_settings(mesh)
+    vec = lambda v: tuple(f32(x) for x in v)
+    return R.RlParams(f32(s["grasp_radius"]), vec(s["grasp_offset"]), f32(s["max_speed"]),
+                      f32(s["obs_scale"]), vec(s["obs_origin"]), vec(s["box_lo"]),
+                      vec(s["box_hi"]), s["tracked"])
+
+
+def exact_policy(hold):
+    """Weights whose every product and sum is exact in float32 and bfloat16:
+    a[0:6] fixed tool velocities, a[6] = 1 - c * grasp flag (observation 9),
+    c = 0.5 (hold: closed all the time) or 2 (toggle: a held particle is
+    released the next step, a released grasper closes again)."""
+    H, F = R.HIDDEN, R.OBS
+    flat = np.zeros(R.NUM_PARAMS, np.float32)
+    flat[0 * F + 9] = 1.0                         # unit 0 of layer 1 copies the flag
+    off2 = H * F + H
+    flat[off2 + 0 * H + 0] = 1.0                  # unit 0 of layer 2 copies unit 0
+    off3 = off2 + H * H + H
+    flat[off3 + 6 * H + 0] = -(0.5 if hold else 2.0)
+    flat[-R.ACTIONS:] = [0.5, -0.25, 1.0, -0.5, 0.25, -1.0, 1.0]
+    return flat
+
+
+def start_state(num_envs, env_ids=None, seed=0):
+    tools, target = W.rl_start(num_envs, seed, env_ids=env_ids)
+    ids = np.arange(num_envs) if env_ids is None else np.asarray(env_ids)
+    grasped = np.where(ids % 3 == 1, HELD0, -1).astype(np.int32)
+    return tools, target, grasped
+
+
+def run_gpu(xp, wl, policy_params, steps, tools, target, grasped, per_step=True):
+    """Returns per-step tool centres and grasp states, observations, actions
+    and the final positions."""
+    import torch
+    m = wl.meshes[0]
+    p = K.lib_params(xp, wl)
+    N = wl.num_envs
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b, \
+            xp.Policy(policy_params) as pol:
+        rp = xp.make_rl_params(**rl_settings(m))
+        tp = torch.from_numpy(np.ascontiguousarray(tools)).cuda()
+        gr = torch.from_numpy(np.ascontiguousarray(grasped)).cuda()
+        tg = torch.from_numpy(np.ascontiguousarray(target)).cuda()
+        obs = torch.zeros((steps, N, R.OBS), dtype=torch.float32, device="cuda")
+        act = torch.zeros((steps, N, R.ACTIONS), dtype=torch.float32, device="cuda")
+        tool_hist, grasp_hist = [], []
+        if per_step:
+            for s in range(steps):
+                b.rl_step(pol, rp, 1, tp, gr, tg, obs[s], act[s])
+                tool_hist.append(tp.cpu().numpy().copy())
+                grasp_hist.append(gr.cpu().numpy().copy())
+        else:
+            b.rl_step(pol, rp, steps, tp, gr, tg, obs, act)
+            tool_hist.append(tp.cpu().numpy().copy())
+            grasp_hist.append(gr.cpu().numpy().copy())
+        torch.cuda.synchronize()
+        x = b.positions()
+        offs = b.env_offsets
+    return (np.array(tool_hist), np.array(grasp_hist), obs.cpu().numpy(), act.cpu().numpy(),
+            x, offs)
+
+
+def run_oracle(oracle_lib, wl, policy_params, steps, tools, target, grasped, env_ids):
+    om = K.oracle_meshes(oracle_lib, wl)[0]
+    params = K.oracle_params(oracle_lib, wl)
+    rl = oracle_rl_params(wl.meshes[0])
+    net = R.unpack_policy(policy_params)
+    return [R.run_env_rl(om, wl.compliance[e], params, rl, net, tools[n], target[n], steps,
+                         grasped0=int(grasped[n]))
+            for n, e in enumerate(env_ids)]
+
+
+def decisions_clear(ref):
+    return bool(np.all(np.abs(ref.actions[:, 6]) >= DECISION_MARGIN) and
+                np.all(ref.select_margin >= SELECT_MARGIN))
+
+
+def compare(ref, n, e, got, pos_tol, act_tol, offs, steps_checked):
+    tool_hist, grasp_hist, obs, act, x, _ = got
+    xe = K.env_block(x, offs, e)
+    err = K.max_position_error(xe, ref.x)
+    assert err <= pos_tol, f"env {e}: position error {err:.3e} > {pos_tol:.3e}"
+    s = steps_checked
+    t_err = np.max(np.abs(tool_hist[:, e] - ref.tools[s]))
+    assert t_err <= pos_tol, f"env {e}: tool error {t_err:.3e}"
+    assert np.array_equal(grasp_hist[:, e], ref.grasped[s]), \
+        f"env {e}: grasp {grasp_hist[:, e]} vs {ref.grasped[s]}"
+    o_err = np.max(np.abs(obs[:, e] - ref.obs))
+    assert o_err <= pos_tol * W.RL_OBS_SCALE + 1e-6, f"env {e}: observation error {o_err:.3e}"
+    a_err = np.max(np.abs(act[:, e] - ref.actions))
+    assert a_err <= act_tol, f"env {e}: action error {a_err:.3e}"
+    return err, a_err
+
+
+# --------------------------------------------------------------------------------------
+@pytest.mark.parametrize("hold", [True, False], ids=["hold", "toggle"])
+def test_rl_exact_policy_parity(xp, oracle_lib, hold):
+    """37 environments (ragged against the 16-environment tiles), 10 steps,
+    one call per step: grasping, holding, releasing and dragging to the plain
+    gate, actions exact."""
+    N, steps = 37, 10
+    wl = W.rl_workload(N, seed=0)
+    tools, target, grasped = start_state(N)
+    pp = exact_policy(hold)
+    got = run_gpu(xp, wl, pp, steps, tools, target, grasped)
+    refs = run_oracle(oracle_lib, wl, pp, steps, tools, target, grasped, range(N))
+    clear = [n for n in range(N) if np.all(refs[n].select_margin >= SELECT_MARGIN)]
+    assert len(clear) >= 0.9 * N
+    worst = 0.0
+    for n in clear:
+        err, a_err = compare(refs[n], n, n, got, K.POS_TOL, 0.0, got[5], slice(None))
+        worst = max(worst, err)
+    held = np.array([r.grasped for r in refs])
+    assert np.any(held >= 0)
+    if hold:
+        assert np.all(held[1::3] == HELD0)                  # kept although not the closest
+    else:
+        assert np.any((held[:, :-1] >= 0) & (held[:, 1:] < 0))   # releases
+        assert np.any((held[:, :-1] < 0) & (held[:, 1:] >= 0))   # fresh grasps
+    print(f"max position error {worst:.3e} m over {len(clear)} environments")
+
+
+def test_rl_random_policy_parity(xp, oracle_lib):
+    """The random-init policy of the benchmark, 37 environments, 8 steps in
+    one call (final state) and one step per call (history)."""
+    N, steps = 37, 8
+    wl = W.rl_workload(N, seed=0)
+    tools, target, grasped = start_state(N)
+    pp = W.rl_policy_params(0)
+    got = run_gpu(xp, wl, pp, steps, tools, target, grasped)
+    refs = run_oracle(oracle_lib, wl, pp, steps, tools, target, grasped, range(N))
+    drift = steps * ACT_TOL * W.RL_MAX_SPEED * wl.dt
+    clear = [n for n in range(N) if decisions_clear(refs[n])]
+    assert len(clear) >= 0.75 * N, f"only {len(clear)} environments with clear decisions"
+    worst_x = worst_a = 0.0
+    for n in clear:
+        err, a_err = compare(refs[n], n, n, got, K.POS_TOL + drift, ACT_TOL, got[5], slice(None))
+        worst_x, worst_a = max(worst_x, err), max(worst_a, a_err)
+    # every environment: a valid grasp state
+    m = wl.meshes[0]
+    g = got[1][-1]
+    assert np.all((g == -1) | ((g >= 0) & (g < m.num_vertices)))
+    assert np.all(m.inv_mass[g[g >= 0]] > 0)
+    # the same run in one call ends in the same state, bit for bit
+    one = run_gpu(xp, wl, pp, steps, tools, target, grasped, per_step=False)
+    assert np.array_equal(one[4], got[4])
+    assert np.array_equal(one[0][-1], got[0][-1]) and np.array_equal(one[1][-1], got[1][-1])
+    assert np.array_equal(one[2], got[2]) and np.array_equal(one[3], got[3])
+    print(f"max position error {worst_x:.3e} m, action error {worst_a:.3e}")
+
+
+def test_rl_full_size_sampled(xp, oracle_lib):
+    """8192 environments (the benchmark's launch), 2 steps: first-step
+    observations, actions and grasp commands of every environment against the
+    oracle, and the whole run of sampled environments."""
+    N, steps = 8192, 2
+    wl = W.rl_workload(N, seed=0)
+    tools, target, grasped = start_state(N)
+    pp = W.rl_policy_params(0)
+    got = run_gpu(xp, wl, pp, steps, tools, target, grasped)
+    m = wl.meshes[0]
+    rl = oracle_rl_params(m)
+    net = R.unpack_policy(pp)
+    rest = m.rest_pos.astype(np.float64)
+    o0 = np.stack([R.observe(rest, rest, tools[e], target[e],
+                             int(grasped[e]) if grasped[e] >= 0 else -1, rl.tracked,
+                             rl.obs_scale, rl.obs_origin) for e in range(N)])
+    a0 = R.policy(net, o0)
+    assert np.max(np.abs(got[2][0] - o0)) <= 1e-6
+    assert np.max(np.abs(got[3][0] - a0)) <= ACT_TOL
+    clear = np.abs(a0[:, 6]) >= DECISION_MARGIN
+    closed = a0[:, 6] > 0
+    g1 = got[1][0]
+    assert np.all(g1[clear & ~closed] == -1)
+    assert np.all(g1[clear & closed & (grasped >= 0)] == HELD0)
+    sample = [0, 1, 2, 15, 16, 17, 1000, 2047, 4095, 4096, 6001, 8190, 8191]
+    t_s, tg_s, g_s = start_state(len(sample), env_ids=sample)
+    refs = run_oracle(oracle_lib, wl, pp, steps, t_s, tg_s, g_s, sample)
+    drift = steps * ACT_TOL * W.RL_MAX_SPEED * wl.dt
+    checked = 0
+    for n, e in enumerate(sample):
+        if decisions_clear(refs[n]):
+            compare(refs[n], n, e, got, K.POS_TOL + drift, ACT_TOL, got[5], slice(None))
+            checked += 1
+    assert checked >= 0.75 * len(sample)
+
+
+def test_rl_zero_steps_and_optional_outputs(xp):
+    import torch
+    wl = W.rl_workload(20, seed=1)
+    tools, target, grasped = start_state(20)
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, K.lib_params(xp, wl)) as b, \
+            xp.Policy(W.rl_policy_params(1)) as pol:
+        rp = xp.make_rl_params(**rl_settings(wl.meshes[0]))
+        tp = torch.from_numpy(tools).cuda()
+        gr = torch.from_numpy(grasped).cuda()
+        tg = torch.from_numpy(target).cuda()
+        x0 = b.positions()
+        b.rl_step(pol, rp, 0, tp, gr, tg)
+        torch.cuda.synchronize()
+        assert np.array_equal(b.positions(), x0)
+        assert np.array_equal(tp.cpu().numpy(), tools)
+        b.rl_step(pol, rp, 3, tp, gr, tg)           # no observation or action buffers
+        torch.cuda.synchronize()
+        assert not np.array_equal(b.positions(), x0)
+
+
+def test_rl_rejects_bad_arguments(xp):
+    import torch
+    wl = W.rl_workload(8, seed=0)
+    tools, target, grasped = start_state(8)
+    tp = torch.from_numpy(tools).cuda()
+    gr = torch.from_numpy(grasped).cuda()
+    tg = torch.from_numpy(target).cuda()
+    settings = rl_settings(wl.meshes[0])
+    with xp.Policy(W.rl_policy_params(0)) as pol:
+        with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, K.lib_params(xp, wl)) as b:
+            bad = dict(settings, tracked=np.full(18, wl.meshes[0].num_vertices, np.int32))
+            with pytest.raises(xp.XpbdError, match="tracked"):
+                b.rl_step(pol, xp.make_rl_params(**bad), 1, tp, gr, tg)
+            with pytest.raises(xp.XpbdError, match="grasp_radius"):
+                b.rl_step(pol, xp.make_rl_params(**dict(settings, grasp_radius=0.0)), 1, tp, gr, tg)
+            with pytest.raises(xp.XpbdError, match="box"):
+                b.rl_step(pol, xp.make_rl_params(**dict(settings, box_lo=(1, 1, 1))), 1, tp, gr, tg)
+            rp = xp.make_rl_params(**settings)
+            st = xp._lib.xpbd_rl_step(b.handle, pol.handle, rp, 1, tools.ctypes.data,
+                                      gr.data_ptr(), tg.data_ptr(), None, None)
+            assert st == xp.XPBD_E_ARG and "device memory" in xp.xpbd_last_error()
+        p = K.lib_params(xp, wl)
+        p.solver_variant = xp.VARIANT_LDS
+        with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b:
+            with pytest.raises(xp.XpbdError, match="register"):
+                b.rl_step(pol, xp.make_rl_params(**settings), 1, tp, gr, tg)
+        one = W.batch_workload(8, seed=0)
+        with xp.Batch(K.lib_meshes(one), one.env_mesh, one.compliance, K.lib_params(xp, one)) as b:
+            with pytest.raises(xp.XpbdError, match="two sphere tools"):
+                b.rl_step(pol, xp.make_rl_params(**dict(settings, tracked=np.arange(18))), 1, tp,
+                          gr, tg)
+    bad = W.rl_policy_params(0)
+    bad[5] = np.nan
+    with pytest.raises(xp.XpbdError, match="finite"):
+        xp.Policy(bad)
+    with pytest.raises(xp.XpbdError, match="parameters"):
+        xp.Policy(np.zeros(10, np.float32))
