@@ -15,7 +15,7 @@ Prints one JSON line with the throughput in environment-substeps per second,
 the roofline of the step kernel and the FP64 oracle timed on the host cores
 on a bounded sample of the same workload.
 
-    python bench.py [--steps 1000] [--warmup 20] [--workload batch|single]
+    python bench.py [--steps 1000] [--warmup 20] [--workload batch|uneven|single|rl]
 """
 import argparse
 import json
@@ -53,9 +53,12 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000, help="timed steps")
     ap.add_argument("--warmup", type=int, default=20, help="untimed steps first")
-    ap.add_argument("--workload", choices=["batch", "uneven", "single"], default="batch")
+    ap.add_argument("--workload", choices=["batch", "uneven", "single", "rl"], default="batch",
+                    help="rl: the RL-style step (observations, policy network, tool motion, "
+                         "grasping and the simulation step of 12x8x3 slabs with two tools)")
     ap.add_argument("--envs", type=int, default=0,
-                    help="environments (0: 1024 for the batch workload, 4096 for the uneven one)")
+                    help="environments (0: 1024 for the batch workload, 4096 for the uneven one, "
+                         "8192 for the RL-style step)")
     ap.add_argument("--steps-per-launch", type=int, default=1)
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library's choice)")
     ap.add_argument("--variant", type=int, default=0,
@@ -110,20 +113,25 @@ def copy_calibration(mib):
     print(f"copied {mib} MiB", flush=True)
 
 
-def measured_traffic(workload, steps_per_launch, args):
-    """HBM bytes per step launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
-    recorded in profiles/, if they were taken on this kernel source and launch shape."""
+def source_sha(name):
     import hashlib
-    path = os.path.join(ROOT, "profiles", "xpbd_step_traffic.json")
-    src = os.path.join(ROOT, "paper_2503_18616_amd", "csrc", "xpbd_kernels.hip")
+    with open(os.path.join(ROOT, "paper_2503_18616_amd", "csrc", name), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(workload, steps_per_launch, args, record="xpbd_step_traffic.json"):
+    """HBM bytes per step launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
+    recorded in profiles/, if they were taken on this kernel source, this launch
+    selection (the runtime source) and the default launch shape."""
+    path = os.path.join(ROOT, "profiles", record)
     if (not os.path.exists(path) or steps_per_launch != 1 or args.variant or args.packing
             or args.block or args.group):
         return None
     with open(path) as f:
         rec = json.load(f)
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if rec.get("kernel_source_sha256") != sha or rec.get("workload") != workload:
+    if (rec.get("kernel_source_sha256") != source_sha("xpbd_kernels.hip")
+            or rec.get("runtime_source_sha256") != source_sha("xpbd_runtime.hip")
+            or rec.get("workload") != workload):
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -256,6 +264,128 @@ def learned_leg(args, wl_fn, mesh, make_batch, I, S):
             "network": "27-128-128-3 ReLU, bf16 MFMA, fp32 accumulate"}
 
 
+def mesh_sizes(xpbd, m):
+    """(kept edges, kept tets, particles, free particles) of a mesh."""
+    info = xpbd.xpbd_prepare_mesh(m.rest_pos, m.inv_mass, m.tets)
+    return (int(info["edges"].shape[0]), int(info["tets"].shape[0]), m.num_vertices,
+            int((m.inv_mass > 0).sum()))
+
+
+def rl_bench(args):
+    """The RL-style step (include/xpbd_rl.h): per step and environment the
+    observations, the 64-256-256-7 policy, the tool motion, the grasp and the
+    simulation step.  The timed region is K xpbd_rl_step calls of one step
+    each (as an RL loop that reads every step's observations), all on the
+    batch's stream, bracketed by HIP events."""
+    import numpy as np
+    import torch
+
+    from paper_2503_18616_amd import workloads as W
+    from paper_2503_18616_amd import xpbd
+
+    N = args.envs or 8192
+    total = args.warmup + args.steps
+    wl = W.rl_workload(N, seed=0, num_steps=total)
+    m = wl.meshes[0]
+    S, I = wl.substeps, wl.iterations
+    E, T, V, v_free = mesh_sizes(xpbd, m)
+    stream = torch.cuda.current_stream()
+    params = xpbd.make_params(wl.dt, S, I, wl.gravity, 2, wl.tool_radius, block_size=args.block,
+                              solver_variant=args.variant, colour_packing=args.packing,
+                              envs_per_group=args.group)
+    t_create = time.perf_counter()
+    batch = xpbd.Batch([(m.rest_pos, m.inv_mass, m.tets)], wl.env_mesh, wl.compliance, params,
+                       stream=stream.cuda_stream)
+    policy = xpbd.Policy(W.rl_policy_params(0), stream=stream.cuda_stream)
+    t_create = time.perf_counter() - t_create
+    lo, hi = W.rl_box()
+    rp = xpbd.make_rl_params(W.RL_GRASP_RADIUS, W.RL_GRASP_OFFSET, W.RL_MAX_SPEED,
+                             W.RL_OBS_SCALE, W.rl_origin(), lo, hi, W.rl_tracked(m))
+    tools0, target = W.rl_start(N, 0)
+    tp = torch.from_numpy(tools0).cuda()
+    gr = torch.full((N,), -1, dtype=torch.int32, device="cuda")
+    tg = torch.from_numpy(target).cuda()
+    obs = torch.zeros((1, N, xpbd.RL_OBS), dtype=torch.float32, device="cuda")
+    act = torch.zeros((1, N, xpbd.RL_ACTIONS), dtype=torch.float32, device="cuda")
+    progress(f"{wl.name}: set up in {t_create:.1f} s")
+    for _ in range(args.warmup):
+        batch.rl_step(policy, rp, 1, tp, gr, tg, obs, act)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for s in range(args.steps):
+        if s == args.steps - 1:
+            batch.set_flags(xpbd.F_RESIDUAL)
+        batch.rl_step(policy, rp, 1, tp, gr, tg, obs, act)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    progress(f"timed {args.steps} RL steps: {ms / args.steps:.3f} ms per step")
+    holding = int((gr >= 0).sum())
+    resid = batch.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)
+    batch.close()
+    policy.close()
+
+    step_s = ms / 1e3 / args.steps
+    flops = N * S * (I * (E * FLOPS_EDGE + T * FLOPS_TET) + v_free * FLOPS_PARTICLE)
+    policy_flops = N * 2 * (xpbd.RL_OBS * xpbd.RL_HIDDEN + xpbd.RL_HIDDEN * xpbd.RL_HIDDEN +
+                            xpbd.RL_HIDDEN * xpbd.RL_ACTIONS)
+    roofline = {"bound": "alu", "achieved": flops / step_s / 1e12,
+                "peak": PEAK_FP32_NONPACKED / 1e12, "unit": "TFLOP/s",
+                "frac": flops / step_s / PEAK_FP32_NONPACKED,
+                "traffic": measured_traffic(wl.name, 1, args, "rl_step_traffic.json"),
+                "kernel": "xpbd_step_reg_kernel (grasping), timed with the policy kernel "
+                          "of the same step",
+                "launch_ms": step_s * 1e3, "flops_per_launch": flops}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        import oracle.rl as R
+        from concurrent.futures import ThreadPoolExecutor
+        f32 = lambda v: float(np.float32(v))
+        om = oracle.prepare_mesh(m.rest_pos, m.inv_mass, m.tets)
+        op = oracle.OracleParams(f32(wl.dt), S, I, tuple(f32(g) for g in wl.gravity), 2,
+                                 tuple(f32(r) for r in wl.tool_radius))
+        vec = lambda v: tuple(f32(x) for x in v)
+        orl = R.RlParams(f32(W.RL_GRASP_RADIUS), vec(W.RL_GRASP_OFFSET), f32(W.RL_MAX_SPEED),
+                         f32(W.RL_OBS_SCALE), vec(W.rl_origin()), vec(lo), vec(hi),
+                         W.rl_tracked(m))
+        net = R.unpack_policy(W.rl_policy_params(0))
+        envs = list(range(0, N, max(1, N // args.cpu_envs)))[:args.cpu_envs]
+        steps = min(args.cpu_steps, 30)
+        threads = min(16, os.cpu_count() or 1, len(envs))
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=threads) as pool:
+            list(pool.map(lambda e: R.run_env_rl(om, wl.compliance[e], op, orl, net, tools0[e],
+                                                 target[e], steps), envs))
+        dt = time.perf_counter() - t0
+        progress(f"oracle sample: {dt:.1f} s")
+        cpu = {"value": len(envs) * steps * S / dt, "unit": "env-substeps/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"{len(envs)} of the {N} environments x {steps} RL steps "
+                         f"({len(envs) * steps * S} env-substeps, FP64, {dt:.1f} s wall)"}
+
+    out = {
+        "metric": METRIC, "value": N * args.steps * S / (ms / 1e3), "unit": "env-substeps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "envs": N, "grid": [m.nx, m.ny, m.nz], "particles": V,
+                   "edges": E, "tets": T, "substeps": S, "iterations": I, "tools": 2,
+                   "create_s": round(t_create, 3), "solver": "plain (no warm start)",
+                   "policy": "64-256-256-7 bf16 (random init)",
+                   "env_steps_per_s": N * args.steps / (ms / 1e3),
+                   "policy_gflop_per_step": policy_flops / 1e9,
+                   "holding_at_end": holding,
+                   "residual_rms_mean": float(resid[:, 0].mean()),
+                   "residual_max": float(resid[:, 1].max())},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -277,6 +407,9 @@ def main():
     from paper_2503_18616_amd import xpbd
 
     torch.cuda.set_device(0)
+    if args.workload == "rl":
+        rl_bench(args)
+        return
     total = args.warmup + args.steps
     if args.workload == "batch":
         args.envs = args.envs or 1024

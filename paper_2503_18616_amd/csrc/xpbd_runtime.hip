@@ -293,19 +293,60 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     int lds_limit = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
 
-    // register-multiplier variant: environments per workgroup G (requested, else 1:
-    // two per workgroup measured slower on the 1024-environment batch), then the
-    // smallest block of 256, 512 or 1024 threads (or the requested one) whose
-    // round schedule for G copies of every mesh fits the register banks
+    // register-multiplier variant.  A batch of one mesh with block size and
+    // environments per workgroup both left to the library takes the (B, G) of
+    // B in {128, 256, 512, 1024}, G in {1, 2} that the occupancy model below
+    // rates fastest.  Otherwise: G as requested, else 1, then the smallest
+    // block of 256, 512 or 1024 threads (or the requested one) whose round
+    // schedule for G copies of every mesh fits the register banks.
     bool use_registers = false;
     int reg_block = 0, reg_rounds = 0, reg_group = 1;
+    bool scored = false;
+    int lds_cu = 0, num_cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                  device));
+    HIP_TRY(hipDeviceGetAttribute(&num_cus, hipDeviceAttributeMultiprocessorCount, device));
+    lds_cu = std::max(lds_cu, lds_limit);
     const bool pow2_block = params->block_size == 0 ||
                             (params->block_size & (params->block_size - 1)) == 0;
     const bool jacobi = params->solver_variant == XPBD_VARIANT_JACOBI;
     const bool capsules = params->tool_shape == XPBD_TOOL_CAPSULE && params->num_tools > 0;
     if (capsules && params->solver_variant == XPBD_VARIANT_REGISTERS)
         return fail(XPBD_E_CAPACITY, "capsule tools need the LDS or Jacobi variant");
-    if (params->solver_variant != XPBD_VARIANT_LDS && !jacobi && !capsules && pow2_block) {
+    const bool reg_possible =
+        params->solver_variant != XPBD_VARIANT_LDS && !jacobi && !capsules && pow2_block;
+    if (reg_possible && prepared.size() == 1 && params->block_size == 0 &&
+        params->envs_per_group == 0) {
+        // Occupancy model: a round (a lane's constraint of one colour, then
+        // the colour's barrier) costs about the same whatever B and G, and a
+        // CU holds as many workgroups as its 16 resident waves of this kernel
+        // (its registers allow four per SIMD) and its LDS allow.  Time of a
+        // step ~ (passes of groups over the CUs) x rounds; ties go to the
+        // smaller block, then to one environment per workgroup.
+        const PreparedMesh &pm = prepared[0];
+        double best = 0.0;
+        for (int B : {128, 256, 512, 1024})
+            for (int G : {1, 2}) {
+                int r = count_rounds(pm, B, G);
+                r += r % 2;
+                const uint32_t lm = xpbd::reg_lds_layout(G * pm.num_vertices).total;
+                if (r > xpbd::kMaxRounds || G * pm.num_vertices > 16 * B ||
+                    G * pm.num_vertices > 16384 || lm > (uint32_t)lds_limit)
+                    continue;
+                const int per_cu = std::max(1, std::min(16 / (B / 64), (int)((uint32_t)lds_cu / lm)));
+                const int64_t groups = ((int64_t)num_envs + G - 1) / G;
+                const int64_t slots = (int64_t)per_cu * std::max(num_cus, 1);
+                const double cost = (double)((groups + slots - 1) / slots) * r;
+                if (!use_registers || cost < best) {
+                    use_registers = scored = true;
+                    best = cost;
+                    reg_block = B;
+                    reg_rounds = r;
+                    reg_group = G;
+                }
+            }
+    }
+    if (reg_possible && !scored) {
         std::vector<int> group_tries;
         if (params->envs_per_group)
             group_tries.push_back(params->envs_per_group);
@@ -389,16 +430,12 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     // together; a requested block size makes one class.
     std::vector<int> mesh_block((size_t)num_meshes, block), mesh_class((size_t)num_meshes, 0);
     if (use_registers) {
-        int lds_cu = 0;
-        HIP_TRY(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
-                                      device));
-        lds_cu = std::max(lds_cu, lds_limit);
         const int G = reg_group;
         std::vector<std::pair<int, int>> keys;
         for (int32_t m = 0; m < num_meshes; ++m) {
             const PreparedMesh &pm = b->meshes[(size_t)m];
             int B = block;
-            if (params->block_size == 0) {
+            if (params->block_size == 0 && !scored) {
                 for (int cand : {256, 512, 1024}) {
                     int r = count_rounds(pm, cand, G);
                     r += r % 2;
