@@ -35,6 +35,10 @@ randomly initialised policy network standing in for the RL agent.  One step:
    the prediction, the Gauss-Seidel iterations (edges, tetrahedra, tool
    contacts: ``oracle_iterate``) each followed by the dragging constraint of
    the held particle (``oracle_project_drag``), and the velocity update.
+   With ``learned`` (``RlLearned``) each substep follows the learned warm
+   start of ``oracle.run_env_learned`` instead: the corrector's correction
+   added to the prediction, the minimum sweeps, the residual check with the
+   stall rule, the fallback sweeps (every sweep followed by the drag).
 """
 from __future__ import annotations
 
@@ -130,6 +134,16 @@ def move_tools(tools, actions, rl: RlParams, dt):
 
 
 @dataclass
+class RlLearned:
+    """The learned warm start's settings (see ``oracle.run_env_learned``)."""
+    corrector: object            # (x_prev, v_start, x_hat, nbr) -> [V, 3], or None
+    min_iterations: int
+    max_iterations: int
+    threshold: float
+    stall_ratio: float = 0.0
+
+
+@dataclass
 class RlResult:
     x: np.ndarray                # [V][3] after the last step
     v: np.ndarray
@@ -138,6 +152,7 @@ class RlResult:
     obs: np.ndarray              # [steps][64]
     actions: np.ndarray          # [steps][7]
     select_margin: np.ndarray    # [steps] relative gap of the grasp choice (inf: no choice made)
+    iterations: np.ndarray = None  # [steps][substeps] sweeps (learned runs)
 
 
 def _select_margin(x, w, point, radius):
@@ -154,8 +169,10 @@ def _select_margin(x, w, point, radius):
 
 
 def run_env_rl(mesh: OracleMesh, compliance, params: OracleParams, rl: RlParams, net: PolicyNet,
-               tools0, target, num_steps, x0=None, v0=None, grasped0=-1) -> RlResult:
+               tools0, target, num_steps, x0=None, v0=None, grasped0=-1,
+               learned: RlLearned = None) -> RlResult:
     """Advance one environment by ``num_steps`` RL steps (module docstring)."""
+    from . import warmstart as ws
     lib = _load()
     if params.num_tools != TOOLS:
         raise ValueError("the RL step has two tools")
@@ -184,6 +201,26 @@ def run_env_rl(mesh: OracleMesh, compliance, params: OracleParams, rl: RlParams,
     out_obs = np.zeros((num_steps, OBS))
     out_act = np.zeros((num_steps, ACTIONS))
     margin = np.full(num_steps, np.inf)
+    its = np.zeros((num_steps, params.substeps), np.int32)
+    nbr = ws.axis_neighbours(mesh.rest) if learned is not None and learned.corrector else None
+    r2 = np.zeros(2)
+
+    def sweep(centres, g, point):
+        lib.oracle_iterate(_dp(x), _dp(mesh.w), E, _ip(edges), _dp(rlen), _dp(rv),
+                           _ip(tets), len(eptr) - 1, _ip(eptr),
+                           _ip(eorder if eorder.size else np.zeros(1, np.int32)),
+                           len(tptr) - 1, _ip(tptr),
+                           _ip(torder if torder.size else np.zeros(1, np.int32)),
+                           atd, atv, _dp(lam), V, TOOLS, _dp(centres), _dp(radius),
+                           _ip(cand), ncand)
+        if g >= 0:
+            lib.oracle_project_drag(_dp(x), _dp(mesh.w), g, _dp(point))
+
+    def residual():
+        lib.oracle_residual(_dp(x), E, _ip(edges), _dp(rlen), T, _ip(tets), _dp(rv), atd, atv,
+                            _dp(lam), _dp(r2))
+        return float(r2[0])
+
     for step in range(num_steps):
         o = observe(x, mesh.rest, tools, target, g, rl.tracked, rl.obs_scale, rl.obs_origin)
         a = policy(net, o)
@@ -203,18 +240,34 @@ def run_env_rl(mesh: OracleMesh, compliance, params: OracleParams, rl: RlParams,
                                              _dp(np.ascontiguousarray(centres[t])),
                                              float(radius[t]), _ip(row))
             cand[t] = row
-        for _ in range(params.substeps):
+        for sub in range(params.substeps):
+            v_start = v.copy()
             lib.oracle_predict(V, _dp(mesh.w), h, _dp(grav), _dp(x), _dp(v), _dp(x_prev))
             lam[:] = 0.0
-            for _ in range(params.iterations):
-                lib.oracle_iterate(_dp(x), _dp(mesh.w), E, _ip(edges), _dp(rlen), _dp(rv),
-                                   _ip(tets), len(eptr) - 1, _ip(eptr),
-                                   _ip(eorder if eorder.size else np.zeros(1, np.int32)),
-                                   len(tptr) - 1, _ip(tptr),
-                                   _ip(torder if torder.size else np.zeros(1, np.int32)),
-                                   atd, atv, _dp(lam), V, TOOLS, _dp(centres), _dp(radius),
-                                   _ip(cand), ncand)
-                if g >= 0:
-                    lib.oracle_project_drag(_dp(x), _dp(mesh.w), g, _dp(point))
+            if learned is None:
+                for _ in range(params.iterations):
+                    sweep(centres, g, point)
+                its[step, sub] = params.iterations
+            else:
+                if learned.corrector is not None:
+                    x += learned.corrector(x_prev, v_start, x, nbr)
+                n_it = 0
+                lo, hi = learned.min_iterations, learned.max_iterations
+                stall_check = learned.stall_ratio > 0.0 and lo >= 1 and hi > lo
+                before = np.nan
+                for _ in range(lo):
+                    if stall_check and n_it == lo - 1:
+                        before = residual()
+                    sweep(centres, g, point)
+                    n_it += 1
+                if hi > lo:
+                    rms = residual()
+                    go_on = rms > learned.threshold
+                    if go_on and stall_check:
+                        go_on = rms <= learned.stall_ratio * before
+                    while go_on and n_it < hi:
+                        sweep(centres, g, point)
+                        n_it += 1
+                its[step, sub] = n_it
             lib.oracle_velocity(V, h, _dp(x), _dp(x_prev), _dp(v))
-    return RlResult(x, v, out_tools, out_g, out_obs, out_act, margin)
+    return RlResult(x, v, out_tools, out_g, out_obs, out_act, margin, its)

@@ -281,3 +281,48 @@ def test_rl_generators():
     again, _ = W.rl_start(5, 3, env_ids=[10, 11, 12, 13, 14])
     assert np.array_equal(again, tools[10:15])
     assert W.rl_policy_params(0).size == R.NUM_PARAMS
+
+
+# ------------------------------------------------------------ learned warm start inside the step
+def grasping_net():
+    """Grasper up at half speed and closed; probe still."""
+    return constant_net(np.array([0, 0, 0.5, 0, 0, 0, 1.0], np.float32))
+
+
+@pytest.mark.parametrize("lo,hi,threshold,expect", [(3, 3, np.inf, 3), (2, 6, np.inf, 2),
+                                                    (2, 6, -1.0, 6)])
+def test_learned_driver_without_corrector_is_the_plain_step(scene, lo, hi, threshold, expect):
+    m, om, rl, params, tools0, target = scene
+    net = grasping_net()
+    learned = R.RlLearned(None, lo, hi, threshold)
+    got = R.run_env_rl(om, (1e-6, 1e-7), params, rl, net, tools0, target, 4, learned=learned)
+    p = oracle.OracleParams(params.dt, params.substeps, expect, params.gravity, 2,
+                            params.tool_radius)
+    plain = R.run_env_rl(om, (1e-6, 1e-7), p, rl, net, tools0, target, 4)
+    assert np.all(got.iterations == expect)
+    assert np.array_equal(got.x, plain.x) and np.array_equal(got.v, plain.v)
+    assert np.array_equal(got.grasped, plain.grasped) and np.all(got.grasped >= 0)
+
+
+def test_learned_driver_stall_rule_and_corrector(scene):
+    m, om, rl, params, tools0, target = scene
+    net = grasping_net()
+    # a corrector that moves nothing changes nothing
+    zero = R.RlLearned(lambda xp, vs, xh, nbr: np.zeros_like(xh), 2, 6, -1.0, stall_ratio=0.9)
+    none = R.RlLearned(None, 2, 6, -1.0, stall_ratio=0.9)
+    a = R.run_env_rl(om, (1e-6, 1e-7), params, rl, net, tools0, target, 4, learned=zero)
+    b = R.run_env_rl(om, (1e-6, 1e-7), params, rl, net, tools0, target, 4, learned=none)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.iterations, b.iterations)
+    assert set(np.unique(b.iterations)) <= {2, 6}
+    # a stall ratio near 0 stops every substep at the minimum (no sweep lowers
+    # the residual a trillionfold); with ratio 1 only the sweeps that raised
+    # the residual stop, and the grasper's drag makes some do
+    least = R.run_env_rl(om, (1e-6, 1e-7), params, rl, net, tools0, target, 2,
+                         learned=R.RlLearned(None, 2, 6, -1.0, stall_ratio=1e-12))
+    one = R.run_env_rl(om, (1e-6, 1e-7), params, rl, net, tools0, target, 2,
+                       learned=R.RlLearned(None, 2, 6, -1.0, stall_ratio=1.0))
+    assert np.all(least.iterations == 2)
+    assert set(np.unique(one.iterations)) == {2, 6}
+    # the held particle still ends every step on the dragging point
+    g = int(b.grasped[-1])
+    np.testing.assert_allclose(b.x[g], b.tools[-1, 0] + rl.grasp_offset, atol=1e-15)
