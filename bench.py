@@ -271,6 +271,133 @@ def mesh_sizes(xpbd, m):
             int((m.inv_mass > 0).sum()))
 
 
+def rl_learned_leg(args, make_batch, policy, rp, S, I):
+    """The learned warm start inside the RL-style step: train the network on
+    substeps recorded from RL steps of a separate training batch (untimed),
+    then time RL steps with the learned warm start against plain RL steps
+    from the same state (positions, velocities, tool centres, grasps)."""
+    import numpy as np
+    import torch
+
+    from paper_2503_18616_amd import warmstart as trainer
+    from paper_2503_18616_amd import workloads as W
+    from paper_2503_18616_amd import xpbd
+
+    def rl_state(n, seed):
+        tools0, target = W.rl_start(n, seed)
+        return (torch.from_numpy(tools0).cuda(), torch.full((n,), -1, dtype=torch.int32,
+                                                             device="cuda"),
+                torch.from_numpy(target).cuda())
+
+    def snapshot(b, tp, gr):
+        return b.positions(), b.velocities(), tp.clone(), gr.clone()
+
+    def restore(b, tp, gr, snap):
+        b.write(xpbd.FIELD_POS, snap[0])
+        b.write(xpbd.FIELD_VEL, snap[1])
+        tp.copy_(snap[2])
+        gr.copy_(snap[3])
+
+    t0 = time.perf_counter()
+    warm, n_rec = 20, args.train_records
+    tw = W.rl_workload(args.train_envs, seed=1)
+    NP = args.train_envs * tw.meshes[0].num_vertices
+    subs = [k % S for k in range(n_rec)]
+
+    def record(b, net, tp, gr, tg):
+        feats = torch.zeros((n_rec * NP, xpbd.MLP_FEATURE_STRIDE), dtype=torch.bfloat16,
+                            device="cuda")
+        targets = torch.zeros((n_rec * NP, 4), dtype=torch.float32, device="cuda")
+        for k, sub in enumerate(subs):
+            b.rl_step_learned(policy, rp, net, 1, tp, gr, tg, I, I, np.inf,
+                              apply_correction=False, record_substep=sub,
+                              record_features=feats[k * NP:(k + 1) * NP],
+                              record_targets=targets[k * NP:(k + 1) * NP])
+        return feats, targets
+
+    with make_batch(tw, 0) as tb:
+        tp, gr, tg = rl_state(args.train_envs, 1)
+        for _ in range(warm):
+            tb.rl_step(policy, rp, 1, tp, gr, tg)
+        snap = snapshot(tb, tp, gr)
+        with xpbd.Mlp(None, None, np.ones(xpbd.MLP_FEATURES), None, np.ones(3)) as pilot:
+            f0, t0_ = record(tb, pilot, tp, gr, tg)
+        norm = trainer.normalisation(f0, t0_)
+        del f0, t0_
+        restore(tb, tp, gr, snap)
+        net = xpbd.Mlp(trainer.he_init(0), *norm)
+        feats, targets = record(tb, net, tp, gr, tg)
+    rows = int((feats[:, 31].float() > 0).sum())
+    losses = trainer.train(net, feats, targets, args.train_steps)
+    del feats, targets
+    train_s = time.perf_counter() - t0
+    progress(f"RL learned warm start: trained in {train_s:.1f} s")
+
+    N = args.envs or 8192
+    steps = args.learned_steps
+    wl = W.rl_workload(N, seed=0)
+    its = torch.zeros(steps * S * N, dtype=torch.int32, device="cuda")
+    with make_batch(wl, xpbd.F_RESIDUAL) as pb, make_batch(wl, xpbd.F_RESIDUAL) as lb:
+        tp, gr, tg = rl_state(N, 0)
+        warm_res = []
+        for _ in range(args.warmup):
+            pb.rl_step(policy, rp, 1, tp, gr, tg)
+            warm_res.append(pb.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)[:, 0].copy())
+        threshold = float(np.quantile(np.concatenate(warm_res), args.learned_quantile))
+        snap = snapshot(pb, tp, gr)
+        ltp, lgr = tp.clone(), gr.clone()
+        restore(lb, ltp, lgr, snap)
+        stream = torch.cuda.current_stream()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for s in range(steps):
+            lb.rl_step_learned(policy, rp, net, 1, ltp, lgr, tg, args.learned_min, I, threshold,
+                               iterations=its[s * S * N:(s + 1) * S * N],
+                               stall_ratio=args.learned_stall)
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+        start.record(stream)
+        for s in range(steps):
+            pb.rl_step(policy, rp, 1, tp, gr, tg)
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms_plain = start.elapsed_time(end)
+        # the residual of every step (last substep), untimed, from the same state
+        r_l, r_p = [], []
+        for b, out in ((lb, r_l), (pb, r_p)):
+            restore(b, tp, gr, snap)
+            for s in range(steps):
+                if b is lb:
+                    b.rl_step_learned(policy, rp, net, 1, tp, gr, tg, args.learned_min, I,
+                                      threshold, stall_ratio=args.learned_stall)
+                else:
+                    b.rl_step(policy, rp, 1, tp, gr, tg)
+                out.append(b.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)[:, 0].copy())
+        r_l, r_p = np.concatenate(r_l), np.concatenate(r_p)
+    net.close()
+    it = its.cpu().numpy()
+    return {"value": N * steps * S / (ms / 1e3), "unit": "env-substeps/s",
+            "ms_per_step": ms / steps, "steps": steps,
+            "plain_value_same_steps": N * steps * S / (ms_plain / 1e3),
+            "min_iterations": args.learned_min, "max_iterations": I,
+            "stall_ratio": args.learned_stall, "threshold": threshold,
+            "threshold_rule": f"plain {I}-sweep residual, {args.learned_quantile:g} quantile "
+                              f"over {args.warmup} warm-up steps",
+            "sweeps_mean": float(it.mean()),
+            "fallback_fraction": float((it > args.learned_min).mean()),
+            "residual_rms_mean": float(r_l.mean()),
+            "plain_residual_rms_mean": float(r_p.mean()),
+            "residual_matched": bool(r_l.mean() <= r_p.mean()),
+            "training": {"envs": args.train_envs, "recorded_substeps": n_rec,
+                         "free_rows": rows, "adam_steps": args.train_steps,
+                         "loss_first": float(np.mean(losses[:5])),
+                         "loss_last": float(np.mean(losses[-50:])), "seconds": train_s},
+            "network": "27-128-128-3 ReLU, bf16 MFMA, fp32 accumulate"}
+
+
 def rl_bench(args):
     """The RL-style step (include/xpbd_rl.h): per step and environment the
     observations, the 64-256-256-7 policy, the tool motion, the grasp and the
@@ -325,6 +452,16 @@ def rl_bench(args):
     holding = int((gr >= 0).sum())
     resid = batch.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)
     batch.close()
+
+    learned = None
+    if not args.no_learned and args.variant in (0, 1) and not args.group:
+        def make(w, flags):
+            p = xpbd.make_params(w.dt, S, I, w.gravity, 2, w.tool_radius, flags=flags,
+                                 block_size=args.block, solver_variant=xpbd.VARIANT_REGISTERS,
+                                 colour_packing=args.packing, envs_per_group=1)
+            return xpbd.Batch([(m.rest_pos, m.inv_mass, m.tets)], w.env_mesh, w.compliance, p,
+                              stream=stream.cuda_stream)
+        learned = rl_learned_leg(args, make, policy, rp, S, I)
     policy.close()
 
     step_s = ms / 1e3 / args.steps
@@ -381,7 +518,7 @@ def rl_bench(args):
                    "holding_at_end": holding,
                    "residual_rms_mean": float(resid[:, 0].mean()),
                    "residual_max": float(resid[:, 1].max())},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "learned": learned,
     }
     print(json.dumps(out), flush=True)
 

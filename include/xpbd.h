@@ -103,10 +103,10 @@ typedef struct {
     float tool_radius[2];/* m, > 0 for each used tool */
     uint32_t flags;      /* XPBD_F_* */
     int32_t block_size;  /* threads per workgroup: 0 = chosen by the library (register
-                            variant, one mesh with envs_per_group 0 as well: the block
-                            of 128 .. 1024 and the environments per workgroup whose
-                            rounds, times the passes of workgroups over the CUs at the
-                            occupancy their waves and LDS allow, are fewest; several
+                            variant, one mesh: the block of 128 .. 1024 and, unless
+                            envs_per_group fixes it, the environments per workgroup
+                            whose rounds, times the passes of workgroups over the CUs
+                            at the occupancy their waves and LDS allow, are fewest; several
                             meshes: per mesh, the smallest of 256, 512, 1024 whose rounds
                             fit; meshes of equal block and LDS tier form a size class,
                             and the classes run concurrently), else a multiple of 64 in
@@ -116,7 +116,7 @@ typedef struct {
     int32_t envs_per_group; /* register variant: environments that share one workgroup,
                                its LDS and its rounds (lanes of a round may belong to
                                different environments): 0 = chosen by the library (see
-                               block_size; 1 unless both are left to it for one mesh),
+                               block_size; 1 for several meshes),
                                else 1 or 2.  Environments are grouped per mesh in index
                                order; the LDS variant always uses 1. */
     int32_t tool_shape;     /* XPBD_TOOL_*: spheres against particles, or capsules against

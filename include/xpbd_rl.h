@@ -47,6 +47,7 @@
 #include <stdint.h>
 
 #include "xpbd.h"
+#include "xpbd_learned.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -104,6 +105,22 @@ void xpbd_policy_destroy(xpbd_policy *p);
 xpbd_status xpbd_rl_step(xpbd_batch *b, const xpbd_policy *policy, const xpbd_rl_params *params,
                          int32_t num_steps, float *tool_pos, int32_t *grasped,
                          const float *target, float *obs, float *actions);
+
+/*
+ * xpbd_rl_step with the learned warm start (include/xpbd_learned.h): the
+ * simulation step of every RL step is one step of xpbd_step_learned with the
+ * network net and the settings *learned (correction, minimum sweeps, residual
+ * threshold, stall ratio, fallback sweeps), the grasper included.
+ * learned->iterations (device int32, or NULL) receives
+ * [num_steps][substeps][N] sweep counts; a recording (record_substep >= 0)
+ * holds the last RL step's.  Needs, besides xpbd_rl_step's, what
+ * xpbd_step_learned needs (one environment per workgroup, one size class).
+ */
+xpbd_status xpbd_rl_step_learned(xpbd_batch *b, const xpbd_policy *policy,
+                                 const xpbd_rl_params *params, const xpbd_mlp *net,
+                                 const xpbd_learned_params *learned, int32_t num_steps,
+                                 float *tool_pos, int32_t *grasped, const float *target,
+                                 float *obs, float *actions);
 
 #ifdef __cplusplus
 }

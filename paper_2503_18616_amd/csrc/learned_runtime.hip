@@ -10,6 +10,7 @@
 
 #include "../../include/xpbd_learned.h"
 #include "batch.h"
+#include "learned_step.h"
 #include "mesh_setup.h"
 #include "mlp_device.h"
 #include "runtime_util.h"
@@ -232,31 +233,12 @@ xpbd_status xpbd_step_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
         return fail(XPBD_E_ARG, "batch and params are required");
     if (num_steps < 0)
         return fail(XPBD_E_ARG, "num_steps must be >= 0");
-    if (!b->register_variant || b->envs_per_group != 1 || b->classes.size() != 1 ||
-        b->params.tool_shape != XPBD_TOOL_SPHERE)
-        return fail(XPBD_E_CAPACITY, "the learned step needs the register variant with one "
-                    "environment per workgroup and one size class (set block_size for meshes "
-                    "of different sizes)");
-    if (lp->min_iterations < 0 || lp->max_iterations < lp->min_iterations)
-        return fail(XPBD_E_ARG, "need 0 <= min_iterations <= max_iterations");
-    if (!std::isfinite(lp->threshold) && !std::isinf(lp->threshold))
-        return fail(XPBD_E_ARG, "threshold must not be NaN");
-    if (!(lp->stall_ratio >= 0.0f && lp->stall_ratio <= 1.0f))
-        return fail(XPBD_E_ARG, "stall_ratio must be in [0, 1] (got %g)", (double)lp->stall_ratio);
-    const bool record = lp->record_substep >= 0;
-    if ((lp->apply_correction || record) && !net)
-        return fail(XPBD_E_ARG, "the correction and the recording need a network");
-    if (record && (lp->record_substep >= b->params.substeps || !lp->record_features ||
-                   !lp->record_targets || !is_device_pointer(lp->record_features) ||
-                   !is_device_pointer(lp->record_targets)))
-        return fail(XPBD_E_ARG, "record_substep must name a substep and both record buffers "
-                    "must be device memory");
-    if (lp->iterations && !is_device_pointer(lp->iterations))
-        return fail(XPBD_E_ARG, "iterations must be device memory");
+    xpbd_status st = xpbd::check_learned(b, net, lp);
+    if (st != XPBD_OK)
+        return st;
     if (num_steps == 0)
         return XPBD_OK;
     const int tools = b->params.num_tools;
-    const int64_t NP = b->total_particles;
     const float *tools_dev = nullptr;
     if (tools > 0) {
         if (!tool_pos)
@@ -279,6 +261,48 @@ xpbd_status xpbd_step_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
             tools_dev = b->tool_staging;
         }
     }
+    return xpbd::run_learned(b, net, num_steps, tools_dev, lp, nullptr);
+}
+
+}  // extern "C"
+
+// Checks of a learned step's batch and parameters (before any device work).
+xpbd_status xpbd::check_learned(const xpbd_batch *b, const xpbd_mlp *net,
+                                const xpbd_learned_params *lp)
+{
+    if (!b->register_variant || b->envs_per_group != 1 || b->classes.size() != 1 ||
+        b->params.tool_shape != XPBD_TOOL_SPHERE)
+        return fail(XPBD_E_CAPACITY, "the learned step needs the register variant with one "
+                    "environment per workgroup and one size class (set block_size for meshes "
+                    "of different sizes)");
+    if (lp->min_iterations < 0 || lp->max_iterations < lp->min_iterations)
+        return fail(XPBD_E_ARG, "need 0 <= min_iterations <= max_iterations");
+    if (!std::isfinite(lp->threshold) && !std::isinf(lp->threshold))
+        return fail(XPBD_E_ARG, "threshold must not be NaN");
+    if (!(lp->stall_ratio >= 0.0f && lp->stall_ratio <= 1.0f))
+        return fail(XPBD_E_ARG, "stall_ratio must be in [0, 1] (got %g)", (double)lp->stall_ratio);
+    const bool record = lp->record_substep >= 0;
+    if ((lp->apply_correction || record) && !net)
+        return fail(XPBD_E_ARG, "the correction and the recording need a network");
+    if (record && (lp->record_substep >= b->params.substeps || !lp->record_features ||
+                   !lp->record_targets || !is_device_pointer(lp->record_features) ||
+                   !is_device_pointer(lp->record_targets)))
+        return fail(XPBD_E_ARG, "record_substep must name a substep and both record buffers "
+                    "must be device memory");
+    if (lp->iterations && !is_device_pointer(lp->iterations))
+        return fail(XPBD_E_ARG, "iterations must be device memory");
+    return XPBD_OK;
+}
+
+// num_steps learned steps with the tool poses in device memory; grasp is null
+// or names the RL step's grasp state.
+xpbd_status xpbd::run_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_steps,
+                              const float *tools_dev, const xpbd_learned_params *lp,
+                              const GraspArgs *grasp)
+{
+    const int tools = b->params.num_tools;
+    const int64_t NP = b->total_particles;
+    const bool record = lp->record_substep >= 0;
     xpbd_status st;
     if (!b->learned_xhat && ((st = b->alloc(reinterpret_cast<void **>(&b->learned_xhat),
                                             sizeof(float) * 3 * (size_t)NP)) ||
@@ -327,6 +351,12 @@ xpbd_status xpbd_step_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
         a.tool_radius2[t] = r * r;
         const float reach = 2.0f * r;
         a.tool_reach2[t] = reach * reach;
+    }
+    if (grasp) {
+        a.grasp = grasp->state;
+        for (int k = 0; k < 3; ++k)
+            a.grasp_offset[k] = grasp->offset[k];
+        a.grasp_radius2 = grasp->radius * grasp->radius;
     }
     xpbd::LearnedArgs L;
     std::memset(&L, 0, sizeof L);
@@ -378,5 +408,3 @@ xpbd_status xpbd_step_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
     b->residual_valid = b->residual_valid || resid;
     return XPBD_OK;
 }
-
-}  // extern "C"

@@ -8,6 +8,7 @@
 
 #include "../../include/xpbd_rl.h"
 #include "batch.h"
+#include "learned_step.h"
 #include "rl_device.h"
 #include "runtime_util.h"
 #include "xpbd_device.h"
@@ -64,6 +65,79 @@ void cut(const float *w, int rows, int cols, bool permuted, uint16_t *out)
                     const size_t at = (((size_t)t * blocks + kb) * 64 + lane) * 8 + i;
                     out[at] = row < rows ? to_bf16(w[(size_t)row * cols + 32 * kb + slot]) : 0;
                 }
+}
+
+// Checks shared by the RL entry points (host only).
+xpbd_status check_rl(const xpbd_batch *b, const xpbd_policy *policy, const xpbd_rl_params *params,
+                     int32_t num_steps, const float *tool_pos, const int32_t *grasped,
+                     const float *target, const float *obs, const float *actions)
+{
+    if (!b || !policy || !params)
+        return fail(XPBD_E_ARG, "batch, policy and params must not be NULL");
+    if (num_steps < 0)
+        return fail(XPBD_E_ARG, "num_steps must be >= 0 (got %d)", num_steps);
+    if (b->params.num_tools != 2 || b->params.tool_shape != XPBD_TOOL_SPHERE)
+        return fail(XPBD_E_ARG, "the RL step needs a batch with two sphere tools");
+    if (!b->register_variant)
+        return fail(XPBD_E_ARG, "the RL step needs the register-multiplier solver variant");
+    if (!tool_pos || !grasped || !target)
+        return fail(XPBD_E_ARG, "tool_pos, grasped and target must not be NULL");
+    const void *device_ptrs[5] = {tool_pos, grasped, target, obs, actions};
+    for (const void *q : device_ptrs)
+        if (q && !is_device_pointer(q))
+            return fail(XPBD_E_ARG, "tool_pos, grasped, target, obs and actions must be device memory");
+    const xpbd_rl_params &P = *params;
+    if (!(std::isfinite(P.grasp_radius) && P.grasp_radius > 0.0f))
+        return fail(XPBD_E_ARG, "grasp_radius must be finite and > 0");
+    if (!(std::isfinite(P.max_speed) && P.max_speed >= 0.0f) || !std::isfinite(P.obs_scale))
+        return fail(XPBD_E_ARG, "max_speed must be finite and >= 0, obs_scale finite");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(P.grasp_offset[k]) || !std::isfinite(P.obs_origin[k]) ||
+            !std::isfinite(P.box_lo[k]) || !std::isfinite(P.box_hi[k]) ||
+            !(P.box_lo[k] <= P.box_hi[k]))
+            return fail(XPBD_E_ARG, "offsets, origin and box must be finite with box_lo <= box_hi");
+    for (int j = 0; j < XPBD_RL_TRACKED; ++j)
+        for (const auto &m : b->meshes)
+            if (P.tracked[j] < 0 || P.tracked[j] >= m.num_vertices)
+                return fail(XPBD_E_ARG, "tracked[%d] = %d is outside a mesh of %d particles", j,
+                            P.tracked[j], m.num_vertices);
+    return XPBD_OK;
+}
+
+xpbd::RlArgs rl_args(const xpbd_batch *b, const xpbd_rl_params &P, float *tool_pos,
+                     int32_t *grasped, const float *target)
+{
+    xpbd::RlArgs r;
+    std::memset(&r, 0, sizeof r);
+    r.meshes = b->meshes_dev;
+    r.envs = b->envs_dev;
+    r.pos = b->pos;
+    r.total_particles = b->total_particles;
+    r.num_envs = b->num_envs;
+    r.tool_pos = tool_pos;
+    r.grasp = grasped;
+    r.target = target;
+    for (int j = 0; j < XPBD_RL_TRACKED; ++j)
+        r.tracked[j] = P.tracked[j];
+    r.obs_scale = P.obs_scale;
+    r.max_speed = P.max_speed;
+    r.dt = b->params.dt;
+    for (int k = 0; k < 3; ++k) {
+        r.obs_origin[k] = P.obs_origin[k];
+        r.box_lo[k] = P.box_lo[k];
+        r.box_hi[k] = P.box_hi[k];
+    }
+    return r;
+}
+
+xpbd::GraspArgs grasp_args(const xpbd_rl_params &P, int32_t *grasped)
+{
+    xpbd::GraspArgs g;
+    g.state = grasped;
+    g.radius = P.grasp_radius;
+    for (int k = 0; k < 3; ++k)
+        g.offset[k] = P.grasp_offset[k];
+    return g;
 }
 
 }  // namespace
@@ -133,70 +207,49 @@ xpbd_status xpbd_rl_step(xpbd_batch *b, const xpbd_policy *policy, const xpbd_rl
                          const float *target, float *obs, float *actions)
 {
     g_error.clear();
-    if (!b || !policy || !params)
-        return fail(XPBD_E_ARG, "batch, policy and params must not be NULL");
-    if (num_steps < 0)
-        return fail(XPBD_E_ARG, "num_steps must be >= 0 (got %d)", num_steps);
-    if (b->params.num_tools != 2 || b->params.tool_shape != XPBD_TOOL_SPHERE)
-        return fail(XPBD_E_ARG, "the RL step needs a batch with two sphere tools");
-    if (!b->register_variant)
-        return fail(XPBD_E_ARG, "the RL step needs the register-multiplier solver variant");
-    if (!tool_pos || !grasped || !target)
-        return fail(XPBD_E_ARG, "tool_pos, grasped and target must not be NULL");
-    const float *device_ptrs[5] = {tool_pos, reinterpret_cast<const float *>(grasped), target, obs,
-                                   actions};
-    for (const float *q : device_ptrs)
-        if (q && !is_device_pointer(q))
-            return fail(XPBD_E_ARG, "tool_pos, grasped, target, obs and actions must be device memory");
-    const xpbd_rl_params &P = *params;
-    if (!(std::isfinite(P.grasp_radius) && P.grasp_radius > 0.0f))
-        return fail(XPBD_E_ARG, "grasp_radius must be finite and > 0");
-    if (!(std::isfinite(P.max_speed) && P.max_speed >= 0.0f) || !std::isfinite(P.obs_scale))
-        return fail(XPBD_E_ARG, "max_speed must be finite and >= 0, obs_scale finite");
-    for (int k = 0; k < 3; ++k)
-        if (!std::isfinite(P.grasp_offset[k]) || !std::isfinite(P.obs_origin[k]) ||
-            !std::isfinite(P.box_lo[k]) || !std::isfinite(P.box_hi[k]) ||
-            !(P.box_lo[k] <= P.box_hi[k]))
-            return fail(XPBD_E_ARG, "offsets, origin and box must be finite with box_lo <= box_hi");
-    for (int j = 0; j < XPBD_RL_TRACKED; ++j)
-        for (const auto &m : b->meshes)
-            if (P.tracked[j] < 0 || P.tracked[j] >= m.num_vertices)
-                return fail(XPBD_E_ARG, "tracked[%d] = %d is outside a mesh of %d particles", j,
-                            P.tracked[j], m.num_vertices);
-    if (num_steps == 0)
-        return XPBD_OK;
-
-    xpbd::RlArgs r;
-    std::memset(&r, 0, sizeof r);
-    r.meshes = b->meshes_dev;
-    r.envs = b->envs_dev;
-    r.pos = b->pos;
-    r.total_particles = b->total_particles;
-    r.num_envs = b->num_envs;
-    r.tool_pos = tool_pos;
-    r.grasp = grasped;
-    r.target = target;
-    for (int j = 0; j < XPBD_RL_TRACKED; ++j)
-        r.tracked[j] = P.tracked[j];
-    r.obs_scale = P.obs_scale;
-    r.max_speed = P.max_speed;
-    r.dt = b->params.dt;
-    for (int k = 0; k < 3; ++k) {
-        r.obs_origin[k] = P.obs_origin[k];
-        r.box_lo[k] = P.box_lo[k];
-        r.box_hi[k] = P.box_hi[k];
-    }
-    xpbd::GraspArgs grasp;
-    grasp.state = grasped;
-    grasp.radius = P.grasp_radius;
-    for (int k = 0; k < 3; ++k)
-        grasp.offset[k] = P.grasp_offset[k];
+    xpbd_status st = check_rl(b, policy, params, num_steps, tool_pos, grasped, target, obs, actions);
+    if (st != XPBD_OK || num_steps == 0)
+        return st;
+    xpbd::RlArgs r = rl_args(b, *params, tool_pos, grasped, target);
+    const xpbd::GraspArgs grasp = grasp_args(*params, grasped);
     const size_t N = (size_t)b->num_envs;
     for (int32_t step = 0; step < num_steps; ++step) {
         r.obs = obs ? obs + (size_t)step * N * XPBD_RL_OBS : nullptr;
         r.actions = actions ? actions + (size_t)step * N * XPBD_RL_ACTIONS : nullptr;
         HIP_TRY(xpbd::launch_rl_policy(r, policy->d, b->stream));
-        const xpbd_status st = xpbd::run_step(b, 1, tool_pos, &grasp);
+        st = xpbd::run_step(b, 1, tool_pos, &grasp);
+        if (st != XPBD_OK)
+            return st;
+    }
+    return XPBD_OK;
+}
+
+xpbd_status xpbd_rl_step_learned(xpbd_batch *b, const xpbd_policy *policy,
+                                 const xpbd_rl_params *params, const xpbd_mlp *net,
+                                 const xpbd_learned_params *learned, int32_t num_steps,
+                                 float *tool_pos, int32_t *grasped, const float *target,
+                                 float *obs, float *actions)
+{
+    g_error.clear();
+    if (!learned)
+        return fail(XPBD_E_ARG, "learned params must not be NULL");
+    xpbd_status st = check_rl(b, policy, params, num_steps, tool_pos, grasped, target, obs, actions);
+    if (st != XPBD_OK)
+        return st;
+    if ((st = xpbd::check_learned(b, net, learned)) != XPBD_OK || num_steps == 0)
+        return st;
+    xpbd::RlArgs r = rl_args(b, *params, tool_pos, grasped, target);
+    const xpbd::GraspArgs grasp = grasp_args(*params, grasped);
+    const size_t N = (size_t)b->num_envs;
+    xpbd_learned_params lp = *learned;
+    for (int32_t step = 0; step < num_steps; ++step) {
+        r.obs = obs ? obs + (size_t)step * N * XPBD_RL_OBS : nullptr;
+        r.actions = actions ? actions + (size_t)step * N * XPBD_RL_ACTIONS : nullptr;
+        lp.iterations = learned->iterations
+                            ? learned->iterations + (size_t)step * b->params.substeps * N
+                            : nullptr;
+        HIP_TRY(xpbd::launch_rl_policy(r, policy->d, b->stream));
+        st = xpbd::run_learned(b, net, 1, tool_pos, &lp, &grasp);
         if (st != XPBD_OK)
             return st;
     }

@@ -1363,8 +1363,10 @@ __device__ __forceinline__ void eval_round(const float4 *xw, const RoundTables &
 // One substep of one environment from the predicted positions in L.xhat
 // (start-of-substep positions in A.pos): min_iterations sweeps, the residual
 // RMS, and the remaining sweeps up to max_iterations when it exceeds the
-// threshold; then v = (x - x_prev) / h and the write-back.
-template <int NB>
+// threshold; then v = (x - x_prev) / h and the write-back.  GRASP: tool 0
+// drags the particle A.grasp names (taken at the first substep of a step, as
+// in xpbd_step_reg_kernel) after the contacts of every sweep.
+template <int NB, bool GRASP>
 __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, LearnedArgs L)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1438,6 +1440,53 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
     }
     const bool any_contact = block_any(cand != 0u, scratch + 32, wave, lane, num_waves);
 
+    // grasping (Sec. III-A.2): the held particle's slot (uniform; -1 for none);
+    // a closed grasper holding nothing takes, at the first substep of the
+    // step, the free particle closest to the dragging point strictly within
+    // reach on the start-of-step positions (key: squared distance bits, id)
+    int held = -1, owner = -1;
+    float3 drag = make_float3(0.f, 0.f, 0.f);
+    if constexpr (GRASP) {
+        int32_t *gs = reinterpret_cast<int32_t *>(smem + Lay.scratch + kRegScratchGrasp);
+        uint64_t *part = reinterpret_cast<uint64_t *>(smem + Lay.scratch + kRegScratchGrasp + 16);
+        drag = make_float3(tool0.x + A.grasp_offset[0], tool0.y + A.grasp_offset[1],
+                           tool0.z + A.grasp_offset[2]);
+        if (tid == 0) {
+            const int h = A.grasp[env];
+            const bool ok = h >= 0 && h < V && md.inv_mass[h] > 0.0f;
+            gs[0] = ok ? (int)md.slot_of[h] : -1;
+            gs[1] = h == -2 && L.first_substep ? 1 : 0;
+        }
+        __syncthreads();
+        if (gs[1]) {
+            uint64_t best = ~0ull;
+            for (int i = tid; i < V; i += B) {
+                const float4 p = make_float4(prev[i], prev[V + i], prev[2 * V + i], xw[i].w);
+                const float dx = p.x - drag.x, dy = p.y - drag.y, dz = p.z - drag.z;
+                const float d2 = dx * dx + dy * dy + dz * dz;
+                if (p.w > 0.0f && d2 < A.grasp_radius2) {
+                    const uint64_t key = (uint64_t)__float_as_uint(d2) << 32 | (uint32_t)md.id_of[i];
+                    best = key < best ? key : best;
+                }
+            }
+            best = wave_min_u64(best);
+            if (lane == 0)
+                part[wave] = best;
+            __syncthreads();
+            if (tid == 0) {
+                uint64_t m = ~0ull;
+                for (int w = 0; w < num_waves; ++w)
+                    m = part[w] < m ? part[w] : m;
+                const int id = m == ~0ull ? -1 : (int)(uint32_t)m;
+                gs[0] = id >= 0 ? (int)md.slot_of[id] : -1;
+                A.grasp[env] = id;
+            }
+            __syncthreads();
+        }
+        held = __builtin_amdgcn_readfirstlane(gs[0]);
+        owner = held >= 0 ? held % B : -1;
+    }
+
     RoundTables tab;
     tab.rr = (const XPBD_GLOBAL Record *)(uintptr_t)md.round_rec;
     tab.R = R;
@@ -1460,7 +1509,7 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
                 run_round<1>(xw, tab, r + 1, slot_b, active, tets, barriers, bank1, alpha_d1,
                              alpha_v1);
             }
-        if (any_contact) {
+        if (any_contact || (GRASP && held >= 0)) {
             for (int t = 0; t < tools; ++t) {
                 const float3 ct = t == 0 ? tool0 : tool1;
                 const float rt = t == 0 ? A.tool_radius[0] : A.tool_radius[1];
@@ -1468,6 +1517,15 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
                 for (int k = 0, i = tid; i < V; ++k, i += B)
                     if ((cand >> (16 * t + k)) & 1u)
                         project_contact(xw, i, ct.x, ct.y, ct.z, rt, rt2);
+            }
+            // the dragging constraint (k_s = 1): the held particle onto the
+            // dragging point, by its slot's owner after its own contacts
+            if (GRASP && tid == owner) {
+                float4 p = xw[held];
+                p.x = drag.x;
+                p.y = drag.y;
+                p.z = drag.z;
+                xw[held] = p;
             }
             __syncthreads();
         }
@@ -1858,7 +1916,7 @@ template <int NB>
 hipError_t launch_substep_variant(const StepArgs &args, const LearnedArgs &largs, int block,
                                   uint32_t lds_bytes, hipStream_t stream)
 {
-    auto kernel = xpbd_substep_reg_kernel<NB>;
+    auto kernel = args.grasp ? xpbd_substep_reg_kernel<NB, true> : xpbd_substep_reg_kernel<NB, false>;
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)lds_bytes);

@@ -293,12 +293,12 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     int lds_limit = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
 
-    // register-multiplier variant.  A batch of one mesh with block size and
-    // environments per workgroup both left to the library takes the (B, G) of
-    // B in {128, 256, 512, 1024}, G in {1, 2} that the occupancy model below
-    // rates fastest.  Otherwise: G as requested, else 1, then the smallest
-    // block of 256, 512 or 1024 threads (or the requested one) whose round
-    // schedule for G copies of every mesh fits the register banks.
+    // register-multiplier variant.  A batch of one mesh with the block size
+    // left to the library takes the (B, G) of B in {128, 256, 512, 1024} and G
+    // in {1, 2} (or the requested G) that the occupancy model below rates
+    // fastest.  Otherwise: G as requested, else 1, then the smallest block of
+    // 256, 512 or 1024 threads (or the requested one) whose round schedule for
+    // G copies of every mesh fits the register banks.
     bool use_registers = false;
     int reg_block = 0, reg_rounds = 0, reg_group = 1;
     bool scored = false;
@@ -315,8 +315,7 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         return fail(XPBD_E_CAPACITY, "capsule tools need the LDS or Jacobi variant");
     const bool reg_possible =
         params->solver_variant != XPBD_VARIANT_LDS && !jacobi && !capsules && pow2_block;
-    if (reg_possible && prepared.size() == 1 && params->block_size == 0 &&
-        params->envs_per_group == 0) {
+    if (reg_possible && prepared.size() == 1 && params->block_size == 0) {
         // Occupancy model: a round (a lane's constraint of one colour, then
         // the colour's barrier) costs about the same whatever B and G, and a
         // CU holds as many workgroups as its 16 resident waves of this kernel
@@ -327,6 +326,8 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         double best = 0.0;
         for (int B : {128, 256, 512, 1024})
             for (int G : {1, 2}) {
+                if (params->envs_per_group && G != params->envs_per_group)
+                    continue;
                 int r = count_rounds(pm, B, G);
                 r += r % 2;
                 const uint32_t lm = xpbd::reg_lds_layout(G * pm.num_vertices).total;

@@ -70,7 +70,7 @@ EXPORTED = ["xpbd_create_batch", "xpbd_step", "xpbd_read_state", "xpbd_write_sta
             "xpbd_prepare_mesh", "xpbd_mlp_create", "xpbd_mlp_get_params", "xpbd_mlp_set_params",
             "xpbd_mlp_forward", "xpbd_mlp_train_step", "xpbd_mlp_destroy", "xpbd_axis_neighbours",
             "xpbd_step_learned", "xpbd_autotune", "xpbd_surface_faces", "xpbd_policy_create",
-            "xpbd_policy_destroy", "xpbd_rl_step"]
+            "xpbd_policy_destroy", "xpbd_rl_step", "xpbd_rl_step_learned"]
 
 # learned warm start (include/xpbd_learned.h)
 MLP_FEATURES = 27
@@ -489,6 +489,12 @@ _lib.xpbd_rl_step.argtypes = [_V, _V, ctypes.POINTER(XpbdRlParams), ctypes.c_int
                               _V, _V]
 
 
+_lib.xpbd_rl_step_learned.restype = ctypes.c_int
+_lib.xpbd_rl_step_learned.argtypes = [_V, _V, ctypes.POINTER(XpbdRlParams), _V,
+                                      ctypes.POINTER(XpbdLearnedParams), ctypes.c_int32, _V, _V,
+                                      _V, _V, _V]
+
+
 def make_rl_params(grasp_radius, grasp_offset, max_speed, obs_scale, obs_origin, box_lo, box_hi,
                    tracked) -> XpbdRlParams:
     p = XpbdRlParams()
@@ -519,12 +525,7 @@ def xpbd_policy_destroy(policy):
     _lib.xpbd_policy_destroy(policy)
 
 
-def xpbd_rl_step(batch, policy, params: XpbdRlParams, num_steps, tool_pos, grasped, target,
-                 obs=None, actions=None):
-    """RL steps on the batch's stream; every array is a contiguous device tensor:
-    tool_pos float32 [N, 2, 3], grasped int32 [N] (both updated in place),
-    target float32 [N, 3], obs float32 [num_steps, N, 64] or None, actions
-    float32 [num_steps, N, 7] or None (sizes checked here)."""
+def _check_rl_buffers(batch, num_steps, tool_pos, grasped, target, obs, actions):
     n_envs = _BATCHES.get(batch, (None,))[0]
     steps = int(num_steps)
     need = [(tool_pos, "torch.float32", n_envs * 6, "tool_pos"),
@@ -539,8 +540,32 @@ def xpbd_rl_step(batch, policy, params: XpbdRlParams, num_steps, tool_pos, grasp
             raise TypeError(f"{what} must be a contiguous device tensor")
         if str(t.dtype) != dtype or t.numel() != count:
             raise ValueError(f"{what} must be {dtype} with {count} elements")
-    _check(_lib.xpbd_rl_step(batch, policy, ctypes.byref(params), steps, _ptr(tool_pos),
+
+
+def xpbd_rl_step(batch, policy, params: XpbdRlParams, num_steps, tool_pos, grasped, target,
+                 obs=None, actions=None):
+    """RL steps on the batch's stream; every array is a contiguous device tensor:
+    tool_pos float32 [N, 2, 3], grasped int32 [N] (both updated in place),
+    target float32 [N, 3], obs float32 [num_steps, N, 64] or None, actions
+    float32 [num_steps, N, 7] or None (sizes checked here)."""
+    _check_rl_buffers(batch, num_steps, tool_pos, grasped, target, obs, actions)
+    _check(_lib.xpbd_rl_step(batch, policy, ctypes.byref(params), int(num_steps), _ptr(tool_pos),
                              _ptr(grasped), _ptr(target), _ptr(obs), _ptr(actions)))
+
+
+def xpbd_rl_step_learned(batch, policy, params: XpbdRlParams, net, num_steps, tool_pos, grasped,
+                         target, min_iterations, max_iterations, threshold, obs=None,
+                         actions=None, apply_correction=True, iterations=None, stall_ratio=0.0,
+                         record_substep=-1, record_features=None, record_targets=None):
+    """xpbd_rl_step with the learned warm start (see include/xpbd_rl.h);
+    iterations: device int32 [num_steps * substeps * N] or None."""
+    _check_rl_buffers(batch, num_steps, tool_pos, grasped, target, obs, actions)
+    lp = XpbdLearnedParams(int(bool(apply_correction)), int(min_iterations), int(max_iterations),
+                           float(threshold), int(record_substep), _ptr(record_features),
+                           _ptr(record_targets), _ptr(iterations), float(stall_ratio))
+    _check(_lib.xpbd_rl_step_learned(batch, policy, ctypes.byref(params), net, ctypes.byref(lp),
+                                     int(num_steps), _ptr(tool_pos), _ptr(grasped), _ptr(target),
+                                     _ptr(obs), _ptr(actions)))
 
 
 # --------------------------------------------------------------------- convenience
@@ -625,6 +650,12 @@ class Batch:
                 obs=None, actions=None):
         xpbd_rl_step(self.handle, policy.handle, params, num_steps, tool_pos, grasped, target,
                      obs, actions)
+
+    def rl_step_learned(self, policy, params: XpbdRlParams, net, num_steps, tool_pos, grasped,
+                        target, min_iterations, max_iterations, threshold, **kw):
+        xpbd_rl_step_learned(self.handle, policy.handle, params,
+                             net.handle if net is not None else None, num_steps, tool_pos,
+                             grasped, target, min_iterations, max_iterations, threshold, **kw)
 
     def read(self, field, dst=None, raise_nonfinite=True):
         return xpbd_read_state(self.handle, field, dst, raise_nonfinite)

@@ -297,3 +297,117 @@ def test_rl_rejects_bad_arguments(xp):
         xp.Policy(bad)
     with pytest.raises(xp.XpbdError, match="parameters"):
         xp.Policy(np.zeros(10, np.float32))
+
+
+# ------------------------------------------------------------ learned warm start inside the step
+def test_rl_learned_without_correction_is_the_plain_rl_step(xp):
+    """xpbd_rl_step_learned with no correction and the plain sweep count is
+    xpbd_rl_step bit for bit (positions, velocities, tools, grasps,
+    observations, actions, contact lists)."""
+    import torch
+    N, steps = 37, 5
+    wl = W.rl_workload(N, seed=2)
+    tools, target, grasped = start_state(N, seed=2)
+    out = []
+    for learned in (False, True):
+        with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, K.lib_params(xp, wl)) as b, \
+                xp.Policy(W.rl_policy_params(0)) as pol:
+            rp = xp.make_rl_params(**rl_settings(wl.meshes[0]))
+            tp = torch.from_numpy(tools).cuda()
+            gr = torch.from_numpy(grasped).cuda()
+            tg = torch.from_numpy(target).cuda()
+            obs = torch.zeros((steps, N, R.OBS), dtype=torch.float32, device="cuda")
+            act = torch.zeros((steps, N, R.ACTIONS), dtype=torch.float32, device="cuda")
+            if learned:
+                b.rl_step_learned(pol, rp, None, steps, tp, gr, tg, wl.iterations, wl.iterations,
+                                  np.inf, obs=obs, actions=act, apply_correction=False)
+            else:
+                b.rl_step(pol, rp, steps, tp, gr, tg, obs, act)
+            torch.cuda.synchronize()
+            out.append([b.positions(), b.velocities(), tp.cpu().numpy(), gr.cpu().numpy(),
+                        obs.cpu().numpy(), act.cpu().numpy(), b.read(xp.FIELD_CONTACTS)])
+    for a, c in zip(*out):
+        assert np.array_equal(a, c)
+    assert np.any(out[0][3] >= 0)
+
+
+@pytest.mark.parametrize("threshold,expect_its", [(np.inf, 2), (-1.0, 4)])
+def test_rl_learned_follows_the_oracle(xp, oracle_lib, threshold, expect_its):
+    """An exactly computed policy (the grasper closes and lifts), a random
+    warm-start network: 20 environments, 6 steps; sweep counts exact,
+    positions, tools and grasps to the plain gate."""
+    import torch
+    from oracle import warmstart as ws
+    from tests.test_gpu_learned import flat, random_net
+    N, steps = 20, 6
+    wl = W.rl_workload(N, seed=4)
+    tools, target, grasped = start_state(N, seed=4)
+    pp = exact_policy(hold=True)
+    in_scale = 1.0 / np.array([2e-4] * 3 + [0.1] * 3 + [2e-3] * 3 + [2e-5] * 18)
+    net = random_net(8, out_scale=2e-5)
+    net.in_scale = in_scale.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(8)
+    net.in_shift = (rng.uniform(-0.3, 0.3, 27) / in_scale).astype(np.float32).astype(np.float64)
+    net.out_shift = np.array([1e-6, -1e-6, -3e-6], np.float32).astype(np.float64)
+    om = K.oracle_meshes(oracle_lib, wl)[0]
+    free = om.w > 0
+
+    def corr(x_prev, v_start, x_hat, nbr):
+        return ws.correction(net, ws.features(x_prev, v_start, x_hat, om.rest, nbr), free)
+
+    params = K.oracle_params(oracle_lib, wl)
+    rl = oracle_rl_params(wl.meshes[0])
+    pnet = R.unpack_policy(pp)
+    learned = R.RlLearned(corr, 2, 4, threshold)
+    refs = [R.run_env_rl(om, wl.compliance[e], params, rl, pnet, tools[e], target[e], steps,
+                         grasped0=int(grasped[e]), learned=learned) for e in range(N)]
+    its = torch.zeros(steps * wl.substeps * N, dtype=torch.int32, device="cuda")
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, K.lib_params(xp, wl)) as b, \
+            xp.Policy(pp) as pol, \
+            xp.Mlp(flat(net), net.in_shift, net.in_scale, net.out_shift, net.out_scale) as m:
+        rp = xp.make_rl_params(**rl_settings(wl.meshes[0]))
+        tp = torch.from_numpy(tools).cuda()
+        gr = torch.from_numpy(grasped).cuda()
+        tg = torch.from_numpy(target).cuda()
+        b.rl_step_learned(pol, rp, m, steps, tp, gr, tg, 2, 4, threshold, iterations=its)
+        torch.cuda.synchronize()
+        x = b.positions()
+        offs = b.env_offsets
+        t_end, g_end = tp.cpu().numpy(), gr.cpu().numpy()
+    it = its.cpu().numpy().reshape(steps, wl.substeps, N)
+    assert np.all(it == expect_its)
+    worst = 0.0
+    clear = [e for e in range(N) if np.all(refs[e].select_margin >= SELECT_MARGIN)]
+    assert len(clear) >= 0.9 * N
+    for e in clear:
+        assert np.all(refs[e].iterations == expect_its)
+        err = K.max_position_error(K.env_block(x, offs, e), refs[e].x)
+        worst = max(worst, err)
+        assert err <= K.POS_TOL, f"env {e}: position error {err:.3e}"
+        assert np.max(np.abs(t_end[e] - refs[e].tools[-1])) <= K.POS_TOL
+        assert g_end[e] == refs[e].grasped[-1]
+    assert np.all(g_end[clear] >= 0)
+    print(f"max position error {worst:.3e} m")
+
+
+def test_rl_learned_rejects_what_the_learned_step_rejects(xp):
+    import torch
+    wl = W.rl_workload(8, seed=0)
+    tools, target, grasped = start_state(8)
+    tp = torch.from_numpy(tools).cuda()
+    gr = torch.from_numpy(grasped).cuda()
+    tg = torch.from_numpy(target).cuda()
+    p = K.lib_params(xp, wl)
+    p.envs_per_group = 2
+    with xp.Policy(W.rl_policy_params(0)) as pol, \
+            xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b:
+        rp = xp.make_rl_params(**rl_settings(wl.meshes[0]))
+        with pytest.raises(xp.XpbdError, match="one environment per workgroup"):
+            b.rl_step_learned(pol, rp, None, 1, tp, gr, tg, 2, 8, np.inf, apply_correction=False)
+    with xp.Policy(W.rl_policy_params(0)) as pol, \
+            xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, K.lib_params(xp, wl)) as b:
+        rp = xp.make_rl_params(**rl_settings(wl.meshes[0]))
+        with pytest.raises(xp.XpbdError, match="need a network"):
+            b.rl_step_learned(pol, rp, None, 1, tp, gr, tg, 2, 8, np.inf)
+        with pytest.raises(xp.XpbdError, match="min_iterations"):
+            b.rl_step_learned(pol, rp, None, 1, tp, gr, tg, 5, 2, np.inf, apply_correction=False)
