@@ -411,3 +411,53 @@ def test_rl_learned_rejects_what_the_learned_step_rejects(xp):
             b.rl_step_learned(pol, rp, None, 1, tp, gr, tg, 2, 8, np.inf)
         with pytest.raises(xp.XpbdError, match="min_iterations"):
             b.rl_step_learned(pol, rp, None, 1, tp, gr, tg, 5, 2, np.inf, apply_correction=False)
+
+
+@pytest.mark.parametrize("grids,n", [([(12, 8, 3), (20, 12, 6)], 9), ([(12, 8, 3)], 1)],
+                         ids=["two-size-classes", "one-env"])
+def test_rl_step_on_uneven_batches(xp, oracle_lib, grids, n):
+    """Two meshes whose register launches fall in different size classes
+    (concurrent class streams), and a batch of one environment: the exact
+    policy's grasp and drag follow the oracle environment by environment."""
+    import torch
+    meshes = [W.slab_mesh(*g) for g in grids]
+    env_mesh = (np.arange(n) % len(meshes)).astype(np.int32)
+    wl = W.Workload("rl-uneven", meshes, env_mesh, W.log_uniform_compliance(n, 1e-7, 1e-5, 5),
+                    iterations=8, num_steps=6, seed=5, num_tools=2)
+    steps = 6
+    tools, target, grasped = start_state(n, seed=5)
+    pp = exact_policy(hold=False)
+    tracked = W.rl_tracked(meshes[0])            # top-face ids of the smaller slab exist in both
+    settings = dict(rl_settings(meshes[0]), tracked=tracked)
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, K.lib_params(xp, wl)) as b, \
+            xp.Policy(pp) as pol:
+        rp = xp.make_rl_params(**settings)
+        tp = torch.from_numpy(tools).cuda()
+        gr = torch.from_numpy(grasped).cuda()
+        tg = torch.from_numpy(target).cuda()
+        hist = []
+        for _ in range(steps):
+            b.rl_step(pol, rp, 1, tp, gr, tg)
+            hist.append(gr.cpu().numpy().copy())
+        torch.cuda.synchronize()
+        x = b.positions()
+        offs = b.env_offsets
+        t_end = tp.cpu().numpy()
+    oms = K.oracle_meshes(oracle_lib, wl)
+    params = K.oracle_params(oracle_lib, wl)
+    rl = oracle_rl_params(meshes[0])
+    rl.tracked = tracked
+    pnet = R.unpack_policy(pp)
+    hist = np.array(hist)
+    checked = 0
+    for e in range(n):
+        ref = R.run_env_rl(oms[env_mesh[e]], wl.compliance[e], params, rl, pnet, tools[e],
+                           target[e], steps, grasped0=int(grasped[e]))
+        if np.any(ref.select_margin < SELECT_MARGIN):
+            continue
+        checked += 1
+        err = K.max_position_error(K.env_block(x, offs, e), ref.x)
+        assert err <= K.POS_TOL, f"env {e}: position error {err:.3e}"
+        assert np.max(np.abs(t_end[e] - ref.tools[-1])) <= K.POS_TOL
+        assert np.array_equal(hist[:, e], ref.grasped)
+    assert checked >= max(1, n - 1)
