@@ -64,6 +64,8 @@ struct xpbd_batch {
     uint16_t *learned_feat = nullptr;        // [total particles][32] features of the correction
     uint8_t *learned_cand = nullptr;         // [total particles]
     int32_t correct_workgroups = 0;          // persistent workgroups of the correction pass
+    int32_t *learned_chunk0 = nullptr;       // [meshes] first 32-particle chunk with a free particle
+    int32_t learned_chunks = 0;              // chunks per environment the correction visits
     int32_t max_vertices = 0;
 
     ~xpbd_batch()

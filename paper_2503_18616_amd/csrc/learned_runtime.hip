@@ -313,6 +313,23 @@ xpbd_status xpbd::run_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
         (st = b->alloc(reinterpret_cast<void **>(&b->learned_feat),
                        sizeof(uint16_t) * 32 * (size_t)NP)))
         return st;
+    if (lp->apply_correction && !b->learned_chunk0) {
+        // the correction's 32-particle chunks: those before a mesh's first
+        // free particle hold pinned particles only and are skipped
+        std::vector<int32_t> c0(b->meshes.size(), 0);
+        int32_t chunks = 1;
+        for (size_t m = 0; m < b->meshes.size(); ++m) {
+            const auto &pm = b->meshes[m];
+            int32_t first = 0;
+            while (first < pm.num_vertices && !(pm.inv_mass[(size_t)first] > 0.0f))
+                ++first;
+            c0[m] = std::min(first, pm.num_vertices - 1) / 32;
+            chunks = std::max(chunks, (pm.num_vertices + 31) / 32 - c0[m]);
+        }
+        if ((st = b->upload(&b->learned_chunk0, c0)))
+            return st;
+        b->learned_chunks = chunks;
+    }
     if (lp->apply_correction && !b->correct_workgroups) {
         int device = 0, cus = 0;
         HIP_TRY(hipGetDevice(&device));
@@ -371,6 +388,8 @@ xpbd_status xpbd::run_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
     L.max_iterations = lp->max_iterations;
     L.stall_ratio = lp->stall_ratio;
     L.max_vertices = b->max_vertices;
+    L.chunk0 = b->learned_chunk0;
+    L.chunks = b->learned_chunks;
     const bool resid = (b->params.flags & XPBD_F_RESIDUAL) != 0;
     const bool want_lambda = (b->params.flags & XPBD_F_LAMBDA) || resid;
     const int S = b->params.substeps;

@@ -154,7 +154,8 @@ __device__ void stage_network(CorrectLds &S, const MlpDev &net, int tid)
 
 // Grid: persistent workgroups of 256 threads (three per CU).  Wave w of the
 // grid takes the work items w, w + total waves, ...; item k is particles
-// 32 (k % G) .. + 31 of environment k / G, G = ceil(max vertices / 32).
+// 32 (k % G + c0) .. + 31 of environment k / G, G = L.chunks, c0 = L.chunk0
+// of the environment's mesh (chunks of pinned particles only are skipped).
 // Reads the feature rows L.features and adds the correction to the predicted
 // positions L.xhat of the free particles.
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
@@ -172,7 +173,7 @@ learned_correct_kernel(StepArgs A, LearnedArgs L, MlpDev net)
         oshift[o] = net.out_shift[o];
         oscale[o] = net.out_scale[o];
     }
-    const int G = (L.max_vertices + 16 * kTiles - 1) / (16 * kTiles);
+    const int G = L.chunks;
     const int items = A.num_envs * G;
     const int waves = gridDim.x * (kThreads / 64);
     // the loads of a work item are issued one item ahead, so they are in
@@ -193,7 +194,7 @@ learned_correct_kernel(StepArgs A, LearnedArgs L, MlpDev net)
         const MeshDev &md = A.meshes[ed.mesh];
         d.V = md.num_vertices;
         d.off = ed.particle_offset;
-        d.p0 = (item % G) * 16 * kTiles;
+        d.p0 = (item % G + L.chunk0[ed.mesh]) * 16 * kTiles;
         if (d.p0 >= d.V)
             return;
         d.ok = true;
@@ -314,8 +315,7 @@ hipError_t launch_learned_correct(const StepArgs &args, const LearnedArgs &largs
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess)
         return err;
-    const int G = (largs.max_vertices + 16 * kTiles - 1) / (16 * kTiles);
-    const int64_t items = (int64_t)args.num_envs * G;
+    const int64_t items = (int64_t)args.num_envs * largs.chunks;
     const int64_t needed = (items + kThreads / 64 - 1) / (kThreads / 64);
     const int grid = (int)(needed < num_workgroups ? needed : num_workgroups);
     hipLaunchKernelGGL(learned_correct_kernel, dim3((unsigned)grid), dim3(kThreads), lds, stream,

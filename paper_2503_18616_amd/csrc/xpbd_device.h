@@ -128,6 +128,11 @@ struct LearnedArgs {
     int32_t first_substep;       // 1: find the contact candidates on the start-of-step positions
     int32_t step;                // row of tool_pos used by this substep
     int32_t max_vertices;
+    // network pass: per mesh the first 32-particle chunk that holds a free
+    // particle (the chunks before it hold pinned particles only, which the
+    // correction leaves alone), and the chunks per environment it visits
+    const int32_t *chunk0;       // [meshes]
+    int32_t chunks;
 };
 
 // Per-workgroup LDS layout for an environment of a given mesh.
