@@ -294,15 +294,11 @@ xpbd_status xpbd::check_learned(const xpbd_batch *b, const xpbd_mlp *net,
     return XPBD_OK;
 }
 
-// num_steps learned steps with the tool poses in device memory; grasp is null
-// or names the RL step's grasp state.
-xpbd_status xpbd::run_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_steps,
-                              const float *tools_dev, const xpbd_learned_params *lp,
-                              const GraspArgs *grasp)
+// The learned step's device workspace, allocated on first use (before any
+// launch, so that a captured step allocates nothing).
+xpbd_status xpbd::learned_workspace(xpbd_batch *b, const xpbd_learned_params *lp)
 {
-    const int tools = b->params.num_tools;
     const int64_t NP = b->total_particles;
-    const bool record = lp->record_substep >= 0;
     xpbd_status st;
     if (!b->learned_xhat && ((st = b->alloc(reinterpret_cast<void **>(&b->learned_xhat),
                                             sizeof(float) * 3 * (size_t)NP)) ||
@@ -336,6 +332,21 @@ xpbd_status xpbd::run_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
         b->correct_workgroups = 3 * std::max(cus, 1);   // three 51 KB workgroups fit a CU's LDS
     }
+
+    return XPBD_OK;
+}
+
+// num_steps learned steps with the tool poses in device memory; grasp is null
+// or names the RL step's grasp state.
+xpbd_status xpbd::run_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_steps,
+                              const float *tools_dev, const xpbd_learned_params *lp,
+                              const GraspArgs *grasp)
+{
+    const int tools = b->params.num_tools;
+    const bool record = lp->record_substep >= 0;
+    xpbd_status st = learned_workspace(b, lp);
+    if (st != XPBD_OK)
+        return st;
 
     xpbd::StepArgs a;
     std::memset(&a, 0, sizeof a);

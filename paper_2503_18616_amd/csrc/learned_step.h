@@ -7,6 +7,8 @@
 
 namespace xpbd {
 
+// The learned step's workspace (allocated on first use).
+xpbd_status learned_workspace(xpbd_batch *b, const xpbd_learned_params *lp);
 // Batch and parameter checks of a learned step (host only).
 xpbd_status check_learned(const xpbd_batch *b, const xpbd_mlp *net,
                           const xpbd_learned_params *lp);

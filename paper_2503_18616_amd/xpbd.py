@@ -70,7 +70,9 @@ EXPORTED = ["xpbd_create_batch", "xpbd_step", "xpbd_read_state", "xpbd_write_sta
             "xpbd_prepare_mesh", "xpbd_mlp_create", "xpbd_mlp_get_params", "xpbd_mlp_set_params",
             "xpbd_mlp_forward", "xpbd_mlp_train_step", "xpbd_mlp_destroy", "xpbd_axis_neighbours",
             "xpbd_step_learned", "xpbd_autotune", "xpbd_surface_faces", "xpbd_policy_create",
-            "xpbd_policy_destroy", "xpbd_rl_step", "xpbd_rl_step_learned"]
+            "xpbd_policy_destroy", "xpbd_rl_step", "xpbd_rl_step_learned",
+            "xpbd_step_graph_create", "xpbd_rl_graph_create", "xpbd_graph_launch",
+            "xpbd_graph_destroy"]
 
 # learned warm start (include/xpbd_learned.h)
 MLP_FEATURES = 27
@@ -568,7 +570,93 @@ def xpbd_rl_step_learned(batch, policy, params: XpbdRlParams, net, num_steps, to
                                      _ptr(obs), _ptr(actions)))
 
 
+# captured steps (include/xpbd_graph.h)
+_lib.xpbd_step_graph_create.restype = ctypes.c_int
+_lib.xpbd_step_graph_create.argtypes = [_V, _V, ctypes.POINTER(XpbdLearnedParams), _V,
+                                        ctypes.POINTER(ctypes.c_void_p)]
+_lib.xpbd_rl_graph_create.restype = ctypes.c_int
+_lib.xpbd_rl_graph_create.argtypes = [_V, _V, ctypes.POINTER(XpbdRlParams), _V,
+                                      ctypes.POINTER(XpbdLearnedParams), _V, _V, _V, _V, _V,
+                                      ctypes.POINTER(ctypes.c_void_p)]
+_lib.xpbd_graph_launch.restype = ctypes.c_int
+_lib.xpbd_graph_launch.argtypes = [_V, ctypes.c_int32]
+_lib.xpbd_graph_destroy.restype = None
+_lib.xpbd_graph_destroy.argtypes = [_V]
+
+
+def make_learned_params(min_iterations, max_iterations, threshold, apply_correction=True,
+                        record_substep=-1, record_features=None, record_targets=None,
+                        iterations=None, stall_ratio=0.0) -> XpbdLearnedParams:
+    return XpbdLearnedParams(int(bool(apply_correction)), int(min_iterations),
+                             int(max_iterations), float(threshold), int(record_substep),
+                             _ptr(record_features), _ptr(record_targets), _ptr(iterations),
+                             float(stall_ratio))
+
+
+def xpbd_step_graph_create(batch, net, learned, tool_pos):
+    """One step (learned: XpbdLearnedParams or None) reading tool_pos (a
+    contiguous device tensor [N, tools, 3]) at every replay."""
+    n_envs, n_tools, per_tool = _BATCHES.get(batch, (None, None, 3))
+    if n_tools:
+        if not hasattr(tool_pos, "data_ptr") or not tool_pos.is_cuda or \
+                not tool_pos.is_contiguous() or str(tool_pos.dtype) != "torch.float32" or \
+                tool_pos.numel() != n_envs * n_tools * per_tool:
+            raise ValueError("tool_pos must be a contiguous float32 device tensor of one step")
+    h = ctypes.c_void_p()
+    _check(_lib.xpbd_step_graph_create(batch, net, ctypes.byref(learned) if learned else None,
+                                       _ptr(tool_pos), ctypes.byref(h)))
+    return h.value
+
+
+def xpbd_rl_graph_create(batch, policy, params: XpbdRlParams, net, learned, tool_pos, grasped,
+                         target, obs=None, actions=None):
+    _check_rl_buffers(batch, 1, tool_pos, grasped, target, obs, actions)
+    h = ctypes.c_void_p()
+    _check(_lib.xpbd_rl_graph_create(batch, policy, ctypes.byref(params), net,
+                                     ctypes.byref(learned) if learned else None, _ptr(tool_pos),
+                                     _ptr(grasped), _ptr(target), _ptr(obs), _ptr(actions),
+                                     ctypes.byref(h)))
+    return h.value
+
+
+def xpbd_graph_launch(graph, times=1):
+    _check(_lib.xpbd_graph_launch(graph, int(times)))
+
+
+def xpbd_graph_destroy(graph):
+    _lib.xpbd_graph_destroy(graph)
+
+
 # --------------------------------------------------------------------- convenience
+class Graph:
+    """Owning wrapper around a captured step; keeps the buffers it names alive."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def launch(self, times=1):
+        xpbd_graph_launch(self.handle, times)
+
+    def close(self):
+        if self.handle:
+            xpbd_graph_destroy(self.handle)
+            self.handle = None
+        self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 class Policy:
     """Owning wrapper around a policy handle."""
 
@@ -656,6 +744,19 @@ class Batch:
         xpbd_rl_step_learned(self.handle, policy.handle, params,
                              net.handle if net is not None else None, num_steps, tool_pos,
                              grasped, target, min_iterations, max_iterations, threshold, **kw)
+
+    def step_graph(self, tool_pos, net=None, learned: XpbdLearnedParams = None):
+        """A captured step (see include/xpbd_graph.h); learned from make_learned_params."""
+        h = xpbd_step_graph_create(self.handle, net.handle if net is not None else None, learned,
+                                   tool_pos)
+        return Graph(h, (tool_pos, net, learned))
+
+    def rl_graph(self, policy, params: XpbdRlParams, tool_pos, grasped, target, obs=None,
+                 actions=None, net=None, learned: XpbdLearnedParams = None):
+        h = xpbd_rl_graph_create(self.handle, policy.handle, params,
+                                 net.handle if net is not None else None, learned, tool_pos,
+                                 grasped, target, obs, actions)
+        return Graph(h, (policy, params, tool_pos, grasped, target, obs, actions, net, learned))
 
     def read(self, field, dst=None, raise_nonfinite=True):
         return xpbd_read_state(self.handle, field, dst, raise_nonfinite)

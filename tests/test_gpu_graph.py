@@ -1,0 +1,142 @@
+"""Captured steps (include/xpbd_graph.h): every replay of a graph equals the
+step the corresponding eager call makes, bit for bit.  Each test replays the
+graph several times with the program's own eager work (copies of the next
+step's tool poses, read-backs, synchronisations) between the replays and
+checks every replay."""
+import numpy as np
+import pytest
+
+import oracle.rl as R
+from paper_2503_18616_amd import workloads as W
+from tests import cases as K
+from tests.test_gpu_rl import exact_policy, rl_settings, start_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def xp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2503_18616_amd import xpbd
+    return xpbd
+
+
+def small_net(xp):
+    """A random warm-start network with a small output scale (as in the learned tests)."""
+    from tests.test_gpu_learned import flat, random_net
+    net = random_net(8, out_scale=2e-5)
+    in_scale = 1.0 / np.array([2e-4] * 3 + [0.1] * 3 + [2e-3] * 3 + [2e-5] * 18)
+    net.in_scale = in_scale.astype(np.float32).astype(np.float64)
+    return xp.Mlp(flat(net), np.zeros(27), net.in_scale, np.zeros(3), net.out_scale)
+
+
+@pytest.mark.parametrize("learned", [False, True], ids=["plain", "learned"])
+def test_step_graph_replays_equal_eager_steps(xp, learned):
+    import torch
+    N, steps = 24, 6
+    wl = W.batch_workload(N, seed=7, num_steps=steps)
+    tools = torch.from_numpy(W.tool_path(steps, N, 7, start_depth=6e-3)).cuda()
+    p = K.lib_params(xp, wl)
+    p.solver_variant = xp.VARIANT_REGISTERS
+    net = small_net(xp) if learned else None
+    S = wl.substeps
+    its_e = torch.zeros(S * N, dtype=torch.int32, device="cuda")
+    its_g = torch.zeros(S * N, dtype=torch.int32, device="cuda")
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as eager, \
+            xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as cap:
+        buf = torch.zeros_like(tools[0])
+        lp = xp.make_learned_params(2, 8, -1.0, stall_ratio=0.9, iterations=its_g) \
+            if learned else None
+        with cap.step_graph(buf, net, lp) as g:
+            assert np.array_equal(cap.positions(), eager.positions())   # capture ran nothing
+            for s in range(steps):
+                if learned:
+                    eager.step_learned(net, 1, tools[s:s + 1], 2, 8, -1.0, stall_ratio=0.9,
+                                       iterations=its_e)
+                else:
+                    eager.step(1, tools[s:s + 1])
+                buf.copy_(tools[s])
+                g.launch()
+                torch.cuda.synchronize()
+                assert np.array_equal(cap.positions(), eager.positions()), f"replay {s}"
+                assert np.array_equal(cap.velocities(), eager.velocities()), f"replay {s}"
+                assert np.array_equal(cap.read(xp.FIELD_CONTACTS), eager.read(xp.FIELD_CONTACTS))
+                if learned:
+                    assert np.array_equal(its_g.cpu().numpy(), its_e.cpu().numpy())
+            # several replays in one call
+            for s in range(2):
+                eager.step_learned(net, 1, tools[-1:], 2, 8, -1.0, stall_ratio=0.9,
+                                   iterations=its_e) if learned else eager.step(1, tools[-1:])
+            g.launch(2)
+            torch.cuda.synchronize()
+            assert np.array_equal(cap.positions(), eager.positions())
+    if net is not None:
+        net.close()
+
+
+@pytest.mark.parametrize("learned", [False, True], ids=["plain", "learned"])
+def test_rl_graph_replays_equal_eager_rl_steps(xp, learned):
+    import torch
+    N, steps = 37, 6
+    wl = W.rl_workload(N, seed=3)
+    tools, target, grasped = start_state(N, seed=3)
+    pp = W.rl_policy_params(0)
+    net = small_net(xp) if learned else None
+    S = wl.substeps
+    bufs = []
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, K.lib_params(xp, wl)) as eager, \
+            xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, K.lib_params(xp, wl)) as cap, \
+            xp.Policy(pp) as pol:
+        rp = xp.make_rl_params(**rl_settings(wl.meshes[0]))
+        for _ in range(2):
+            bufs.append(dict(tp=torch.from_numpy(tools).cuda(),
+                             gr=torch.from_numpy(grasped).cuda(),
+                             tg=torch.from_numpy(target).cuda(),
+                             obs=torch.zeros((1, N, R.OBS), dtype=torch.float32, device="cuda"),
+                             act=torch.zeros((1, N, R.ACTIONS), dtype=torch.float32,
+                                             device="cuda"),
+                             its=torch.zeros(S * N, dtype=torch.int32, device="cuda")))
+        e, c = bufs
+        lp = xp.make_learned_params(2, 8, -1.0, stall_ratio=0.9, iterations=c["its"]) \
+            if learned else None
+        with cap.rl_graph(pol, rp, c["tp"], c["gr"], c["tg"], c["obs"], c["act"], net, lp) as g:
+            for s in range(steps):
+                if learned:
+                    eager.rl_step_learned(pol, rp, net, 1, e["tp"], e["gr"], e["tg"], 2, 8, -1.0,
+                                          obs=e["obs"], actions=e["act"], stall_ratio=0.9,
+                                          iterations=e["its"])
+                else:
+                    eager.rl_step(pol, rp, 1, e["tp"], e["gr"], e["tg"], e["obs"], e["act"])
+                g.launch()
+                torch.cuda.synchronize()
+                assert np.array_equal(cap.positions(), eager.positions()), f"replay {s}"
+                for k in ("tp", "gr", "obs", "act", "its"):
+                    assert torch.equal(c[k], e[k]), f"replay {s}: {k}"
+            assert int((c["gr"] >= 0).sum()) > 0
+    if net is not None:
+        net.close()
+
+
+def test_graph_rejects_bad_arguments(xp):
+    import torch
+    wl = W.batch_workload(4, seed=0, num_steps=1)
+    host_tools = W.tool_path(1, 4, 0)[0]
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, K.lib_params(xp, wl)) as b:
+        import ctypes
+        h = ctypes.c_void_p()
+        st = xp._lib.xpbd_step_graph_create(b.handle, None, None, host_tools.ctypes.data,
+                                            ctypes.byref(h))
+        assert st == xp.XPBD_E_ARG and "device memory" in xp.xpbd_last_error()
+        assert xp._lib.xpbd_graph_launch(None, 1) == xp.XPBD_E_ARG
+        with b.step_graph(torch.from_numpy(host_tools).cuda()) as g:
+            with pytest.raises(xp.XpbdError, match="times"):
+                g.launch(-1)
+            g.launch(0)
+    # two size classes: one launch per class and step, not captured
+    meshes = [W.slab_mesh(12, 8, 3), W.slab_mesh(20, 12, 6)]
+    uw = W.Workload("two", meshes, np.array([0, 1], np.int32),
+                    W.log_uniform_compliance(2, 1e-7, 1e-5, 1), iterations=4, num_steps=1, seed=1)
+    with xp.Batch(K.lib_meshes(uw), uw.env_mesh, uw.compliance, K.lib_params(xp, uw)) as b:
+        with pytest.raises(xp.XpbdError, match="one size class"):
+            b.step_graph(torch.from_numpy(W.tool_path(1, 2, 1)[0]).cuda())
