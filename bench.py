@@ -359,6 +359,16 @@ def rl_learned_leg(args, make_batch, policy, rp, S, I):
         end.record(stream)
         torch.cuda.synchronize()
         ms = start.elapsed_time(end)
+        # the learned RL step captured in a graph, replayed from where it stopped
+        lp = xpbd.make_learned_params(args.learned_min, I, threshold, stall_ratio=args.learned_stall)
+        with lb.rl_graph(policy, rp, ltp, lgr, tg, net=net, learned=lp) as g:
+            g.launch(2)
+            torch.cuda.synchronize()
+            start.record(stream)
+            g.launch(steps)
+            end.record(stream)
+            torch.cuda.synchronize()
+        graph_ms = start.elapsed_time(end) / steps
         start.record(stream)
         for s in range(steps):
             pb.rl_step(policy, rp, 1, tp, gr, tg)
@@ -380,7 +390,7 @@ def rl_learned_leg(args, make_batch, policy, rp, S, I):
     net.close()
     it = its.cpu().numpy()
     return {"value": N * steps * S / (ms / 1e3), "unit": "env-substeps/s",
-            "ms_per_step": ms / steps, "steps": steps,
+            "ms_per_step": ms / steps, "steps": steps, "graph_ms_per_step": graph_ms,
             "plain_value_same_steps": N * steps * S / (ms_plain / 1e3),
             "min_iterations": args.learned_min, "max_iterations": I,
             "stall_ratio": args.learned_stall, "threshold": threshold,
@@ -451,6 +461,19 @@ def rl_bench(args):
     progress(f"timed {args.steps} RL steps: {ms / args.steps:.3f} ms per step")
     holding = int((gr >= 0).sum())
     resid = batch.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)
+    # the same RL step captured in a graph (include/xpbd_graph.h) and replayed
+    # from the state the timed steps left
+    batch.set_flags(0)
+    graph_steps = min(args.steps, 100)
+    with batch.rl_graph(policy, rp, tp, gr, tg, obs, act) as g:
+        g.launch(2)
+        torch.cuda.synchronize()
+        start.record(stream)
+        g.launch(graph_steps)
+        end.record(stream)
+        torch.cuda.synchronize()
+    graph_ms = start.elapsed_time(end) / graph_steps
+    progress(f"graph replays: {graph_ms:.3f} ms per step")
     batch.close()
 
     learned = None
@@ -516,6 +539,7 @@ def rl_bench(args):
                    "env_steps_per_s": N * args.steps / (ms / 1e3),
                    "policy_gflop_per_step": policy_flops / 1e9,
                    "holding_at_end": holding,
+                   "graph_ms_per_step": graph_ms,
                    "residual_rms_mean": float(resid[:, 0].mean()),
                    "residual_max": float(resid[:, 1].max())},
         "roofline": roofline, "cpu_baseline": cpu, "learned": learned,
