@@ -326,3 +326,56 @@ def test_learned_driver_stall_rule_and_corrector(scene):
     # the held particle still ends every step on the dragging point
     g = int(b.grasped[-1])
     np.testing.assert_allclose(b.x[g], b.tools[-1, 0] + rl.grasp_offset, atol=1e-15)
+
+
+def path_net(w1=1.0, w2=1.0, w3=1.0, b2=0.0, k=3, u=0, v=0, o=6):
+    """One path input k -> unit u -> unit v -> output o with the given weights."""
+    H, F = R.HIDDEN, R.OBS
+    flat = np.zeros(R.NUM_PARAMS, np.float32)
+    flat[u * F + k] = w1
+    off2 = H * F + H
+    flat[off2 + v * H + u] = w2
+    flat[off2 + H * H + v] = b2
+    off3 = off2 + H * H + H
+    flat[off3 + o * H + v] = w3
+    return R.unpack_policy(flat)
+
+
+def test_policy_relu_and_rounding_of_every_layer():
+    o = np.zeros(64)
+    # relu after layer 2: a negative second-layer value is blocked
+    o[3] = 0.75
+    assert R.policy(path_net(w2=-1.0), o)[6] == 0.0
+    # the input is rounded: 1 + 2^-8 ties to 1, so 3 x input is 3, not 3.0117 -> 3.015625
+    o[3] = 1.0 + 2.0 ** -8
+    assert R.policy(path_net(w1=3.0), o)[6] == 3.0
+    # the first hidden layer is rounded: (1 + 2^-7)^2 = 1 + 2^-6 + 2^-14 becomes 1 + 2^-6,
+    # and with b2 = 2^-8 - 2^-6 the second layer lands exactly on the tie 1 + 2^-8,
+    # which rounds to even (1); the unrounded value would sit above the tie (1 + 2^-7)
+    o[3] = 1.0 + 2.0 ** -7
+    net = path_net(w1=1.0 + 2.0 ** -7, b2=2.0 ** -8 - 2.0 ** -6)
+    assert R.policy(net, o)[6] == 1.0
+
+
+def test_learned_driver_adds_the_correction_to_the_prediction(scene):
+    """Without sweeps a substep is the prediction plus the correction: with a
+    constant correction c on free particles and zero start velocity, after K
+    substeps v = K (h g + c / h) and x = x0 + h (h g + c / h) K (K + 1) / 2."""
+    m, om, rl, params, tools0, target = scene
+    c = np.array([1e-5, -2e-5, 3e-6])
+    free = om.w > 0
+
+    def corr(x_prev, v_start, x_hat, nbr):
+        out = np.zeros_like(x_hat)
+        out[free] = c
+        return out
+    net = constant_net(np.array([0, 0, 0, 0, 0, 0, -1.0], np.float32))
+    res = R.run_env_rl(om, (1e-6, 1e-7), params, rl, net, tools0, target, 1,
+                       learned=R.RlLearned(corr, 0, 0, np.inf))
+    assert np.all(res.iterations == 0)
+    K = params.substeps
+    h = params.dt / K
+    step = h * np.asarray(params.gravity) + c / h
+    np.testing.assert_allclose(res.v[free], np.broadcast_to(K * step, res.v[free].shape), atol=1e-9)
+    np.testing.assert_allclose(res.x[free], om.rest[free] + h * step * K * (K + 1) / 2, atol=1e-12)
+    assert np.array_equal(res.x[~free], om.rest[~free])
