@@ -59,6 +59,9 @@ def parse_args():
     ap.add_argument("--envs", type=int, default=0,
                     help="environments (0: 1024 for the batch workload, 4096 for the uneven one, "
                          "8192 for the RL-style step)")
+    ap.add_argument("--seed", type=int, default=0,
+                    help="seed of the workload's draws (compliances, tool paths, RL starts and "
+                         "policy); the learned leg trains on seed + 1")
     ap.add_argument("--steps-per-launch", type=int, default=1)
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = library's choice)")
     ap.add_argument("--variant", type=int, default=0,
@@ -164,7 +167,7 @@ def learned_leg(args, wl_fn, mesh, make_batch, I, S):
     t0 = time.perf_counter()
     # training run: its own seeds, the same mesh and compliance distribution
     warm = 20
-    tw = wl_fn(args.train_envs, seed=1, num_steps=warm + args.train_records)
+    tw = wl_fn(args.train_envs, seed=args.seed + 1, num_steps=warm + args.train_records)
     ttools = torch.from_numpy(lifted(tw.tools(warm + args.train_records), args)).cuda()
     subs = [k % S for k in range(args.train_records)]
     with make_batch(tw, 0) as tb:
@@ -187,7 +190,7 @@ def learned_leg(args, wl_fn, mesh, make_batch, I, S):
     # evaluation: plain and learned from the same state of the benchmark workload
     N = args.envs
     total = args.warmup + args.learned_steps
-    wl = wl_fn(N, seed=0, num_steps=total)
+    wl = wl_fn(N, seed=args.seed, num_steps=total)
     tools = torch.from_numpy(lifted(wl.tools(total), args)).cuda()
     its = torch.zeros(args.learned_steps * S * N, dtype=torch.int32, device="cuda")
     with make_batch(wl, xpbd.F_RESIDUAL) as pb, make_batch(wl, xpbd.F_RESIDUAL) as lb:
@@ -256,6 +259,7 @@ def learned_leg(args, wl_fn, mesh, make_batch, I, S):
             "residual_rms_mean": float(r_l.mean()),
             "plain_residual_rms_mean": float(r_p.mean()),
             "residual_matched": bool(r_l.mean() <= r_p.mean()),
+            "residual_ratio": float(r_l.mean() / r_p.mean()),
             "residual_by_sweeps": by_sweeps,
             "training": {"envs": args.train_envs, "recorded_substeps": args.train_records,
                          "free_rows": rows, "adam_steps": args.train_steps,
@@ -300,7 +304,7 @@ def rl_learned_leg(args, make_batch, policy, rp, S, I):
 
     t0 = time.perf_counter()
     warm, n_rec = 20, args.train_records
-    tw = W.rl_workload(args.train_envs, seed=1)
+    tw = W.rl_workload(args.train_envs, seed=args.seed + 1)
     NP = args.train_envs * tw.meshes[0].num_vertices
     subs = [k % S for k in range(n_rec)]
 
@@ -316,7 +320,7 @@ def rl_learned_leg(args, make_batch, policy, rp, S, I):
         return feats, targets
 
     with make_batch(tw, 0) as tb:
-        tp, gr, tg = rl_state(args.train_envs, 1)
+        tp, gr, tg = rl_state(args.train_envs, args.seed + 1)
         for _ in range(warm):
             tb.rl_step(policy, rp, 1, tp, gr, tg)
         snap = snapshot(tb, tp, gr)
@@ -335,10 +339,10 @@ def rl_learned_leg(args, make_batch, policy, rp, S, I):
 
     N = args.envs or 8192
     steps = args.learned_steps
-    wl = W.rl_workload(N, seed=0)
+    wl = W.rl_workload(N, seed=args.seed)
     its = torch.zeros(steps * S * N, dtype=torch.int32, device="cuda")
     with make_batch(wl, xpbd.F_RESIDUAL) as pb, make_batch(wl, xpbd.F_RESIDUAL) as lb:
-        tp, gr, tg = rl_state(N, 0)
+        tp, gr, tg = rl_state(N, args.seed)
         warm_res = []
         for _ in range(args.warmup):
             pb.rl_step(policy, rp, 1, tp, gr, tg)
@@ -401,6 +405,7 @@ def rl_learned_leg(args, make_batch, policy, rp, S, I):
             "residual_rms_mean": float(r_l.mean()),
             "plain_residual_rms_mean": float(r_p.mean()),
             "residual_matched": bool(r_l.mean() <= r_p.mean()),
+            "residual_ratio": float(r_l.mean() / r_p.mean()),
             "training": {"envs": args.train_envs, "recorded_substeps": n_rec,
                          "free_rows": rows, "adam_steps": args.train_steps,
                          "loss_first": float(np.mean(losses[:5])),
@@ -422,7 +427,7 @@ def rl_bench(args):
 
     N = args.envs or 8192
     total = args.warmup + args.steps
-    wl = W.rl_workload(N, seed=0, num_steps=total)
+    wl = W.rl_workload(N, seed=args.seed, num_steps=total)
     m = wl.meshes[0]
     S, I = wl.substeps, wl.iterations
     E, T, V, v_free = mesh_sizes(xpbd, m)
@@ -433,12 +438,12 @@ def rl_bench(args):
     t_create = time.perf_counter()
     batch = xpbd.Batch([(m.rest_pos, m.inv_mass, m.tets)], wl.env_mesh, wl.compliance, params,
                        stream=stream.cuda_stream)
-    policy = xpbd.Policy(W.rl_policy_params(0), stream=stream.cuda_stream)
+    policy = xpbd.Policy(W.rl_policy_params(args.seed), stream=stream.cuda_stream)
     t_create = time.perf_counter() - t_create
     lo, hi = W.rl_box()
     rp = xpbd.make_rl_params(W.RL_GRASP_RADIUS, W.RL_GRASP_OFFSET, W.RL_MAX_SPEED,
                              W.RL_OBS_SCALE, W.rl_origin(), lo, hi, W.rl_tracked(m))
-    tools0, target = W.rl_start(N, 0)
+    tools0, target = W.rl_start(N, args.seed)
     tp = torch.from_numpy(tools0).cuda()
     gr = torch.full((N,), -1, dtype=torch.int32, device="cuda")
     tg = torch.from_numpy(target).cuda()
@@ -512,7 +517,7 @@ def rl_bench(args):
         orl = R.RlParams(f32(W.RL_GRASP_RADIUS), vec(W.RL_GRASP_OFFSET), f32(W.RL_MAX_SPEED),
                          f32(W.RL_OBS_SCALE), vec(W.rl_origin()), vec(lo), vec(hi),
                          W.rl_tracked(m))
-        net = R.unpack_policy(W.rl_policy_params(0))
+        net = R.unpack_policy(W.rl_policy_params(args.seed))
         envs = list(range(0, N, max(1, N // args.cpu_envs)))[:args.cpu_envs]
         steps = min(args.cpu_steps, 30)
         threads = min(16, os.cpu_count() or 1, len(envs))
@@ -532,7 +537,8 @@ def rl_bench(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "envs": N, "grid": [m.nx, m.ny, m.nz], "particles": V,
+        "config": {"workload": wl.name, "seed": args.seed, "envs": N, "grid": [m.nx, m.ny, m.nz],
+                   "particles": V,
                    "edges": E, "tets": T, "substeps": S, "iterations": I, "tools": 2,
                    "create_s": round(t_create, 3), "solver": "plain (no warm start)",
                    "policy": "64-256-256-7 bf16 (random init)",
@@ -574,12 +580,12 @@ def main():
     total = args.warmup + args.steps
     if args.workload == "batch":
         args.envs = args.envs or 1024
-        wl = W.batch_workload(args.envs, seed=0, num_steps=total)
+        wl = W.batch_workload(args.envs, seed=args.seed, num_steps=total)
     elif args.workload == "uneven":
         args.envs = args.envs or 4096
-        wl = W.uneven_workload(args.envs, seed=0, num_steps=total)
+        wl = W.uneven_workload(args.envs, seed=args.seed, num_steps=total)
     else:
-        wl = W.single_env_workload(seed=0)
+        wl = W.single_env_workload(seed=args.seed)
         wl.num_steps = total
         args.envs = 1
     m = wl.meshes[0]
@@ -696,7 +702,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "envs": N, "meshes": len(wl.meshes),
+        "config": {"workload": wl.name, "seed": args.seed, "envs": N, "meshes": len(wl.meshes),
                    "grid": [m.nx, m.ny, m.nz] if len(wl.meshes) == 1 else "per environment",
                    "particles": V if len(wl.meshes) == 1 else int(Vs.sum()),
                    "edges": E if len(wl.meshes) == 1 else int(Es.sum()),
