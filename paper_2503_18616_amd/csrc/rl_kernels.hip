@@ -1,5 +1,6 @@
 // The RL-style step's observation, policy and tool-motion pass (gfx950): one
-// wave per 16 environments.  The wave first writes the environments'
+// wave per 32 environments (two 16-environment tiles that share every weight
+// fragment the wave loads).  The wave first writes the environments'
 // observations (one observation per lane and environment, coalesced) to LDS
 // and to the caller's buffer, then runs the 64 -> 256 -> 256 -> 7 policy on
 // the matrix cores (v_mfma_f32_16x16x32_bf16, bfloat16 operands, float32
@@ -96,15 +97,27 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// Grid: ceil(N / 16) workgroups of one wave; workgroup w takes environments
-// 16 w .. 16 w + 15.
+constexpr int kTiles = 2;                            // 16-environment tiles per wave
+constexpr int kWaveEnvs = kRlEnvsPerWave * kTiles;   // environments per wave
+
+// One observation of one environment, for lane l (observation l): the value
+// and the grasp word (lane 9) are loaded first for all of the wave's
+// environments, then combined, so that the gathers are in flight together.
+struct ObsLoad {
+    float v;        // loaded value (tool, target or particle coordinate), or grasp bits
+    float rest;     // the tracked particle's rest coordinate (lanes >= 10)
+};
+
+// Grid: ceil(N / 32) workgroups of one wave; workgroup w takes environments
+// 32 w .. 32 w + 31 as two tiles of 16.
 __global__ void __launch_bounds__(64) rl_policy_kernel(RlArgs R, PolicyDev P)
 {
-    __shared__ __align__(16) float obs[kRlEnvsPerWave * kPitch];
-    __shared__ float act[kRlEnvsPerWave * 8];
-    __shared__ int held[kRlEnvsPerWave];
+    __shared__ __align__(16) float obs[kWaveEnvs * kPitch];
+    __shared__ float act[kWaveEnvs * 8];
+    __shared__ int held[kWaveEnvs];
     const int l = threadIdx.x;
-    const int base = blockIdx.x * kRlEnvsPerWave;
+    const int base = blockIdx.x * kWaveEnvs;
+    const int N = R.num_envs;
     const int NP = R.total_particles;
     const float s = R.obs_scale;
 
@@ -116,73 +129,121 @@ __global__ void __launch_bounds__(64) rl_policy_kernel(RlArgs R, PolicyDev P)
     for (int q = 0; q < kRlTracked; ++q)
         tp = j == q ? R.tracked[q] : tp;
     const float origin = c == 0 ? R.obs_origin[0] : (c == 1 ? R.obs_origin[1] : R.obs_origin[2]);
-    for (int r = 0; r < kRlEnvsPerWave; ++r) {
+    // the environments' particle offsets and mesh tables: one lane per
+    // environment (out-of-range environments repeat the last one and are
+    // not written), shared through LDS
+    __shared__ int env_off[kWaveEnvs], env_nv[kWaveEnvs];
+    __shared__ const float *env_rest[kWaveEnvs];
+    __shared__ const float *env_w[kWaveEnvs];
+    if (l < kWaveEnvs) {
+        const EnvDev ed = R.envs[min(base + l, N - 1)];
+        const MeshDev &md = R.meshes[ed.mesh];
+        env_off[l] = ed.particle_offset;
+        env_nv[l] = md.num_vertices;
+        env_rest[l] = md.rest_pos;
+        env_w[l] = md.inv_mass;
+    }
+    __syncthreads();
+    // every gather of the wave's environments first, then the arithmetic
+    ObsLoad ld[kWaveEnvs];
+#pragma unroll
+    for (int r = 0; r < kWaveEnvs; ++r) {
+        const int e = min(base + r, N - 1);
+        const float *src = l < 6    ? R.tool_pos + (size_t)e * 6 + l
+                           : l < 9  ? R.target + (size_t)e * 3 + c
+                           : l == 9 ? reinterpret_cast<const float *>(R.grasp + e)
+                                    : R.pos + (size_t)c * NP + env_off[r] + tp;
+        ld[r].v = *src;
+        ld[r].rest = l >= 10 ? env_rest[r][3 * tp + c] : origin;
+    }
+#pragma unroll
+    for (int r = 0; r < kWaveEnvs; ++r) {
         const int e = base + r;
-        float v = 0.0f;
-        if (e < R.num_envs) {
-            const EnvDev ed = R.envs[e];
-            const MeshDev &md = R.meshes[ed.mesh];
-            if (l < 6) {
-                v = (R.tool_pos[(size_t)e * 6 + l] - origin) * s;
-            } else if (l < 9) {
-                v = (R.target[(size_t)e * 3 + c] - origin) * s;
-            } else if (l == 9) {
-                const int h = R.grasp[e];
-                const bool ok = h >= 0 && h < md.num_vertices && md.inv_mass[h] > 0.0f;
-                v = ok ? 1.0f : 0.0f;
-                held[r] = ok ? h : -1;
-            } else {
-                v = (R.pos[(size_t)c * NP + ed.particle_offset + tp] - md.rest_pos[3 * tp + c]) * s;
-            }
-            if (R.obs)
-                R.obs[(size_t)e * kRlObs + l] = v;
-        } else if (l == 9) {
-            held[r] = -1;
+        float v = (ld[r].v - ld[r].rest) * s;
+        if (l == 9) {
+            const int h = __float_as_int(ld[r].v);
+            const bool ok = h >= 0 && h < env_nv[r] && env_w[r][h] > 0.0f;
+            v = ok ? 1.0f : 0.0f;
+            held[r] = ok && e < N ? h : -1;
         }
+        if (e >= N)
+            v = 0.0f;
+        else if (R.obs)
+            R.obs[(size_t)e * kRlObs + l] = v;
         obs[r * kPitch + l] = v;
     }
     __syncthreads();
 
     const int n = l & 15, g = l >> 4;
-    const bf16x8 x0 = pack_inputs(&obs[n * kPitch + 8 * g]);
-    const bf16x8 x1 = pack_inputs(&obs[n * kPitch + 32 + 8 * g]);
-    // layer 1: 16 unit tiles, two k blocks
-    bf16x8 h1[8];
+    bf16x8 x0[kTiles], x1[kTiles];
 #pragma unroll
-    for (int t = 0; t < 16; t += 2) {
-        f32x4 lo = bias(P.b1, t, g), hi = bias(P.b1, t + 1, g);
-        lo = mfma(fragment(P.w1, (2 * t + 0) * 64 + l), x0, lo);
-        hi = mfma(fragment(P.w1, (2 * t + 2) * 64 + l), x0, hi);
-        lo = mfma(fragment(P.w1, (2 * t + 1) * 64 + l), x1, lo);
-        hi = mfma(fragment(P.w1, (2 * t + 3) * 64 + l), x1, hi);
-        h1[t / 2] = relu_pack(lo, hi);
+    for (int t = 0; t < kTiles; ++t) {
+        x0[t] = pack_inputs(&obs[(16 * t + n) * kPitch + 8 * g]);
+        x1[t] = pack_inputs(&obs[(16 * t + n) * kPitch + 32 + 8 * g]);
+    }
+    // layer 1: 16 unit tiles, two k blocks; every fragment serves both tiles
+    bf16x8 h1[kTiles][8];
+#pragma unroll
+    for (int u = 0; u < 16; u += 2) {
+        const bf16x8 a0 = fragment(P.w1, (2 * u + 0) * 64 + l), a1 = fragment(P.w1, (2 * u + 1) * 64 + l);
+        const bf16x8 b0 = fragment(P.w1, (2 * u + 2) * 64 + l), b1 = fragment(P.w1, (2 * u + 3) * 64 + l);
+        const f32x4 blo = bias(P.b1, u, g), bhi = bias(P.b1, u + 1, g);
+#pragma unroll
+        for (int t = 0; t < kTiles; ++t) {
+            f32x4 lo = mfma(a0, x0[t], blo), hi = mfma(b0, x0[t], bhi);
+            lo = mfma(a1, x1[t], lo);
+            hi = mfma(b1, x1[t], hi);
+            h1[t][u / 2] = relu_pack(lo, hi);
+        }
     }
     // layer 2: 16 unit tiles, eight k blocks
-    bf16x8 h2[8];
+    bf16x8 h2[kTiles][8];
 #pragma unroll
-    for (int t = 0; t < 16; t += 2) {
-        f32x4 lo = bias(P.b2, t, g), hi = bias(P.b2, t + 1, g);
+    for (int u = 0; u < 16; u += 2) {
+        f32x4 lo[kTiles], hi[kTiles];
+        const f32x4 blo = bias(P.b2, u, g), bhi = bias(P.b2, u + 1, g);
+#pragma unroll
+        for (int t = 0; t < kTiles; ++t) {
+            lo[t] = blo;
+            hi[t] = bhi;
+        }
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb) {
-            lo = mfma(fragment(P.w2, (8 * t + kb) * 64 + l), h1[kb], lo);
-            hi = mfma(fragment(P.w2, (8 * t + 8 + kb) * 64 + l), h1[kb], hi);
+            const bf16x8 a = fragment(P.w2, (8 * u + kb) * 64 + l);
+            const bf16x8 b = fragment(P.w2, (8 * u + 8 + kb) * 64 + l);
+#pragma unroll
+            for (int t = 0; t < kTiles; ++t) {
+                lo[t] = mfma(a, h1[t][kb], lo[t]);
+                hi[t] = mfma(b, h1[t][kb], hi[t]);
+            }
         }
-        h2[t / 2] = relu_pack(lo, hi);
+#pragma unroll
+        for (int t = 0; t < kTiles; ++t)
+            h2[t][u / 2] = relu_pack(lo[t], hi[t]);
     }
     // layer 3: one unit tile (actions 0..6, units 7..15 zero)
-    f32x4 y = bias(P.b3, 0, g);
+    f32x4 y[kTiles];
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb)
-        y = mfma(fragment(P.w3, kb * 64 + l), h2[kb], y);
-    // lane (n, g) holds actions 4 g .. 4 g + 3 of environment base + n
+    for (int t = 0; t < kTiles; ++t)
+        y[t] = bias(P.b3, 0, g);
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+        const bf16x8 a = fragment(P.w3, kb * 64 + l);
+#pragma unroll
+        for (int t = 0; t < kTiles; ++t)
+            y[t] = mfma(a, h2[t][kb], y[t]);
+    }
+    // lane (n, g) holds actions 4 g .. 4 g + 3 of environment 16 t + n of the wave
     if (g < 2) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            act[n * 8 + 4 * g + q] = y[q];
+        for (int t = 0; t < kTiles; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                act[(16 * t + n) * 8 + 4 * g + q] = y[t][q];
     }
     __syncthreads();
 
-    if (l < kRlEnvsPerWave && base + l < R.num_envs) {
+    if (l < kWaveEnvs && base + l < N) {
         const int e = base + l;
         float a[kRlActions];
 #pragma unroll
@@ -216,7 +277,7 @@ hipError_t launch_rl_policy(const RlArgs &args, const PolicyDev &policy, hipStre
 {
     if (args.num_envs <= 0)
         return hipSuccess;
-    const int grid = (args.num_envs + kRlEnvsPerWave - 1) / kRlEnvsPerWave;
+    const int grid = (args.num_envs + kWaveEnvs - 1) / kWaveEnvs;
     hipLaunchKernelGGL(rl_policy_kernel, dim3((unsigned)grid), dim3(64), 0, stream, args, policy);
     return hipGetLastError();
 }
