@@ -87,9 +87,11 @@ __device__ __forceinline__ bf16x8 fragment(const uint16_t *base, int index)
     return r;
 }
 
+// Bias fragment of a unit tile from the LDS copy: lane group g holds units
+// 4 g .. 4 g + 3 of the tile.
 __device__ __forceinline__ f32x4 bias(const float *b, int tile, int g)
 {
-    return reinterpret_cast<const GLOBAL f32x4 *>((uintptr_t)b)[4 * tile + g];
+    return *reinterpret_cast<const f32x4 *>(b + 16 * tile + 4 * g);
 }
 
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
@@ -115,7 +117,21 @@ __global__ void __launch_bounds__(64) rl_policy_kernel(RlArgs R, PolicyDev P)
     __shared__ __align__(16) float obs[kWaveEnvs * kPitch];
     __shared__ float act[kWaveEnvs * 8];
     __shared__ int held[kWaveEnvs];
+    // the biases (b1, b2, b3 with zero padding: 528 floats) in LDS, so that
+    // reading them never waits on the weight-fragment loads in flight
+    __shared__ __align__(16) float bs[2 * kRlHidden + 16];
     const int l = threadIdx.x;
+    {
+        const GLOBAL f32x4 *src1 = reinterpret_cast<const GLOBAL f32x4 *>((uintptr_t)P.b1);
+        const GLOBAL f32x4 *src2 = reinterpret_cast<const GLOBAL f32x4 *>((uintptr_t)P.b2);
+        const GLOBAL f32x4 *src3 = reinterpret_cast<const GLOBAL f32x4 *>((uintptr_t)P.b3);
+        const f32x4 v1 = src1[l], v2 = src2[l];
+        const f32x4 v3 = l < 4 ? src3[l] : f32x4{0.f, 0.f, 0.f, 0.f};
+        *reinterpret_cast<f32x4 *>(&bs[4 * l]) = v1;
+        *reinterpret_cast<f32x4 *>(&bs[kRlHidden + 4 * l]) = v2;
+        if (l < 4)
+            *reinterpret_cast<f32x4 *>(&bs[2 * kRlHidden + 4 * l]) = v3;
+    }
     const int base = blockIdx.x * kWaveEnvs;
     const int N = R.num_envs;
     const int NP = R.total_particles;
@@ -153,24 +169,42 @@ __global__ void __launch_bounds__(64) rl_policy_kernel(RlArgs R, PolicyDev P)
                            : l < 9  ? R.target + (size_t)e * 3 + c
                            : l == 9 ? reinterpret_cast<const float *>(R.grasp + e)
                                     : R.pos + (size_t)c * NP + env_off[r] + tp;
-        ld[r].v = *src;
-        ld[r].rest = l >= 10 ? env_rest[r][3 * tp + c] : origin;
+        ld[r].v = *reinterpret_cast<const GLOBAL float *>((uintptr_t)src);
+        ld[r].rest = l >= 10 ? reinterpret_cast<const GLOBAL float *>(
+                                   (uintptr_t)env_rest[r])[3 * tp + c]
+                             : origin;
     }
+    // the grasp flag's inverse masses (lane 9), all gathered before any store
+    // (branch-free: every lane loads, other lanes and ids out of range read
+    // particle 0, so the 32 loads are in flight together)
+    float wh[kWaveEnvs];
+#pragma unroll
+    for (int r = 0; r < kWaveEnvs; ++r) {
+        const int h = __float_as_int(ld[r].v);
+        const bool in = l == 9 && h >= 0 && h < env_nv[r];
+        const float w = reinterpret_cast<const GLOBAL float *>((uintptr_t)env_w[r])[in ? h : 0];
+        wh[r] = in ? w : 0.0f;
+    }
+    // the observations in registers, then every store
+    float vv[kWaveEnvs];
 #pragma unroll
     for (int r = 0; r < kWaveEnvs; ++r) {
         const int e = base + r;
         float v = (ld[r].v - ld[r].rest) * s;
         if (l == 9) {
             const int h = __float_as_int(ld[r].v);
-            const bool ok = h >= 0 && h < env_nv[r] && env_w[r][h] > 0.0f;
+            const bool ok = wh[r] > 0.0f;
             v = ok ? 1.0f : 0.0f;
             held[r] = ok && e < N ? h : -1;
         }
-        if (e >= N)
-            v = 0.0f;
-        else if (R.obs)
-            R.obs[(size_t)e * kRlObs + l] = v;
-        obs[r * kPitch + l] = v;
+        vv[r] = e < N ? v : 0.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < kWaveEnvs; ++r) {
+        const int e = base + r;
+        if (e < N && R.obs)
+            R.obs[(size_t)e * kRlObs + l] = vv[r];
+        obs[r * kPitch + l] = vv[r];
     }
     __syncthreads();
 
@@ -181,57 +215,76 @@ __global__ void __launch_bounds__(64) rl_policy_kernel(RlArgs R, PolicyDev P)
         x0[t] = pack_inputs(&obs[(16 * t + n) * kPitch + 8 * g]);
         x1[t] = pack_inputs(&obs[(16 * t + n) * kPitch + 32 + 8 * g]);
     }
-    // layer 1: 16 unit tiles, two k blocks; every fragment serves both tiles
-    bf16x8 h1[kTiles][8];
+    // The three layers as one stream of 168 weight fragments (W1: 16 unit
+    // tiles x 2 k blocks, W2: 16 x 8, W3: 8), each serving both environment
+    // tiles.  Fragment f + kDepth is loaded while fragment f is used, from a
+    // ring of kDepth registers, so that kDepth loads are in flight: with one
+    // or two waves per CU nothing else hides their latency.
+    constexpr int kF1 = 32, kF2 = 128, kF3 = 8, kF = kF1 + kF2 + kF3, kDepth = 16;
+    auto load = [&](int f) -> bf16x8 {
+        return f < kF1 ? fragment(P.w1, f * 64 + l)
+               : f < kF1 + kF2 ? fragment(P.w2, (f - kF1) * 64 + l)
+                               : fragment(P.w3, (f - kF1 - kF2) * 64 + l);
+    };
+    bf16x8 ring[kDepth];
 #pragma unroll
-    for (int u = 0; u < 16; u += 2) {
-        const bf16x8 a0 = fragment(P.w1, (2 * u + 0) * 64 + l), a1 = fragment(P.w1, (2 * u + 1) * 64 + l);
-        const bf16x8 b0 = fragment(P.w1, (2 * u + 2) * 64 + l), b1 = fragment(P.w1, (2 * u + 3) * 64 + l);
-        const f32x4 blo = bias(P.b1, u, g), bhi = bias(P.b1, u + 1, g);
+    for (int f = 0; f < kDepth; ++f)
+        ring[f] = load(f);
+    bf16x8 h1[kTiles][8], h2[kTiles][8];
+    f32x4 acc[kTiles][2], y[kTiles];
+#pragma clang loop unroll(full)
+    for (int f = 0; f < kF; ++f) {
+        const bf16x8 a = ring[f % kDepth];
+        if (f + kDepth < kF)
+            ring[f % kDepth] = load(f + kDepth);
+        if (f < kF1) {
+            // layer 1: unit tile u = f / 2, k block f % 2 (the two halves of the input)
+            const int u = f / 2, kb = f % 2;
+            if (kb == 0) {
+                const f32x4 b = bias(bs, u, g);
 #pragma unroll
-        for (int t = 0; t < kTiles; ++t) {
-            f32x4 lo = mfma(a0, x0[t], blo), hi = mfma(b0, x0[t], bhi);
-            lo = mfma(a1, x1[t], lo);
-            hi = mfma(b1, x1[t], hi);
-            h1[t][u / 2] = relu_pack(lo, hi);
-        }
-    }
-    // layer 2: 16 unit tiles, eight k blocks
-    bf16x8 h2[kTiles][8];
+                for (int t = 0; t < kTiles; ++t)
+                    acc[t][u % 2] = mfma(a, x0[t], b);
+            } else {
 #pragma unroll
-    for (int u = 0; u < 16; u += 2) {
-        f32x4 lo[kTiles], hi[kTiles];
-        const f32x4 blo = bias(P.b2, u, g), bhi = bias(P.b2, u + 1, g);
+                for (int t = 0; t < kTiles; ++t)
+                    acc[t][u % 2] = mfma(a, x1[t], acc[t][u % 2]);
+                if (u % 2 == 1) {
 #pragma unroll
-        for (int t = 0; t < kTiles; ++t) {
-            lo[t] = blo;
-            hi[t] = bhi;
-        }
-#pragma unroll
-        for (int kb = 0; kb < 8; ++kb) {
-            const bf16x8 a = fragment(P.w2, (8 * u + kb) * 64 + l);
-            const bf16x8 b = fragment(P.w2, (8 * u + 8 + kb) * 64 + l);
-#pragma unroll
-            for (int t = 0; t < kTiles; ++t) {
-                lo[t] = mfma(a, h1[t][kb], lo[t]);
-                hi[t] = mfma(b, h1[t][kb], hi[t]);
+                    for (int t = 0; t < kTiles; ++t)
+                        h1[t][u / 2] = relu_pack(acc[t][0], acc[t][1]);
+                }
             }
+        } else if (f < kF1 + kF2) {
+            // layer 2: unit tile u, k block kb
+            const int u = (f - kF1) / 8, kb = (f - kF1) % 8;
+            if (kb == 0) {
+                const f32x4 b = bias(bs + kRlHidden, u, g);
+#pragma unroll
+                for (int t = 0; t < kTiles; ++t)
+                    acc[t][u % 2] = b;
+            }
+#pragma unroll
+            for (int t = 0; t < kTiles; ++t)
+                acc[t][u % 2] = mfma(a, h1[t][kb], acc[t][u % 2]);
+            if (kb == 7 && u % 2 == 1) {
+#pragma unroll
+                for (int t = 0; t < kTiles; ++t)
+                    h2[t][u / 2] = relu_pack(acc[t][0], acc[t][1]);
+            }
+        } else {
+            // layer 3: one unit tile (actions 0..6, units 7..15 zero), k block kb
+            const int kb = f - kF1 - kF2;
+            if (kb == 0) {
+                const f32x4 b = bias(bs + 2 * kRlHidden, 0, g);
+#pragma unroll
+                for (int t = 0; t < kTiles; ++t)
+                    y[t] = b;
+            }
+#pragma unroll
+            for (int t = 0; t < kTiles; ++t)
+                y[t] = mfma(a, h2[t][kb], y[t]);
         }
-#pragma unroll
-        for (int t = 0; t < kTiles; ++t)
-            h2[t][u / 2] = relu_pack(lo[t], hi[t]);
-    }
-    // layer 3: one unit tile (actions 0..6, units 7..15 zero)
-    f32x4 y[kTiles];
-#pragma unroll
-    for (int t = 0; t < kTiles; ++t)
-        y[t] = bias(P.b3, 0, g);
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb) {
-        const bf16x8 a = fragment(P.w3, kb * 64 + l);
-#pragma unroll
-        for (int t = 0; t < kTiles; ++t)
-            y[t] = mfma(a, h2[t][kb], y[t]);
     }
     // lane (n, g) holds actions 4 g .. 4 g + 3 of environment 16 t + n of the wave
     if (g < 2) {
