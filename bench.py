@@ -440,6 +440,7 @@ def rl_bench(args):
                        stream=stream.cuda_stream)
     policy = xpbd.Policy(W.rl_policy_params(args.seed), stream=stream.cuda_stream)
     t_create = time.perf_counter() - t_create
+    launch = batch.info()
     lo, hi = W.rl_box()
     rp = xpbd.make_rl_params(W.RL_GRASP_RADIUS, W.RL_GRASP_OFFSET, W.RL_MAX_SPEED,
                              W.RL_OBS_SCALE, W.rl_origin(), lo, hi, W.rl_tracked(m))
@@ -541,6 +542,7 @@ def rl_bench(args):
                    "particles": V,
                    "edges": E, "tets": T, "substeps": S, "iterations": I, "tools": 2,
                    "create_s": round(t_create, 3), "solver": "plain (no warm start)",
+                   "launch": launch,
                    "policy": "64-256-256-7 bf16 (random init)",
                    "env_steps_per_s": N * args.steps / (ms / 1e3),
                    "policy_gflop_per_step": policy_flops / 1e9,
@@ -625,7 +627,9 @@ def main():
     batch = xpbd.Batch([(mm.rest_pos, mm.inv_mass, mm.tets) for mm in wl.meshes], wl.env_mesh,
                        wl.compliance, params, stream=stream.cuda_stream)
     t_create = time.perf_counter() - t_create
-    progress(f"{wl.name}: {N} environments of {len(wl.meshes)} meshes set up in {t_create:.1f} s")
+    launch = batch.info()
+    progress(f"{wl.name}: {N} environments of {len(wl.meshes)} meshes set up in {t_create:.1f} s; "
+             f"launch {launch}")
     spl = args.steps_per_launch
     for s in range(0, args.warmup, spl):
         batch.step(spl, tools[s:s + spl])
@@ -712,6 +716,7 @@ def main():
                    "tool_lift_m": args.tool_lift, "autotune": tuned,
                    "tool_shape": args.tool_shape,
                    "solver_variant": ["auto", "registers", "lds", "jacobi"][args.variant],
+                   "launch": launch,
                    "residual_rms_mean": float(resid[:, 0].mean()),
                    "residual_max": float(resid[:, 1].max())},
         "roofline": roofline, "lds": lds_line, "hbm": hbm_line, "cpu_baseline": cpu,

@@ -259,6 +259,28 @@ xpbd_status xpbd_autotune(const xpbd_mesh *meshes, int32_t num_meshes, const int
                           void *hip_stream, int32_t num_steps, const float *tool_pos,
                           float *ms_per_step);
 
+/*
+ * The launch configuration a batch runs with (what the library chose for
+ * the zero, "library's choice", entries of xpbd_params), for inspection.
+ * For the register variant the figures are those of the largest size class;
+ * workgroups_per_cu is how many of its workgroups a CU holds at once (by
+ * the 16 resident waves of the kernel and by the CU's LDS), waves_per_cu the
+ * waves that makes.  Host only.  XPBD_E_ARG for NULL pointers.
+ */
+typedef struct {
+    int32_t solver_variant;    /* XPBD_VARIANT_REGISTERS, _LDS or _JACOBI */
+    int32_t block_size;        /* threads per workgroup */
+    int32_t envs_per_group;    /* environments per workgroup */
+    int32_t size_classes;      /* concurrent launches per step (register variant) */
+    int32_t lambda_banks;      /* 32-round multiplier banks (register variant) */
+    int32_t lds_bytes;         /* LDS per workgroup */
+    int32_t workgroups;        /* workgroups of the largest class */
+    int32_t workgroups_per_cu;
+    int32_t waves_per_cu;
+} xpbd_batch_info;
+
+xpbd_status xpbd_get_batch_info(const xpbd_batch *b, xpbd_batch_info *out);
+
 /* Free the batch and its device memory (waits for its stream).  NULL is ignored. */
 void xpbd_destroy_batch(xpbd_batch *b);
 

@@ -4,9 +4,12 @@
 // caller's stream; the fastest candidate's configuration is returned.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "../../include/xpbd.h"
+#include "batch.h"
 #include "runtime_util.h"
 
 namespace {
@@ -107,6 +110,50 @@ xpbd_status xpbd_autotune(const xpbd_mesh *meshes, int32_t num_meshes, const int
     ms_per_step[0] = best;
     ms_per_step[1] = default_ms;
     xpbd::g_error.clear();
+    return XPBD_OK;
+}
+
+xpbd_status xpbd_get_batch_info(const xpbd_batch *b, xpbd_batch_info *out)
+{
+    using xpbd::fail;
+    xpbd::g_error.clear();
+    if (!b || !out)
+        return fail(XPBD_E_ARG, "batch and out must not be NULL");
+    std::memset(out, 0, sizeof *out);
+    out->solver_variant = b->register_variant ? XPBD_VARIANT_REGISTERS
+                          : b->params.solver_variant == XPBD_VARIANT_JACOBI ? XPBD_VARIANT_JACOBI
+                                                                           : XPBD_VARIANT_LDS;
+    out->envs_per_group = b->envs_per_group;
+    int block = b->block, banks = b->lambda_banks, groups = b->num_envs;
+    uint32_t lds = b->lds_bytes;
+    if (b->register_variant) {
+        out->size_classes = (int32_t)b->classes.size();
+        int32_t most = -1;
+        for (const RegClass &c : b->classes)
+            if (c.num_groups > most) {
+                most = c.num_groups;
+                block = c.block;
+                banks = c.lambda_banks;
+                lds = c.lds_bytes;
+                groups = c.num_groups;
+            }
+    } else {
+        out->size_classes = 1;
+        banks = 0;
+    }
+    int lds_cu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                  b->device));
+    const int waves = (block + 63) / 64;
+    int per_cu = 16 / (waves > 0 ? waves : 1);
+    if (lds > 0 && lds_cu > 0)
+        per_cu = std::min(per_cu, (int)((uint32_t)lds_cu / lds));
+    out->block_size = block;
+    out->lambda_banks = banks;
+    out->lds_bytes = (int32_t)lds;
+    out->workgroups = groups;
+    out->workgroups_per_cu = std::max(per_cu, 1);
+    out->waves_per_cu = out->workgroups_per_cu * waves;
     return XPBD_OK;
 }
 

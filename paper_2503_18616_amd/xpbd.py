@@ -72,7 +72,7 @@ EXPORTED = ["xpbd_create_batch", "xpbd_step", "xpbd_read_state", "xpbd_write_sta
             "xpbd_step_learned", "xpbd_autotune", "xpbd_surface_faces", "xpbd_policy_create",
             "xpbd_policy_destroy", "xpbd_rl_step", "xpbd_rl_step_learned",
             "xpbd_step_graph_create", "xpbd_rl_graph_create", "xpbd_graph_launch",
-            "xpbd_graph_destroy"]
+            "xpbd_graph_destroy", "xpbd_get_batch_info"]
 
 # learned warm start (include/xpbd_learned.h)
 MLP_FEATURES = 27
@@ -105,6 +105,14 @@ class XpbdParams(ctypes.Structure):
                 ("envs_per_group", ctypes.c_int32), ("tool_shape", ctypes.c_int32)]
 
 
+class XpbdBatchInfo(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in (
+        "solver_variant", "block_size", "envs_per_group", "size_classes", "lambda_banks",
+        "lds_bytes", "workgroups", "workgroups_per_cu", "waves_per_cu")]
+
+
+_lib.xpbd_get_batch_info.restype = ctypes.c_int
+_lib.xpbd_get_batch_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(XpbdBatchInfo)]
 _lib.xpbd_create_batch.restype = ctypes.c_int
 _lib.xpbd_create_batch.argtypes = [ctypes.POINTER(XpbdMesh), ctypes.c_int32, ctypes.c_void_p,
                                    ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(XpbdParams),
@@ -355,6 +363,13 @@ def xpbd_write_state(batch, field, src):
     if isinstance(src, np.ndarray):
         src = np.ascontiguousarray(src, dtype=np.float32)
     _check(_lib.xpbd_write_state(batch, int(field), _ptr(src), _nbytes(src)))
+
+
+def xpbd_get_batch_info(batch) -> dict:
+    """The launch configuration the batch runs with (include/xpbd.h)."""
+    info = XpbdBatchInfo()
+    _check(_lib.xpbd_get_batch_info(batch, ctypes.byref(info)))
+    return {name: int(getattr(info, name)) for name, _ in XpbdBatchInfo._fields_}
 
 
 def xpbd_destroy_batch(batch):
@@ -760,6 +775,9 @@ class Batch:
 
     def read(self, field, dst=None, raise_nonfinite=True):
         return xpbd_read_state(self.handle, field, dst, raise_nonfinite)
+
+    def info(self):
+        return xpbd_get_batch_info(self.handle)
 
     def positions(self):
         return self.read(FIELD_POS).reshape(-1, 3)

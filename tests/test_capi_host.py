@@ -232,3 +232,10 @@ def test_rl_constants_match_the_oracle(xp):
 def ctypes_sizeof_rl_params(xp):
     import ctypes
     return ctypes.sizeof(xp.XpbdRlParams)
+
+
+def test_batch_info_rejects_null(xp):
+    import ctypes
+    assert xp._lib.xpbd_get_batch_info(None, None) == xp.XPBD_E_ARG
+    info = xp.XpbdBatchInfo()
+    assert xp._lib.xpbd_get_batch_info(None, ctypes.byref(info)) == xp.XPBD_E_ARG

@@ -123,3 +123,34 @@ def test_autotune_picks_a_configuration_that_runs(xp, oracle_lib):
         for n, e in enumerate(sample):
             err = K.max_position_error(K.env_block(x, b.env_offsets, e), refs[n].x)
             assert err <= K.POS_TOL, f"env {e}: {err:.3e}"
+
+
+def test_batch_info_reports_the_chosen_launch(xp):
+    """The occupancy model's choices: 256 threads and one environment per
+    workgroup for the 16x10x4 slab (4 per CU), 128 threads for the 12x8x3
+    slab (8 per CU), size classes for uneven meshes, and the LDS variant."""
+    wl = W.batch_workload(1024, seed=0, num_steps=1)
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, K.lib_params(xp, wl)) as b:
+        i = b.info()
+        assert (i["solver_variant"], i["block_size"], i["envs_per_group"], i["size_classes"]) == \
+            (xp.VARIANT_REGISTERS, 256, 1, 1)
+        assert (i["workgroups"], i["workgroups_per_cu"], i["waves_per_cu"], i["lambda_banks"]) == \
+            (1024, 4, 16, 2)
+    rl = W.rl_workload(8192, seed=0)
+    with xp.Batch(K.lib_meshes(rl), rl.env_mesh, rl.compliance, K.lib_params(xp, rl)) as b:
+        i = b.info()
+        assert (i["block_size"], i["envs_per_group"], i["workgroups_per_cu"], i["waves_per_cu"]) == \
+            (128, 1, 8, 16)
+    # 64 environments fit one pass at any block: the fewest rounds win (256 threads)
+    rl = W.rl_workload(64, seed=0)
+    with xp.Batch(K.lib_meshes(rl), rl.env_mesh, rl.compliance, K.lib_params(xp, rl)) as b:
+        assert b.info()["block_size"] == 256
+    un = W.uneven_workload(64, seed=0, num_steps=1)
+    with xp.Batch(K.lib_meshes(un), un.env_mesh, un.compliance, K.lib_params(xp, un)) as b:
+        assert b.info()["size_classes"] >= 2
+    p = K.lib_params(xp, wl)
+    p.solver_variant = xp.VARIANT_LDS
+    small = W.batch_workload(4, seed=0, num_steps=1)
+    with xp.Batch(K.lib_meshes(small), small.env_mesh, small.compliance, p) as b:
+        i = b.info()
+        assert i["solver_variant"] == xp.VARIANT_LDS and i["size_classes"] == 1
