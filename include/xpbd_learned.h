@@ -6,7 +6,7 @@
  * After the prediction of a substep, a per-particle network maps 27 local
  * features of the predicted state to a correction of the predicted position,
  * so that the Gauss-Seidel sweeps start closer to the solution.  The plain
- * sweeps remain the judge: after min_iterations the residual RMS of the
+ * sweeps still decide convergence: after min_iterations the residual RMS of the
  * environment (the mean over all constraints of ((C + alpha~ lambda) / rest)^2,
  * square-rooted, as XPBD_FIELD_RESIDUAL reports it) is compared with a
  * threshold, and the sweeps continue to max_iterations when it is above

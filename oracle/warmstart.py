@@ -7,8 +7,8 @@ The warm start is not part of FF-SRL's method: it is the learned extension
 built on its substep (Alg. 1).  After the prediction of a substep, a small
 per-particle network maps 27 local features of the predicted state to a
 correction of the predicted position; the Gauss-Seidel iterations of the
-substep then start from the corrected positions.  The plain iterations stay
-the judge: after ``min_iterations`` the constraint residual of the
+substep then start from the corrected positions.  The plain iterations still
+decide convergence: after ``min_iterations`` the constraint residual of the
 environment is evaluated (the RMS of (C + alpha~ lambda) / rest over all
 constraints, as ``oracle_residual`` defines it) and, if it exceeds the
 threshold, the substep continues to ``max_iterations``.
