@@ -961,7 +961,10 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
     tab.tid = tid;
     const uint64_t active = A.meshes[A.envs[env[0]].mesh].wave_active[__builtin_amdgcn_readfirstlane(wave)];
     const uint64_t tets = md.tet_mask, barriers = md.barrier_mask;
+    // (issued in this order, as in every round: the loop then waits for the
+    // older fetch only, instead of for both)
     Record slot_a = fetch_record(tab, 0, active & 1u);         // records of the next two
+    __builtin_amdgcn_sched_barrier(0);
     Record slot_b = fetch_record(tab, 1, (active >> 1) & 1u);  // rounds (even, odd)
 
     uint32_t cand = 0u;  // bit 16 t + k: the particle in slot k * B + tid is a candidate of tool t
@@ -1494,7 +1497,8 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
     tab.tid = tid;
     const uint64_t active = A.meshes[ed.mesh].wave_active[__builtin_amdgcn_readfirstlane(wave)];
     const uint64_t tets = md.tet_mask, barriers = md.barrier_mask;
-    Record slot_a = fetch_record(tab, 0, active & 1u);
+    Record slot_a = fetch_record(tab, 0, active & 1u);   // in this order (see xpbd_step_reg_kernel)
+    __builtin_amdgcn_sched_barrier(0);
     Record slot_b = fetch_record(tab, 1, (active >> 1) & 1u);
     const float alpha_d1[1] = {alpha_d}, alpha_v1[1] = {alpha_v};
 
