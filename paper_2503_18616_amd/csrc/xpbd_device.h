@@ -44,7 +44,7 @@ struct MeshDev {
     // tet (ab, cd, rest volume bits); the top two bits of the first word hold
     // the environment index within the group; lanes without a constraint hold
     // kInvalidRecord in the first word
-    const uint32_t *round_rec;   // [padded rounds][block][3]
+    const uint32_t *round_rec;   // [padded rounds + 2][block][3], the last two rows = rows 0, 1
     const int32_t *rr_id;        // [padded rounds][block] e << 24 | constraint id (tets: E + id), -1
     uint64_t wave_active[16];    // bit r: wave w has a constraint in round r
     uint64_t tet_mask;           // bit r: round r projects tetrahedra

@@ -808,14 +808,15 @@ struct RoundTables {
     int tid;
 };
 
-// Every wave fetches exactly one record per round (a wave without a
-// constraint in round r fetches its lane's entry of round 0, which stays
-// cache-resident), so the loads retire in order and each round waits only
-// for the fetch issued two rounds before it.  The address depends only on
-// (round, lane), so the fetch can run rounds ahead.
-__device__ __forceinline__ Record fetch_record(const RoundTables &t, int r, bool active)
+// Every wave fetches exactly one record per round (also a wave without a
+// constraint in round r: the table is L2-resident), so the loads retire in
+// order and each round waits only for the fetch issued two rounds before it.
+// The address depends only on (round, lane), so the fetch can run rounds
+// ahead; rows R and R + 1 of the table repeat rows 0 and 1, so round r
+// fetches row r + 2 with no wrap.
+__device__ __forceinline__ Record fetch_record(const RoundTables &t, int r)
 {
-    const XPBD_GLOBAL Record *p = t.rr + (active ? r : 0) * t.B + t.tid;
+    const XPBD_GLOBAL Record *p = t.rr + r * t.B + t.tid;
     Record rec;
     rec.w0 = p->w0;
     rec.w1 = p->w1;
@@ -857,9 +858,7 @@ __device__ __forceinline__ void run_round(float4 *xw, const RoundTables &t, int 
     asm volatile("v_mov_b32 %0, %3\n\tv_mov_b32 %1, %4\n\tv_mov_b32 %2, %5"
                  : "=v"(w0), "=v"(w1), "=v"(w2)
                  : "v"(slot.w0), "v"(slot.w1), "v"(slot.w2));
-    int r2 = r + 2;
-    r2 = r2 >= t.R ? r2 - t.R : r2;
-    slot = fetch_record(t, r2, (active >> r2) & 1u);
+    slot = fetch_record(t, r + 2);
     if (((active >> r) & 1u) && w0 != kInvalidRecord) {
         uint32_t e = 0u, ab = w0;
         if constexpr (EG > 1) {
@@ -963,9 +962,9 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
     const uint64_t tets = md.tet_mask, barriers = md.barrier_mask;
     // (issued in this order, as in every round: the loop then waits for the
     // older fetch only, instead of for both)
-    Record slot_a = fetch_record(tab, 0, active & 1u);         // records of the next two
+    Record slot_a = fetch_record(tab, 0);   // records of the next two rounds (even, odd)
     __builtin_amdgcn_sched_barrier(0);
-    Record slot_b = fetch_record(tab, 1, (active >> 1) & 1u);  // rounds (even, odd)
+    Record slot_b = fetch_record(tab, 1);
 
     uint32_t cand = 0u;  // bit 16 t + k: the particle in slot k * B + tid is a candidate of tool t
     for (int step = 0; step < A.num_steps; ++step) {
@@ -1337,9 +1336,7 @@ __device__ __forceinline__ void eval_round(const float4 *xw, const RoundTables &
     asm volatile("v_mov_b32 %0, %3\n\tv_mov_b32 %1, %4\n\tv_mov_b32 %2, %5"
                  : "=v"(w0), "=v"(w1), "=v"(w2)
                  : "v"(slot.w0), "v"(slot.w1), "v"(slot.w2));
-    int r2 = r + 2;
-    r2 = r2 >= t.R ? r2 - t.R : r2;
-    slot = fetch_record(t, r2, (active >> r2) & 1u);
+    slot = fetch_record(t, r + 2);
     if (((active >> r) & 1u) && w0 != kInvalidRecord) {
         const float l = bank[r & 31];
         float q;
@@ -1497,9 +1494,9 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
     tab.tid = tid;
     const uint64_t active = A.meshes[ed.mesh].wave_active[__builtin_amdgcn_readfirstlane(wave)];
     const uint64_t tets = md.tet_mask, barriers = md.barrier_mask;
-    Record slot_a = fetch_record(tab, 0, active & 1u);   // in this order (see xpbd_step_reg_kernel)
+    Record slot_a = fetch_record(tab, 0);   // in this order (see xpbd_step_reg_kernel)
     __builtin_amdgcn_sched_barrier(0);
-    Record slot_b = fetch_record(tab, 1, (active >> 1) & 1u);
+    Record slot_b = fetch_record(tab, 1);
     const float alpha_d1[1] = {alpha_d}, alpha_v1[1] = {alpha_v};
 
     auto sweep = [&]() {

@@ -614,8 +614,10 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         int32_t edge_rounds = 0;
         for (const int4 &rd : rounds)
             edge_rounds += (rd.z == xpbd::ROUND_EDGE && rd.y > rd.x) ? 1 : 0;
+        // two rows beyond the last round repeat rounds 0 and 1: the kernel
+        // fetches the record of round r + 2 in round r without wrapping
         std::vector<uint32_t> &round_rec = h.round_rec;
-        round_rec.assign((size_t)std::max(num_rounds, 1) * block * 3, 0u);
+        round_rec.assign(((size_t)std::max(num_rounds, 1) + 2) * block * 3, 0u);
         for (size_t q = 0; q < round_rec.size(); q += 3)
             round_rec[q] = xpbd::kInvalidRecord;
         std::vector<int32_t> &rr_id = h.rr_id;
@@ -657,6 +659,9 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
             if (rd.w)
                 d.barrier_mask |= 1ull << r;
         }
+        if (num_rounds >= 2)
+            std::copy(round_rec.begin(), round_rec.begin() + (size_t)2 * block * 3,
+                      round_rec.begin() + (size_t)num_rounds * block * 3);
         d.num_rounds = use_registers ? num_rounds : 0;
         d.num_edge_rounds = edge_rounds;
         d.num_vertices = V;
