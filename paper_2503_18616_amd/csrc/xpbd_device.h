@@ -43,7 +43,8 @@ struct MeshDev {
     // lane l in round r sits at [r][l]; edge (pair, rest length bits, 0),
     // tet (ab, cd, rest volume bits); the top two bits of the first word hold
     // the environment index within the group; lanes without a constraint hold
-    // kInvalidRecord in the first word
+    // a padding record whose slots all name slot G V (an LDS particle at the
+    // origin with zero inverse mass, so its projections change nothing), rest 0
     const uint32_t *round_rec;   // [padded rounds + 2][block][3], the last two rows = rows 0, 1
     const int32_t *rr_id;        // [padded rounds][block] e << 24 | constraint id (tets: E + id), -1
     uint64_t wave_active[16];    // bit r: wave w has a constraint in round r
@@ -54,7 +55,6 @@ struct MeshDev {
     int32_t pad2[2];
 };
 
-constexpr uint32_t kInvalidRecord = 0xffffffffu;
 
 // Rounds of the register-multiplier kernel: a colour is cut into rounds of at
 // most blockDim constraints (lane l takes the l-th); a workgroup barrier
@@ -206,7 +206,7 @@ hipError_t launch_step(const StepArgs &args, int block, int particles_per_thread
 // kRegScratchGrasp.. the grasp state (int32 [G] held slots, int32 [G] search
 // flags, uint64 [16 waves][G] partial minima of the grasp search).
 struct RegLdsLayout {
-    uint32_t xw;       // float4 [V]  position + inverse mass
+    uint32_t xw;       // float4 [V + 1]  position + inverse mass; slot V: padding particle
     uint32_t vel;      // float [3][V]
     uint32_t prev;     // float [3][V]  positions at the start of the substep
     uint32_t scratch;  // kRegScratchBytes
@@ -222,7 +222,7 @@ __host__ __device__ inline RegLdsLayout reg_lds_layout(int32_t V)
 {
     RegLdsLayout l;
     l.xw = 0;
-    l.vel = 16u * (uint32_t)V;
+    l.vel = 16u * ((uint32_t)V + 1u);
     l.prev = l.vel + 12u * (uint32_t)V;
     l.scratch = align_up(l.prev + 12u * (uint32_t)V, 16);
     l.total = l.scratch + kRegScratchBytes;

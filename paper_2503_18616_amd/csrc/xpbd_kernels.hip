@@ -806,6 +806,7 @@ struct RoundTables {
     int R;                            // rounds (even)
     int B;
     int tid;
+    uint32_t pad;                     // slot of the padding particle
 };
 
 // Every wave fetches exactly one record per round (also a wave without a
@@ -859,7 +860,7 @@ __device__ __forceinline__ void run_round(float4 *xw, const RoundTables &t, int 
                  : "=v"(w0), "=v"(w1), "=v"(w2)
                  : "v"(slot.w0), "v"(slot.w1), "v"(slot.w2));
     slot = fetch_record(t, r + 2);
-    if (((active >> r) & 1u) && w0 != kInvalidRecord) {
+    if ((active >> r) & 1u) {   // padding lanes project the padding particle: no effect
         uint32_t e = 0u, ab = w0;
         if constexpr (EG > 1) {
             e = w0 >> 30;
@@ -938,6 +939,8 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
             vel[VS + sl] = A.vel[NP + off[e] + i];
             vel[2 * VS + sl] = A.vel[2 * NP + off[e] + i];
         }
+    if (tid == 0)
+        xw[VS] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // padding particle
     // environment of each of this thread's slots k * B + tid: bits 2k, 2k + 1
     uint32_t slot_env = 0u;
     if constexpr (EG > 1)
@@ -958,6 +961,7 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
     tab.R = R;
     tab.B = B;
     tab.tid = tid;
+    tab.pad = (uint32_t)VS;
     const uint64_t active = A.meshes[A.envs[env[0]].mesh].wave_active[__builtin_amdgcn_readfirstlane(wave)];
     const uint64_t tets = md.tet_mask, barriers = md.barrier_mask;
     // (issued in this order, as in every round: the loop then waits for the
@@ -1337,7 +1341,7 @@ __device__ __forceinline__ void eval_round(const float4 *xw, const RoundTables &
                  : "=v"(w0), "=v"(w1), "=v"(w2)
                  : "v"(slot.w0), "v"(slot.w1), "v"(slot.w2));
     slot = fetch_record(t, r + 2);
-    if (((active >> r) & 1u) && w0 != kInvalidRecord) {
+    if (((active >> r) & 1u) && (w0 & 0xffffu) != t.pad) {
         const float l = bank[r & 31];
         float q;
         if ((tets >> r) & 1u) {
@@ -1403,6 +1407,8 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
         prev[V + sl] = A.pos[NP + off + i];
         prev[2 * V + sl] = A.pos[2 * NP + off + i];
     }
+    if (tid == 0)
+        xw[V] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // padding particle
     lambda_bank bank0 = 0.0f, bank1 = 0.0f;
 
     // sphere centres of this step and the contact candidates (bit 16 t + k: slot k B + tid)
@@ -1492,6 +1498,7 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
     tab.R = R;
     tab.B = B;
     tab.tid = tid;
+    tab.pad = (uint32_t)V;
     const uint64_t active = A.meshes[ed.mesh].wave_active[__builtin_amdgcn_readfirstlane(wave)];
     const uint64_t tets = md.tet_mask, barriers = md.barrier_mask;
     Record slot_a = fetch_record(tab, 0);   // in this order (see xpbd_step_reg_kernel)

@@ -618,8 +618,9 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         // fetches the record of round r + 2 in round r without wrapping
         std::vector<uint32_t> &round_rec = h.round_rec;
         round_rec.assign(((size_t)std::max(num_rounds, 1) + 2) * block * 3, 0u);
+        const uint32_t pad = (uint32_t)GV | ((uint32_t)GV << 16);   // padding particle
         for (size_t q = 0; q < round_rec.size(); q += 3)
-            round_rec[q] = xpbd::kInvalidRecord;
+            round_rec[q] = pad;
         std::vector<int32_t> &rr_id = h.rr_id;
         rr_id.assign((size_t)std::max(num_rounds, 1) * block, -1);
         MeshDev &d = h.d;
@@ -627,6 +628,8 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         for (int32_t r = 0; r < num_rounds && use_registers; ++r) {
             const int4 rd = rounds[(size_t)r];
             const bool is_edge = r < edge_rounds;
+            for (int32_t l = rd.y - rd.x; l < block && !is_edge; ++l)
+                round_rec[((size_t)r * block + l) * 3 + 1] = pad;   // tet padding: c = d = pad
             for (int32_t l = 0; l < block && rd.x + l < rd.y; ++l) {
                 const int32_t j = rd.x + l;   // slot within its kind
                 uint32_t *at = &round_rec[((size_t)r * block + l) * 3];
