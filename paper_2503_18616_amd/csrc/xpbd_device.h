@@ -40,7 +40,9 @@ struct MeshDev {
     const uint16_t *slot_of;     // [G V]
     const uint16_t *id_of;       // [G V]  inverse of slot_of
     // round-major records of the register-multiplier kernel: the record of
-    // lane l in round r sits at [r][l]; edge (pair, rest length bits, 0),
+    // lane l in round r sits at [r][l]; particles as LDS byte offsets with one
+    // environment per workgroup, as slot indices with more; edge (pair, rest
+    // length bits, 0),
     // tet (ab, cd, rest volume bits); the top two bits of the first word hold
     // the environment index within the group; lanes without a constraint hold
     // a padding record whose slots all name slot G V (an LDS particle at the

@@ -34,25 +34,48 @@ constexpr float kThirtySixth = 1.0f / 36.0f;
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Particle f of the LDS array xw, f counting kUnit bytes (16: a slot index,
+// 1: a byte offset).
+template <int kUnit>
+__device__ __forceinline__ float4 &lds_particle(float4 *xw, uint32_t f)
+{
+    return *reinterpret_cast<float4 *>(reinterpret_cast<unsigned char *>(xw) + f * kUnit);
+}
+// Store the position of p into particle r (its inverse mass is unchanged).
+__device__ __forceinline__ void store_position(float4 &r, const float4 &p)
+{
+    r.x = p.x;
+    r.y = p.y;
+    r.z = p.z;
+}
+
+template <int kUnit>
+__device__ __forceinline__ const float4 &lds_particle(const float4 *xw, uint32_t f)
+{
+    return *reinterpret_cast<const float4 *>(reinterpret_cast<const unsigned char *>(xw) + f * kUnit);
+}
+
 // Distance constraint C = |x_a - x_b| - d (Eq. 1), one XPBD projection of
-// edge (a, b) with rest length `rest`; `lam` is the edge's multiplier.
-__device__ __forceinline__ void edge_update(float4 *xw, int a, int b, float rest,
+// edge (a, b) with rest length `rest`; `lam` is the edge's multiplier.  An
+// edge shorter than the minimum length or with a vanishing denominator is
+// left as it is (its correction is selected to zero, so no branch is taken).
+template <int kUnit = 16>
+__device__ __forceinline__ void edge_update(float4 *xw, uint32_t a, uint32_t b, float rest,
                                             float alpha_tilde, float &lam)
 {
-    float4 pa = xw[a];
-    float4 pb = xw[b];
+    float4 &ra = lds_particle<kUnit>(xw, a);
+    float4 &rb = lds_particle<kUnit>(xw, b);
+    float4 pa = ra;
+    float4 pb = rb;
     const float dx = pa.x - pb.x, dy = pa.y - pb.y, dz = pa.z - pb.z;
     const float l2 = dx * dx + dy * dy + dz * dz;
-    if (!(l2 >= kMinEdgeLength2))
-        return;
     const float inv_len = fast_rsq(l2);
     const float C = l2 * inv_len - rest;
     const float denom = pa.w + pb.w + alpha_tilde;
-    if (!(denom > kMinDenominator))
-        return;
-    const float dl = (-C - alpha_tilde * lam) * fast_rcp(denom);
-    lam += dl;
-    const float s = dl * inv_len;          // dlambda times the unit direction's scale
+    const bool ok = l2 >= kMinEdgeLength2 && denom > kMinDenominator;
+    const float dl = ok ? (-C - alpha_tilde * lam) * fast_rcp(denom) : 0.0f;
+    lam = ok ? lam + dl : lam;
+    const float s = ok ? dl * inv_len : 0.0f;   // dlambda times the unit direction's scale
     const float sa = pa.w * s, sb = pb.w * s;
     pa.x += sa * dx;
     pa.y += sa * dy;
@@ -60,22 +83,25 @@ __device__ __forceinline__ void edge_update(float4 *xw, int a, int b, float rest
     pb.x -= sb * dx;
     pb.y -= sb * dy;
     pb.z -= sb * dz;
-    xw[a] = pa;
-    xw[b] = pb;
+    store_position(ra, pa);
+    store_position(rb, pb);
 }
 
 // Volume constraint C = (1/6)(x_ba x x_ca).x_da - V0 (Eqs. 2-3 with the
 // analytic gradients), one XPBD projection of tetrahedron (a | b << 16,
 // c | d << 16) with rest volume `rest`.  G_i are six times the gradients.
+template <int kUnit = 16>
 __device__ __forceinline__ void tet_update(float4 *xw, uint32_t ab, uint32_t cd, float rest,
                                            float alpha_tilde, float &lam)
 {
-    const int a = (int)(ab & 0xffffu), b = (int)(ab >> 16);
-    const int c = (int)(cd & 0xffffu), d = (int)(cd >> 16);
-    float4 pa = xw[a];
-    float4 pb = xw[b];
-    float4 pc = xw[c];
-    float4 pd = xw[d];
+    float4 &ra = lds_particle<kUnit>(xw, ab & 0xffffu);
+    float4 &rb = lds_particle<kUnit>(xw, ab >> 16);
+    float4 &rc = lds_particle<kUnit>(xw, cd & 0xffffu);
+    float4 &rd = lds_particle<kUnit>(xw, cd >> 16);
+    float4 pa = ra;
+    float4 pb = rb;
+    float4 pc = rc;
+    float4 pd = rd;
     const float bax = pb.x - pa.x, bay = pb.y - pa.y, baz = pb.z - pa.z;
     const float cax = pc.x - pa.x, cay = pc.y - pa.y, caz = pc.z - pa.z;
     const float dax = pd.x - pa.x, day = pd.y - pa.y, daz = pd.z - pa.z;
@@ -90,10 +116,9 @@ __device__ __forceinline__ void tet_update(float4 *xw, uint32_t ab, uint32_t cd,
                      pc.w * (gcx * gcx + gcy * gcy + gcz * gcz) +
                      pd.w * (gdx * gdx + gdy * gdy + gdz * gdz);
     const float denom = wg * kThirtySixth + alpha_tilde;
-    if (!(denom > kMinDenominator))
-        return;
-    const float dl = (-C - alpha_tilde * lam) * fast_rcp(denom);
-    lam += dl;
+    const bool ok = denom > kMinDenominator;   // else no correction (selected, no branch)
+    const float dl = ok ? (-C - alpha_tilde * lam) * fast_rcp(denom) : 0.0f;
+    lam = ok ? lam + dl : lam;
     const float s = dl * kSixth;
     const float sa = pa.w * s, sb = pb.w * s, sc = pc.w * s, sd = pd.w * s;
     pa.x += sa * gax;
@@ -108,10 +133,10 @@ __device__ __forceinline__ void tet_update(float4 *xw, uint32_t ab, uint32_t cd,
     pd.x += sd * gdx;
     pd.y += sd * gdy;
     pd.z += sd * gdz;
-    xw[a] = pa;
-    xw[b] = pb;
-    xw[c] = pc;
-    xw[d] = pd;
+    store_position(ra, pa);
+    store_position(rb, pb);
+    store_position(rc, pc);
+    store_position(rd, pd);
 }
 
 // Jacobi forms of the two projections (Sec. III-A.1): the correction of every
@@ -806,7 +831,7 @@ struct RoundTables {
     int R;                            // rounds (even)
     int B;
     int tid;
-    uint32_t pad;                     // slot of the padding particle
+    uint32_t pad;                     // padding particle in the records' units
 };
 
 // Every wave fetches exactly one record per round (also a wave without a
@@ -866,12 +891,14 @@ __device__ __forceinline__ void run_round(float4 *xw, const RoundTables &t, int 
             e = w0 >> 30;
             ab = w0 & 0x3fffffffu;
         }
+        // one environment per workgroup: the records hold LDS byte offsets
+        constexpr int kUnit = EG == 1 ? 1 : 16;
         float l = bank[r & 31];
         if ((tets >> r) & 1u)
-            tet_update(xw, ab, w1, __uint_as_float(w2), pick<EG>(alpha_v, e), l);
+            tet_update<kUnit>(xw, ab, w1, __uint_as_float(w2), pick<EG>(alpha_v, e), l);
         else
-            edge_update(xw, (int)(ab & 0xffffu), (int)(ab >> 16), __uint_as_float(w1),
-                        pick<EG>(alpha_d, e), l);
+            edge_update<kUnit>(xw, ab & 0xffffu, ab >> 16, __uint_as_float(w1),
+                               pick<EG>(alpha_d, e), l);
         bank[r & 31] = l;
     }
     if ((barriers >> r) & 1u)
@@ -961,7 +988,7 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
     tab.R = R;
     tab.B = B;
     tab.tid = tid;
-    tab.pad = (uint32_t)VS;
+    tab.pad = EG == 1 ? 16u * (uint32_t)VS : (uint32_t)VS;   // in the records' units
     const uint64_t active = A.meshes[A.envs[env[0]].mesh].wave_active[__builtin_amdgcn_readfirstlane(wave)];
     const uint64_t tets = md.tet_mask, barriers = md.barrier_mask;
     // (issued in this order, as in every round: the loop then waits for the
@@ -1345,8 +1372,8 @@ __device__ __forceinline__ void eval_round(const float4 *xw, const RoundTables &
         const float l = bank[r & 31];
         float q;
         if ((tets >> r) & 1u) {
-            const float4 pa = xw[w0 & 0xffffu], pb = xw[w0 >> 16];
-            const float4 pc = xw[w1 & 0xffffu], pd = xw[w1 >> 16];
+            const float4 pa = lds_particle<1>(xw, w0 & 0xffffu), pb = lds_particle<1>(xw, w0 >> 16);
+            const float4 pc = lds_particle<1>(xw, w1 & 0xffffu), pd = lds_particle<1>(xw, w1 >> 16);
             const float bax = pb.x - pa.x, bay = pb.y - pa.y, baz = pb.z - pa.z;
             const float cax = pc.x - pa.x, cay = pc.y - pa.y, caz = pc.z - pa.z;
             const float dax = pd.x - pa.x, day = pd.y - pa.y, daz = pd.z - pa.z;
@@ -1355,7 +1382,7 @@ __device__ __forceinline__ void eval_round(const float4 *xw, const RoundTables &
             const float rest = __uint_as_float(w2);
             q = (vol - rest + alpha_v * l) / rest;
         } else {
-            const float4 pa = xw[w0 & 0xffffu], pb = xw[w0 >> 16];
+            const float4 pa = lds_particle<1>(xw, w0 & 0xffffu), pb = lds_particle<1>(xw, w0 >> 16);
             const float dx = pa.x - pb.x, dy = pa.y - pb.y, dz = pa.z - pb.z;
             const float rest = __uint_as_float(w1);
             q = (sqrtf(dx * dx + dy * dy + dz * dz) - rest + alpha_d * l) / rest;
@@ -1498,7 +1525,7 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
     tab.R = R;
     tab.B = B;
     tab.tid = tid;
-    tab.pad = (uint32_t)V;
+    tab.pad = 16u * (uint32_t)V;   // byte offset (one environment per workgroup)
     const uint64_t active = A.meshes[ed.mesh].wave_active[__builtin_amdgcn_readfirstlane(wave)];
     const uint64_t tets = md.tet_mask, barriers = md.barrier_mask;
     Record slot_a = fetch_record(tab, 0);   // in this order (see xpbd_step_reg_kernel)

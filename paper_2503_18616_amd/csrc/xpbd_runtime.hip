@@ -402,6 +402,11 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     if (use_registers) {
         stage = false;
         lds = xpbd::reg_lds_layout(reg_group * vmax).total;
+        // the round records hold 16-bit particle fields: LDS byte offsets with
+        // one environment per workgroup (the LDS limit keeps them below 65536)
+        if (reg_group == 1 && 16 * ((int64_t)vmax + 1) > 0xffff)
+            return fail(XPBD_E_CAPACITY, "mesh of %d particles is too large for the register "
+                        "variant", vmax);
     }
     if (lds > (uint32_t)lds_limit)
         return fail(XPBD_E_CAPACITY, "environment needs %u bytes of LDS; the device has %d",
@@ -618,7 +623,11 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         // fetches the record of round r + 2 in round r without wrapping
         std::vector<uint32_t> &round_rec = h.round_rec;
         round_rec.assign(((size_t)std::max(num_rounds, 1) + 2) * block * 3, 0u);
-        const uint32_t pad = (uint32_t)GV | ((uint32_t)GV << 16);   // padding particle
+        // particle fields: LDS byte offsets with one environment per workgroup,
+        // slot indices (16 bytes each) with more
+        // (16 (G V + 1) <= 65535: checked where the variant is chosen)
+        const uint32_t unit = G == 1 ? 16u : 1u;
+        const uint32_t pad = (uint32_t)GV * unit | ((uint32_t)GV * unit << 16);   // padding particle
         for (size_t q = 0; q < round_rec.size(); q += 3)
             round_rec[q] = pad;
         std::vector<int32_t> &rr_id = h.rr_id;
@@ -636,8 +645,8 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
                 if (is_edge) {
                     const int32_t q = geslot[(size_t)j], e = q / E, id = q - e * E;
                     const uint8_t *o = xpbd::vertex_order(2, eorder[(size_t)q]);
-                    const uint32_t a = (uint32_t)slot_of[(size_t)gedges[2 * (size_t)q + o[0]]];
-                    const uint32_t bb = (uint32_t)slot_of[(size_t)gedges[2 * (size_t)q + o[1]]];
+                    const uint32_t a = unit * (uint32_t)slot_of[(size_t)gedges[2 * (size_t)q + o[0]]];
+                    const uint32_t bb = unit * (uint32_t)slot_of[(size_t)gedges[2 * (size_t)q + o[1]]];
                     const float rest = (float)pm.rest_length[(size_t)id];
                     at[0] = a | (bb << 16) | ((uint32_t)e << 30);
                     std::memcpy(&at[1], &rest, 4);
@@ -648,7 +657,7 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
                     const uint8_t *o = xpbd::vertex_order(4, torder[(size_t)q]);
                     uint32_t v[4];
                     for (int k = 0; k < 4; ++k)
-                        v[k] = (uint32_t)slot_of[(size_t)gtets[4 * (size_t)q + o[k]]];
+                        v[k] = unit * (uint32_t)slot_of[(size_t)gtets[4 * (size_t)q + o[k]]];
                     const float rest = (float)pm.rest_volume[(size_t)id];
                     at[0] = v[0] | (v[1] << 16) | ((uint32_t)e << 30);
                     at[1] = v[2] | (v[3] << 16);
