@@ -828,7 +828,6 @@ struct Record {
 
 struct RoundTables {
     const XPBD_GLOBAL Record *rr;
-    int R;                            // rounds (even)
     int B;
     int tid;
     uint32_t pad;                     // padding particle in the records' units
@@ -985,7 +984,6 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
     // round tables and this wave's masks (uniform); prime the two-round prefetch
     RoundTables tab;
     tab.rr = (const XPBD_GLOBAL Record *)(uintptr_t)md.round_rec;
-    tab.R = R;
     tab.B = B;
     tab.tid = tid;
     tab.pad = EG == 1 ? 16u * (uint32_t)VS : (uint32_t)VS;   // in the records' units
@@ -1522,7 +1520,6 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
 
     RoundTables tab;
     tab.rr = (const XPBD_GLOBAL Record *)(uintptr_t)md.round_rec;
-    tab.R = R;
     tab.B = B;
     tab.tid = tid;
     tab.pad = 16u * (uint32_t)V;   // byte offset (one environment per workgroup)
