@@ -384,6 +384,34 @@ def run_env(mesh: OracleMesh, compliance, params: OracleParams, tool_pos, num_st
                         resid[:num_steps] if resid is not None else None)
 
 
+def iterate(mesh: OracleMesh, x, alpha_tilde_d, alpha_tilde_v, lam=None, centres=None,
+            radii=None, candidates=None):
+    """One Gauss-Seidel iteration of ``oracle_iterate`` on one environment:
+    x [V][3] and the multipliers lam [E+T] are updated in place (lam zeros
+    if None); centres [tools][3], radii [tools] and candidates (one id list
+    per tool) describe the sphere tools (none if None).  Returns (x, lam)."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    V, E, T = mesh.num_vertices, mesh.num_edges, mesh.num_tets
+    lam = np.zeros(max(E + T, 1)) if lam is None else lam
+    nt = 0 if centres is None else len(centres)
+    cand = np.zeros((max(nt, 1), V), np.int32)
+    ncand = (ctypes.c_int * max(nt, 1))()
+    for t in range(nt):
+        ids = np.asarray(candidates[t], np.int32)
+        cand[t, :len(ids)] = ids
+        ncand[t] = len(ids)
+    c = _f64(np.asarray(centres, float).reshape(-1, 3)) if nt else np.zeros((1, 3))
+    r = _f64(np.asarray(radii, float).reshape(-1)) if nt else np.zeros(1)
+    lib.oracle_iterate(_dp(x), _dp(mesh.w), E, _ip(mesh.edges), _dp(mesh.rest_length),
+                       _dp(mesh.rest_volume), _ip(mesh.tets),
+                       mesh.num_edge_colours, _ip(mesh.edge_ptr), _ip(mesh.edge_order),
+                       mesh.num_tet_colours, _ip(mesh.tet_ptr), _ip(mesh.tet_order),
+                       float(alpha_tilde_d), float(alpha_tilde_v), _dp(lam),
+                       V, nt, _dp(c), _dp(r), _ip(cand), ncand)
+    return x, lam
+
+
 def iterate_jacobi(x, w, edges, rest_length, tets, rest_volume, alpha_tilde_d=0.0,
                    alpha_tilde_v=0.0, lam=None):
     """One iteration of ``oracle_iterate_jacobi`` without tools, on raw arrays:

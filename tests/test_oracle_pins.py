@@ -464,3 +464,65 @@ def test_contact_candidates_f32_matches_fp64_outside_band(oracle_lib, c1):
     ids32 = oracle_lib.contact_candidates_f32(om.rest, om.w, tp[0], p.tool_radius[0])
     ids64 = r.contacts[0, 0, :r.contact_count[0, 0]]
     assert np.array_equal(ids32, ids64)
+
+
+# ------------------------------------------------------------------ order inside an iteration
+def _compose(oracle_lib, om, x, at_d, at_v, centre, radius, cand, order):
+    """One iteration built from the individually pinned projections (P1, P2,
+    P13) in the given order of the three phases."""
+    x = x.copy()
+    lam = np.zeros(om.num_edges + om.num_tets)
+    for phase in order:
+        if phase == "edges":
+            for c in range(om.num_edge_colours):
+                for p in range(om.edge_ptr[c], om.edge_ptr[c + 1]):
+                    e = int(om.edge_order[p])
+                    a, b = om.edges[e]
+                    x, lam[e] = oracle_lib.project_distance(x, om.w, a, b, om.rest_length[e],
+                                                            at_d, lam[e])
+        elif phase == "tets":
+            for c in range(om.num_tet_colours):
+                for p in range(om.tet_ptr[c], om.tet_ptr[c + 1]):
+                    t = int(om.tet_order[p])
+                    j = om.num_edges + t
+                    x, lam[j] = oracle_lib.project_volume(x, om.w, om.tets[t], om.rest_volume[t],
+                                                          at_v, lam[j])
+        else:
+            for i in cand:
+                x[i] = oracle_lib.project_contact(x[i], centre, radius)
+    return x, lam
+
+
+@pytest.mark.parametrize("grid", [(1, 1, 1), (2, 1, 1)])
+def test_iteration_runs_edges_then_tets_then_contact(oracle_lib, grid):
+    """One oracle iteration is the distance colours in ascending order (the
+    first projection loop of Alg. 1), then the volume colours (its second
+    loop), then the push-out of the candidates, after the deformation
+    constraints (Sec. III-A.3).  The state is chosen so that every other
+    order of the three phases ends elsewhere, so a swapped loop fails here."""
+    m = W.slab_mesh(*grid)
+    om = oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass, m.tets)
+    rng = np.random.default_rng(41)
+    free = om.w > 0
+    x0 = om.rest + np.where(free[:, None], rng.uniform(-2e-3, 2e-3, om.rest.shape), 0.0)
+    r = W.TOOL_RADIUS
+    # the sphere presses the first free particle: 0.4 r from its centre
+    i0 = int(np.flatnonzero(free)[0])
+    centre = x0[i0] + np.array([0.3, -0.2, 0.25 * np.sqrt(3.0)]) * r * 0.8
+    cand = [i for i in np.flatnonzero(free) if np.linalg.norm(x0[i] - centre) < 2 * r]
+    assert cand == [i0]
+    at_d, at_v = 1e-6 / H ** 2, 1e-7 / H ** 2
+    x, lam = oracle_lib.iterate(om, x0.copy(), at_d, at_v, centres=[centre], radii=[r],
+                                candidates=[cand])
+    want_x, want_lam = _compose(oracle_lib, om, x0, at_d, at_v, centre, r, cand,
+                                ("edges", "tets", "contact"))
+    assert np.array_equal(x, want_x)
+    assert np.array_equal(lam[:om.num_edges + om.num_tets], want_lam)
+    # the particle ends on the sphere: the push-out came last
+    assert np.linalg.norm(x[i0] - centre) == pytest.approx(r, rel=1e-14)
+    import itertools
+    for order in itertools.permutations(("edges", "tets", "contact")):
+        if order == ("edges", "tets", "contact"):
+            continue
+        other, _ = _compose(oracle_lib, om, x0, at_d, at_v, centre, r, cand, order)
+        assert np.abs(other - want_x).max() > 1e-7, order

@@ -149,6 +149,42 @@ def test_adam_first_step_moves_by_lr_against_the_gradient_sign():
     assert np.allclose(p[0], [1.0 - 0.01, -2.0 + 0.01, 3.0 - 0.01], rtol=0, atol=1e-9)
 
 
+def test_adam_constant_gradient_has_unbiased_moments():
+    """With the same gradient g every step, the bias-corrected moments are g
+    and g^2 exactly (Kingma and Ba 2015, Sec. 3), so every step moves by
+    lr g / (|g| + eps), for any beta1 and beta2."""
+    g = np.array([0.5, -4.0, 2e-3, 0.0])
+    for beta1, beta2 in ((0.9, 0.999), (0.5, 0.9)):
+        p = [np.array([1.0, -2.0, 3.0, 0.25])]
+        opt = ws.Adam(lr=0.01, beta1=beta1, beta2=beta2, eps=1e-6)
+        for t in range(1, 6):
+            before = p[0].copy()
+            opt.step(p, [g.copy()])
+            assert np.allclose(p[0], before - 0.01 * g / (np.abs(g) + 1e-6), rtol=0, atol=1e-14)
+
+
+def test_adam_moments_are_the_bias_corrected_exponential_averages():
+    """Five steps of varying gradients against the non-recursive form of
+    Adam's moments: m_t = (1 - b1) sum_k b1^(t-k) g_k and v_t = (1 - b2)
+    sum_k b2^(t-k) g_k^2, divided by 1 - b1^t and 1 - b2^t (Kingma and Ba
+    2015, Alg. 1 and Sec. 3).  A missing accumulation of either moment, a
+    wrong decay or a missing bias correction changes the second step on."""
+    rng = np.random.default_rng(9)
+    grads = [rng.normal(size=6) * rng.uniform(0.01, 3.0, size=6) for _ in range(5)]
+    lr, b1, b2, eps = 0.01, 0.9, 0.999, 1e-8
+    p = [np.linspace(-1.0, 1.0, 6)]
+    want = p[0].copy()
+    opt = ws.Adam(lr=lr, beta1=b1, beta2=b2, eps=eps)
+    for t in range(1, 6):
+        opt.step(p, [grads[t - 1].copy()])
+        m = sum((1 - b1) * b1 ** (t - k) * grads[k - 1] for k in range(1, t + 1))
+        v = sum((1 - b2) * b2 ** (t - k) * grads[k - 1] ** 2 for k in range(1, t + 1))
+        want = want - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+        np.testing.assert_allclose(p[0], want, rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(opt.m[0], m, rtol=1e-13, atol=1e-16)
+        np.testing.assert_allclose(opt.v[0], v, rtol=1e-13, atol=1e-18)
+
+
 @pytest.fixture(scope="module")
 def small():
     wl = W.single_env_workload(seed=0)
