@@ -39,13 +39,21 @@ FLOPS_PARTICLE = 18    # prediction + velocity update of a free particle, per su
 LDS_EDGE = 2 * 16 + 2 * 12 + 2 * 4 + 8      # 72 B
 LDS_TET = 4 * 16 + 4 * 12 + 2 * 4 + 12      # 132 B
 LDS_PARTICLE = 16 + 16 + 16 + 16            # predict read + write, velocity read, + lambda reset share
+# of which written (positions, the multiplier; the particle's position and velocity)
+LDS_EDGE_W = 2 * 12 + 4
+LDS_TET_W = 4 * 12 + 4
+LDS_PARTICLE_W = 32
 # Algorithmic HBM bytes per environment and launch: positions and velocities in
 # and out (48 B per particle), inverse masses (4 B), tool poses (12 B per tool and step).
 HBM_PARTICLE = 48 + 4
 
-PEAK_FP32_NONPACKED = 256 * 64 * 2 * 2.4e9   # 78.6 TFLOP/s: 256 CU x 64 lanes x FMA x 2.4 GHz
+CLOCK = 2.4e9                                # peak engine clock, Hz
+CUS = 256
+PEAK_FP32 = 157.3e12                         # published FP32 vector peak (packed FP32 issue)
+PEAK_FP32_NONPACKED = CUS * 64 * 2 * CLOCK   # 78.6 TFLOP/s: 256 CU x 64 lanes x FMA x 2.4 GHz
 PEAK_HBM = 8.0e12                            # B/s
-PEAK_LDS = 256 * 128 * 2.4e9                 # 78.6 TB/s at 128 B/clk/CU
+LDS_PEAK_RECORD = "lds_peak.json"            # measured LDS bytes per clock per CU (--lds-peak)
+LDS_ASSUMED_B_PER_CLK = 128.0                # used only when no measurement is recorded
 
 
 def parse_args():
@@ -69,6 +77,9 @@ def parse_args():
     ap.add_argument("--packing", type=int, default=0,
                     help="0 = library's choice, 1 = id order, 2 = 8-lane bank groups, 3 = 16-lane, "
                          "4 = scattered + 16-lane, 5 = searched")
+    ap.add_argument("--colouring", type=int, default=0,
+                    help="0 = greedy (default), 1 = largest first, 2 = largest first with "
+                         "colours of 65..100 cut to one wave of 64")
     ap.add_argument("--group", type=int, default=0,
                     help="environments per workgroup (0 = library's choice, 1 or 2)")
     ap.add_argument("--cpu-envs", type=int, default=64, help="oracle sample: environments")
@@ -79,7 +90,7 @@ def parse_args():
                          "(xpbd_autotune) and bench the fastest (0: the default configuration)")
     ap.add_argument("--tool-shape", choices=["sphere", "capsule"], default="sphere",
                     help="spheres against particles, or 2 cm capsules against the surface "
-                         "faces (needs the LDS or Jacobi variant)")
+                         "faces (one environment per workgroup)")
     ap.add_argument("--tool-lift", type=float, default=0.0, metavar="M",
                     help="raise every tool pose by M metres (1.0: no contact anywhere)")
     ap.add_argument("--no-learned", action="store_true",
@@ -97,10 +108,71 @@ def parse_args():
     ap.add_argument("--train-records", type=int, default=24,
                     help="recorded substeps (one per step) of the training run")
     ap.add_argument("--train-steps", type=int, default=1500, help="Adam steps")
+    ap.add_argument("--lds-peak", action="store_true",
+                    help="only run the LDS bandwidth probe (16-byte reads, 12-byte writes) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB mebibytes (reference for the "
                          "HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def lds_peaks():
+    """(read, write) LDS bytes per clock per CU: the conflict-free 16-byte read
+    and 12-byte write rates measured by the library's probe (recorded in
+    profiles/), else the assumed figure for both."""
+    path = os.path.join(ROOT, "profiles", LDS_PEAK_RECORD)
+    if os.path.exists(path):
+        with open(path) as f:
+            rec = json.load(f)
+        return float(rec["read_b128_bytes_per_clk_per_cu"]), float(rec["write_b96_bytes_per_clk_per_cu"]), True
+    return LDS_ASSUMED_B_PER_CLK, LDS_ASSUMED_B_PER_CLK, False
+
+
+def host_threads(work_items):
+    """Threads for the oracle's CPU baseline: every CPU this process may run on,
+    capped by OMP_NUM_THREADS where the host sets it (the GPU machine sets it to
+    the 16-core share one GPU's jobs get), and by the work items.  Returns the
+    count and a description of the host."""
+    allowed = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    share = os.environ.get("OMP_NUM_THREADS")
+    cap = int(share) if share and share.isdigit() and int(share) > 0 else allowed
+    threads = max(1, min(allowed, cap, work_items))
+    return threads, {"host_cpus": os.cpu_count(), "cpus_allowed": allowed,
+                     "omp_num_threads": share, "threads": threads}
+
+
+def lds_roofline(total, written, launch_s):
+    """LDS line of a launch that moves `total` algorithmic bytes, `written` of
+    them written: the shortest time the measured read and write rates allow
+    for that mix, as a fraction of the launch."""
+    rd, wr, measured = lds_peaks()
+    t_min = (total - written) / (rd * CUS * CLOCK) + written / (wr * CUS * CLOCK)
+    return {"achieved": total / launch_s / 1e9, "unit": "GB/s",
+            "peak": total / t_min / 1e9, "frac": t_min / launch_s, "bytes_per_launch": total,
+            "written_bytes_per_launch": written,
+            "peak_read_bytes_per_clk_per_cu": rd, "peak_write_bytes_per_clk_per_cu": wr,
+            "peak_source": "measured (profiles/" + LDS_PEAK_RECORD + ")" if measured
+            else "assumed 128 B/clk/CU"}
+
+
+def lds_peak_probe():
+    """Run the LDS probe (include/xpbd_probe.h) for both access forms and print
+    one JSON line: bytes per clock per CU from the workgroups' own cycle counts
+    and from the event time at the 2.4 GHz peak clock."""
+    import torch
+    from paper_2503_18616_amd import xpbd
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    groups, per_cu = 2 * CUS, 2
+    out = {}
+    for name, kind in (("read_b128", xpbd.PROBE_LDS_READ_B128), ("write_b96", xpbd.PROBE_LDS_WRITE_B96)):
+        ms, nbytes, cycles, ticks = xpbd.xpbd_lds_probe(kind, groups, 20000, stream)
+        out[name] = {"ms": ms, "bytes": nbytes, "workgroups": groups, "reps": 20000,
+                     "cycles_per_workgroup": cycles, "clock_ghz": cycles / ticks * 0.1,
+                     "bytes_per_clk_per_cu": nbytes / groups * per_cu / cycles,
+                     "bytes_per_clk_per_cu_at_2p4ghz": nbytes / (ms * 1e-3) / CLOCK / CUS}
+        progress(f"LDS {name}: {out[name]}")
+    print(json.dumps(out), flush=True)
 
 
 def copy_calibration(mib):
@@ -182,89 +254,129 @@ def learned_leg(args, wl_fn, mesh, make_batch, I, S):
         net = xpbd.Mlp(trainer.he_init(0), *norm)
         feats, targets = trainer.record(tb, net, ttools[warm:], subs, I)
     rows = int((feats[:, 31].float() > 0).sum())
+    torch.cuda.synchronize()
+    t_adam = time.perf_counter()
     losses = trainer.train(net, feats, targets, args.train_steps)
+    torch.cuda.synchronize()
+    adam_s = time.perf_counter() - t_adam
     del feats, targets
     train_s = time.perf_counter() - t0
-    progress(f"learned warm start: trained in {train_s:.1f} s")
+    progress(f"learned warm start: trained in {train_s:.1f} s ({args.train_steps} Adam steps "
+             f"in {adam_s:.3f} s)")
 
     # evaluation: plain and learned from the same state of the benchmark workload
     N = args.envs
     total = args.warmup + args.learned_steps
     wl = wl_fn(N, seed=args.seed, num_steps=total)
     tools = torch.from_numpy(lifted(wl.tools(total), args)).cuda()
-    its = torch.zeros(args.learned_steps * S * N, dtype=torch.int32, device="cuda")
+    L = args.learned_steps
     with make_batch(wl, xpbd.F_RESIDUAL) as pb, make_batch(wl, xpbd.F_RESIDUAL) as lb:
         warm_res = []
         for s in range(args.warmup):
             pb.step(1, tools[s:s + 1])
             warm_res.append(pb.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)[:, 0].copy())
         threshold = float(np.quantile(np.concatenate(warm_res), args.learned_quantile))
-        lb.write(xpbd.FIELD_POS, pb.positions())
-        lb.write(xpbd.FIELD_VEL, pb.velocities())
         x0, v0 = pb.positions(), pb.velocities()
+
+        def restore(b):
+            b.write(xpbd.FIELD_POS, x0)
+            b.write(xpbd.FIELD_VEL, v0)
+
         # residual after k sweeps from the same state, plain and learned, no fallback
         by_sweeps = {"plain": {}, "learned": {}}
-        probe = min(10, args.learned_steps)
+        probe = min(10, L)
         for k in (1, 2, 4, I):
             for mode in ("plain", "learned"):
-                lb.write(xpbd.FIELD_POS, x0)
-                lb.write(xpbd.FIELD_VEL, v0)
+                restore(lb)
                 r = []
                 for s in range(args.warmup, args.warmup + probe):
                     lb.step_learned(net, 1, tools[s:s + 1], k, k, np.inf,
                                     apply_correction=mode == "learned")
                     r.append(lb.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)[:, 0].copy())
                 by_sweeps[mode][str(k)] = float(np.concatenate(r).mean())
-        lb.write(xpbd.FIELD_POS, x0)
-        lb.write(xpbd.FIELD_VEL, v0)
+
+        # the three solvers from the same state: plain (xpbd_step), learned with
+        # the stall rule, learned with fallback whenever the residual is above
+        # the threshold (stall ratio 0)
+        legs = {"learned": args.learned_stall, "learned_stall0": 0.0}
         stream = torch.cuda.current_stream()
         start = torch.cuda.Event(enable_timing=True)
         end = torch.cuda.Event(enable_timing=True)
+        ms = {}
+        for name, stall in legs.items():
+            restore(lb)
+            torch.cuda.synchronize()
+            start.record(stream)
+            lb.step_learned(net, L, tools[args.warmup:total], args.learned_min, I, threshold,
+                            stall_ratio=stall)
+            end.record(stream)
+            torch.cuda.synchronize()
+            ms[name] = start.elapsed_time(end)
+        restore(pb)
         torch.cuda.synchronize()
         start.record(stream)
-        lb.step_learned(net, args.learned_steps, tools[args.warmup:total], args.learned_min, I,
-                        threshold, iterations=its, stall_ratio=args.learned_stall)
+        pb.step(L, tools[args.warmup:total])
         end.record(stream)
         torch.cuda.synchronize()
-        ms = start.elapsed_time(end)
-        start.record(stream)
-        pb.step(args.learned_steps, tools[args.warmup:total])
-        end.record(stream)
-        torch.cuda.synchronize()
-        ms_plain = start.elapsed_time(end)
-        # the residual of every step (last substep), untimed, from the same state
-        r_l, r_p = [], []
-        for b, out in ((lb, r_l), (pb, r_p)):
-            b.write(xpbd.FIELD_POS, x0)
-            b.write(xpbd.FIELD_VEL, v0)
-            for s in range(args.warmup, total):
-                if b is lb:
-                    b.step_learned(net, 1, tools[s:s + 1], args.learned_min, I, threshold,
-                                   stall_ratio=args.learned_stall)
-                else:
-                    b.step(1, tools[s:s + 1])
-                out.append(b.read(xpbd.FIELD_RESIDUAL).reshape(N, 2)[:, 0].copy())
-        r_l, r_p = np.concatenate(r_l), np.concatenate(r_p)
+        ms["plain"] = start.elapsed_time(end)
+        # the same runs again, untimed, with every env-substep's sweeps and final
+        # residual recorded (the runs are deterministic: the same trajectories;
+        # plain through the learned entry point without correction, bit for bit
+        # the plain step)
+        its = torch.zeros(L * S * N, dtype=torch.int32, device="cuda")
+        res = torch.zeros(L * S * N, dtype=torch.float32, device="cuda")
+        stats = {}
+        for name in ("plain", *legs):
+            restore(lb)
+            if name == "plain":
+                lb.step_learned(None, L, tools[args.warmup:total], I, I, np.inf,
+                                apply_correction=False, iterations=its, residuals=res)
+            else:
+                lb.step_learned(net, L, tools[args.warmup:total], args.learned_min, I, threshold,
+                                stall_ratio=legs[name], iterations=its, residuals=res)
+            it, r = its.cpu().numpy(), res.cpu().numpy().astype(np.float64)
+            stats[name] = {"sweeps_mean": float(it.mean()),
+                           "fallback_fraction": float((it > args.learned_min).mean())
+                           if name != "plain" else 0.0,
+                           "residual_mean": float(r.mean()),
+                           "residual_p50": float(np.quantile(r, 0.5)),
+                           "residual_p99": float(np.quantile(r, 0.99)),
+                           "residual_max": float(r.max()),
+                           "above_threshold": float((r > threshold).mean())}
     net.close()
-    it = its.cpu().numpy()
-    return {"value": N * args.learned_steps * S / (ms / 1e3), "unit": "env-substeps/s",
-            "ms_per_step": ms / args.learned_steps, "steps": args.learned_steps,
-            "plain_value_same_steps": N * args.learned_steps * S / (ms_plain / 1e3),
+
+    def rate(t):
+        return N * L * S / (t / 1e3)
+
+    def matched(name):
+        return bool(stats[name]["residual_mean"] <= stats["plain"]["residual_mean"] and
+                    stats[name]["residual_p99"] <= stats["plain"]["residual_p99"])
+    st = stats["learned"]
+    return {"value": rate(ms["learned"]), "unit": "env-substeps/s",
+            "ms_per_step": ms["learned"] / L, "steps": L,
+            "plain_value_same_steps": rate(ms["plain"]),
             "min_iterations": args.learned_min, "max_iterations": I,
             "stall_ratio": args.learned_stall,
             "threshold": threshold, "threshold_rule": f"plain {I}-sweep residual, "
             f"{args.learned_quantile:g} quantile over {args.warmup} warm-up steps",
-            "sweeps_mean": float(it.mean()),
-            "fallback_fraction": float((it > args.learned_min).mean()),
-            "residual_rms_mean": float(r_l.mean()),
-            "plain_residual_rms_mean": float(r_p.mean()),
-            "residual_matched": bool(r_l.mean() <= r_p.mean()),
-            "residual_ratio": float(r_l.mean() / r_p.mean()),
+            "sweeps_mean": st["sweeps_mean"], "fallback_fraction": st["fallback_fraction"],
+            "residual_rms_mean": st["residual_mean"],
+            "plain_residual_rms_mean": stats["plain"]["residual_mean"],
+            "residual_matched": matched("learned"),
+            "residual_matched_rule": "mean and 0.99 quantile of the per-env-substep residual "
+                                     "at most the plain solver's, over the same steps",
+            "residual_ratio": st["residual_mean"] / stats["plain"]["residual_mean"],
+            "stall0": {"value": rate(ms["learned_stall0"]), "ms_per_step": ms["learned_stall0"] / L,
+                       "residual_matched": matched("learned_stall0"),
+                       "sweeps_mean": stats["learned_stall0"]["sweeps_mean"],
+                       "fallback_fraction": stats["learned_stall0"]["fallback_fraction"]},
+            "per_substep_residual": stats,
             "residual_by_sweeps": by_sweeps,
             "training": {"envs": args.train_envs, "recorded_substeps": args.train_records,
                          "free_rows": rows, "adam_steps": args.train_steps,
                          "loss_first": float(np.mean(losses[:5])),
-                         "loss_last": float(np.mean(losses[-50:])), "seconds": train_s},
+                         "loss_last": float(np.mean(losses[-50:])), "seconds": train_s,
+                         "adam_seconds": adam_s},
             "network": "27-128-128-3 ReLU, bf16 MFMA, fp32 accumulate"}
 
 
@@ -434,7 +546,7 @@ def rl_bench(args):
     stream = torch.cuda.current_stream()
     params = xpbd.make_params(wl.dt, S, I, wl.gravity, 2, wl.tool_radius, block_size=args.block,
                               solver_variant=args.variant, colour_packing=args.packing,
-                              envs_per_group=args.group)
+                              envs_per_group=args.group, colouring=args.colouring)
     t_create = time.perf_counter()
     batch = xpbd.Batch([(m.rest_pos, m.inv_mass, m.tets)], wl.env_mesh, wl.compliance, params,
                        stream=stream.cuda_stream)
@@ -451,6 +563,8 @@ def rl_bench(args):
     obs = torch.zeros((1, N, xpbd.RL_OBS), dtype=torch.float32, device="cuda")
     act = torch.zeros((1, N, xpbd.RL_ACTIONS), dtype=torch.float32, device="cuda")
     progress(f"{wl.name}: set up in {t_create:.1f} s")
+    batch.set_flags(xpbd.F_RESIDUAL)   # allocate the multiplier buffer before the timed region
+    batch.set_flags(0)
     for _ in range(args.warmup):
         batch.rl_step(policy, rp, 1, tp, gr, tg, obs, act)
     torch.cuda.synchronize()
@@ -487,7 +601,8 @@ def rl_bench(args):
         def make(w, flags):
             p = xpbd.make_params(w.dt, S, I, w.gravity, 2, w.tool_radius, flags=flags,
                                  block_size=args.block, solver_variant=xpbd.VARIANT_REGISTERS,
-                                 colour_packing=args.packing, envs_per_group=1)
+                                 colour_packing=args.packing, envs_per_group=1,
+                                 colouring=args.colouring)
             return xpbd.Batch([(m.rest_pos, m.inv_mass, m.tets)], w.env_mesh, w.compliance, p,
                               stream=stream.cuda_stream)
         learned = rl_learned_leg(args, make, policy, rp, S, I)
@@ -498,8 +613,9 @@ def rl_bench(args):
     policy_flops = N * 2 * (xpbd.RL_OBS * xpbd.RL_HIDDEN + xpbd.RL_HIDDEN * xpbd.RL_HIDDEN +
                             xpbd.RL_HIDDEN * xpbd.RL_ACTIONS)
     roofline = {"bound": "alu", "achieved": flops / step_s / 1e12,
-                "peak": PEAK_FP32_NONPACKED / 1e12, "unit": "TFLOP/s",
-                "frac": flops / step_s / PEAK_FP32_NONPACKED,
+                "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                "frac": flops / step_s / PEAK_FP32,
+                "frac_nonpacked_issue": flops / step_s / PEAK_FP32_NONPACKED,
                 "traffic": measured_traffic(wl.name, 1, args, "rl_step_traffic.json"),
                 "kernel": "xpbd_step_reg_kernel (grasping), timed with the policy kernel "
                           "of the same step",
@@ -521,7 +637,7 @@ def rl_bench(args):
         net = R.unpack_policy(W.rl_policy_params(args.seed))
         envs = list(range(0, N, max(1, N // args.cpu_envs)))[:args.cpu_envs]
         steps = min(args.cpu_steps, 30)
-        threads = min(16, os.cpu_count() or 1, len(envs))
+        threads, host = host_threads(len(envs))
         t0 = time.perf_counter()
         with ThreadPoolExecutor(max_workers=threads) as pool:
             list(pool.map(lambda e: R.run_env_rl(om, wl.compliance[e], op, orl, net, tools0[e],
@@ -529,7 +645,7 @@ def rl_bench(args):
         dt = time.perf_counter() - t0
         progress(f"oracle sample: {dt:.1f} s")
         cpu = {"value": len(envs) * steps * S / dt, "unit": "env-substeps/s", "cores": threads,
-               "kind": "oracle",
+               "kind": "oracle", "host": host,
                "sample": f"{len(envs)} of the {N} environments x {steps} RL steps "
                          f"({len(envs) * steps * S} env-substeps, FP64, {dt:.1f} s wall)"}
 
@@ -543,6 +659,7 @@ def rl_bench(args):
                    "edges": E, "tets": T, "substeps": S, "iterations": I, "tools": 2,
                    "create_s": round(t_create, 3), "solver": "plain (no warm start)",
                    "launch": launch,
+                   "colouring": ["greedy", "largest-first", "waves"][args.colouring],
                    "policy": "64-256-256-7 bf16 (random init)",
                    "env_steps_per_s": N * args.steps / (ms / 1e3),
                    "policy_gflop_per_step": policy_flops / 1e9,
@@ -565,6 +682,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.lds_peak:
+        lds_peak_probe()
         return
     if args.steps % args.steps_per_launch or args.warmup % args.steps_per_launch:
         sys.exit("--steps and --warmup must be multiples of --steps-per-launch")
@@ -609,7 +729,7 @@ def main():
     params = xpbd.make_params(wl.dt, S, I, wl.gravity, wl.num_tools, wl.tool_radius,
                               flags=0, block_size=args.block,
                               solver_variant=args.variant, colour_packing=args.packing,
-                              envs_per_group=args.group,
+                              envs_per_group=args.group, colouring=args.colouring,
                               tool_shape=xpbd.TOOL_CAPSULE if capsules else xpbd.TOOL_SPHERE)
     stream = torch.cuda.current_stream()
     tuned = None
@@ -631,6 +751,11 @@ def main():
     progress(f"{wl.name}: {N} environments of {len(wl.meshes)} meshes set up in {t_create:.1f} s; "
              f"launch {launch}")
     spl = args.steps_per_launch
+    # the residual of the last timed launch needs the multiplier buffer: enable
+    # it once here, so that switching the flag on inside the timed region
+    # allocates nothing
+    batch.set_flags(xpbd.F_RESIDUAL)
+    batch.set_flags(0)
     for s in range(0, args.warmup, spl):
         batch.step(spl, tools[s:s + spl])
     torch.cuda.synchronize()
@@ -657,15 +782,16 @@ def main():
     Es, Ts, Vs, Fs = (env_sizes[:, k] for k in range(4))
     flops = int(spl * S * (I * (Es * FLOPS_EDGE + Ts * FLOPS_TET) + Fs * FLOPS_PARTICLE).sum())
     lds = int(spl * S * (I * (Es * LDS_EDGE + Ts * LDS_TET) + Vs * LDS_PARTICLE).sum())
+    lds_w = int(spl * S * (I * (Es * LDS_EDGE_W + Ts * LDS_TET_W) + Vs * LDS_PARTICLE_W).sum())
     hbm = int((Vs * HBM_PARTICLE + spl * wl.num_tools * 12).sum())
     roofline = {"bound": "alu", "achieved": flops / launch_s / 1e12,
-                "peak": PEAK_FP32_NONPACKED / 1e12, "unit": "TFLOP/s",
-                "frac": flops / launch_s / PEAK_FP32_NONPACKED,
+                "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                "frac": flops / launch_s / PEAK_FP32,
                 "traffic": measured_traffic(wl.name, spl, args),
-                "kernel": "xpbd_step_kernel", "launch_ms": launch_s * 1e3,
-                "flops_per_launch": flops}
-    lds_line = {"achieved": lds / launch_s / 1e9, "peak": PEAK_LDS / 1e9, "unit": "GB/s",
-                "frac": lds / launch_s / PEAK_LDS, "bytes_per_launch": lds}
+                "kernel": "xpbd_step_reg_kernel", "launch_ms": launch_s * 1e3,
+                "flops_per_launch": flops,
+                "frac_nonpacked_issue": flops / launch_s / PEAK_FP32_NONPACKED}
+    lds_line = lds_roofline(lds, lds_w, launch_s)
     hbm_line = {"achieved": hbm / launch_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                 "frac": hbm / launch_s / PEAK_HBM, "bytes_per_launch": hbm}
 
@@ -680,14 +806,14 @@ def main():
         op = oracle.OracleParams(f32(wl.dt), S, I, tuple(f32(g) for g in wl.gravity),
                                  wl.num_tools, tuple(f32(r) for r in wl.tool_radius))
         cpu_tools = lifted(wl.tools(args.cpu_steps, env_ids=sample_envs), args)
-        threads = min(16, os.cpu_count() or 1, len(sample_envs))
+        threads, host = host_threads(len(sample_envs))
         t0 = time.perf_counter()
         oracle.run_batch(om, wl.env_mesh, wl.compliance, op, cpu_tools, args.cpu_steps,
                          env_ids=sample_envs, threads=threads)
         dt = time.perf_counter() - t0
         progress(f"oracle sample: {dt:.1f} s")
         cpu = {"value": len(sample_envs) * args.cpu_steps * S / dt, "unit": "env-substeps/s",
-               "cores": threads, "kind": "oracle",
+               "cores": threads, "kind": "oracle", "host": host,
                "sample": f"{len(sample_envs)} of the {N} environments x {args.cpu_steps} steps "
                          f"({len(sample_envs) * args.cpu_steps * S} env-substeps, FP64, "
                          f"{dt:.1f} s wall)"}
@@ -696,7 +822,7 @@ def main():
     if not args.no_learned and args.workload == "batch" and not capsules and args.variant in (0, 1):
         def make(w, flags):
             p = xpbd.make_params(w.dt, S, I, w.gravity, w.num_tools, w.tool_radius, flags=flags,
-                                 solver_variant=xpbd.VARIANT_REGISTERS)
+                                 solver_variant=xpbd.VARIANT_REGISTERS, colouring=args.colouring)
             return xpbd.Batch([(m.rest_pos, m.inv_mass, m.tets)], w.env_mesh, w.compliance, p,
                               stream=stream.cuda_stream)
         learned = learned_leg(args, W.batch_workload, m, make, I, S)
@@ -716,6 +842,7 @@ def main():
                    "tool_lift_m": args.tool_lift, "autotune": tuned,
                    "tool_shape": args.tool_shape,
                    "solver_variant": ["auto", "registers", "lds", "jacobi"][args.variant],
+                   "colouring": ["greedy", "largest-first", "waves"][args.colouring],
                    "launch": launch,
                    "residual_rms_mean": float(resid[:, 0].mean()),
                    "residual_max": float(resid[:, 1].max())},

@@ -121,6 +121,8 @@ typedef struct {
                                order; the LDS variant always uses 1. */
     int32_t tool_shape;     /* XPBD_TOOL_*: spheres against particles, or capsules against
                                the surface triangles */
+    int32_t colouring;      /* XPBD_COLOURING_*: how the edge and tetrahedron constraints
+                               are split into colours (0 = greedy) */
 } xpbd_params;
 
 /* Values of xpbd_params.tool_shape.
@@ -138,10 +140,29 @@ typedef struct {
  *            out with k_c = 1 as the constraint d - r >= 0 on its point
  *            closest to the segment (d that distance; the correction of
  *            corner i is proportional to w_i and its barycentric weight).
- *            Needs the LDS or Jacobi variant (AUTO picks LDS); the
- *            contact fields then hold the number of candidate faces per
+ *            Runs on every variant with one environment per workgroup
+ *            (AUTO picks the register variant where the rounds fit);
+ *            the contact fields then hold the number of candidate faces per
  *            tool and no particle lists (all -1). */
 enum { XPBD_TOOL_SPHERE = 0, XPBD_TOOL_CAPSULE = 1 };
+
+/* Values of xpbd_params.colouring.  The colours of a mesh are the sets of
+ * constraints projected in parallel (no two share a particle); the sweeps of
+ * Alg. 1 visit the distance colours, then the volume colours, in ascending
+ * order.  A different colouring is a different Gauss-Seidel order: an equally
+ * valid solve, not the same numbers.
+ *   GREEDY         constraints in index order, each taking the smallest colour
+ *                  no constraint sharing a particle holds (the default)
+ *   LARGEST_FIRST  recursive largest first: each colour in turn is grown into
+ *                  a maximal set from the uncoloured constraints, starting from
+ *                  the one with the most uncoloured conflicts and adding the
+ *                  candidate with the most conflicts among those already ruled
+ *                  out (then the fewest among the candidates, then the lowest
+ *                  index); fewer and larger colours
+ *   WAVES          LARGEST_FIRST, but a colour that would end with 65 to 100
+ *                  members keeps its first 64 (the others stay uncoloured),
+ *                  so that it fills one 64-lane wave instead of most of two */
+enum { XPBD_COLOURING_GREEDY = 0, XPBD_COLOURING_LARGEST_FIRST = 1, XPBD_COLOURING_WAVES = 2 };
 
 /* Values of xpbd_params.colour_packing.  Constraints of one colour share no
  * particle, so their order changes no result; it only decides which lanes
@@ -300,6 +321,12 @@ const char *xpbd_last_error(void);
  */
 xpbd_status xpbd_prepare_mesh(const xpbd_mesh *mesh, int32_t *counts, int32_t *edges,
                               int32_t *tets, int32_t *colours, float *rest);
+
+/* xpbd_prepare_mesh with the colouring of the edge and tetrahedron
+ * constraints named (XPBD_COLOURING_*; XPBD_E_ARG for another value). */
+xpbd_status xpbd_prepare_mesh_coloured(const xpbd_mesh *mesh, int32_t colouring, int32_t *counts,
+                                       int32_t *edges, int32_t *tets, int32_t *colours,
+                                       float *rest);
 
 /*
  * Host-only: the surface triangles the capsule tools act on (the same set-up

@@ -13,8 +13,10 @@
  * capture (the batch's flags, the learned and RL parameters) hold for every
  * replay.  A graph belongs to its batch: destroy it before the batch, the
  * policy and the network it names.  Errors: negative xpbd_status values with
- * xpbd_last_error() set.  Needs a batch of one size class (one launch per
- * step).
+ * xpbd_last_error() set.  A batch of several size classes (uneven meshes:
+ * one launch per class on streams of its own) is captured with its fork and
+ * join, so the classes run as parallel branches of the graph; the learned
+ * step itself needs one size class.
  */
 #ifndef XPBD_GRAPH_H
 #define XPBD_GRAPH_H

@@ -87,12 +87,27 @@ xpbd_status xpbd_mlp_forward(xpbd_mlp *net, const uint16_t *features, int32_t n,
  * row j of features (device bfloat16 [.][32]; a row counts only if its free
  * flag, feature 31, is set) and targets (device float32 [.][4], normalised,
  * columns 0..2).  learning_rate 0 computes the loss and gradient without
- * updating.  loss (host, may be NULL) receives the mean loss (synchronises);
- * grad (device float32 [XPBD_MLP_PARAMS], may be NULL) the normalised
- * gradient.  n >= 1. */
+ * updating.  loss (may be NULL) receives the mean loss: a host pointer after
+ * a synchronisation of the stream, a device pointer (one float) in stream
+ * order without one; grad (device float32 [XPBD_MLP_PARAMS], may be NULL)
+ * the normalised gradient.  n >= 1. */
 xpbd_status xpbd_mlp_train_step(xpbd_mlp *net, const uint16_t *features, const float *targets,
                                 const int32_t *rows, int32_t n, float learning_rate, float *loss,
                                 float *grad);
+
+/* Normalisation of the network's inputs and outputs from a recording made
+ * with the identity normalisation (in_shift 0, in_scale 1): over the n rows
+ * (device bfloat16 features [n][32], float32 targets [n][4]) whose free flag
+ * (feature 31) is set, the mean and the population standard deviation of
+ * every feature and target column, computed on the device in double
+ * precision in a fixed order.  Host outputs: in_shift [27] the feature
+ * means, in_scale [27] 1 / std (1 where the std is 0), out_shift [3] the
+ * target means, out_scale [3] max(std, 1e-12).  Runs on hip_stream (NULL:
+ * the null stream) and synchronises it; allocates and frees a device
+ * workspace of about 60 KB.  XPBD_E_ARG for null or host inputs or n < 1. */
+xpbd_status xpbd_mlp_normalisation(const uint16_t *features, const float *targets, int64_t n,
+                                   void *hip_stream, float *in_shift, float *in_scale,
+                                   float *out_shift, float *out_scale);
 
 void xpbd_mlp_destroy(xpbd_mlp *net);
 
@@ -116,6 +131,9 @@ typedef struct {
                                   that sweep lowered it to at most stall_ratio times that
                                   value (a stalled sweep marks a state the further sweeps
                                   cannot improve, as where the tool holds particles) */
+    float *residuals;          /* device float32 [num_steps][substeps][N]: the residual RMS
+                                  after each substep's last sweep (the check's value when no
+                                  further sweep ran, else evaluated once more), or NULL */
 } xpbd_learned_params;
 
 /* Advance every environment by num_steps steps one substep at a time: the
@@ -129,6 +147,7 @@ typedef struct {
  * iterations and no recording, the result equals xpbd_step's bit for bit. */
 xpbd_status xpbd_step_learned(xpbd_batch *batch, const xpbd_mlp *net, int32_t num_steps,
                               const float *tool_pos, const xpbd_learned_params *params);
+
 
 #ifdef __cplusplus
 }

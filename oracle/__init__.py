@@ -69,6 +69,9 @@ def _load():
                                                ctypes.POINTER(ctypes.c_int)]
             lib.oracle_greedy_colour.restype = ctypes.c_int
             lib.oracle_greedy_colour.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I, _I]
+            lib.oracle_largest_first_colour.restype = ctypes.c_int
+            lib.oracle_largest_first_colour.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                        _I, ctypes.c_int, _I]
             lib.oracle_residual.restype = None
             lib.oracle_residual.argtypes = [_D, ctypes.c_int, _I, _D, ctypes.c_int, _I, _D,
                                             ctypes.c_double, ctypes.c_double, _D, _D]
@@ -195,6 +198,33 @@ def greedy_colour(num_vertices, verts):
     return out[:n], nc
 
 
+# colourings of the edge and tetrahedron constraints (R10, R13)
+COLOURING_GREEDY, COLOURING_LARGEST_FIRST, COLOURING_WAVES = 0, 1, 2
+WAVE_CUT_ABOVE = 100
+
+
+def largest_first_colour(num_vertices, verts, cut_above=0):
+    """Largest-first colours of constraints verts[n][k] (R13); returns (colours, count)."""
+    verts = _i32(verts)
+    n, k = verts.shape
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    nc = _load().oracle_largest_first_colour(int(num_vertices), int(n), int(k), _ip(verts),
+                                             int(cut_above), _ip(out))
+    if nc < 0:
+        raise OracleError(f"oracle_largest_first_colour failed: {nc}")
+    return out[:n], nc
+
+
+def colour(num_vertices, verts, colouring=COLOURING_GREEDY):
+    """Colours of constraints verts[n][k] by the named colouring; (colours, count)."""
+    if len(verts) == 0:
+        return np.zeros(0, np.int32), 0
+    if colouring == COLOURING_GREEDY:
+        return greedy_colour(num_vertices, verts)
+    cut = WAVE_CUT_ABOVE if colouring == COLOURING_WAVES else 0
+    return largest_first_colour(num_vertices, verts, cut)
+
+
 def schedule(colours, num_colours):
     """Processing order: colour ascending, constraint id ascending inside a colour."""
     colours = np.asarray(colours, dtype=np.int64)
@@ -278,8 +308,9 @@ class OracleMesh:
         return int(self.tets.shape[0])
 
 
-def prepare_mesh(rest_pos, inv_mass, tets) -> OracleMesh:
-    """Orientation, rest values, edges and colours of one mesh, from raw input."""
+def prepare_mesh(rest_pos, inv_mass, tets, colouring=COLOURING_GREEDY) -> OracleMesh:
+    """Orientation, rest values, edges and colours of one mesh, from raw input;
+    colouring names the colouring of the edges and tetrahedra (R10, R13)."""
     lib = _load()
     rest = _f64(rest_pos).reshape(-1, 3)
     w = _f64(inv_mass).reshape(-1)
@@ -303,8 +334,8 @@ def prepare_mesh(rest_pos, inv_mass, tets) -> OracleMesh:
         raise OracleError(f"oracle_setup_edges failed: {rc}")
     E = ne.value
     edges, rl = edges[:E].copy(), rl[:E].copy()
-    ecol, nec = greedy_colour(V, edges) if E else (np.zeros(0, np.int32), 0)
-    tcol, ntc = greedy_colour(V, tout) if T else (np.zeros(0, np.int32), 0)
+    ecol, nec = colour(V, edges, colouring)
+    tcol, ntc = colour(V, tout, colouring)
     eptr, eorder = schedule(ecol, nec)
     tptr, torder = schedule(tcol, ntc)
     faces = surface_faces(rest, tout) if T else np.zeros((0, 3), np.int32)

@@ -62,6 +62,7 @@
  *       order and gives each the smallest colour not used by an earlier
  *       constraint sharing any particle; edges and tetrahedra are coloured
  *       separately.
+ *       R13 below is an alternative colouring the same way (largest first).
  *   R11 Capsule tools (the paper's grasper capsules, Sec. III-A.2/3) act on
  *       the surface triangles (faces of exactly one kept tetrahedron, ordered
  *       outward), not on particles: a capsule is a segment p0 p1 and a radius
@@ -86,6 +87,14 @@
  *       at most that one).  The drag constraint (k_s = 1, rest length 0)
  *       runs after the tool contacts of every iteration, so the held
  *       particle ends every iteration on the dragging point.
+ *
+ *   R13 Largest-first colouring, selectable instead of R10 for the edges and
+ *       the tetrahedra (recursive largest first, Leighton 1979): colours are
+ *       built one at a time as maximal sets of disjoint uncoloured
+ *       constraints (rules at oracle_largest_first_colour); optionally a
+ *       colour of 65 .. cut_above members is cut to its first 64, so that it
+ *       fills one 64-wide group of parallel lanes.  A colouring only fixes the
+ *       Gauss-Seidel order (R1); both sides take it from the same rules.
  *
  * Every function below is pinned by the not-gpu tests (closed forms,
  * invariants and brute force on tiny meshes).
@@ -396,6 +405,150 @@ int oracle_greedy_colour(int V, int n, int k, const int32_t *verts, int32_t *col
     return num_colours;
 }
 
+/* Recursive largest-first colouring (R13), an alternative to R10 with fewer
+ * and larger colours.  Colours are built one after the other; colour c is a
+ * maximal set of mutually disjoint constraints (no shared particle) taken
+ * from those without a colour yet:
+ *   - it starts with the uncoloured constraint that conflicts with the most
+ *     other uncoloured constraints (ties: the lowest index);
+ *   - then, while some uncoloured constraint conflicts with no member
+ *     ("candidate"), it adds the candidate that conflicts with the most
+ *     "excluded" constraints (uncoloured ones that conflict with a member),
+ *     ties broken by the fewest conflicts with other candidates, then by the
+ *     lowest index.
+ * With cut_above > 64, a colour that ends with 65 .. cut_above members keeps
+ * only its first 64 (in the order they were added); the others stay
+ * uncoloured for the following colours.  Counts are recomputed from scratch
+ * for every choice.  Returns the number of colours or a negative error. */
+int oracle_largest_first_colour(int V, int n, int k, const int32_t *verts, int cut_above,
+                                int32_t *colour_out)
+{
+    if (V <= 0 || n < 0 || k <= 0 || (n > 0 && (!verts || !colour_out)))
+        return ORACLE_E_ARG;
+    /* neighbours of every constraint (sharing a particle), without repeats */
+    int *start = (int *)calloc((size_t)V + 1, sizeof(int));
+    int *touch = (int *)malloc(sizeof(int) * ((size_t)n * k + 1));
+    int *nb_start = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+    int *mark = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+    int *state = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+    int *order = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+    if (!start || !touch || !nb_start || !mark || !state || !order) {
+        free(start); free(touch); free(nb_start); free(mark); free(state); free(order);
+        return ORACLE_E_NOMEM;
+    }
+    for (int i = 0; i < n * k; ++i)
+        start[verts[i] + 1]++;
+    for (int v = 0; v < V; ++v)
+        start[v + 1] += start[v];
+    {
+        int *pos = (int *)malloc(sizeof(int) * ((size_t)V + 1));
+        if (!pos) {
+            free(start); free(touch); free(nb_start); free(mark); free(state); free(order);
+            return ORACLE_E_NOMEM;
+        }
+        memcpy(pos, start, sizeof(int) * (size_t)(V + 1));
+        for (int c = 0; c < n; ++c)
+            for (int j = 0; j < k; ++j)
+                touch[pos[verts[c * k + j]]++] = c;
+        free(pos);
+    }
+    size_t total = 0;
+    for (int c = 0; c < n; ++c)
+        mark[c] = -1;
+    for (int c = 0; c < n; ++c) {
+        nb_start[c] = (int)total;
+        for (int j = 0; j < k; ++j) {
+            int v = verts[c * k + j];
+            for (int p = start[v]; p < start[v + 1]; ++p)
+                if (touch[p] != c && mark[touch[p]] != c) {
+                    mark[touch[p]] = c;
+                    ++total;
+                }
+        }
+    }
+    nb_start[n] = (int)total;
+    int *nb = (int *)malloc(sizeof(int) * (total + 1));
+    if (!nb) {
+        free(start); free(touch); free(nb_start); free(mark); free(state); free(order);
+        return ORACLE_E_NOMEM;
+    }
+    for (int c = 0; c < n; ++c)
+        mark[c] = -1;
+    for (int c = 0; c < n; ++c) {
+        int q = nb_start[c];
+        for (int j = 0; j < k; ++j) {
+            int v = verts[c * k + j];
+            for (int p = start[v]; p < start[v + 1]; ++p)
+                if (touch[p] != c && mark[touch[p]] != c) {
+                    mark[touch[p]] = c;
+                    nb[q++] = touch[p];
+                }
+        }
+    }
+    free(start);
+    free(touch);
+
+    enum { COLOURED = 0, CANDIDATE = 1, EXCLUDED = 2, MEMBER = 3 };
+    for (int c = 0; c < n; ++c)
+        colour_out[c] = -1;
+    int left = n, num_colours = 0;
+    while (left > 0) {
+        for (int c = 0; c < n; ++c)
+            state[c] = colour_out[c] >= 0 ? COLOURED : CANDIDATE;
+        /* first member: most conflicts among the uncoloured */
+        int best = -1, best_count = -1;
+        for (int c = 0; c < n; ++c) {
+            if (state[c] != CANDIDATE)
+                continue;
+            int cnt = 0;
+            for (int p = nb_start[c]; p < nb_start[c + 1]; ++p)
+                cnt += state[nb[p]] != COLOURED;
+            if (cnt > best_count) {
+                best = c;
+                best_count = cnt;
+            }
+        }
+        int members = 0;
+        while (best >= 0) {
+            state[best] = MEMBER;
+            order[members++] = best;
+            for (int p = nb_start[best]; p < nb_start[best + 1]; ++p)
+                if (state[nb[p]] == CANDIDATE)
+                    state[nb[p]] = EXCLUDED;
+            /* next member: most conflicts with the excluded, then fewest with candidates */
+            best = -1;
+            int best_x = -1, best_u = 0;
+            for (int c = 0; c < n; ++c) {
+                if (state[c] != CANDIDATE)
+                    continue;
+                int x = 0, u = 0;
+                for (int p = nb_start[c]; p < nb_start[c + 1]; ++p) {
+                    x += state[nb[p]] == EXCLUDED;
+                    u += state[nb[p]] == CANDIDATE;
+                }
+                if (x > best_x || (x == best_x && u < best_u)) {
+                    best = c;
+                    best_x = x;
+                    best_u = u;
+                }
+            }
+        }
+        int keep = members;
+        if (cut_above > 64 && members > 64 && members <= cut_above)
+            keep = 64;
+        for (int q = 0; q < keep; ++q)
+            colour_out[order[q]] = num_colours;
+        left -= keep;
+        ++num_colours;
+    }
+    free(nb);
+    free(nb_start);
+    free(mark);
+    free(state);
+    free(order);
+    return num_colours;
+}
+
 /* ------------------------------------------------------------------ */
 /* Simulation (Algorithm 1 with readings R1-R8)                        */
 /* ------------------------------------------------------------------ */
@@ -576,7 +729,9 @@ void oracle_iterate_jacobi(double *x, const double *w,
 /* ------------------------------------------------------------------ */
 
 /* Closest point on triangle (a, b, c) to p, by the region of p's projection:
- * vertex, edge or interior.  Writes the point and its barycentrics. */
+ * vertex, edge or interior.  Writes the point and its barycentrics.  The
+ * region tests are the published method of C. Ericson, Real-Time Collision
+ * Detection (Morgan Kaufmann 2005), Sec. 5.1.5. */
 static void closest_on_triangle(const double *p, const double *a, const double *b,
                                 const double *c, double *q, double *bary)
 {
@@ -615,7 +770,9 @@ static void closest_on_triangle(const double *p, const double *a, const double *
         q[k] = bary[0] * a[k] + bary[1] * b[k] + bary[2] * c[k];
 }
 
-/* Closest points of segments p0 p1 and q0 q1: parameters s, t in [0, 1]. */
+/* Closest points of segments p0 p1 and q0 q1: parameters s, t in [0, 1]
+ * (the clamped solution of C. Ericson, Real-Time Collision Detection, 2005,
+ * Sec. 5.1.9). */
 static void closest_segments(const double *p0, const double *p1, const double *q0,
                              const double *q1, double *s_out, double *t_out)
 {

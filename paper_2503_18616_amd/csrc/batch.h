@@ -13,11 +13,13 @@
 #include "xpbd_device.h"
 
 // A size class of the register variant: environments whose meshes share a
-// block size and an LDS tier run in one launch; several classes run
+// block size, an LDS tier and a number of environments per workgroup run in
+// one launch; several classes run
 // concurrently on streams of their own, forked from and joined to the
 // batch's stream.
 struct RegClass {
     int block = 256;
+    int group = 1;                  // environments per workgroup
     int lambda_banks = 1;
     uint32_t lds_bytes = 0;
     int32_t num_groups = 0;

@@ -27,13 +27,14 @@ struct xpbd_graph {
 
 namespace {
 
-// Record body() (launches on b->stream only, no allocation, no
-// synchronisation) into a graph.
+// Record body() (launches on b->stream, no allocation, no synchronisation)
+// into a graph.  A batch of several size classes forks its class streams from
+// the batch's stream with an event and joins them back with events; inside
+// the capture those streams join it, so the classes become parallel branches
+// of the graph between the fork and the join.
 template <typename Body>
 xpbd_status capture(xpbd_batch *b, Body &&body, xpbd_graph **out)
 {
-    if (b->classes.size() > 1)
-        return fail(XPBD_E_ARG, "graph capture needs a batch of one size class");
     hipStream_t cs = nullptr;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipStream_t saved = b->stream;

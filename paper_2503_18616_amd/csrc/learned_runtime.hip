@@ -185,6 +185,7 @@ xpbd_status xpbd_mlp_train_step(xpbd_mlp *net, const uint16_t *features, const f
     if (!is_device_pointer(features) || !is_device_pointer(targets) ||
         (grad && !is_device_pointer(grad)) || (rows && !is_device_pointer(rows)))
         return fail(XPBD_E_ARG, "features, targets, rows and grad must be device memory");
+    const bool loss_on_device = loss && is_device_pointer(loss);
     const int groups = (n + xpbd::kMlpTile - 1) / xpbd::kMlpTile;
     if (groups > net->partial_groups) {
         HIP_TRY(hipStreamSynchronize(net->stream));
@@ -203,11 +204,46 @@ xpbd_status xpbd_mlp_train_step(xpbd_mlp *net, const uint16_t *features, const f
     if (learning_rate > 0.0f)
         step = ++net->adam_step;
     HIP_TRY(xpbd::launch_mlp_train(net->d, features, targets, rows, n, net->partial, net->stats,
-                                   learning_rate, 0.9f, 0.999f, 1e-8f, step, grad, net->loss,
-                                   net->stream));
-    if (loss) {
+                                   learning_rate, 0.9f, 0.999f, 1e-8f, step, grad,
+                                   loss_on_device ? loss : net->loss, net->stream));
+    if (loss && !loss_on_device) {
         HIP_TRY(hipMemcpyAsync(loss, net->loss, sizeof(float), hipMemcpyDeviceToHost, net->stream));
         HIP_TRY(hipStreamSynchronize(net->stream));
+    }
+    return XPBD_OK;
+}
+
+xpbd_status xpbd_mlp_normalisation(const uint16_t *features, const float *targets, int64_t n,
+                                   void *hip_stream, float *in_shift, float *in_scale,
+                                   float *out_shift, float *out_scale)
+{
+    g_error.clear();
+    if (!features || !targets || n < 1 || !in_shift || !in_scale || !out_shift || !out_scale)
+        return fail(XPBD_E_ARG, "features, targets, n >= 1 and the four outputs are required");
+    if (!is_device_pointer(features) || !is_device_pointer(targets))
+        return fail(XPBD_E_ARG, "features and targets must be device memory");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const size_t bytes = xpbd::mlp_normalisation_workspace();
+    void *ws = nullptr;
+    HIP_TRY(hipMalloc(&ws, bytes));
+    float host[2 * xpbd::kMlpFeatures + 6];
+    hipError_t e = xpbd::launch_mlp_normalisation(features, targets, n, ws, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host, static_cast<char *>(ws) + bytes - sizeof host, sizeof host,
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    (void)hipFree(ws);
+    if (e != hipSuccess)
+        return fail(XPBD_E_HIP, "normalisation: %s", hipGetErrorString(e));
+    const int F = xpbd::kMlpFeatures;
+    for (int c = 0; c < F; ++c) {
+        in_shift[c] = host[c];
+        in_scale[c] = host[F + c];
+    }
+    for (int k = 0; k < 3; ++k) {
+        out_shift[k] = host[2 * F + k];
+        out_scale[k] = host[2 * F + 3 + k];
     }
     return XPBD_OK;
 }
@@ -291,6 +327,8 @@ xpbd_status xpbd::check_learned(const xpbd_batch *b, const xpbd_mlp *net,
                     "must be device memory");
     if (lp->iterations && !is_device_pointer(lp->iterations))
         return fail(XPBD_E_ARG, "iterations must be device memory");
+    if (lp->residuals && !is_device_pointer(lp->residuals))
+        return fail(XPBD_E_ARG, "residuals must be device memory");
     return XPBD_OK;
 }
 
@@ -310,18 +348,9 @@ xpbd_status xpbd::learned_workspace(xpbd_batch *b, const xpbd_learned_params *lp
                        sizeof(uint16_t) * 32 * (size_t)NP)))
         return st;
     if (lp->apply_correction && !b->learned_chunk0) {
-        // the correction's 32-particle chunks: those before a mesh's first
-        // free particle hold pinned particles only and are skipped
-        std::vector<int32_t> c0(b->meshes.size(), 0);
+        std::vector<int32_t> c0;
         int32_t chunks = 1;
-        for (size_t m = 0; m < b->meshes.size(); ++m) {
-            const auto &pm = b->meshes[m];
-            int32_t first = 0;
-            while (first < pm.num_vertices && !(pm.inv_mass[(size_t)first] > 0.0f))
-                ++first;
-            c0[m] = std::min(first, pm.num_vertices - 1) / 32;
-            chunks = std::max(chunks, (pm.num_vertices + 31) / 32 - c0[m]);
-        }
+        learned_chunks(b, c0, chunks);
         if ((st = b->upload(&b->learned_chunk0, c0)))
             return st;
         b->learned_chunks = chunks;
@@ -336,17 +365,41 @@ xpbd_status xpbd::learned_workspace(xpbd_batch *b, const xpbd_learned_params *lp
     return XPBD_OK;
 }
 
+void xpbd::learned_chunks(const xpbd_batch *b, std::vector<int32_t> &c0, int32_t &chunks)
+{
+    c0.assign(b->meshes.size(), 0);
+    chunks = 1;
+    for (size_t m = 0; m < b->meshes.size(); ++m) {
+        const auto &pm = b->meshes[m];
+        int32_t first = 0;
+        while (first < pm.num_vertices && !(pm.inv_mass[(size_t)first] > 0.0f))
+            ++first;
+        c0[m] = std::min(first, pm.num_vertices - 1) / 32;
+        chunks = std::max(chunks, (pm.num_vertices + 31) / 32 - c0[m]);
+    }
+}
+
 // num_steps learned steps with the tool poses in device memory; grasp is null
 // or names the RL step's grasp state.
 xpbd_status xpbd::run_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_steps,
                               const float *tools_dev, const xpbd_learned_params *lp,
-                              const GraspArgs *grasp)
+                              const GraspArgs *grasp, const LearnedWorkspace *ws)
 {
     const int tools = b->params.num_tools;
     const bool record = lp->record_substep >= 0;
-    xpbd_status st = learned_workspace(b, lp);
-    if (st != XPBD_OK)
-        return st;
+    LearnedWorkspace own;
+    if (!ws) {
+        xpbd_status st = learned_workspace(b, lp);
+        if (st != XPBD_OK)
+            return st;
+        own.xhat = b->learned_xhat;
+        own.feat = b->learned_feat;
+        own.cand = b->learned_cand;
+        own.chunk0 = b->learned_chunk0;
+        own.chunks = b->learned_chunks;
+        own.correct_workgroups = b->correct_workgroups;
+        ws = &own;
+    }
 
     xpbd::StepArgs a;
     std::memset(&a, 0, sizeof a);
@@ -388,8 +441,8 @@ xpbd_status xpbd::run_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
     }
     xpbd::LearnedArgs L;
     std::memset(&L, 0, sizeof L);
-    L.xhat = b->learned_xhat;
-    L.cand = b->learned_cand;
+    L.xhat = ws->xhat;
+    L.cand = ws->cand;
     L.in_shift = net ? net->in_shift : nullptr;
     L.in_scale = net ? net->in_scale : nullptr;
     L.out_shift = net ? net->d.out_shift : nullptr;
@@ -399,13 +452,13 @@ xpbd_status xpbd::run_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
     L.max_iterations = lp->max_iterations;
     L.stall_ratio = lp->stall_ratio;
     L.max_vertices = b->max_vertices;
-    L.chunk0 = b->learned_chunk0;
-    L.chunks = b->learned_chunks;
+    L.chunk0 = ws->chunk0;
+    L.chunks = ws->chunks;
     const bool resid = (b->params.flags & XPBD_F_RESIDUAL) != 0;
     const bool want_lambda = (b->params.flags & XPBD_F_LAMBDA) || resid;
     const int S = b->params.substeps;
     auto feature_buffer = [&](int sub) {
-        return record && sub == lp->record_substep ? lp->record_features : b->learned_feat;
+        return record && sub == lp->record_substep ? lp->record_features : ws->feat;
     };
     for (int step = 0; step < num_steps; ++step)
         for (int sub = 0; sub < S; ++sub) {
@@ -417,6 +470,8 @@ xpbd_status xpbd::run_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
             L.record_targets = rec ? lp->record_targets : nullptr;
             L.iterations = lp->iterations ? lp->iterations + ((size_t)step * S + sub) * b->num_envs
                                           : nullptr;
+            L.residuals = lp->residuals ? lp->residuals + ((size_t)step * S + sub) * b->num_envs
+                                        : nullptr;
             a.lambda_out = last && want_lambda ? b->lambda : nullptr;
             L.next_features = nullptr;
             if (lp->apply_correction) {
@@ -425,7 +480,7 @@ xpbd_status xpbd::run_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
                 L.features = feature_buffer(sub);
                 if (step == 0 && sub == 0)
                     HIP_TRY(xpbd::launch_learned_predict(a, L, b->stream));
-                HIP_TRY(xpbd::launch_learned_correct(a, L, net->d, b->correct_workgroups,
+                HIP_TRY(xpbd::launch_learned_correct(a, L, net->d, ws->correct_workgroups,
                                                      b->stream));
                 if (!last)
                     L.next_features = feature_buffer((sub + 1) % S);

@@ -12,6 +12,9 @@
 namespace xpbd {
 namespace {
 
+// WAVES colouring: a colour of 65 .. kWaveCutAbove members is cut to 64.
+constexpr int32_t kWaveCutAbove = 100;
+
 // Six times the signed volume of (a, b, c, d): the determinant of the edge
 // vectors b - a, c - a, d - a, expanded along its first row.
 double six_volume(const float *p, int32_t a, int32_t b, int32_t c, int32_t d)
@@ -51,6 +54,81 @@ int32_t greedy_colouring(int32_t num_vertices, int32_t n, int32_t k, const int32
         colour[(size_t)j] = c;
         for (int32_t i = 0; i < k; ++i)
             taken[(size_t)q[i]].push_back(c);
+    }
+    return count;
+}
+
+int32_t largest_first_colouring(int32_t num_vertices, int32_t n, int32_t k, const int32_t *ids,
+                                int32_t cut_above, std::vector<int32_t> &colour)
+{
+    colour.assign((size_t)n, -1);
+    // conflict lists: constraints sharing a particle, without repeats
+    std::vector<std::vector<int32_t>> at((size_t)num_vertices);
+    for (int32_t j = 0; j < n; ++j)
+        for (int32_t i = 0; i < k; ++i)
+            at[(size_t)ids[(size_t)j * k + i]].push_back(j);
+    std::vector<std::vector<int32_t>> adj((size_t)n);
+    std::vector<int32_t> seen((size_t)n, -1);
+    for (int32_t j = 0; j < n; ++j) {
+        seen[(size_t)j] = j;
+        for (int32_t i = 0; i < k; ++i)
+            for (int32_t o : at[(size_t)ids[(size_t)j * k + i]])
+                if (seen[(size_t)o] != j) {
+                    seen[(size_t)o] = j;
+                    adj[(size_t)j].push_back(o);
+                }
+    }
+    // state of a constraint while one colour is built
+    enum : uint8_t { DONE = 0, CANDIDATE = 1, EXCLUDED = 2 };
+    std::vector<uint8_t> state((size_t)n, CANDIDATE);
+    std::vector<int32_t> in_u((size_t)n), in_x((size_t)n);   // conflicts among candidates / excluded
+    std::vector<int32_t> picked;
+    int32_t left = n, count = 0;
+    while (left > 0) {
+        int32_t best = -1;
+        for (int32_t j = 0; j < n; ++j) {
+            if (state[(size_t)j] == DONE)
+                continue;
+            in_x[(size_t)j] = 0;
+            int32_t u = 0;
+            for (int32_t o : adj[(size_t)j])
+                u += state[(size_t)o] != DONE;
+            in_u[(size_t)j] = u;
+            if (best < 0 || u > in_u[(size_t)best])
+                best = j;
+        }
+        picked.clear();
+        while (best >= 0) {
+            picked.push_back(best);
+            state[(size_t)best] = EXCLUDED;   // taken: leaves the candidates
+            for (int32_t o : adj[(size_t)best])
+                if (state[(size_t)o] != DONE)
+                    --in_u[(size_t)o];
+            for (int32_t o : adj[(size_t)best])
+                if (state[(size_t)o] == CANDIDATE) {
+                    state[(size_t)o] = EXCLUDED;
+                    for (int32_t p : adj[(size_t)o])
+                        if (state[(size_t)p] != DONE) {
+                            --in_u[(size_t)p];
+                            ++in_x[(size_t)p];
+                        }
+                }
+            best = -1;
+            for (int32_t j = 0; j < n; ++j)
+                if (state[(size_t)j] == CANDIDATE &&
+                    (best < 0 || in_x[(size_t)j] > in_x[(size_t)best] ||
+                     (in_x[(size_t)j] == in_x[(size_t)best] && in_u[(size_t)j] < in_u[(size_t)best])))
+                    best = j;
+        }
+        size_t keep = picked.size();
+        if (cut_above > 64 && keep > 64 && keep <= (size_t)cut_above)
+            keep = 64;
+        for (size_t q = 0; q < keep; ++q)
+            colour[(size_t)picked[q]] = count;
+        left -= (int32_t)keep;
+        for (int32_t j = 0; j < n; ++j)
+            state[(size_t)j] = colour[(size_t)j] >= 0 ? DONE : CANDIDATE;
+        ++count;
     }
     return count;
 }
@@ -638,7 +716,7 @@ void axis_neighbours(int32_t num_vertices, const float *rest_pos, std::vector<in
 
 int prepare_mesh(int32_t num_vertices, int32_t num_tets, const float *rest_pos,
                  const float *inv_mass, const int32_t *tets, PreparedMesh &out,
-                 std::string &error)
+                 std::string &error, int32_t colouring)
 {
     char msg[256];
     if (num_vertices < 1 || num_vertices > 65535) {
@@ -730,10 +808,18 @@ int prepare_mesh(int32_t num_vertices, int32_t num_tets, const float *rest_pos,
         out.rest_length.push_back(std::sqrt(s));
     }
 
-    out.num_edge_colours = greedy_colouring(num_vertices, out.num_edges(), 2, out.edges.data(),
-                                            out.edge_colour);
-    out.num_tet_colours = greedy_colouring(num_vertices, out.num_tets(), 4, out.tets.data(),
-                                           out.tet_colour);
+    if (colouring == XPBD_COLOURING_GREEDY) {
+        out.num_edge_colours = greedy_colouring(num_vertices, out.num_edges(), 2,
+                                                out.edges.data(), out.edge_colour);
+        out.num_tet_colours = greedy_colouring(num_vertices, out.num_tets(), 4, out.tets.data(),
+                                               out.tet_colour);
+    } else {
+        const int32_t cut = colouring == XPBD_COLOURING_WAVES ? kWaveCutAbove : 0;
+        out.num_edge_colours = largest_first_colouring(num_vertices, out.num_edges(), 2,
+                                                       out.edges.data(), cut, out.edge_colour);
+        out.num_tet_colours = largest_first_colouring(num_vertices, out.num_tets(), 4,
+                                                      out.tets.data(), cut, out.tet_colour);
+    }
 
     // surface triangles (capsule tools): faces of exactly one kept tetrahedron,
     // ordered outward (away from the tetrahedron's fourth vertex), sorted by

@@ -31,15 +31,31 @@ struct PreparedMesh {
 };
 
 // Returns 0 on success; on failure a negative xpbd_status and a message.
+// colouring: XPBD_COLOURING_* of the edge and tetrahedron constraints (the
+// surface faces always take the greedy colouring).
 int prepare_mesh(int32_t num_vertices, int32_t num_tets, const float *rest_pos,
                  const float *inv_mass, const int32_t *tets, PreparedMesh &out,
-                 std::string &error);
+                 std::string &error, int32_t colouring = 0);
 
 // Greedy colouring: constraints are visited in index order and each takes the
 // smallest colour not held by an already coloured constraint that shares a
 // particle.  ids: [n][k].  Returns the number of colours.
 int32_t greedy_colouring(int32_t num_vertices, int32_t n, int32_t k, const int32_t *ids,
                          std::vector<int32_t> &colour);
+
+// Recursive largest-first colouring (Leighton 1979): colours are built one at
+// a time, each as a maximal set of constraints that share no particle, drawn
+// from the constraints not yet coloured.  A colour starts with the constraint
+// that conflicts with the most uncoloured ones; every further pick is a
+// candidate (one sharing no particle with the colour so far) with the most
+// conflicts among the constraints already excluded from the colour, then the
+// fewest among the remaining candidates, then the lowest index.  With
+// cut_above > 64, a colour that ends with more than 64 and at most cut_above
+// members keeps only its first 64 picks (the rest return to the uncoloured
+// pool), so that it fills one 64-wide wave instead of most of a second one.
+// ids: [n][k].  Returns the number of colours.
+int32_t largest_first_colouring(int32_t num_vertices, int32_t n, int32_t k, const int32_t *ids,
+                                int32_t cut_above, std::vector<int32_t> &colour);
 
 // Order of the constraints inside each colour (the "packing"; it does not
 // change results because constraints of one colour share no particle).

@@ -57,4 +57,12 @@ hipError_t launch_mlp_train(const MlpDev &net, const uint16_t *feat, const float
                             float beta1, float beta2, float eps, int step, float *grad_out,
                             float *loss_out, hipStream_t stream);
 
+// Normalisation statistics of n training rows (features [n][32] bfloat16,
+// targets [n][4]) over the rows whose free flag is set; workspace: device
+// memory of mlp_normalisation_workspace() bytes, whose last 60 floats receive
+// [in_shift 27 | in_scale 27 | out_shift 3 | out_scale 3].
+size_t mlp_normalisation_workspace();
+hipError_t launch_mlp_normalisation(const uint16_t *feat, const float *targets, int64_t n,
+                                    void *workspace, hipStream_t stream);
+
 }  // namespace xpbd

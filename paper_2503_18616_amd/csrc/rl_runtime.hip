@@ -248,6 +248,9 @@ xpbd_status xpbd_rl_step_learned(xpbd_batch *b, const xpbd_policy *policy,
         lp.iterations = learned->iterations
                             ? learned->iterations + (size_t)step * b->params.substeps * N
                             : nullptr;
+        lp.residuals = learned->residuals
+                           ? learned->residuals + (size_t)step * b->params.substeps * N
+                           : nullptr;
         HIP_TRY(xpbd::launch_rl_policy(r, policy->d, b->stream));
         st = xpbd::run_learned(b, net, 1, tool_pos, &lp, &grasp);
         if (st != XPBD_OK)

@@ -123,6 +123,7 @@ struct LearnedArgs {
     const float *out_scale;      // [4]
     float *record_targets;       // [total particles][4] (x - x_hat - out_shift) / out_scale, or null
     int32_t *iterations;         // [N] sweeps run in this substep, or null
+    float *residuals;            // [N] residual RMS after this substep's last sweep, or null
     float threshold;             // residual RMS above which the sweeps continue
     float stall_ratio;           // > 0: no further sweeps when the last minimum sweep stalled
     int32_t min_iterations;
@@ -212,6 +213,7 @@ struct RegLdsLayout {
     uint32_t vel;      // float [3][V]
     uint32_t prev;     // float [3][V]  positions at the start of the substep
     uint32_t scratch;  // kRegScratchBytes
+    uint32_t faces;    // uint8 [tools][F]  capsule tools: candidate flags of the surface faces
     uint32_t total;
 };
 
@@ -219,15 +221,17 @@ constexpr uint32_t kRegScratchTools = 384;
 constexpr uint32_t kRegScratchGrasp = 512;
 constexpr uint32_t kRegScratchBytes = 1024;
 constexpr int kMaxEnvsPerGroup = 2;
+constexpr int kMaxCapsuleBlock = 512;   // register variant with capsule tools
 
-__host__ __device__ inline RegLdsLayout reg_lds_layout(int32_t V)
+__host__ __device__ inline RegLdsLayout reg_lds_layout(int32_t V, int32_t face_flags = 0)
 {
     RegLdsLayout l;
     l.xw = 0;
     l.vel = 16u * ((uint32_t)V + 1u);
     l.prev = l.vel + 12u * (uint32_t)V;
     l.scratch = align_up(l.prev + 12u * (uint32_t)V, 16);
-    l.total = l.scratch + kRegScratchBytes;
+    l.faces = l.scratch + kRegScratchBytes;
+    l.total = l.faces + align_up((uint32_t)face_flags, 16);
     return l;
 }
 

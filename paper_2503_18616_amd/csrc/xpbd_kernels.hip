@@ -228,7 +228,8 @@ __device__ __forceinline__ V3 cross(V3 a, V3 b)
 }
 
 // Barycentrics of the point of triangle (a, b, c) closest to p (vertex, edge
-// or interior region of p's projection).
+// or interior region of p's projection; the region tests of C. Ericson,
+// Real-Time Collision Detection, 2005, Sec. 5.1.5).
 __device__ V3 triangle_closest(V3 p, V3 a, V3 b, V3 c)
 {
     const V3 ab = b - a, ac = c - a, ap = p - a;
@@ -263,7 +264,8 @@ __device__ V3 triangle_closest(V3 p, V3 a, V3 b, V3 c)
     return {1.f - v - w, v, w};
 }
 
-// Parameters (s on p0 p1, t on q0 q1) of the closest points of two segments.
+// Parameters (s on p0 p1, t on q0 q1) of the closest points of two segments
+// (the clamped solution of Ericson 2005, Sec. 5.1.9).
 __device__ void segments_closest(V3 p0, V3 p1, V3 q0, V3 q1, float &s, float &t)
 {
     const V3 d1 = p1 - p0, d2 = q1 - q0, r = p0 - q0;
@@ -904,6 +906,11 @@ __device__ __forceinline__ void run_round(float4 *xw, const RoundTables &t, int 
         __syncthreads();
 }
 
+// Tool modes of the register kernel: spheres against particles, spheres with
+// the grasper's dragging constraint (RL-style step), capsules against the
+// surface faces (one environment per workgroup).
+enum { kRegSpheres = 0, kRegGrasp = 1, kRegCapsules = 2 };
+
 // One workgroup per group of EG environments of one mesh: group g holds
 // environments A.groups[EG g .. EG g + EG); an entry ~e (negative) repeats
 // environment e as filler and writes nothing.  The group's particles share
@@ -912,9 +919,12 @@ __device__ __forceinline__ void run_round(float4 *xw, const RoundTables &t, int 
 // particles as float4 (x, y, z, w), velocities and start-of-substep positions
 // (structure of arrays), then scratch.  Multipliers live in registers (NB
 // banks of 32 rounds).
-template <int NB, int EG, bool GRASP>
-__global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
+template <int NB, int EG, int MODE>
+__device__ __forceinline__ void step_reg_body(StepArgs A)
 {
+    constexpr bool GRASP = MODE == kRegGrasp;
+    constexpr bool CAPSULE = MODE == kRegCapsules;
+    static_assert(!CAPSULE || EG == 1, "capsule tools run one environment per workgroup");
     extern __shared__ __align__(16) unsigned char smem[];
     const int group = blockIdx.x;
     const int tid = threadIdx.x;
@@ -945,7 +955,9 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
     const int R = md.num_rounds;
     const int R0 = R < 32 ? R : 32;
     const int tools = A.num_tools;
-    const RegLdsLayout L = reg_lds_layout(VS);
+    const int F = CAPSULE ? md.num_faces : 0;
+    const RegLdsLayout L = reg_lds_layout(VS, CAPSULE ? tools * F : 0);
+    uint8_t *fflag = smem + L.faces;   // capsules: [tools][F] candidate flags
     float4 *xw = reinterpret_cast<float4 *>(smem + L.xw);
     float *vel = reinterpret_cast<float *>(smem + L.vel);      // [3][VS]
     float *prev = reinterpret_cast<float *>(smem + L.prev);    // [3][VS]
@@ -997,8 +1009,16 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
 
     uint32_t cand = 0u;  // bit 16 t + k: the particle in slot k * B + tid is a candidate of tool t
     for (int step = 0; step < A.num_steps; ++step) {
-        // instrument state (sphere centres of every environment of the group)
-        if (tid < 2 * EG) {
+        // instrument state (sphere centres of every environment of the group;
+        // capsules: the two axis end points of every tool, tool_c[2 t + k])
+        if constexpr (CAPSULE) {
+            if (tid < 2 * tools) {
+                const float *c = A.tool_pos +
+                                 (((size_t)step * A.num_envs + env[0]) * tools + (tid >> 1)) * 6 +
+                                 3 * (tid & 1);
+                tool_c[tid] = make_float4(c[0], c[1], c[2], 0.0f);
+            }
+        } else if (tid < 2 * EG) {
             const int e = tid >> 1, t = tid & 1;
             if (t < tools) {
                 int g = A.groups[group * EG + e];
@@ -1085,12 +1105,32 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
         }
         // contact candidates on the start-of-step positions
         cand = 0u;
-        for (int t = 0; t < tools; ++t) {
-            const float reach2 = t == 0 ? A.tool_reach2[0] : A.tool_reach2[1];
-            for (int k = 0, i = opaque(tid); i < VS; ++k, i += B) {
-                const float4 ct = tool_c[2 * (int)((slot_env >> (2 * k)) & 3u) + t];
-                if (within_reach(xw[i], ct.x, ct.y, ct.z, reach2))
-                    cand |= 1u << (16 * t + k);
+        if constexpr (CAPSULE) {
+            // faces with a free corner closer than 2r to the axis (Sec. III-A.3);
+            // bit t of cand: this thread flagged a face of tool t
+            for (int t = 0; t < tools; ++t) {
+                const float4 c0 = tool_c[2 * t], c1 = tool_c[2 * t + 1];
+                const float r = t == 0 ? A.tool_radius[0] : A.tool_radius[1];
+                for (int j = tid; j < F; j += B) {
+                    const uint2 f = md.faces[j];
+                    const float4 pa = xw[md.slot_of[f.x & 0xffffu]], pb = xw[md.slot_of[f.x >> 16]],
+                                 pc = xw[md.slot_of[f.y]];
+                    V3 bary, sp;
+                    const bool flag = (pa.w > 0.f || pb.w > 0.f || pc.w > 0.f) &&
+                                      segment_triangle(v3(c0), v3(c1), v3(pa), v3(pb), v3(pc), bary,
+                                                       sp) < 4.f * r * r;
+                    fflag[t * F + j] = flag ? 1 : 0;
+                    cand |= flag ? 1u << t : 0u;
+                }
+            }
+        } else {
+            for (int t = 0; t < tools; ++t) {
+                const float reach2 = t == 0 ? A.tool_reach2[0] : A.tool_reach2[1];
+                for (int k = 0, i = opaque(tid); i < VS; ++k, i += B) {
+                    const float4 ct = tool_c[2 * (int)((slot_env >> (2 * k)) & 3u) + t];
+                    if (within_reach(xw[i], ct.x, ct.y, ct.z, reach2))
+                        cand |= 1u << (16 * t + k);
+                }
             }
         }
         const bool any_contact = block_any(cand != 0u, scratch + 32, wave, lane, num_waves);
@@ -1133,7 +1173,25 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
                         run_round<EG>(xw, tab, r + 1, slot_b, active, tets, barriers, bank1,
                                       alpha_d, alpha_v);
                     }
-                if (any_contact || (GRASP && grasping)) {
+                if (CAPSULE && any_contact) {
+                    // flagged faces pushed out of every capsule, face colour by
+                    // face colour (faces of one colour share no particle)
+                    for (int t = 0; t < tools; ++t) {
+                        const V3 c0 = v3(tool_c[2 * t]), c1 = v3(tool_c[2 * t + 1]);
+                        const float rt = t == 0 ? A.tool_radius[0] : A.tool_radius[1];
+                        for (int c = 0; c < md.num_face_colours; ++c) {
+                            const int end = md.face_ptr[c + 1];
+                            for (int j = md.face_ptr[c] + tid; j < end; j += B)
+                                if (fflag[t * F + j]) {
+                                    const uint2 f = md.faces[j];
+                                    const uint32_t sa = md.slot_of[f.x & 0xffffu],
+                                                   sb = md.slot_of[f.x >> 16], sc = md.slot_of[f.y];
+                                    capsule_push(xw, make_uint2(sa | sb << 16, sc), c0, c1, rt);
+                                }
+                            __syncthreads();
+                        }
+                    }
+                } else if (any_contact || (GRASP && grasping)) {
                     for (int t = 0; t < tools; ++t) {
                         const float rt = t == 0 ? A.tool_radius[0] : A.tool_radius[1];
                         const float rt2 = t == 0 ? A.tool_radius2[0] : A.tool_radius2[1];
@@ -1198,12 +1256,32 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
 
     // contact candidates of the last step as ascending mesh ids, per
     // environment: flag them by mesh id in a byte map (the start-of-substep
-    // positions are no longer needed), then compact in mesh order
+    // positions are no longer needed), then compact in mesh order; capsules:
+    // the number of candidate faces per tool and no particle list
     uint8_t *flag_of = reinterpret_cast<uint8_t *>(prev);
     const int kmax = (V + B - 1) / B;
+    if constexpr (CAPSULE) {
+        for (int t = 0; t < tools; ++t) {
+            int mine = 0;
+            for (int j = tid; j < F; j += B)
+                mine += fflag[t * F + j];
+            const float total = wave_sum((float)mine);
+            if (lane == 0)
+                scratch[wave] = (uint32_t)total;
+            __syncthreads();
+            int n = 0;
+            for (int w = 0; w < num_waves; ++w)
+                n += (int)scratch[w];
+            for (int i = tid; i < V; i += B)
+                A.contacts[(size_t)t * NP + off[0] + i] = -1;
+            if (tid == 0 && writes[0])
+                A.contact_counts[env[0] * tools + t] = n;
+            __syncthreads();
+        }
+    }
 #pragma unroll
     for (int e = 0; e < EG; ++e) {
-        if (!writes[e])
+        if (CAPSULE || !writes[e])
             continue;
         for (int t = 0; t < tools; ++t) {
             for (int i = tid; i < V; i += B)
@@ -1263,6 +1341,21 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
             for (int r = 32; r < R; ++r)
                 store(r, bank1[r & 31]);
     }
+}
+
+template <int NB, int EG, int MODE>
+__global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
+{
+    step_reg_body<NB, EG, MODE>(A);
+}
+
+// Capsule tools: the face push-out's closest-point search needs more
+// registers than 1024-thread workgroups leave a lane, so this instantiation
+// is bounded to 512 threads (two waves per SIMD and workgroup).
+template <int NB>
+__global__ void __launch_bounds__(512) xpbd_step_reg_kernel_capsules(StepArgs A)
+{
+    step_reg_body<NB, 1, kRegCapsules>(A);
 }
 
 // ---------------------------------------------------------------------------
@@ -1599,15 +1692,23 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
             before = residual_rms();
         sweep();
     }
+    float final_rms = 0.0f;
+    bool measured = false;   // final_rms holds the residual after the last sweep
     if (check) {
         const float rms = residual_rms();
+        final_rms = rms;
+        measured = true;
         bool go_on = rms > L.threshold;
         if (go_on && stall_check)
             go_on = rms <= L.stall_ratio * before;
-        if (go_on)
+        if (go_on) {
             for (; n_it < L.max_iterations; ++n_it)
                 sweep();
+            measured = false;
+        }
     }
+    if (L.residuals && !measured)
+        final_rms = residual_rms();
 
     // velocity update and write-back (structure of arrays); slot_of[i] belongs
     // to other threads' sweeps, hence the barrier
@@ -1642,6 +1743,8 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
             A.nonfinite[env] = 1;
         if (L.iterations)
             L.iterations[env] = n_it;
+        if (L.residuals)
+            L.residuals[env] = final_rms;
     }
 
     // the prediction and features of the next substep from the state just
@@ -1880,8 +1983,19 @@ hipError_t launch_ppt(const StepArgs &args, int block, bool jacobi, bool stage, 
 template <int NB, int EG>
 hipError_t launch_reg_variant(const StepArgs &args, int block, uint32_t lds_bytes, hipStream_t stream)
 {
-    // the grasping code only in the launches that grasp (it costs registers)
-    auto kernel = args.grasp ? xpbd_step_reg_kernel<NB, EG, true> : xpbd_step_reg_kernel<NB, EG, false>;
+    // the grasping and capsule code only in the launches that use them (they
+    // cost registers)
+    auto kernel = args.grasp ? xpbd_step_reg_kernel<NB, EG, kRegGrasp>
+                             : xpbd_step_reg_kernel<NB, EG, kRegSpheres>;
+    if (args.tool_shape == 1) {   // XPBD_TOOL_CAPSULE
+        if constexpr (EG == 1) {
+            if (block > 512)
+                return hipErrorInvalidValue;
+            kernel = xpbd_step_reg_kernel_capsules<NB>;
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)lds_bytes);

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <numeric>
 #include <random>
@@ -62,6 +63,8 @@ xpbd_status validate_params(const xpbd_params *p)
         return fail(XPBD_E_ARG, "unknown solver_variant %d", p->solver_variant);
     if (p->colour_packing < XPBD_PACKING_AUTO || p->colour_packing > XPBD_PACKING_SEARCH)
         return fail(XPBD_E_ARG, "unknown colour_packing %d", p->colour_packing);
+    if (p->colouring < XPBD_COLOURING_GREEDY || p->colouring > XPBD_COLOURING_WAVES)
+        return fail(XPBD_E_ARG, "unknown colouring %d", p->colouring);
     if (p->envs_per_group < 0 || p->envs_per_group > xpbd::kMaxEnvsPerGroup)
         return fail(XPBD_E_ARG, "envs_per_group must be 0, 1 or 2 (got %d)", p->envs_per_group);
     if (p->tool_shape != XPBD_TOOL_SPHERE && p->tool_shape != XPBD_TOOL_CAPSULE)
@@ -174,13 +177,23 @@ const char *xpbd_last_error(void) { return g_error.c_str(); }
 xpbd_status xpbd_prepare_mesh(const xpbd_mesh *mesh, int32_t *counts, int32_t *edges,
                               int32_t *tets, int32_t *colours, float *rest)
 {
+    return xpbd_prepare_mesh_coloured(mesh, XPBD_COLOURING_GREEDY, counts, edges, tets, colours,
+                                      rest);
+}
+
+xpbd_status xpbd_prepare_mesh_coloured(const xpbd_mesh *mesh, int32_t colouring, int32_t *counts,
+                                       int32_t *edges, int32_t *tets, int32_t *colours,
+                                       float *rest)
+{
     g_error.clear();
     if (!mesh || !counts)
         return fail(XPBD_E_ARG, "mesh and counts must not be NULL");
+    if (colouring < XPBD_COLOURING_GREEDY || colouring > XPBD_COLOURING_WAVES)
+        return fail(XPBD_E_ARG, "unknown colouring %d", colouring);
     PreparedMesh pm;
     std::string err;
     int rc = xpbd::prepare_mesh(mesh->num_vertices, mesh->num_tets, mesh->rest_pos,
-                                mesh->inv_mass, mesh->tets, pm, err);
+                                mesh->inv_mass, mesh->tets, pm, err, colouring);
     if (rc != XPBD_OK)
         return fail((xpbd_status)rc, "%s", err.c_str());
     const int32_t E = pm.num_edges(), T = pm.num_tets();
@@ -257,7 +270,7 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         std::string err;
         int rc = xpbd::prepare_mesh(meshes[m].num_vertices, meshes[m].num_tets,
                                     meshes[m].rest_pos, meshes[m].inv_mass, meshes[m].tets,
-                                    prepared[(size_t)m], err);
+                                    prepared[(size_t)m], err, params->colouring);
         if (rc != XPBD_OK)
             return fail((xpbd_status)rc, "mesh %d: %s", m, err.c_str());
     }
@@ -311,10 +324,18 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
                             (params->block_size & (params->block_size - 1)) == 0;
     const bool jacobi = params->solver_variant == XPBD_VARIANT_JACOBI;
     const bool capsules = params->tool_shape == XPBD_TOOL_CAPSULE && params->num_tools > 0;
-    if (capsules && params->solver_variant == XPBD_VARIANT_REGISTERS)
-        return fail(XPBD_E_CAPACITY, "capsule tools need the LDS or Jacobi variant");
-    const bool reg_possible =
-        params->solver_variant != XPBD_VARIANT_LDS && !jacobi && !capsules && pow2_block;
+    if (capsules && params->envs_per_group > 1)
+        return fail(XPBD_E_CAPACITY, "capsule tools run one environment per workgroup");
+    const bool reg_possible = params->solver_variant != XPBD_VARIANT_LDS && !jacobi && pow2_block;
+    // LDS of a register-variant workgroup of G environments of a mesh (capsule
+    // tools add a candidate flag per surface face and tool)
+    const int face_tools = capsules ? params->num_tools : 0;
+    auto reg_lds = [&](const PreparedMesh &pm, int G) {
+        return xpbd::reg_lds_layout(G * pm.num_vertices, face_tools * pm.num_faces()).total;
+    };
+    int32_t max_faces = 0;
+    for (const auto &pm : prepared)
+        max_faces = std::max(max_faces, pm.num_faces());
     if (reg_possible && prepared.size() == 1 && params->block_size == 0) {
         // Occupancy model: a round (a lane's constraint of one colour, then
         // the colour's barrier) costs about the same whatever B and G, and a
@@ -326,11 +347,13 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         double best = 0.0;
         for (int B : {128, 256, 512, 1024})
             for (int G : {1, 2}) {
-                if (params->envs_per_group && G != params->envs_per_group)
+                if (capsules && B > xpbd::kMaxCapsuleBlock)
+                    continue;
+                if ((params->envs_per_group && G != params->envs_per_group) || (capsules && G > 1))
                     continue;
                 int r = count_rounds(pm, B, G);
                 r += r % 2;
-                const uint32_t lm = xpbd::reg_lds_layout(G * pm.num_vertices).total;
+                const uint32_t lm = reg_lds(pm, G);
                 if (r > xpbd::kMaxRounds || G * pm.num_vertices > 16 * B ||
                     G * pm.num_vertices > 16384 || lm > (uint32_t)lds_limit)
                     continue;
@@ -354,7 +377,7 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         else
             group_tries.push_back(1);
         const int tries[3] = {256, 512, 1024};
-        const int n_tries = params->block_size ? 1 : 3;
+        const int n_tries = params->block_size ? 1 : capsules ? 2 : 3;
         for (int G : group_tries) {
             for (int k = 0; k < n_tries && !use_registers; ++k) {
                 const int B = params->block_size ? params->block_size : tries[k];
@@ -363,8 +386,10 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
                     worst = std::max(worst, count_rounds(pm, B, G));
                 worst += worst % 2;   // padded to an even count
                 const bool fits = worst <= xpbd::kMaxRounds && G * vmax <= 16 * B &&
+                                  (!capsules || B <= xpbd::kMaxCapsuleBlock) &&
                                   G * vmax <= 16384 && B / 64 <= 16 &&
-                                  xpbd::reg_lds_layout(G * vmax).total <= (uint32_t)lds_limit;
+                                  xpbd::reg_lds_layout(G * vmax, face_tools * max_faces).total <=
+                                      (uint32_t)lds_limit;
                 if (fits) {
                     use_registers = true;
                     reg_block = B;
@@ -401,7 +426,7 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     uint32_t lds = stage ? lds_staged : lds_global;
     if (use_registers) {
         stage = false;
-        lds = xpbd::reg_lds_layout(reg_group * vmax).total;
+        lds = xpbd::reg_lds_layout(reg_group * vmax, face_tools * max_faces).total;
         // the round records hold 16-bit particle fields: LDS byte offsets with
         // one environment per workgroup (the LDS limit keeps them below 65536)
         if (reg_group == 1 && 16 * ((int64_t)vmax + 1) > 0xffff)
@@ -430,31 +455,60 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     b->meshes = std::move(prepared);
 
     // register variant: each mesh gets the smallest block whose rounds fit the
-    // register banks (every mesh fits the batch-wide choice), and an LDS tier:
-    // the most workgroups per CU its LDS and the 16 resident waves of a CU
-    // allow.  Meshes of equal (block, tier) form a size class, launched
-    // together; a requested block size makes one class.
+    // register banks (every mesh fits the batch-wide choice), a number of
+    // environments per workgroup and an LDS tier: the most workgroups per CU
+    // its LDS and the 16 resident waves of a CU allow.  Meshes of equal
+    // (block, tier, environments per workgroup) form a size class, launched
+    // together; a requested block size makes one class.  With several meshes
+    // and the environments per workgroup left to the library, a mesh shares
+    // its workgroups between two environments where the occupancy model rates
+    // that faster: environments resident per CU divided by rounds per sweep
+    // (the small meshes, whose colours fill a fraction of a block, run two to
+    // a workgroup in about the rounds of one).
     std::vector<int> mesh_block((size_t)num_meshes, block), mesh_class((size_t)num_meshes, 0);
+    std::vector<int> mesh_group((size_t)num_meshes, reg_group);
     if (use_registers) {
-        const int G = reg_group;
-        std::vector<std::pair<int, int>> keys;
+        std::vector<std::array<int, 3>> keys;
         for (int32_t m = 0; m < num_meshes; ++m) {
             const PreparedMesh &pm = b->meshes[(size_t)m];
             int B = block;
             if (params->block_size == 0 && !scored) {
                 for (int cand : {256, 512, 1024}) {
-                    int r = count_rounds(pm, cand, G);
+                    if (capsules && cand > xpbd::kMaxCapsuleBlock)
+                        continue;
+                    int r = count_rounds(pm, cand, reg_group);
                     r += r % 2;
-                    if (r <= xpbd::kMaxRounds && G * pm.num_vertices <= 16 * cand) {
+                    if (r <= xpbd::kMaxRounds && reg_group * pm.num_vertices <= 16 * cand) {
                         B = cand;
                         break;
                     }
                 }
             }
+            int G = reg_group;
+            if (num_meshes > 1 && params->envs_per_group == 0 && params->block_size == 0 &&
+                !capsules) {
+                double best_rate = 0.0;
+                for (int g : {1, 2}) {
+                    int r = count_rounds(pm, B, g);
+                    r += r % 2;
+                    const uint32_t lm = reg_lds(pm, g);
+                    if (r > xpbd::kMaxRounds || g * pm.num_vertices > 16 * B ||
+                        g * pm.num_vertices > 16384 || lm > (uint32_t)lds_limit)
+                        continue;
+                    const int per_cu =
+                        std::max(1, std::min(16 / (B / 64), (int)((uint32_t)lds_cu / lm)));
+                    const double rate = (double)(per_cu * g) / (double)std::max(r, 1);
+                    if (rate > best_rate * 1.0001) {
+                        best_rate = rate;
+                        G = g;
+                    }
+                }
+            }
             mesh_block[(size_t)m] = B;
-            const uint32_t lm = xpbd::reg_lds_layout(G * pm.num_vertices).total;
+            mesh_group[(size_t)m] = G;
+            const uint32_t lm = reg_lds(pm, G);
             const int tier = std::max(1, std::min(16 / (B / 64), (int)((uint32_t)lds_cu / lm)));
-            const std::pair<int, int> key(B, tier);
+            const std::array<int, 3> key{B, tier, G};
             auto it = std::find(keys.begin(), keys.end(), key);
             if (it == keys.end()) {
                 keys.push_back(key);
@@ -464,15 +518,16 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         }
         b->classes.resize(keys.size());
         for (size_t c = 0; c < keys.size(); ++c) {
-            b->classes[c].block = keys[c].first;
+            b->classes[c].block = keys[c][0];
+            b->classes[c].group = keys[c][2];
             b->classes[c].lds_bytes = 0;
             b->classes[c].lambda_banks = 1;
         }
         for (int32_t m = 0; m < num_meshes; ++m) {
             RegClass &c = b->classes[(size_t)mesh_class[(size_t)m]];
             const PreparedMesh &pm = b->meshes[(size_t)m];
-            c.lds_bytes = std::max(c.lds_bytes, xpbd::reg_lds_layout(G * pm.num_vertices).total);
-            int r = count_rounds(pm, c.block, G);
+            c.lds_bytes = std::max(c.lds_bytes, reg_lds(pm, c.group));
+            int r = count_rounds(pm, c.block, c.group);
             r += r % 2;
             if (r > 32)
                 c.lambda_banks = 2;
@@ -562,7 +617,7 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         // group constraint e E + j / e T + j), its LDS placement, lane packing and
         // round-major record tables with per-wave activity and the kind / barrier
         // masks of the round schedule
-        const int G = use_registers ? reg_group : 1;
+        const int G = use_registers ? mesh_group[(size_t)m] : 1;
         const int32_t GV = G * V;
         std::vector<int32_t> gedges((size_t)G * E * 2), gtets((size_t)G * T * 4);
         std::vector<int32_t> gecol((size_t)G * E), gtcol((size_t)G * T);
@@ -794,7 +849,6 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     // workgroups start first; a group left short repeats its last environment
     // as filler (~env)
     if (use_registers) {
-        const int G = b->envs_per_group;
         std::vector<int32_t> order((size_t)num_meshes);
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
@@ -805,6 +859,7 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         for (int32_t e = 0; e < num_envs; ++e)
             mine[(size_t)env_mesh[e]].push_back(e);
         for (size_t c = 0; c < b->classes.size(); ++c) {
+            const int G = b->classes[c].group;
             std::vector<int32_t> groups;
             for (int32_t m : order) {
                 if (mesh_class[(size_t)m] != (int)c)
@@ -826,6 +881,9 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         b->block = b->classes[0].block;
         b->lds_bytes = b->classes[0].lds_bytes;
         b->lambda_banks = b->classes[0].lambda_banks;
+        b->envs_per_group = b->classes[0].group;
+        for (const RegClass &c : b->classes)
+            b->envs_per_group = std::max(b->envs_per_group, c.group);
     }
 
     // environments
@@ -975,7 +1033,7 @@ xpbd_status xpbd::run_step(xpbd_batch *b, int32_t num_steps, const float *tools_
         const RegClass &c = b->classes[0];
         a.groups = c.groups_dev;
         a.num_groups = c.num_groups;
-        HIP_TRY(xpbd::launch_step_reg(a, c.block, c.lambda_banks, b->envs_per_group, c.lds_bytes,
+        HIP_TRY(xpbd::launch_step_reg(a, c.block, c.lambda_banks, c.group, c.lds_bytes,
                                       resid, b->stream));
     } else if (b->register_variant) {
         // one launch per size class on the class streams, joined before the residual
@@ -986,7 +1044,7 @@ xpbd_status xpbd::run_step(xpbd_batch *b, int32_t num_steps, const float *tools_
             HIP_TRY(hipStreamWaitEvent(c.stream, b->fork, 0));
             a.groups = c.groups_dev;
             a.num_groups = c.num_groups;
-            HIP_TRY(xpbd::launch_step_reg(a, c.block, c.lambda_banks, b->envs_per_group,
+            HIP_TRY(xpbd::launch_step_reg(a, c.block, c.lambda_banks, c.group,
                                           c.lds_bytes, false, c.stream));
             HIP_TRY(hipEventRecord(c.done, c.stream));
         }

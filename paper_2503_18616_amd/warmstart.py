@@ -44,33 +44,36 @@ def record(batch: "xpbd.Batch", net: "xpbd.Mlp", tool_pos, substeps, iterations)
 def normalisation(feats, targets):
     """(in_shift, in_scale, out_shift, out_scale): means and 1 / std of the
     features, means and std of the targets, over the free rows of a recording
-    made with the identity normalisation."""
-    f = feats.float().cpu().numpy().astype(np.float64)
-    t = targets.cpu().numpy().astype(np.float64)
-    free = f[:, 31] > 0
-    mf, sf = f[free, :xpbd.MLP_FEATURES].mean(axis=0), f[free, :xpbd.MLP_FEATURES].std(axis=0)
-    mt, st = t[free, :3].mean(axis=0), t[free, :3].std(axis=0)
-    in_scale = np.where(sf > 0, 1.0 / np.maximum(sf, 1e-30), 1.0)
-    return (mf.astype(np.float32), in_scale.astype(np.float32), mt.astype(np.float32),
-            np.maximum(st, 1e-12).astype(np.float32))
+    made with the identity normalisation (computed by the library's kernels,
+    xpbd_mlp_normalisation)."""
+    return xpbd.xpbd_mlp_normalisation(feats, targets)
 
 
 def train(net: "xpbd.Mlp", feats, targets, steps: int, batch: int = 8192, lr: float = 1e-3,
           seed: int = 0, final_lr: float = 1e-4):
     """Adam steps on minibatches drawn from a seeded permutation of the free
     recorded rows (epoch after epoch; the learning rate decays geometrically
-    from lr to final_lr).  Returns the loss of every step."""
+    from lr to final_lr).  Returns the loss of every step.
+
+    The host only queues launches: the permutations are drawn and checked
+    against the tables before the first step, each step's loss goes to a
+    device buffer, and the losses are read back once at the end."""
     import torch
     rng = np.random.default_rng(seed)
     free = np.flatnonzero(feats[:, 31].float().cpu().numpy() > 0).astype(np.int32)
     batch = min(batch, free.size)
-    order = torch.from_numpy(free[rng.permutation(free.size)]).cuda()
-    losses, at = [], 0
+    epochs, at, starts = [free[rng.permutation(free.size)]], 0, []
     for s in range(steps):
         if at + batch > free.size:
-            order = torch.from_numpy(free[rng.permutation(free.size)]).cuda()
+            epochs.append(free[rng.permutation(free.size)])
             at = 0
-        rate = lr * (final_lr / lr) ** (s / max(steps - 1, 1))
-        losses.append(net.train_step(feats, targets, rate, rows=order[at:at + batch]))
+        starts.append((len(epochs) - 1) * free.size + at)
         at += batch
-    return losses
+    order = torch.from_numpy(np.concatenate(epochs)).cuda()
+    xpbd.check_rows(order, feats.shape[0])
+    losses = torch.zeros(max(steps, 1), dtype=torch.float32, device="cuda")
+    for s in range(steps):
+        rate = lr * (final_lr / lr) ** (s / max(steps - 1, 1))
+        net.train_step(feats, targets, rate, rows=order[starts[s]:starts[s] + batch],
+                       loss_out=losses[s:s + 1], rows_checked=True)
+    return [float(v) for v in losses[:steps].cpu().numpy()]

@@ -72,7 +72,8 @@ EXPORTED = ["xpbd_create_batch", "xpbd_step", "xpbd_read_state", "xpbd_write_sta
             "xpbd_step_learned", "xpbd_autotune", "xpbd_surface_faces", "xpbd_policy_create",
             "xpbd_policy_destroy", "xpbd_rl_step", "xpbd_rl_step_learned",
             "xpbd_step_graph_create", "xpbd_rl_graph_create", "xpbd_graph_launch",
-            "xpbd_graph_destroy", "xpbd_get_batch_info"]
+            "xpbd_graph_destroy", "xpbd_get_batch_info", "xpbd_lds_probe",
+            "xpbd_prepare_mesh_coloured", "xpbd_mlp_normalisation"]
 
 # learned warm start (include/xpbd_learned.h)
 MLP_FEATURES = 27
@@ -102,7 +103,8 @@ class XpbdParams(ctypes.Structure):
                 ("num_tools", ctypes.c_int32), ("tool_radius", ctypes.c_float * 2),
                 ("flags", ctypes.c_uint32), ("block_size", ctypes.c_int32),
                 ("solver_variant", ctypes.c_int32), ("colour_packing", ctypes.c_int32),
-                ("envs_per_group", ctypes.c_int32), ("tool_shape", ctypes.c_int32)]
+                ("envs_per_group", ctypes.c_int32), ("tool_shape", ctypes.c_int32),
+                ("colouring", ctypes.c_int32)]
 
 
 class XpbdBatchInfo(ctypes.Structure):
@@ -138,6 +140,10 @@ _lib.xpbd_last_error.argtypes = []
 _lib.xpbd_prepare_mesh.restype = ctypes.c_int
 _lib.xpbd_prepare_mesh.argtypes = [ctypes.POINTER(XpbdMesh), ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+_lib.xpbd_prepare_mesh_coloured.restype = ctypes.c_int
+_lib.xpbd_prepare_mesh_coloured.argtypes = [ctypes.POINTER(XpbdMesh), ctypes.c_int32,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p]
 
 
 class XpbdLearnedParams(ctypes.Structure):
@@ -145,7 +151,7 @@ class XpbdLearnedParams(ctypes.Structure):
                 ("max_iterations", ctypes.c_int32), ("threshold", ctypes.c_float),
                 ("record_substep", ctypes.c_int32), ("record_features", ctypes.c_void_p),
                 ("record_targets", ctypes.c_void_p), ("iterations", ctypes.c_void_p),
-                ("stall_ratio", ctypes.c_float)]
+                ("stall_ratio", ctypes.c_float), ("residuals", ctypes.c_void_p)]
 
 
 _V = ctypes.c_void_p
@@ -168,6 +174,7 @@ _lib.xpbd_step_learned.argtypes = [_V, _V, ctypes.c_int32, _V, ctypes.POINTER(Xp
 
 # handle -> (num_envs, num_tools), to check tool-pose buffers before a launch
 _BATCHES = {}
+_SUBSTEPS = {}
 
 
 class XpbdError(RuntimeError):
@@ -214,7 +221,7 @@ def _mesh_struct(rest_pos, inv_mass, tets, keep):
 def make_params(dt, substeps, iterations, gravity=(0.0, 0.0, -9.81), num_tools=1,
                 tool_radius=(0.005, 0.005), flags=0, block_size=0,
                 solver_variant=VARIANT_AUTO, colour_packing=PACKING_AUTO,
-                envs_per_group=0, tool_shape=0) -> XpbdParams:
+                envs_per_group=0, tool_shape=0, colouring=0) -> XpbdParams:
     p = XpbdParams()
     p.dt = dt
     p.substeps = substeps
@@ -229,6 +236,7 @@ def make_params(dt, substeps, iterations, gravity=(0.0, 0.0, -9.81), num_tools=1
     p.colour_packing = colour_packing
     p.envs_per_group = envs_per_group
     p.tool_shape = tool_shape
+    p.colouring = colouring
     return p
 
 
@@ -267,19 +275,21 @@ def xpbd_surface_faces(rest_pos, inv_mass, tets):
     return faces[:F], colours[:F], int(counts[1])
 
 
-def xpbd_prepare_mesh(rest_pos, inv_mass, tets):
+def xpbd_prepare_mesh(rest_pos, inv_mass, tets, colouring=0):
     """Host-only set-up of one mesh: dict of edges, tets, colours and rest values."""
     keep = []
     m = _mesh_struct(rest_pos, inv_mass, tets, keep)
     counts = np.zeros(4, np.int32)
-    _check(_lib.xpbd_prepare_mesh(ctypes.byref(m), counts.ctypes.data, None, None, None, None))
+    _check(_lib.xpbd_prepare_mesh_coloured(ctypes.byref(m), int(colouring), counts.ctypes.data,
+                                           None, None, None, None))
     E, T = int(counts[0]), int(counts[1])
     edges = np.zeros((E, 2), np.int32)
     tout = np.zeros((T, 4), np.int32)
     colours = np.zeros(E + T, np.int32)
     rest = np.zeros(E + T, np.float32)
-    _check(_lib.xpbd_prepare_mesh(ctypes.byref(m), counts.ctypes.data, edges.ctypes.data,
-                                  tout.ctypes.data, colours.ctypes.data, rest.ctypes.data))
+    _check(_lib.xpbd_prepare_mesh_coloured(ctypes.byref(m), int(colouring), counts.ctypes.data,
+                                           edges.ctypes.data, tout.ctypes.data,
+                                           colours.ctypes.data, rest.ctypes.data))
     return {"edges": edges, "tets": tout, "edge_colour": colours[:E], "tet_colour": colours[E:],
             "num_edge_colours": int(counts[2]), "num_tet_colours": int(counts[3]),
             "rest_length": rest[:E], "rest_volume": rest[E:]}
@@ -300,7 +310,24 @@ def xpbd_create_batch(meshes, env_mesh, compliance, params: XpbdParams, stream=N
                                   ctypes.byref(out)))
     _BATCHES[out.value] = (int(env_mesh.shape[0]), int(params.num_tools),
                            6 if params.tool_shape == TOOL_CAPSULE else 3)
+    _SUBSTEPS[out.value] = int(params.substeps)
     return out.value
+
+
+# LDS bandwidth probe (include/xpbd_probe.h)
+PROBE_LDS_READ_B128 = 0
+PROBE_LDS_WRITE_B96 = 1
+_lib.xpbd_lds_probe.restype = ctypes.c_int
+_lib.xpbd_lds_probe.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                ctypes.c_void_p]
+
+
+def xpbd_lds_probe(kind, workgroups, reps, stream=None):
+    """(ms, bytes, cycles per workgroup, 100 MHz ticks per workgroup) of one timed
+    probe launch; see include/xpbd_probe.h."""
+    out = np.zeros(4, np.float64)
+    _check(_lib.xpbd_lds_probe(int(kind), int(workgroups), int(reps), stream, out.ctypes.data))
+    return tuple(float(v) for v in out)
 
 
 def xpbd_autotune(meshes, env_mesh, compliance, params: XpbdParams, num_steps, tool_pos,
@@ -374,6 +401,7 @@ def xpbd_get_batch_info(batch) -> dict:
 
 def xpbd_destroy_batch(batch):
     _BATCHES.pop(batch, None)
+    _SUBSTEPS.pop(batch, None)
     _lib.xpbd_destroy_batch(batch)
 
 
@@ -391,6 +419,16 @@ def _check_tool_pos(batch, num_steps, tool_pos):
         if not isinstance(tool_pos, np.ndarray) and str(tool_pos.dtype) != "torch.float32":
             raise TypeError("tool_pos must be float32")
     return tool_pos
+
+
+def _check_per_substep(batch, num_steps, t, dtype_name, what):
+    """A per-substep output buffer [num_steps * substeps * N] (device, contiguous)."""
+    if t is None:
+        return
+    n = _device_rows(t, 1, dtype_name, what)
+    n_envs, subs = _BATCHES.get(batch, (None,))[0], _SUBSTEPS.get(batch)
+    if n_envs is not None and subs is not None and n < int(num_steps) * subs * n_envs:
+        raise ValueError(f"{what} holds {n} values; the launch writes {int(num_steps) * subs * n_envs}")
 
 
 def xpbd_mlp_create(params, in_shift, in_scale, out_shift, out_scale, stream=None):
@@ -445,9 +483,39 @@ def xpbd_mlp_forward(net, features, y):
     _check(_lib.xpbd_mlp_forward(net, _ptr(features), n, _ptr(y)))
 
 
-def xpbd_mlp_train_step(net, features, targets, learning_rate, grad=None, rows=None):
+_lib.xpbd_mlp_normalisation.restype = ctypes.c_int
+_lib.xpbd_mlp_normalisation.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p]
+
+
+def xpbd_mlp_normalisation(features, targets, stream=None):
+    """(in_shift [27], in_scale [27], out_shift [3], out_scale [3]) float32 of a
+    recording (device bfloat16 [n, 32], float32 [n, 4]); see include/xpbd_learned.h."""
+    n = _device_rows(features, MLP_FEATURE_STRIDE, "torch.bfloat16", "features")
+    if _device_rows(targets, 4, "torch.float32", "targets") != n:
+        raise ValueError("targets need one row per feature row")
+    ish, isc = np.zeros(MLP_FEATURES, np.float32), np.zeros(MLP_FEATURES, np.float32)
+    osh, osc = np.zeros(3, np.float32), np.zeros(3, np.float32)
+    _check(_lib.xpbd_mlp_normalisation(_ptr(features), _ptr(targets), n, stream, ish.ctypes.data,
+                                       isc.ctypes.data, osh.ctypes.data, osc.ctypes.data))
+    return ish, isc, osh, osc
+
+
+def check_rows(rows, n):
+    """Raise unless every index of the device int32 tensor rows lies in [0, n)
+    (reads the tensor back: one synchronisation)."""
+    if rows.numel() and (int(rows.min()) < 0 or int(rows.max()) >= n):
+        raise ValueError("rows must index the feature table")
+
+
+def xpbd_mlp_train_step(net, features, targets, learning_rate, grad=None, rows=None,
+                        loss_out=None, rows_checked=False):
     """One training step on every row, or on the rows listed in ``rows`` (device
-    int32, each index checked here against the tables); returns the mean loss."""
+    int32, each index checked here against the tables unless the caller has
+    checked them, rows_checked).  Returns the mean loss; with ``loss_out`` (a
+    device float32 tensor of one value) the loss goes there in stream order
+    instead and nothing synchronises (returns None)."""
     n = _device_rows(features, MLP_FEATURE_STRIDE, "torch.bfloat16", "features")
     if _device_rows(targets, 4, "torch.float32", "targets") != n:
         raise ValueError("targets need one row per feature row")
@@ -456,8 +524,14 @@ def xpbd_mlp_train_step(net, features, targets, learning_rate, grad=None, rows=N
     count = n
     if rows is not None:
         count = _device_rows(rows, 1, "torch.int32", "rows")
-        if count and (int(rows.min()) < 0 or int(rows.max()) >= n):
-            raise ValueError("rows must index the feature table")
+        if not rows_checked:
+            check_rows(rows, n)
+    if loss_out is not None:
+        if _device_rows(loss_out, 1, "torch.float32", "loss_out") < 1:
+            raise ValueError("loss_out needs one value")
+        _check(_lib.xpbd_mlp_train_step(net, _ptr(features), _ptr(targets), _ptr(rows), count,
+                                        float(learning_rate), _ptr(loss_out), _ptr(grad)))
+        return None
     loss = ctypes.c_float(0.0)
     _check(_lib.xpbd_mlp_train_step(net, _ptr(features), _ptr(targets), _ptr(rows), count,
                                     float(learning_rate), ctypes.addressof(loss), _ptr(grad)))
@@ -479,14 +553,17 @@ def xpbd_axis_neighbours(rest_pos):
 
 def xpbd_step_learned(batch, net, num_steps, tool_pos, min_iterations, max_iterations,
                       threshold, apply_correction=True, record_substep=-1, record_features=None,
-                      record_targets=None, iterations=None, stall_ratio=0.0):
+                      record_targets=None, iterations=None, stall_ratio=0.0, residuals=None):
     """One substep per launch with the network's correction; see include/xpbd_learned.h.
-    record_features / record_targets / iterations: device tensors (bfloat16 [NP, 32],
-    float32 [NP, 4], int32 [num_steps * substeps * N]) or None."""
+    record_features / record_targets / iterations / residuals: device tensors (bfloat16
+    [NP, 32], float32 [NP, 4], int32 and float32 [num_steps * substeps * N]) or None."""
     tool_pos = _check_tool_pos(batch, num_steps, tool_pos)
+    _check_per_substep(batch, num_steps, iterations, "torch.int32", "iterations")
+    _check_per_substep(batch, num_steps, residuals, "torch.float32", "residuals")
     lp = XpbdLearnedParams(int(bool(apply_correction)), int(min_iterations), int(max_iterations),
                            float(threshold), int(record_substep), _ptr(record_features),
-                           _ptr(record_targets), _ptr(iterations), float(stall_ratio))
+                           _ptr(record_targets), _ptr(iterations), float(stall_ratio),
+                           _ptr(residuals))
     _check(_lib.xpbd_step_learned(batch, net, int(num_steps), _ptr(tool_pos), ctypes.byref(lp)))
 
 
@@ -573,13 +650,17 @@ def xpbd_rl_step(batch, policy, params: XpbdRlParams, num_steps, tool_pos, grasp
 def xpbd_rl_step_learned(batch, policy, params: XpbdRlParams, net, num_steps, tool_pos, grasped,
                          target, min_iterations, max_iterations, threshold, obs=None,
                          actions=None, apply_correction=True, iterations=None, stall_ratio=0.0,
-                         record_substep=-1, record_features=None, record_targets=None):
+                         record_substep=-1, record_features=None, record_targets=None,
+                         residuals=None):
     """xpbd_rl_step with the learned warm start (see include/xpbd_rl.h);
-    iterations: device int32 [num_steps * substeps * N] or None."""
+    iterations / residuals: device int32 / float32 [num_steps * substeps * N] or None."""
     _check_rl_buffers(batch, num_steps, tool_pos, grasped, target, obs, actions)
+    _check_per_substep(batch, num_steps, iterations, "torch.int32", "iterations")
+    _check_per_substep(batch, num_steps, residuals, "torch.float32", "residuals")
     lp = XpbdLearnedParams(int(bool(apply_correction)), int(min_iterations), int(max_iterations),
                            float(threshold), int(record_substep), _ptr(record_features),
-                           _ptr(record_targets), _ptr(iterations), float(stall_ratio))
+                           _ptr(record_targets), _ptr(iterations), float(stall_ratio),
+                           _ptr(residuals))
     _check(_lib.xpbd_rl_step_learned(batch, policy, ctypes.byref(params), net, ctypes.byref(lp),
                                      int(num_steps), _ptr(tool_pos), _ptr(grasped), _ptr(target),
                                      _ptr(obs), _ptr(actions)))
@@ -601,11 +682,11 @@ _lib.xpbd_graph_destroy.argtypes = [_V]
 
 def make_learned_params(min_iterations, max_iterations, threshold, apply_correction=True,
                         record_substep=-1, record_features=None, record_targets=None,
-                        iterations=None, stall_ratio=0.0) -> XpbdLearnedParams:
+                        iterations=None, stall_ratio=0.0, residuals=None) -> XpbdLearnedParams:
     return XpbdLearnedParams(int(bool(apply_correction)), int(min_iterations),
                              int(max_iterations), float(threshold), int(record_substep),
                              _ptr(record_features), _ptr(record_targets), _ptr(iterations),
-                             float(stall_ratio))
+                             float(stall_ratio), _ptr(residuals))
 
 
 def xpbd_step_graph_create(batch, net, learned, tool_pos):
@@ -711,8 +792,10 @@ class Mlp:
     def forward(self, features, y):
         xpbd_mlp_forward(self.handle, features, y)
 
-    def train_step(self, features, targets, learning_rate, grad=None, rows=None):
-        return xpbd_mlp_train_step(self.handle, features, targets, learning_rate, grad, rows)
+    def train_step(self, features, targets, learning_rate, grad=None, rows=None, loss_out=None,
+                   rows_checked=False):
+        return xpbd_mlp_train_step(self.handle, features, targets, learning_rate, grad, rows,
+                                   loss_out, rows_checked)
 
     def close(self):
         if self.handle:

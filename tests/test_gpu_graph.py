@@ -133,10 +133,40 @@ def test_graph_rejects_bad_arguments(xp):
             with pytest.raises(xp.XpbdError, match="times"):
                 g.launch(-1)
             g.launch(0)
-    # two size classes: one launch per class and step, not captured
+    # two size classes: the plain step is captured, the learned one needs one class
     meshes = [W.slab_mesh(12, 8, 3), W.slab_mesh(20, 12, 6)]
     uw = W.Workload("two", meshes, np.array([0, 1], np.int32),
                     W.log_uniform_compliance(2, 1e-7, 1e-5, 1), iterations=4, num_steps=1, seed=1)
     with xp.Batch(K.lib_meshes(uw), uw.env_mesh, uw.compliance, K.lib_params(xp, uw)) as b:
+        assert b.info()["size_classes"] == 2
+        net = small_net(xp)
+        lp = xp.make_learned_params(2, 4, -1.0)
         with pytest.raises(xp.XpbdError, match="one size class"):
-            b.step_graph(torch.from_numpy(W.tool_path(1, 2, 1)[0]).cuda())
+            b.step_graph(torch.from_numpy(W.tool_path(1, 2, 1)[0]).cuda(), net, lp)
+        net.close()
+
+
+def test_uneven_batch_graph_replays_equal_eager_steps(xp):
+    """The 4096-environment uneven workload (675 slabs in several size
+    classes, each one launch per step on its own stream): one step captured
+    with the classes' fork and join, replayed with eager steps of a second
+    batch and copies of the next tool poses in between; every replay equals
+    the eager step bit for bit."""
+    import torch
+    steps = 4
+    wl = W.uneven_workload(4096, seed=0, num_steps=steps)
+    tools = torch.from_numpy(wl.tools(steps)).cuda()
+    p = K.lib_params(xp, wl)
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as eager, \
+            xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as cap:
+        assert cap.info()["size_classes"] >= 2
+        buf = torch.zeros_like(tools[0])
+        with cap.step_graph(buf) as g:
+            for s in range(steps):
+                eager.step(1, tools[s:s + 1])
+                buf.copy_(tools[s])
+                g.launch()
+                torch.cuda.synchronize()
+                assert np.array_equal(cap.positions(), eager.positions()), f"replay {s}"
+                assert np.array_equal(cap.velocities(), eager.velocities()), f"replay {s}"
+                assert np.array_equal(cap.read(xp.FIELD_CONTACTS), eager.read(xp.FIELD_CONTACTS))

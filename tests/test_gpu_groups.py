@@ -61,6 +61,39 @@ def test_groups_of_two_are_bitwise_equal_to_single_envs(xp):
         assert b.read(xp.FIELD_CONTACT_COUNTS).sum() > 0
 
 
+def small_meshes_workload(seed=5):
+    """Slabs of 105 to 504 particles with odd environment counts: the
+    library's per-class choice runs the smallest two to a workgroup."""
+    grids = [(6, 4, 2), (7, 4, 2), (8, 5, 3), (11, 6, 5)]
+    meshes = [W.slab_mesh(*g) for g in grids]
+    env_mesh = np.array([0, 1, 2, 3, 0, 0, 1, 2, 3, 3, 0], np.int32)
+    return W.Workload("small-meshes", meshes, env_mesh,
+                      W.log_uniform_compliance(len(env_mesh), 1e-7, 1e-5, seed), iterations=8,
+                      num_steps=40, seed=seed)
+
+
+def test_per_class_groups_are_bitwise_equal_to_single_envs(xp):
+    """Several meshes with the environments per workgroup left to the library:
+    the small meshes' classes run two environments per workgroup, the others
+    one (the batch reports the largest); with the packing fixed to id order
+    the results equal one environment per workgroup bit for bit."""
+    wl = small_meshes_workload()
+    steps = 40
+    tools = W.tool_path(steps, wl.num_envs, wl.seed, start_depth=6e-3)
+    flags = xp.F_LAMBDA | xp.F_RESIDUAL
+    with grouped_batch(xp, wl, 1, xp.PACKING_ID_ORDER, flags) as a, \
+            grouped_batch(xp, wl, 0, xp.PACKING_ID_ORDER, flags) as b:
+        assert a.info()["envs_per_group"] == 1
+        assert b.info()["envs_per_group"] == 2 and b.info()["size_classes"] >= 2
+        a.step(steps, tools)
+        b.step(steps, tools)
+        assert np.array_equal(a.positions(), b.positions())
+        assert np.array_equal(a.velocities(), b.velocities())
+        for f in (xp.FIELD_LAMBDA, xp.FIELD_CONTACTS, xp.FIELD_CONTACT_COUNTS,
+                  xp.FIELD_RESIDUAL):
+            assert np.array_equal(a.read(f), b.read(f)), f
+
+
 def test_groups_of_two_oracle_parity(xp, oracle_lib):
     wl = uneven_odd_workload(seed=4)
     steps = 60
@@ -148,6 +181,7 @@ def test_batch_info_reports_the_chosen_launch(xp):
     un = W.uneven_workload(64, seed=0, num_steps=1)
     with xp.Batch(K.lib_meshes(un), un.env_mesh, un.compliance, K.lib_params(xp, un)) as b:
         assert b.info()["size_classes"] >= 2
+        assert b.info()["envs_per_group"] == 2      # the small meshes' classes
     p = K.lib_params(xp, wl)
     p.solver_variant = xp.VARIANT_LDS
     small = W.batch_workload(4, seed=0, num_steps=1)

@@ -127,6 +127,75 @@ def test_adam_step_matches_oracle_and_training_reduces_loss(xp):
     assert last < 0.2 * first
 
 
+def test_adam_steps_match_oracle_over_several_steps(xp):
+    """Four Adam steps on the GPU, each on another minibatch, against the
+    oracle's Adam fed with the gradient the GPU reports for the same step:
+    only the optimiser is compared (moments carried across the steps, bias
+    correction, the update), in FP64 on the oracle's side.  From the second
+    step on the update depends on both moments' decay, so a wrong or missing
+    accumulation shows up here."""
+    import torch
+    net = random_net(6)
+    rng = np.random.default_rng(7)
+    n = 512
+    a0 = ws.bf16(rng.standard_normal((n, 27)))
+    free = np.ones(n, bool)
+    t = np.tanh(a0[:, :3] * 0.5)
+    tgt = np.zeros((n, 4), np.float32)
+    tgt[:, :3] = t
+    feats, targets = feature_rows(a0, free), torch.tensor(tgt).cuda()
+    lr = 1e-3
+    opt = ws.Adam(lr=lr)
+    with xp.Mlp(flat(net), None, np.ones(27), None, net.out_scale) as m:
+        params = unflat(net, m.params())
+        moved = np.zeros(xp.MLP_PARAMS)
+        for k in range(1, 5):
+            rows = torch.tensor(np.sort(rng.choice(n, 160, replace=False)).astype(np.int32)).cuda()
+            g = torch.zeros(xp.MLP_PARAMS, dtype=torch.float32, device="cuda")
+            before = m.params().astype(np.float64)
+            m.train_step(feats, targets, lr, grad=g, rows=rows)
+            got = m.params().astype(np.float64)
+            opt.step(params, unflat(net, g.cpu().numpy()))
+            want = np.concatenate([p.reshape(-1) for p in params])
+            # float32 master weights round once per step; fp32 moments and
+            # update arithmetic stay within 1e-5 of the step size
+            ulp = np.spacing(np.abs(want).astype(np.float32)).astype(np.float64)
+            err = np.abs(got - want)
+            assert (err <= k * (ulp + 1e-5 * lr)).all(), (k, float((err / (ulp + 1e-5 * lr)).max()))
+            moved = np.maximum(moved, np.abs(got - before))
+    assert moved.max() > 0.5 * lr      # the steps did move the weights
+
+
+def test_normalisation_statistics_match_numpy(xp):
+    """The library's normalisation of a recording (means and population
+    standard deviations over the free rows, in double precision on the GPU)
+    against numpy's on the same rows: features as bfloat16 values of realistic
+    scales with a constant column and a ragged row count, targets float32."""
+    import torch
+    rng = np.random.default_rng(12)
+    n = 100_003
+    scale = np.array([2e-4] * 3 + [0.1] * 3 + [2e-3] * 3 + [2e-5] * 18)
+    shift = np.array([0.0] * 6 + [0.05] * 3 + [1e-3] * 18)
+    f = np.zeros((n, 32), np.float32)
+    f[:, :27] = rng.normal(size=(n, 27)) * scale + shift
+    f[:, 20] = 0.25                                   # a constant column: std 0
+    f[:, 31] = rng.random(n) > 0.2
+    feats = torch.tensor(f).to(torch.bfloat16).cuda()
+    t = np.zeros((n, 4), np.float32)
+    t[:, :3] = rng.normal(size=(n, 3)) * 3e-6 + 1e-6
+    ish, isc, osh, osc = xp.xpbd_mlp_normalisation(feats, torch.tensor(t).cuda())
+    fb = feats.float().cpu().numpy().astype(np.float64)
+    free = fb[:, 31] > 0
+    mf, sf = fb[free, :27].mean(axis=0), fb[free, :27].std(axis=0)
+    mt, st = t[free, :3].astype(np.float64).mean(axis=0), t[free, :3].astype(np.float64).std(axis=0)
+    np.testing.assert_allclose(ish, mf, rtol=1e-6, atol=1e-12)
+    want_scale = np.where(sf > 0, 1.0 / np.maximum(sf, 1e-30), 1.0)
+    np.testing.assert_allclose(isc, want_scale, rtol=1e-5)
+    assert isc[20] == 1.0
+    np.testing.assert_allclose(osh, mt, rtol=1e-5, atol=1e-13)
+    np.testing.assert_allclose(osc, np.maximum(st, 1e-12), rtol=1e-5)
+
+
 def make_batch(xp, wl, flags=0):
     p = K.lib_params(xp, wl, flags)
     p.solver_variant = xp.VARIANT_REGISTERS
@@ -204,6 +273,90 @@ def test_stalled_fallback_follows_the_oracle(xp, oracle_lib):
     assert np.array_equal(its.cpu().numpy(), ref.iterations.ravel())
     err = K.max_position_error(x, ref.x)
     assert err <= K.POS_TOL, f"max position error {err:.3e}"
+
+
+@pytest.fixture(scope="module")
+def full_size_learned(oracle_lib):
+    """The benchmark's learned configuration at full size, oracle side: 1024
+    environments of the 16x10x4 slab (per-environment compliances and tool
+    walks), 10 plain steps, then 20 learned steps with 2 sweeps, the residual
+    check and fallback to 8.  The threshold follows the benchmark's rule (the
+    0.99 quantile of the plain solver's residual at the end of each warm-up
+    step), taken here from the oracle's plain runs of the sampled
+    environments; the network is a seeded random one at realistic feature and
+    output scales (no input of the oracle comes from the GPU)."""
+    from concurrent.futures import ThreadPoolExecutor
+    warm, steps = 10, 20
+    wl = W.batch_workload(1024, seed=0, num_steps=warm + steps)
+    tools = wl.tools(warm + steps)
+    sample = list(range(0, 1024, 64))
+    om = K.oracle_meshes(oracle_lib, wl)[0]
+    P = K.oracle_params(oracle_lib, wl)
+    threads = min(16, len(sample))
+    with ThreadPoolExecutor(threads) as pool:
+        pre = list(pool.map(lambda e: oracle_lib.run_env(om, wl.compliance[e], P, tools[:warm, e],
+                                                         warm, want_residual=True), sample))
+    threshold = float(np.quantile(np.concatenate([r.residual[:, -1, 0] for r in pre]), 0.99))
+    in_scale = 1.0 / np.array([2e-4] * 3 + [0.1] * 3 + [2e-3] * 3 + [2e-5] * 18)
+    net = random_net(8, out_scale=2e-6)
+    net.in_scale = in_scale.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(8)
+    net.in_shift = (rng.uniform(-0.3, 0.3, 27) / in_scale).astype(np.float32).astype(np.float64)
+    free = om.w > 0
+    nbr = ws.axis_neighbours(om.rest)
+
+    def corr(x_prev, v_start, x_hat, nb):
+        return ws.correction(net, ws.features(x_prev, v_start, x_hat, om.rest, nb), free)
+
+    refs = {}
+    for stall, envs in ((0.9, range(len(sample))), (0.0, range(0, len(sample), 2))):
+        def run(n, stall=stall):
+            e = sample[n]
+            return oracle_lib.run_env_learned(om, wl.compliance[e], P, tools[warm:, e], steps, corr,
+                                              2, 8, threshold, x0=pre[n].x, v0=pre[n].v, nbr=nbr,
+                                              stall_ratio=stall)
+        with ThreadPoolExecutor(threads) as pool:
+            refs[stall] = dict(zip(envs, pool.map(run, envs)))
+    return wl, tools, sample, net, threshold, refs, warm, steps
+
+
+@pytest.mark.parametrize("stall", [0.9, 0.0])
+def test_full_size_learned_step_follows_the_oracle(xp, full_size_learned, stall):
+    """The learned step as the benchmark runs it (stall ratio 0.9), and with
+    fallback whenever the residual is above the threshold (stall ratio 0), on
+    the full 1024-environment batch: sampled environments against the
+    oracle's learned driver, positions to the parity gate; sweep counts equal
+    wherever the oracle's decision is at least 0.5 % from its tie (the
+    residual against the threshold, and the stall ratio where it applies)."""
+    import torch
+    wl, tools, sample, net, threshold, refs, warm, steps = full_size_learned
+    N, S = wl.num_envs, wl.substeps
+    its = torch.zeros(steps * S * N, dtype=torch.int32, device="cuda")
+    with make_batch(xp, wl) as b, \
+            xp.Mlp(flat(net), net.in_shift, net.in_scale, net.out_shift, net.out_scale) as m:
+        b.step(warm, tools[:warm])
+        b.step_learned(m, steps, tools[warm:], 2, 8, threshold, iterations=its, stall_ratio=stall)
+        x = b.positions()
+        offsets = b.env_offsets
+    it = its.cpu().numpy().reshape(steps, S, N)
+    counts = {2: 0, 8: 0}
+    for n, ref in refs[stall].items():
+        e = sample[n]
+        err = K.max_position_error(K.env_block(x, offsets, e), ref.x)
+        assert err <= K.POS_TOL, f"env {e}: max position error {err:.3e}"
+        early = ref.early_residual
+        clear = np.abs(early - threshold) >= 0.005 * threshold
+        if stall > 0:
+            ratio = ref.checks[:, :, 2] / ref.checks[:, :, 1]
+            clear &= (early <= threshold) | (np.abs(ratio - stall) >= 0.005 * stall)
+        got = it[:, :, e]
+        assert np.array_equal(got[clear], ref.iterations[clear]), f"env {e}"
+        assert np.isin(got, (2, 8)).all()
+        for k in counts:
+            counts[k] += int((ref.iterations == k).sum())
+    # the sample holds both decisions without the stall rule; with it the
+    # rule stops every fallback in this sample
+    assert counts[2] > 0 and (counts[8] > 0 if stall == 0 else True), counts
 
 
 def test_next_substep_features_equal_the_prediction_kernel(xp):

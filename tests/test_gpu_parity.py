@@ -449,9 +449,9 @@ def test_flags_can_change_between_steps(xp):
 
 def test_uneven_4096_sampled_parity(xp, oracle_lib):
     """The 4096-environment uneven workload (675 distinct slabs of 105 to 1911
-    particles) in one launch: the smallest and largest environments and four
-    others follow the oracle after 20 steps."""
-    steps = 20
+    particles) as the benchmark launches it: the smallest and largest
+    environments and four others follow the oracle after 100 steps."""
+    steps = 100
     wl = W.uneven_workload(4096, seed=0, num_steps=steps)
     V = np.array([m.num_vertices for m in wl.meshes])[wl.env_mesh]
     sample = sorted({int(np.argmin(V)), int(np.argmax(V)), 0, 1000, 2047, 4095})
@@ -500,12 +500,14 @@ def test_jacobi_follows_the_oracle(xp, oracle_lib, case):
     assert max(np.abs(plain[e].x - refs[e].x).max() for e in envs) > K.POS_TOL
 
 
-@pytest.mark.parametrize("case", ["single", "batch-3-envs", "jacobi"])
+@pytest.mark.parametrize("case", ["single", "batch-3-envs", "single-lds", "batch-3-envs-lds",
+                                  "jacobi"])
 def test_capsule_tools_follow_the_oracle(xp, oracle_lib, case):
     """Capsule tools against the surface faces (XPBD_TOOL_CAPSULE): positions
     follow the oracle's capsule driver; the first step's candidate-face counts
-    are equal."""
-    if case == "batch-3-envs":
+    are equal.  The library's choice runs them on the register variant; the
+    LDS and Jacobi variants are checked too."""
+    if case.startswith("batch-3-envs"):
         wl = W.batch_workload(3, seed=9, num_steps=30)
     else:
         wl = W.single_env_workload(seed=9)
@@ -520,9 +522,13 @@ def test_capsule_tools_follow_the_oracle(xp, oracle_lib, case):
     assert sum(r.contact_count.sum() for r in refs) > 0
     p = K.lib_params(xp, wl)
     p.tool_shape = xp.TOOL_CAPSULE
+    want = xp.VARIANT_REGISTERS
     if jacobi:
-        p.solver_variant = xp.VARIANT_JACOBI
+        p.solver_variant = want = xp.VARIANT_JACOBI
+    elif case.endswith("-lds"):
+        p.solver_variant = want = xp.VARIANT_LDS
     with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b:
+        assert b.info()["solver_variant"] == want
         b.step(1, caps[:1])
         counts = b.read(xp.FIELD_CONTACT_COUNTS).reshape(wl.num_envs, 1)
         assert [int(c) for c in counts[:, 0]] == [int(r.contact_count[0, 0]) for r in refs]

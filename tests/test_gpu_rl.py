@@ -98,9 +98,10 @@ def run_gpu(xp, wl, policy_params, steps, tools, target, grasped, per_step=True)
         tg = torch.from_numpy(np.ascontiguousarray(target)).cuda()
         obs = torch.zeros((steps, N, R.OBS), dtype=torch.float32, device="cuda")
         act = torch.zeros((steps, N, R.ACTIONS), dtype=torch.float32, device="cuda")
-        tool_hist, grasp_hist = [], []
+        tool_hist, grasp_hist, x_hist = [], [], []
         if per_step:
             for s in range(steps):
+                x_hist.append(b.positions())
                 b.rl_step(pol, rp, 1, tp, gr, tg, obs[s], act[s])
                 tool_hist.append(tp.cpu().numpy().copy())
                 grasp_hist.append(gr.cpu().numpy().copy())
@@ -111,8 +112,36 @@ def run_gpu(xp, wl, policy_params, steps, tools, target, grasped, per_step=True)
         torch.cuda.synchronize()
         x = b.positions()
         offs = b.env_offsets
+    run_gpu.x_hist = x_hist    # start-of-step positions of the last per-step run
     return (np.array(tool_hist), np.array(grasp_hist), obs.cpu().numpy(), act.cpu().numpy(),
             x, offs)
+
+
+def check_grasps_valid(wl, got, e, x_hist, prev_grasp):
+    """An environment whose decisions lie inside the oracle's tie bands: every
+    grasp the GPU took names a free particle strictly within r_l of the
+    dragging point, whose squared distance (FP64, from the GPU's own
+    start-of-step positions and tool centre) is within SELECT_MARGIN r_l^2 of
+    the smallest over the free particles; a grasper that closed on nothing had
+    no free particle clearly within reach."""
+    m = wl.meshes[0]
+    tool_hist, grasp_hist, _, act, _, offs = got
+    r2 = W.RL_GRASP_RADIUS ** 2
+    free = m.inv_mass > 0
+    before = prev_grasp
+    for s in range(len(x_hist)):
+        g = int(grasp_hist[s, e])
+        xs = K.env_block(x_hist[s], offs, e).astype(np.float64)
+        point = tool_hist[s, e, 0].astype(np.float64) + np.asarray(W.RL_GRASP_OFFSET)
+        d2 = np.sum((xs - point) ** 2, axis=1)
+        best = d2[free].min()
+        if g >= 0 and g != before:            # a fresh grasp in step s
+            assert free[g], f"env {e} step {s}: grasped pinned particle {g}"
+            assert d2[g] < r2 * (1 + SELECT_MARGIN), f"env {e} step {s}: {g} out of reach"
+            assert d2[g] - best <= SELECT_MARGIN * r2, f"env {e} step {s}: {g} not closest"
+        elif g < 0 and act[s, e, 6] > DECISION_MARGIN and before < 0:
+            assert best >= r2 * (1 - SELECT_MARGIN), f"env {e} step {s}: closed on nothing"
+        before = g
 
 
 def run_oracle(oracle_lib, wl, policy_params, steps, tools, target, grasped, env_ids):
@@ -185,12 +214,15 @@ def test_rl_random_policy_parity(xp, oracle_lib):
     got = run_gpu(xp, wl, pp, steps, tools, target, grasped)
     refs = run_oracle(oracle_lib, wl, pp, steps, tools, target, grasped, range(N))
     drift = steps * ACT_TOL * W.RL_MAX_SPEED * wl.dt
+    x_hist = run_gpu.x_hist
     clear = [n for n in range(N) if decisions_clear(refs[n])]
     assert len(clear) >= 0.75 * N, f"only {len(clear)} environments with clear decisions"
     worst_x = worst_a = 0.0
     for n in clear:
         err, a_err = compare(refs[n], n, n, got, K.POS_TOL + drift, ACT_TOL, got[5], slice(None))
         worst_x, worst_a = max(worst_x, err), max(worst_a, a_err)
+    for n in set(range(N)) - set(clear):
+        check_grasps_valid(wl, got, n, x_hist, int(grasped[n]))
     # every environment: a valid grasp state
     m = wl.meshes[0]
     g = got[1][-1]
@@ -213,6 +245,7 @@ def test_rl_full_size_sampled(xp, oracle_lib):
     tools, target, grasped = start_state(N)
     pp = W.rl_policy_params(0)
     got = run_gpu(xp, wl, pp, steps, tools, target, grasped)
+    x_hist = run_gpu.x_hist
     m = wl.meshes[0]
     rl = oracle_rl_params(m)
     net = R.unpack_policy(pp)
@@ -238,6 +271,9 @@ def test_rl_full_size_sampled(xp, oracle_lib):
             compare(refs[n], n, e, got, K.POS_TOL + drift, ACT_TOL, got[5], slice(None))
             checked += 1
     assert checked >= 0.75 * len(sample)
+    # every environment of the batch: grasps valid and inside the tie band
+    for e in range(N):
+        check_grasps_valid(wl, got, e, x_hist, int(grasped[e]))
 
 
 def test_rl_zero_steps_and_optional_outputs(xp):

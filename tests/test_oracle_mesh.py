@@ -139,3 +139,84 @@ def test_all_pinned_constraints_dropped(oracle_lib):
     assert all((w[q] > 0).any() for q in om.tets)
     assert all((w[e] > 0).any() for e in om.edges)
     assert om.num_tets == int(sum((m.tets == 0).any(axis=1)))
+
+
+# ------------------------------------------------------------------ largest-first colouring
+def _chain(n):
+    """n distance constraints (i, i + 1) along a chain of n + 1 particles."""
+    return np.array([[i, i + 1] for i in range(n)], np.int32)
+
+
+def test_largest_first_on_a_chain_by_hand(oracle_lib):
+    """On a chain the conflict graph is a path.  Largest first starts with the
+    lowest-index constraint of the largest conflict count (constraint 1: two
+    conflicts), which rules out 0 and 2; then the candidate with the most
+    ruled-out neighbours is 3, which rules out 4; then 5.  The remaining
+    constraints 0, 2, 4 form the second colour.  Greedy gives the opposite
+    parity."""
+    lf, n_lf = oracle_lib.largest_first_colour(7, _chain(6))
+    assert n_lf == 2
+    assert lf.tolist() == [1, 0, 1, 0, 1, 0]
+    gr, n_gr = oracle_lib.greedy_colour(7, _chain(6))
+    assert n_gr == 2 and gr.tolist() == [0, 1, 0, 1, 0, 1]
+
+
+def test_largest_first_star_and_ties_by_hand(oracle_lib):
+    """A star of four constraints around particle 0 plus one constraint (5, 6)
+    apart.  Every star constraint has three conflicts, so the first colour
+    starts with the lowest index, 0, rules out 1..3 and adds the only
+    candidate left, 4; the star constraints 1, 2, 3 then take one colour each
+    in index order."""
+    verts = np.array([[0, 1], [0, 2], [0, 3], [0, 4], [5, 6]], np.int32)
+    lf, n = oracle_lib.largest_first_colour(7, verts)
+    assert n == 4 and lf.tolist() == [0, 1, 2, 3, 0]
+
+
+def test_largest_first_cut_keeps_the_first_64_picks(oracle_lib):
+    """100 disjoint constraints form one colour of 100 members.  With the cut at
+    100 that colour keeps its first 64 picks (all tied: by index, 0..63) and
+    the other 36 form the next colour; with the cut at 99 it stays whole."""
+    verts = np.array([[2 * i, 2 * i + 1] for i in range(100)], np.int32)
+    whole, n = oracle_lib.largest_first_colour(200, verts, 99)
+    assert n == 1 and not whole.any()
+    cut, n = oracle_lib.largest_first_colour(200, verts, 100)
+    assert n == 2
+    assert (cut[:64] == 0).all() and (cut[64:] == 1).all()
+
+
+@pytest.mark.parametrize("grid", GRIDS)
+@pytest.mark.parametrize("colouring", [1, 2])
+def test_largest_first_colours_are_valid_and_maximal(oracle_lib, grid, colouring):
+    """Every colour is a set of constraints sharing no particle; a colour that
+    was not cut is maximal among the constraints coloured after it (each of
+    them conflicts with one of its members); with the cut no colour has 65 to
+    100 members."""
+    m = W.slab_mesh(*grid)
+    om = oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass, m.tets, colouring=colouring)
+    for verts, col, nc in ((om.edges, om.edge_colour, om.num_edge_colours),
+                           (om.tets, om.tet_colour, om.num_tet_colours)):
+        assert col.min() == 0 and col.max() == nc - 1
+        sizes = np.bincount(col, minlength=nc)
+        touched = []
+        for c in range(nc):
+            members = verts[col == c].ravel()
+            assert len(np.unique(members)) == len(members), f"colour {c} shares a particle"
+            touched.append(set(members.tolist()))
+        for j in range(len(col)):
+            for c in range(col[j]):
+                cut = colouring == 2 and sizes[c] == 64
+                if not cut:
+                    assert touched[c] & set(verts[j].tolist()), (j, c)
+        if colouring == 2:
+            assert not ((sizes > 64) & (sizes <= oracle_lib.WAVE_CUT_ABOVE)).any()
+
+
+def test_largest_first_reaches_the_degree_bound(oracle_lib):
+    """On the 8x5x3 and 12x8x3 slabs largest first colours the tetrahedra with
+    32 colours: the largest number of tetrahedra sharing one particle, a lower
+    bound for any colouring, so the count is optimal (greedy needs 37)."""
+    for grid in ((8, 5, 3), (12, 8, 3)):
+        m = W.slab_mesh(*grid)
+        om = oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass, m.tets, colouring=1)
+        degree = np.bincount(om.tets.ravel()).max()
+        assert degree == 32 and om.num_tet_colours == degree
