@@ -8,6 +8,7 @@ import os
 import re
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(PKG, "csrc")
@@ -59,34 +60,40 @@ def _check_register_kernels(remarks: str):
                            "multiplier bank was not kept in VGPRs")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link the shared library; returns its path."""
-    os.makedirs(BUILD, exist_ok=True)
-    objects = []
-    for name in HIP_SOURCES:
-        obj = os.path.join(BUILD, name + ".o")
-        cmd = [HIPCC, *HIP_FLAGS, "-c", os.path.join(SRC, name), "-o", obj]
-        if name == "xpbd_kernels.hip":
-            cmd.append("-Rpass-analysis=kernel-resource-usage")
-            if verbose:
-                print(" ".join(cmd), flush=True)
-            out = subprocess.run(cmd, capture_output=True, text=True)
-            if out.returncode != 0:
-                sys.stderr.write(out.stderr)
-                raise subprocess.CalledProcessError(out.returncode, cmd)
-            _check_register_kernels(out.stderr)
-        else:
-            _run(cmd, verbose)
-        objects.append(obj)
-    for name in CXX_SOURCES:
+def _compile(name, verbose):
+    """Compile one source into _build/; returns the object's path."""
+    if name in CXX_SOURCES:
         obj = os.path.join(BUILD, name + ".o")
         _run(["g++", *CXX_FLAGS, "-c", os.path.join(SRC, name), "-o", obj], verbose)
-        objects.append(obj)
+        return obj
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [HIPCC, *HIP_FLAGS, "-c", os.path.join(SRC, name), "-o", obj]
+    if name == "xpbd_kernels.hip":
+        cmd.append("-Rpass-analysis=kernel-resource-usage")
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        out = subprocess.run(cmd, capture_output=True, text=True)
+        if out.returncode != 0:
+            sys.stderr.write(out.stderr)
+            raise subprocess.CalledProcessError(out.returncode, cmd)
+        _check_register_kernels(out.stderr)
+    else:
+        _run(cmd, verbose)
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source (several at once) and link the shared library;
+    returns its path."""
+    os.makedirs(BUILD, exist_ok=True)
+    names = HIP_SOURCES + CXX_SOURCES
+    jobs = max(1, min(len(names), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        objects = list(pool.map(lambda n: _compile(n, verbose), names))
     tmp = LIB + f".tmp{os.getpid()}"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objects], verbose)
     os.replace(tmp, LIB)
     return LIB
-
 
 if __name__ == "__main__":
     print(build(verbose="-q" not in sys.argv))
