@@ -148,6 +148,29 @@ typedef struct {
 xpbd_status xpbd_step_learned(xpbd_batch *batch, const xpbd_mlp *net, int32_t num_steps,
                               const float *tool_pos, const xpbd_learned_params *params);
 
+/* Bytes of the device array that holds the allocation-free step's workspace
+ * (80 MiB; one copy per device the library runs on, held until the process
+ * ends). */
+#define XPBD_NOALLOC_SCRATCH_BYTES (80u << 20)
+
+/* xpbd_step_learned for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same steps and results, with the workspace (predicted
+ * positions 12 B, feature rows 64 B with the correction, candidate bits 1 B
+ * per particle, 4 B per mesh, each part 256-byte aligned) taken from a
+ * fixed device array of XPBD_NOALLOC_SCRATCH_BYTES instead of buffers the
+ * batch allocates; no hipMalloc, hipFree or other allocation.  tool_pos must
+ * be device memory.  The batch's device must be current.
+ * Errors: XPBD_E_CAPACITY when the workspace exceeds the array (about 1.09 M
+ * particles with the correction), XPBD_E_ARG for host tool poses or another
+ * device, and every error of xpbd_step_learned; no device work is done after
+ * an error.  Every call on a device shares that device's array and finds the
+ * last call's contents in it (each call writes what it reads first): calls
+ * that overlap on one device race, so callers serialise them (one stream, or
+ * events between streams). */
+xpbd_status xpbd_step_learned_noalloc(xpbd_batch *batch, const xpbd_mlp *net, int32_t num_steps,
+                                      const float *tool_pos, const xpbd_learned_params *params);
+
 
 #ifdef __cplusplus
 }

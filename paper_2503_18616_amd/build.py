@@ -19,7 +19,7 @@ ARCH = "gfx950"
 
 HIP_SOURCES = ["xpbd_kernels.hip", "xpbd_runtime.hip", "mlp_kernels.hip", "warmstart_kernels.hip",
                "learned_runtime.hip", "tune_runtime.hip", "rl_kernels.hip", "rl_runtime.hip",
-               "graph_runtime.hip", "lds_probe.hip", "norm_kernels.hip"]
+               "graph_runtime.hip", "lds_probe.hip", "norm_kernels.hip", "noalloc_runtime.hip"]
 CXX_SOURCES = ["mesh_setup.cpp"]
 
 # Packed FP32 instructions are kept out of every kernel.  The promotion budget

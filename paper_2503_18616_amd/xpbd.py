@@ -73,7 +73,8 @@ EXPORTED = ["xpbd_create_batch", "xpbd_step", "xpbd_read_state", "xpbd_write_sta
             "xpbd_policy_destroy", "xpbd_rl_step", "xpbd_rl_step_learned",
             "xpbd_step_graph_create", "xpbd_rl_graph_create", "xpbd_graph_launch",
             "xpbd_graph_destroy", "xpbd_get_batch_info", "xpbd_lds_probe",
-            "xpbd_prepare_mesh_coloured", "xpbd_mlp_normalisation"]
+            "xpbd_prepare_mesh_coloured", "xpbd_mlp_normalisation",
+            "xpbd_step_learned_noalloc"]
 
 # learned warm start (include/xpbd_learned.h)
 MLP_FEATURES = 27
@@ -171,6 +172,11 @@ _lib.xpbd_axis_neighbours.restype = ctypes.c_int
 _lib.xpbd_axis_neighbours.argtypes = [ctypes.POINTER(XpbdMesh), _V]
 _lib.xpbd_step_learned.restype = ctypes.c_int
 _lib.xpbd_step_learned.argtypes = [_V, _V, ctypes.c_int32, _V, ctypes.POINTER(XpbdLearnedParams)]
+_lib.xpbd_step_learned_noalloc.restype = ctypes.c_int
+_lib.xpbd_step_learned_noalloc.argtypes = [_V, _V, ctypes.c_int32, _V,
+                                           ctypes.POINTER(XpbdLearnedParams)]
+# bytes of the allocation-free learned step's device array
+NOALLOC_SCRATCH_BYTES = 80 << 20
 
 # handle -> (num_envs, num_tools), to check tool-pose buffers before a launch
 _BATCHES = {}
@@ -567,6 +573,24 @@ def xpbd_step_learned(batch, net, num_steps, tool_pos, min_iterations, max_itera
     _check(_lib.xpbd_step_learned(batch, net, int(num_steps), _ptr(tool_pos), ctypes.byref(lp)))
 
 
+def xpbd_step_learned_noalloc(batch, net, num_steps, tool_pos, min_iterations, max_iterations,
+                              threshold, apply_correction=True, record_substep=-1,
+                              record_features=None, record_targets=None, iterations=None,
+                              stall_ratio=0.0, residuals=None):
+    """xpbd_step_learned without device allocation (workspace in the library's
+    fixed device array); tool_pos must be a device tensor.  See
+    include/xpbd_learned.h."""
+    tool_pos = _check_tool_pos(batch, num_steps, tool_pos)
+    _check_per_substep(batch, num_steps, iterations, "torch.int32", "iterations")
+    _check_per_substep(batch, num_steps, residuals, "torch.float32", "residuals")
+    lp = XpbdLearnedParams(int(bool(apply_correction)), int(min_iterations), int(max_iterations),
+                           float(threshold), int(record_substep), _ptr(record_features),
+                           _ptr(record_targets), _ptr(iterations), float(stall_ratio),
+                           _ptr(residuals))
+    _check(_lib.xpbd_step_learned_noalloc(batch, net, int(num_steps), _ptr(tool_pos),
+                                          ctypes.byref(lp)))
+
+
 class XpbdRlParams(ctypes.Structure):
     _fields_ = [("grasp_radius", ctypes.c_float), ("grasp_offset", ctypes.c_float * 3),
                 ("max_speed", ctypes.c_float), ("obs_scale", ctypes.c_float),
@@ -831,6 +855,12 @@ class Batch:
                      **kw):
         xpbd_step_learned(self.handle, net.handle if net is not None else None, num_steps,
                           tool_pos, min_iterations, max_iterations, threshold, **kw)
+
+    def step_learned_noalloc(self, net, num_steps, tool_pos, min_iterations, max_iterations,
+                             threshold, **kw):
+        xpbd_step_learned_noalloc(self.handle, net.handle if net is not None else None,
+                                  num_steps, tool_pos, min_iterations, max_iterations,
+                                  threshold, **kw)
 
     def rl_step(self, policy, params: XpbdRlParams, num_steps, tool_pos, grasped, target,
                 obs=None, actions=None):
