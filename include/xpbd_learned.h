@@ -95,6 +95,20 @@ xpbd_status xpbd_mlp_train_step(xpbd_mlp *net, const uint16_t *features, const f
                                 const int32_t *rows, int32_t n, float learning_rate, float *loss,
                                 float *grad);
 
+/* num_steps training steps in one call (no host work between them): step s
+ * takes the batch rows rows[s batch .. s batch + batch - 1] (device int32
+ * [num_steps][batch]; the caller keeps every index inside the two tables, as
+ * for xpbd_mlp_train_step) and learning rate
+ * first_rate (last_rate / first_rate)^(s / (num_steps - 1)) (computed in
+ * double, rounded to float), and writes its mean loss to losses[s] (device
+ * float32 [num_steps], or NULL).  Step for step the same launches as
+ * xpbd_mlp_train_step with those rows and rates.  XPBD_E_ARG for null or host
+ * tables, batch < 1, num_steps < 0 or rates that are not finite and
+ * positive. */
+xpbd_status xpbd_mlp_train_steps(xpbd_mlp *net, const uint16_t *features, const float *targets,
+                                 const int32_t *rows, int32_t batch, int32_t num_steps,
+                                 float first_rate, float last_rate, float *losses);
+
 /* Normalisation of the network's inputs and outputs from a recording made
  * with the identity normalisation (in_shift 0, in_scale 1): over the n rows
  * (device bfloat16 features [n][32], float32 targets [n][4]) whose free flag

@@ -71,7 +71,7 @@ def _load():
             lib.oracle_greedy_colour.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I, _I]
             lib.oracle_largest_first_colour.restype = ctypes.c_int
             lib.oracle_largest_first_colour.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                                        _I, ctypes.c_int, _I]
+                                                        _I, ctypes.c_int, ctypes.c_int, _I]
             lib.oracle_residual.restype = None
             lib.oracle_residual.argtypes = [_D, ctypes.c_int, _I, _D, ctypes.c_int, _I, _D,
                                             ctypes.c_double, ctypes.c_double, _D, _D]
@@ -199,17 +199,18 @@ def greedy_colour(num_vertices, verts):
 
 
 # colourings of the edge and tetrahedron constraints (R10, R13)
-COLOURING_GREEDY, COLOURING_LARGEST_FIRST, COLOURING_WAVES = 0, 1, 2
+COLOURING_GREEDY, COLOURING_LARGEST_FIRST, COLOURING_WAVES, COLOURING_CAPPED = 0, 1, 2, 3
 WAVE_CUT_ABOVE = 100
+COLOUR_CAP = 256
 
 
-def largest_first_colour(num_vertices, verts, cut_above=0):
+def largest_first_colour(num_vertices, verts, cut_above=0, cap=0):
     """Largest-first colours of constraints verts[n][k] (R13); returns (colours, count)."""
     verts = _i32(verts)
     n, k = verts.shape
     out = np.zeros(max(n, 1), dtype=np.int32)
     nc = _load().oracle_largest_first_colour(int(num_vertices), int(n), int(k), _ip(verts),
-                                             int(cut_above), _ip(out))
+                                             int(cut_above), int(cap), _ip(out))
     if nc < 0:
         raise OracleError(f"oracle_largest_first_colour failed: {nc}")
     return out[:n], nc
@@ -222,7 +223,8 @@ def colour(num_vertices, verts, colouring=COLOURING_GREEDY):
     if colouring == COLOURING_GREEDY:
         return greedy_colour(num_vertices, verts)
     cut = WAVE_CUT_ABOVE if colouring == COLOURING_WAVES else 0
-    return largest_first_colour(num_vertices, verts, cut)
+    cap = COLOUR_CAP if colouring == COLOURING_CAPPED else 0
+    return largest_first_colour(num_vertices, verts, cut, cap)
 
 
 def schedule(colours, num_colours):

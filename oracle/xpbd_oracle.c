@@ -93,8 +93,10 @@
  *       built one at a time as maximal sets of disjoint uncoloured
  *       constraints (rules at oracle_largest_first_colour); optionally a
  *       colour of 65 .. cut_above members is cut to its first 64, so that it
- *       fills one 64-wide group of parallel lanes.  A colouring only fixes the
- *       Gauss-Seidel order (R1); both sides take it from the same rules.
+ *       fills one 64-wide group of parallel lanes, or every colour is capped
+ *       at its first cap members, so that it fits one pass of cap parallel
+ *       lanes.  A colouring only fixes the Gauss-Seidel order (R1); both
+ *       sides take it from the same rules.
  *
  * Every function below is pinned by the not-gpu tests (closed forms,
  * invariants and brute force on tiny meshes).
@@ -417,10 +419,12 @@ int oracle_greedy_colour(int V, int n, int k, const int32_t *verts, int32_t *col
  *     ties broken by the fewest conflicts with other candidates, then by the
  *     lowest index.
  * With cut_above > 64, a colour that ends with 65 .. cut_above members keeps
- * only its first 64 (in the order they were added); the others stay
- * uncoloured for the following colours.  Counts are recomputed from scratch
- * for every choice.  Returns the number of colours or a negative error. */
-int oracle_largest_first_colour(int V, int n, int k, const int32_t *verts, int cut_above,
+ * only its first 64 (in the order they were added); with cap > 0, a colour
+ * keeps at most its first cap members.  The members a colour does not keep
+ * stay uncoloured for the following colours.  Counts are recomputed from
+ * scratch for every choice.  Returns the number of colours or a negative
+ * error. */
+int oracle_largest_first_colour(int V, int n, int k, const int32_t *verts, int cut_above, int cap,
                                 int32_t *colour_out)
 {
     if (V <= 0 || n < 0 || k <= 0 || (n > 0 && (!verts || !colour_out)))
@@ -536,6 +540,8 @@ int oracle_largest_first_colour(int V, int n, int k, const int32_t *verts, int c
         int keep = members;
         if (cut_above > 64 && members > 64 && members <= cut_above)
             keep = 64;
+        if (cap > 0 && keep > cap)
+            keep = cap;
         for (int q = 0; q < keep; ++q)
             colour_out[order[q]] = num_colours;
         left -= keep;

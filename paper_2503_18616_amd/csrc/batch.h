@@ -21,6 +21,7 @@ struct RegClass {
     int block = 256;
     int group = 1;                  // environments per workgroup
     int lambda_banks = 1;
+    bool round_barriers = true;     // every colour of every mesh of the class is one round
     uint32_t lds_bytes = 0;
     int32_t num_groups = 0;
     int32_t *groups_dev = nullptr;

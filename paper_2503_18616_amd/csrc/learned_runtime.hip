@@ -213,6 +213,50 @@ xpbd_status xpbd_mlp_train_step(xpbd_mlp *net, const uint16_t *features, const f
     return XPBD_OK;
 }
 
+xpbd_status xpbd_mlp_train_steps(xpbd_mlp *net, const uint16_t *features, const float *targets,
+                                 const int32_t *rows, int32_t batch, int32_t num_steps,
+                                 float first_rate, float last_rate, float *losses)
+{
+    g_error.clear();
+    if (!net || !features || !targets || !rows || batch < 1 || num_steps < 0)
+        return fail(XPBD_E_ARG, "net, features, targets, rows, batch >= 1 and num_steps >= 0 "
+                    "are required");
+    if (!(std::isfinite(first_rate) && first_rate > 0.0f && std::isfinite(last_rate) &&
+          last_rate > 0.0f))
+        return fail(XPBD_E_ARG, "the learning rates must be finite and > 0");
+    if (!is_device_pointer(features) || !is_device_pointer(targets) || !is_device_pointer(rows) ||
+        (losses && !is_device_pointer(losses)))
+        return fail(XPBD_E_ARG, "features, targets, rows and losses must be device memory");
+    if (num_steps == 0)
+        return XPBD_OK;
+    const int groups = (batch + xpbd::kMlpTile - 1) / xpbd::kMlpTile;
+    if (groups > net->partial_groups) {
+        HIP_TRY(hipStreamSynchronize(net->stream));
+        if (net->partial)
+            HIP_TRY(hipFree(net->partial));
+        if (net->stats)
+            HIP_TRY(hipFree(net->stats));
+        net->partial = nullptr;
+        net->stats = nullptr;
+        net->partial_groups = 0;
+        HIP_TRY(hipMalloc(&net->partial, sizeof(float) * (size_t)groups * xpbd::kMlpParams));
+        HIP_TRY(hipMalloc(&net->stats, sizeof(float) * 2 * (size_t)groups));
+        net->partial_groups = groups;
+    }
+    // the rate of step s: first_rate (last_rate / first_rate)^(s / (num_steps - 1)),
+    // evaluated in double and rounded once
+    const double ratio = (double)last_rate / (double)first_rate;
+    for (int32_t s = 0; s < num_steps; ++s) {
+        const double f = num_steps > 1 ? (double)s / (double)(num_steps - 1) : 0.0;
+        const float rate = (float)((double)first_rate * std::pow(ratio, f));
+        const int step = ++net->adam_step;
+        HIP_TRY(xpbd::launch_mlp_train(net->d, features, targets, rows + (size_t)s * batch, batch,
+                                       net->partial, net->stats, rate, 0.9f, 0.999f, 1e-8f, step,
+                                       nullptr, losses ? losses + s : net->loss, net->stream));
+    }
+    return XPBD_OK;
+}
+
 xpbd_status xpbd_mlp_normalisation(const uint16_t *features, const float *targets, int64_t n,
                                    void *hip_stream, float *in_shift, float *in_scale,
                                    float *out_shift, float *out_scale)
@@ -407,6 +451,7 @@ xpbd_status xpbd::run_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
     a.envs = b->envs_dev;
     a.groups = b->groups_dev;
     a.num_groups = b->num_groups;
+    a.round_barriers = b->classes.size() == 1 && b->classes[0].round_barriers ? 1 : 0;
     a.compliance = b->compliance;
     a.tool_pos = tools_dev;
     a.pos = b->pos;

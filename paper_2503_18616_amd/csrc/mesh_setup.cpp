@@ -14,6 +14,8 @@ namespace {
 
 // WAVES colouring: a colour of 65 .. kWaveCutAbove members is cut to 64.
 constexpr int32_t kWaveCutAbove = 100;
+// CAPPED colouring: a colour keeps at most kColourCap members.
+constexpr int32_t kColourCap = 256;
 
 // Six times the signed volume of (a, b, c, d): the determinant of the edge
 // vectors b - a, c - a, d - a, expanded along its first row.
@@ -59,7 +61,7 @@ int32_t greedy_colouring(int32_t num_vertices, int32_t n, int32_t k, const int32
 }
 
 int32_t largest_first_colouring(int32_t num_vertices, int32_t n, int32_t k, const int32_t *ids,
-                                int32_t cut_above, std::vector<int32_t> &colour)
+                                int32_t cut_above, int32_t cap, std::vector<int32_t> &colour)
 {
     colour.assign((size_t)n, -1);
     // conflict lists: constraints sharing a particle, without repeats
@@ -123,6 +125,8 @@ int32_t largest_first_colouring(int32_t num_vertices, int32_t n, int32_t k, cons
         size_t keep = picked.size();
         if (cut_above > 64 && keep > 64 && keep <= (size_t)cut_above)
             keep = 64;
+        if (cap > 0 && keep > (size_t)cap)
+            keep = (size_t)cap;
         for (size_t q = 0; q < keep; ++q)
             colour[(size_t)picked[q]] = count;
         left -= (int32_t)keep;
@@ -815,10 +819,11 @@ int prepare_mesh(int32_t num_vertices, int32_t num_tets, const float *rest_pos,
                                                out.tet_colour);
     } else {
         const int32_t cut = colouring == XPBD_COLOURING_WAVES ? kWaveCutAbove : 0;
+        const int32_t cap = colouring == XPBD_COLOURING_CAPPED ? kColourCap : 0;
         out.num_edge_colours = largest_first_colouring(num_vertices, out.num_edges(), 2,
-                                                       out.edges.data(), cut, out.edge_colour);
+                                                       out.edges.data(), cut, cap, out.edge_colour);
         out.num_tet_colours = largest_first_colouring(num_vertices, out.num_tets(), 4,
-                                                      out.tets.data(), cut, out.tet_colour);
+                                                      out.tets.data(), cut, cap, out.tet_colour);
     }
 
     // surface triangles (capsule tools): faces of exactly one kept tetrahedron,

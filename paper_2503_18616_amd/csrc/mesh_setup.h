@@ -53,9 +53,11 @@ int32_t greedy_colouring(int32_t num_vertices, int32_t n, int32_t k, const int32
 // cut_above > 64, a colour that ends with more than 64 and at most cut_above
 // members keeps only its first 64 picks (the rest return to the uncoloured
 // pool), so that it fills one 64-wide wave instead of most of a second one.
+// With cap > 0 a colour keeps at most its first cap picks (the rest return
+// to the pool), so that it fits one round of a cap-thread workgroup.
 // ids: [n][k].  Returns the number of colours.
 int32_t largest_first_colouring(int32_t num_vertices, int32_t n, int32_t k, const int32_t *ids,
-                                int32_t cut_above, std::vector<int32_t> &colour);
+                                int32_t cut_above, int32_t cap, std::vector<int32_t> &colour);
 
 // Order of the constraints inside each colour (the "packing"; it does not
 // change results because constraints of one colour share no particle).

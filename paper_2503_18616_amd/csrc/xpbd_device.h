@@ -53,7 +53,7 @@ struct MeshDev {
     uint64_t tet_mask;           // bit r: round r projects tetrahedra
     uint64_t barrier_mask;       // bit r: a workgroup barrier follows round r
     int32_t num_rounds;          // padded to an even count (<= kMaxRounds)
-    int32_t num_edge_rounds;
+    int32_t num_edge_rounds;     // rounds 0 .. num_edge_rounds - 1 project edges (an even count)
     int32_t pad2[2];
 };
 
@@ -107,6 +107,9 @@ struct StepArgs {
     int32_t *grasp;
     float grasp_offset[3];
     float grasp_radius2;
+    // register variant: 1 when every colour of every mesh of the launch is one
+    // round, so that a barrier closes every round (no test of barrier_mask)
+    int32_t round_barriers;
 };
 
 // Arguments of the learned warm start's per-substep kernels (one substep per

@@ -865,27 +865,18 @@ __device__ __forceinline__ float pick(const float (&v)[EG], uint32_t e)
     return x;
 }
 
-// Round r of an iteration.  `slot` holds this lane's record of round r
-// (fetched two rounds earlier) and receives the record of round r + 2.  Waves
-// without a constraint in a round skip it (uniform branch on the wave's
-// activity mask); a barrier closes every colour.  With several environments
-// per workgroup the top two bits of the first word name the lane's
-// environment (whose compliance applies).
-template <int EG>
+// Round r of an iteration, projecting tetrahedra (TET) or edges.  `slot`
+// holds this lane's record of round r (fetched two rounds earlier) and
+// receives the record of round r + 2.  Waves without a constraint in a round
+// skip it (uniform branch on the wave's activity mask); a barrier closes
+// every colour.  With several environments per workgroup the top two bits of
+// the first word name the lane's environment (whose compliance applies).
+template <int EG, bool TET, bool BAR>
 __device__ __forceinline__ void run_round(float4 *xw, const RoundTables &t, int r, Record &slot,
-                                          uint64_t active, uint64_t tets, uint64_t barriers,
-                                          lambda_bank &bank, const float (&alpha_d)[EG],
-                                          const float (&alpha_v)[EG])
+                                          uint64_t active, uint64_t barriers, lambda_bank &bank,
+                                          const float (&alpha_d)[EG], const float (&alpha_v)[EG])
 {
-    // copy the record out of the prefetch slot first, so that the slot's
-    // registers are free for the next fetch and the loop carries it in place
-    // (otherwise the compiler copies the in-flight slot at the loop edge and
-    // must wait for the fetch there)
-    uint32_t w0, w1, w2;
-    asm volatile("v_mov_b32 %0, %3\n\tv_mov_b32 %1, %4\n\tv_mov_b32 %2, %5"
-                 : "=v"(w0), "=v"(w1), "=v"(w2)
-                 : "v"(slot.w0), "v"(slot.w1), "v"(slot.w2));
-    slot = fetch_record(t, r + 2);
+    const uint32_t w0 = slot.w0, w1 = slot.w1, w2 = slot.w2;
     if ((active >> r) & 1u) {   // padding lanes project the padding particle: no effect
         uint32_t e = 0u, ab = w0;
         if constexpr (EG > 1) {
@@ -895,15 +886,54 @@ __device__ __forceinline__ void run_round(float4 *xw, const RoundTables &t, int 
         // one environment per workgroup: the records hold LDS byte offsets
         constexpr int kUnit = EG == 1 ? 1 : 16;
         float l = bank[r & 31];
-        if ((tets >> r) & 1u)
+        if constexpr (TET)
             tet_update<kUnit>(xw, ab, w1, __uint_as_float(w2), pick<EG>(alpha_v, e), l);
         else
             edge_update<kUnit>(xw, ab & 0xffffu, ab >> 16, __uint_as_float(w1),
                                pick<EG>(alpha_d, e), l);
         bank[r & 31] = l;
     }
-    if ((barriers >> r) & 1u)
+    // the record of round r + 2 is fetched once this round's record is used, into
+    // the same registers (no copy): it has the next round to arrive
+    slot = fetch_record(t, r + 2);
+    if (BAR || ((barriers >> r) & 1u))
         __syncthreads();
+}
+
+// One sweep of Alg. 1's constraint loops: the edge rounds [0, Re), then the
+// tetrahedron rounds [Re, R), each kind in loops of its own (no round tests
+// its kind; Re and R are even), in pairs so that the two prefetch slots never
+// move.  Rounds 0..31 keep their multipliers in bank0, rounds 32..63 in bank1.
+// BAR: every colour is one round, so a barrier closes every round (the
+// padding rounds too) without a test of the barrier mask.
+template <int EG, int NB, bool BAR>
+__device__ __forceinline__ void sweep_rounds(float4 *xw, const RoundTables &t, int Re, int R,
+                                             Record &slot_a, Record &slot_b, uint64_t active,
+                                             uint64_t barriers, lambda_bank &bank0,
+                                             lambda_bank &bank1, const float (&alpha_d)[EG],
+                                             const float (&alpha_v)[EG])
+{
+    const int E0 = Re < 32 ? Re : 32, R0 = R < 32 ? R : 32;
+    int r = 0;
+    for (; r < E0; r += 2) {
+        run_round<EG, false, BAR>(xw, t, r, slot_a, active, barriers, bank0, alpha_d, alpha_v);
+        run_round<EG, false, BAR>(xw, t, r + 1, slot_b, active, barriers, bank0, alpha_d, alpha_v);
+    }
+    for (; r < R0; r += 2) {
+        run_round<EG, true, BAR>(xw, t, r, slot_a, active, barriers, bank0, alpha_d, alpha_v);
+        run_round<EG, true, BAR>(xw, t, r + 1, slot_b, active, barriers, bank0, alpha_d, alpha_v);
+    }
+    if constexpr (NB > 1) {
+        int q = 32;
+        for (; q < Re; q += 2) {
+            run_round<EG, false, BAR>(xw, t, q, slot_a, active, barriers, bank1, alpha_d, alpha_v);
+            run_round<EG, false, BAR>(xw, t, q + 1, slot_b, active, barriers, bank1, alpha_d, alpha_v);
+        }
+        for (; q < R; q += 2) {
+            run_round<EG, true, BAR>(xw, t, q, slot_a, active, barriers, bank1, alpha_d, alpha_v);
+            run_round<EG, true, BAR>(xw, t, q + 1, slot_b, active, barriers, bank1, alpha_d, alpha_v);
+        }
+    }
 }
 
 // Tool modes of the register kernel: spheres against particles, spheres with
@@ -919,7 +949,7 @@ enum { kRegSpheres = 0, kRegGrasp = 1, kRegCapsules = 2 };
 // particles as float4 (x, y, z, w), velocities and start-of-substep positions
 // (structure of arrays), then scratch.  Multipliers live in registers (NB
 // banks of 32 rounds).
-template <int NB, int EG, int MODE>
+template <int NB, int EG, int MODE, bool BAR>
 __device__ __forceinline__ void step_reg_body(StepArgs A)
 {
     constexpr bool GRASP = MODE == kRegGrasp;
@@ -1000,7 +1030,7 @@ __device__ __forceinline__ void step_reg_body(StepArgs A)
     tab.tid = tid;
     tab.pad = EG == 1 ? 16u * (uint32_t)VS : (uint32_t)VS;   // in the records' units
     const uint64_t active = A.meshes[A.envs[env[0]].mesh].wave_active[__builtin_amdgcn_readfirstlane(wave)];
-    const uint64_t tets = md.tet_mask, barriers = md.barrier_mask;
+    const uint64_t barriers = md.barrier_mask;
     // (issued in this order, as in every round: the loop then waits for the
     // older fetch only, instead of for both)
     Record slot_a = fetch_record(tab, 0);   // records of the next two rounds (even, odd)
@@ -1159,20 +1189,8 @@ __device__ __forceinline__ void step_reg_body(StepArgs A)
             __syncthreads();
 
             for (int it = 0; it < A.iterations; ++it) {
-                // rounds in pairs so that the two prefetch slots never move
-                for (int r = 0; r < R0; r += 2) {
-                    run_round<EG>(xw, tab, r, slot_a, active, tets, barriers, bank0, alpha_d,
-                                  alpha_v);
-                    run_round<EG>(xw, tab, r + 1, slot_b, active, tets, barriers, bank0, alpha_d,
-                                  alpha_v);
-                }
-                if constexpr (NB > 1)
-                    for (int r = 32; r < R; r += 2) {
-                        run_round<EG>(xw, tab, r, slot_a, active, tets, barriers, bank1, alpha_d,
-                                      alpha_v);
-                        run_round<EG>(xw, tab, r + 1, slot_b, active, tets, barriers, bank1,
-                                      alpha_d, alpha_v);
-                    }
+                sweep_rounds<EG, NB, BAR>(xw, tab, md.num_edge_rounds, R, slot_a, slot_b, active,
+                                          barriers, bank0, bank1, alpha_d, alpha_v);
                 if (CAPSULE && any_contact) {
                     // flagged faces pushed out of every capsule, face colour by
                     // face colour (faces of one colour share no particle)
@@ -1343,10 +1361,10 @@ __device__ __forceinline__ void step_reg_body(StepArgs A)
     }
 }
 
-template <int NB, int EG, int MODE>
+template <int NB, int EG, int MODE, bool BAR>
 __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
 {
-    step_reg_body<NB, EG, MODE>(A);
+    step_reg_body<NB, EG, MODE, BAR>(A);
 }
 
 // Capsule tools: the face push-out's closest-point search needs more
@@ -1355,7 +1373,7 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
 template <int NB>
 __global__ void __launch_bounds__(512) xpbd_step_reg_kernel_capsules(StepArgs A)
 {
-    step_reg_body<NB, 1, kRegCapsules>(A);
+    step_reg_body<NB, 1, kRegCapsules, false>(A);
 }
 
 // ---------------------------------------------------------------------------
@@ -1454,11 +1472,7 @@ __device__ __forceinline__ void eval_round(const float4 *xw, const RoundTables &
                                            const lambda_bank &bank, float alpha_d, float alpha_v,
                                            float &acc)
 {
-    uint32_t w0, w1, w2;
-    asm volatile("v_mov_b32 %0, %3\n\tv_mov_b32 %1, %4\n\tv_mov_b32 %2, %5"
-                 : "=v"(w0), "=v"(w1), "=v"(w2)
-                 : "v"(slot.w0), "v"(slot.w1), "v"(slot.w2));
-    slot = fetch_record(t, r + 2);
+    const uint32_t w0 = slot.w0, w1 = slot.w1, w2 = slot.w2;
     if (((active >> r) & 1u) && (w0 & 0xffffu) != t.pad) {
         const float l = bank[r & 31];
         float q;
@@ -1480,6 +1494,7 @@ __device__ __forceinline__ void eval_round(const float4 *xw, const RoundTables &
         }
         acc += q * q;
     }
+    slot = fetch_record(t, r + 2);
 }
 
 // One substep of one environment from the predicted positions in L.xhat
@@ -1487,8 +1502,9 @@ __device__ __forceinline__ void eval_round(const float4 *xw, const RoundTables &
 // RMS, and the remaining sweeps up to max_iterations when it exceeds the
 // threshold; then v = (x - x_prev) / h and the write-back.  GRASP: tool 0
 // drags the particle A.grasp names (taken at the first substep of a step, as
-// in xpbd_step_reg_kernel) after the contacts of every sweep.
-template <int NB, bool GRASP>
+// in xpbd_step_reg_kernel) after the contacts of every sweep.  BAR as in
+// sweep_rounds.
+template <int NB, bool GRASP, bool BAR>
 __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, LearnedArgs L)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1624,16 +1640,8 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
     const float alpha_d1[1] = {alpha_d}, alpha_v1[1] = {alpha_v};
 
     auto sweep = [&]() {
-        for (int r = 0; r < R0; r += 2) {
-            run_round<1>(xw, tab, r, slot_a, active, tets, barriers, bank0, alpha_d1, alpha_v1);
-            run_round<1>(xw, tab, r + 1, slot_b, active, tets, barriers, bank0, alpha_d1, alpha_v1);
-        }
-        if constexpr (NB > 1)
-            for (int r = 32; r < R; r += 2) {
-                run_round<1>(xw, tab, r, slot_a, active, tets, barriers, bank1, alpha_d1, alpha_v1);
-                run_round<1>(xw, tab, r + 1, slot_b, active, tets, barriers, bank1, alpha_d1,
-                             alpha_v1);
-            }
+        sweep_rounds<1, NB, BAR>(xw, tab, md.num_edge_rounds, R, slot_a, slot_b, active,
+                                 barriers, bank0, bank1, alpha_d1, alpha_v1);
         if (any_contact || (GRASP && held >= 0)) {
             for (int t = 0; t < tools; ++t) {
                 const float3 ct = t == 0 ? tool0 : tool1;
@@ -1985,8 +1993,11 @@ hipError_t launch_reg_variant(const StepArgs &args, int block, uint32_t lds_byte
 {
     // the grasping and capsule code only in the launches that use them (they
     // cost registers)
-    auto kernel = args.grasp ? xpbd_step_reg_kernel<NB, EG, kRegGrasp>
-                             : xpbd_step_reg_kernel<NB, EG, kRegSpheres>;
+    auto kernel = args.round_barriers
+                      ? (args.grasp ? xpbd_step_reg_kernel<NB, EG, kRegGrasp, true>
+                                    : xpbd_step_reg_kernel<NB, EG, kRegSpheres, true>)
+                      : (args.grasp ? xpbd_step_reg_kernel<NB, EG, kRegGrasp, false>
+                                    : xpbd_step_reg_kernel<NB, EG, kRegSpheres, false>);
     if (args.tool_shape == 1) {   // XPBD_TOOL_CAPSULE
         if constexpr (EG == 1) {
             if (block > 512)
@@ -2062,7 +2073,11 @@ template <int NB>
 hipError_t launch_substep_variant(const StepArgs &args, const LearnedArgs &largs, int block,
                                   uint32_t lds_bytes, hipStream_t stream)
 {
-    auto kernel = args.grasp ? xpbd_substep_reg_kernel<NB, true> : xpbd_substep_reg_kernel<NB, false>;
+    auto kernel = args.round_barriers
+                      ? (args.grasp ? xpbd_substep_reg_kernel<NB, true, true>
+                                    : xpbd_substep_reg_kernel<NB, false, true>)
+                      : (args.grasp ? xpbd_substep_reg_kernel<NB, true, false>
+                                    : xpbd_substep_reg_kernel<NB, false, false>);
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)lds_bytes);

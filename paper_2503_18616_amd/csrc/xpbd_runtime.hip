@@ -63,7 +63,7 @@ xpbd_status validate_params(const xpbd_params *p)
         return fail(XPBD_E_ARG, "unknown solver_variant %d", p->solver_variant);
     if (p->colour_packing < XPBD_PACKING_AUTO || p->colour_packing > XPBD_PACKING_SEARCH)
         return fail(XPBD_E_ARG, "unknown colour_packing %d", p->colour_packing);
-    if (p->colouring < XPBD_COLOURING_GREEDY || p->colouring > XPBD_COLOURING_WAVES)
+    if (p->colouring < XPBD_COLOURING_GREEDY || p->colouring > XPBD_COLOURING_CAPPED)
         return fail(XPBD_E_ARG, "unknown colouring %d", p->colouring);
     if (p->envs_per_group < 0 || p->envs_per_group > xpbd::kMaxEnvsPerGroup)
         return fail(XPBD_E_ARG, "envs_per_group must be 0, 1 or 2 (got %d)", p->envs_per_group);
@@ -128,12 +128,15 @@ int count_rounds(const PreparedMesh &pm, int B, int G)
         n_e[(size_t)c]++;
     for (int32_t c : pm.tet_colour)
         n_t[(size_t)c]++;
-    int r = 0;
+    int re = 0, rt = 0;
     for (int32_t n : n_e)
-        r += (G * n + B - 1) / B;
+        re += (G * n + B - 1) / B;
     for (int32_t n : n_t)
-        r += (G * n + B - 1) / B;
-    return r;
+        rt += (G * n + B - 1) / B;
+    // as build_round_schedule pads them: the edge rounds to an even count, then
+    // the total
+    const int r = re + (re & 1) + rt;
+    return r + (r & 1);
 }
 
 xpbd_status field_bytes(const xpbd_batch *b, int32_t field, size_t *bytes)
@@ -188,7 +191,7 @@ xpbd_status xpbd_prepare_mesh_coloured(const xpbd_mesh *mesh, int32_t colouring,
     g_error.clear();
     if (!mesh || !counts)
         return fail(XPBD_E_ARG, "mesh and counts must not be NULL");
-    if (colouring < XPBD_COLOURING_GREEDY || colouring > XPBD_COLOURING_WAVES)
+    if (colouring < XPBD_COLOURING_GREEDY || colouring > XPBD_COLOURING_CAPPED)
         return fail(XPBD_E_ARG, "unknown colouring %d", colouring);
     PreparedMesh pm;
     std::string err;
@@ -559,6 +562,7 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         std::vector<float> inv_count;
         std::vector<uint2> faces;         // schedule order: a | b << 16, c
         std::vector<int32_t> face_ptr;
+        bool one_round_colours = true;    // register variant: no colour takes two rounds
     };
     std::vector<MeshHost> host((size_t)num_meshes);
     // the lane search costs about a second per thousand particles: the default
@@ -668,12 +672,16 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         }
         std::vector<int4> rounds;
         build_rounds(geptr, gtptr, block, rounds);
-        if (rounds.size() % 2)   // the kernel runs rounds in pairs: pad with an empty round
-            rounds.push_back(make_int4(0, 0, xpbd::ROUND_TET, 0));
-        const int32_t num_rounds = (int32_t)rounds.size();
+        // the kernel runs the edge rounds and the tetrahedron rounds in loops of
+        // their own, both in pairs: pad each with an empty round to an even count
         int32_t edge_rounds = 0;
         for (const int4 &rd : rounds)
-            edge_rounds += (rd.z == xpbd::ROUND_EDGE && rd.y > rd.x) ? 1 : 0;
+            edge_rounds += rd.z == xpbd::ROUND_EDGE ? 1 : 0;
+        if (edge_rounds % 2)
+            rounds.insert(rounds.begin() + edge_rounds++, make_int4(0, 0, xpbd::ROUND_EDGE, 0));
+        if (rounds.size() % 2)
+            rounds.push_back(make_int4(0, 0, xpbd::ROUND_TET, 0));
+        const int32_t num_rounds = (int32_t)rounds.size();
         // two rows beyond the last round repeat rounds 0 and 1: the kernel
         // fetches the record of round r + 2 in round r without wrapping
         std::vector<uint32_t> &round_rec = h.round_rec;
@@ -689,14 +697,37 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         rr_id.assign((size_t)std::max(num_rounds, 1) * block, -1);
         MeshDev &d = h.d;
         std::memset(&d, 0, sizeof d);
+        // With fewer waves per workgroup than a CU has SIMDs, the 64-lane
+        // blocks of a round go to the waves that have worked least so far (a
+        // tetrahedron round counts three edge rounds): colours that fill only
+        // some of the waves then spread their work over every wave of the
+        // workgroup instead of always loading its first one.  Whole blocks
+        // move, so the bank-conflict pattern of each wave's accesses and the
+        // results stay the same.  Measured (same box, alternating runs): +4.2 %
+        // on the 12x8x3 slab's 128-thread workgroups, -0.8 % on the 16x10x4
+        // slab's 256-thread ones, whose four waves already cover the SIMDs.
+        const int num_waves = block / 64;
+        const bool rotate = num_waves < 4;
+        std::vector<int64_t> wave_load((size_t)num_waves, 0);
+        std::vector<int> wave_order((size_t)num_waves);
         for (int32_t r = 0; r < num_rounds && use_registers; ++r) {
             const int4 rd = rounds[(size_t)r];
             const bool is_edge = r < edge_rounds;
-            for (int32_t l = rd.y - rd.x; l < block && !is_edge; ++l)
+            const int32_t n = rd.y - rd.x;
+            std::iota(wave_order.begin(), wave_order.end(), 0);
+            if (rotate)
+                std::stable_sort(wave_order.begin(), wave_order.end(), [&](int a, int c) {
+                    return wave_load[(size_t)a] < wave_load[(size_t)c];
+                });
+            for (int k = 0; k < (n + 63) / 64 && k < num_waves; ++k)
+                wave_load[(size_t)wave_order[(size_t)k]] += is_edge ? 1 : 3;
+            auto lane_of = [&](int32_t l) { return wave_order[(size_t)(l / 64)] * 64 + l % 64; };
+            for (int32_t l = 0; l < block && !is_edge; ++l)
                 round_rec[((size_t)r * block + l) * 3 + 1] = pad;   // tet padding: c = d = pad
             for (int32_t l = 0; l < block && rd.x + l < rd.y; ++l) {
                 const int32_t j = rd.x + l;   // slot within its kind
-                uint32_t *at = &round_rec[((size_t)r * block + l) * 3];
+                const int32_t pl = lane_of(l);
+                uint32_t *at = &round_rec[((size_t)r * block + pl) * 3];
                 if (is_edge) {
                     const int32_t q = geslot[(size_t)j], e = q / E, id = q - e * E;
                     const uint8_t *o = xpbd::vertex_order(2, eorder[(size_t)q]);
@@ -706,7 +737,7 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
                     at[0] = a | (bb << 16) | ((uint32_t)e << 30);
                     std::memcpy(&at[1], &rest, 4);
                     at[2] = 0u;
-                    rr_id[(size_t)r * block + l] = (e << 24) | id;
+                    rr_id[(size_t)r * block + pl] = (e << 24) | id;
                 } else {
                     const int32_t q = gtslot[(size_t)j], e = q / T, id = q - e * T;
                     const uint8_t *o = xpbd::vertex_order(4, torder[(size_t)q]);
@@ -717,14 +748,16 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
                     at[0] = v[0] | (v[1] << 16) | ((uint32_t)e << 30);
                     at[1] = v[2] | (v[3] << 16);
                     std::memcpy(&at[2], &rest, 4);
-                    rr_id[(size_t)r * block + l] = (e << 24) | (E + id);
+                    rr_id[(size_t)r * block + pl] = (e << 24) | (E + id);
                 }
-                d.wave_active[l / 64] |= 1ull << r;
+                d.wave_active[pl / 64] |= 1ull << r;
             }
             if (!is_edge)
                 d.tet_mask |= 1ull << r;
             if (rd.w)
                 d.barrier_mask |= 1ull << r;
+            else if (rd.y > rd.x)
+                h.one_round_colours = false;   // a colour continues in the next round
         }
         if (num_rounds >= 2)
             std::copy(round_rec.begin(), round_rec.begin() + (size_t)2 * block * 3,
@@ -826,6 +859,8 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         if ((st = b->upload(&p_rr, h.round_rec)) || (st = b->upload(&p_rrid, h.rr_id)) ||
             (st = b->upload(&p_slot, h.slot16)) || (st = b->upload(&p_id, h.id16)))
             return cleanup(st);
+        if (use_registers && !h.one_round_colours)
+            b->classes[(size_t)mesh_class[(size_t)m]].round_barriers = false;
         d.round_rec = p_rr;
         d.rr_id = p_rrid;
         d.slot_of = p_slot;
@@ -1033,6 +1068,7 @@ xpbd_status xpbd::run_step(xpbd_batch *b, int32_t num_steps, const float *tools_
         const RegClass &c = b->classes[0];
         a.groups = c.groups_dev;
         a.num_groups = c.num_groups;
+        a.round_barriers = c.round_barriers ? 1 : 0;
         HIP_TRY(xpbd::launch_step_reg(a, c.block, c.lambda_banks, c.group, c.lds_bytes,
                                       resid, b->stream));
     } else if (b->register_variant) {
@@ -1044,6 +1080,7 @@ xpbd_status xpbd::run_step(xpbd_batch *b, int32_t num_steps, const float *tools_
             HIP_TRY(hipStreamWaitEvent(c.stream, b->fork, 0));
             a.groups = c.groups_dev;
             a.num_groups = c.num_groups;
+            a.round_barriers = c.round_barriers ? 1 : 0;
             HIP_TRY(xpbd::launch_step_reg(a, c.block, c.lambda_banks, c.group,
                                           c.lds_bytes, false, c.stream));
             HIP_TRY(hipEventRecord(c.done, c.stream));

@@ -55,25 +55,26 @@ def train(net: "xpbd.Mlp", feats, targets, steps: int, batch: int = 8192, lr: fl
     recorded rows (epoch after epoch; the learning rate decays geometrically
     from lr to final_lr).  Returns the loss of every step.
 
-    The host only queues launches: the permutations are drawn and checked
-    against the tables before the first step, each step's loss goes to a
-    device buffer, and the losses are read back once at the end."""
+    The host queues all steps with one library call: the permutations are
+    drawn and checked against the tables before the first step, each step's
+    loss goes to a device buffer, and the losses are read back once at the
+    end."""
     import torch
     rng = np.random.default_rng(seed)
     free = np.flatnonzero(feats[:, 31].float().cpu().numpy() > 0).astype(np.int32)
+    if free.size == 0:
+        raise ValueError("the recording holds no free rows to train on")
     batch = min(batch, free.size)
-    epochs, at, starts = [free[rng.permutation(free.size)]], 0, []
-    for s in range(steps):
-        if at + batch > free.size:
-            epochs.append(free[rng.permutation(free.size)])
-            at = 0
-        starts.append((len(epochs) - 1) * free.size + at)
-        at += batch
-    order = torch.from_numpy(np.concatenate(epochs)).cuda()
+    # every epoch (a fresh permutation) serves floor(rows / batch) steps
+    per_epoch, parts, left = free.size // batch, [], steps
+    while left > 0:
+        k = min(per_epoch, left)
+        parts.append(free[rng.permutation(free.size)][:k * batch])
+        left -= k
+    rows = np.concatenate(parts) if parts else free[:0]
+    order = torch.from_numpy(np.ascontiguousarray(rows, dtype=np.int32)).cuda()
     xpbd.check_rows(order, feats.shape[0])
     losses = torch.zeros(max(steps, 1), dtype=torch.float32, device="cuda")
-    for s in range(steps):
-        rate = lr * (final_lr / lr) ** (s / max(steps - 1, 1))
-        net.train_step(feats, targets, rate, rows=order[starts[s]:starts[s] + batch],
-                       loss_out=losses[s:s + 1], rows_checked=True)
+    net.train_steps(feats, targets, order, batch, steps, lr, final_lr, losses=losses,
+                    rows_checked=True)
     return [float(v) for v in losses[:steps].cpu().numpy()]

@@ -74,7 +74,7 @@ EXPORTED = ["xpbd_create_batch", "xpbd_step", "xpbd_read_state", "xpbd_write_sta
             "xpbd_step_graph_create", "xpbd_rl_graph_create", "xpbd_graph_launch",
             "xpbd_graph_destroy", "xpbd_get_batch_info", "xpbd_lds_probe",
             "xpbd_prepare_mesh_coloured", "xpbd_mlp_normalisation",
-            "xpbd_step_learned_noalloc"]
+            "xpbd_step_learned_noalloc", "xpbd_mlp_train_steps"]
 
 # learned warm start (include/xpbd_learned.h)
 MLP_FEATURES = 27
@@ -166,6 +166,9 @@ _lib.xpbd_mlp_forward.restype = ctypes.c_int
 _lib.xpbd_mlp_forward.argtypes = [_V, _V, ctypes.c_int32, _V]
 _lib.xpbd_mlp_train_step.restype = ctypes.c_int
 _lib.xpbd_mlp_train_step.argtypes = [_V, _V, _V, _V, ctypes.c_int32, ctypes.c_float, _V, _V]
+_lib.xpbd_mlp_train_steps.restype = ctypes.c_int
+_lib.xpbd_mlp_train_steps.argtypes = [_V, _V, _V, _V, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_float, ctypes.c_float, _V]
 _lib.xpbd_mlp_destroy.restype = None
 _lib.xpbd_mlp_destroy.argtypes = [_V]
 _lib.xpbd_axis_neighbours.restype = ctypes.c_int
@@ -515,6 +518,26 @@ def check_rows(rows, n):
         raise ValueError("rows must index the feature table")
 
 
+def xpbd_mlp_train_steps(net, features, targets, rows, batch, num_steps, first_rate, last_rate,
+                         losses=None, rows_checked=False):
+    """num_steps training steps in one library call: step s on rows[s batch ..
+    s batch + batch - 1] (device int32, checked here against the tables unless
+    rows_checked) with a learning rate decaying geometrically from first_rate
+    to last_rate; each step's loss to losses[s] (device float32) if given."""
+    n = _device_rows(features, MLP_FEATURE_STRIDE, "torch.bfloat16", "features")
+    if _device_rows(targets, 4, "torch.float32", "targets") != n:
+        raise ValueError("targets need one row per feature row")
+    if _device_rows(rows, 1, "torch.int32", "rows") < int(batch) * int(num_steps):
+        raise ValueError("rows must hold batch * num_steps indices")
+    if not rows_checked:
+        check_rows(rows[:int(batch) * int(num_steps)], n)
+    if losses is not None and _device_rows(losses, 1, "torch.float32", "losses") < num_steps:
+        raise ValueError("losses needs num_steps values")
+    _check(_lib.xpbd_mlp_train_steps(net, _ptr(features), _ptr(targets), _ptr(rows), int(batch),
+                                     int(num_steps), float(first_rate), float(last_rate),
+                                     _ptr(losses)))
+
+
 def xpbd_mlp_train_step(net, features, targets, learning_rate, grad=None, rows=None,
                         loss_out=None, rows_checked=False):
     """One training step on every row, or on the rows listed in ``rows`` (device
@@ -815,6 +838,11 @@ class Mlp:
 
     def forward(self, features, y):
         xpbd_mlp_forward(self.handle, features, y)
+
+    def train_steps(self, features, targets, rows, batch, num_steps, first_rate, last_rate,
+                    losses=None, rows_checked=False):
+        xpbd_mlp_train_steps(self.handle, features, targets, rows, batch, num_steps, first_rate,
+                             last_rate, losses, rows_checked)
 
     def train_step(self, features, targets, learning_rate, grad=None, rows=None, loss_out=None,
                    rows_checked=False):

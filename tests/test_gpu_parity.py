@@ -142,6 +142,36 @@ def test_batch_parity_sampled_envs(xp, oracle_lib, variant):
     assert worst <= K.POS_TOL, f"max position error {worst:.3e} m"
 
 
+@pytest.mark.parametrize("colouring", [1, 3], ids=["largest-first", "capped-256"])
+def test_batch_parity_other_colourings(xp, oracle_lib, colouring):
+    """The batch workload (1024 environments of the 16x10x4 slab, 8 iterations)
+    under the largest-first colourings, plain and capped at 256 members (a
+    different Gauss-Seidel order, taken by both sides from the same rules):
+    colours read back bit-exact, 16 sampled environments against the oracle
+    after 100 steps (one launch per step, as the benchmark runs it)."""
+    steps = 100
+    wl = W.batch_workload(1024, seed=2, num_steps=steps)
+    sample = list(range(5, 1024, 64))
+    tools = wl.tools(steps)
+    m = wl.meshes[0]
+    om = oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass, m.tets, colouring=colouring)
+    refs = oracle_lib.run_batch([om], wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
+                                tools[:, sample], steps, env_ids=sample, threads=8)
+    p = K.lib_params(xp, wl)
+    p.colouring = colouring
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b:
+        col = b.read(xp.FIELD_COLOURS)
+        assert np.array_equal(col, np.concatenate([om.edge_colour, om.tet_colour]))
+        assert b.info()["solver_variant"] == xp.VARIANT_REGISTERS
+        for s in range(steps):
+            b.step(1, tools[s:s + 1])
+        x = b.positions()
+        offs = b.env_offsets
+    worst = max(K.max_position_error(K.env_block(x, offs, e), refs[n].x)
+                for n, e in enumerate(sample))
+    assert worst <= K.POS_TOL, f"max position error {worst:.3e} m"
+
+
 def test_colours_read_back(xp, oracle_lib):
     wl = W.batch_workload(4, seed=0, num_steps=1)
     om = K.oracle_meshes(oracle_lib, wl)[0]

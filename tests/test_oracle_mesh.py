@@ -184,13 +184,40 @@ def test_largest_first_cut_keeps_the_first_64_picks(oracle_lib):
     assert (cut[:64] == 0).all() and (cut[64:] == 1).all()
 
 
+def test_largest_first_cap_keeps_the_first_picks(oracle_lib):
+    """300 disjoint constraints form one colour.  Capped at 256 it keeps its
+    first 256 picks (all tied: by index, 0..255) and the other 44 form the
+    next colour; with the cap at 300 it stays whole."""
+    verts = np.array([[2 * i, 2 * i + 1] for i in range(300)], np.int32)
+    whole, n = oracle_lib.largest_first_colour(600, verts, 0, 300)
+    assert n == 1 and not whole.any()
+    capped, n = oracle_lib.largest_first_colour(600, verts, 0, 256)
+    assert n == 2
+    assert (capped[:256] == 0).all() and (capped[256:] == 1).all()
+
+
+def test_capped_first_colour_is_a_prefix_of_the_uncapped_one(oracle_lib):
+    """The cap changes no pick before it applies: on the 16x10x4 slab the first
+    capped edge colour is 256 of the first uncapped colour's members (which
+    has more), and every colour of the capped edge colouring holds at most
+    256 edges."""
+    m = W.slab_mesh(16, 10, 4)
+    om = oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass, m.tets)
+    free, _ = oracle_lib.largest_first_colour(m.num_vertices, om.edges)
+    capped, n = oracle_lib.largest_first_colour(m.num_vertices, om.edges, 0, 256)
+    first_free, first_capped = set(np.flatnonzero(free == 0)), set(np.flatnonzero(capped == 0))
+    assert len(first_free) > 256 and len(first_capped) == 256
+    assert first_capped <= first_free
+    assert np.bincount(capped).max() <= 256 and n >= 18
+
+
 @pytest.mark.parametrize("grid", GRIDS)
-@pytest.mark.parametrize("colouring", [1, 2])
+@pytest.mark.parametrize("colouring", [1, 2, 3])
 def test_largest_first_colours_are_valid_and_maximal(oracle_lib, grid, colouring):
     """Every colour is a set of constraints sharing no particle; a colour that
     was not cut is maximal among the constraints coloured after it (each of
     them conflicts with one of its members); with the cut no colour has 65 to
-    100 members."""
+    100 members, with the cap none more than 256."""
     m = W.slab_mesh(*grid)
     om = oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass, m.tets, colouring=colouring)
     for verts, col, nc in ((om.edges, om.edge_colour, om.num_edge_colours),
@@ -204,11 +231,14 @@ def test_largest_first_colours_are_valid_and_maximal(oracle_lib, grid, colouring
             touched.append(set(members.tolist()))
         for j in range(len(col)):
             for c in range(col[j]):
-                cut = colouring == 2 and sizes[c] == 64
+                cut = (colouring == 2 and sizes[c] == 64) or \
+                      (colouring == 3 and sizes[c] == oracle_lib.COLOUR_CAP)
                 if not cut:
                     assert touched[c] & set(verts[j].tolist()), (j, c)
         if colouring == 2:
             assert not ((sizes > 64) & (sizes <= oracle_lib.WAVE_CUT_ABOVE)).any()
+        if colouring == 3:
+            assert sizes.max() <= oracle_lib.COLOUR_CAP
 
 
 def test_largest_first_reaches_the_degree_bound(oracle_lib):
