@@ -78,12 +78,14 @@ def parse_args():
     ap.add_argument("--packing", type=int, default=0,
                     help="0 = library's choice, 1 = id order, 2 = 8-lane bank groups, 3 = 16-lane, "
                          "4 = scattered + 16-lane, 5 = searched")
-    ap.add_argument("--colouring", type=int, default=3,
+    ap.add_argument("--colouring", type=int, default=None,
                     help="constraint colouring (a Gauss-Seidel order; the oracle takes the same): "
                          "0 = greedy (the library's default), 1 = largest first, 2 = largest "
                          "first with colours of 65..100 cut to one wave of 64, 3 = largest first "
-                         "with colours capped at 256 members (default: every colour is one "
-                         "round of a 256-thread workgroup)")
+                         "with colours capped at 256 members (default: 3, so that every colour "
+                         "is one round of a 256-thread workgroup; 1 for the uneven workload, "
+                         "whose largest meshes the cap would push past the register variant's "
+                         "64 rounds)")
     ap.add_argument("--group", type=int, default=0,
                     help="environments per workgroup (0 = library's choice, 1 or 2)")
     ap.add_argument("--cpu-envs", type=int, default=64, help="oracle sample: environments")
@@ -117,7 +119,10 @@ def parse_args():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB mebibytes (reference for the "
                          "HBM byte counters) and exit")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.colouring is None:
+        args.colouring = 1 if args.workload == "uneven" else 3
+    return args
 
 
 def lds_peaks():
@@ -201,7 +206,7 @@ def source_sha(name):
 def measured_traffic(workload, steps_per_launch, args, record="xpbd_step_traffic.json"):
     """HBM bytes per step launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
     recorded in profiles/, if they were taken on this kernel source, this launch
-    selection (the runtime source) and the default launch shape."""
+    selection (the runtime source), this colouring and the default launch shape."""
     path = os.path.join(ROOT, "profiles", record)
     if (not os.path.exists(path) or steps_per_launch != 1 or args.variant or args.packing
             or args.block or args.group):
@@ -210,7 +215,7 @@ def measured_traffic(workload, steps_per_launch, args, record="xpbd_step_traffic
         rec = json.load(f)
     if (rec.get("kernel_source_sha256") != source_sha("xpbd_kernels.hip")
             or rec.get("runtime_source_sha256") != source_sha("xpbd_runtime.hip")
-            or rec.get("workload") != workload):
+            or rec.get("workload") != workload or rec.get("colouring", 0) != args.colouring):
         return None
     return rec["traffic_bytes_per_launch"]
 

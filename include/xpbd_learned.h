@@ -95,19 +95,23 @@ xpbd_status xpbd_mlp_train_step(xpbd_mlp *net, const uint16_t *features, const f
                                 const int32_t *rows, int32_t n, float learning_rate, float *loss,
                                 float *grad);
 
-/* num_steps training steps in one call (no host work between them): step s
- * takes the batch rows rows[s batch .. s batch + batch - 1] (device int32
- * [num_steps][batch]; the caller keeps every index inside the two tables, as
- * for xpbd_mlp_train_step) and learning rate
+/* num_steps training steps in one call (no host work between them).  Step s
+ * trains on the batch rows rows[(start_s + j) mod num_rows], j < batch: a
+ * window of the device int32 row list rows [num_rows] (num_rows >= batch;
+ * the caller keeps every index inside the two tables, as for
+ * xpbd_mlp_train_step) that may wrap around its end, with start_s = starts[s]
+ * (host int64 [num_steps], each in [0, num_rows)) or, with starts NULL,
+ * (s batch) mod num_rows; its learning rate is
  * first_rate (last_rate / first_rate)^(s / (num_steps - 1)) (computed in
- * double, rounded to float), and writes its mean loss to losses[s] (device
- * float32 [num_steps], or NULL).  Step for step the same launches as
- * xpbd_mlp_train_step with those rows and rates.  XPBD_E_ARG for null or host
- * tables, batch < 1, num_steps < 0 or rates that are not finite and
- * positive. */
+ * double, rounded to float); its mean loss goes to losses[s] (device float32
+ * [num_steps], or NULL).  Step for step the same computation as
+ * xpbd_mlp_train_step on those rows with that rate.  XPBD_E_ARG for null or
+ * misplaced tables, batch < 1, num_rows < batch, num_steps < 0, a start
+ * outside [0, num_rows) or rates that are not finite and positive. */
 xpbd_status xpbd_mlp_train_steps(xpbd_mlp *net, const uint16_t *features, const float *targets,
-                                 const int32_t *rows, int32_t batch, int32_t num_steps,
-                                 float first_rate, float last_rate, float *losses);
+                                 const int32_t *rows, int64_t num_rows, const int64_t *starts,
+                                 int32_t batch, int32_t num_steps, float first_rate,
+                                 float last_rate, float *losses);
 
 /* Normalisation of the network's inputs and outputs from a recording made
  * with the identity normalisation (in_shift 0, in_scale 1): over the n rows

@@ -203,7 +203,8 @@ xpbd_status xpbd_mlp_train_step(xpbd_mlp *net, const uint16_t *features, const f
     int step = net->adam_step;
     if (learning_rate > 0.0f)
         step = ++net->adam_step;
-    HIP_TRY(xpbd::launch_mlp_train(net->d, features, targets, rows, n, net->partial, net->stats,
+    HIP_TRY(xpbd::launch_mlp_train(net->d, features, targets, rows, 0, n, n, net->partial,
+                                   net->stats,
                                    learning_rate, 0.9f, 0.999f, 1e-8f, step, grad,
                                    loss_on_device ? loss : net->loss, net->stream));
     if (loss && !loss_on_device) {
@@ -214,19 +215,27 @@ xpbd_status xpbd_mlp_train_step(xpbd_mlp *net, const uint16_t *features, const f
 }
 
 xpbd_status xpbd_mlp_train_steps(xpbd_mlp *net, const uint16_t *features, const float *targets,
-                                 const int32_t *rows, int32_t batch, int32_t num_steps,
-                                 float first_rate, float last_rate, float *losses)
+                                 const int32_t *rows, int64_t num_rows, const int64_t *starts,
+                                 int32_t batch, int32_t num_steps, float first_rate,
+                                 float last_rate, float *losses)
 {
     g_error.clear();
-    if (!net || !features || !targets || !rows || batch < 1 || num_steps < 0)
-        return fail(XPBD_E_ARG, "net, features, targets, rows, batch >= 1 and num_steps >= 0 "
-                    "are required");
+    if (!net || !features || !targets || !rows || batch < 1 || num_steps < 0 ||
+        num_rows < batch)
+        return fail(XPBD_E_ARG, "net, features, targets, rows, batch >= 1, num_rows >= batch and "
+                    "num_steps >= 0 are required");
     if (!(std::isfinite(first_rate) && first_rate > 0.0f && std::isfinite(last_rate) &&
           last_rate > 0.0f))
         return fail(XPBD_E_ARG, "the learning rates must be finite and > 0");
     if (!is_device_pointer(features) || !is_device_pointer(targets) || !is_device_pointer(rows) ||
         (losses && !is_device_pointer(losses)))
         return fail(XPBD_E_ARG, "features, targets, rows and losses must be device memory");
+    if (starts && is_device_pointer(starts))
+        return fail(XPBD_E_ARG, "starts must be host memory");
+    for (int32_t s = 0; starts && s < num_steps; ++s)
+        if (starts[s] < 0 || starts[s] >= num_rows)
+            return fail(XPBD_E_ARG, "starts[%d] = %lld is outside [0, num_rows)", s,
+                        (long long)starts[s]);
     if (num_steps == 0)
         return XPBD_OK;
     const int groups = (batch + xpbd::kMlpTile - 1) / xpbd::kMlpTile;
@@ -249,8 +258,9 @@ xpbd_status xpbd_mlp_train_steps(xpbd_mlp *net, const uint16_t *features, const 
     for (int32_t s = 0; s < num_steps; ++s) {
         const double f = num_steps > 1 ? (double)s / (double)(num_steps - 1) : 0.0;
         const float rate = (float)((double)first_rate * std::pow(ratio, f));
+        const int64_t start = starts ? starts[s] : (int64_t)s * batch % num_rows;
         const int step = ++net->adam_step;
-        HIP_TRY(xpbd::launch_mlp_train(net->d, features, targets, rows + (size_t)s * batch, batch,
+        HIP_TRY(xpbd::launch_mlp_train(net->d, features, targets, rows, start, num_rows, batch,
                                        net->partial, net->stats, rate, 0.9f, 0.999f, 1e-8f, step,
                                        nullptr, losses ? losses + s : net->loss, net->stream));
     }

@@ -48,14 +48,17 @@ hipError_t launch_mlp_sync(const MlpDev &net, hipStream_t stream);
 hipError_t launch_mlp_forward(const MlpDev &net, const uint16_t *feat, int n, float *y_out,
                               float *pos, int64_t np, hipStream_t stream);
 // Gradient of the masked mean squared error on n samples (sample j is row
-// rows[j] of feat / targets, or row j without a row list), then one Adam step
+// rows[(rows_start + j) mod rows_count] of feat / targets, with
+// rows_start < rows_count and n <= rows_count, or row j without a row list),
+// then one Adam step
 // (skipped when lr == 0).  partial: [ceil(n / 64)][kMlpParams], stats:
 // [ceil(n / 64)][2] scratch; grad_out (float32 [kMlpParams]) and loss_out may
 // be null.
 hipError_t launch_mlp_train(const MlpDev &net, const uint16_t *feat, const float *targets,
-                            const int32_t *rows, int n, float *partial, float *stats, float lr,
-                            float beta1, float beta2, float eps, int step, float *grad_out,
-                            float *loss_out, hipStream_t stream);
+                            const int32_t *rows, int64_t rows_start, int64_t rows_count, int n,
+                            float *partial, float *stats, float lr, float beta1, float beta2,
+                            float eps, int step, float *grad_out, float *loss_out,
+                            hipStream_t stream);
 
 // Normalisation statistics of n training rows (features [n][32] bfloat16,
 // targets [n][4]) over the rows whose free flag is set; workspace: device

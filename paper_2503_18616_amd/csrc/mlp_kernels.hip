@@ -72,17 +72,33 @@ struct MlpFwdLds {
     uint16_t a2[S * PH];
 };
 
-// Load the features of samples base .. base + S (rows beyond n are zero); sample
-// j reads row rows[j] when a row list is given, else row j.  The unit-major
-// copy only when a0t is given.
+// The table row of sample j: with a row list, entry (start + j) mod count of
+// the list (a window that may wrap around its end; start < count and
+// j < count), else row j.
+struct RowList {
+    const int32_t *rows;
+    int64_t start, count;
+    __device__ int64_t operator()(int64_t j) const
+    {
+        if (!rows)
+            return j;
+        int64_t k = start + j;
+        k = k >= count ? k - count : k;
+        return (int64_t)rows[k];
+    }
+};
+
+// Load the features of samples base .. base + S (rows beyond n are zero);
+// sample j reads table row rows(j).  The unit-major copy only when a0t is
+// given.
 __device__ void load_features(uint16_t *a0, uint16_t *a0t, const uint16_t *feat,
-                              const int32_t *rows, int64_t base, int n, int tid)
+                              const RowList &rows, int64_t base, int n, int tid)
 {
     for (int i = tid; i < S * F / 8; i += 256) {
         const int s = i / (F / 8), c = (i % (F / 8)) * 8;
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
         if (base + s < n) {
-            const int64_t r = rows ? (int64_t)rows[base + s] : base + s;
+            const int64_t r = rows(base + s);
             v = *reinterpret_cast<const uint4 *>(feat + r * F + c);
         }
         *reinterpret_cast<uint4 *>(&a0[s * PF + c]) = v;
@@ -163,7 +179,7 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(MlpDev net, const uint
     __shared__ MlpFwdLds L;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t base = (int64_t)blockIdx.x * S;
-    load_features(L.a0, nullptr, feat, nullptr, base, n, tid);
+    load_features(L.a0, nullptr, feat, RowList{nullptr, 0, 0}, base, n, tid);
     __syncthreads();
     hidden_layer<F, false>(L.a0, PF, net.w1, net.b1, L.a1, nullptr, nullptr, wave, lane);
     __syncthreads();
@@ -203,7 +219,7 @@ __device__ __forceinline__ float column_sum(f32x4 v)
 // (unnormalised) go to partial[blockIdx.x][param], its loss sum and sample
 // count to stats[blockIdx.x][2].  targets: float32 [n][4] in scaled units.
 __global__ void __launch_bounds__(256) mlp_grad_kernel(MlpDev net, const uint16_t *feat,
-                                                       const float *targets, const int32_t *rows,
+                                                       const float *targets, RowList rows,
                                                        int n, float *partial, float *stats)
 {
     __shared__ MlpLds L;
@@ -228,7 +244,7 @@ __global__ void __launch_bounds__(256) mlp_grad_kernel(MlpDev net, const uint16_
             const int s = 16 * wave + 4 * (lane >> 4) + e;
             float d = 0.f;
             if (o < 3 && base + s < n && bf16_float(L.a0[s * PF + 31]) > 0.f) {
-                const int64_t r = rows ? (int64_t)rows[base + s] : base + s;
+                const int64_t r = rows(base + s);
                 d = acc[e] + net.b3[o] - targets[r * 4 + o];
                 cnt += o == 0 ? 1.f : 0.f;
             }
@@ -452,13 +468,18 @@ hipError_t launch_mlp_forward(const MlpDev &net, const uint16_t *feat, int n, fl
 }
 
 hipError_t launch_mlp_train(const MlpDev &net, const uint16_t *feat, const float *targets,
-                            const int32_t *rows, int n, float *partial, float *stats, float lr,
-                            float beta1, float beta2, float eps, int step, float *grad_out,
-                            float *loss_out, hipStream_t stream)
+                            const int32_t *rows, int64_t rows_start, int64_t rows_count, int n,
+                            float *partial, float *stats, float lr, float beta1, float beta2,
+                            float eps, int step, float *grad_out, float *loss_out,
+                            hipStream_t stream)
 {
     const int groups = (n + S - 1) / S;
+    RowList list;
+    list.rows = rows;
+    list.start = rows_start;
+    list.count = rows_count;
     hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)groups), dim3(256), 0, stream, net, feat,
-                       targets, rows, n, partial, stats);
+                       targets, list, n, partial, stats);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;

@@ -829,11 +829,29 @@ struct Record {
 };
 
 struct RoundTables {
-    const XPBD_GLOBAL Record *rr;
-    int B;
-    int tid;
+    __amdgpu_buffer_rsrc_t rsrc;      // the mesh's record table as a buffer
+    uint32_t lane_bytes;              // byte offset of this lane's record in a row
+    uint32_t row_bytes;               // bytes of one row (blockDim records)
     uint32_t pad;                     // padding particle in the records' units
 };
+
+// The record table [rounds + 2][B] of a mesh (12-byte records) as a buffer:
+// a row's offset is a scalar, the lane's offset a fixed register, so a fetch
+// needs no per-round address arithmetic in the vector unit; reads beyond the
+// table return zeros.
+__device__ __forceinline__ RoundTables round_tables(const MeshDev &md, int B, int tid,
+                                                    uint32_t pad)
+{
+    RoundTables t;
+    const uint32_t row = 12u * (uint32_t)B;
+    t.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(md.round_rec), (short)0,
+                                               (int)(row * (uint32_t)(md.num_rounds + 2)),
+                                               0x00020000);
+    t.lane_bytes = 12u * (uint32_t)tid;
+    t.row_bytes = row;
+    t.pad = pad;
+    return t;
+}
 
 // Every wave fetches exactly one record per round (also a wave without a
 // constraint in round r: the table is L2-resident), so the loads retire in
@@ -843,11 +861,13 @@ struct RoundTables {
 // fetches row r + 2 with no wrap.
 __device__ __forceinline__ Record fetch_record(const RoundTables &t, int r)
 {
-    const XPBD_GLOBAL Record *p = t.rr + r * t.B + t.tid;
+    typedef unsigned int v3u __attribute__((ext_vector_type(3)));
+    const v3u v = __builtin_amdgcn_raw_buffer_load_b96(t.rsrc, (int)t.lane_bytes,
+                                                       (int)((uint32_t)r * t.row_bytes), 0);
     Record rec;
-    rec.w0 = p->w0;
-    rec.w1 = p->w1;
-    rec.w2 = p->w2;
+    rec.w0 = v.x;
+    rec.w1 = v.y;
+    rec.w2 = v.z;
     return rec;
 }
 
@@ -1024,11 +1044,9 @@ __device__ __forceinline__ void step_reg_body(StepArgs A)
     __syncthreads();
 
     // round tables and this wave's masks (uniform); prime the two-round prefetch
-    RoundTables tab;
-    tab.rr = (const XPBD_GLOBAL Record *)(uintptr_t)md.round_rec;
-    tab.B = B;
-    tab.tid = tid;
-    tab.pad = EG == 1 ? 16u * (uint32_t)VS : (uint32_t)VS;   // in the records' units
+    // (padding particle in the records' units)
+    const RoundTables tab =
+        round_tables(md, B, tid, EG == 1 ? 16u * (uint32_t)VS : (uint32_t)VS);
     const uint64_t active = A.meshes[A.envs[env[0]].mesh].wave_active[__builtin_amdgcn_readfirstlane(wave)];
     const uint64_t barriers = md.barrier_mask;
     // (issued in this order, as in every round: the loop then waits for the
@@ -1627,11 +1645,8 @@ __global__ void __launch_bounds__(1024) xpbd_substep_reg_kernel(StepArgs A, Lear
         owner = held >= 0 ? held % B : -1;
     }
 
-    RoundTables tab;
-    tab.rr = (const XPBD_GLOBAL Record *)(uintptr_t)md.round_rec;
-    tab.B = B;
-    tab.tid = tid;
-    tab.pad = 16u * (uint32_t)V;   // byte offset (one environment per workgroup)
+    // (padding particle as a byte offset: one environment per workgroup)
+    const RoundTables tab = round_tables(md, B, tid, 16u * (uint32_t)V);
     const uint64_t active = A.meshes[ed.mesh].wave_active[__builtin_amdgcn_readfirstlane(wave)];
     const uint64_t tets = md.tet_mask, barriers = md.barrier_mask;
     Record slot_a = fetch_record(tab, 0);   // in this order (see xpbd_step_reg_kernel)

@@ -2,15 +2,17 @@
 
     python -m paper_2503_18616_amd.profile_summary \\
         --trace DIR --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR \\
-        --copy-mib 256 --workload NAME --command "..." --out profiles/NAME.md
+        --copy-mib 256 --workload NAME --colouring C --command "..." --out profiles/NAME.md \\
+        [--record xpbd_step_traffic.json]
 
 DIR are rocprofv3 ``--output-format csv`` directories: a ``--kernel-trace
 --stats`` run of the bench, ``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``
 runs of the bench, and the same two counters over ``bench.py
 --copy-calibration MIB`` (a plain device copy of known size, which gives the
 scale of each counter).  Writes the markdown summary and
-profiles/xpbd_step_traffic.json (HBM bytes per step launch, scaled, with the
-SHA-256 of the kernel source they were measured on).
+a traffic record under profiles/ (HBM bytes per step launch, scaled, with the
+SHA-256 of the kernel and runtime sources they were measured on and the
+colouring).
 """
 from __future__ import annotations
 
@@ -24,11 +26,12 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 KERNEL_SOURCE = os.path.join(PKG, "csrc", "xpbd_kernels.hip")
+RUNTIME_SOURCE = os.path.join(PKG, "csrc", "xpbd_runtime.hip")
 STEP_KERNEL = "xpbd_step_"
 
 
-def kernel_source_sha256() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
+def source_sha256(path) -> str:
+    with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
 
 
@@ -54,8 +57,12 @@ def main():
         ap.add_argument("--" + k.replace("_", "-"), required=True)
     ap.add_argument("--copy-mib", type=int, required=True)
     ap.add_argument("--workload", required=True)
+    ap.add_argument("--colouring", type=int, required=True,
+                    help="the colouring the profiled runs used (bench.py --colouring)")
     ap.add_argument("--command", required=True)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--record", default="xpbd_step_traffic.json",
+                    help="file under profiles/ that receives the traffic record")
     ap.add_argument("--extra", nargs="*", default=[],
                     help="further --pmc csv directories; their counters are listed per dispatch")
     args = ap.parse_args()
@@ -99,11 +106,13 @@ def main():
         lines.append("")
     with open(args.out, "w") as f:
         f.write("\n".join(lines))
-    rec = {"kernel_source_sha256": kernel_source_sha256(), "workload": args.workload,
+    rec = {"kernel_source_sha256": source_sha256(KERNEL_SOURCE),
+           "runtime_source_sha256": source_sha256(RUNTIME_SOURCE),
+           "workload": args.workload, "colouring": args.colouring,
            "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
            "fetch_scale": fetch_scale, "write_scale": write_scale,
            "traffic_bytes_per_launch": traffic, "command": args.command}
-    with open(os.path.join(ROOT, "profiles", "xpbd_step_traffic.json"), "w") as f:
+    with open(os.path.join(ROOT, "profiles", args.record), "w") as f:
         json.dump(rec, f, indent=1)
     print("\n".join(lines))
 

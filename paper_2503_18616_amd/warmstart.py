@@ -51,28 +51,21 @@ def normalisation(feats, targets):
 
 def train(net: "xpbd.Mlp", feats, targets, steps: int, batch: int = 8192, lr: float = 1e-3,
           seed: int = 0, final_lr: float = 1e-4):
-    """Adam steps on minibatches drawn from a seeded permutation of the free
-    recorded rows (epoch after epoch; the learning rate decays geometrically
-    from lr to final_lr).  Returns the loss of every step.
+    """Adam steps on minibatches of the free recorded rows (the learning rate
+    decays geometrically from lr to final_lr).  Returns the loss of every
+    step.
 
-    The host queues all steps with one library call: the permutations are
-    drawn and checked against the tables before the first step, each step's
-    loss goes to a device buffer, and the losses are read back once at the
-    end."""
+    The free rows are shuffled once (seeded); step s takes the next ``batch``
+    rows of that order, wrapping around its end, so successive passes over
+    the rows start at shifting offsets.  The host queues all steps with one
+    library call and reads the losses back once at the end."""
     import torch
     rng = np.random.default_rng(seed)
     free = np.flatnonzero(feats[:, 31].float().cpu().numpy() > 0).astype(np.int32)
     if free.size == 0:
         raise ValueError("the recording holds no free rows to train on")
     batch = min(batch, free.size)
-    # every epoch (a fresh permutation) serves floor(rows / batch) steps
-    per_epoch, parts, left = free.size // batch, [], steps
-    while left > 0:
-        k = min(per_epoch, left)
-        parts.append(free[rng.permutation(free.size)][:k * batch])
-        left -= k
-    rows = np.concatenate(parts) if parts else free[:0]
-    order = torch.from_numpy(np.ascontiguousarray(rows, dtype=np.int32)).cuda()
+    order = torch.from_numpy(np.ascontiguousarray(free[rng.permutation(free.size)])).cuda()
     xpbd.check_rows(order, feats.shape[0])
     losses = torch.zeros(max(steps, 1), dtype=torch.float32, device="cuda")
     net.train_steps(feats, targets, order, batch, steps, lr, final_lr, losses=losses,

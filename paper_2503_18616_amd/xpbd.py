@@ -167,8 +167,8 @@ _lib.xpbd_mlp_forward.argtypes = [_V, _V, ctypes.c_int32, _V]
 _lib.xpbd_mlp_train_step.restype = ctypes.c_int
 _lib.xpbd_mlp_train_step.argtypes = [_V, _V, _V, _V, ctypes.c_int32, ctypes.c_float, _V, _V]
 _lib.xpbd_mlp_train_steps.restype = ctypes.c_int
-_lib.xpbd_mlp_train_steps.argtypes = [_V, _V, _V, _V, ctypes.c_int32, ctypes.c_int32,
-                                      ctypes.c_float, ctypes.c_float, _V]
+_lib.xpbd_mlp_train_steps.argtypes = [_V, _V, _V, _V, ctypes.c_int64, _V, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_float, ctypes.c_float, _V]
 _lib.xpbd_mlp_destroy.restype = None
 _lib.xpbd_mlp_destroy.argtypes = [_V]
 _lib.xpbd_axis_neighbours.restype = ctypes.c_int
@@ -519,23 +519,29 @@ def check_rows(rows, n):
 
 
 def xpbd_mlp_train_steps(net, features, targets, rows, batch, num_steps, first_rate, last_rate,
-                         losses=None, rows_checked=False):
-    """num_steps training steps in one library call: step s on rows[s batch ..
-    s batch + batch - 1] (device int32, checked here against the tables unless
-    rows_checked) with a learning rate decaying geometrically from first_rate
-    to last_rate; each step's loss to losses[s] (device float32) if given."""
+                         starts=None, losses=None, rows_checked=False):
+    """num_steps training steps in one library call: step s on the window of
+    ``batch`` entries of the device int32 row list ``rows`` that begins at
+    starts[s] (host int64 array; None: s * batch) and wraps around its end,
+    with a learning rate decaying geometrically from first_rate to last_rate;
+    each step's loss to losses[s] (device float32) if given.  The row list is
+    checked here against the tables unless rows_checked."""
     n = _device_rows(features, MLP_FEATURE_STRIDE, "torch.bfloat16", "features")
     if _device_rows(targets, 4, "torch.float32", "targets") != n:
         raise ValueError("targets need one row per feature row")
-    if _device_rows(rows, 1, "torch.int32", "rows") < int(batch) * int(num_steps):
-        raise ValueError("rows must hold batch * num_steps indices")
+    num_rows = _device_rows(rows, 1, "torch.int32", "rows")
     if not rows_checked:
-        check_rows(rows[:int(batch) * int(num_steps)], n)
+        check_rows(rows, n)
     if losses is not None and _device_rows(losses, 1, "torch.float32", "losses") < num_steps:
         raise ValueError("losses needs num_steps values")
-    _check(_lib.xpbd_mlp_train_steps(net, _ptr(features), _ptr(targets), _ptr(rows), int(batch),
-                                     int(num_steps), float(first_rate), float(last_rate),
-                                     _ptr(losses)))
+    st = None
+    if starts is not None:
+        st = np.ascontiguousarray(starts, dtype=np.int64)
+        if st.size < num_steps:
+            raise ValueError("starts needs num_steps values")
+    _check(_lib.xpbd_mlp_train_steps(net, _ptr(features), _ptr(targets), _ptr(rows), int(num_rows),
+                                     _ptr(st), int(batch), int(num_steps), float(first_rate),
+                                     float(last_rate), _ptr(losses)))
 
 
 def xpbd_mlp_train_step(net, features, targets, learning_rate, grad=None, rows=None,
@@ -840,9 +846,9 @@ class Mlp:
         xpbd_mlp_forward(self.handle, features, y)
 
     def train_steps(self, features, targets, rows, batch, num_steps, first_rate, last_rate,
-                    losses=None, rows_checked=False):
+                    starts=None, losses=None, rows_checked=False):
         xpbd_mlp_train_steps(self.handle, features, targets, rows, batch, num_steps, first_rate,
-                             last_rate, losses, rows_checked)
+                             last_rate, starts, losses, rows_checked)
 
     def train_step(self, features, targets, learning_rate, grad=None, rows=None, loss_out=None,
                    rows_checked=False):

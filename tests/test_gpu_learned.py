@@ -167,32 +167,41 @@ def test_adam_steps_match_oracle_over_several_steps(xp):
 
 
 def test_training_steps_in_one_call_equal_single_steps(xp):
-    """xpbd_mlp_train_steps (all steps of a run in one library call, the
-    learning rate decaying geometrically) against the same steps issued one
-    xpbd_mlp_train_step call at a time with the rates it states: weights and
-    per-step losses bit for bit."""
+    """xpbd_mlp_train_steps (all steps of a run in one library call, each on a
+    window of one row list that may wrap around its end, the learning rate
+    decaying geometrically) against the same steps issued one
+    xpbd_mlp_train_step call at a time with the rows and rates it states:
+    weights and per-step losses bit for bit, for given starts and for the
+    default ones (s * batch mod the list's length)."""
     import torch
-    net = random_net(9)
     rng = np.random.default_rng(9)
-    n, batch, steps = 700, 192, 6
+    n, batch, steps, count = 700, 192, 6, 500
     a0 = ws.bf16(rng.standard_normal((n, 27)))
     tgt = np.zeros((n, 4), np.float32)
     tgt[:, :3] = np.tanh(a0[:, :3] * 0.5)
     feats, targets = feature_rows(a0, np.ones(n, bool)), torch.tensor(tgt).cuda()
-    rows = torch.tensor(rng.integers(0, n, steps * batch).astype(np.int32)).cuda()
+    rows_np = rng.integers(0, n, count).astype(np.int32)
+    rows = torch.tensor(rows_np).cuda()
     first, last = np.float32(2e-3), np.float32(3e-4)
     rates = [np.float32(float(first) * (float(last) / float(first)) ** (s / (steps - 1)))
              for s in range(steps)]
-    with xp.Mlp(flat(net), None, np.ones(27), None, net.out_scale) as a, \
-            xp.Mlp(flat(net), None, np.ones(27), None, net.out_scale) as b:
-        losses = torch.zeros(steps, dtype=torch.float32, device="cuda")
-        a.train_steps(feats, targets, rows, batch, steps, float(first), float(last), losses=losses)
-        single = [b.train_step(feats, targets, float(rates[s]),
-                               rows=rows[s * batch:(s + 1) * batch].contiguous())
-                  for s in range(steps)]
-        assert np.array_equal(a.params(), b.params())
-        assert np.array_equal(losses.cpu().numpy(), np.float32(single))
-        assert not np.array_equal(a.params(), flat(net))
+    for starts in (np.array([0, 420, 17, 499, 308, 250], np.int64), None):
+        st = starts if starts is not None else np.arange(steps, dtype=np.int64) * batch % count
+        assert (st + batch > count).any()   # some windows wrap
+        net = random_net(9)
+        with xp.Mlp(flat(net), None, np.ones(27), None, net.out_scale) as a, \
+                xp.Mlp(flat(net), None, np.ones(27), None, net.out_scale) as b:
+            losses = torch.zeros(steps, dtype=torch.float32, device="cuda")
+            a.train_steps(feats, targets, rows, batch, steps, float(first), float(last),
+                          starts=starts, losses=losses)
+            single = []
+            for s in range(steps):
+                window = rows_np[(st[s] + np.arange(batch)) % count]
+                single.append(b.train_step(feats, targets, float(rates[s]),
+                                           rows=torch.tensor(window).cuda()))
+            assert np.array_equal(a.params(), b.params())
+            assert np.array_equal(losses.cpu().numpy(), np.float32(single))
+            assert not np.array_equal(a.params(), flat(net))
 
 
 def test_normalisation_statistics_match_numpy(xp):
