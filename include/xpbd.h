@@ -164,9 +164,11 @@ enum { XPBD_TOOL_SPHERE = 0, XPBD_TOOL_CAPSULE = 1 };
  *                  so that it fills one 64-lane wave instead of most of two
  *   CAPPED         LARGEST_FIRST, but a colour keeps at most its first 256
  *                  members (the others stay uncoloured), so that every colour
- *                  is one round of a 256-thread workgroup */
+ *                  is one round of a 256-thread workgroup
+ *   CAPPED_128     the same with at most 128 members: one round of a
+ *                  128-thread workgroup */
 enum { XPBD_COLOURING_GREEDY = 0, XPBD_COLOURING_LARGEST_FIRST = 1, XPBD_COLOURING_WAVES = 2,
-       XPBD_COLOURING_CAPPED = 3 };
+       XPBD_COLOURING_CAPPED = 3, XPBD_COLOURING_CAPPED_128 = 4 };
 
 /* Values of xpbd_params.colour_packing.  Constraints of one colour share no
  * particle, so their order changes no result; it only decides which lanes

@@ -199,9 +199,11 @@ def greedy_colour(num_vertices, verts):
 
 
 # colourings of the edge and tetrahedron constraints (R10, R13)
-COLOURING_GREEDY, COLOURING_LARGEST_FIRST, COLOURING_WAVES, COLOURING_CAPPED = 0, 1, 2, 3
+(COLOURING_GREEDY, COLOURING_LARGEST_FIRST, COLOURING_WAVES, COLOURING_CAPPED,
+ COLOURING_CAPPED_128) = 0, 1, 2, 3, 4
 WAVE_CUT_ABOVE = 100
 COLOUR_CAP = 256
+COLOUR_CAP_128 = 128
 
 
 def largest_first_colour(num_vertices, verts, cut_above=0, cap=0):
@@ -223,7 +225,7 @@ def colour(num_vertices, verts, colouring=COLOURING_GREEDY):
     if colouring == COLOURING_GREEDY:
         return greedy_colour(num_vertices, verts)
     cut = WAVE_CUT_ABOVE if colouring == COLOURING_WAVES else 0
-    cap = COLOUR_CAP if colouring == COLOURING_CAPPED else 0
+    cap = {COLOURING_CAPPED: COLOUR_CAP, COLOURING_CAPPED_128: COLOUR_CAP_128}.get(colouring, 0)
     return largest_first_colour(num_vertices, verts, cut, cap)
 
 

@@ -14,20 +14,24 @@
 
 // A size class of the register variant: environments whose meshes share a
 // block size, an LDS tier and a number of environments per workgroup run in
-// one launch; several classes run
-// concurrently on streams of their own, forked from and joined to the
-// batch's stream.
+// one launch; several classes run concurrently on up to kClassLanes streams
+// (the batch's own and streams forked from and joined to it).
 struct RegClass {
     int block = 256;
     int group = 1;                  // environments per workgroup
     int lambda_banks = 1;
+    int rounds = 0;                 // rounds per sweep of its largest mesh
     bool round_barriers = true;     // every colour of every mesh of the class is one round
     uint32_t lds_bytes = 0;
     int32_t num_groups = 0;
     int32_t *groups_dev = nullptr;
-    hipStream_t stream = nullptr;   // own stream when the batch has several classes
-    hipEvent_t done = nullptr;
+    int lane = 0;                   // 0: the batch's stream, k > 0: lanes[k - 1]
 };
+
+// Streams a multi-class step uses at most, the batch's own included: HIP maps
+// a process's streams onto 4 hardware queues by default, and classes whose
+// streams share a queue run one after the other.
+constexpr int kClassLanes = 4;
 
 struct xpbd_batch {
     int device = 0;
@@ -46,6 +50,9 @@ struct xpbd_batch {
     int32_t *groups_dev = nullptr;
     uint32_t lds_bytes = 0;
     std::vector<RegClass> classes;           // register variant
+    std::vector<int> class_order;            // launch order: largest estimated work first
+    std::vector<hipStream_t> lanes;          // forked streams of a multi-class step
+    std::vector<hipEvent_t> lane_done;
     hipEvent_t fork = nullptr;               // start of a step on the batch's stream
     std::vector<xpbd::PreparedMesh> meshes;
     std::vector<int32_t> env_mesh;
@@ -74,14 +81,12 @@ struct xpbd_batch {
     ~xpbd_batch()
     {
         (void)hipStreamSynchronize(stream);
-        for (auto &c : classes) {
-            if (c.stream) {
-                (void)hipStreamSynchronize(c.stream);
-                (void)hipStreamDestroy(c.stream);
-            }
-            if (c.done)
-                (void)hipEventDestroy(c.done);
+        for (hipStream_t l : lanes) {
+            (void)hipStreamSynchronize(l);
+            (void)hipStreamDestroy(l);
         }
+        for (hipEvent_t e : lane_done)
+            (void)hipEventDestroy(e);
         if (fork)
             (void)hipEventDestroy(fork);
         for (auto &a : allocations)

@@ -14,8 +14,9 @@ namespace {
 
 // WAVES colouring: a colour of 65 .. kWaveCutAbove members is cut to 64.
 constexpr int32_t kWaveCutAbove = 100;
-// CAPPED colouring: a colour keeps at most kColourCap members.
+// CAPPED and CAPPED_128 colourings: a colour keeps at most this many members.
 constexpr int32_t kColourCap = 256;
+constexpr int32_t kColourCap128 = 128;
 
 // Six times the signed volume of (a, b, c, d): the determinant of the edge
 // vectors b - a, c - a, d - a, expanded along its first row.
@@ -819,7 +820,9 @@ int prepare_mesh(int32_t num_vertices, int32_t num_tets, const float *rest_pos,
                                                out.tet_colour);
     } else {
         const int32_t cut = colouring == XPBD_COLOURING_WAVES ? kWaveCutAbove : 0;
-        const int32_t cap = colouring == XPBD_COLOURING_CAPPED ? kColourCap : 0;
+        const int32_t cap = colouring == XPBD_COLOURING_CAPPED       ? kColourCap
+                            : colouring == XPBD_COLOURING_CAPPED_128 ? kColourCap128
+                                                                      : 0;
         out.num_edge_colours = largest_first_colouring(num_vertices, out.num_edges(), 2,
                                                        out.edges.data(), cut, cap, out.edge_colour);
         out.num_tet_colours = largest_first_colouring(num_vertices, out.num_tets(), 4,

@@ -63,7 +63,7 @@ xpbd_status validate_params(const xpbd_params *p)
         return fail(XPBD_E_ARG, "unknown solver_variant %d", p->solver_variant);
     if (p->colour_packing < XPBD_PACKING_AUTO || p->colour_packing > XPBD_PACKING_SEARCH)
         return fail(XPBD_E_ARG, "unknown colour_packing %d", p->colour_packing);
-    if (p->colouring < XPBD_COLOURING_GREEDY || p->colouring > XPBD_COLOURING_CAPPED)
+    if (p->colouring < XPBD_COLOURING_GREEDY || p->colouring > XPBD_COLOURING_CAPPED_128)
         return fail(XPBD_E_ARG, "unknown colouring %d", p->colouring);
     if (p->envs_per_group < 0 || p->envs_per_group > xpbd::kMaxEnvsPerGroup)
         return fail(XPBD_E_ARG, "envs_per_group must be 0, 1 or 2 (got %d)", p->envs_per_group);
@@ -191,7 +191,7 @@ xpbd_status xpbd_prepare_mesh_coloured(const xpbd_mesh *mesh, int32_t colouring,
     g_error.clear();
     if (!mesh || !counts)
         return fail(XPBD_E_ARG, "mesh and counts must not be NULL");
-    if (colouring < XPBD_COLOURING_GREEDY || colouring > XPBD_COLOURING_CAPPED)
+    if (colouring < XPBD_COLOURING_GREEDY || colouring > XPBD_COLOURING_CAPPED_128)
         return fail(XPBD_E_ARG, "unknown colouring %d", colouring);
     PreparedMesh pm;
     std::string err;
@@ -532,15 +532,9 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
             c.lds_bytes = std::max(c.lds_bytes, reg_lds(pm, c.group));
             int r = count_rounds(pm, c.block, c.group);
             r += r % 2;
+            c.rounds = std::max(c.rounds, r);
             if (r > 32)
                 c.lambda_banks = 2;
-        }
-        if (b->classes.size() > 1) {
-            HIP_TRY(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
-            for (auto &c : b->classes) {
-                HIP_TRY(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
-                HIP_TRY(hipEventCreateWithFlags(&c.done, hipEventDisableTiming));
-            }
         }
     }
 
@@ -910,6 +904,56 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
             if (st != XPBD_OK)
                 return cleanup(st);
         }
+        // streams of a multi-class step: the classes, largest estimated work
+        // first (passes of their workgroups over the CUs at their occupancy,
+        // times rounds per sweep), each to the stream with the least work so
+        // far, the batch's own stream first
+        const int ncls = (int)b->classes.size();
+        b->class_order.resize((size_t)ncls);
+        std::iota(b->class_order.begin(), b->class_order.end(), 0);
+        if (ncls > 1) {
+            const int cus = num_cus;
+            std::vector<double> est((size_t)ncls, 0.0);
+            for (int c = 0; c < ncls; ++c) {
+                const RegClass &rc = b->classes[(size_t)c];
+                const int waves = rc.block / 64;
+                const int per_cu = std::max(1, std::min(16 / std::max(waves, 1),
+                                                        (int)((uint32_t)lds_cu /
+                                                              std::max(rc.lds_bytes, 1u))));
+                const int64_t slots = (int64_t)per_cu * std::max(cus, 1);
+                const int64_t passes = (rc.num_groups + slots - 1) / slots;
+                est[(size_t)c] = (double)passes * (double)rc.rounds;
+            }
+            std::stable_sort(b->class_order.begin(), b->class_order.end(),
+                             [&](int x, int y) { return est[(size_t)x] > est[(size_t)y]; });
+            const int nl = std::min(ncls, kClassLanes);
+            std::vector<double> load((size_t)nl, 0.0);
+            for (int c : b->class_order) {
+                if (b->classes[(size_t)c].num_groups == 0)
+                    continue;
+                int best = 0;
+                for (int l = 1; l < nl; ++l)
+                    if (load[(size_t)l] < load[(size_t)best])
+                        best = l;
+                load[(size_t)best] += est[(size_t)c];
+                b->classes[(size_t)c].lane = best;
+            }
+            hipError_t he = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+            for (int l = 1; l < nl && he == hipSuccess; ++l) {
+                hipStream_t ls = nullptr;
+                hipEvent_t ev = nullptr;
+                he = hipStreamCreateWithFlags(&ls, hipStreamNonBlocking);
+                if (he == hipSuccess)
+                    b->lanes.push_back(ls);   // the batch destroys what it holds
+                if (he == hipSuccess)
+                    he = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                if (he == hipSuccess)
+                    b->lane_done.push_back(ev);
+            }
+            if (he != hipSuccess)
+                return cleanup(fail(XPBD_E_HIP, "creating the class streams failed: %s",
+                                    hipGetErrorString(he)));
+        }
         // the single-class fields of the batch (the learned step needs one class)
         b->groups_dev = b->classes[0].groups_dev;
         b->num_groups = b->classes[0].num_groups;
@@ -1072,22 +1116,26 @@ xpbd_status xpbd::run_step(xpbd_batch *b, int32_t num_steps, const float *tools_
         HIP_TRY(xpbd::launch_step_reg(a, c.block, c.lambda_banks, c.group, c.lds_bytes,
                                       resid, b->stream));
     } else if (b->register_variant) {
-        // one launch per size class on the class streams, joined before the residual
+        // one launch per size class, largest first, on the batch's stream and
+        // the lanes forked from it, joined before the residual
         HIP_TRY(hipEventRecord(b->fork, b->stream));
-        for (const RegClass &c : b->classes) {
+        for (hipStream_t l : b->lanes)
+            HIP_TRY(hipStreamWaitEvent(l, b->fork, 0));
+        for (int ci : b->class_order) {
+            const RegClass &c = b->classes[(size_t)ci];
             if (c.num_groups == 0)
                 continue;
-            HIP_TRY(hipStreamWaitEvent(c.stream, b->fork, 0));
             a.groups = c.groups_dev;
             a.num_groups = c.num_groups;
             a.round_barriers = c.round_barriers ? 1 : 0;
-            HIP_TRY(xpbd::launch_step_reg(a, c.block, c.lambda_banks, c.group,
-                                          c.lds_bytes, false, c.stream));
-            HIP_TRY(hipEventRecord(c.done, c.stream));
+            HIP_TRY(xpbd::launch_step_reg(a, c.block, c.lambda_banks, c.group, c.lds_bytes,
+                                          false,
+                                          c.lane == 0 ? b->stream : b->lanes[(size_t)c.lane - 1]));
         }
-        for (const RegClass &c : b->classes)
-            if (c.num_groups > 0)
-                HIP_TRY(hipStreamWaitEvent(b->stream, c.done, 0));
+        for (size_t l = 0; l < b->lanes.size(); ++l) {
+            HIP_TRY(hipEventRecord(b->lane_done[l], b->lanes[l]));
+            HIP_TRY(hipStreamWaitEvent(b->stream, b->lane_done[l], 0));
+        }
         if (resid)
             HIP_TRY(xpbd::launch_residual(a, b->stream));
     } else

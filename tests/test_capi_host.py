@@ -65,11 +65,11 @@ def test_mesh_setup_bit_exact_with_oracle(xp, oracle_lib, grid):
     assert ulp_close(lib["rest_volume"], om.rest_volume)
 
 
-@pytest.mark.parametrize("colouring", [1, 2, 3])
+@pytest.mark.parametrize("colouring", [1, 2, 3, 4])
 @pytest.mark.parametrize("grid", GRIDS)
 def test_largest_first_colourings_bit_exact_with_oracle(xp, oracle_lib, grid, colouring):
     """The library's largest-first colourings (plain, with the cut of
-    65..100-member colours to 64, and capped at 256 members) equal the
+    65..100-member colours to 64, and capped at 256 or 128 members) equal the
     oracle's, constraint by constraint."""
     m = W.slab_mesh(*grid)
     lib = xp.xpbd_prepare_mesh(m.rest_pos, m.inv_mass, m.tets, colouring=colouring)
@@ -88,7 +88,7 @@ def test_mesh_setup_on_perturbed_and_shuffled_meshes(xp, oracle_lib):
         perm = rng.permutation(m.num_tets)
         tets = m.tets[perm]
         w = m.inv_mass * rng.uniform(0.5, 2.0, size=m.num_vertices).astype(np.float32)
-        for colouring in (0, 1, 2, 3):
+        for colouring in (0, 1, 2, 3, 4):
             lib = xp.xpbd_prepare_mesh(rest, w, tets, colouring=colouring)
             om = oracle_lib.prepare_mesh(rest, w, tets, colouring=colouring)
             assert np.array_equal(lib["edges"], om.edges)
@@ -148,7 +148,7 @@ def _create_error(xp, meshes=None, env_mesh=None, compliance=None, **pkw):
     (dict(flags=0x80), -1), (dict(block_size=96), -1), (dict(block_size=2048), -1),
     (dict(gravity=(0.0, float("inf"), 0.0)), -1), (dict(envs_per_group=3), -1),
     (dict(envs_per_group=-1), -1), (dict(colour_packing=6), -1), (dict(solver_variant=4), -1),
-    (dict(colouring=4), -1), (dict(colouring=-1), -1),
+    (dict(colouring=5), -1), (dict(colouring=-1), -1),
 ])
 def test_create_rejects_bad_params(xp, kw, status):
     assert _create_error(xp, **kw).status == status

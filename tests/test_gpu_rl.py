@@ -83,12 +83,13 @@ def start_state(num_envs, env_ids=None, seed=0):
     return tools, target, grasped
 
 
-def run_gpu(xp, wl, policy_params, steps, tools, target, grasped, per_step=True):
+def run_gpu(xp, wl, policy_params, steps, tools, target, grasped, per_step=True, colouring=0):
     """Returns per-step tool centres and grasp states, observations, actions
     and the final positions."""
     import torch
     m = wl.meshes[0]
     p = K.lib_params(xp, wl)
+    p.colouring = colouring
     N = wl.num_envs
     with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b, \
             xp.Policy(policy_params) as pol:
@@ -144,8 +145,10 @@ def check_grasps_valid(wl, got, e, x_hist, prev_grasp):
         before = g
 
 
-def run_oracle(oracle_lib, wl, policy_params, steps, tools, target, grasped, env_ids):
-    om = K.oracle_meshes(oracle_lib, wl)[0]
+def run_oracle(oracle_lib, wl, policy_params, steps, tools, target, grasped, env_ids,
+               colouring=0):
+    m = wl.meshes[0]
+    om = oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass, m.tets, colouring=colouring)
     params = K.oracle_params(oracle_lib, wl)
     rl = oracle_rl_params(wl.meshes[0])
     net = R.unpack_policy(policy_params)
@@ -236,15 +239,18 @@ def test_rl_random_policy_parity(xp, oracle_lib):
     print(f"max position error {worst_x:.3e} m, action error {worst_a:.3e}")
 
 
-def test_rl_full_size_sampled(xp, oracle_lib):
+@pytest.mark.parametrize("colouring", [0, 4], ids=["greedy", "capped-128"])
+def test_rl_full_size_sampled(xp, oracle_lib, colouring):
     """8192 environments (the benchmark's launch), 2 steps: first-step
     observations, actions and grasp commands of every environment against the
-    oracle, and the whole run of sampled environments."""
+    oracle, and the whole run of sampled environments; under the greedy
+    colouring and under the benchmark's (largest first, capped at 128
+    members, one round of the 128-thread workgroups per colour)."""
     N, steps = 8192, 2
     wl = W.rl_workload(N, seed=0)
     tools, target, grasped = start_state(N)
     pp = W.rl_policy_params(0)
-    got = run_gpu(xp, wl, pp, steps, tools, target, grasped)
+    got = run_gpu(xp, wl, pp, steps, tools, target, grasped, colouring=colouring)
     x_hist = run_gpu.x_hist
     m = wl.meshes[0]
     rl = oracle_rl_params(m)
@@ -263,7 +269,7 @@ def test_rl_full_size_sampled(xp, oracle_lib):
     assert np.all(g1[clear & closed & (grasped >= 0)] == HELD0)
     sample = [0, 1, 2, 15, 16, 17, 1000, 2047, 4095, 4096, 6001, 8190, 8191]
     t_s, tg_s, g_s = start_state(len(sample), env_ids=sample)
-    refs = run_oracle(oracle_lib, wl, pp, steps, t_s, tg_s, g_s, sample)
+    refs = run_oracle(oracle_lib, wl, pp, steps, t_s, tg_s, g_s, sample, colouring=colouring)
     drift = steps * ACT_TOL * W.RL_MAX_SPEED * wl.dt
     checked = 0
     for n, e in enumerate(sample):

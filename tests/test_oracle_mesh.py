@@ -212,7 +212,7 @@ def test_capped_first_colour_is_a_prefix_of_the_uncapped_one(oracle_lib):
 
 
 @pytest.mark.parametrize("grid", GRIDS)
-@pytest.mark.parametrize("colouring", [1, 2, 3])
+@pytest.mark.parametrize("colouring", [1, 2, 3, 4])
 def test_largest_first_colours_are_valid_and_maximal(oracle_lib, grid, colouring):
     """Every colour is a set of constraints sharing no particle; a colour that
     was not cut is maximal among the constraints coloured after it (each of
@@ -231,14 +231,16 @@ def test_largest_first_colours_are_valid_and_maximal(oracle_lib, grid, colouring
             touched.append(set(members.tolist()))
         for j in range(len(col)):
             for c in range(col[j]):
-                cut = (colouring == 2 and sizes[c] == 64) or \
-                      (colouring == 3 and sizes[c] == oracle_lib.COLOUR_CAP)
+                cap = {3: oracle_lib.COLOUR_CAP, 4: oracle_lib.COLOUR_CAP_128}.get(colouring)
+                cut = (colouring == 2 and sizes[c] == 64) or (cap is not None and sizes[c] == cap)
                 if not cut:
                     assert touched[c] & set(verts[j].tolist()), (j, c)
         if colouring == 2:
             assert not ((sizes > 64) & (sizes <= oracle_lib.WAVE_CUT_ABOVE)).any()
         if colouring == 3:
             assert sizes.max() <= oracle_lib.COLOUR_CAP
+        if colouring == 4:
+            assert sizes.max() <= oracle_lib.COLOUR_CAP_128
 
 
 def test_largest_first_reaches_the_degree_bound(oracle_lib):
