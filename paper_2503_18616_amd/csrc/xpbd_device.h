@@ -216,9 +216,28 @@ struct RegLdsLayout {
     uint32_t vel;      // float [3][V]
     uint32_t prev;     // float [3][V]  positions at the start of the substep
     uint32_t scratch;  // kRegScratchBytes
-    uint32_t faces;    // uint8 [tools][F]  capsule tools: candidate flags of the surface faces
+    uint32_t faces;    // capsule tools: [tools] x capsule_face_bytes (below)
     uint32_t total;
 };
+
+// LDS of one capsule tool in the register variant, for a mesh of F surface
+// faces in C colours: the candidate flags as 64-bit words [ceil(F / 64)]; the
+// candidates compacted colour by colour, as the LDS slots of their corners
+// (uint32 a | b << 16 [F], uint16 c [F]); the list's colour bounds uint16 [C + 1].
+struct CapsuleFaceLayout {
+    uint32_t flags, ab, c, bounds, total;
+};
+
+__host__ __device__ inline CapsuleFaceLayout capsule_face_layout(int32_t F, int32_t C)
+{
+    CapsuleFaceLayout l;
+    l.flags = 0;
+    l.ab = align_up(8u * (((uint32_t)F + 63u) / 64u), 16);
+    l.c = l.ab + align_up(4u * (uint32_t)F, 16);
+    l.bounds = l.c + align_up(2u * (uint32_t)F, 16);
+    l.total = l.bounds + align_up(2u * ((uint32_t)C + 1u), 16);
+    return l;
+}
 
 constexpr uint32_t kRegScratchTools = 384;
 constexpr uint32_t kRegScratchGrasp = 512;
@@ -226,7 +245,8 @@ constexpr uint32_t kRegScratchBytes = 1024;
 constexpr int kMaxEnvsPerGroup = 2;
 constexpr int kMaxCapsuleBlock = 512;   // register variant with capsule tools
 
-__host__ __device__ inline RegLdsLayout reg_lds_layout(int32_t V, int32_t face_flags = 0)
+// face_bytes: tools x capsule_face_layout(F, C).total for capsule tools, else 0
+__host__ __device__ inline RegLdsLayout reg_lds_layout(int32_t V, int32_t face_bytes = 0)
 {
     RegLdsLayout l;
     l.xw = 0;
@@ -234,7 +254,7 @@ __host__ __device__ inline RegLdsLayout reg_lds_layout(int32_t V, int32_t face_f
     l.prev = l.vel + 12u * (uint32_t)V;
     l.scratch = align_up(l.prev + 12u * (uint32_t)V, 16);
     l.faces = l.scratch + kRegScratchBytes;
-    l.total = l.faces + align_up((uint32_t)face_flags, 16);
+    l.total = l.faces + align_up((uint32_t)face_bytes, 16);
     return l;
 }
 

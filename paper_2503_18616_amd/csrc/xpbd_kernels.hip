@@ -265,26 +265,23 @@ __device__ V3 triangle_closest(V3 p, V3 a, V3 b, V3 c)
 }
 
 // Parameters (s on p0 p1, t on q0 q1) of the closest points of two segments
-// (the clamped solution of Ericson 2005, Sec. 5.1.9).
-__device__ void segments_closest(V3 p0, V3 p1, V3 q0, V3 q1, float &s, float &t)
+// (the clamped solution of Ericson 2005, Sec. 5.1.9), returned as (s, t).
+// Values, not references: a store through a reference chosen per branch
+// would put the caller's variables in scratch memory.
+__device__ float2 segments_closest(V3 p0, V3 p1, V3 q0, V3 q1)
 {
     const V3 d1 = p1 - p0, d2 = q1 - q0, r = p0 - q0;
     const float a = dot(d1, d1), e = dot(d2, d2), f = dot(d2, r);
-    s = t = 0.f;
     if (a <= 1e-30f && e <= 1e-30f)
-        return;
-    if (a <= 1e-30f) {
-        t = fminf(fmaxf(f / e, 0.f), 1.f);
-        return;
-    }
+        return make_float2(0.f, 0.f);
+    if (a <= 1e-30f)
+        return make_float2(0.f, fminf(fmaxf(f / e, 0.f), 1.f));
     const float c = dot(d1, r);
-    if (e <= 1e-30f) {
-        s = fminf(fmaxf(-c / a, 0.f), 1.f);
-        return;
-    }
+    if (e <= 1e-30f)
+        return make_float2(fminf(fmaxf(-c / a, 0.f), 1.f), 0.f);
     const float b = dot(d1, d2), den = a * e - b * b;
-    s = den > 0.f ? fminf(fmaxf((b * f - c * e) / den, 0.f), 1.f) : 0.f;
-    t = (b * s + f) / e;
+    float s = den > 0.f ? fminf(fmaxf((b * f - c * e) / den, 0.f), 1.f) : 0.f;
+    float t = (b * s + f) / e;
     if (t < 0.f) {
         t = 0.f;
         s = fminf(fmaxf(-c / a, 0.f), 1.f);
@@ -292,6 +289,7 @@ __device__ void segments_closest(V3 p0, V3 p1, V3 q0, V3 q1, float &s, float &t)
         t = 1.f;
         s = fminf(fmaxf((b - c) / a, 0.f), 1.f);
     }
+    return make_float2(s, t);
 }
 
 // Squared distance of segment p0 p1 and triangle (a, b, c); bary and s_pt
@@ -299,6 +297,7 @@ __device__ void segments_closest(V3 p0, V3 p1, V3 q0, V3 q1, float &s, float &t)
 __device__ float segment_triangle(V3 p0, V3 p1, V3 a, V3 b, V3 c, V3 &bary, V3 &s_pt)
 {
     float best = 3.0e38f;
+#pragma unroll
     for (int e = 0; e < 2; ++e) {
         const V3 p = e == 0 ? p0 : p1;
         const V3 w = triangle_closest(p, a, b, c);
@@ -310,19 +309,19 @@ __device__ float segment_triangle(V3 p0, V3 p1, V3 a, V3 b, V3 c, V3 &bary, V3 &
             s_pt = p;
         }
     }
-    const V3 v[3] = {a, b, c};
+    // the three edges a b, b c, c a; the weights are written out per edge, as
+    // an indexed array here would live in scratch memory
+#pragma unroll
     for (int e = 0; e < 3; ++e) {
-        const V3 e0 = v[e], e1 = v[(e + 1) % 3];
-        float ts, te;
-        segments_closest(p0, p1, e0, e1, ts, te);
+        const V3 e0 = e == 0 ? a : e == 1 ? b : c, e1 = e == 0 ? b : e == 1 ? c : a;
+        const float2 st = segments_closest(p0, p1, e0, e1);
+        const float ts = st.x, te = st.y;
         const V3 ps = p0 + ts * (p1 - p0), pe = e0 + te * (e1 - e0);
         const float d2 = dot(pe - ps, pe - ps);
         if (d2 < best) {
             best = d2;
-            float wv[3] = {0.f, 0.f, 0.f};
-            wv[e] = 1.f - te;
-            wv[(e + 1) % 3] = te;
-            bary = {wv[0], wv[1], wv[2]};
+            bary = e == 0 ? V3{1.f - te, te, 0.f} : e == 1 ? V3{0.f, 1.f - te, te}
+                                                          : V3{te, 0.f, 1.f - te};
             s_pt = ps;
         }
     }
@@ -344,12 +343,38 @@ __device__ float segment_triangle(V3 p0, V3 p1, V3 a, V3 b, V3 c, V3 &bary, V3 &
     return best;
 }
 
+// True when triangle (a, b, c) certainly lies farther than reach from segment
+// p0 p1, so that the exact closest-point test can be skipped: the sphere about
+// the centroid through the farthest corner stays beyond reach of the segment,
+// or both end points lie on one side of the triangle's plane, beyond reach of
+// it.  Both bounds keep a margin of 0.1 % of reach, far above the error of the
+// hardware reciprocal and square root they use.
+__device__ __forceinline__ bool face_beyond(V3 p0, V3 p1, V3 a, V3 b, V3 c, float reach)
+{
+    const V3 g = (1.f / 3.f) * (a + b + c);
+    const float r2 = fmaxf(fmaxf(dot(a - g, a - g), dot(b - g, b - g)), dot(c - g, c - g));
+    const V3 d = p1 - p0;
+    const float dd = dot(d, d);
+    const float s = dd > 0.f ? fminf(fmaxf(dot(g - p0, d) * __builtin_amdgcn_rcpf(dd), 0.f), 1.f)
+                             : 0.f;
+    const V3 q = p0 + s * d - g;
+    const float lim = __builtin_amdgcn_sqrtf(r2) + 1.001f * reach;
+    if (dot(q, q) > lim * lim)
+        return true;
+    const V3 n = cross(b - a, c - a);
+    const float h0 = dot(p0 - a, n), h1 = dot(p1 - a, n);
+    const float m2 = (1.001f * reach) * (1.001f * reach) * dot(n, n);
+    return h0 * h1 > 0.f && h0 * h0 > m2 && h1 * h1 > m2;
+}
+
 // Push face (a | b << 16, c) out of capsule p0 p1 of radius r with k_c = 1:
 // C = d - r on the closest point q = sum b_i x_i, gradient b_i n.
 __device__ void capsule_push(float4 *xw, uint2 f, V3 p0, V3 p1, float r)
 {
     const int ia = (int)(f.x & 0xffffu), ib = (int)(f.x >> 16), ic = (int)f.y;
     float4 pa = xw[ia], pb = xw[ib], pc = xw[ic];
+    if (face_beyond(p0, p1, v3(pa), v3(pb), v3(pc), r))
+        return;
     V3 bary, s;
     const float d2 = segment_triangle(p0, p1, v3(pa), v3(pb), v3(pc), bary, s);
     if (!(d2 < r * r))
@@ -380,6 +405,118 @@ __device__ void capsule_push(float4 *xw, uint2 f, V3 p0, V3 p1, float r)
     pc.x += sc * n.x;
     pc.y += sc * n.y;
     pc.z += sc * n.z;
+    xw[ia] = pa;
+    xw[ib] = pb;
+    xw[ic] = pc;
+}
+
+// The push-out of capsule_push by the 4 lanes of a group (q = lane & 3, all 4
+// lanes active, one face per group), with hardware reciprocals.  Every closest
+// pair of a segment and a triangle is one of: an end point and its projection
+// into the plane when that falls inside the triangle; the segment and an
+// edge; a crossing of the triangle (distance 0); and where several pairs are
+// closest (a segment parallel to the plane), one of these is among them.
+// Lane q < 3 takes the segment against edge q (a b, b c, c a) and a point
+// candidate: end point p0 (q = 0), p1 (q = 1), or the crossing of the plane
+// (q = 2).  The group's minimum, in segment_triangle's order (end points,
+// edges, with a crossing inside the triangle winning outright) and first on
+// ties, gives the closest pair; lane 0 moves the face.
+__device__ void capsule_push_lanes(float4 *xw, uint2 f, V3 p0, V3 p1, float r, int q)
+{
+    const int ia = (int)(f.x & 0xffffu), ib = (int)(f.x >> 16), ic = (int)f.y;
+    float4 pa = xw[ia], pb = xw[ib], pc = xw[ic];
+    const V3 a = v3(pa), b = v3(pb), c = v3(pc);
+    const V3 ab = b - a, ac = c - a, dir = p1 - p0;
+    // segment against edge q (Ericson 2005, Sec. 5.1.9, clamped, as selects)
+    const V3 e0 = q == 0 ? a : q == 1 ? b : c, e1 = q == 0 ? b : q == 1 ? c : a;
+    const V3 d2v = e1 - e0, rv = p0 - e0;
+    const float sa = dot(dir, dir), se = dot(d2v, d2v), sf = dot(d2v, rv), sc = dot(dir, rv),
+                sb = dot(dir, d2v);
+    const float ia_ = __builtin_amdgcn_rcpf(sa), ie_ = __builtin_amdgcn_rcpf(se);
+    const float den = sa * se - sb * sb;
+    float ss = den > 0.f ? fminf(fmaxf((sb * sf - sc * se) * __builtin_amdgcn_rcpf(den), 0.f), 1.f)
+                         : 0.f;
+    float tt = (sb * ss + sf) * ie_;
+    const float s_lo = fminf(fmaxf(-sc * ia_, 0.f), 1.f), s_hi = fminf(fmaxf((sb - sc) * ia_, 0.f), 1.f);
+    ss = tt < 0.f ? s_lo : tt > 1.f ? s_hi : ss;
+    tt = fminf(fmaxf(tt, 0.f), 1.f);
+    const bool pa_deg = sa <= 1e-30f, pe_deg = se <= 1e-30f;
+    ss = pa_deg ? 0.f : pe_deg ? s_lo : ss;
+    tt = pa_deg ? (pe_deg ? 0.f : fminf(fmaxf(sf * ie_, 0.f), 1.f)) : pe_deg ? 0.f : tt;
+    const V3 ps = p0 + ss * dir, pe = e0 + tt * d2v;
+    const float d2_edge = dot(pe - ps, pe - ps);
+    const V3 bary_edge = q == 0 ? V3{1.f - tt, tt, 0.f} : q == 1 ? V3{0.f, 1.f - tt, tt}
+                                                              : V3{tt, 0.f, 1.f - tt};
+    // point candidate: the projection of x into the plane, inside the triangle
+    const V3 n = cross(ab, ac);
+    const float nn = dot(n, n), inv_nn = __builtin_amdgcn_rcpf(nn);
+    const float h0 = dot(p0 - a, n), h1 = dot(p1 - a, n);
+    const bool crosses = h0 != h1 && ((h0 <= 0.f) != (h1 <= 0.f) || h0 == 0.f);
+    const float tc = h0 != h1 ? h0 * __builtin_amdgcn_rcpf(h0 - h1) : 0.f;
+    const V3 x = q == 0 ? p0 : q == 1 ? p1 : p0 + tc * dir;
+    const V3 ax = x - a;
+    const float d00 = dot(ab, ab), d01 = dot(ab, ac), d11 = dot(ac, ac);
+    const float d20 = dot(ax, ab), d21 = dot(ax, ac), ib_ = __builtin_amdgcn_rcpf(d00 * d11 - d01 * d01);
+    const float v = (d11 * d20 - d01 * d21) * ib_, w = (d00 * d21 - d01 * d20) * ib_;
+    const float u = 1.f - v - w;
+    const bool inside = nn > 0.f && u >= 0.f && v >= 0.f && w >= 0.f;
+    const float h = dot(ax, n);
+    const float d2_point = q == 2 ? (crosses && inside ? -1.f : 3.0e38f)
+                                  : (inside ? h * h * inv_nn : 3.0e38f);
+    // this lane's best in order (point candidates 0, 1 come before the edges,
+    // the crossing after them), then the group's
+    const int k_point = q == 2 ? 5 : q, k_edge = 2 + q;
+    const bool point_first = q == 2 ? d2_point < 0.f : true;
+    const bool take_point = point_first ? !(d2_edge < d2_point) : d2_point < d2_edge;
+    float best = take_point ? d2_point : d2_edge;
+    int best_k = take_point ? k_point : k_edge;
+    if (q == 3) {
+        best = 3.0e38f;
+        best_k = 7;
+    }
+#pragma unroll
+    for (int m = 1; m < 4; m <<= 1) {
+        const float ob = __shfl_xor(best, m, 4);
+        const int ok = __shfl_xor(best_k, m, 4);
+        if (ob < best || (ob == best && ok < best_k)) {   // a crossing's -1 is below all
+            best = ob;
+            best_k = ok;
+        }
+    }
+    // the winner's lane and candidate
+    const int src = (int)(__lane_id() & ~3u) |
+                    (best_k < 2 ? best_k : best_k <= 4 ? best_k - 2 : best_k == 5 ? 2 : 3);
+    const bool point_won = best_k < 2 || best_k == 5;
+    const V3 my_bary = point_won ? V3{u, v, w} : bary_edge, my_s = point_won ? x : ps;
+    const V3 bw = {__shfl(my_bary.x, src), __shfl(my_bary.y, src), __shfl(my_bary.z, src)};
+    const V3 sw = {__shfl(my_s.x, src), __shfl(my_s.y, src), __shfl(my_s.z, src)};
+    const float d2 = best_k == 5 ? 0.f : best;
+    if (q != 0 || !(d2 < r * r))
+        return;
+    const float d = __builtin_amdgcn_sqrtf(d2);
+    V3 nrm;
+    if (d > 1e-12f) {
+        const V3 y = bw.x * a + bw.y * b + bw.z * c;
+        nrm = __builtin_amdgcn_rcpf(d) * (y - sw);
+    } else {
+        if (!(nn > 0.f))
+            return;
+        nrm = __builtin_amdgcn_rsqf(nn) * n;
+    }
+    const float dn = pa.w * bw.x * bw.x + pb.w * bw.y * bw.y + pc.w * bw.z * bw.z;
+    if (!(dn > kMinDenominator))
+        return;
+    const float k = -(d - r) * __builtin_amdgcn_rcpf(dn);
+    const float ka = pa.w * bw.x * k, kb = pb.w * bw.y * k, kc = pc.w * bw.z * k;
+    pa.x += ka * nrm.x;
+    pa.y += ka * nrm.y;
+    pa.z += ka * nrm.z;
+    pb.x += kb * nrm.x;
+    pb.y += kb * nrm.y;
+    pb.z += kb * nrm.z;
+    pc.x += kc * nrm.x;
+    pc.y += kc * nrm.y;
+    pc.z += kc * nrm.z;
     xw[ia] = pa;
     xw[ib] = pb;
     xw[ic] = pc;
@@ -1006,8 +1143,10 @@ __device__ __forceinline__ void step_reg_body(StepArgs A)
     const int R0 = R < 32 ? R : 32;
     const int tools = A.num_tools;
     const int F = CAPSULE ? md.num_faces : 0;
-    const RegLdsLayout L = reg_lds_layout(VS, CAPSULE ? tools * F : 0);
-    uint8_t *fflag = smem + L.faces;   // capsules: [tools][F] candidate flags
+    const int FC = CAPSULE ? md.num_face_colours : 0;
+    const CapsuleFaceLayout FL = capsule_face_layout(F, FC);
+    const RegLdsLayout L = reg_lds_layout(VS, CAPSULE ? tools * (int)FL.total : 0);
+    uint8_t *faces_lds = smem + L.faces;   // capsules: [tools] candidate faces
     float4 *xw = reinterpret_cast<float4 *>(smem + L.xw);
     float *vel = reinterpret_cast<float *>(smem + L.vel);      // [3][VS]
     float *prev = reinterpret_cast<float *>(smem + L.prev);    // [3][VS]
@@ -1154,20 +1293,27 @@ __device__ __forceinline__ void step_reg_body(StepArgs A)
         // contact candidates on the start-of-step positions
         cand = 0u;
         if constexpr (CAPSULE) {
-            // faces with a free corner closer than 2r to the axis (Sec. III-A.3);
+            // faces with a free corner closer than 2r to the axis (Sec. III-A.3),
+            // as 64-bit flag words (a wave's 64 consecutive faces per word);
             // bit t of cand: this thread flagged a face of tool t
             for (int t = 0; t < tools; ++t) {
-                const float4 c0 = tool_c[2 * t], c1 = tool_c[2 * t + 1];
+                const V3 c0 = v3(tool_c[2 * t]), c1 = v3(tool_c[2 * t + 1]);
                 const float r = t == 0 ? A.tool_radius[0] : A.tool_radius[1];
+                uint64_t *flags = reinterpret_cast<uint64_t *>(faces_lds + t * FL.total + FL.flags);
                 for (int j = tid; j < F; j += B) {
                     const uint2 f = md.faces[j];
                     const float4 pa = xw[md.slot_of[f.x & 0xffffu]], pb = xw[md.slot_of[f.x >> 16]],
                                  pc = xw[md.slot_of[f.y]];
-                    V3 bary, sp;
-                    const bool flag = (pa.w > 0.f || pb.w > 0.f || pc.w > 0.f) &&
-                                      segment_triangle(v3(c0), v3(c1), v3(pa), v3(pb), v3(pc), bary,
-                                                       sp) < 4.f * r * r;
-                    fflag[t * F + j] = flag ? 1 : 0;
+                    bool flag = (pa.w > 0.f || pb.w > 0.f || pc.w > 0.f) &&
+                                !face_beyond(c0, c1, v3(pa), v3(pb), v3(pc), 2.f * r);
+                    if (flag) {
+                        V3 bary, sp;
+                        flag = segment_triangle(c0, c1, v3(pa), v3(pb), v3(pc), bary, sp) <
+                               4.f * r * r;
+                    }
+                    const uint64_t word = __ballot(flag);
+                    if (lane == 0)
+                        flags[(j - lane) >> 6] = word;
                     cand |= flag ? 1u << t : 0u;
                 }
             }
@@ -1182,6 +1328,40 @@ __device__ __forceinline__ void step_reg_body(StepArgs A)
             }
         }
         const bool any_contact = block_any(cand != 0u, scratch + 32, wave, lane, num_waves);
+        if constexpr (CAPSULE) {
+            // one wave per tool lists the flagged faces colour by colour, as
+            // the LDS slots of their corners, with the colour bounds
+            for (int t = 0; t < tools; ++t)
+                if (wave == (t & (num_waves - 1))) {
+                    uint8_t *base = faces_lds + t * FL.total;
+                    const uint64_t *flags = reinterpret_cast<const uint64_t *>(base + FL.flags);
+                    uint32_t *list_ab = reinterpret_cast<uint32_t *>(base + FL.ab);
+                    uint16_t *list_c = reinterpret_cast<uint16_t *>(base + FL.c);
+                    uint16_t *bounds = reinterpret_cast<uint16_t *>(base + FL.bounds);
+                    int n = 0;
+                    for (int c = 0; c < FC; ++c) {
+                        if (lane == 0)
+                            bounds[c] = (uint16_t)n;
+                        const int hi = md.face_ptr[c + 1];
+                        for (int j0 = any_contact ? md.face_ptr[c] : hi; j0 < hi; j0 += 64) {
+                            const int j = j0 + lane;
+                            const bool f = j < hi && ((flags[j >> 6] >> (j & 63)) & 1u);
+                            const uint64_t m = __ballot(f);
+                            if (f) {
+                                const int at = n + __popcll(m & __lanemask_lt());
+                                const uint2 fc = md.faces[j];
+                                list_ab[at] = (uint32_t)md.slot_of[fc.x & 0xffffu] |
+                                              (uint32_t)md.slot_of[fc.x >> 16] << 16;
+                                list_c[at] = (uint16_t)md.slot_of[fc.y];
+                            }
+                            n += __popcll(m);
+                        }
+                    }
+                    if (lane == 0)
+                        bounds[FC] = (uint16_t)n;
+                }
+            __syncthreads();
+        }
 
         for (int sub = 0; sub < A.substeps; ++sub) {
             // predict velocity and position (Alg. 1); pinned particles stay put
@@ -1211,19 +1391,27 @@ __device__ __forceinline__ void step_reg_body(StepArgs A)
                                           barriers, bank0, bank1, alpha_d, alpha_v);
                 if (CAPSULE && any_contact) {
                     // flagged faces pushed out of every capsule, face colour by
-                    // face colour (faces of one colour share no particle)
+                    // face colour (faces of one colour share no particle); a
+                    // colour without flagged faces costs no barrier, and the
+                    // colours rotate over the waves
                     for (int t = 0; t < tools; ++t) {
                         const V3 c0 = v3(tool_c[2 * t]), c1 = v3(tool_c[2 * t + 1]);
                         const float rt = t == 0 ? A.tool_radius[0] : A.tool_radius[1];
-                        for (int c = 0; c < md.num_face_colours; ++c) {
-                            const int end = md.face_ptr[c + 1];
-                            for (int j = md.face_ptr[c] + tid; j < end; j += B)
-                                if (fflag[t * F + j]) {
-                                    const uint2 f = md.faces[j];
-                                    const uint32_t sa = md.slot_of[f.x & 0xffffu],
-                                                   sb = md.slot_of[f.x >> 16], sc = md.slot_of[f.y];
-                                    capsule_push(xw, make_uint2(sa | sb << 16, sc), c0, c1, rt);
-                                }
+                        const uint8_t *base = faces_lds + t * FL.total;
+                        const uint32_t *list_ab = reinterpret_cast<const uint32_t *>(base + FL.ab);
+                        const uint16_t *list_c = reinterpret_cast<const uint16_t *>(base + FL.c);
+                        const uint16_t *bounds = reinterpret_cast<const uint16_t *>(base + FL.bounds);
+                        for (int c = 0; c < FC; ++c) {
+                            const int lo = __builtin_amdgcn_readfirstlane(bounds[c]);
+                            const int hi = __builtin_amdgcn_readfirstlane(bounds[c + 1]);
+                            if (lo == hi)
+                                continue;
+                            // face k of the colour: wave (k + c) mod waves, the
+                            // 4-lane group k / waves of that wave
+                            const int first = (lane >> 2) * num_waves + ((wave - c) & (num_waves - 1));
+                            for (int j = lo + first; j < hi; j += 16 * num_waves)
+                                capsule_push_lanes(xw, make_uint2(list_ab[j], list_c[j]), c0, c1, rt,
+                                                   lane & 3);
                             __syncthreads();
                         }
                     }
@@ -1293,26 +1481,18 @@ __device__ __forceinline__ void step_reg_body(StepArgs A)
     // contact candidates of the last step as ascending mesh ids, per
     // environment: flag them by mesh id in a byte map (the start-of-substep
     // positions are no longer needed), then compact in mesh order; capsules:
-    // the number of candidate faces per tool and no particle list
+    // the number of candidate faces per tool of the last step (its list's
+    // length) and no particle list
     uint8_t *flag_of = reinterpret_cast<uint8_t *>(prev);
     const int kmax = (V + B - 1) / B;
     if constexpr (CAPSULE) {
         for (int t = 0; t < tools; ++t) {
-            int mine = 0;
-            for (int j = tid; j < F; j += B)
-                mine += fflag[t * F + j];
-            const float total = wave_sum((float)mine);
-            if (lane == 0)
-                scratch[wave] = (uint32_t)total;
-            __syncthreads();
-            int n = 0;
-            for (int w = 0; w < num_waves; ++w)
-                n += (int)scratch[w];
+            const uint16_t *bounds =
+                reinterpret_cast<const uint16_t *>(faces_lds + t * FL.total + FL.bounds);
             for (int i = tid; i < V; i += B)
                 A.contacts[(size_t)t * NP + off[0] + i] = -1;
             if (tid == 0 && writes[0])
-                A.contact_counts[env[0] * tools + t] = n;
-            __syncthreads();
+                A.contact_counts[env[0] * tools + t] = A.num_steps > 0 ? (int)bounds[FC] : 0;
         }
     }
 #pragma unroll
@@ -1387,9 +1567,12 @@ __global__ void __launch_bounds__(1024) xpbd_step_reg_kernel(StepArgs A)
 
 // Capsule tools: the face push-out's closest-point search needs more
 // registers than 1024-thread workgroups leave a lane, so this instantiation
-// is bounded to 512 threads (two waves per SIMD and workgroup).
+// is bounded to 512 threads (two waves per SIMD and workgroup); with one
+// multiplier bank it is held to the 128 registers that keep four 256-thread
+// workgroups on a CU.
 template <int NB>
-__global__ void __launch_bounds__(512) xpbd_step_reg_kernel_capsules(StepArgs A)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 4 : 2)))
+xpbd_step_reg_kernel_capsules(StepArgs A)
 {
     step_reg_body<NB, 1, kRegCapsules, false>(A);
 }

@@ -331,14 +331,18 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
         return fail(XPBD_E_CAPACITY, "capsule tools run one environment per workgroup");
     const bool reg_possible = params->solver_variant != XPBD_VARIANT_LDS && !jacobi && pow2_block;
     // LDS of a register-variant workgroup of G environments of a mesh (capsule
-    // tools add a candidate flag per surface face and tool)
+    // tools add their candidate faces: flags and a compacted list per tool)
     const int face_tools = capsules ? params->num_tools : 0;
-    auto reg_lds = [&](const PreparedMesh &pm, int G) {
-        return xpbd::reg_lds_layout(G * pm.num_vertices, face_tools * pm.num_faces()).total;
+    auto face_bytes = [&](const PreparedMesh &pm) {
+        return face_tools *
+               (int32_t)xpbd::capsule_face_layout(pm.num_faces(), pm.num_face_colours).total;
     };
-    int32_t max_faces = 0;
+    auto reg_lds = [&](const PreparedMesh &pm, int G) {
+        return xpbd::reg_lds_layout(G * pm.num_vertices, face_bytes(pm)).total;
+    };
+    int32_t max_face_bytes = 0;
     for (const auto &pm : prepared)
-        max_faces = std::max(max_faces, pm.num_faces());
+        max_face_bytes = std::max(max_face_bytes, face_bytes(pm));
     if (reg_possible && prepared.size() == 1 && params->block_size == 0) {
         // Occupancy model: a round (a lane's constraint of one colour, then
         // the colour's barrier) costs about the same whatever B and G, and a
@@ -391,7 +395,7 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
                 const bool fits = worst <= xpbd::kMaxRounds && G * vmax <= 16 * B &&
                                   (!capsules || B <= xpbd::kMaxCapsuleBlock) &&
                                   G * vmax <= 16384 && B / 64 <= 16 &&
-                                  xpbd::reg_lds_layout(G * vmax, face_tools * max_faces).total <=
+                                  xpbd::reg_lds_layout(G * vmax, max_face_bytes).total <=
                                       (uint32_t)lds_limit;
                 if (fits) {
                     use_registers = true;
@@ -429,7 +433,7 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     uint32_t lds = stage ? lds_staged : lds_global;
     if (use_registers) {
         stage = false;
-        lds = xpbd::reg_lds_layout(reg_group * vmax, face_tools * max_faces).total;
+        lds = xpbd::reg_lds_layout(reg_group * vmax, max_face_bytes).total;
         // the round records hold 16-bit particle fields: LDS byte offsets with
         // one environment per workgroup (the LDS limit keeps them below 65536)
         if (reg_group == 1 && 16 * ((int64_t)vmax + 1) > 0xffff)

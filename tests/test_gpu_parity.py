@@ -530,6 +530,41 @@ def test_jacobi_follows_the_oracle(xp, oracle_lib, case):
     assert max(np.abs(plain[e].x - refs[e].x).max() for e in envs) > K.POS_TOL
 
 
+def test_capsule_full_size_sampled(xp, oracle_lib):
+    """Capsule tools on the benchmark's shape: 1024 environments of the
+    16x10x4 slab under the colouring capped at 256 members (53 rounds, two
+    multiplier banks), one launch per step for 30 steps.  16 sampled
+    environments: the first step's candidate-face counts equal the oracle's,
+    the positions follow its capsule driver."""
+    steps = 30
+    wl = W.batch_workload(1024, seed=4, num_steps=steps)
+    sample = list(range(3, 1024, 64))
+    caps = W.capsule_path(steps, wl.num_envs, wl.seed)
+    m = wl.meshes[0]
+    om = oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass, m.tets,
+                                 colouring=oracle_lib.COLOURING_CAPPED)
+    op = K.oracle_params(oracle_lib, wl)
+    refs = [oracle_lib.run_env_capsule(om, wl.compliance[e], op, caps[:, e].astype(np.float64),
+                                       steps) for e in sample]
+    assert sum(int(r.contact_count[0, 0]) for r in refs) > 0
+    p = K.lib_params(xp, wl)
+    p.tool_shape = xp.TOOL_CAPSULE
+    p.colouring = 3   # XPBD_COLOURING_CAPPED
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b:
+        info = b.info()
+        assert info["solver_variant"] == xp.VARIANT_REGISTERS and info["lambda_banks"] == 2
+        b.step(1, caps[:1])
+        counts = b.read(xp.FIELD_CONTACT_COUNTS).reshape(wl.num_envs, 1)
+        assert [int(counts[e, 0]) for e in sample] == [int(r.contact_count[0, 0]) for r in refs]
+        for s in range(1, steps):
+            b.step(1, caps[s:s + 1])
+        x = b.positions()
+        offs = b.env_offsets
+    worst = max(K.max_position_error(K.env_block(x, offs, e), refs[n].x)
+                for n, e in enumerate(sample))
+    assert worst <= K.POS_TOL, f"max position error {worst:.3e} m"
+
+
 @pytest.mark.parametrize("case", ["single", "batch-3-envs", "single-lds", "batch-3-envs-lds",
                                   "jacobi"])
 def test_capsule_tools_follow_the_oracle(xp, oracle_lib, case):
