@@ -230,11 +230,14 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
 /*
  * Advance every environment by num_steps steps in one kernel launch.
  * tool_pos: float [num_steps][N][num_tools][3] sphere centres (capsules: [6],
- * the two axis ends), host or device, ignored when num_tools == 0.  Asynchronous on the batch's stream
- * (a host tool_pos is copied before the call returns).  num_steps == 0 does
- * nothing.
+ * the two axis ends), host or device, ignored when num_tools == 0;
+ * tool_pos_bytes: its size in bytes, which must equal what the steps read
+ * (num_steps * N * num_tools * 3 or 6 * 4), else XPBD_E_ARG and no work.
+ * Asynchronous on the batch's stream (a host tool_pos is copied before the
+ * call returns).  num_steps == 0 does nothing.
  */
-xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos);
+xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos,
+                      size_t tool_pos_bytes);
 
 /*
  * Copy a field (XPBD_FIELD_*) into dst (host or device), dst_bytes must equal
@@ -272,8 +275,9 @@ xpbd_status xpbd_field_bytes(const xpbd_batch *b, int32_t field, size_t *bytes);
  * the first candidate is the library's default (all four 0).  Each candidate
  * is a batch created from the given meshes, environments and compliances
  * (the other fields of *params are kept, flags cleared) on hip_stream,
- * stepped once untimed and then num_steps times with tool_pos (as in
- * xpbd_step, from the rest state) between two events, and destroyed;
+ * stepped once untimed (on the first step's poses) and then num_steps times
+ * with tool_pos (tool_pos_bytes as in xpbd_step for num_steps steps; from the
+ * rest state) between two events, and destroyed;
  * candidates the library rejects with XPBD_E_CAPACITY are skipped.  On
  * success the four fields of *params hold the fastest candidate,
  * ms_per_step[0] its time per step and ms_per_step[1] the default's (host
@@ -284,7 +288,7 @@ xpbd_status xpbd_field_bytes(const xpbd_batch *b, int32_t field, size_t *bytes);
 xpbd_status xpbd_autotune(const xpbd_mesh *meshes, int32_t num_meshes, const int32_t *env_mesh,
                           int32_t num_envs, const float *compliance, xpbd_params *params,
                           void *hip_stream, int32_t num_steps, const float *tool_pos,
-                          float *ms_per_step);
+                          size_t tool_pos_bytes, float *ms_per_step);
 
 /*
  * The launch configuration a batch runs with (what the library chose for

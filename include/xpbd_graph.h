@@ -36,13 +36,14 @@ typedef struct xpbd_graph xpbd_graph;
 /*
  * One step of xpbd_step (learned == NULL) or of xpbd_step_learned (net and
  * *learned as for that call) with the tool poses read from tool_pos (device
- * float [N][num_tools][3] or [6] for capsules, at every replay).
- * XPBD_E_ARG: null pointers, tool_pos not in device memory, or what the
- * step itself rejects.
+ * float [N][num_tools][3] or [6] for capsules, at every replay;
+ * tool_pos_bytes its size, one step's poses as in xpbd_step).
+ * XPBD_E_ARG: null pointers, tool_pos not in device memory or of another
+ * size, or what the step itself rejects.
  */
 xpbd_status xpbd_step_graph_create(xpbd_batch *b, const xpbd_mlp *net,
                                    const xpbd_learned_params *learned, const float *tool_pos,
-                                   xpbd_graph **out);
+                                   size_t tool_pos_bytes, xpbd_graph **out);
 
 /*
  * One RL step (include/xpbd_rl.h): xpbd_rl_step when learned is NULL, else

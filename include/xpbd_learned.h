@@ -157,14 +157,15 @@ typedef struct {
 /* Advance every environment by num_steps steps one substep at a time: the
  * prediction and the features (with net's normalisation), the network's correction
  * when apply_correction is set, then the sweeps of xpbd_learned_params.
- * tool_pos as in xpbd_step.  net may be NULL only without correction and
+ * tool_pos and tool_pos_bytes as in xpbd_step.  net may be NULL only without correction and
  * without recording (plain sweeps with the residual check).  Needs the
  * register variant with one environment per workgroup (XPBD_E_CAPACITY
  * otherwise).  XPBD_F_RESIDUAL and XPBD_F_LAMBDA apply to the last substep.
  * With apply_correction 0, min_iterations = max_iterations = the batch's
  * iterations and no recording, the result equals xpbd_step's bit for bit. */
 xpbd_status xpbd_step_learned(xpbd_batch *batch, const xpbd_mlp *net, int32_t num_steps,
-                              const float *tool_pos, const xpbd_learned_params *params);
+                              const float *tool_pos, size_t tool_pos_bytes,
+                              const xpbd_learned_params *params);
 
 /* Bytes of the device array that holds the allocation-free step's workspace
  * (80 MiB; one copy per device the library runs on, held until the process
@@ -178,7 +179,7 @@ xpbd_status xpbd_step_learned(xpbd_batch *batch, const xpbd_mlp *net, int32_t nu
  * per particle, 4 B per mesh, each part 256-byte aligned) taken from a
  * fixed device array of XPBD_NOALLOC_SCRATCH_BYTES instead of buffers the
  * batch allocates; no hipMalloc, hipFree or other allocation.  tool_pos must
- * be device memory.  The batch's device must be current.
+ * be device memory (tool_pos_bytes as in xpbd_step).  The batch's device must be current.
  * Errors: XPBD_E_CAPACITY when the workspace exceeds the array (about 1.09 M
  * particles with the correction), XPBD_E_ARG for host tool poses or another
  * device, and every error of xpbd_step_learned; no device work is done after
@@ -187,7 +188,8 @@ xpbd_status xpbd_step_learned(xpbd_batch *batch, const xpbd_mlp *net, int32_t nu
  * that overlap on one device race, so callers serialise them (one stream, or
  * events between streams). */
 xpbd_status xpbd_step_learned_noalloc(xpbd_batch *batch, const xpbd_mlp *net, int32_t num_steps,
-                                      const float *tool_pos, const xpbd_learned_params *params);
+                                      const float *tool_pos, size_t tool_pos_bytes,
+                                      const xpbd_learned_params *params);
 
 
 #ifdef __cplusplus

@@ -127,6 +127,13 @@ struct GraspArgs {
     float radius;        // r_l
 };
 
+// Bytes of num_steps steps of tool poses ([num_steps][N][tools][3], or [6]
+// for capsules), and the check of a caller's declared byte count against it
+// (XPBD_E_ARG on a mismatch or a NULL buffer when the batch has tools).
+size_t tool_bytes(const xpbd_batch *b, int32_t num_steps);
+xpbd_status check_tool_bytes(const xpbd_batch *b, int32_t num_steps, const float *tool_pos,
+                             size_t tool_pos_bytes);
+
 // num_steps steps with the tool poses in device memory ([num_steps][N][tools][3]
 // or [6] for capsules); grasp is null or names the grasp state (register variant).
 xpbd_status run_step(xpbd_batch *b, int32_t num_steps, const float *tools_dev,

@@ -78,13 +78,16 @@ extern "C" {
 
 xpbd_status xpbd_step_graph_create(xpbd_batch *b, const xpbd_mlp *net,
                                    const xpbd_learned_params *learned, const float *tool_pos,
-                                   xpbd_graph **out)
+                                   size_t tool_pos_bytes, xpbd_graph **out)
 {
     g_error.clear();
     if (!b || !out)
         return fail(XPBD_E_ARG, "batch and out must not be NULL");
     *out = nullptr;
-    if (b->params.num_tools > 0 && (!tool_pos || !is_device_pointer(tool_pos)))
+    xpbd_status checked = xpbd::check_tool_bytes(b, 1, tool_pos, tool_pos_bytes);
+    if (checked != XPBD_OK)
+        return checked;
+    if (b->params.num_tools > 0 && !is_device_pointer(tool_pos))
         return fail(XPBD_E_ARG, "tool_pos must be device memory");
     if (learned) {
         xpbd_status st = xpbd::check_learned(b, net, learned);
@@ -92,9 +95,11 @@ xpbd_status xpbd_step_graph_create(xpbd_batch *b, const xpbd_mlp *net,
             st = xpbd::learned_workspace(b, learned);
         if (st != XPBD_OK)
             return st;
-        return capture(b, [&] { return xpbd_step_learned(b, net, 1, tool_pos, learned); }, out);
+        return capture(
+            b, [&] { return xpbd_step_learned(b, net, 1, tool_pos, tool_pos_bytes, learned); },
+            out);
     }
-    return capture(b, [&] { return xpbd_step(b, 1, tool_pos); }, out);
+    return capture(b, [&] { return xpbd_step(b, 1, tool_pos, tool_pos_bytes); }, out);
 }
 
 xpbd_status xpbd_rl_graph_create(xpbd_batch *b, const xpbd_policy *policy,

@@ -316,7 +316,8 @@ xpbd_status xpbd_axis_neighbours(const xpbd_mesh *mesh, int32_t *out)
 }
 
 xpbd_status xpbd_step_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_steps,
-                              const float *tool_pos, const xpbd_learned_params *lp)
+                              const float *tool_pos, size_t tool_pos_bytes,
+                              const xpbd_learned_params *lp)
 {
     g_error.clear();
     if (!b || !lp)
@@ -328,12 +329,13 @@ xpbd_status xpbd_step_learned(xpbd_batch *b, const xpbd_mlp *net, int32_t num_st
         return st;
     if (num_steps == 0)
         return XPBD_OK;
+    st = xpbd::check_tool_bytes(b, num_steps, tool_pos, tool_pos_bytes);
+    if (st != XPBD_OK)
+        return st;
     const int tools = b->params.num_tools;
     const float *tools_dev = nullptr;
     if (tools > 0) {
-        if (!tool_pos)
-            return fail(XPBD_E_ARG, "tool_pos is NULL but the batch has %d tools", tools);
-        const size_t bytes = (size_t)num_steps * b->num_envs * tools * 3 * sizeof(float);
+        const size_t bytes = tool_pos_bytes;
         if (is_device_pointer(tool_pos)) {
             tools_dev = tool_pos;
         } else {

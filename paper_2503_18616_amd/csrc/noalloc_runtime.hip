@@ -73,7 +73,8 @@ __global__ void chunk_table_kernel(const xpbd::MeshDev *__restrict__ meshes, int
 extern "C" {
 
 xpbd_status xpbd_step_learned_noalloc(xpbd_batch *b, const xpbd_mlp *net, int32_t num_steps,
-                                      const float *tool_pos, const xpbd_learned_params *lp)
+                                      const float *tool_pos, size_t tool_pos_bytes,
+                                      const xpbd_learned_params *lp)
 {
     g_error.clear();
     if (!b || !lp)
@@ -83,8 +84,11 @@ xpbd_status xpbd_step_learned_noalloc(xpbd_batch *b, const xpbd_mlp *net, int32_
     xpbd_status st = xpbd::check_learned(b, net, lp);
     if (st != XPBD_OK)
         return st;
+    st = xpbd::check_tool_bytes(b, num_steps, tool_pos, tool_pos_bytes);
+    if (st != XPBD_OK)
+        return st;
     const int tools = b->params.num_tools;
-    if (tools > 0 && (!tool_pos || !is_device_pointer(tool_pos)))
+    if (tools > 0 && num_steps > 0 && !is_device_pointer(tool_pos))
         return fail(XPBD_E_ARG, "tool_pos must be device memory (host poses would need a "
                     "staging buffer)");
     int device = 0;

@@ -38,7 +38,7 @@ extern "C" {
 xpbd_status xpbd_autotune(const xpbd_mesh *meshes, int32_t num_meshes, const int32_t *env_mesh,
                           int32_t num_envs, const float *compliance, xpbd_params *params,
                           void *hip_stream, int32_t num_steps, const float *tool_pos,
-                          float *ms_per_step)
+                          size_t tool_pos_bytes, float *ms_per_step)
 {
     using xpbd::fail;
     xpbd::g_error.clear();
@@ -74,10 +74,11 @@ xpbd_status xpbd_autotune(const xpbd_mesh *meshes, int32_t num_meshes, const int
             break;
         }
         float ms = 0.0f;
-        st = xpbd_step(b, 1, tool_pos);
+        // one untimed step on the first step's poses, then the timed steps
+        st = xpbd_step(b, 1, tool_pos, tool_pos_bytes / (size_t)num_steps);
         hipError_t e = hipSuccess;
         if (st == XPBD_OK && (e = hipEventRecord(t0, stream)) == hipSuccess) {
-            st = xpbd_step(b, num_steps, tool_pos);
+            st = xpbd_step(b, num_steps, tool_pos, tool_pos_bytes);
             if (st == XPBD_OK && (e = hipEventRecord(t1, stream)) == hipSuccess &&
                 (e = hipEventSynchronize(t1)) == hipSuccess)
                 e = hipEventElapsedTime(&ms, t0, t1);

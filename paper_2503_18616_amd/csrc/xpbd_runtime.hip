@@ -1024,7 +1024,8 @@ xpbd_status xpbd_create_batch(const xpbd_mesh *meshes, int32_t num_meshes,
     return XPBD_OK;
 }
 
-xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
+xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos,
+                      size_t tool_pos_bytes)
 {
     g_error.clear();
     if (!b)
@@ -1033,13 +1034,13 @@ xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
         return fail(XPBD_E_ARG, "num_steps must be >= 0");
     if (num_steps == 0)
         return XPBD_OK;
+    const xpbd_status checked = xpbd::check_tool_bytes(b, num_steps, tool_pos, tool_pos_bytes);
+    if (checked != XPBD_OK)
+        return checked;
     const int tools = b->params.num_tools;
     const float *tools_dev = nullptr;
     if (tools > 0) {
-        if (!tool_pos)
-            return fail(XPBD_E_ARG, "tool_pos is NULL but the batch has %d tools", tools);
-        const size_t per_tool = b->params.tool_shape == XPBD_TOOL_CAPSULE ? 6 : 3;
-        const size_t bytes = (size_t)num_steps * b->num_envs * tools * per_tool * sizeof(float);
+        const size_t bytes = tool_pos_bytes;
         if (is_device_pointer(tool_pos)) {
             tools_dev = tool_pos;
         } else {
@@ -1061,6 +1062,29 @@ xpbd_status xpbd_step(xpbd_batch *b, int32_t num_steps, const float *tool_pos)
 }
 
 }  // extern "C"
+
+size_t xpbd::tool_bytes(const xpbd_batch *b, int32_t num_steps)
+{
+    const size_t per_tool = b->params.tool_shape == XPBD_TOOL_CAPSULE ? 6 : 3;
+    const size_t tools = b->params.num_tools > 0 ? (size_t)b->params.num_tools : 0;
+    return (size_t)(num_steps > 0 ? num_steps : 0) * (size_t)b->num_envs * tools * per_tool *
+           sizeof(float);
+}
+
+xpbd_status xpbd::check_tool_bytes(const xpbd_batch *b, int32_t num_steps, const float *tool_pos,
+                                   size_t tool_pos_bytes)
+{
+    const int tools = b->params.num_tools;
+    if (tools <= 0 || num_steps <= 0)
+        return XPBD_OK;
+    if (!tool_pos)
+        return fail(XPBD_E_ARG, "tool_pos is NULL but the batch has %d tools", tools);
+    const size_t want = tool_bytes(b, num_steps);
+    if (tool_pos_bytes != want)
+        return fail(XPBD_E_ARG, "tool_pos holds %zu bytes; %d steps of %d environments with %d "
+                    "tools read %zu", tool_pos_bytes, num_steps, b->num_envs, tools, want);
+    return XPBD_OK;
+}
 
 // The launches of num_steps steps with the tool poses in device memory; the
 // RL-style step passes its grasp state (register variant only).

@@ -121,11 +121,11 @@ _lib.xpbd_create_batch.argtypes = [ctypes.POINTER(XpbdMesh), ctypes.c_int32, cty
                                    ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(XpbdParams),
                                    ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
 _lib.xpbd_step.restype = ctypes.c_int
-_lib.xpbd_step.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+_lib.xpbd_step.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]
 _lib.xpbd_autotune.restype = ctypes.c_int
 _lib.xpbd_autotune.argtypes = [ctypes.POINTER(XpbdMesh), ctypes.c_int32, ctypes.c_void_p,
                                ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                               ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+                               ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
 _lib.xpbd_read_state.restype = ctypes.c_int
 _lib.xpbd_read_state.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]
 _lib.xpbd_write_state.restype = ctypes.c_int
@@ -174,9 +174,10 @@ _lib.xpbd_mlp_destroy.argtypes = [_V]
 _lib.xpbd_axis_neighbours.restype = ctypes.c_int
 _lib.xpbd_axis_neighbours.argtypes = [ctypes.POINTER(XpbdMesh), _V]
 _lib.xpbd_step_learned.restype = ctypes.c_int
-_lib.xpbd_step_learned.argtypes = [_V, _V, ctypes.c_int32, _V, ctypes.POINTER(XpbdLearnedParams)]
+_lib.xpbd_step_learned.argtypes = [_V, _V, ctypes.c_int32, _V, ctypes.c_size_t,
+                                   ctypes.POINTER(XpbdLearnedParams)]
 _lib.xpbd_step_learned_noalloc.restype = ctypes.c_int
-_lib.xpbd_step_learned_noalloc.argtypes = [_V, _V, ctypes.c_int32, _V,
+_lib.xpbd_step_learned_noalloc.argtypes = [_V, _V, ctypes.c_int32, _V, ctypes.c_size_t,
                                            ctypes.POINTER(XpbdLearnedParams)]
 # bytes of the allocation-free learned step's device array
 NOALLOC_SCRATCH_BYTES = 80 << 20
@@ -197,6 +198,15 @@ def _check(status):
         raise XpbdError(status, xpbd_last_error())
 
 
+def _nbytes(a):
+    """Bytes of a numpy array or torch tensor (None -> 0)."""
+    if a is None:
+        return 0
+    if isinstance(a, np.ndarray):
+        return int(a.nbytes)
+    return int(a.numel()) * int(a.element_size())
+
+
 def _ptr(a):
     """Address of a contiguous numpy array or torch tensor (None -> NULL)."""
     if a is None:
@@ -210,12 +220,6 @@ def _ptr(a):
             raise ValueError("tensor must be contiguous")
         return a.data_ptr()
     raise TypeError(f"unsupported buffer type {type(a)}")
-
-
-def _nbytes(a):
-    if isinstance(a, np.ndarray):
-        return a.nbytes
-    return a.numel() * a.element_size()
 
 
 def _mesh_struct(rest_pos, inv_mass, tets, keep):
@@ -359,7 +363,7 @@ def xpbd_autotune(meshes, env_mesh, compliance, params: XpbdParams, num_steps, t
     s = default_stream() if stream is None else stream
     _check(_lib.xpbd_autotune(arr, len(meshes), env_mesh.ctypes.data, n, compliance.ctypes.data,
                               ctypes.byref(params), s or None, int(num_steps), _ptr(tool_pos),
-                              ms))
+                              _nbytes(tool_pos), ms))
     return float(ms[0]), float(ms[1])
 
 
@@ -369,7 +373,7 @@ def xpbd_step(batch, num_steps, tool_pos):
     The kernel reads exactly num_steps * N * tools * 3 floats, so the buffer's
     element count and dtype are checked here before the launch."""
     tool_pos = _check_tool_pos(batch, num_steps, tool_pos)
-    _check(_lib.xpbd_step(batch, int(num_steps), _ptr(tool_pos)))
+    _check(_lib.xpbd_step(batch, int(num_steps), _ptr(tool_pos), _nbytes(tool_pos)))
 
 
 def xpbd_set_flags(batch, flags):
@@ -599,7 +603,8 @@ def xpbd_step_learned(batch, net, num_steps, tool_pos, min_iterations, max_itera
                            float(threshold), int(record_substep), _ptr(record_features),
                            _ptr(record_targets), _ptr(iterations), float(stall_ratio),
                            _ptr(residuals))
-    _check(_lib.xpbd_step_learned(batch, net, int(num_steps), _ptr(tool_pos), ctypes.byref(lp)))
+    _check(_lib.xpbd_step_learned(batch, net, int(num_steps), _ptr(tool_pos), _nbytes(tool_pos),
+                                  ctypes.byref(lp)))
 
 
 def xpbd_step_learned_noalloc(batch, net, num_steps, tool_pos, min_iterations, max_iterations,
@@ -617,7 +622,7 @@ def xpbd_step_learned_noalloc(batch, net, num_steps, tool_pos, min_iterations, m
                            _ptr(record_targets), _ptr(iterations), float(stall_ratio),
                            _ptr(residuals))
     _check(_lib.xpbd_step_learned_noalloc(batch, net, int(num_steps), _ptr(tool_pos),
-                                          ctypes.byref(lp)))
+                                          _nbytes(tool_pos), ctypes.byref(lp)))
 
 
 class XpbdRlParams(ctypes.Structure):
@@ -722,7 +727,7 @@ def xpbd_rl_step_learned(batch, policy, params: XpbdRlParams, net, num_steps, to
 # captured steps (include/xpbd_graph.h)
 _lib.xpbd_step_graph_create.restype = ctypes.c_int
 _lib.xpbd_step_graph_create.argtypes = [_V, _V, ctypes.POINTER(XpbdLearnedParams), _V,
-                                        ctypes.POINTER(ctypes.c_void_p)]
+                                        ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]
 _lib.xpbd_rl_graph_create.restype = ctypes.c_int
 _lib.xpbd_rl_graph_create.argtypes = [_V, _V, ctypes.POINTER(XpbdRlParams), _V,
                                       ctypes.POINTER(XpbdLearnedParams), _V, _V, _V, _V, _V,
@@ -753,7 +758,7 @@ def xpbd_step_graph_create(batch, net, learned, tool_pos):
             raise ValueError("tool_pos must be a contiguous float32 device tensor of one step")
     h = ctypes.c_void_p()
     _check(_lib.xpbd_step_graph_create(batch, net, ctypes.byref(learned) if learned else None,
-                                       _ptr(tool_pos), ctypes.byref(h)))
+                                       _ptr(tool_pos), _nbytes(tool_pos), ctypes.byref(h)))
     return h.value
 
 

@@ -126,8 +126,12 @@ def test_graph_rejects_bad_arguments(xp):
         import ctypes
         h = ctypes.c_void_p()
         st = xp._lib.xpbd_step_graph_create(b.handle, None, None, host_tools.ctypes.data,
-                                            ctypes.byref(h))
+                                            host_tools.nbytes, ctypes.byref(h))
         assert st == xp.XPBD_E_ARG and "device memory" in xp.xpbd_last_error()
+        dev_tools = torch.from_numpy(host_tools).cuda()
+        st = xp._lib.xpbd_step_graph_create(b.handle, None, None, dev_tools.data_ptr(),
+                                            host_tools.nbytes - 4, ctypes.byref(h))
+        assert st == xp.XPBD_E_ARG and "bytes" in xp.xpbd_last_error()
         assert xp._lib.xpbd_graph_launch(None, 1) == xp.XPBD_E_ARG
         with b.step_graph(torch.from_numpy(host_tools).cuda()) as g:
             with pytest.raises(xp.XpbdError, match="times"):

@@ -7,6 +7,8 @@ start-of-step positions; against the FP64 trajectory they may differ only for
 particles whose distance to the sphere is within the trajectories' position
 error of the reach 2r).
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -170,6 +172,32 @@ def test_batch_parity_other_colourings(xp, oracle_lib, colouring):
     worst = max(K.max_position_error(K.env_block(x, offs, e), refs[n].x)
                 for n, e in enumerate(sample))
     assert worst <= K.POS_TOL, f"max position error {worst:.3e} m"
+
+
+def test_step_checks_the_pose_byte_count(xp):
+    """The C ABI's step calls take the byte count of the tool poses: a count
+    that differs from what the steps read (either way, host or device poses)
+    is XPBD_E_ARG and changes nothing; the exact count runs."""
+    import torch
+    wl = W.batch_workload(4, seed=0, num_steps=3)
+    tools = np.ascontiguousarray(wl.tools(3), dtype=np.float32)
+    dev = torch.from_numpy(tools).cuda()
+    lp = xp.XpbdLearnedParams(0, wl.iterations, wl.iterations, 0.0, -1, None, None, None, 0.0,
+                              None)
+    p = K.lib_params(xp, wl)
+    p.envs_per_group = 1   # what the learned step needs
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b:
+        x0 = b.positions()
+        for ptr in (tools.ctypes.data, dev.data_ptr()):
+            for nbytes in (tools.nbytes - 4, tools.nbytes + 4, 0):
+                assert xp._lib.xpbd_step(b.handle, 3, ptr, nbytes) == xp.XPBD_E_ARG
+                assert "bytes" in xp.xpbd_last_error()
+                assert xp._lib.xpbd_step_learned(b.handle, None, 3, ptr, nbytes,
+                                                 ctypes.byref(lp)) == xp.XPBD_E_ARG
+        assert xp._lib.xpbd_step(b.handle, 3, None, tools.nbytes) == xp.XPBD_E_ARG
+        assert np.array_equal(b.positions(), x0)
+        assert xp._lib.xpbd_step(b.handle, 3, dev.data_ptr(), tools.nbytes) == xp.XPBD_OK
+        assert not np.array_equal(b.positions(), x0)
 
 
 def test_colours_read_back(xp, oracle_lib):
