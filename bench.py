@@ -207,10 +207,11 @@ def source_sha(name):
 def measured_traffic(workload, steps_per_launch, args, record="xpbd_step_traffic.json"):
     """HBM bytes per step launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
     recorded in profiles/, if they were taken on this kernel source, this launch
-    selection (the runtime source), this colouring and the default launch shape."""
+    selection (the runtime source), this colouring, the default launch shape and
+    the default tools (spheres on their paths)."""
     path = os.path.join(ROOT, "profiles", record)
     if (not os.path.exists(path) or steps_per_launch != 1 or args.variant or args.packing
-            or args.block or args.group):
+            or args.block or args.group or args.tool_shape != "sphere" or args.tool_lift):
         return None
     with open(path) as f:
         rec = json.load(f)
