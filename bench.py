@@ -222,6 +222,17 @@ def measured_traffic(workload, steps_per_launch, args, record="xpbd_step_traffic
     return rec["traffic_bytes_per_launch"]
 
 
+def loss_summary(losses, window=50):
+    """Training loss over the first and the last `window` Adam steps (mean and
+    median: a minibatch's loss is heavy-tailed where a few rows carry large
+    corrections)."""
+    import numpy as np
+    first, last = np.asarray(losses[:window]), np.asarray(losses[-window:])
+    return {"loss_first": float(first.mean()), "loss_last": float(last.mean()),
+            "loss_first_median": float(np.median(first)),
+            "loss_last_median": float(np.median(last)), "loss_window": int(window)}
+
+
 def progress(msg):
     """A progress line on stderr (stdout carries only the result line)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -385,8 +396,7 @@ def learned_leg(args, wl_fn, mesh, make_batch, I, S):
             "residual_by_sweeps": by_sweeps,
             "training": {"envs": args.train_envs, "recorded_substeps": args.train_records,
                          "free_rows": rows, "adam_steps": args.train_steps,
-                         "loss_first": float(np.mean(losses[:5])),
-                         "loss_last": float(np.mean(losses[-50:])), "seconds": train_s,
+                         **loss_summary(losses), "seconds": train_s,
                          "adam_seconds": adam_s},
             "network": "27-128-128-3 ReLU, bf16 MFMA, fp32 accumulate"}
 
@@ -531,8 +541,7 @@ def rl_learned_leg(args, make_batch, policy, rp, S, I):
             "residual_ratio": float(r_l.mean() / r_p.mean()),
             "training": {"envs": args.train_envs, "recorded_substeps": n_rec,
                          "free_rows": rows, "adam_steps": args.train_steps,
-                         "loss_first": float(np.mean(losses[:5])),
-                         "loss_last": float(np.mean(losses[-50:])), "seconds": train_s},
+                         **loss_summary(losses), "seconds": train_s},
             "network": "27-128-128-3 ReLU, bf16 MFMA, fp32 accumulate"}
 
 
