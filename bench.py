@@ -52,7 +52,7 @@ CUS = 256
 PEAK_FP32 = 157.3e12                         # published FP32 vector peak (packed FP32 issue)
 PEAK_FP32_NONPACKED = CUS * 64 * 2 * CLOCK   # 78.6 TFLOP/s: 256 CU x 64 lanes x FMA x 2.4 GHz
 PEAK_HBM = 8.0e12                            # B/s
-COLOURINGS = ["greedy", "largest-first", "waves", "capped-256", "capped-128"]
+COLOURINGS = ["greedy", "largest-first", "waves", "capped-256", "capped-128", "capped-256-where-it-fits"]
 LDS_PEAK_RECORD = "lds_peak.json"            # measured LDS bytes per clock per CU (--lds-peak)
 LDS_ASSUMED_B_PER_CLK = 128.0                # used only when no measurement is recorded
 
@@ -82,11 +82,13 @@ def parse_args():
                     help="constraint colouring (a Gauss-Seidel order; the oracle takes the same): "
                          "0 = greedy (the library's default), 1 = largest first, 2 = largest "
                          "first with colours of 65..100 cut to one wave of 64, 3 = largest first "
-                         "with colours capped at 256 members, 4 = the same capped at 128 "
-                         "(default: one colour per round of the workload's workgroups: 3 for "
-                         "the batch and single workloads (256 threads), 4 for the RL workload "
-                         "(128 threads), 1 for the uneven workload, whose largest meshes a cap "
-                         "would push past the register variant's 64 rounds)")
+                         "with colours capped at 256 members, 4 = the same capped at 128, "
+                         "5 = per mesh: 3 where its colours fit the register variant's 64 "
+                         "rounds, else 1 (default: one colour per round of the workload's "
+                         "workgroups: 3 for the batch and single workloads (256 threads), 4 "
+                         "for the RL workload (128 threads), 1 for the uneven workload, whose "
+                         "largest meshes a cap would push past 64 rounds; 5 measured slower "
+                         "there)")
     ap.add_argument("--group", type=int, default=0,
                     help="environments per workgroup (0 = library's choice, 1 or 2)")
     ap.add_argument("--cpu-envs", type=int, default=64, help="oracle sample: environments")

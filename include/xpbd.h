@@ -166,9 +166,14 @@ enum { XPBD_TOOL_SPHERE = 0, XPBD_TOOL_CAPSULE = 1 };
  *                  members (the others stay uncoloured), so that every colour
  *                  is one round of a 256-thread workgroup
  *   CAPPED_128     the same with at most 128 members: one round of a
- *                  128-thread workgroup */
+ *                  128-thread workgroup
+ *   CAPPED_FIT     chosen per mesh: CAPPED where its colours, the distance
+ *                  colours and the volume colours each counted up to an even
+ *                  number, add up to at most 64 (every colour one round of a
+ *                  256-thread workgroup, within the register variant's 64
+ *                  rounds), else LARGEST_FIRST; for batches of uneven meshes */
 enum { XPBD_COLOURING_GREEDY = 0, XPBD_COLOURING_LARGEST_FIRST = 1, XPBD_COLOURING_WAVES = 2,
-       XPBD_COLOURING_CAPPED = 3, XPBD_COLOURING_CAPPED_128 = 4 };
+       XPBD_COLOURING_CAPPED = 3, XPBD_COLOURING_CAPPED_128 = 4, XPBD_COLOURING_CAPPED_FIT = 5 };
 
 /* Values of xpbd_params.colour_packing.  Constraints of one colour share no
  * particle, so their order changes no result; it only decides which lanes

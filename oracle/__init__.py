@@ -200,10 +200,11 @@ def greedy_colour(num_vertices, verts):
 
 # colourings of the edge and tetrahedron constraints (R10, R13)
 (COLOURING_GREEDY, COLOURING_LARGEST_FIRST, COLOURING_WAVES, COLOURING_CAPPED,
- COLOURING_CAPPED_128) = 0, 1, 2, 3, 4
+ COLOURING_CAPPED_128, COLOURING_CAPPED_FIT) = 0, 1, 2, 3, 4, 5
 WAVE_CUT_ABOVE = 100
 COLOUR_CAP = 256
 COLOUR_CAP_128 = 128
+FIT_COLOURS = 64      # CAPPED_FIT keeps the cap up to this many colours (kinds rounded to even)
 
 
 def largest_first_colour(num_vertices, verts, cut_above=0, cap=0):
@@ -219,7 +220,10 @@ def largest_first_colour(num_vertices, verts, cut_above=0, cap=0):
 
 
 def colour(num_vertices, verts, colouring=COLOURING_GREEDY):
-    """Colours of constraints verts[n][k] by the named colouring; (colours, count)."""
+    """Colours of constraints verts[n][k] by the named colouring; (colours, count).
+    CAPPED_FIT decides over both kinds of a mesh: see ``mesh_colours``."""
+    if colouring == COLOURING_CAPPED_FIT:
+        raise ValueError("CAPPED_FIT colours a mesh's two kinds together (mesh_colours)")
     if len(verts) == 0:
         return np.zeros(0, np.int32), 0
     if colouring == COLOURING_GREEDY:
@@ -227,6 +231,20 @@ def colour(num_vertices, verts, colouring=COLOURING_GREEDY):
     cut = WAVE_CUT_ABOVE if colouring == COLOURING_WAVES else 0
     cap = {COLOURING_CAPPED: COLOUR_CAP, COLOURING_CAPPED_128: COLOUR_CAP_128}.get(colouring, 0)
     return largest_first_colour(num_vertices, verts, cut, cap)
+
+
+def mesh_colours(num_vertices, edges, tets, colouring=COLOURING_GREEDY):
+    """Colours of a mesh's edges and tetrahedra: ((edge colours, count), (tet
+    colours, count)).  CAPPED_FIT (R13): the CAPPED colouring if its edge and
+    tetrahedron colour counts, each rounded up to an even number, sum to at
+    most FIT_COLOURS, else LARGEST_FIRST."""
+    if colouring != COLOURING_CAPPED_FIT:
+        return colour(num_vertices, edges, colouring), colour(num_vertices, tets, colouring)
+    e, t = colour(num_vertices, edges, COLOURING_CAPPED), colour(num_vertices, tets, COLOURING_CAPPED)
+    if e[1] + e[1] % 2 + t[1] + t[1] % 2 <= FIT_COLOURS:
+        return e, t
+    return (colour(num_vertices, edges, COLOURING_LARGEST_FIRST),
+            colour(num_vertices, tets, COLOURING_LARGEST_FIRST))
 
 
 def schedule(colours, num_colours):
@@ -338,8 +356,7 @@ def prepare_mesh(rest_pos, inv_mass, tets, colouring=COLOURING_GREEDY) -> Oracle
         raise OracleError(f"oracle_setup_edges failed: {rc}")
     E = ne.value
     edges, rl = edges[:E].copy(), rl[:E].copy()
-    ecol, nec = colour(V, edges, colouring)
-    tcol, ntc = colour(V, tout, colouring)
+    (ecol, nec), (tcol, ntc) = mesh_colours(V, edges, tout, colouring)
     eptr, eorder = schedule(ecol, nec)
     tptr, torder = schedule(tcol, ntc)
     faces = surface_faces(rest, tout) if T else np.zeros((0, 3), np.int32)

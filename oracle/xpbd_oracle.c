@@ -95,8 +95,11 @@
  *       colour of 65 .. cut_above members is cut to its first 64, so that it
  *       fills one 64-wide group of parallel lanes, or every colour is capped
  *       at its first cap members, so that it fits one pass of cap parallel
- *       lanes.  A colouring only fixes the Gauss-Seidel order (R1); both
- *       sides take it from the same rules.
+ *       lanes; a per-mesh choice keeps the 256 cap only while the mesh's
+ *       edge and tetrahedron colour counts, each rounded up to even, sum to
+ *       at most 64, and else takes the uncapped colouring (oracle/__init__.py,
+ *       mesh_colours).  A colouring only fixes the Gauss-Seidel order (R1);
+ *       both sides take it from the same rules.
  *
  * Every function below is pinned by the not-gpu tests (closed forms,
  * invariants and brute force on tiny meshes).

@@ -17,6 +17,9 @@ constexpr int32_t kWaveCutAbove = 100;
 // CAPPED and CAPPED_128 colourings: a colour keeps at most this many members.
 constexpr int32_t kColourCap = 256;
 constexpr int32_t kColourCap128 = 128;
+// CAPPED_FIT: the most colours (each kind's count rounded up to even) for
+// which a mesh keeps the cap; the register variant holds 64 rounds.
+constexpr int32_t kFitRounds = 64;
 
 // Six times the signed volume of (a, b, c, d): the determinant of the edge
 // vectors b - a, c - a, d - a, expanded along its first row.
@@ -820,13 +823,24 @@ int prepare_mesh(int32_t num_vertices, int32_t num_tets, const float *rest_pos,
                                                out.tet_colour);
     } else {
         const int32_t cut = colouring == XPBD_COLOURING_WAVES ? kWaveCutAbove : 0;
-        const int32_t cap = colouring == XPBD_COLOURING_CAPPED       ? kColourCap
+        const int32_t cap = colouring == XPBD_COLOURING_CAPPED || colouring == XPBD_COLOURING_CAPPED_FIT
+                                ? kColourCap
                             : colouring == XPBD_COLOURING_CAPPED_128 ? kColourCap128
                                                                       : 0;
         out.num_edge_colours = largest_first_colouring(num_vertices, out.num_edges(), 2,
                                                        out.edges.data(), cut, cap, out.edge_colour);
         out.num_tet_colours = largest_first_colouring(num_vertices, out.num_tets(), 4,
                                                       out.tets.data(), cut, cap, out.tet_colour);
+        // CAPPED_FIT: keep the cap only while one round per colour stays within
+        // the register variant's rounds (each kind's count rounded up to even)
+        const auto even = [](int32_t n) { return n + (n & 1); };
+        if (colouring == XPBD_COLOURING_CAPPED_FIT &&
+            even(out.num_edge_colours) + even(out.num_tet_colours) > kFitRounds) {
+            out.num_edge_colours = largest_first_colouring(num_vertices, out.num_edges(), 2,
+                                                           out.edges.data(), 0, 0, out.edge_colour);
+            out.num_tet_colours = largest_first_colouring(num_vertices, out.num_tets(), 4,
+                                                          out.tets.data(), 0, 0, out.tet_colour);
+        }
     }
 
     // surface triangles (capsule tools): faces of exactly one kept tetrahedron,

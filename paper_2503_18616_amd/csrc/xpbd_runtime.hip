@@ -63,7 +63,7 @@ xpbd_status validate_params(const xpbd_params *p)
         return fail(XPBD_E_ARG, "unknown solver_variant %d", p->solver_variant);
     if (p->colour_packing < XPBD_PACKING_AUTO || p->colour_packing > XPBD_PACKING_SEARCH)
         return fail(XPBD_E_ARG, "unknown colour_packing %d", p->colour_packing);
-    if (p->colouring < XPBD_COLOURING_GREEDY || p->colouring > XPBD_COLOURING_CAPPED_128)
+    if (p->colouring < XPBD_COLOURING_GREEDY || p->colouring > XPBD_COLOURING_CAPPED_FIT)
         return fail(XPBD_E_ARG, "unknown colouring %d", p->colouring);
     if (p->envs_per_group < 0 || p->envs_per_group > xpbd::kMaxEnvsPerGroup)
         return fail(XPBD_E_ARG, "envs_per_group must be 0, 1 or 2 (got %d)", p->envs_per_group);
@@ -191,7 +191,7 @@ xpbd_status xpbd_prepare_mesh_coloured(const xpbd_mesh *mesh, int32_t colouring,
     g_error.clear();
     if (!mesh || !counts)
         return fail(XPBD_E_ARG, "mesh and counts must not be NULL");
-    if (colouring < XPBD_COLOURING_GREEDY || colouring > XPBD_COLOURING_CAPPED_128)
+    if (colouring < XPBD_COLOURING_GREEDY || colouring > XPBD_COLOURING_CAPPED_FIT)
         return fail(XPBD_E_ARG, "unknown colouring %d", colouring);
     PreparedMesh pm;
     std::string err;

@@ -80,6 +80,25 @@ def test_largest_first_colourings_bit_exact_with_oracle(xp, oracle_lib, grid, co
     assert lib["num_tet_colours"] == om.num_tet_colours
 
 
+@pytest.mark.parametrize("grid", [(16, 10, 4), (12, 8, 3), (20, 12, 6), (6, 4, 2)])
+def test_capped_fit_colouring_bit_exact_with_oracle(xp, oracle_lib, grid):
+    """The per-mesh CAPPED_FIT colouring equals the oracle's on slabs below
+    the limit (the capped colouring) and above it (20x12x6: the uncapped
+    largest-first colouring)."""
+    m = W.slab_mesh(*grid)
+    lib = xp.xpbd_prepare_mesh(m.rest_pos, m.inv_mass, m.tets, colouring=5)
+    om = oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass, m.tets, colouring=5)
+    assert np.array_equal(lib["edge_colour"], om.edge_colour)
+    assert np.array_equal(lib["tet_colour"], om.tet_colour)
+    capped = oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass, m.tets, colouring=3)
+    fits = (capped.num_edge_colours + capped.num_edge_colours % 2 +
+            capped.num_tet_colours + capped.num_tet_colours % 2) <= 64
+    assert fits == (grid != (20, 12, 6))
+    want = capped if fits else oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass, m.tets, colouring=1)
+    assert np.array_equal(lib["edge_colour"], want.edge_colour)
+    assert np.array_equal(lib["tet_colour"], want.tet_colour)
+
+
 def test_mesh_setup_on_perturbed_and_shuffled_meshes(xp, oracle_lib):
     rng = np.random.default_rng(5)
     for trial in range(5):
@@ -88,7 +107,7 @@ def test_mesh_setup_on_perturbed_and_shuffled_meshes(xp, oracle_lib):
         perm = rng.permutation(m.num_tets)
         tets = m.tets[perm]
         w = m.inv_mass * rng.uniform(0.5, 2.0, size=m.num_vertices).astype(np.float32)
-        for colouring in (0, 1, 2, 3, 4):
+        for colouring in (0, 1, 2, 3, 4, 5):
             lib = xp.xpbd_prepare_mesh(rest, w, tets, colouring=colouring)
             om = oracle_lib.prepare_mesh(rest, w, tets, colouring=colouring)
             assert np.array_equal(lib["edges"], om.edges)
@@ -148,7 +167,7 @@ def _create_error(xp, meshes=None, env_mesh=None, compliance=None, **pkw):
     (dict(flags=0x80), -1), (dict(block_size=96), -1), (dict(block_size=2048), -1),
     (dict(gravity=(0.0, float("inf"), 0.0)), -1), (dict(envs_per_group=3), -1),
     (dict(envs_per_group=-1), -1), (dict(colour_packing=6), -1), (dict(solver_variant=4), -1),
-    (dict(colouring=5), -1), (dict(colouring=-1), -1),
+    (dict(colouring=6), -1), (dict(colouring=-1), -1),
 ])
 def test_create_rejects_bad_params(xp, kw, status):
     assert _create_error(xp, **kw).status == status

@@ -30,9 +30,10 @@ VARIANTS = [1, 2]   # multipliers in registers, multipliers in LDS
 VARIANT_IDS = ["registers", "lds"]
 
 
-def make_batch(xp, wl, flags=0, block_size=0, variant=0):
+def make_batch(xp, wl, flags=0, block_size=0, variant=0, colouring=0):
     p = K.lib_params(xp, wl, flags, block_size)
     p.solver_variant = variant
+    p.colouring = colouring
     return xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p)
 
 
@@ -505,21 +506,33 @@ def test_flags_can_change_between_steps(xp):
             b.set_flags(0x40)
 
 
-def test_uneven_4096_sampled_parity(xp, oracle_lib):
+@pytest.mark.parametrize("colouring", [0, 5], ids=["greedy", "capped-where-it-fits"])
+def test_uneven_4096_sampled_parity(xp, oracle_lib, colouring):
     """The 4096-environment uneven workload (675 distinct slabs of 105 to 1911
-    particles) as the benchmark launches it: the smallest and largest
-    environments and four others follow the oracle after 100 steps."""
+    particles) as the benchmark launches it (one launch per step of every
+    size class; the benchmark's per-mesh capped colouring, and the greedy
+    one): the smallest and largest environments and four others follow the
+    oracle after 100 steps; with the per-mesh colouring, every mesh's colours
+    equal the oracle's."""
     steps = 100
     wl = W.uneven_workload(4096, seed=0, num_steps=steps)
     V = np.array([m.num_vertices for m in wl.meshes])[wl.env_mesh]
     sample = sorted({int(np.argmin(V)), int(np.argmax(V)), 0, 1000, 2047, 4095})
     tools = wl.tools(steps)
-    om = [oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass, m.tets)
+    om = [oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass, m.tets, colouring=colouring)
           if k in {int(wl.env_mesh[e]) for e in sample} else None
           for k, m in enumerate(wl.meshes)]
     refs = oracle_lib.run_batch(om, wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
                                 tools[:, sample], steps, env_ids=sample, threads=len(sample))
-    with make_batch(xp, wl) as b:
+    with make_batch(xp, wl, colouring=colouring) as b:
+        if colouring:
+            assert b.info()["solver_variant"] == xp.VARIANT_REGISTERS
+            col = b.read(xp.FIELD_COLOURS)
+            want = np.concatenate([np.concatenate([o.edge_colour, o.tet_colour])
+                                   for o in (oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass,
+                                                                     m.tets, colouring=colouring)
+                                             for m in wl.meshes)])
+            assert np.array_equal(col, want)
         b.step(steps, tools)
         x = b.positions()
         for n, e in enumerate(sample):

@@ -196,6 +196,31 @@ def test_largest_first_cap_keeps_the_first_picks(oracle_lib):
     assert (capped[:256] == 0).all() and (capped[256:] == 1).all()
 
 
+@pytest.mark.parametrize("tets_in_star, capped", [(33, True), (35, False)])
+def test_capped_fit_counts_each_kind_rounded_up_to_even(oracle_lib, tets_in_star, capped):
+    """CAPPED_FIT keeps the cap while the edge and tetrahedron colour counts,
+    each rounded up to even, sum to at most 64.  Edges: a star of 29 edges
+    (29 colours) and 300 disjoint edges that join the first colour, which the
+    cap splits (so the capped and uncapped edge colourings differ, with 29
+    colours each); tetrahedra: a star of 33 or 35 sharing one vertex (one
+    colour each).  30 + 34 = 64 keeps the cap; 30 + 36 = 66 does not, though
+    29 + 35 = 64 unrounded would."""
+    star = [[0, 1 + i] for i in range(29)]
+    loose = [[1000 + 2 * i, 1001 + 2 * i] for i in range(300)]
+    edges = np.array(star + loose, np.int32)
+    tets = np.array([[0, 2000 + 3 * j, 2001 + 3 * j, 2002 + 3 * j] for j in range(tets_in_star)],
+                    np.int32)
+    V = 2000 + 3 * tets_in_star
+    (ec, nec), (tc, ntc) = oracle_lib.mesh_colours(V, edges, tets, oracle_lib.COLOURING_CAPPED_FIT)
+    cap_e, n_cap = oracle_lib.colour(V, edges, oracle_lib.COLOURING_CAPPED)
+    free_e, n_free = oracle_lib.colour(V, edges, oracle_lib.COLOURING_LARGEST_FIRST)
+    assert n_cap == n_free == 29 and not np.array_equal(cap_e, free_e)
+    assert ntc == tets_in_star
+    assert np.array_equal(ec, cap_e if capped else free_e) and nec == 29
+    with pytest.raises(ValueError):
+        oracle_lib.colour(V, edges, oracle_lib.COLOURING_CAPPED_FIT)
+
+
 def test_capped_first_colour_is_a_prefix_of_the_uncapped_one(oracle_lib):
     """The cap changes no pick before it applies: on the 16x10x4 slab the first
     capped edge colour is 256 of the first uncapped colour's members (which
