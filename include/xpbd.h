@@ -171,7 +171,7 @@ enum { XPBD_TOOL_SPHERE = 0, XPBD_TOOL_CAPSULE = 1 };
  *                  colours and the volume colours each counted up to an even
  *                  number, add up to at most 64 (every colour one round of a
  *                  256-thread workgroup, within the register variant's 64
- *                  rounds), else LARGEST_FIRST; for batches of uneven meshes */
+ *                  rounds), else LARGEST_FIRST */
 enum { XPBD_COLOURING_GREEDY = 0, XPBD_COLOURING_LARGEST_FIRST = 1, XPBD_COLOURING_WAVES = 2,
        XPBD_COLOURING_CAPPED = 3, XPBD_COLOURING_CAPPED_128 = 4, XPBD_COLOURING_CAPPED_FIT = 5 };
 
