@@ -539,7 +539,12 @@ def rl_learned_leg(args, make_batch, policy, rp, S, I):
             "fallback_fraction": float((it > args.learned_min).mean()),
             "residual_rms_mean": float(r_l.mean()),
             "plain_residual_rms_mean": float(r_p.mean()),
-            "residual_matched": bool(r_l.mean() <= r_p.mean()),
+            "residual_p99": float(np.quantile(r_l, 0.99)),
+            "plain_residual_p99": float(np.quantile(r_p, 0.99)),
+            "residual_matched": bool(r_l.mean() <= r_p.mean()
+                                     and np.quantile(r_l, 0.99) <= np.quantile(r_p, 0.99)),
+            "residual_matched_rule": "mean and 0.99 quantile of the per-env-step residual (last "
+                                     "substep) at most the plain solver's, over the same steps",
             "residual_ratio": float(r_l.mean() / r_p.mean()),
             "training": {"envs": args.train_envs, "recorded_substeps": n_rec,
                          "free_rows": rows, "adam_steps": args.train_steps,
