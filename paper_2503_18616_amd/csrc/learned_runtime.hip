@@ -415,7 +415,7 @@ xpbd_status xpbd::learned_workspace(xpbd_batch *b, const xpbd_learned_params *lp
         int device = 0, cus = 0;
         HIP_TRY(hipGetDevice(&device));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
-        b->correct_workgroups = 3 * std::max(cus, 1);   // three 51 KB workgroups fit a CU's LDS
+        b->correct_workgroups = kCorrectWorkgroupsPerCu * std::max(cus, 1);
     }
 
     return XPBD_OK;
@@ -430,8 +430,8 @@ void xpbd::learned_chunks(const xpbd_batch *b, std::vector<int32_t> &c0, int32_t
         int32_t first = 0;
         while (first < pm.num_vertices && !(pm.inv_mass[(size_t)first] > 0.0f))
             ++first;
-        c0[m] = std::min(first, pm.num_vertices - 1) / 32;
-        chunks = std::max(chunks, (pm.num_vertices + 31) / 32 - c0[m]);
+        c0[m] = std::min(first, pm.num_vertices - 1) / kCorrectChunk;
+        chunks = std::max(chunks, (pm.num_vertices + kCorrectChunk - 1) / kCorrectChunk - c0[m]);
     }
 }
 

@@ -14,6 +14,10 @@ constexpr int kMlpHidden = 128;
 constexpr int kMlpOutputs = 3;
 constexpr int kMlpTile = 64;       // samples per workgroup
 constexpr float kMlpClip = 8.0f;   // the correction clamps y to [-8, 8] (network units)
+// The correction kernel: particles per work item (16-particle matrix tiles of
+// one wave) and persistent workgroups per CU.
+constexpr int kCorrectChunk = 32;
+constexpr int kCorrectWorkgroupsPerCu = 3;
 
 // Flat parameter order (float32): W1 [128][27], b1 [128], W2 [128][128], b2 [128],
 // W3 [3][128], b3 [3]; weights are [out][in].

@@ -10,6 +10,7 @@
 #include "../../include/xpbd_learned.h"
 #include "batch.h"
 #include "learned_step.h"
+#include "mlp_device.h"
 #include "runtime_util.h"
 #include "xpbd_device.h"
 
@@ -52,7 +53,7 @@ xpbd_status scratch_base(int device, unsigned char **out)
     return XPBD_OK;
 }
 
-// First 32-particle chunk of every mesh that holds a free particle (the
+// First kCorrectChunk-particle chunk of every mesh that holds a free particle (the
 // correction skips the chunks before it): one thread per mesh.
 __global__ void chunk_table_kernel(const xpbd::MeshDev *__restrict__ meshes, int32_t num_meshes,
                                    int32_t *__restrict__ chunk0)
@@ -65,7 +66,7 @@ __global__ void chunk_table_kernel(const xpbd::MeshDev *__restrict__ meshes, int
     int first = 0;
     while (first < V && !(w[first] > 0.0f))
         ++first;
-    chunk0[m] = (first < V - 1 ? first : V - 1) / 32;
+    chunk0[m] = (first < V - 1 ? first : V - 1) / xpbd::kCorrectChunk;
 }
 
 }  // namespace
@@ -130,13 +131,14 @@ xpbd_status xpbd_step_learned_noalloc(xpbd_batch *b, const xpbd_mlp *net, int32_
             int32_t first = 0;
             while (first < pm.num_vertices && !(pm.inv_mass[(size_t)first] > 0.0f))
                 ++first;
-            const int32_t c0 = std::min(first, pm.num_vertices - 1) / 32;
-            chunks = std::max(chunks, (pm.num_vertices + 31) / 32 - c0);
+            const int32_t c0 = std::min(first, pm.num_vertices - 1) / xpbd::kCorrectChunk;
+            const int32_t n = (pm.num_vertices + xpbd::kCorrectChunk - 1) / xpbd::kCorrectChunk;
+            chunks = std::max(chunks, n - c0);
         }
         ws.chunks = chunks;
         int cus = 0;
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
-        ws.correct_workgroups = 3 * std::max(cus, 1);   // as the allocating step
+        ws.correct_workgroups = xpbd::kCorrectWorkgroupsPerCu * std::max(cus, 1);   // as the allocating step
         const int block = 64;
         const int grid = (int)((num_meshes + block - 1) / block);
         hipLaunchKernelGGL(chunk_table_kernel, dim3(grid), dim3(block), 0, b->stream,

@@ -35,7 +35,7 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 #define GLOBAL __attribute__((address_space(1)))
 
 constexpr int kThreads = 256;   // threads per workgroup (four independent waves)
-constexpr int kTiles = 2;       // 16-particle tiles per wave step
+constexpr int kTiles = kCorrectChunk / 16;   // 16-particle tiles per work item
 constexpr int PF = 40;          // pitch (bfloat16) of W1 rows
 constexpr int PW = 136;         // pitch (bfloat16) of W2 and W3 rows
 constexpr int H = kMlpHidden;
@@ -152,13 +152,15 @@ __device__ void stage_network(CorrectLds &S, const MlpDev &net, int tid)
     __syncthreads();
 }
 
-// Grid: persistent workgroups of 256 threads (three per CU).  Wave w of the
-// grid takes the work items w, w + total waves, ...; item k is particles
-// 32 (k % G + c0) .. + 31 of environment k / G, G = L.chunks, c0 = L.chunk0
+// Grid: persistent workgroups of 256 threads (kCorrectWorkgroupsPerCu per
+// CU).  Wave w of the grid takes the work items w, w + total waves, ...; item
+// k is particles C (k % G + c0) .. + C - 1 of environment k / G, C =
+// kCorrectChunk, G = L.chunks, c0 = L.chunk0
 // of the environment's mesh (chunks of pinned particles only are skipped).
 // Reads the feature rows L.features and adds the correction to the predicted
 // positions L.xhat of the free particles.
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
+__global__ void __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(kCorrectWorkgroupsPerCu, kCorrectWorkgroupsPerCu)))
 learned_correct_kernel(StepArgs A, LearnedArgs L, MlpDev net)
 {
     extern __shared__ __align__(16) unsigned char smem[];
