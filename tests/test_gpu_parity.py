@@ -371,6 +371,44 @@ def test_nonfinite_state_is_reported(xp):
         assert b.read(xp.FIELD_NONFINITE).tolist() == [0, 0, 0]
 
 
+def test_degenerate_meshes_beside_a_slab(xp, oracle_lib):
+    """Degenerate meshes in one batch with an ordinary slab, the tool pressing
+    each: a slab whose every particle is pinned (no constraint is kept: no
+    rounds at all) stays exactly at rest with zero velocity; a single
+    tetrahedron with one free corner (three edges and one volume) and the
+    8x5x3 slab follow the oracle after 20 steps."""
+    import dataclasses
+    slab = W.slab_mesh(8, 5, 3)
+    pinned = W.slab_mesh(2, 1, 1)
+    pinned = dataclasses.replace(pinned, inv_mass=np.zeros_like(pinned.inv_mass))
+    tet_pos = np.array([[0.0, 0.0, 0.0], [0.02, 0.0, 0.0], [0.0, 0.02, 0.0],
+                        [0.005, 0.005, 0.02]], np.float32)
+    one_tet = dataclasses.replace(slab, nx=1, ny=1, nz=1, rest_pos=tet_pos,
+                                  tets=np.array([[0, 1, 2, 3]], np.int32),
+                                  inv_mass=np.array([0.0, 0.0, 0.0, 1000.0], np.float32))
+    meshes = [pinned, one_tet, slab]
+    wl = W.Workload("degenerate", meshes, np.array([0, 1, 2, 2], np.int32),
+                    W.log_uniform_compliance(4, 1e-7, 1e-5, 3), iterations=4, num_steps=20, seed=3)
+    steps = 20
+    tools = W.tool_path(steps, wl.num_envs, wl.seed, start_depth=4e-3)
+    om = K.oracle_meshes(oracle_lib, wl)
+    assert len(om[0].edges) == 0 and len(om[0].tets) == 0
+    assert len(om[1].edges) == 3 and len(om[1].tets) == 1
+    refs = oracle_lib.run_batch(om, wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
+                                tools, steps, threads=4)
+    with make_batch(xp, wl) as b:
+        assert b.info()["solver_variant"] == xp.VARIANT_REGISTERS
+        b.step(steps, tools)
+        x, v = b.positions(), b.velocities()
+        offs = b.env_offsets
+    assert np.array_equal(K.env_block(x, offs, 0), pinned.rest_pos)
+    assert not K.env_block(v, offs, 0).any()
+    for e in (1, 2, 3):
+        err = K.max_position_error(K.env_block(x, offs, e), refs[e].x)
+        assert err <= K.POS_TOL, f"env {e}: {err:.3e}"
+    assert not np.array_equal(K.env_block(x, offs, 1)[3], tet_pos[3])   # the free corner moved
+
+
 def test_zero_steps_and_zero_iterations(xp):
     wl = W.single_env_workload()
     with make_batch(xp, wl) as b:
