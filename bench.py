@@ -142,8 +142,8 @@ def lds_peaks():
 
 def host_threads(work_items):
     """Threads for the oracle's CPU baseline: every CPU this process may run on,
-    capped by OMP_NUM_THREADS where the host sets it (the GPU machine sets it to
-    the 16-core share one GPU's jobs get), and by the work items.  Returns the
+    capped by OMP_NUM_THREADS where the host sets it (a shared host may set it
+    to the core share one GPU's jobs get), and by the work items.  Returns the
     count and a description of the host."""
     allowed = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     share = os.environ.get("OMP_NUM_THREADS")

@@ -82,7 +82,7 @@ def main():
     wk, nw = counter_mean(args.write, "WRITE_SIZE", is_step)
     traffic = (fk * fetch_scale + wk * write_scale) * 1024.0
 
-    lines = [f"# Step kernel — {args.workload}", "", "Command (repo root on the GPU box):", "",
+    lines = [f"# Step kernel — {args.workload}", "", "Command (from the repository root):", "",
              "    " + args.command, "",
              "| kernel | calls | total (ns) | average (ns) | share |", "|---|---|---|---|---|"]
     for r in stats:
