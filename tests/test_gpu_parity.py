@@ -644,6 +644,47 @@ def test_capsule_full_size_sampled(xp, oracle_lib):
     assert worst <= K.POS_TOL, f"max position error {worst:.3e} m"
 
 
+@pytest.mark.parametrize("block", [0, 64])
+def test_two_capsules_follow_the_oracle(xp, oracle_lib, block):
+    """Two capsule tools on the register kernel (each tool's flagged faces
+    listed and pushed on their own, tool by tool): a second capsule 2.5 cm
+    along y from the first, radii 5 and 4 mm; 3 environments of the 16x10x4
+    slab over 30 steps.  With 64-thread workgroups one wave lists both
+    tools (on the 8x5x3 slab, whose colours fit 64 rounds of 64 lanes).
+    First-step candidate counts equal the oracle's, positions within the
+    tolerance."""
+    import dataclasses
+    steps = 30
+    wl = dataclasses.replace(W.batch_workload(3, seed=11, num_steps=steps), num_tools=2,
+                             tool_radius=(W.TOOL_RADIUS, 0.004))
+    if block:
+        wl = dataclasses.replace(wl, meshes=[W.slab_mesh(8, 5, 3)])
+    one = W.capsule_path(steps, wl.num_envs, wl.seed)[:, :, 0]
+    two = one.copy()
+    two[..., 1] += 0.025
+    two[..., 4] += 0.025
+    caps = np.ascontiguousarray(np.stack([one, two], axis=2), dtype=np.float32)
+    om = K.oracle_meshes(oracle_lib, wl)
+    op = K.oracle_params(oracle_lib, wl)
+    refs = [oracle_lib.run_env_capsule(om[0], wl.compliance[e], op, caps[:, e].astype(np.float64),
+                                       steps) for e in range(wl.num_envs)]
+    assert all(r.contact_count[0, 1] > 0 and r.contact_count[0, 0] > 0 for r in refs)
+    p = K.lib_params(xp, wl, block_size=block)
+    p.tool_shape = xp.TOOL_CAPSULE
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b:
+        assert b.info()["solver_variant"] == xp.VARIANT_REGISTERS
+        if block:
+            assert b.info()["block_size"] == block
+        b.step(1, caps[:1])
+        counts = b.read(xp.FIELD_CONTACT_COUNTS).reshape(wl.num_envs, 2)
+        assert counts.tolist() == [[int(c) for c in r.contact_count[0]] for r in refs]
+        b.step(steps - 1, caps[1:])
+        x = b.positions()
+    for e in range(wl.num_envs):
+        err = K.max_position_error(K.env_block(x, b.env_offsets, e), refs[e].x)
+        assert err <= K.POS_TOL, f"env {e}: {err:.3e}"
+
+
 @pytest.mark.parametrize("case", ["single", "batch-3-envs", "single-lds", "batch-3-envs-lds",
                                   "jacobi"])
 def test_capsule_tools_follow_the_oracle(xp, oracle_lib, case):
