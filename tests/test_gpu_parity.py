@@ -685,6 +685,38 @@ def test_two_capsules_follow_the_oracle(xp, oracle_lib, block):
         assert err <= K.POS_TOL, f"env {e}: {err:.3e}"
 
 
+def test_capsules_on_uneven_meshes(xp, oracle_lib):
+    """Capsule tools on a batch of three slab sizes (8x5x3, 12x8x3, 20x12x6:
+    size classes on their own streams, each mesh with its own face list and
+    colours): every environment follows the oracle over 20 steps, with the
+    first step's candidate counts equal."""
+    steps = 20
+    meshes = [W.slab_mesh(8, 5, 3), W.slab_mesh(12, 8, 3), W.slab_mesh(20, 12, 6)]
+    wl = W.Workload("uneven-capsules", meshes, np.array([2, 0, 1, 2, 1], np.int32),
+                    W.log_uniform_compliance(5, 1e-7, 1e-5, 13), iterations=4, num_steps=steps,
+                    seed=13)
+    caps = W.capsule_path(steps, wl.num_envs, wl.seed)
+    om = K.oracle_meshes(oracle_lib, wl)
+    op = K.oracle_params(oracle_lib, wl)
+    refs = [oracle_lib.run_env_capsule(om[int(wl.env_mesh[e])], wl.compliance[e], op,
+                                       caps[:, e].astype(np.float64), steps)
+            for e in range(wl.num_envs)]
+    assert all(r.contact_count[0, 0] > 0 for r in refs)
+    p = K.lib_params(xp, wl)
+    p.tool_shape = xp.TOOL_CAPSULE
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b:
+        info = b.info()
+        assert info["solver_variant"] == xp.VARIANT_REGISTERS and info["size_classes"] >= 2
+        b.step(1, caps[:1])
+        counts = b.read(xp.FIELD_CONTACT_COUNTS).reshape(wl.num_envs, 1)
+        assert [int(c) for c in counts[:, 0]] == [int(r.contact_count[0, 0]) for r in refs]
+        b.step(steps - 1, caps[1:])
+        x = b.positions()
+    for e in range(wl.num_envs):
+        err = K.max_position_error(K.env_block(x, b.env_offsets, e), refs[e].x)
+        assert err <= K.POS_TOL, f"env {e}: {err:.3e}"
+
+
 @pytest.mark.parametrize("case", ["single", "batch-3-envs", "single-lds", "batch-3-envs-lds",
                                   "jacobi"])
 def test_capsule_tools_follow_the_oracle(xp, oracle_lib, case):
