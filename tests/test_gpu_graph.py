@@ -75,6 +75,33 @@ def test_step_graph_replays_equal_eager_steps(xp, learned):
         net.close()
 
 
+def test_capsule_step_graph_replays_equal_eager_steps(xp):
+    """A captured step with capsule tools (the register kernel's face lists
+    rebuilt in every replay) equals the eager steps bit for bit, candidate
+    counts included."""
+    import torch
+    N, steps = 12, 5
+    wl = W.batch_workload(N, seed=5, num_steps=steps)
+    caps = torch.from_numpy(np.ascontiguousarray(W.capsule_path(steps, N, 5),
+                                                 dtype=np.float32)).cuda()
+    p = K.lib_params(xp, wl)
+    p.tool_shape = xp.TOOL_CAPSULE
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as eager, \
+            xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as cap:
+        assert cap.info()["solver_variant"] == xp.VARIANT_REGISTERS
+        buf = torch.zeros_like(caps[0])
+        with cap.step_graph(buf) as g:
+            for s in range(steps):
+                eager.step(1, caps[s:s + 1])
+                buf.copy_(caps[s])
+                g.launch()
+                torch.cuda.synchronize()
+                assert np.array_equal(cap.positions(), eager.positions()), f"replay {s}"
+                assert np.array_equal(cap.read(xp.FIELD_CONTACT_COUNTS),
+                                      eager.read(xp.FIELD_CONTACT_COUNTS)), f"replay {s}"
+                assert cap.read(xp.FIELD_CONTACT_COUNTS).sum() > 0
+
+
 @pytest.mark.parametrize("learned", [False, True], ids=["plain", "learned"])
 def test_rl_graph_replays_equal_eager_rl_steps(xp, learned):
     import torch
