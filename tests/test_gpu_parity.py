@@ -680,6 +680,10 @@ def test_two_capsules_follow_the_oracle(xp, oracle_lib, block):
         assert counts.tolist() == [[int(c) for c in r.contact_count[0]] for r in refs]
         b.step(steps - 1, caps[1:])
         x = b.positions()
+    # all steps in one launch, on a fresh batch: the same bits
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as again:
+        again.step(steps, caps)
+        assert np.array_equal(again.positions(), x)
     for e in range(wl.num_envs):
         err = K.max_position_error(K.env_block(x, b.env_offsets, e), refs[e].x)
         assert err <= K.POS_TOL, f"env {e}: {err:.3e}"
