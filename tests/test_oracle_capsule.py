@@ -133,3 +133,75 @@ def test_pressing_capsule_pushes_faces_out_and_is_rigid_motion_invariant():
     r2 = oracle.run_env_capsule(om2, (1e-6, 1e-7), p2, caps2, 10)
     assert np.array_equal(r2.contact_count, r.contact_count)
     np.testing.assert_allclose(r2.x, r.x @ R.T + t, rtol=0, atol=1e-12)
+
+
+def _candidate_set_distance(p0, p1, a, b, c):
+    """Squared segment-triangle distance as the minimum over the kinds of
+    closest pairs (each end point against the triangle's plane where its
+    projection falls inside, the segment against each edge, a crossing of
+    the triangle), written from the geometry: the claim that any closest pair
+    is of one of these kinds, checked against the oracle's routine."""
+    def seg_seg(p, q, r, s):
+        # minimum over a fine grid refined by the exact 1-D minimisations
+        d1, d2, w = q - p, s - r, p - r
+        a_, e_, f_ = d1 @ d1, d2 @ d2, d2 @ w
+        c_, b_ = d1 @ w, d1 @ d2
+        best = np.inf
+        cands = [(0.0, 0.0), (1.0, 0.0), (0.0, 1.0), (1.0, 1.0)]
+        for sv in (0.0, 1.0):   # t free with s fixed at an end
+            cands.append((sv, np.clip((b_ * sv + f_) / e_, 0, 1)))
+        for tv in (0.0, 1.0):   # s free with t fixed at an end
+            cands.append((np.clip((b_ * tv - c_) / a_, 0, 1), tv))
+        den = a_ * e_ - b_ * b_
+        if den > 1e-300:        # both free (interior stationary point)
+            sv, tv = (b_ * f_ - c_ * e_) / den, (a_ * f_ - b_ * c_) / den
+            if 0 <= sv <= 1 and 0 <= tv <= 1:
+                cands.append((sv, tv))
+        for sv, tv in cands:
+            best = min(best, float(np.sum((p + sv * d1 - (r + tv * d2)) ** 2)))
+        return best
+
+    n = np.cross(b - a, c - a)
+    nn = n @ n
+    best = min(seg_seg(p0, p1, a, b), seg_seg(p0, p1, b, c), seg_seg(p0, p1, c, a))
+    for x in (p0, p1):
+        y = x - ((x - a) @ n) / nn * n
+        # barycentric coordinates of the projection by signed areas
+        wa = np.cross(b - y, c - y) @ n / nn
+        wb = np.cross(c - y, a - y) @ n / nn
+        if wa >= 0 and wb >= 0 and 1 - wa - wb >= 0:
+            best = min(best, float(((x - a) @ n) ** 2 / nn))
+    h0, h1 = (p0 - a) @ n, (p1 - a) @ n
+    if h0 != h1 and h0 * h1 <= 0:
+        x = p0 + h0 / (h0 - h1) * (p1 - p0)
+        wa = np.cross(b - x, c - x) @ n / nn
+        wb = np.cross(c - x, a - x) @ n / nn
+        if wa >= 0 and wb >= 0 and 1 - wa - wb >= 0:
+            best = 0.0
+    return best
+
+
+def test_closest_pair_kinds_cover_every_configuration():
+    """Any closest pair of a segment and a triangle is an end point with its
+    projection inside the triangle, a segment-edge pair, or a crossing (the
+    reading the register kernel's push-out takes); the minimum over those
+    kinds equals the oracle's segment_triangle, on random configurations and
+    on segments parallel to the plane above the interior, along an edge and
+    through the triangle."""
+    rng = np.random.default_rng(33)
+    cases = []
+    for _ in range(300):
+        a, b, c = rng.normal(size=(3, 3))
+        p0, p1 = rng.normal(size=(2, 3)) * 1.5
+        cases.append((p0, p1, a, b, c))
+    a, b, c = np.array([0.0, 0, 0]), np.array([1.0, 0, 0]), np.array([0.0, 1, 0])
+    cases += [
+        (np.array([0.1, 0.1, 0.3]), np.array([0.3, 0.2, 0.3]), a, b, c),    # parallel, above
+        (np.array([-0.5, 0.0, 0.2]), np.array([1.5, 0.0, 0.2]), a, b, c),   # parallel, over an edge
+        (np.array([0.2, 0.2, -0.4]), np.array([0.2, 0.2, 0.4]), a, b, c),   # through the interior
+        (np.array([2.0, 2.0, 0.0]), np.array([3.0, 2.5, 0.0]), a, b, c),    # in the plane, outside
+        (np.array([0.2, -0.3, 0.0]), np.array([0.2, 0.3, 0.0]), a, b, c),   # in the plane, across an edge
+    ]
+    for p0, p1, a, b, c in cases:
+        d2, *_ = oracle.segment_triangle(p0, p1, a, b, c)
+        assert abs(_candidate_set_distance(p0, p1, a, b, c) - d2) <= 1e-12 * (1 + d2)
