@@ -371,6 +371,29 @@ def test_nonfinite_state_is_reported(xp):
         assert b.read(xp.FIELD_NONFINITE).tolist() == [0, 0, 0]
 
 
+def test_extreme_compliances_follow_the_oracle(xp, oracle_lib):
+    """Compliances at the ends of the range: zero (the stiff PBD limit of
+    the compliance form) for both kinds, for one kind only, and 1e-3 (a soft
+    solid), with the tool pressing: every environment follows the oracle over
+    50 steps."""
+    steps = 50
+    m = W.slab_mesh(8, 5, 3)
+    comp = np.array([[0.0, 0.0], [1e-8, 0.0], [1e-3, 1e-3], [0.0, 1e-4]], np.float32)
+    wl = W.Workload("compliance-ends", [m], np.zeros(4, np.int32), comp, iterations=4,
+                    num_steps=steps, seed=17)
+    tools = W.tool_path(steps, wl.num_envs, wl.seed, start_depth=5e-3)
+    om = K.oracle_meshes(oracle_lib, wl)
+    refs = oracle_lib.run_batch(om, wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
+                                tools, steps, threads=4)
+    with make_batch(xp, wl) as b:
+        b.step(steps, tools)
+        x = b.positions()
+        offs = b.env_offsets
+    for e in range(wl.num_envs):
+        err = K.max_position_error(K.env_block(x, offs, e), refs[e].x)
+        assert err <= K.POS_TOL, f"env {e} (compliance {comp[e].tolist()}): {err:.3e}"
+
+
 def test_degenerate_meshes_beside_a_slab(xp, oracle_lib):
     """Degenerate meshes in one batch with an ordinary slab, the tool pressing
     each: a slab whose every particle is pinned (no constraint is kept: no
