@@ -394,6 +394,44 @@ def test_extreme_compliances_follow_the_oracle(xp, oracle_lib):
         assert err <= K.POS_TOL, f"env {e} (compliance {comp[e].tolist()}): {err:.3e}"
 
 
+def test_irregular_meshes_follow_the_oracle(xp, oracle_lib):
+    """Meshes off the regular grid: rest positions perturbed by 0.5 mm,
+    tetrahedra shuffled (so some are given inside out and are reoriented),
+    inverse masses scaled per particle by 0.5..2; two such meshes, three
+    environments, the tool pressing: every environment follows the oracle
+    over 30 steps."""
+    import dataclasses
+    rng = np.random.default_rng(23)
+    meshes = []
+    for grid in ((6, 4, 2), (9, 5, 3)):
+        m = W.slab_mesh(*grid)
+        rest = (m.rest_pos + rng.normal(scale=5e-4, size=m.rest_pos.shape)).astype(np.float32)
+        perm = rng.permutation(m.num_tets)
+        tets = m.tets[perm].copy()
+        flip = rng.random(len(tets)) < 0.5
+        tets[flip] = tets[flip][:, [1, 0, 2, 3]]
+        w = (m.inv_mass * rng.uniform(0.5, 2.0, size=m.num_vertices)).astype(np.float32)
+        meshes.append(dataclasses.replace(m, rest_pos=rest, tets=tets, inv_mass=w))
+    steps = 30
+    wl = W.Workload("irregular", meshes, np.array([1, 0, 1], np.int32),
+                    W.log_uniform_compliance(3, 1e-7, 1e-5, 23), iterations=4, num_steps=steps,
+                    seed=23)
+    tools = W.tool_path(steps, wl.num_envs, wl.seed, start_depth=5e-3)
+    om = K.oracle_meshes(oracle_lib, wl)
+    refs = oracle_lib.run_batch(om, wl.env_mesh, wl.compliance, K.oracle_params(oracle_lib, wl),
+                                tools, steps, threads=3)
+    with make_batch(xp, wl) as b:
+        col = b.read(xp.FIELD_COLOURS)
+        assert np.array_equal(col, np.concatenate([np.concatenate([o.edge_colour, o.tet_colour])
+                                                   for o in om]))
+        b.step(steps, tools)
+        x = b.positions()
+        offs = b.env_offsets
+    for e in range(wl.num_envs):
+        err = K.max_position_error(K.env_block(x, offs, e), refs[e].x)
+        assert err <= K.POS_TOL, f"env {e}: {err:.3e}"
+
+
 def test_degenerate_meshes_beside_a_slab(xp, oracle_lib):
     """Degenerate meshes in one batch with an ordinary slab, the tool pressing
     each: a slab whose every particle is pinned (no constraint is kept: no
