@@ -113,6 +113,25 @@ def test_single_launch_equals_step_by_step(xp, variant):
         assert np.array_equal(a.velocities(), b.velocities())
 
 
+def test_uneven_single_launch_equals_step_by_step(xp):
+    """A batch of several size classes (classes on forked streams, one launch
+    per class per call) stepped 12 steps in one call equals 12 calls of one
+    step, bit for bit, contacts included."""
+    meshes = [W.slab_mesh(6, 4, 2), W.slab_mesh(12, 8, 3), W.slab_mesh(20, 12, 6)]
+    wl = W.Workload("classes", meshes, np.array([0, 2, 1, 0, 1, 2, 0], np.int32),
+                    W.log_uniform_compliance(7, 1e-7, 1e-5, 29), iterations=4, num_steps=12,
+                    seed=29)
+    tools = wl.tools(12)
+    with make_batch(xp, wl) as a, make_batch(xp, wl) as b:
+        assert a.info()["size_classes"] >= 2
+        a.step(12, tools)
+        for s in range(12):
+            b.step(1, tools[s:s + 1])
+        assert np.array_equal(a.positions(), b.positions())
+        assert np.array_equal(a.velocities(), b.velocities())
+        assert np.array_equal(a.read(xp.FIELD_CONTACTS), b.read(xp.FIELD_CONTACTS))
+
+
 @pytest.mark.parametrize("variant", VARIANTS, ids=VARIANT_IDS)
 def test_batch_parity_sampled_envs(xp, oracle_lib, variant):
     """1024 environments of the 16x10x4 slab, 8 iterations, per-env compliances and
