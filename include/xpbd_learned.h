@@ -158,9 +158,9 @@ typedef struct {
  * prediction and the features (with net's normalisation), the network's correction
  * when apply_correction is set, then the sweeps of xpbd_learned_params.
  * tool_pos and tool_pos_bytes as in xpbd_step.  net may be NULL only without correction and
- * without recording (plain sweeps with the residual check).  Needs the
- * register variant with one environment per workgroup (XPBD_E_CAPACITY
- * otherwise).  XPBD_F_RESIDUAL and XPBD_F_LAMBDA apply to the last substep.
+ * without recording (plain sweeps with the residual check).  Needs sphere
+ * tools and the register variant with one environment per workgroup and one
+ * size class (XPBD_E_CAPACITY otherwise).  XPBD_F_RESIDUAL and XPBD_F_LAMBDA apply to the last substep.
  * With apply_correction 0, min_iterations = max_iterations = the batch's
  * iterations and no recording, the result equals xpbd_step's bit for bit. */
 xpbd_status xpbd_step_learned(xpbd_batch *batch, const xpbd_mlp *net, int32_t num_steps,

@@ -364,9 +364,9 @@ xpbd_status xpbd::check_learned(const xpbd_batch *b, const xpbd_mlp *net,
 {
     if (!b->register_variant || b->envs_per_group != 1 || b->classes.size() != 1 ||
         b->params.tool_shape != XPBD_TOOL_SPHERE)
-        return fail(XPBD_E_CAPACITY, "the learned step needs the register variant with one "
-                    "environment per workgroup and one size class (set block_size for meshes "
-                    "of different sizes)");
+        return fail(XPBD_E_CAPACITY, "the learned step needs sphere tools and the register "
+                    "variant with one environment per workgroup and one size class (set "
+                    "block_size for meshes of different sizes)");
     if (lp->min_iterations < 0 || lp->max_iterations < lp->min_iterations)
         return fail(XPBD_E_ARG, "need 0 <= min_iterations <= max_iterations");
     if (!std::isfinite(lp->threshold) && !std::isinf(lp->threshold))

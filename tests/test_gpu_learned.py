@@ -255,6 +255,22 @@ def test_plain_substeps_equal_the_fused_step(xp):
         assert b.read(xp.FIELD_CONTACT_COUNTS).sum() > 0
 
 
+def test_learned_step_refuses_capsule_tools(xp):
+    """The learned step projects sphere contacts only: a batch with capsule
+    tools is refused with XPBD_E_CAPACITY before any launch, its state
+    untouched."""
+    wl = W.batch_workload(2, seed=3, num_steps=1)
+    p = K.lib_params(xp, wl)
+    p.tool_shape = xp.TOOL_CAPSULE
+    caps = W.capsule_path(1, 2, 3)
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b:
+        x0 = b.positions()
+        with pytest.raises(xp.XpbdError) as e:
+            b.step_learned(None, 1, caps, 2, 2, np.inf, apply_correction=False)
+        assert e.value.status == xp.XPBD_E_CAPACITY and "sphere" in str(e.value)
+        assert np.array_equal(b.positions(), x0)
+
+
 @pytest.mark.parametrize("threshold,expect_its", [(np.inf, 2), (-1.0, 4)])
 def test_learned_substeps_follow_the_oracle(xp, oracle_lib, threshold, expect_its):
     import torch
