@@ -255,6 +255,21 @@ def test_plain_substeps_equal_the_fused_step(xp):
         assert b.read(xp.FIELD_CONTACT_COUNTS).sum() > 0
 
 
+def test_learned_step_host_and_device_poses_agree(xp):
+    """Tool poses from host memory (staged by the library) and from device
+    memory give the same learned steps, bit for bit."""
+    import torch
+    wl = W.batch_workload(6, seed=19, num_steps=4)
+    tools = np.ascontiguousarray(W.tool_path(4, 6, 19, start_depth=6e-3), dtype=np.float32)
+    net = xp.Mlp(flat(random_net(19)), np.zeros(27), np.ones(27), np.zeros(3), np.full(3, 1e-4))
+    with make_batch(xp, wl) as a, make_batch(xp, wl) as b:
+        a.step_learned(net, 4, tools, 2, 8, 1e-3, stall_ratio=0.9)
+        b.step_learned(net, 4, torch.from_numpy(tools).cuda(), 2, 8, 1e-3, stall_ratio=0.9)
+        assert np.array_equal(a.positions(), b.positions())
+        assert np.array_equal(a.velocities(), b.velocities())
+    net.close()
+
+
 def test_learned_step_refuses_capsule_tools(xp):
     """The learned step projects sphere contacts only: a batch with capsule
     tools is refused with XPBD_E_CAPACITY before any launch, its state
