@@ -270,6 +270,57 @@ def test_learned_step_host_and_device_poses_agree(xp):
     net.close()
 
 
+def test_learned_step_on_meshes_of_two_sizes(xp, oracle_lib):
+    """Two slab sizes in one size class (block_size given): without the
+    correction the learned step equals the plain step bit for bit; with a
+    network (two sweeps per substep) each environment follows the oracle's
+    learned driver over 10 steps.  Without block_size the batch has two
+    classes and the learned step refuses it."""
+    import torch
+    meshes = [W.slab_mesh(6, 4, 2), W.slab_mesh(12, 8, 3)]
+    steps = 10
+    wl = W.Workload("two-sizes", meshes, np.array([1, 0, 1], np.int32),
+                    W.log_uniform_compliance(3, 1e-7, 1e-5, 31), iterations=4, num_steps=steps,
+                    seed=31)
+    tools = np.ascontiguousarray(W.tool_path(steps, 3, 31, start_depth=6e-3), dtype=np.float32)
+    p = K.lib_params(xp, wl, block_size=256)
+    p.solver_variant = xp.VARIANT_REGISTERS
+    in_scale = 1.0 / np.array([2e-4] * 3 + [0.1] * 3 + [2e-3] * 3 + [2e-5] * 18)
+    net = random_net(31, out_scale=2e-5)
+    net.in_scale = in_scale.astype(np.float32).astype(np.float64)
+    om = K.oracle_meshes(oracle_lib, wl)
+    refs = []
+    for e in range(wl.num_envs):
+        o = om[int(wl.env_mesh[e])]
+
+        def corr(x_prev, v_start, x_hat, nbr, o=o):
+            return ws.correction(net, ws.features(x_prev, v_start, x_hat, o.rest, nbr), o.w > 0)
+        refs.append(oracle_lib.run_env_learned(o, wl.compliance[e],
+                                               K.oracle_params(oracle_lib, wl), tools[:, e],
+                                               steps, corr, 2, 4, np.inf))
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as a, \
+            xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b, \
+            xp.Mlp(flat(net), net.in_shift, net.in_scale, net.out_shift, net.out_scale) as m:
+        assert a.info()["size_classes"] == 1
+        a.step(steps, tools)
+        b.step_learned(None, steps, tools, wl.iterations, wl.iterations, np.inf,
+                       apply_correction=False)
+        assert np.array_equal(a.positions(), b.positions())
+        with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as c:
+            c.step_learned(m, steps, torch.from_numpy(tools).cuda(), 2, 4, np.inf)
+            x = c.positions()
+            offs = c.env_offsets
+    for e in range(wl.num_envs):
+        err = K.max_position_error(K.env_block(x, offs, e), refs[e].x)
+        assert err <= K.POS_TOL, f"env {e}: {err:.3e}"
+    q = K.lib_params(xp, wl)
+    with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, q) as d:
+        if d.info()["size_classes"] > 1:
+            with pytest.raises(xp.XpbdError) as err:
+                d.step_learned(None, 1, tools[:1], 2, 2, np.inf, apply_correction=False)
+            assert err.value.status == xp.XPBD_E_CAPACITY
+
+
 def test_learned_step_refuses_capsule_tools(xp):
     """The learned step projects sphere contacts only: a batch with capsule
     tools is refused with XPBD_E_CAPACITY before any launch, its state
