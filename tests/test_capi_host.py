@@ -275,3 +275,24 @@ def test_batch_info_rejects_null(xp):
     assert xp._lib.xpbd_get_batch_info(None, None) == xp.XPBD_E_ARG
     info = xp.XpbdBatchInfo()
     assert xp._lib.xpbd_get_batch_info(None, ctypes.byref(info)) == xp.XPBD_E_ARG
+
+
+def test_binding_refuses_to_load_without_the_library(tmp_path):
+    """The product path has no fallback: a package copy without libxpbd.so
+    raises ImportError when the binding (or a module built on it) loads."""
+    import shutil
+    import subprocess
+    import sys
+    src = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2503_18616_amd")
+    dst = tmp_path / "paper_2503_18616_amd"
+    dst.mkdir()
+    for name in os.listdir(src):
+        if name.endswith(".py"):
+            shutil.copy(os.path.join(src, name), dst / name)
+    for module in ("xpbd", "warmstart"):
+        r = subprocess.run([sys.executable, "-c", f"import paper_2503_18616_amd.{module}"],
+                           cwd=tmp_path, capture_output=True, text=True, timeout=120,
+                           env={**os.environ, "PYTHONPATH": str(tmp_path)})
+        assert r.returncode != 0
+        assert "ImportError" in r.stderr and "libxpbd.so is missing" in r.stderr
