@@ -630,8 +630,8 @@ def test_uneven_4096_sampled_parity(xp, oracle_lib, colouring):
     particles) as the benchmark launches it (one launch per step of every
     size class; the benchmark's per-mesh capped colouring, and the greedy
     one): the smallest and largest environments and four others follow the
-    oracle after 100 steps; with the per-mesh colouring, every mesh's colours
-    equal the oracle's."""
+    oracle after 100 steps; with the per-mesh colouring, the colours of every
+    32nd mesh and of the sampled environments' meshes equal the oracle's."""
     steps = 100
     wl = W.uneven_workload(4096, seed=0, num_steps=steps)
     V = np.array([m.num_vertices for m in wl.meshes])[wl.env_mesh]
@@ -646,11 +646,21 @@ def test_uneven_4096_sampled_parity(xp, oracle_lib, colouring):
         if colouring:
             assert b.info()["solver_variant"] == xp.VARIANT_REGISTERS
             col = b.read(xp.FIELD_COLOURS)
-            want = np.concatenate([np.concatenate([o.edge_colour, o.tet_colour])
-                                   for o in (oracle_lib.prepare_mesh(m.rest_pos, m.inv_mass,
-                                                                     m.tets, colouring=colouring)
-                                             for m in wl.meshes)])
-            assert np.array_equal(col, want)
+            # A mesh's colours are those of its edges, then of its tets;
+            # constraints whose particles are all pinned are not kept.
+            pairs = [0, 1, 0, 2, 0, 3, 1, 2, 1, 3, 2, 3]
+            counts = []
+            for m in wl.meshes:
+                free = m.inv_mass.reshape(-1) > 0
+                e = np.unique(np.sort(m.tets[:, pairs].reshape(-1, 2), axis=1), axis=0)
+                counts.append(int(free[e].any(axis=1).sum()) + int(free[m.tets].any(axis=1).sum()))
+            off = np.concatenate([[0], np.cumsum(counts)])
+            assert off[-1] == len(col)
+            for k in sorted(set(range(0, len(wl.meshes), 32)) | {int(wl.env_mesh[e]) for e in sample}):
+                o = om[k] or oracle_lib.prepare_mesh(wl.meshes[k].rest_pos, wl.meshes[k].inv_mass,
+                                                     wl.meshes[k].tets, colouring=colouring)
+                assert np.array_equal(col[off[k]:off[k + 1]],
+                                      np.concatenate([o.edge_colour, o.tet_colour])), f"mesh {k}"
         b.step(steps, tools)
         x = b.positions()
         for n, e in enumerate(sample):
