@@ -62,11 +62,12 @@ def test_groups_of_two_are_bitwise_equal_to_single_envs(xp):
 
 
 def small_meshes_workload(seed=5):
-    """Slabs of 105 to 504 particles with odd environment counts: the
-    library's per-class choice runs the smallest two to a workgroup."""
-    grids = [(6, 4, 2), (7, 4, 2), (8, 5, 3), (11, 6, 5)]
+    """Slabs of 105 to 1911 particles with odd environment counts: the
+    library's per-class choice runs the small ones two to a workgroup and the
+    largest one alone."""
+    grids = [(6, 4, 2), (7, 4, 2), (8, 5, 3), (11, 6, 5), (20, 12, 6)]
     meshes = [W.slab_mesh(*g) for g in grids]
-    env_mesh = np.array([0, 1, 2, 3, 0, 0, 1, 2, 3, 3, 0], np.int32)
+    env_mesh = np.array([0, 1, 2, 3, 0, 0, 1, 2, 3, 3, 0, 4, 4, 4], np.int32)
     return W.Workload("small-meshes", meshes, env_mesh,
                       W.log_uniform_compliance(len(env_mesh), 1e-7, 1e-5, seed), iterations=8,
                       num_steps=40, seed=seed)
