@@ -299,9 +299,12 @@ xpbd_status xpbd_autotune(const xpbd_mesh *meshes, int32_t num_meshes, const int
  * The launch configuration a batch runs with (what the library chose for
  * the zero, "library's choice", entries of xpbd_params), for inspection.
  * For the register variant the figures are those of the largest size class;
- * workgroups_per_cu is how many of its workgroups a CU holds at once (by
- * the 16 resident waves of the kernel and by the CU's LDS), waves_per_cu the
- * waves that makes.  Host only.  XPBD_E_ARG for NULL pointers.
+ * workgroups_per_cu is how many of its workgroups a CU holds at once (for
+ * the register variant as the HIP runtime's occupancy calculator gives it,
+ * on the current device, for the kernel a step without a grasp runs: its
+ * registers, block and LDS; for the others by 16 resident waves and the
+ * CU's LDS), waves_per_cu the waves that makes.  Host only.  XPBD_E_ARG for
+ * NULL pointers, XPBD_E_HIP if the occupancy query fails.
  */
 typedef struct {
     int32_t solver_variant;    /* XPBD_VARIANT_REGISTERS, _LDS or _JACOBI */

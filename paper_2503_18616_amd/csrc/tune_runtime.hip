@@ -125,7 +125,8 @@ xpbd_status xpbd_get_batch_info(const xpbd_batch *b, xpbd_batch_info *out)
                           : b->params.solver_variant == XPBD_VARIANT_JACOBI ? XPBD_VARIANT_JACOBI
                                                                            : XPBD_VARIANT_LDS;
     out->envs_per_group = b->envs_per_group;
-    int block = b->block, banks = b->lambda_banks, groups = b->num_envs;
+    int block = b->block, banks = b->lambda_banks, groups = b->num_envs, group = 1;
+    bool barriers = true;
     uint32_t lds = b->lds_bytes;
     if (b->register_variant) {
         out->size_classes = (int32_t)b->classes.size();
@@ -137,6 +138,8 @@ xpbd_status xpbd_get_batch_info(const xpbd_batch *b, xpbd_batch_info *out)
                 banks = c.lambda_banks;
                 lds = c.lds_bytes;
                 groups = c.num_groups;
+                barriers = c.round_barriers;
+                group = c.group;
             }
     } else {
         out->size_classes = 1;
@@ -149,6 +152,13 @@ xpbd_status xpbd_get_batch_info(const xpbd_batch *b, xpbd_batch_info *out)
     int per_cu = 16 / (waves > 0 ? waves : 1);
     if (lds > 0 && lds_cu > 0)
         per_cu = std::min(per_cu, (int)((uint32_t)lds_cu / lds));
+    if (b->register_variant) {
+        // the kernel's own registers may allow fewer (capsule tools)
+        xpbd::StepArgs a{};
+        a.tool_shape = b->params.tool_shape;
+        a.round_barriers = barriers ? 1 : 0;
+        HIP_TRY(xpbd::step_reg_occupancy(a, block, banks, group, lds, &per_cu));
+    }
     out->block_size = block;
     out->lambda_banks = banks;
     out->lds_bytes = (int32_t)lds;

@@ -262,6 +262,12 @@ __host__ __device__ inline RegLdsLayout reg_lds_layout(int32_t V, int32_t face_b
 // envs_per_group in {1, 2}; one workgroup per group.
 hipError_t launch_step_reg(const StepArgs &args, int block, int lambda_banks, int envs_per_group,
                            uint32_t lds_bytes, bool want_residual, hipStream_t stream);
+// Workgroups of the register kernel that a launch with these arguments runs
+// (tool shape, grasp, round barriers) a CU holds at once, as the HIP
+// runtime's occupancy calculator gives it from the kernel's registers, the
+// block and the LDS.
+hipError_t step_reg_occupancy(const StepArgs &args, int block, int lambda_banks,
+                              int envs_per_group, uint32_t lds_bytes, int *per_cu);
 // Residual RMS and max of every environment from the multipliers of the last
 // launch (register variant).
 hipError_t launch_residual(const StepArgs &args, hipStream_t stream);

@@ -2186,25 +2186,48 @@ hipError_t launch_ppt(const StepArgs &args, int block, bool jacobi, bool stage, 
                  : launch_variant<PPT, false, false>(args, block, lds, s);
 }
 
+using RegKernel = void (*)(StepArgs);
+
+// The register kernel a launch with these arguments runs: the grasping and
+// capsule code only in the launches that use them (they cost registers).
+// nullptr: capsule tools with several environments per workgroup.
+template <int NB, int EG>
+RegKernel reg_kernel(const StepArgs &args)
+{
+    if (args.tool_shape == 1) {   // XPBD_TOOL_CAPSULE
+        if constexpr (EG == 1)
+            return xpbd_step_reg_kernel_capsules<NB>;
+        else
+            return nullptr;
+    }
+    return args.round_barriers
+               ? (args.grasp ? xpbd_step_reg_kernel<NB, EG, kRegGrasp, true>
+                             : xpbd_step_reg_kernel<NB, EG, kRegSpheres, true>)
+               : (args.grasp ? xpbd_step_reg_kernel<NB, EG, kRegGrasp, false>
+                             : xpbd_step_reg_kernel<NB, EG, kRegSpheres, false>);
+}
+
+template <int EG>
+RegKernel reg_kernel_banks(const StepArgs &args, int lambda_banks)
+{
+    return lambda_banks == 1 ? reg_kernel<1, EG>(args)
+           : lambda_banks == 2 ? reg_kernel<2, EG>(args)
+                               : nullptr;
+}
+
+RegKernel reg_kernel_for(const StepArgs &args, int lambda_banks, int envs_per_group)
+{
+    return envs_per_group == 1   ? reg_kernel_banks<1>(args, lambda_banks)
+           : envs_per_group == 2 ? reg_kernel_banks<2>(args, lambda_banks)
+                                 : nullptr;
+}
+
 template <int NB, int EG>
 hipError_t launch_reg_variant(const StepArgs &args, int block, uint32_t lds_bytes, hipStream_t stream)
 {
-    // the grasping and capsule code only in the launches that use them (they
-    // cost registers)
-    auto kernel = args.round_barriers
-                      ? (args.grasp ? xpbd_step_reg_kernel<NB, EG, kRegGrasp, true>
-                                    : xpbd_step_reg_kernel<NB, EG, kRegSpheres, true>)
-                      : (args.grasp ? xpbd_step_reg_kernel<NB, EG, kRegGrasp, false>
-                                    : xpbd_step_reg_kernel<NB, EG, kRegSpheres, false>);
-    if (args.tool_shape == 1) {   // XPBD_TOOL_CAPSULE
-        if constexpr (EG == 1) {
-            if (block > 512)
-                return hipErrorInvalidValue;
-            kernel = xpbd_step_reg_kernel_capsules<NB>;
-        } else {
-            return hipErrorInvalidValue;
-        }
-    }
+    const RegKernel kernel = reg_kernel<NB, EG>(args);
+    if (!kernel || (args.tool_shape == 1 && block > kMaxCapsuleBlock))
+        return hipErrorInvalidValue;
     hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)lds_bytes);
@@ -2251,6 +2274,21 @@ hipError_t launch_step_reg(const StepArgs &args, int block, int lambda_banks, in
         return err;
     hipLaunchKernelGGL(residual_kernel, dim3((unsigned)args.num_envs), dim3(256), 0, stream, args);
     return hipGetLastError();
+}
+
+hipError_t step_reg_occupancy(const StepArgs &args, int block, int lambda_banks,
+                              int envs_per_group, uint32_t lds_bytes, int *per_cu)
+{
+    const RegKernel kernel = reg_kernel_for(args, lambda_banks, envs_per_group);
+    if (!kernel || !per_cu)
+        return hipErrorInvalidValue;
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds_bytes);
+    if (err != hipSuccess)
+        return err;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        per_cu, reinterpret_cast<const void *>(kernel), block, (size_t)lds_bytes);
 }
 
 hipError_t launch_residual(const StepArgs &args, hipStream_t stream)
