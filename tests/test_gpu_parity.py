@@ -722,6 +722,11 @@ def test_capsule_full_size_sampled(xp, oracle_lib):
     with xp.Batch(K.lib_meshes(wl), wl.env_mesh, wl.compliance, p) as b:
         info = b.info()
         assert info["solver_variant"] == xp.VARIANT_REGISTERS and info["lambda_banks"] == 2
+        # resident workgroups from the occupancy calculator: the capsule
+        # kernel's registers allow no more than the LDS does
+        lds_per_cu = 160 * 1024
+        assert 1 <= info["workgroups_per_cu"] <= lds_per_cu // info["lds_bytes"]
+        assert info["waves_per_cu"] == info["workgroups_per_cu"] * info["block_size"] // 64
         b.step(1, caps[:1])
         counts = b.read(xp.FIELD_CONTACT_COUNTS).reshape(wl.num_envs, 1)
         assert [int(counts[e, 0]) for e in sample] == [int(r.contact_count[0, 0]) for r in refs]
